@@ -1,0 +1,853 @@
+/*
+ * Oracle for the level-crossing-probability (LCP) hot path -- TEST INFRASTRUCTURE.
+ *
+ * A plain, slow, FP64 CPU implementation of what the GPU library computes, written
+ * from the paper (Li, Michaud, Biswas, Shen, "Efficient Level-Crossing Probability
+ * Calculation for Gaussian Process Modeled Data", arXiv 2512.12442).  Only the test
+ * suite, the smoke check and the bench's CPU-baseline leg load this library; the
+ * product path never does.  It shares no code with the HIP library.
+ *
+ * Every loop runs in the order of the definition it implements; OpenMP only
+ * distributes independent points, cells or octree nodes over threads.
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
+ *
+ * Readings of the paper taken here (all listed in the design notes):
+ *  - GP model: the exact-GP special case of eq. (sgp) (inducing set = observations),
+ *    so mu(x) = k*^T (K + s_n^2 I)^-1 y and var(x) = k(x,x) - ||L^-1 k*||^2, latent f.
+ *  - F_M uses the standard deviation, not the variance (Sec. 4.1 prints Sigma).
+ *  - Cell covariance is factored with a semidefinite Cholesky (tolerance 1e-12 of the
+ *    largest diagonal entry); a sample equal to the iso-value counts as crossed.
+ *  - The L-BFGS-B search of Sec. 4.1 is replaced by a fixed-budget bounded search:
+ *    a {lo,mid,hi}^D lattice followed by T normalised projected-gradient steps.
+ *  - Alg. 1 is run on the full model F_M (no local model M'); p = alpha counts as
+ *    "not larger than alpha"; a node without observations takes its side from the
+ *    sign of theta - mu(box centre).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_ENOTPD 2
+#define ORC_ECAP 3
+#define ORC_ENOMEM 4
+
+typedef struct {
+    int kind;          /* 0: squared exponential (Sec. 3), 1: Matern-5/2 (textbook) */
+    int dim;           /* 2 or 3 */
+    int m;             /* number of observations */
+    double s2;         /* signal variance */
+    double ell[3];     /* per-axis lengthscales */
+    double noise;      /* observation-noise variance */
+    const double* X;  /* m x dim observation locations, row-major */
+    const double* L;  /* m x m lower Cholesky factor of K + noise I, row-major */
+    const double* a;  /* m: (K + noise I)^-1 y */
+} orc_model;
+
+typedef struct {
+    int dim;
+    double lo[3];
+    double hi[3];
+    int64_t n[3];      /* vertices per axis; x is the fastest axis */
+} orc_grid;
+
+typedef struct {
+    double alpha;
+    int min_leaf;           /* finest node edge in cells (power of two) */
+    int bound_at_max_depth; /* 1: Alg. 1 as printed (region test at every level) */
+    int steps;              /* projected-gradient steps after the lattice */
+} orc_adapt;
+
+typedef struct {
+    uint64_t key;      /* level << 58 | Morton code of the node coordinates */
+    int32_t level;
+    int32_t n_obs;     /* |M~| : observations inside the closed node box */
+    double p1, p2;     /* max P(Y_i < theta), max P(Y_i > theta) over M~ */
+    int32_t path;      /* 0 prelim subdivide, 1 bound below, 2 bound above, 3 max depth w/o bound */
+    int32_t subdivide;
+    double gmin;       /* minimum of the standardised margin found by the search */
+    double ub;         /* 1 - B^d */
+    double lattice_gap;/* second-smallest minus smallest lattice value */
+    int64_t d;         /* grid vertices inside the node */
+} orc_node_rec;
+
+/* ---------------------------------------------------------------- kernels -- */
+
+static double scaled_r2(int dim, const double* ell, const double* x, const double* z)
+{
+    double r2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        double t = (x[d] - z[d]) / ell[d];
+        r2 += t * t;
+    }
+    return r2;
+}
+
+/* k(x, z): squared exponential s2 exp(-r^2/2) (Sec. 3), Matern-5/2 s2 (1 + sqrt5 r + 5r^2/3) exp(-sqrt5 r). */
+double orc_kernel(int kind, int dim, double s2, const double* ell, const double* x, const double* z)
+{
+    double r2 = scaled_r2(dim, ell, x, z);
+    if (kind == 0) return s2 * exp(-0.5 * r2);
+    double r = sqrt(r2);
+    return s2 * (1.0 + sqrt(5.0) * r + 5.0 * r2 / 3.0) * exp(-sqrt(5.0) * r);
+}
+
+/* Gradient of k(x, z) with respect to x. */
+void orc_kernel_grad(int kind, int dim, double s2, const double* ell, const double* x, const double* z,
+                     double* g)
+{
+    double r2 = scaled_r2(dim, ell, x, z);
+    double f;
+    if (kind == 0) {
+        f = -s2 * exp(-0.5 * r2);
+    } else {
+        double r = sqrt(r2);
+        f = -(5.0 / 3.0) * s2 * (1.0 + sqrt(5.0) * r) * exp(-sqrt(5.0) * r);
+    }
+    for (int d = 0; d < dim; ++d) g[d] = f * (x[d] - z[d]) / (ell[d] * ell[d]);
+}
+
+/* ---------------------------------------------------------- model factor -- */
+
+/* Solve L v = b by forward substitution (L row-major lower, m x m). */
+static void forward_sub(int m, const double* L, const double* b, double* v)
+{
+    for (int i = 0; i < m; ++i) {
+        double s = b[i];
+        for (int j = 0; j < i; ++j) s -= L[(int64_t)i * m + j] * v[j];
+        v[i] = s / L[(int64_t)i * m + i];
+    }
+}
+
+/* Solve L^T v = b by backward substitution. */
+static void backward_sub_t(int m, const double* L, const double* b, double* v)
+{
+    for (int i = m - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < m; ++j) s -= L[(int64_t)j * m + i] * v[j];
+        v[i] = s / L[(int64_t)i * m + i];
+    }
+}
+
+/*
+ * Factor the model (Sec. 3, exact-GP form of eq. (sgp)): K_ij = k(x_i,x_j) + noise d_ij,
+ * K = L L^T by Cholesky-Banachiewicz without pivoting or jitter, a = L^-T L^-1 y.
+ * Returns ORC_ENOTPD if a pivot is not above m * eps * max_i K_ii (numerically singular K).
+ */
+int orc_fit(int kind, int dim, double s2, const double* ell, double noise, int m,
+            const double* X, const double* y, double* L, double* a)
+{
+    double* K = (double*)malloc(sizeof(double) * (size_t)m * m);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    if (!K || !w) { free(K); free(w); return ORC_ENOMEM; }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+            K[(int64_t)i * m + j] = orc_kernel(kind, dim, s2, ell, X + (int64_t)i * dim, X + (int64_t)j * dim)
+                                    + (i == j ? noise : 0.0);
+    memset(L, 0, sizeof(double) * (size_t)m * m);
+    /* A pivot at or below m * eps * max_i K_ii is rounding noise: K is numerically singular. */
+    double kmax = 0.0;
+    for (int i = 0; i < m; ++i) if (K[(int64_t)i * m + i] > kmax) kmax = K[(int64_t)i * m + i];
+    double piv_min = (double)m * 2.220446049250313e-16 * kmax;
+    int rc = ORC_OK;
+    for (int i = 0; i < m && rc == ORC_OK; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = K[(int64_t)i * m + j];
+            for (int k = 0; k < j; ++k) s -= L[(int64_t)i * m + k] * L[(int64_t)j * m + k];
+            if (i == j) {
+                if (!(s > piv_min)) { rc = ORC_ENOTPD; break; }
+                L[(int64_t)i * m + i] = sqrt(s);
+            } else {
+                L[(int64_t)i * m + j] = s / L[(int64_t)j * m + j];
+            }
+        }
+    }
+    if (rc == ORC_OK) {
+        forward_sub(m, L, y, w);
+        backward_sub_t(m, L, w, a);
+    }
+    free(K);
+    free(w);
+    return rc;
+}
+
+/* ------------------------------------------------------------- posterior -- */
+
+/* Posterior of the latent field at one point: mean, variance (clamped at 0), v = L^-1 k*. */
+static void posterior_point(const orc_model* M, const double* x, double* mean, double* var,
+                            double* kbuf, double* v)
+{
+    int m = M->m;
+    for (int j = 0; j < m; ++j) kbuf[j] = orc_kernel(M->kind, M->dim, M->s2, M->ell, M->X + (int64_t)j * M->dim, x);
+    double mu = 0.0;
+    for (int j = 0; j < m; ++j) mu += kbuf[j] * M->a[j];
+    forward_sub(m, M->L, kbuf, v);
+    double nv = 0.0;
+    for (int j = 0; j < m; ++j) nv += v[j] * v[j];
+    double s = M->s2 - nv;
+    *mean = mu;
+    *var = s > 0.0 ? s : 0.0;
+}
+
+/* Posterior mean and variance at n points; optionally v = L^-1 k* per point (n x m). */
+int orc_posterior(const orc_model* M, int64_t n, const double* P, double* mean, double* var, double* V)
+{
+    int m = M->m;
+    int rc = ORC_OK;
+#pragma omp parallel
+    {
+        double* kb = (double*)malloc(sizeof(double) * (size_t)m);
+        double* vb = (double*)malloc(sizeof(double) * (size_t)m);
+        if (!kb || !vb) {
+#pragma omp atomic write
+            rc = ORC_ENOMEM;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                double* v = V ? V + i * m : vb;
+                posterior_point(M, P + i * M->dim, &mean[i], &var[i], kb, v);
+            }
+        }
+        free(kb);
+        free(vb);
+    }
+    return rc;
+}
+
+/* Posterior mean/variance and their gradients at one point (used by the region bound). */
+static void posterior_grad_point(const orc_model* M, const double* x, double* mean, double* var,
+                                 double* dmean, double* dvar, double* kb, double* dkb, double* v, double* w)
+{
+    int m = M->m, D = M->dim;
+    posterior_point(M, x, mean, var, kb, v);
+    for (int j = 0; j < m; ++j) {
+        double g[3];
+        orc_kernel_grad(M->kind, D, M->s2, M->ell, x, M->X + (int64_t)j * D, g);
+        for (int d = 0; d < D; ++d) dkb[(int64_t)d * m + j] = g[d];
+    }
+    for (int d = 0; d < D; ++d) {
+        double dm = 0.0;
+        for (int j = 0; j < m; ++j) dm += dkb[(int64_t)d * m + j] * M->a[j];
+        dmean[d] = dm;
+        forward_sub(m, M->L, dkb + (int64_t)d * m, w);
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += v[j] * w[j];
+        dvar[d] = -2.0 * s;
+    }
+}
+
+int orc_posterior_grad(const orc_model* M, const double* x, double* mean, double* var, double* dmean, double* dvar)
+{
+    int m = M->m;
+    double* buf = (double*)malloc(sizeof(double) * (size_t)m * 6);
+    if (!buf) return ORC_ENOMEM;
+    posterior_grad_point(M, x, mean, var, dmean, dvar, buf, buf + m, buf + 4 * (size_t)m, buf + 5 * (size_t)m);
+    free(buf);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------ cell LCP -- */
+
+/* Semidefinite Cholesky S = C C^T (n x n, row-major, C lower).  A column whose pivot
+ * is not above tau * max_q S_qq is set to zero.  Returns the number of kept columns. */
+int orc_chol_sd(int n, const double* S, double* C, double tau)
+{
+    double mx = 0.0;
+    for (int q = 0; q < n; ++q) if (S[q * n + q] > mx) mx = S[q * n + q];
+    memset(C, 0, sizeof(double) * (size_t)n * n);
+    int rank = 0;
+    for (int k = 0; k < n; ++k) {
+        double d = S[k * n + k];
+        for (int j = 0; j < k; ++j) d -= C[k * n + j] * C[k * n + j];
+        if (!(mx > 0.0) || d <= tau * mx) continue;
+        double ckk = sqrt(d);
+        C[k * n + k] = ckk;
+        for (int i = k + 1; i < n; ++i) {
+            double s = S[i * n + k];
+            for (int j = 0; j < k; ++j) s -= C[i * n + j] * C[k * n + j];
+            C[i * n + k] = s / ckk;
+        }
+        ++rank;
+    }
+    return rank;
+}
+
+/* Monte Carlo count of crossed samples (Sec. 4, cell LCP): y = mu + C z_s; a sample is
+ * crossed unless all corners are below theta or all are above theta. */
+int64_t orc_mc_count(int n, const double* mu, const double* C, double theta, int ns, const double* zb)
+{
+    int64_t cnt = 0;
+    for (int s = 0; s < ns; ++s) {
+        int below = 1, above = 1;
+        for (int q = 0; q < n; ++q) {
+            double yq = mu[q];
+            for (int r = 0; r <= q; ++r) yq += C[q * n + r] * zb[(int64_t)s * n + r];
+            if (!(yq < theta)) below = 0;
+            if (!(yq > theta)) above = 0;
+        }
+        if (!below && !above) ++cnt;
+    }
+    return cnt;
+}
+
+static double vertex_coord(const orc_grid* G, int d, int64_t i)
+{
+    return G->lo[d] + (double)i * ((G->hi[d] - G->lo[d]) / (double)(G->n[d] - 1));
+}
+
+/* Cell covariance of the 2^D corners from per-vertex posterior data. */
+static void cell_cov(const orc_model* M, int nc, const double* xc, const double* varc, const double* const* vc,
+                     double* S)
+{
+    int m = M->m, D = M->dim;
+    for (int p = 0; p < nc; ++p) {
+        S[p * nc + p] = varc[p];
+        for (int q = 0; q < p; ++q) {
+            double dot = 0.0;
+            for (int j = 0; j < m; ++j) dot += vc[p][j] * vc[q][j];
+            double c = orc_kernel(M->kind, D, M->s2, M->ell, xc + p * D, xc + q * D) - dot;
+            S[p * nc + q] = c;
+            S[q * nc + p] = c;
+        }
+    }
+}
+
+/* Corner mean vector and covariance of one cell from vertex arrays of a box of vertices
+ * (vertex (i,j,k) of the box at offset i + bx*(j + by*k)). */
+static int64_t cell_count(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb,
+                          const int64_t* cell, const int64_t* box_lo, const int64_t* box_n,
+                          const double* bmean, const double* bvar, const double* bV)
+{
+    int D = G->dim, nc = 1 << D, m = M->m;
+    double mu[8], var[8], xc[24], S[64], C[64];
+    const double* vc[8];
+    for (int q = 0; q < nc; ++q) {
+        int64_t idx = 0, stride = 1;
+        for (int d = 0; d < D; ++d) {
+            int64_t vi = cell[d] + ((q >> d) & 1);
+            xc[q * D + d] = vertex_coord(G, d, vi);
+            idx += (vi - box_lo[d]) * stride;
+            stride *= box_n[d];
+        }
+        mu[q] = bmean[idx];
+        var[q] = bvar[idx];
+        vc[q] = bV + idx * m;
+    }
+    cell_cov(M, nc, xc, var, vc, S);
+    orc_chol_sd(nc, S, C, 1e-12);
+    return orc_mc_count(nc, mu, C, theta, ns, zb);
+}
+
+/* Posterior at every vertex of a box [box_lo, box_lo + box_n) of grid vertices. */
+static int box_posterior(const orc_model* M, const orc_grid* G, const int64_t* box_lo, const int64_t* box_n,
+                         double** mean, double** var, double** V, int64_t* nv_out)
+{
+    int D = G->dim;
+    int64_t nv = 1;
+    for (int d = 0; d < D; ++d) nv *= box_n[d];
+    double* P = (double*)malloc(sizeof(double) * (size_t)nv * D);
+    *mean = (double*)malloc(sizeof(double) * (size_t)nv);
+    *var = (double*)malloc(sizeof(double) * (size_t)nv);
+    *V = (double*)malloc(sizeof(double) * (size_t)nv * M->m);
+    if (!P || !*mean || !*var || !*V) { free(P); return ORC_ENOMEM; }
+    for (int64_t t = 0; t < nv; ++t) {
+        int64_t r = t;
+        for (int d = 0; d < D; ++d) {
+            P[t * D + d] = vertex_coord(G, d, box_lo[d] + r % box_n[d]);
+            r /= box_n[d];
+        }
+    }
+    int rc = orc_posterior(M, nv, P, *mean, *var, *V);
+    free(P);
+    *nv_out = nv;
+    return rc;
+}
+
+/* Per-vertex posterior mean and variance for the whole grid (x fastest). */
+int orc_grid_posterior(const orc_model* M, const orc_grid* G, double* mean, double* var)
+{
+    int D = G->dim;
+    int64_t nv = 1;
+    for (int d = 0; d < D; ++d) nv *= G->n[d];
+    double* P = (double*)malloc(sizeof(double) * (size_t)nv * D);
+    if (!P) return ORC_ENOMEM;
+    for (int64_t t = 0; t < nv; ++t) {
+        int64_t r = t;
+        for (int d = 0; d < D; ++d) { P[t * D + d] = vertex_coord(G, d, r % G->n[d]); r /= G->n[d]; }
+    }
+    int rc = orc_posterior(M, nv, P, mean, var, NULL);
+    free(P);
+    return rc;
+}
+
+/* Dense LCP (Sec. 4 baseline) for the cells whose slowest-axis index lies in [c0, c1).
+ * lcp receives those cells in x-fastest order. */
+int orc_lcp_cells(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb,
+                  int64_t c0, int64_t c1, double* lcp)
+{
+    int D = G->dim, sa = D - 1;
+    int64_t box_lo[3] = {0, 0, 0}, box_n[3] = {1, 1, 1};
+    for (int d = 0; d < D; ++d) { box_lo[d] = 0; box_n[d] = G->n[d]; }
+    box_lo[sa] = c0;
+    box_n[sa] = c1 - c0 + 1;
+    double *mean = NULL, *var = NULL, *V = NULL;
+    int64_t nv;
+    int rc = box_posterior(M, G, box_lo, box_n, &mean, &var, &V, &nv);
+    if (rc == ORC_OK) {
+        int64_t ncell = 1;
+        int64_t cn[3] = {1, 1, 1};
+        for (int d = 0; d < D; ++d) { cn[d] = G->n[d] - 1; }
+        cn[sa] = c1 - c0;
+        for (int d = 0; d < D; ++d) ncell *= cn[d];
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t t = 0; t < ncell; ++t) {
+            int64_t cell[3], r = t;
+            for (int d = 0; d < D; ++d) { cell[d] = r % cn[d]; r /= cn[d]; }
+            cell[sa] += c0;
+            int64_t cnt = cell_count(M, G, theta, ns, zb, cell, box_lo, box_n, mean, var, V);
+            lcp[t] = (double)cnt / (double)ns;
+        }
+    }
+    free(mean);
+    free(var);
+    free(V);
+    return rc;
+}
+
+/* Corner mean and covariance of one cell (exposed for the tests). */
+int orc_cell_moments(const orc_model* M, const orc_grid* G, const int64_t* cell, double* mu, double* S)
+{
+    int D = G->dim, nc = 1 << D;
+    int64_t box_lo[3] = {0, 0, 0}, box_n[3] = {1, 1, 1};
+    for (int d = 0; d < D; ++d) { box_lo[d] = cell[d]; box_n[d] = 2; }
+    double *mean = NULL, *var = NULL, *V = NULL;
+    int64_t nv;
+    int rc = box_posterior(M, G, box_lo, box_n, &mean, &var, &V, &nv);
+    if (rc == ORC_OK) {
+        double xc[24], vr[8];
+        const double* vc[8];
+        for (int q = 0; q < nc; ++q) {
+            for (int d = 0; d < D; ++d) xc[q * D + d] = vertex_coord(G, d, cell[d] + ((q >> d) & 1));
+            mu[q] = mean[q];
+            vr[q] = var[q];
+            vc[q] = V + (int64_t)q * M->m;
+        }
+        cell_cov(M, nc, xc, vr, vc, S);
+    }
+    free(mean);
+    free(var);
+    free(V);
+    return rc;
+}
+
+/* ------------------------------------------------------- region bound -- */
+
+/* Standardised margin g = side (theta - mu) / sigma; its minimum over a region gives
+ * B = Phi(g_min) = min F_M (side +1) or min (1 - F_M) (side -1), Sec. 4.1. */
+static double margin(double side, double theta, double mu, double var)
+{
+    double num = side * (theta - mu);
+    if (var > 0.0) return num / sqrt(var);
+    if (num > 0.0) return INFINITY;
+    if (num < 0.0) return -INFINITY;
+    return 0.0;
+}
+
+typedef struct {
+    const orc_model* M;
+    double theta;
+    double* kb;
+    double* dkb;
+    double* v;
+    double* w;
+} bound_ws;
+
+static double margin_at(bound_ws* B, double side, const double* x)
+{
+    double mu, var;
+    posterior_point(B->M, x, &mu, &var, B->kb, B->v);
+    return margin(side, B->theta, mu, var);
+}
+
+/* Margin and its gradient; returns 0 if the gradient is not usable (sigma = 0). */
+static int margin_grad_at(bound_ws* B, double side, const double* x, double* g, double* grad)
+{
+    int D = B->M->dim;
+    double mu, var, dmu[3], dvar[3];
+    posterior_grad_point(B->M, x, &mu, &var, dmu, dvar, B->kb, B->dkb, B->v, B->w);
+    *g = margin(side, B->theta, mu, var);
+    if (!(var > 0.0)) return 0;
+    double sd = sqrt(var);
+    for (int d = 0; d < D; ++d) {
+        double dsd = dvar[d] / (2.0 * sd);
+        grad[d] = side * (-dmu[d] * sd - (B->theta - mu) * dsd) / var;
+    }
+    return 1;
+}
+
+/* Fixed-budget search for the minimum of g over the box [blo, bhi]: the 3^D lattice
+ * {lo, mid, hi}^D (lowest index wins ties), then `steps` projected steps of length
+ * 2^-(k+1) of the box width along the normalised, box-scaled negative gradient. */
+static double bound_search(bound_ws* B, double side, const double* blo, const double* bhi, int steps,
+                           double* gap_out)
+{
+    int D = B->M->dim;
+    int npt = 1;
+    for (int d = 0; d < D; ++d) npt *= 3;
+    double best = INFINITY, second = INFINITY, xbest[3];
+    for (int i = 0; i < npt; ++i) {
+        double x[3];
+        int r = i;
+        for (int d = 0; d < D; ++d) {
+            int digit = r % 3;
+            r /= 3;
+            x[d] = digit == 0 ? blo[d] : (digit == 1 ? 0.5 * (blo[d] + bhi[d]) : bhi[d]);
+        }
+        double g = margin_at(B, side, x);
+        if (g < best) {
+            second = best;
+            best = g;
+            memcpy(xbest, x, sizeof(double) * D);
+        } else if (g < second) {
+            second = g;
+        }
+    }
+    if (gap_out) *gap_out = second - best;
+    double gmin = best, x[3], w[3];
+    memcpy(x, xbest, sizeof(double) * D);
+    for (int d = 0; d < D; ++d) w[d] = bhi[d] - blo[d];
+    double eta = 0.5;
+    for (int k = 0; k < steps; ++k, eta *= 0.5) {
+        double g, grad[3];
+        if (!margin_grad_at(B, side, x, &g, grad)) break;
+        double u[3], nrm = 0.0;
+        for (int d = 0; d < D; ++d) { u[d] = w[d] * grad[d]; nrm += u[d] * u[d]; }
+        nrm = sqrt(nrm);
+        if (!(nrm > 0.0) || !isfinite(nrm)) break;
+        for (int d = 0; d < D; ++d) {
+            double xn = x[d] - eta * w[d] * u[d] / nrm;
+            x[d] = xn < blo[d] ? blo[d] : (xn > bhi[d] ? bhi[d] : xn);
+        }
+        double gn = margin_at(B, side, x);
+        if (gn < gmin) gmin = gn;
+    }
+    return gmin;
+}
+
+/* Upper bound 1 - B^d of eq. (upper_bound) for one side, with B = Phi(g_min), computed as
+ * -expm1(d log1p(-t)) with the tail t = erfc(g_min / sqrt2) / 2. */
+double orc_upper_bound(double gmin, int64_t d)
+{
+    double t;
+    if (gmin == INFINITY) t = 0.0;
+    else if (gmin == -INFINITY) t = 1.0;
+    else t = 0.5 * erfc(gmin / sqrt(2.0));
+    if (t >= 1.0) return 1.0;
+    return -expm1((double)d * log1p(-t));
+}
+
+int orc_bound(const orc_model* M, double theta, double side, const double* blo, const double* bhi, int steps,
+              double* gmin, double* gap)
+{
+    int m = M->m;
+    double* buf = (double*)malloc(sizeof(double) * (size_t)m * 6);
+    if (!buf) return ORC_ENOMEM;
+    bound_ws B = {M, theta, buf, buf + m, buf + 4 * (size_t)m, buf + 5 * (size_t)m};
+    *gmin = bound_search(&B, side, blo, bhi, steps, gap);
+    free(buf);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------- octree (Alg. 1) -- */
+
+static uint64_t morton(int D, const int64_t* c, int level)
+{
+    uint64_t key = 0;
+    for (int b = 0; b < level; ++b)
+        for (int d = 0; d < D; ++d)
+            key |= (uint64_t)((c[d] >> b) & 1) << (b * D + d);
+    return key;
+}
+
+typedef struct {
+    const orc_model* M;
+    const orc_grid* G;
+    const orc_adapt* A;
+    double theta;
+    const double* qlo;   /* P(Y_i < theta) per observation */
+    const double* qhi;   /* P(Y_i > theta) per observation */
+    int64_t S0;          /* root edge in cells (power of two) */
+    int Lmax;
+    omp_lock_t lock;
+    uint64_t* leaves; int64_t leaf_cap; int64_t n_leaves;
+    uint64_t* skipped; int64_t skip_cap; int64_t n_skipped;
+    orc_node_rec* recs; int64_t rec_cap; int64_t n_recs;
+} octree_ctx;
+
+static void push(octree_ctx* T, uint64_t* arr, int64_t cap, int64_t* n, uint64_t key)
+{
+    omp_set_lock(&T->lock);
+    if (*n < cap) arr[*n] = key;
+    ++*n;
+    omp_unset_lock(&T->lock);
+}
+
+static void octree_node(octree_ctx* T, int level, const int64_t* c)
+{
+    const orc_model* M = T->M;
+    const orc_grid* G = T->G;
+    int D = G->dim;
+    int64_t s = T->S0 >> level;
+    int64_t clo[3], chi[3];
+    double blo[3], bhi[3];
+    int64_t d_pts = 1;
+    for (int d = 0; d < D; ++d) {
+        clo[d] = c[d] * s;
+        chi[d] = (c[d] + 1) * s;
+        if (chi[d] > G->n[d] - 1) chi[d] = G->n[d] - 1;
+        blo[d] = vertex_coord(G, d, clo[d]);
+        bhi[d] = vertex_coord(G, d, chi[d]);
+        d_pts *= chi[d] - clo[d] + 1;
+    }
+    orc_node_rec rec;
+    memset(&rec, 0, sizeof rec);
+    rec.key = ((uint64_t)level << 58) | morton(D, c, level);
+    rec.level = level;
+    rec.d = d_pts;
+    rec.gmin = NAN;
+    rec.ub = NAN;
+    rec.lattice_gap = NAN;
+
+    int subdivide = 0;
+    if (level == T->Lmax && !T->A->bound_at_max_depth) {
+        rec.path = 3;
+        subdivide = 1;
+    } else {
+        /* M~: observations inside the closed node box; p1, p2 over M~. */
+        int nobs = 0;
+        double p1 = 0.0, p2 = 0.0;
+        for (int i = 0; i < M->m; ++i) {
+            int in = 1;
+            for (int d = 0; d < D; ++d) {
+                double xi = M->X[(int64_t)i * D + d];
+                if (!(xi >= blo[d] && xi <= bhi[d])) { in = 0; break; }
+            }
+            if (!in) continue;
+            if (nobs == 0 || T->qlo[i] > p1) p1 = T->qlo[i];
+            if (nobs == 0 || T->qhi[i] > p2) p2 = T->qhi[i];
+            ++nobs;
+        }
+        rec.n_obs = nobs;
+        rec.p1 = p1;
+        rec.p2 = p2;
+        double alpha = T->A->alpha;
+        if (nobs > 0 && p1 > alpha && p2 > alpha) {
+            rec.path = 0;
+            subdivide = 1;
+        } else {
+            double side;
+            if (nobs > 0) {
+                side = (p2 <= alpha) ? 1.0 : -1.0;
+            } else {
+                double xc[3], mu, var;
+                double* kb = (double*)malloc(sizeof(double) * (size_t)M->m * 2);
+                for (int d = 0; d < D; ++d) xc[d] = 0.5 * (blo[d] + bhi[d]);
+                posterior_point(M, xc, &mu, &var, kb, kb + M->m);
+                free(kb);
+                side = (mu < T->theta) ? 1.0 : -1.0;
+            }
+            rec.path = side > 0 ? 1 : 2;
+            double gap;
+            orc_bound(M, T->theta, side, blo, bhi, T->A->steps, &rec.gmin, &gap);
+            rec.lattice_gap = gap;
+            rec.ub = orc_upper_bound(rec.gmin, d_pts);
+            subdivide = rec.ub > alpha;
+        }
+    }
+    rec.subdivide = subdivide;
+    omp_set_lock(&T->lock);
+    if (T->recs && T->n_recs < T->rec_cap) T->recs[T->n_recs] = rec;
+    ++T->n_recs;
+    omp_unset_lock(&T->lock);
+
+    if (!subdivide) {
+        push(T, T->skipped, T->skip_cap, &T->n_skipped, rec.key);
+        return;
+    }
+    if (level == T->Lmax) {
+        push(T, T->leaves, T->leaf_cap, &T->n_leaves, rec.key);
+        return;
+    }
+    int nchild = 1 << D;
+    for (int i = 0; i < nchild; ++i) {
+        int64_t cc[3] = {0, 0, 0};
+        int empty = 0;
+        for (int d = 0; d < D; ++d) {
+            cc[d] = 2 * c[d] + ((i >> d) & 1);
+            if (cc[d] * (s >> 1) >= G->n[d] - 1) empty = 1;
+        }
+        if (empty) continue;
+#pragma omp task firstprivate(cc) if (level < 4)
+        octree_node(T, level + 1, cc);
+    }
+}
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y);
+}
+
+static int cmp_rec(const void* a, const void* b)
+{
+    uint64_t x = ((const orc_node_rec*)a)->key, y = ((const orc_node_rec*)b)->key;
+    return x < y ? -1 : (x > y);
+}
+
+/* Root edge S0 = smallest power of two >= max_d (n_d - 1) cells; L_max = log2(S0 / min_leaf). */
+void orc_octree_shape(const orc_grid* G, int min_leaf, int64_t* S0, int* Lmax)
+{
+    int64_t mx = 1;
+    for (int d = 0; d < G->dim; ++d) if (G->n[d] - 1 > mx) mx = G->n[d] - 1;
+    int64_t s = 1;
+    while (s < mx) s <<= 1;
+    int l = 0;
+    while ((s >> l) > min_leaf) ++l;
+    *S0 = s;
+    *Lmax = l;
+}
+
+/*
+ * Alg. 1 (octree adaptive query) from the root.  Observation tail probabilities are
+ * P(Y_i < theta) and P(Y_i > theta) under N(mu_i, A_ii), the latent posterior at x_i.
+ * Leaves (set S) and skipped nodes are returned sorted by key; recs (optional) receives
+ * one record per visited node, sorted by key.  Returns ORC_ECAP if a list overflowed
+ * (counts are still exact).
+ */
+int orc_adaptive(const orc_model* M, const orc_grid* G, double theta, const orc_adapt* A,
+                 uint64_t* leaves, int64_t leaf_cap, int64_t* n_leaves,
+                 uint64_t* skipped, int64_t skip_cap, int64_t* n_skipped,
+                 orc_node_rec* recs, int64_t rec_cap, int64_t* n_recs)
+{
+    int m = M->m;
+    double* qlo = (double*)malloc(sizeof(double) * (size_t)m);
+    double* qhi = (double*)malloc(sizeof(double) * (size_t)m);
+    double* mu = (double*)malloc(sizeof(double) * (size_t)m);
+    double* var = (double*)malloc(sizeof(double) * (size_t)m);
+    if (!qlo || !qhi || !mu || !var) { free(qlo); free(qhi); free(mu); free(var); return ORC_ENOMEM; }
+    orc_posterior(M, m, M->X, mu, var, NULL);
+    for (int i = 0; i < m; ++i) {
+        if (var[i] > 0.0) {
+            double z = (theta - mu[i]) / sqrt(var[i]);
+            qlo[i] = 0.5 * erfc(-z / sqrt(2.0));
+            qhi[i] = 0.5 * erfc(z / sqrt(2.0));
+        } else {
+            qlo[i] = mu[i] < theta ? 1.0 : 0.0;
+            qhi[i] = mu[i] > theta ? 1.0 : 0.0;
+        }
+    }
+    octree_ctx T;
+    memset(&T, 0, sizeof T);
+    T.M = M; T.G = G; T.A = A; T.theta = theta; T.qlo = qlo; T.qhi = qhi;
+    orc_octree_shape(G, A->min_leaf, &T.S0, &T.Lmax);
+    T.leaves = leaves; T.leaf_cap = leaf_cap;
+    T.skipped = skipped; T.skip_cap = skip_cap;
+    T.recs = recs; T.rec_cap = rec_cap;
+    omp_init_lock(&T.lock);
+    int64_t root[3] = {0, 0, 0};
+#pragma omp parallel
+#pragma omp single
+    octree_node(&T, 0, root);
+    omp_destroy_lock(&T.lock);
+    int64_t nl = T.n_leaves < leaf_cap ? T.n_leaves : leaf_cap;
+    int64_t ns = T.n_skipped < skip_cap ? T.n_skipped : skip_cap;
+    int64_t nr = T.n_recs < rec_cap ? T.n_recs : rec_cap;
+    if (leaves) qsort(leaves, (size_t)nl, sizeof(uint64_t), cmp_u64);
+    if (skipped) qsort(skipped, (size_t)ns, sizeof(uint64_t), cmp_u64);
+    if (recs) qsort(recs, (size_t)nr, sizeof(orc_node_rec), cmp_rec);
+    *n_leaves = T.n_leaves;
+    *n_skipped = T.n_skipped;
+    if (n_recs) *n_recs = T.n_recs;
+    free(qlo); free(qhi); free(mu); free(var);
+    if (T.n_leaves > leaf_cap || T.n_skipped > skip_cap || (recs && T.n_recs > rec_cap)) return ORC_ECAP;
+    return ORC_OK;
+}
+
+static void key_decode(int D, uint64_t key, int* level, int64_t* c)
+{
+    *level = (int)(key >> 58);
+    uint64_t mc = key & ((1ull << 58) - 1);
+    for (int d = 0; d < D; ++d) c[d] = 0;
+    for (int b = 0; b < *level; ++b)
+        for (int d = 0; d < D; ++d)
+            c[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
+}
+
+/* LCP of every cell inside the given leaves (only these are reconstructed); each
+ * cell is computed exactly as in the dense path.  lcp covers the whole cell grid and
+ * is written only inside leaves. */
+int orc_lcp_leaves(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb,
+                   int64_t S0, const uint64_t* keys, int64_t nkeys, double* lcp)
+{
+    int D = G->dim;
+    int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nkeys; ++t) {
+        int level;
+        int64_t c[3], clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0}, box_n[3] = {1, 1, 1};
+        key_decode(D, keys[t], &level, c);
+        int64_t s = S0 >> level;
+        for (int d = 0; d < D; ++d) {
+            clo[d] = c[d] * s;
+            chi[d] = (c[d] + 1) * s;
+            if (chi[d] > G->n[d] - 1) chi[d] = G->n[d] - 1;
+            box_n[d] = chi[d] - clo[d] + 1;
+        }
+        double *mean = NULL, *var = NULL, *V = NULL;
+        int64_t nv;
+        if (box_posterior(M, G, clo, box_n, &mean, &var, &V, &nv) != ORC_OK) {
+#pragma omp atomic write
+            rc = ORC_ENOMEM;
+        } else {
+            int64_t cn[3] = {1, 1, 1}, ncell = 1;
+            for (int d = 0; d < D; ++d) { cn[d] = chi[d] - clo[d]; ncell *= cn[d]; }
+            for (int64_t u = 0; u < ncell; ++u) {
+                int64_t cell[3], r = u, lin = 0, stride = 1;
+                for (int d = 0; d < D; ++d) { cell[d] = clo[d] + r % cn[d]; r /= cn[d]; }
+                for (int d = 0; d < D; ++d) { lin += cell[d] * stride; stride *= G->n[d] - 1; }
+                int64_t cnt = cell_count(M, G, theta, ns, zb, cell, clo, box_n, mean, var, V);
+                lcp[lin] = (double)cnt / (double)ns;
+            }
+        }
+        free(mean); free(var); free(V);
+    }
+    return rc;
+}
+
+/* Octree level at which each cell's node stopped (leaf level for cells in S). */
+void orc_level_field(const orc_grid* G, int64_t S0, const uint64_t* keys, int64_t nkeys, uint8_t* field)
+{
+    int D = G->dim;
+    for (int64_t t = 0; t < nkeys; ++t) {
+        int level;
+        int64_t c[3], clo[3] = {0, 0, 0}, chi[3] = {1, 1, 1};
+        key_decode(D, keys[t], &level, c);
+        int64_t s = S0 >> level;
+        for (int d = 0; d < D; ++d) {
+            clo[d] = c[d] * s;
+            chi[d] = (c[d] + 1) * s;
+            if (chi[d] > G->n[d] - 1) chi[d] = G->n[d] - 1;
+        }
+        for (int64_t k = clo[2]; k < (D > 2 ? chi[2] : 1); ++k)
+            for (int64_t j = clo[1]; j < chi[1]; ++j)
+                for (int64_t i = clo[0]; i < chi[0]; ++i)
+                    field[i + (G->n[0] - 1) * (j + (G->n[1] - 1) * k)] = (uint8_t)level;
+    }
+}
+
+int orc_num_threads(void)
+{
+    return omp_get_max_threads();
+}

@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs shared by the oracle-based tests, the GPU path and the bench.
+
+This module only *draws* inputs: observation locations, observation values of a
+synthetic field, kernel hyper-parameters, the grid, the iso-value and the bank of
+standard-normal draws used by the Monte Carlo cell estimate.  It contains none of
+the method's arithmetic (no covariance, posterior, probability or bound), so the
+oracle and the HIP path can both consume its arrays without sharing any code.
+
+The paper evaluates on two datasets (Tangle, Ethanediol, Sec. 5.3) that are not
+available here; the workloads below stand in for them at the paper's scale
+(m = 50 / 500 observations, 128^3 target grid, Sec. 5.3 and Sec. 6.1), with the
+Monte Carlo sample count of Sec. 5.4 (1600) and the threshold alpha = 1e-3 of
+Sec. 6.3.  Every random number the method consumes (the z-bank) is drawn here
+and passed in as an input.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+SE = 0        # squared-exponential (RBF) covariance, Sec. 3
+MATERN52 = 1  # Matern-5/2 covariance (textbook form; not used by the paper)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dim: int
+    kind: int
+    signal_var: float
+    lengthscale: np.ndarray      # (3,) float64, unused trailing entries = 1
+    noise_var: float
+    X: np.ndarray                # (m, dim) float64 observation locations
+    y: np.ndarray                # (m,) float64 observation values
+    lo: np.ndarray               # (3,) grid lower corner
+    hi: np.ndarray               # (3,) grid upper corner
+    npts: np.ndarray             # (3,) int64 vertices per axis (trailing = 1)
+    theta: float                 # iso-value
+    alpha: float                 # skip threshold of the octree query
+    min_leaf: int                # finest octree node edge, in cells
+    zbank: np.ndarray            # (n_samples, 2**dim) float64 N(0,1) draws
+    seed: int = 0
+
+    @property
+    def m(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def n_vertices(self) -> int:
+        return int(np.prod(self.npts[: self.dim]))
+
+    @property
+    def n_cells(self) -> int:
+        return int(np.prod(self.npts[: self.dim] - 1))
+
+    @property
+    def cell_shape(self) -> tuple:
+        """Cell-array shape, slowest axis first (x is the fastest axis)."""
+        return tuple(int(v - 1) for v in self.npts[: self.dim][::-1])
+
+    @property
+    def n_samples(self) -> int:
+        return int(self.zbank.shape[0])
+
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng([int(seed), int(stream)])
+
+
+def _bumps(P, amp, ctr, wid):
+    """Sum of Gaussian bumps; wid has shape (nb,) (isotropic) or (nb, dim)."""
+    d = P[:, None, :] - ctr[None, :, :]
+    if wid.ndim == 1:
+        q = (d * d).sum(-1) / (wid[None, :] ** 2)
+    else:
+        q = ((d / wid[None, :, :]) ** 2).sum(-1)
+    return (amp[None, :] * np.exp(-0.5 * q)).sum(-1)
+
+
+def _zbank(seed, n_samples, dim):
+    return _rng(seed, 4).standard_normal((n_samples, 2 ** dim))
+
+
+def _pad3(v, fill):
+    out = np.full(3, fill, dtype=np.float64)
+    out[: len(v)] = v
+    return out
+
+
+def field2d_bumps(seed: int, m: int = 50, npts: int = 64, n_samples: int = 1600,
+                  name: str = "cfg1_2d") -> Workload:
+    """2D plain method: m uniform locations, 5 isotropic bumps, SE l=0.1, s2=1."""
+    X = _rng(seed, 1).random((m, 2))
+    r = _rng(seed, 2)
+    amp = r.uniform(0.5, 1.0, 5)
+    wid = r.uniform(0.05, 0.2, 5)
+    ctr = r.random((5, 2))
+    y = _bumps(X, amp, ctr, wid)
+    return Workload(name, 2, SE, 1.0, _pad3([0.1, 0.1], 1.0), 1e-4, X, y,
+                    _pad3([0, 0], 0.0), _pad3([1, 1], 0.0),
+                    np.array([npts, npts, 1], np.int64), 0.5, 1e-3, 4,
+                    _zbank(seed, n_samples, 2), seed)
+
+
+def field3d_aniso(seed: int, m: int = 200, npts: int = 64, n_samples: int = 1600,
+                  signal_var: float = 0.1, name: str = "cfg2_3d") -> Workload:
+    """3D plain vs FP32: Sobol locations, 8 anisotropic bumps + 0.01 N(0,1) noise,
+    ARD SE lengthscales (0.08, 0.12, 0.1), iso-value = median of y."""
+    import warnings
+    from scipy.stats import qmc
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")  # m need not be a power of two
+        X = qmc.Sobol(3, scramble=True, seed=_rng(seed, 1)).random(m)
+    r = _rng(seed, 2)
+    amp = r.uniform(0.5, 1.0, 8)
+    wid = r.uniform(0.05, 0.2, (8, 3))
+    ctr = r.random((8, 3))
+    y = _bumps(X, amp, ctr, wid) + 0.01 * _rng(seed, 3).standard_normal(m)
+    return Workload(name, 3, SE, signal_var, np.array([0.08, 0.12, 0.1]), 1e-4, X, y,
+                    np.zeros(3), np.ones(3), np.array([npts] * 3, np.int64),
+                    float(np.median(y)), 1e-3, 4, _zbank(seed, n_samples, 3), seed)
+
+
+def field3d_trig(seed: int, m: int = 500, npts: int = 128, n_samples: int = 1600,
+                 signal_var: float = 1e-3, name: Optional[str] = None,
+                 iso_quantile: float = 0.5) -> Workload:
+    """3D at the paper's scale: m uniform locations, f = sin(6x)cos(5y)sin(4z)
+    + 0.3 * (8 isotropic bumps), noise variance 1e-5, Matern-5/2 l=0.1."""
+    X = _rng(seed, 1).random((m, 3))
+    r = _rng(seed, 2)
+    amp = r.uniform(0.5, 1.0, 8)
+    wid = r.uniform(0.05, 0.2, 8)
+    ctr = r.random((8, 3))
+    f = np.sin(6 * X[:, 0]) * np.cos(5 * X[:, 1]) * np.sin(4 * X[:, 2])
+    y = f + 0.3 * _bumps(X, amp, ctr, wid) + np.sqrt(1e-5) * _rng(seed, 3).standard_normal(m)
+    return Workload(name or f"cfg3_{npts}", 3, MATERN52, signal_var, np.array([0.1, 0.1, 0.1]),
+                    1e-5, X, y, np.zeros(3), np.ones(3), np.array([npts] * 3, np.int64),
+                    float(np.quantile(y, iso_quantile)), 1e-3, 4,
+                    _zbank(seed, n_samples, 3), seed)
+
+
+def random_small(seed: int, dim: int, m: int, npts, kind: int = SE, n_samples: int = 1600,
+                 signal_var: float = 1.0, ell: float = 0.25, noise_var: float = 1e-4,
+                 min_leaf: int = 1, alpha: float = 1e-3) -> Workload:
+    """Tiny random problem for unit and brute-force tests."""
+    npts = np.atleast_1d(np.asarray(npts, np.int64))
+    if npts.size == 1:
+        npts = np.repeat(npts, dim)
+    X = _rng(seed, 1).random((m, dim))
+    y = np.sin(3.0 * X.sum(1)) + 0.1 * _rng(seed, 3).standard_normal(m)
+    return Workload(f"small{dim}d", dim, kind, signal_var, _pad3([ell] * dim, 1.0), noise_var, X, y,
+                    _pad3([0.0] * dim, 0.0), _pad3([1.0] * dim, 0.0),
+                    np.concatenate([npts, np.ones(3 - dim, np.int64)]),
+                    float(np.median(y)), alpha, min_leaf, _zbank(seed, n_samples, dim), seed)
+
+
+def make(name: str, seed: int = 0, **kw) -> Workload:
+    """Named workloads: cfg1_2d, cfg2_3d, cfg3_128, cfg3_256 and reduced variants."""
+    if name == "cfg1_2d":
+        return field2d_bumps(seed, **kw)
+    if name == "cfg2_3d":
+        return field3d_aniso(seed, **kw)
+    if name == "cfg3_128":
+        return field3d_trig(seed, npts=128, **kw)
+    if name == "cfg3_256":
+        return field3d_trig(seed, npts=256, **kw)
+    if name.startswith("cfg3_"):
+        return field3d_trig(seed, npts=int(name.split("_")[1]), **kw)
+    raise KeyError(name)
