@@ -1,0 +1,176 @@
+/*
+ * lcp.h -- C ABI of the MI355X (gfx950) level-crossing-probability library.
+ *
+ * Implements the hot path of Li, Michaud, Biswas, Shen, "Efficient Level-Crossing
+ * Probability Calculation for Gaussian Process Modeled Data" (arXiv 2512.12442):
+ * the GP posterior at grid vertices (Sec. 3, eq. (sgp) in its exact-GP form), the
+ * per-cell level-crossing probability by Monte Carlo (Sec. 4), and the regional
+ * upper bound of eq. (upper_bound) driving the octree query of Alg. 1 (Sec. 4.1,
+ * 4.3), with reconstruction only inside the emitted nodes (end of Sec. 4.3).
+ *
+ * Conventions
+ *  - Every pointer argument is a DEVICE pointer unless its comment says "host".
+ *  - Floating-point inputs are IEEE binary64.  Arrays are dense and row-major;
+ *    grid vertices and cells are ordered with x fastest, then y, then z.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is enqueued
+ *    on it; only gp_fit_factor synchronises it (once, to read the factorisation
+ *    status).  Calls that share a model or workspace must not run concurrently.
+ *  - The library never allocates device memory: the caller passes the model
+ *    memory and a workspace, sized by lcp_model_bytes / lcp_workspace_bytes, and
+ *    keeps them alive while any enqueued work may still use them.
+ *  - Every call returns an lcp_status.  Arguments are validated on the host before
+ *    anything is enqueued; on error nothing is enqueued and lcp_last_error()
+ *    describes the problem (thread-local string, valid until the next call).
+ */
+#ifndef LCP_H
+#define LCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LCP_OK = 0,
+    LCP_EINVAL = 1,          /* invalid argument (sizes, pointers, parameters) */
+    LCP_ENOTPD = 2,          /* K + noise I is numerically singular (Cholesky pivot <= m eps max K_ii) */
+    LCP_ECAPACITY = 3,       /* an output list is smaller than the result; *count holds the true size */
+    LCP_ENOMEM = 4,          /* model memory or workspace smaller than required */
+    LCP_EDEVICE = 5,         /* a HIP runtime call failed */
+    LCP_ENOTSUPPORTED = 6    /* operation not provided by this build */
+} lcp_status;
+
+typedef enum {
+    LCP_KERNEL_SE = 0,       /* squared exponential s2 exp(-r^2/2), Sec. 3 (the paper's RBF, ARD allowed) */
+    LCP_KERNEL_MATERN52 = 1  /* Matern-5/2 s2 (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r), textbook form */
+} lcp_kernel_kind;           /* r^2 = sum_d ((x_d - z_d) / lengthscale_d)^2 */
+
+typedef enum {
+    LCP_FP64 = 0,            /* every step in binary64 */
+    LCP_FP32 = 1,            /* V = L^-1 K*^T on FP32 MFMA; mean, norms, cell factor in FP64; MC in FP32 */
+    LCP_MIXED_BF16X3 = 2,    /* V on BF16 MFMA with a 3-term split product (hi*hi + hi*lo + lo*hi), FP32
+                                accumulation; mean, norms, cell factor in FP64; MC in FP32 */
+    LCP_MIXED_F16X3 = 3      /* as LCP_MIXED_BF16X3 with FP16 halves (22-bit split) on power-of-two scaled
+                                operands; about FP32 accuracy at 16-bit MFMA rate */
+} lcp_precision;
+
+typedef struct {
+    int kind;                /* lcp_kernel_kind */
+    int dim;                 /* 2 or 3 */
+    double signal_var;       /* s2 > 0 */
+    double lengthscale[3];   /* > 0; entries beyond dim are ignored */
+    double noise_var;        /* observation-noise variance >= 0 */
+} lcp_kernel;
+
+typedef struct {
+    int dim;                 /* 2 or 3 (must equal the model's) */
+    double lo[3], hi[3];     /* domain box; vertex i on axis d sits at lo + i (hi - lo) / (npts - 1) */
+    int64_t npts[3];         /* vertices per axis, >= 2 for d < dim; cells per axis = npts - 1 */
+} lcp_grid;
+
+typedef struct {
+    double alpha;            /* skip threshold of Alg. 1, 0 < alpha < 0.5 (the paper uses 1e-3, Sec. 6.3) */
+    int min_leaf_cells;      /* finest node edge in cells, a power of two >= 1 (max depth of Alg. 1);
+                                the octree may have at most 8 levels (root edge / min_leaf_cells <= 128) */
+    int bound_at_max_depth;  /* 1: region test at the finest level too (Alg. 1 as printed); 0: emit */
+    int descent_steps;       /* projected-gradient steps of the bound search after the 3^D lattice, 0..16 */
+} lcp_adapt;
+
+typedef struct {
+    int n_samples;           /* N_s >= 1 (the paper uses 1600, Sec. 5.4) */
+    const double* zbank;     /* n_samples x 2^dim standard normals, shared by every cell (device) */
+} lcp_mc;
+
+typedef struct lcp_model lcp_model;   /* opaque host handle over caller-owned device memory */
+
+/* Status text and the thread's last error message. */
+const char* lcp_status_str(int status);
+const char* lcp_last_error(void);
+
+/* Bytes of device memory a model with m observations needs. */
+size_t lcp_model_bytes(int m, int dim);
+
+/*
+ * gp_fit_factor -- factor the GP model (Sec. 3; the inducing set of eq. (sgp) is the
+ * observation set, so mu_M and A_M are the latent posterior at the observations).
+ * Builds K = k(X, X) + noise I in binary64, its Cholesky factor L, the explicit
+ * inverse L^-1 (binary64, plus FP32 and split-BF16 copies), a = K^-1 y, and the
+ * posterior mean and variance at each observation (used by the preliminary node
+ * test of Alg. 1).
+ *   k        (host) kernel description
+ *   m        number of observations, 1 <= m <= 1024
+ *   X        m x dim observation locations (device, binary64)
+ *   y        m observation values (device, binary64)
+ *   model_mem, model_bytes   caller-owned device memory of >= lcp_model_bytes(m, dim)
+ *            bytes, 256-byte aligned; it holds every device array of the model and must
+ *            outlive the handle
+ *   out      (host) receives the handle; free it with gp_model_free
+ * Synchronises `stream` once.  Returns LCP_ENOTPD if a pivot is not above
+ * m * eps * max_i K_ii (no jitter is added).
+ */
+int gp_fit_factor(const lcp_kernel* k, int m, const double* X, const double* y, void* model_mem,
+                  size_t model_bytes, void* stream, lcp_model** out);
+
+void gp_model_free(lcp_model* model);
+
+/* Size queries of the workspace of each operation (host results); the workspace must be
+ * 256-byte aligned.  n_samples is the Monte Carlo sample count the call will use. */
+int lcp_posterior_workspace(const lcp_model* model, int64_t n, int prec, size_t* bytes);
+int lcp_dense_workspace(const lcp_model* model, const lcp_grid* grid, int prec, int n_samples, size_t* bytes);
+int lcp_adaptive_workspace(const lcp_model* model, const lcp_grid* grid, const lcp_adapt* adapt, int prec,
+                           int n_samples, size_t* bytes);
+
+/*
+ * gp_posterior -- latent posterior mean and variance at n query points (eq. (sgp),
+ * exact-GP form): mean = k*^T a, var = max(0, s2 - ||L^-1 k*||^2).
+ *   Xq    n x dim query points; mean, var: n outputs (binary64).
+ *   prec  lcp_precision of V = L^-1 k*^T (mean is always accumulated in binary64).
+ */
+int gp_posterior(const lcp_model* model, int64_t n, const double* Xq, int prec, double* mean, double* var,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * lcp_dense -- the dense baseline of Sec. 4: posterior at every grid vertex, the
+ * 2^dim-corner covariance of every cell, its (semidefinite) Cholesky factor C and the
+ * Monte Carlo estimate LCP = #{s : not all corners below theta and not all above} / N_s
+ * with corner values mu + C z_s.  A sample equal to theta counts as crossed.
+ *   lcp   prod(npts - 1) cells (binary32, x fastest).
+ */
+int lcp_dense(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec,
+              float* lcp, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * lcp_adaptive -- Alg. 1 (octree adaptive query) on the full model followed by the
+ * reconstruction of Sec. 4.3's last paragraph: cells inside the emitted nodes get the
+ * same Monte Carlo LCP as lcp_dense (same precision, same z-bank); all other cells get 0.
+ * The region test (preliminary decision on the observations inside the closed node box,
+ * then the bound 1 - B^d of eq. (upper_bound) with B from a bounded search of F_M) runs
+ * in binary64 regardless of `prec`.
+ *   lcp          prod(npts - 1) cells (binary32)
+ *   leaves       leaf_cap keys of the emitted nodes, key = level << 58 | Morton(node), ascending
+ *   n_leaves     (device) receives the number of emitted nodes
+ *   level_field  optional (may be NULL): per cell, the octree level at which its node stopped
+ * If the emitted set exceeds leaf_cap, the first leaf_cap keys are written, *n_leaves
+ * receives the true count, and the reconstruction is not performed (LCP stays zero); the
+ * caller sees this after synchronising the stream.
+ */
+int lcp_adaptive(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_adapt* adapt,
+                 const lcp_mc* mc, int prec, float* lcp, uint64_t* leaves, int64_t leaf_cap, int64_t* n_leaves,
+                 uint8_t* level_field, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * lcp_backward -- adjoint of the LCP field with respect to the observation values and
+ * log-lengthscales.  Not provided by this build: the Monte Carlo estimator of Sec. 4 is
+ * piecewise constant in its inputs.  Always returns LCP_ENOTSUPPORTED.
+ */
+int lcp_backward(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_mc* mc,
+                 const float* dL_dlcp, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCP_H */

@@ -1,0 +1,10 @@
+"""MI355X (gfx950) level-crossing probability for GP-modelled fields.
+
+The hot path of Li, Michaud, Biswas, Shen (arXiv 2512.12442): GP posterior at grid
+vertices (Sec. 3), per-cell Monte Carlo level-crossing probability (Sec. 4), and the
+regional upper bound driving the octree query of Alg. 1 (Sec. 4.1-4.3).  The compute
+runs in the HIP library liblcp.so (C ABI in include/lcp.h); this package only marshals
+arguments.
+"""
+from .lcp import (FP32, FP64, MATERN52, MIXED_BF16X3, MIXED_F16X3, PRECISIONS, SE, Adapt, GPModel, Grid, LcpError,  # noqa: F401
+                  adapt_of, grid_of, lib, make_grid)

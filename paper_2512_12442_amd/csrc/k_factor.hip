@@ -1,0 +1,251 @@
+// Model factorisation on the GPU (binary64): K = k(X, X) + noise I, its Cholesky factor,
+// the explicit inverse L^-1 in the MFMA fragment orders used by the posterior kernel,
+// and a = K^-1 y.  Sec. 3 of the paper with the inducing set equal to the observations.
+#include "lcp_internal.h"
+
+namespace lcp {
+
+size_t model_bytes(int m)
+{
+    int mp = (m + 31) / 32 * 32;
+    size_t b = 0;
+    b += align256(sizeof(double) * mp * 4);          // X
+    b += align256(sizeof(double) * mp);              // a
+    b += align256(sizeof(double) * mp);              // y / w scratch
+    b += align256(sizeof(double) * (size_t)mp * mp); // U
+    b += align256(sizeof(double) * (size_t)mp * mp); // Linv
+    b += align256(sizeof(double) * (size_t)mp * mp); // A64
+    b += align256(sizeof(float) * (size_t)mp * mp);  // A32
+    b += 2 * align256(sizeof(__bf16) * (size_t)mp * mp);  // Ahi, Alo
+    b += 2 * align256(sizeof(_Float16) * (size_t)mp * mp); // Hhi, Hlo
+    b += 256;                                        // amax, sA
+    b += 2 * align256(sizeof(double) * mp);          // obs_mu, obs_var
+    b += 256;                                        // info
+    return b;
+}
+
+__global__ void k_pack(const double* __restrict__ X, const double* __restrict__ y, int m, int mp, int dim,
+                       double* __restrict__ Xp, double* __restrict__ w)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mp) return;
+    for (int d = 0; d < 4; ++d) Xp[i * 4 + d] = (i < m && d < dim) ? X[(int64_t)i * dim + d] : 0.0;
+    w[i] = i < m ? y[i] : 0.0;
+}
+
+__global__ void k_build_K(KParams kp, const double* __restrict__ Xp, int m, int mp, double noise,
+                          double* __restrict__ K)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    int i = (int)(t / mp), j = (int)(t % mp);
+    double v = 0.0;
+    if (i < m && j < m) {
+        v = kernel_val(kp, kernel_r2(kp, Xp + i * 4, Xp + j * 4));
+        if (i == j) v += noise;
+    }
+    K[t] = v;
+}
+
+// Left-looking Cholesky of the leading m x m block of K (row-major, leading dim mp), in
+// place: on exit row j of the array holds row j of U = L^T (U[j][i] = L[i][j], i >= j).
+// One work-group; thread i owns column i's running diagonal d_i = K_ii - sum_k U[k][i]^2.
+__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ U, int m, int mp, double piv_min,
+                                                   int* __restrict__ info)
+{
+    __shared__ double d[kMaxM];
+    __shared__ double ucol[kMaxM];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < m; i += nt) d[i] = U[(int64_t)i * mp + i];
+    if (tid == 0) *info = 0;
+    for (int j = 0; j < m; ++j) {
+        __syncthreads();
+        double piv = d[j];
+        if (!(piv > piv_min)) {
+            if (tid == 0) *info = j + 1;
+            return;
+        }
+        double ujj = sqrt(piv);
+        for (int k = tid; k < j; k += nt) ucol[k] = U[(int64_t)k * mp + j];
+        __syncthreads();
+        double inv = 1.0 / ujj;
+        for (int i = j + 1 + tid; i < m; i += nt) {
+            double s = U[(int64_t)j * mp + i];
+            for (int k = 0; k < j; ++k) s = fma(-ucol[k], U[(int64_t)k * mp + i], s);
+            double u = s * inv;
+            U[(int64_t)j * mp + i] = u;
+            d[i] = fma(-u, u, d[i]);
+        }
+        if (tid == 0) U[(int64_t)j * mp + j] = ujj;
+    }
+    __syncthreads();
+    // clear the strictly lower part (it still holds K) so U is a clean upper factor
+    for (int64_t t = tid; t < (int64_t)m * m; t += nt) {
+        int i = (int)(t / m), j = (int)(t % m);
+        if (j < i) U[(int64_t)i * mp + j] = 0.0;
+    }
+}
+
+// Explicit inverse of L = U^T row by row: Linv[i][c] = -(sum_{k=c}^{i-1} L[i][k] Linv[k][c]) / L[i][i].
+__global__ void __launch_bounds__(1024) k_trinv(const double* __restrict__ U, double* __restrict__ Li, int m,
+                                                int mp, double* __restrict__ amax)
+{
+    __shared__ double lrow[kMaxM];
+    __shared__ double wmax[16];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int64_t t = tid; t < (int64_t)mp * mp; t += nt) Li[t] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+        for (int k = tid; k <= i; k += nt) lrow[k] = U[(int64_t)k * mp + i];
+        __syncthreads();
+        double inv = 1.0 / lrow[i];
+        for (int c = tid; c <= i; c += nt) {
+            if (c == i) {
+                Li[(int64_t)i * mp + i] = inv;
+            } else {
+                double s = 0.0;
+                for (int k = c; k < i; ++k) s = fma(lrow[k], Li[(int64_t)k * mp + c], s);
+                Li[(int64_t)i * mp + c] = -s * inv;
+            }
+        }
+        __syncthreads();
+    }
+    // largest |Linv| and the power-of-two scale sA that brings it to [2^14, 2^15) (FP16 max is 65504)
+    double mx = 0.0;
+    for (int64_t t = tid; t < (int64_t)mp * mp; t += nt) mx = fmax(mx, fabs(Li[t]));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < nt / 64; ++w) mx = fmax(mx, wmax[w]);
+        mx = fmax(mx, wmax[0]);
+        int e;
+        frexp(mx, &e);                   // mx = f * 2^e, f in [0.5, 1)
+        amax[0] = mx;
+        amax[1] = ldexp(1.0, 15 - e);    // mx * sA in [2^14, 2^15)
+    }
+}
+
+// a = Linv^T (Linv y): w = Linv y, then a_i = sum_{k >= i} Linv[k][i] w_k.
+__global__ void __launch_bounds__(1024) k_alpha(const double* __restrict__ Li, const double* __restrict__ y,
+                                                double* __restrict__ a, int m, int mp)
+{
+    __shared__ double w[kMaxM];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < m; i += nt) {
+        double s = 0.0;
+        for (int k = 0; k <= i; ++k) s = fma(Li[(int64_t)i * mp + k], y[k], s);
+        w[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < mp; i += nt) {
+        double s = 0.0;
+        if (i < m)
+            for (int k = i; k < m; ++k) s = fma(Li[(int64_t)k * mp + i], w[k], s);
+        a[i] = s;
+    }
+}
+
+// Fragment orders of Linv.
+//  16x16x4 (binary64 and binary32): fragment (i, s), lane l holds Linv[16i + l%16][4s + l/16].
+//  16x16x32 bf16: fragment (i, s), lane l holds Linv[16i + l%16][32s + 8(l/16) + e], e = 0..7,
+//  split as hi = bf16(x), lo = bf16(x - hi); the FP16 copy splits x * sA the same way.
+__global__ void k_frag(const double* __restrict__ Li, int mp, double* __restrict__ A64, float* __restrict__ A32,
+                       __bf16* __restrict__ Ahi, __bf16* __restrict__ Alo, _Float16* __restrict__ Hhi,
+                       _Float16* __restrict__ Hlo, const double* __restrict__ amax)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    {
+        int64_t frag = t / 64;
+        int l = (int)(t % 64);
+        int ks = mp / 4;
+        int i = (int)(frag / ks), s = (int)(frag % ks);
+        double x = Li[(int64_t)(16 * i + l % 16) * mp + 4 * s + l / 16];
+        A64[t] = x;
+        A32[t] = (float)x;
+    }
+    {
+        int64_t frag = t / 512;
+        int rem = (int)(t % 512);
+        int l = rem / 8, e = rem % 8;
+        int ks = mp / 32;
+        int i = (int)(frag / ks), s = (int)(frag % ks);
+        double x = Li[(int64_t)(16 * i + l % 16) * mp + 32 * s + 8 * (l / 16) + e];
+        __bf16 hi = (__bf16)(float)x;
+        __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
+        Ahi[t] = hi;
+        Alo[t] = lo;
+        const double xs = x * amax[1];
+        _Float16 h = (_Float16)xs;
+        Hhi[t] = h;
+        Hlo[t] = (_Float16)(xs - (double)h);
+    }
+}
+
+static void carve(Model& M, char* base)
+{
+    int mp = M.m_pad;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char* p = base + o; o += align256(bytes); return p; };
+    M.X = (double*)take(sizeof(double) * mp * 4);
+    M.a = (double*)take(sizeof(double) * mp);
+    double* w = (double*)take(sizeof(double) * mp);
+    (void)w;
+    M.U = (double*)take(sizeof(double) * (size_t)mp * mp);
+    M.Linv = (double*)take(sizeof(double) * (size_t)mp * mp);
+    M.A64 = (double*)take(sizeof(double) * (size_t)mp * mp);
+    M.A32 = (float*)take(sizeof(float) * (size_t)mp * mp);
+    M.Ahi = (__bf16*)take(sizeof(__bf16) * (size_t)mp * mp);
+    M.Alo = (__bf16*)take(sizeof(__bf16) * (size_t)mp * mp);
+    M.Hhi = (_Float16*)take(sizeof(_Float16) * (size_t)mp * mp);
+    M.Hlo = (_Float16*)take(sizeof(_Float16) * (size_t)mp * mp);
+    M.amax = (double*)take(256);
+    M.obs_mu = (double*)take(sizeof(double) * mp);
+    M.obs_var = (double*)take(sizeof(double) * mp);
+    M.info = (int*)take(256);
+}
+
+static double* ybuf(const Model& M)
+{
+    return (double*)((char*)M.a + align256(sizeof(double) * M.m_pad));
+}
+
+hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t s)
+{
+    carve(M, (char*)M.X);
+    int mp = M.m_pad;
+    double* w = ybuf(M);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, X, y, M.m, mp, M.dim, M.X, w);
+    int64_t n2 = (int64_t)mp * mp;
+    hipLaunchKernelGGL(k_build_K, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.kp, M.X, M.m, mp,
+                       M.k.noise_var, M.U);
+    double piv_min = (double)M.m * 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, M.U, M.m, mp, piv_min, M.info);
+    return hipGetLastError();
+}
+
+// After the status has been read: inverse, a, fragments, observation posterior.
+hipError_t launch_factor_finish(Model& M, hipStream_t s)
+{
+    int mp = M.m_pad;
+    int64_t n2 = (int64_t)mp * mp;
+    hipLaunchKernelGGL(k_trinv, dim3(1), dim3(1024), 0, s, M.U, M.Linv, M.m, mp, M.amax);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, s, M.Linv, ybuf(M), M.a, M.m, mp);
+    hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, mp, M.A64, M.A32,
+                       M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PostTask t{};
+    t.mode = COL_POINTS;
+    t.group = 1;
+    t.count = nullptr;
+    t.n_points = M.m;
+    t.pts = M.X;
+    t.pstride = 4;
+    t.mean = M.obs_mu;
+    t.var = M.obs_var;
+    return launch_posterior(M, LCP_FP64, t, s);
+}
+
+}  // namespace lcp

@@ -1,0 +1,730 @@
+// Octree adaptive query (Alg. 1) run level-synchronously on the GPU, followed by the
+// reconstruction of the emitted nodes only (Sec. 4.3, last paragraph).
+//
+// Per level: a wave per frontier node tests the observations inside the closed node box
+// (p1, p2 of Alg. 1); nodes that need the region bound are compacted by a prefix sum and
+// searched in batches (3^D lattice, then projected-gradient steps) through the binary64
+// posterior kernel; UB = 1 - B^d decides; a second prefix sum writes the children in
+// Morton order, so the frontier -- and the leaf list -- stay sorted by key without a sort.
+// All counts stay in device memory: grids are sized by per-level capacities and kernels
+// loop over the device count, so the whole query is enqueued without host round trips.
+#include "lcp_internal.h"
+
+namespace lcp {
+
+namespace {
+
+struct Oct {
+    GridP g;
+    int D;
+    int64_t S0;
+    int Lmax;
+    double theta;
+    double alpha;
+    int bound_at_max;
+    int steps;
+    int64_t nodes[24];       // node lattice extent per level and axis: nodes[l*3 + d]
+    int64_t statoff[8];      // offset of each level's status grid
+};
+
+__device__ __forceinline__ void key_coords(int D, uint64_t key, int& level, int64_t* c)
+{
+    level = (int)(key >> 58);
+    uint64_t mc = key & ((1ull << 58) - 1);
+    c[0] = c[1] = c[2] = 0;
+    for (int b = 0; b < level; ++b)
+        for (int d = 0; d < D; ++d) c[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
+}
+
+__device__ __forceinline__ uint64_t make_key(int D, int level, const int64_t* c)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < level; ++b)
+        for (int d = 0; d < D; ++d) k |= (uint64_t)((c[d] >> b) & 1) << (b * D + d);
+    return ((uint64_t)level << 58) | k;
+}
+
+// Cell range [clo, chi) of a node, its physical box and vertex count d.
+__device__ __forceinline__ void node_box(const Oct& o, int level, const int64_t* c, int64_t* clo, int64_t* chi,
+                                         double* blo, double* bhi, int64_t* dpts)
+{
+    const int64_t s = o.S0 >> level;
+    int64_t d = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (k < o.D) {
+            clo[k] = c[k] * s;
+            chi[k] = (c[k] + 1) * s;
+            if (chi[k] > o.g.nc[k]) chi[k] = o.g.nc[k];
+            blo[k] = vertex_coord(o.g, k, clo[k]);
+            bhi[k] = vertex_coord(o.g, k, chi[k]);
+            d *= chi[k] - clo[k] + 1;
+        } else {
+            clo[k] = 0;
+            chi[k] = 1;
+            blo[k] = bhi[k] = 0.0;
+        }
+    }
+    *dpts = d;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_isum(int v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Standardised margin of one side: side (theta - mu) / sigma with the sigma = 0 limits.
+__device__ __forceinline__ double margin(double side, double theta, double mu, double var)
+{
+    double num = side * (theta - mu);
+    if (var > 0.0) return num / sqrt(var);
+    if (num > 0.0) return __builtin_inf();
+    if (num < 0.0) return -__builtin_inf();
+    return 0.0;
+}
+
+// P(Y_i < theta), P(Y_i > theta) for each observation from its latent posterior.
+__global__ void k_obs_q(const double* __restrict__ mu, const double* __restrict__ var, int m, double theta,
+                        double* __restrict__ qlo, double* __restrict__ qhi)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    if (var[i] > 0.0) {
+        double z = (theta - mu[i]) / sqrt(var[i]);
+        qlo[i] = 0.5 * erfc(-z / 1.41421356237309504880168872421);
+        qhi[i] = 0.5 * erfc(z / 1.41421356237309504880168872421);
+    } else {
+        qlo[i] = mu[i] < theta ? 1.0 : 0.0;
+        qhi[i] = mu[i] > theta ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_root(uint64_t* keys, int64_t* cnt)
+{
+    keys[0] = 0;
+    *cnt = 1;
+}
+
+// Preliminary decision of Alg. 1 for every frontier node (one wave per node).
+// path: 0 subdivide (both sides above alpha), 1 bound below, 2 bound above,
+//       3 finest level emitted without a test, 4 bound with side from the centre mean.
+__global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t* __restrict__ keys,
+                                                const int64_t* __restrict__ nf_dev, int64_t cap,
+                                                const double* __restrict__ X, int m, const double* __restrict__ qlo,
+                                                const double* __restrict__ qhi, int32_t* __restrict__ path,
+                                                int32_t* __restrict__ need, int32_t* __restrict__ sub)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t nf = *nf_dev;
+    if (nf > cap) nf = cap;
+    for (int64_t f = wid; f < nf; f += nw) {
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        int pth;
+        if (level == o.Lmax && !o.bound_at_max) {
+            pth = 3;
+        } else {
+            int nin = 0;
+            double p1 = -1.0, p2 = -1.0;
+            for (int i = lane; i < m; i += 64) {
+                bool in = true;
+                for (int d = 0; d < o.D; ++d) {
+                    double xi = X[i * 4 + d];
+                    in = in && (xi >= blo[d] && xi <= bhi[d]);
+                }
+                if (in) {
+                    ++nin;
+                    p1 = fmax(p1, qlo[i]);
+                    p2 = fmax(p2, qhi[i]);
+                }
+            }
+            nin = wave_isum(nin);
+            p1 = wave_max(p1);
+            p2 = wave_max(p2);
+            if (nin > 0 && p1 > o.alpha && p2 > o.alpha) pth = 0;
+            else if (nin > 0) pth = (p2 <= o.alpha) ? 1 : 2;
+            else pth = 4;
+        }
+        if (lane == 0) {
+            path[f] = pth;
+            need[f] = (pth == 1 || pth == 2 || pth == 4) ? 1 : 0;
+            sub[f] = (pth == 0 || pth == 3) ? 1 : 0;
+        }
+    }
+}
+
+struct BoundBufs {
+    int32_t* bnode;     // bound-node -> frontier index
+    double* side;
+    double* gmin;
+    double* x;          // current search point, 3 per node
+    int32_t* done;
+    double* lat_pts;    // 3^D points per node, 3 doubles each
+    double* lat_mean;
+    double* lat_var;
+    double* gp_mean;    // posterior with gradient at the current point
+    double* gp_var;
+    double* gp_dmean;
+    double* gp_dvar;
+    int64_t* cnt;       // [0] bound nodes, [1] lattice points
+};
+
+__global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
+                              int64_t cap, const int32_t* __restrict__ need, const int32_t* __restrict__ nidx,
+                              BoundBufs B)
+{
+    int64_t nf = *nf_dev;
+    if (nf > cap) nf = cap;
+    const int npt = o.D == 3 ? 27 : 9;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+        if (!need[f]) continue;
+        const int64_t b = nidx[f];
+        B.bnode[b] = (int32_t)f;
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        for (int i = 0; i < npt; ++i) {
+            int r = i;
+            for (int d = 0; d < 3; ++d) {
+                double x = 0.0;
+                if (d < o.D) {
+                    int digit = r % 3;
+                    r /= 3;
+                    x = digit == 0 ? blo[d] : (digit == 1 ? 0.5 * (blo[d] + bhi[d]) : bhi[d]);
+                }
+                B.lat_pts[(b * npt + i) * 3 + d] = x;
+            }
+        }
+    }
+}
+
+// Side choice (centre mean for nodes without observations), lattice minimum, start point.
+__global__ void k_lattice(Oct o, const int32_t* __restrict__ path, BoundBufs B)
+{
+    const int64_t nb = B.cnt[0];
+    const int npt = o.D == 3 ? 27 : 9;
+    const int centre = o.D == 3 ? 13 : 4;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int p = path[B.bnode[b]];
+        double side;
+        if (p == 1) side = 1.0;
+        else if (p == 2) side = -1.0;
+        else side = (B.lat_mean[b * npt + centre] < o.theta) ? 1.0 : -1.0;
+        double best = __builtin_inf();
+        int ib = 0;
+        for (int i = 0; i < npt; ++i) {
+            double gv = margin(side, o.theta, B.lat_mean[b * npt + i], B.lat_var[b * npt + i]);
+            if (gv < best) {
+                best = gv;
+                ib = i;
+            }
+        }
+        B.side[b] = side;
+        B.gmin[b] = best;
+        B.done[b] = 0;
+        for (int d = 0; d < 3; ++d) B.x[b * 3 + d] = B.lat_pts[(b * npt + ib) * 3 + d];
+    }
+}
+
+// One projected step of the bound search at the current point x_k (posterior and its
+// gradient already evaluated).  For k >= 1 the value at x_k also enters the minimum.
+__global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ keys, BoundBufs B)
+{
+    const int64_t nb = B.cnt[0];
+    double eta = 0.5;
+    for (int i = 0; i < k; ++i) eta *= 0.5;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        if (B.done[b]) continue;
+        const double side = B.side[b];
+        const double mu = B.gp_mean[b], var = B.gp_var[b];
+        const double g = margin(side, o.theta, mu, var);
+        if (k >= 1 && g < B.gmin[b]) B.gmin[b] = g;
+        if (!(var > 0.0)) {
+            B.done[b] = 1;
+            continue;
+        }
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[B.bnode[b]], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        const double sd = sqrt(var);
+        double u[3], nrm = 0.0;
+        for (int d = 0; d < o.D; ++d) {
+            const double dsd = B.gp_dvar[b * 3 + d] / (2.0 * sd);
+            const double gr = side * (-B.gp_dmean[b * 3 + d] * sd - (o.theta - mu) * dsd) / var;
+            u[d] = (bhi[d] - blo[d]) * gr;
+            nrm += u[d] * u[d];
+        }
+        nrm = sqrt(nrm);
+        if (!(nrm > 0.0) || !isfinite(nrm)) {
+            B.done[b] = 1;
+            continue;
+        }
+        for (int d = 0; d < o.D; ++d) {
+            const double w = bhi[d] - blo[d];
+            double xn = B.x[b * 3 + d] - eta * w * u[d] / nrm;
+            B.x[b * 3 + d] = xn < blo[d] ? blo[d] : (xn > bhi[d] ? bhi[d] : xn);
+        }
+    }
+}
+
+// Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)), and the decision.
+__global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
+                              int32_t* __restrict__ sub, double* __restrict__ ub_out)
+{
+    const int64_t nb = B.cnt[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        double gmin = B.gmin[b];
+        if (!B.done[b] && o.steps > 0) {
+            double g = margin(B.side[b], o.theta, B.gp_mean[b], B.gp_var[b]);
+            if (g < gmin) gmin = g;
+        }
+        const int32_t f = B.bnode[b];
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        double t;
+        if (gmin == __builtin_inf()) t = 0.0;
+        else if (gmin == -__builtin_inf()) t = 1.0;
+        else t = 0.5 * erfc(gmin / 1.41421356237309504880168872421);
+        double ub = t >= 1.0 ? 1.0 : -expm1((double)dp * log1p(-t));
+        sub[f] = ub > o.alpha ? 1 : 0;
+        if (ub_out) ub_out[f] = ub;
+    }
+}
+
+// Number of keys each node emits: its in-domain children, or itself as a leaf.
+__global__ void k_emit_count(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
+                             int64_t cap, const int32_t* __restrict__ sub, int32_t* __restrict__ cnt)
+{
+    int64_t nf = *nf_dev;
+    if (nf > cap) nf = cap;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+        int n = 0;
+        if (sub[f]) {
+            if (level == o.Lmax) {
+                n = 1;
+            } else {
+                int lv;
+                int64_t c[3];
+                key_coords(o.D, keys[f], lv, c);
+                const int64_t hs = (o.S0 >> level) >> 1;
+                for (int i = 0; i < (1 << o.D); ++i) {
+                    bool ok = true;
+                    for (int d = 0; d < o.D; ++d) ok = ok && (2 * c[d] + ((i >> d) & 1)) * hs < o.g.nc[d];
+                    n += ok ? 1 : 0;
+                }
+            }
+        }
+        cnt[f] = n;
+    }
+}
+
+__global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
+                       int64_t cap, const int32_t* __restrict__ sub, const int32_t* __restrict__ off,
+                       uint64_t* __restrict__ out, int64_t out_cap, uint8_t* __restrict__ stat)
+{
+    int64_t nf = *nf_dev;
+    if (nf > cap) nf = cap;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+        int lv;
+        int64_t c[3];
+        key_coords(o.D, keys[f], lv, c);
+        const int64_t* nl = o.nodes + level * 3;
+        stat[c[0] + nl[0] * (c[1] + nl[1] * c[2])] = sub[f] ? 2 : 1;
+        if (!sub[f]) continue;
+        int64_t pos = off[f];
+        if (level == o.Lmax) {
+            if (pos < out_cap) out[pos] = keys[f];
+            continue;
+        }
+        const int64_t hs = (o.S0 >> level) >> 1;
+        for (int i = 0; i < (1 << o.D); ++i) {
+            int64_t cc[3] = {0, 0, 0};
+            bool ok = true;
+            for (int d = 0; d < o.D; ++d) {
+                cc[d] = 2 * c[d] + ((i >> d) & 1);
+                ok = ok && cc[d] * hs < o.g.nc[d];
+            }
+            if (!ok) continue;
+            if (pos < out_cap) out[pos] = make_key(o.D, level + 1, cc);
+            ++pos;
+        }
+    }
+}
+
+__global__ void k_set_count(int64_t* dst, const int64_t* src, int64_t mul)
+{
+    *dst = *src * mul;
+}
+
+// Mark the vertices of every leaf's cells.
+__global__ void k_mark(Oct o, int leaf_edge, const uint64_t* __restrict__ leaves, const int64_t* __restrict__ nl_dev,
+                       int64_t leaf_cap, int32_t* __restrict__ vmask)
+{
+    const int64_t nl = *nl_dev;
+    if (nl > leaf_cap) return;
+    int64_t per = 1;
+    for (int d = 0; d < o.D; ++d) per *= leaf_edge + 1;
+    const int64_t total = nl * per;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lf = it / per;
+        int64_t loc = it % per;
+        int lv;
+        int64_t c[3];
+        key_coords(o.D, leaves[lf], lv, c);
+        const int64_t s = o.S0 >> lv;
+        int64_t v[3] = {0, 0, 0};
+        bool ok = true;
+        for (int d = 0; d < o.D; ++d) {
+            int64_t cmin = c[d] * s;
+            int64_t cmax = (c[d] + 1) * s;
+            if (cmax > o.g.nc[d]) cmax = o.g.nc[d];
+            v[d] = cmin + loc % (leaf_edge + 1);
+            loc /= leaf_edge + 1;
+            ok = ok && v[d] <= cmax;
+        }
+        if (!ok) continue;
+        vmask[v[0] + o.g.n[0] * (v[1] + o.g.n[1] * v[2])] = 1;
+    }
+}
+
+__global__ void k_slots(const int32_t* __restrict__ vmask, const int32_t* __restrict__ off, int64_t nv,
+                        int32_t* __restrict__ slot, int32_t* __restrict__ vlist)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        if (vmask[i]) {
+            slot[i] = off[i];
+            vlist[off[i]] = (int32_t)i;
+        } else {
+            slot[i] = -1;
+        }
+    }
+}
+
+// Octree level at which each cell's node stopped.
+__global__ void k_level_field(Oct o, const uint8_t* __restrict__ stat, uint8_t* __restrict__ field)
+{
+    const int64_t nc = o.g.nc[0] * o.g.nc[1] * o.g.nc[2];
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nc; it += (int64_t)gridDim.x * blockDim.x) {
+        int64_t cell[3] = {it % o.g.nc[0], (it / o.g.nc[0]) % o.g.nc[1], it / (o.g.nc[0] * o.g.nc[1])};
+        uint8_t out = 255;
+        for (int l = 0; l <= o.Lmax; ++l) {
+            const int64_t s = o.S0 >> l;
+            const int64_t* nl = o.nodes + l * 3;
+            int64_t lin = (cell[0] / s) + nl[0] * ((cell[1] / s) + nl[1] * (cell[2] / s));
+            uint8_t st = stat[o.statoff[l] + lin];
+            if (st == 1 || (st == 2 && l == o.Lmax)) {
+                out = (uint8_t)l;
+                break;
+            }
+            if (st != 2) break;
+        }
+        field[it] = out;
+    }
+}
+
+inline unsigned gsz(int64_t n, int per)
+{
+    int64_t b = (n + per - 1) / per;
+    if (b > 16384) b = 16384;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+// Workspace layout of lcp_adaptive.
+struct AdaptLayout {
+    size_t total;
+    size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
+    size_t o_bnode, o_side, o_gmin, o_x, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
+    size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb;
+    int64_t capF, nv;
+};
+
+static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns,
+                                int64_t* caps, int64_t* nodes)
+{
+    AdaptLayout L{};
+    const int D = g.dim;
+    int64_t capF = 1, stat_total = 0;
+    for (int l = 0; l <= Lmax; ++l) {
+        const int64_t s = S0 >> l;
+        int64_t c = 1;
+        for (int d = 0; d < 3; ++d) {
+            int64_t nd = d < D ? ceil_div(g.nc[d], s) : 1;
+            nodes[l * 3 + d] = nd;
+            c *= nd;
+        }
+        caps[l] = c;
+        stat_total += c;
+        if (c > capF) capF = c;
+    }
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    const int npt = D == 3 ? 27 : 9;
+    const int ndir = D == 3 ? 13 : 4;
+    const size_t vb = prec == LCP_FP64 ? 8 : 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+    L.o_q = take(sizeof(double) * 2 * M.m_pad);
+    L.o_cnt = take(sizeof(int64_t) * 64);
+    L.o_keys0 = take(8 * capF);
+    L.o_keys1 = take(8 * capF);
+    L.o_path = take(4 * capF);
+    L.o_need = take(4 * capF);
+    L.o_nidx = take(4 * capF);
+    L.o_sub = take(4 * capF);
+    L.o_ecnt = take(4 * capF);
+    L.o_eoff = take(4 * capF);
+    L.o_ub = take(8 * capF);
+    L.o_bnode = take(4 * capF);
+    L.o_side = take(8 * capF);
+    L.o_gmin = take(8 * capF);
+    L.o_x = take(24 * capF);
+    L.o_done = take(4 * capF);
+    L.o_latp = take(24 * capF * npt);
+    L.o_latm = take(8 * capF * npt);
+    L.o_latv = take(8 * capF * npt);
+    L.o_gm = take(8 * capF);
+    L.o_gv = take(8 * capF);
+    L.o_gdm = take(24 * capF);
+    L.o_gdv = take(24 * capF);
+    L.o_stat = take(stat_total);
+    L.o_statoff = take(8 * (Lmax + 1));
+    L.o_scan = take(scan_workspace(nv > capF ? nv : capF));
+    L.o_vmask = take(4 * nv);
+    L.o_voff = take(4 * nv);
+    L.o_slot = take(4 * nv);
+    L.o_vlist = take(4 * nv);
+    L.o_vmean = take(8 * nv);
+    L.o_vvar = take(8 * nv);
+    L.o_V = take(vb * (size_t)nv * M.m_pad);
+    L.o_cross = take(8 * (size_t)nv * ndir);
+    L.o_zb = take(4 * (size_t)ns * (1 << D));
+    L.total = o;
+    L.capF = capF;
+    L.nv = nv;
+    return L;
+}
+
+size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns)
+{
+    int64_t caps[8], nodes[24];
+    return adapt_layout(M, g, S0, Lmax, prec, ns, caps, nodes).total;
+}
+
+hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
+                        int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
+                        int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s)
+{
+    int64_t caps[8], nodes[24];
+    AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, caps, nodes);
+    const int D = g.dim;
+    const int npt = D == 3 ? 27 : 9;
+    Oct o{};
+    o.g = g;
+    o.D = D;
+    o.S0 = S0;
+    o.Lmax = Lmax;
+    o.theta = theta;
+    o.alpha = A.alpha;
+    o.bound_at_max = A.bound_at_max_depth;
+    o.steps = A.descent_steps;
+    for (int i = 0; i < 24; ++i) o.nodes[i] = i < (Lmax + 1) * 3 ? nodes[i] : 1;
+
+    auto P = [&](size_t off) { return (void*)(ws + off); };
+    double* qlo = (double*)P(L.o_q);
+    double* qhi = qlo + M.m_pad;
+    int64_t* cnt = (int64_t*)P(L.o_cnt);   // [0..15] frontier counts, [16] nb, [17] lattice pts, [18] nv
+    uint64_t* keys[2] = {(uint64_t*)P(L.o_keys0), (uint64_t*)P(L.o_keys1)};
+    int32_t* path = (int32_t*)P(L.o_path);
+    int32_t* need = (int32_t*)P(L.o_need);
+    int32_t* nidx = (int32_t*)P(L.o_nidx);
+    int32_t* sub = (int32_t*)P(L.o_sub);
+    int32_t* ecnt = (int32_t*)P(L.o_ecnt);
+    int32_t* eoff = (int32_t*)P(L.o_eoff);
+    uint8_t* stat = (uint8_t*)P(L.o_stat);
+    char* scanws = (char*)P(L.o_scan);
+    BoundBufs B;
+    B.bnode = (int32_t*)P(L.o_bnode);
+    B.side = (double*)P(L.o_side);
+    B.gmin = (double*)P(L.o_gmin);
+    B.x = (double*)P(L.o_x);
+    B.done = (int32_t*)P(L.o_done);
+    B.lat_pts = (double*)P(L.o_latp);
+    B.lat_mean = (double*)P(L.o_latm);
+    B.lat_var = (double*)P(L.o_latv);
+    B.gp_mean = (double*)P(L.o_gm);
+    B.gp_var = (double*)P(L.o_gv);
+    B.gp_dmean = (double*)P(L.o_gdm);
+    B.gp_dvar = (double*)P(L.o_gdv);
+    B.cnt = cnt + 16;
+
+    hipError_t e;
+    {
+        int64_t acc = 0;
+        for (int l = 0; l < 8; ++l) {
+            o.statoff[l] = acc;
+            if (l <= Lmax) acc += caps[l];
+        }
+        e = launch_fill_u8(stat, 0, acc, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_obs_q, dim3((unsigned)ceil_div(M.m, 256)), dim3(256), 0, s, M.obs_mu, M.obs_var, M.m, theta,
+                       qlo, qhi);
+    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, keys[0], cnt + 0);
+    e = launch_fill_f32(lcp, 0.0f, g.nc[0] * g.nc[1] * g.nc[2], s);
+    if (e != hipSuccess) return e;
+
+    for (int l = 0; l <= Lmax; ++l) {
+        uint64_t* kin = keys[l & 1];
+        uint64_t* kout = keys[(l + 1) & 1];
+        const int64_t cap = caps[l];
+        const int64_t* nf = cnt + l;
+        hipLaunchKernelGGL(k_prelim, dim3(gsz(cap * 64, 256)), dim3(256), 0, s, o, l, kin, nf, cap, M.X, M.m, qlo, qhi,
+                           path, need, sub);
+        e = launch_scan(need, nidx, cap, nf, B.cnt + 0, scanws, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bound_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, need, nidx, B);
+        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, B.cnt + 1, B.cnt + 0, (int64_t)npt);
+        // lattice values (binary64)
+        PostTask t{};
+        t.mode = COL_POINTS;
+        t.group = 1;
+        t.count = B.cnt + 1;
+        t.n_points = cap * npt;
+        t.pts = B.lat_pts;
+        t.pstride = 3;
+        t.mean = B.lat_mean;
+        t.var = B.lat_var;
+        e = launch_posterior(M, LCP_FP64, t, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_lattice, dim3(gsz(cap, 256)), dim3(256), 0, s, o, path, B);
+        for (int k = 0; k < A.descent_steps; ++k) {
+            PostTask tg{};
+            tg.mode = COL_POINTS;
+            tg.group = 4;
+            tg.count = B.cnt + 0;
+            tg.n_points = cap;
+            tg.pts = B.x;
+            tg.pstride = 3;
+            tg.mean = B.gp_mean;
+            tg.var = B.gp_var;
+            tg.dmean = B.gp_dmean;
+            tg.dvar = B.gp_dvar;
+            e = launch_posterior(M, LCP_FP64, tg, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B);
+        }
+        if (A.descent_steps > 0) {
+            PostTask tv{};
+            tv.mode = COL_POINTS;
+            tv.group = 1;
+            tv.count = B.cnt + 0;
+            tv.n_points = cap;
+            tv.pts = B.x;
+            tv.pstride = 3;
+            tv.mean = B.gp_mean;
+            tv.var = B.gp_var;
+            e = launch_posterior(M, LCP_FP64, tv, s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub,
+                           (double*)P(L.o_ub));
+        hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
+        int64_t* nout = (l == Lmax) ? n_leaves : cnt + l + 1;
+        e = launch_scan(ecnt, eoff, cap, nf, nout, scanws, s);
+        if (e != hipSuccess) return e;
+        uint64_t* dst = (l == Lmax) ? leaves : kout;
+        const int64_t dcap = (l == Lmax) ? leaf_cap : caps[l + 1];
+        hipLaunchKernelGGL(k_emit, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, eoff, dst, dcap,
+                           stat + o.statoff[l]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (level_field) {
+        hipLaunchKernelGGL(k_level_field, dim3(gsz(g.nc[0] * g.nc[1] * g.nc[2], 256)), dim3(256), 0, s, o, stat,
+                           level_field);
+    }
+
+    // ---- reconstruction of the emitted nodes (Sec. 4.3, last paragraph)
+    const int leaf_edge = (int)(S0 >> Lmax);
+    int32_t* vmask = (int32_t*)P(L.o_vmask);
+    int32_t* voff = (int32_t*)P(L.o_voff);
+    int32_t* slot = (int32_t*)P(L.o_slot);
+    int32_t* vlist = (int32_t*)P(L.o_vlist);
+    int64_t* nvd = cnt + 18;
+    e = launch_fill_i32(vmask, 0, L.nv, s);
+    if (e != hipSuccess) return e;
+    int64_t per = 1;
+    for (int d = 0; d < D; ++d) per *= leaf_edge + 1;
+    hipLaunchKernelGGL(k_mark, dim3(gsz(leaf_cap * per, 256)), dim3(256), 0, s, o, leaf_edge, leaves, n_leaves,
+                       leaf_cap, vmask);
+    e = launch_scan(vmask, voff, L.nv, nullptr, nvd, scanws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_slots, dim3(gsz(L.nv, 256)), dim3(256), 0, s, vmask, voff, L.nv, slot, vlist);
+    double* vmean = (double*)P(L.o_vmean);
+    double* vvar = (double*)P(L.o_vvar);
+    void* V = P(L.o_V);
+    double* cross = (double*)P(L.o_cross);
+    PostTask tp{};
+    tp.mode = COL_GRID;
+    tp.group = 1;
+    tp.count = nvd;
+    tp.n_points = L.nv;
+    tp.grid = g;
+    tp.vlist = vlist;
+    tp.mean = vmean;
+    tp.var = vvar;
+    tp.V = V;
+    e = launch_posterior(M, prec, tp, s);
+    if (e != hipSuccess) return e;
+    e = launch_cross(M, prec, g, vlist, nvd, L.nv, slot, V, cross, s);
+    if (e != hipSuccess) return e;
+    float* zb32 = (float*)P(L.o_zb);
+    if (prec != LCP_FP64) {
+        e = launch_zbank32(zb, zb32, (int64_t)ns << D, s);
+        if (e != hipSuccess) return e;
+    }
+    CellTask ct{};
+    ct.grid = g;
+    ct.prec = prec;
+    ct.theta = theta;
+    ct.ns = ns;
+    ct.zb64 = zb;
+    ct.zb32 = zb32;
+    ct.mean = vmean;
+    ct.var = vvar;
+    ct.cross = cross;
+    ct.slot = slot;
+    ct.leaves = leaves;
+    ct.n_leaves = n_leaves;
+    ct.leaf_cap = leaf_cap;
+    ct.S0 = S0;
+    ct.Lmax = Lmax;
+    ct.leaf_edge = leaf_edge;
+    ct.lcp = lcp;
+    int64_t cpl = 1;
+    for (int d = 0; d < D; ++d) cpl *= leaf_edge;
+    return launch_cells(ct, leaf_cap * cpl, s);
+}
+
+}  // namespace lcp

@@ -1,0 +1,180 @@
+// Internal declarations of the gfx950 LCP library: device helpers, the model layout
+// in device memory, and the launchers each kernel file provides to the host API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "../../include/lcp.h"
+
+namespace lcp {
+
+constexpr int kMaxM = 1024;           // largest supported number of observations
+constexpr int kWave = 64;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// Covariance parameters as the kernels read them.
+struct KParams {
+    int kind;        // lcp_kernel_kind
+    int dim;
+    double s2;       // signal variance
+    double inv_ell[3];
+};
+
+// Regular grid: vertex i on axis d is lo[d] + i * h[d] with h = (hi - lo) / (npts - 1).
+struct GridP {
+    int dim;
+    double lo[3];
+    double h[3];
+    int64_t n[3];    // vertices per axis (1 beyond dim)
+    int64_t nc[3];   // cells per axis (1 beyond dim)
+};
+
+// Coordinate of vertex i on axis d, rounded exactly as lo + i * h with two roundings
+// (no fused multiply-add), so every part of the library agrees on box corners.
+__device__ __forceinline__ double vertex_coord(const GridP& g, int d, int64_t i)
+{
+    return __dadd_rn(g.lo[d], __dmul_rn((double)i, g.h[d]));
+}
+
+__device__ __forceinline__ double kernel_r2(const KParams& p, const double* x, const double* z)
+{
+    double r2 = 0.0;
+    for (int d = 0; d < p.dim; ++d) {
+        double t = (x[d] - z[d]) * p.inv_ell[d];
+        r2 = fma(t, t, r2);
+    }
+    return r2;
+}
+
+// k(x, z) for the squared-exponential and Matern-5/2 covariances.
+__device__ __forceinline__ double kernel_val(const KParams& p, double r2)
+{
+    if (p.kind == LCP_KERNEL_SE) return p.s2 * exp(-0.5 * r2);
+    const double s5 = 2.23606797749978969640917366873;
+    double r = sqrt(r2);
+    return p.s2 * fma(5.0 / 3.0, r2, fma(s5, r, 1.0)) * exp(-s5 * r);
+}
+
+// d k(x, z) / d x_d = f(r) * (x_d - z_d) / ell_d^2; returns f(r).
+__device__ __forceinline__ double kernel_dfac(const KParams& p, double r2)
+{
+    if (p.kind == LCP_KERNEL_SE) return -p.s2 * exp(-0.5 * r2);
+    const double s5 = 2.23606797749978969640917366873;
+    double r = sqrt(r2);
+    return -(5.0 / 3.0) * p.s2 * fma(s5, r, 1.0) * exp(-s5 * r);
+}
+
+// ------------------------------------------------------------- posterior GEMM (K1)
+//
+// V = L^-1 B with B_jc = k(x_j, p_c) (or a derivative of it) generated on the fly.
+// Columns come in groups of `group` (1: value only; 4: value + d/dx_0..2 of one point).
+
+enum ColMode { COL_GRID = 0, COL_POINTS = 1 };
+
+struct PostTask {
+    int mode;                 // ColMode
+    int group;                // 1 or 4 (gradient probes)
+    const int64_t* count;     // device count of POINTS (groups); null -> n_points
+    int64_t n_points;         // host upper bound of the number of points
+    // COL_GRID: vertex id = vlist ? vlist[p] : p
+    GridP grid;
+    const int32_t* vlist;
+    // COL_POINTS: n x dim points, row stride = pstride doubles
+    const double* pts;
+    int pstride;
+    // outputs (per point p): mean[p], var[p]; for group 4: dmean[p*3+d], dvar[p*3+d]
+    double* mean;
+    double* var;
+    double* dmean;
+    double* dvar;
+    void* V;                  // optional: V column per point (value column only), ldv = m_pad
+};
+
+struct Model;  // defined below
+
+hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s);
+
+// ------------------------------------------------------------------- cells (K3)
+
+struct CellTask {
+    GridP grid;
+    int prec;                 // lcp_precision of the Monte Carlo loop
+    double theta;
+    int ns;                   // samples
+    const double* zb64;       // ns x 2^dim
+    const float* zb32;        // ns x 2^dim (FP32 copy)
+    const double* mean;       // per slot
+    const double* var;        // per slot
+    const double* cross;      // per slot x ndir
+    const int32_t* slot;      // vertex id -> slot (null: slot = vertex id)
+    // cell enumeration: dense (leaves == null) or the cells of leaf keys
+    const uint64_t* leaves;
+    const int64_t* n_leaves;  // device count
+    int64_t leaf_cap;
+    int64_t S0;               // root edge in cells
+    int Lmax;
+    int leaf_edge;            // cells per leaf edge
+    float* lcp;               // whole cell field
+};
+
+hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
+                        int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s);
+hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s);
+hipError_t launch_zbank32(const double* zb, float* zb32, int64_t n, hipStream_t s);
+
+// --------------------------------------------------------------- model (K2)
+
+struct Model {
+    lcp_kernel k;
+    KParams kp;
+    int m, m_pad, nrb, dim;
+    double* X;        // m_pad x 4 (zero padded)
+    double* a;        // m_pad
+    double* U;        // m_pad x m_pad, upper factor L^T (row-major); scratch K before factoring
+    double* Linv;     // m_pad x m_pad row-major lower, zero padded
+    double* A64;      // Linv in 16x16x4 MFMA fragment order (binary64)
+    float* A32;       // Linv in 16x16x4 MFMA fragment order (binary32)
+    __bf16* Ahi;      // Linv split, 16x16x32 fragment order, high part
+    __bf16* Alo;      //   low part
+    _Float16* Hhi;    // (Linv * sA) split into FP16 halves, 16x16x32 fragment order
+    _Float16* Hlo;
+    double* amax;     // [0] max |Linv|, [1] sA (power of two), device
+    double* obs_mu;   // m
+    double* obs_var;  // m
+    int* info;
+    int device;
+};
+
+size_t model_bytes(int m);
+hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t s);
+hipError_t launch_factor_finish(Model& M, hipStream_t s);
+
+// ------------------------------------------------------------- octree (K4/K5)
+
+size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns);
+hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
+                        int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
+                        int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s);
+
+// ------------------------------------------------------------------ utilities
+
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// Exclusive scan of n int32 flags (device count or host n) into offsets, total into *total.
+size_t scan_workspace(int64_t n);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, const int64_t* n_dev, int64_t* total,
+                       char* ws, hipStream_t s);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace lcp

@@ -1,0 +1,230 @@
+"""Python binding of the gfx950 LCP library (include/lcp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+liblcp.so.  PyTorch provides device memory and the current stream.  If the shared
+library is missing the import of this module fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblcp.so")
+
+LCP_OK, LCP_EINVAL, LCP_ENOTPD, LCP_ECAPACITY, LCP_ENOMEM, LCP_EDEVICE, LCP_ENOTSUPPORTED = range(7)
+FP64, FP32, MIXED_BF16X3, MIXED_F16X3 = 0, 1, 2, 3
+SE, MATERN52 = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": MIXED_BF16X3, "f16x3": MIXED_F16X3}
+
+
+class LcpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lcp status {status}: {msg}")
+        self.status = status
+
+
+class Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int), ("dim", C.c_int), ("signal_var", C.c_double),
+                ("lengthscale", C.c_double * 3), ("noise_var", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("npts", C.c_int64 * 3)]
+
+
+class Adapt(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("min_leaf_cells", C.c_int), ("bound_at_max_depth", C.c_int),
+                ("descent_steps", C.c_int)]
+
+
+class MC(C.Structure):
+    _fields_ = [("n_samples", C.c_int), ("zbank", C.c_void_p)]
+
+
+EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor", "gp_model_free",
+           "lcp_posterior_workspace", "lcp_dense_workspace", "lcp_adaptive_workspace", "gp_posterior",
+           "lcp_dense", "lcp_adaptive", "lcp_backward"]
+
+_lib = None
+
+
+def lib():
+    """Load liblcp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_12442_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P, I64, SZ = C.c_void_p, C.c_int64, C.c_size_t
+    L.lcp_status_str.restype = C.c_char_p
+    L.lcp_status_str.argtypes = [C.c_int]
+    L.lcp_last_error.restype = C.c_char_p
+    L.lcp_last_error.argtypes = []
+    L.lcp_model_bytes.restype = SZ
+    L.lcp_model_bytes.argtypes = [C.c_int, C.c_int]
+    L.gp_fit_factor.argtypes = [P, C.c_int, P, P, P, SZ, P, C.POINTER(P)]
+    L.gp_model_free.argtypes = [P]
+    L.gp_model_free.restype = None
+    L.lcp_posterior_workspace.argtypes = [P, I64, C.c_int, C.POINTER(SZ)]
+    L.lcp_dense_workspace.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(SZ)]
+    L.lcp_adaptive_workspace.argtypes = [P, P, P, C.c_int, C.c_int, C.POINTER(SZ)]
+    L.gp_posterior.argtypes = [P, I64, P, C.c_int, P, P, P, SZ, P]
+    L.lcp_dense.argtypes = [P, P, C.c_double, P, C.c_int, P, P, SZ, P]
+    L.lcp_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int, P, P, I64, P, P, P, SZ, P]
+    L.lcp_backward.argtypes = [P, P, C.c_double, P, P, P, P, P, SZ, P]
+    for name in EXPORTS:
+        if name not in ("lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_model_free"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != LCP_OK:
+        raise LcpError(status, lib().lcp_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _buffer(nbytes: int, device) -> torch.Tensor:
+    """Device byte buffer whose data pointer is 256-byte aligned."""
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + max(int(nbytes), 1)]
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def make_grid(dim, lo, hi, npts) -> Grid:
+    g = Grid()
+    g.dim = dim
+    for d in range(3):
+        g.lo[d] = float(lo[d]) if d < dim else 0.0
+        g.hi[d] = float(hi[d]) if d < dim else 0.0
+        g.npts[d] = int(npts[d]) if d < dim else 1
+    return g
+
+
+class GPModel:
+    """A factored GP model (gp_fit_factor) living in caller-owned device memory."""
+
+    def __init__(self, kind, dim, signal_var, lengthscale, noise_var, X: torch.Tensor, y: torch.Tensor):
+        L = lib()
+        X = X.to(torch.float64).contiguous()
+        y = y.to(torch.float64).contiguous()
+        assert X.is_cuda and y.is_cuda and X.shape == (y.shape[0], dim)
+        self.k = Kernel(kind, dim, float(signal_var), (C.c_double * 3)(*[float(v) for v in lengthscale[:3]]),
+                        float(noise_var))
+        self.dim, self.m = dim, int(X.shape[0])
+        nb = L.lcp_model_bytes(self.m, dim)
+        if nb == 0:
+            raise LcpError(LCP_EINVAL, f"unsupported number of observations m={self.m}")
+        self.mem = _buffer(nb, X.device)
+        self.device = X.device
+        self._X, self._y = X, y
+        h = C.c_void_p()
+        _check(L.gp_fit_factor(C.byref(self.k), self.m, _ptr(X), _ptr(y), _ptr(self.mem), nb, _stream(),
+                               C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gp_model_free(h)
+            self.h = None
+
+    @classmethod
+    def from_workload(cls, W, device="cuda"):
+        X = torch.as_tensor(W.X, dtype=torch.float64, device=device)
+        y = torch.as_tensor(W.y, dtype=torch.float64, device=device)
+        return cls(W.kind, W.dim, W.signal_var, list(W.lengthscale), W.noise_var, X, y)
+
+    # -------------------------------------------------------------- operations
+    def posterior(self, Xq: torch.Tensor, prec="fp64"):
+        Xq = Xq.to(torch.float64).contiguous()
+        n = int(Xq.shape[0])
+        mean = torch.empty(n, dtype=torch.float64, device=self.device)
+        var = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(lib().gp_posterior(self.h, n, _ptr(Xq), _prec(prec), _ptr(mean), _ptr(var), None, 0, _stream()))
+        return mean, var
+
+    def dense_workspace(self, grid: Grid, prec, n_samples):
+        b = C.c_size_t()
+        _check(lib().lcp_dense_workspace(self.h, C.byref(grid), _prec(prec), int(n_samples), C.byref(b)))
+        return b.value
+
+    def adaptive_workspace(self, grid: Grid, adapt: Adapt, prec, n_samples):
+        b = C.c_size_t()
+        _check(lib().lcp_adaptive_workspace(self.h, C.byref(grid), C.byref(adapt), _prec(prec), int(n_samples),
+                                            C.byref(b)))
+        return b.value
+
+    def lcp_dense(self, grid: Grid, theta: float, zbank: torch.Tensor, prec="fp64", out=None, ws=None):
+        zbank = zbank.to(torch.float64).contiguous()
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr())
+        nb = self.dense_workspace(grid, prec, mc.n_samples)
+        if ws is None or ws.numel() < nb:
+            ws = _buffer(nb, self.device)
+        ncell = 1
+        for d in range(grid.dim):
+            ncell *= grid.npts[d] - 1
+        if out is None:
+            out = torch.empty(ncell, dtype=torch.float32, device=self.device)
+        _check(lib().lcp_dense(self.h, C.byref(grid), float(theta), C.byref(mc), _prec(prec), _ptr(out), _ptr(ws),
+                               ws.numel(), _stream()))
+        return out, ws
+
+    def lcp_adaptive(self, grid: Grid, theta: float, adapt: Adapt, zbank: torch.Tensor, prec="bf16x3", leaf_cap=None,
+                     level_field=True, out=None, ws=None, leaves=None, n_leaves=None):
+        zbank = zbank.to(torch.float64).contiguous()
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr())
+        nb = self.adaptive_workspace(grid, adapt, prec, mc.n_samples)
+        if ws is None or ws.numel() < nb:
+            ws = _buffer(nb, self.device)
+        ncell = 1
+        for d in range(grid.dim):
+            ncell *= grid.npts[d] - 1
+        if out is None:
+            out = torch.empty(ncell, dtype=torch.float32, device=self.device)
+        if leaf_cap is None:
+            leaf_cap = ncell
+        if leaves is None:
+            leaves = torch.zeros(max(int(leaf_cap), 1), dtype=torch.int64, device=self.device)
+        if n_leaves is None:
+            n_leaves = torch.zeros(1, dtype=torch.int64, device=self.device)
+        lf = torch.empty(ncell, dtype=torch.uint8, device=self.device) if level_field else None
+        _check(lib().lcp_adaptive(self.h, C.byref(grid), float(theta), C.byref(adapt), C.byref(mc), _prec(prec),
+                                  _ptr(out), _ptr(leaves), int(leaf_cap), _ptr(n_leaves), _ptr(lf), _ptr(ws),
+                                  ws.numel(), _stream()))
+        return out, leaves, n_leaves, lf, ws
+
+    def lcp_backward(self, grid: Grid, theta: float, zbank: torch.Tensor, dL_dlcp: torch.Tensor):
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr())
+        dy = torch.zeros(self.m, dtype=torch.float64, device=self.device)
+        dl = torch.zeros(3, dtype=torch.float64, device=self.device)
+        _check(lib().lcp_backward(self.h, C.byref(grid), float(theta), C.byref(mc), _ptr(dL_dlcp), _ptr(dy),
+                                  _ptr(dl), None, 0, _stream()))
+        return dy, dl
+
+
+def grid_of(W) -> Grid:
+    return make_grid(W.dim, W.lo, W.hi, W.npts)
+
+
+def adapt_of(W, min_leaf=None, bound_at_max_depth=1, steps=4, alpha=None) -> Adapt:
+    return Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf), int(bound_at_max_depth),
+                 int(steps))

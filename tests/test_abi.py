@@ -1,0 +1,77 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point the
+header declares, and rejects invalid arguments on the host before enqueueing work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2512_12442_amd as lcp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lcp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_header_function():
+    names = header_functions()
+    assert {"gp_fit_factor", "gp_posterior", "lcp_dense", "lcp_adaptive", "lcp_backward"} <= set(names)
+    L = lcp.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lcp.lcp.EXPORTS) == names
+
+
+def test_status_strings_and_model_bytes():
+    L = lcp.lib()
+    assert L.lcp_status_str(0) == b"ok"
+    assert L.lcp_status_str(2).startswith(b"covariance")
+    assert L.lcp_model_bytes(0, 3) == 0 and L.lcp_model_bytes(1025, 3) == 0
+    assert L.lcp_model_bytes(500, 3) > 500 * 500 * 8 * 3
+
+
+def _fit(kind=0, dim=3, s2=1.0, ell=(0.1, 0.1, 0.1), noise=1e-4, m=10, X=None, y=None, mem=None, nb=0):
+    L = lcp.lib()
+    k = lcp.lcp.Kernel(kind, dim, s2, (C.c_double * 3)(*ell), noise)
+    h = C.c_void_p()
+    rc = L.gp_fit_factor(C.byref(k), m, X, y, mem, nb, None, C.byref(h))
+    return rc, L.lcp_last_error().decode(), h
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(dim=4), "dim"), (dict(kind=7), "kernel"), (dict(s2=0.0), "signal_var"), (dict(s2=float("nan")), "signal_var"),
+    (dict(noise=-1.0), "noise_var"), (dict(ell=(0.1, -1.0, 0.1)), "lengthscale"), (dict(m=0), "m = 0"),
+    (dict(m=2000), "m = 2000"), (dict(), "must not be NULL"),
+])
+def test_fit_rejects_invalid_arguments(kw, frag):
+    rc, msg, h = _fit(**kw)
+    assert rc == lcp.lcp.LCP_EINVAL and frag in msg and not h.value
+
+
+def test_fit_rejects_small_or_misaligned_model_memory():
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation fails first
+    rc, msg, _ = _fit(X=fake, y=fake, mem=fake, nb=16)
+    assert rc == lcp.lcp.LCP_ENOMEM and "model memory" in msg
+    rc, msg, _ = _fit(X=fake, y=fake, mem=C.c_void_p(0x1010), nb=1 << 30)
+    assert rc == lcp.lcp.LCP_EINVAL and "aligned" in msg
+
+
+def test_backward_reports_not_supported():
+    L = lcp.lib()
+    rc = L.lcp_backward(None, None, 0.0, None, None, None, None, None, 0, None)
+    assert rc == lcp.lcp.LCP_ENOTSUPPORTED
+
+
+def test_null_model_rejected_everywhere():
+    L = lcp.lib()
+    b = C.c_size_t()
+    assert L.lcp_dense_workspace(None, None, 0, 1600, C.byref(b)) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_adaptive_workspace(None, None, None, 0, 1600, C.byref(b)) == lcp.lcp.LCP_EINVAL
+    assert L.gp_posterior(None, 1, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_dense(None, None, 0.0, None, 0, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_adaptive(None, None, 0.0, None, None, 0, None, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
