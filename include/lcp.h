@@ -169,6 +169,20 @@ int lcp_backward(const lcp_model* model, const lcp_grid* grid, double theta, con
                  const float* dL_dlcp, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
                  void* stream);
 
+/*
+ * Stage timer (tracing).  lcp_profile_begin(mask) enables it for the stages whose bit is
+ * set: 0 model factorisation, 1 posterior GEMM at vertices / query points, 2 binary64
+ * posterior probes of the region bound, 3 neighbour cross-covariances, 4 cell factor and
+ * Monte Carlo, 5 octree tests / prefix sums / emission, 6 fills and conversions.  Each
+ * launch of an enabled stage is bracketed by hipEvents recorded on the launch stream.
+ * lcp_profile_end(ms, launches, n_stages) waits for those events, disables the timer and
+ * writes per stage the summed elapsed milliseconds and the number of bracketed launches
+ * (host arrays of n_stages entries, either may be NULL).  Process-wide; calls from several
+ * threads while it is enabled share one record list.
+ */
+int lcp_profile_begin(unsigned stage_mask);
+int lcp_profile_end(double* ms, int64_t* launches, int n_stages);
+
 #ifdef __cplusplus
 }
 #endif

@@ -255,6 +255,7 @@ hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t*
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s)
 {
     if (nv_cap <= 0) return hipSuccess;
+    StageScope sc(s, ST_CROSS);
     unsigned grid = grid_for(nv_cap * 64, 256);
     if (prec == LCP_FP64)
         hipLaunchKernelGGL(k_cross<double>, dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, vlist, nv_dev, nv_cap,
@@ -268,6 +269,7 @@ hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t*
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s)
 {
     if (ncells_cap <= 0) return hipSuccess;
+    StageScope sc(s, ST_CELLS);
     unsigned grid = grid_for(ncells_cap, 256);
     const bool f64 = t.prec == LCP_FP64;
     if (t.grid.dim == 3) {
@@ -282,24 +284,28 @@ hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s)
 
 hipError_t launch_zbank32(const double* zb, float* zb32, int64_t n, hipStream_t s)
 {
+    StageScope sc(s, ST_MISC);
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, zb, zb32, n);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s)
 {
+    StageScope sc(s, ST_MISC);
     hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s)
 {
+    StageScope sc(s, ST_MISC);
     hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s)
 {
+    StageScope sc(s, ST_MISC);
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }

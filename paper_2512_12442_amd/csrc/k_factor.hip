@@ -214,6 +214,7 @@ static double* ybuf(const Model& M)
 hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t s)
 {
     carve(M, (char*)M.X);
+    StageScope sc(s, ST_FACTOR);
     int mp = M.m_pad;
     double* w = ybuf(M);
     hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, X, y, M.m, mp, M.dim, M.X, w);
@@ -228,6 +229,7 @@ hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t
 // After the status has been read: inverse, a, fragments, observation posterior.
 hipError_t launch_factor_finish(Model& M, hipStream_t s)
 {
+    StageScope sc(s, ST_FACTOR);
     int mp = M.m_pad;
     int64_t n2 = (int64_t)mp * mp;
     hipLaunchKernelGGL(k_trinv, dim3(1), dim3(1024), 0, s, M.U, M.Linv, M.m, mp, M.amax);

@@ -588,9 +588,12 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         e = launch_fill_u8(stat, 0, acc, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_obs_q, dim3((unsigned)ceil_div(M.m, 256)), dim3(256), 0, s, M.obs_mu, M.obs_var, M.m, theta,
-                       qlo, qhi);
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, keys[0], cnt + 0);
+    {
+        StageScope sc(s, ST_OCTREE);
+        hipLaunchKernelGGL(k_obs_q, dim3((unsigned)ceil_div(M.m, 256)), dim3(256), 0, s, M.obs_mu, M.obs_var, M.m,
+                           theta, qlo, qhi);
+        hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, keys[0], cnt + 0);
+    }
     e = launch_fill_f32(lcp, 0.0f, g.nc[0] * g.nc[1] * g.nc[2], s);
     if (e != hipSuccess) return e;
 
@@ -599,12 +602,15 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         uint64_t* kout = keys[(l + 1) & 1];
         const int64_t cap = caps[l];
         const int64_t* nf = cnt + l;
+        {
+        StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_prelim, dim3(gsz(cap * 64, 256)), dim3(256), 0, s, o, l, kin, nf, cap, M.X, M.m, qlo, qhi,
                            path, need, sub);
         e = launch_scan(need, nidx, cap, nf, B.cnt + 0, scanws, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_bound_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, need, nidx, B);
         hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, B.cnt + 1, B.cnt + 0, (int64_t)npt);
+        }
         // lattice values (binary64)
         PostTask t{};
         t.mode = COL_POINTS;
@@ -615,9 +621,13 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         t.pstride = 3;
         t.mean = B.lat_mean;
         t.var = B.lat_var;
+        t.stage = ST_BOUND;
         e = launch_posterior(M, LCP_FP64, t, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_lattice, dim3(gsz(cap, 256)), dim3(256), 0, s, o, path, B);
+        {
+            StageScope sc(s, ST_OCTREE);
+            hipLaunchKernelGGL(k_lattice, dim3(gsz(cap, 256)), dim3(256), 0, s, o, path, B);
+        }
         for (int k = 0; k < A.descent_steps; ++k) {
             PostTask tg{};
             tg.mode = COL_POINTS;
@@ -630,8 +640,10 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             tg.var = B.gp_var;
             tg.dmean = B.gp_dmean;
             tg.dvar = B.gp_dvar;
+            tg.stage = ST_BOUND;
             e = launch_posterior(M, LCP_FP64, tg, s);
             if (e != hipSuccess) return e;
+            StageScope sc(s, ST_OCTREE);
             hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B);
         }
         if (A.descent_steps > 0) {
@@ -644,9 +656,11 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             tv.pstride = 3;
             tv.mean = B.gp_mean;
             tv.var = B.gp_var;
+            tv.stage = ST_BOUND;
             e = launch_posterior(M, LCP_FP64, tv, s);
             if (e != hipSuccess) return e;
         }
+        StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub,
                            (double*)P(L.o_ub));
         hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
@@ -661,6 +675,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         if (e != hipSuccess) return e;
     }
     if (level_field) {
+        StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_level_field, dim3(gsz(g.nc[0] * g.nc[1] * g.nc[2], 256)), dim3(256), 0, s, o, stat,
                            level_field);
     }
@@ -676,11 +691,14 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     if (e != hipSuccess) return e;
     int64_t per = 1;
     for (int d = 0; d < D; ++d) per *= leaf_edge + 1;
+    {
+    StageScope sc(s, ST_OCTREE);
     hipLaunchKernelGGL(k_mark, dim3(gsz(leaf_cap * per, 256)), dim3(256), 0, s, o, leaf_edge, leaves, n_leaves,
                        leaf_cap, vmask);
     e = launch_scan(vmask, voff, L.nv, nullptr, nvd, scanws, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_slots, dim3(gsz(L.nv, 256)), dim3(256), 0, s, vmask, voff, L.nv, slot, vlist);
+    }
     double* vmean = (double*)P(L.o_vmean);
     double* vvar = (double*)P(L.o_vvar);
     void* V = P(L.o_V);
@@ -695,6 +713,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     tp.mean = vmean;
     tp.var = vvar;
     tp.V = V;
+    tp.stage = ST_POSTERIOR;
     e = launch_posterior(M, prec, tp, s);
     if (e != hipSuccess) return e;
     e = launch_cross(M, prec, g, vlist, nvd, L.nv, slot, V, cross, s);

@@ -354,6 +354,7 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s)
 {
     if (t.n_points <= 0) return hipSuccess;
+    StageScope sc(s, t.stage);
     const bool grad = t.group == 4;
     // LDS: binary64 with 32 columns needs 32 * (m_pad + 4) * 8 bytes (<= 160 KB for m_pad <= 608)
     const bool small = M.m_pad <= 576;

@@ -258,6 +258,7 @@ int gp_posterior(const lcp_model* M, int64_t n, const double* Xq, int prec, doub
     t.pstride = M->dim;
     t.mean = mean;
     t.var = var;
+    t.stage = ST_POSTERIOR;
     hipError_t e = launch_posterior(*M, prec, t, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, "gp_posterior");
     return ok();
@@ -304,6 +305,7 @@ int lcp_dense(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_
     t.mean = mean;
     t.var = var;
     t.V = V;
+    t.stage = ST_POSTERIOR;
     e = launch_posterior(*M, prec, t, s);
     if (e != hipSuccess) return dev_fail(e, "posterior");
     e = launch_cross(*M, prec, g, nullptr, nullptr, nv, nullptr, V, cross, s);

@@ -95,6 +95,7 @@ struct PostTask {
     double* dmean;
     double* dvar;
     void* V;                  // optional: V column per point (value column only), ldv = m_pad
+    int stage;                // stage-timer stage of this launch
 };
 
 struct Model;  // defined below
@@ -173,6 +174,31 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 size_t scan_workspace(int64_t n);
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, const int64_t* n_dev, int64_t* total,
                        char* ws, hipStream_t s);
+
+// Stages of the stage timer (bit positions of the lcp_profile_begin mask).
+enum Stage {
+    ST_FACTOR = 0,      // model factorisation
+    ST_POSTERIOR = 1,   // posterior GEMM at grid vertices / query points
+    ST_BOUND = 2,       // binary64 posterior probes of the region bound
+    ST_CROSS = 3,       // neighbour cross-covariances
+    ST_CELLS = 4,       // cell factor + Monte Carlo
+    ST_OCTREE = 5,      // node tests, prefix sums, emission, leaf enumeration
+    ST_MISC = 6         // fills and conversions
+};
+
+// Brackets the launches issued during its lifetime with events when the stage is profiled.
+class StageScope {
+public:
+    StageScope(hipStream_t s, int stage);
+    ~StageScope();
+    StageScope(const StageScope&) = delete;
+    StageScope& operator=(const StageScope&) = delete;
+
+private:
+    hipStream_t s_;
+    int stage_;
+    int idx_;
+};
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

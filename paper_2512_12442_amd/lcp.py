@@ -48,7 +48,9 @@ class MC(C.Structure):
 
 EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor", "gp_model_free",
            "lcp_posterior_workspace", "lcp_dense_workspace", "lcp_adaptive_workspace", "gp_posterior",
-           "lcp_dense", "lcp_adaptive", "lcp_backward"]
+           "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end"]
+
+STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
 _lib = None
 
@@ -78,6 +80,8 @@ def lib():
     L.lcp_dense.argtypes = [P, P, C.c_double, P, C.c_int, P, P, SZ, P]
     L.lcp_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int, P, P, I64, P, P, P, SZ, P]
     L.lcp_backward.argtypes = [P, P, C.c_double, P, P, P, P, P, SZ, P]
+    L.lcp_profile_begin.argtypes = [C.c_uint]
+    L.lcp_profile_end.argtypes = [P, P, C.c_int]
     for name in EXPORTS:
         if name not in ("lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_model_free"):
             getattr(L, name).restype = C.c_int
@@ -219,6 +223,31 @@ class GPModel:
         _check(lib().lcp_backward(self.h, C.byref(grid), float(theta), C.byref(mc), _ptr(dL_dlcp), _ptr(dy),
                                   _ptr(dl), None, 0, _stream()))
         return dy, dl
+
+
+class StageTimer:
+    """Per-stage kernel time from hipEvents the library records on its launch stream."""
+
+    def __init__(self, stages=None):
+        names = stages or STAGES
+        self.mask = 0
+        for n in names:
+            self.mask |= 1 << STAGES.index(n)
+        self.ms = {}
+        self.launches = {}
+
+    def __enter__(self):
+        _check(lib().lcp_profile_begin(self.mask))
+        return self
+
+    def __exit__(self, *exc):
+        import numpy as np
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().lcp_profile_end(ms.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p), len(STAGES)))
+        self.ms = {n: float(ms[i]) for i, n in enumerate(STAGES) if self.mask >> i & 1}
+        self.launches = {n: int(cnt[i]) for i, n in enumerate(STAGES) if self.mask >> i & 1}
+        return False
 
 
 def grid_of(W) -> Grid:
