@@ -23,63 +23,117 @@ __device__ __forceinline__ void dir_offset(int D, int dir, int& dx, int& dy, int
     dz = D == 3 ? code / 9 - 1 : 0;
 }
 
-// One wave per vertex slot: cross[slot][dir] = k(x_p, x_q) - v_p . v_q for q = p + dir.
-// Each V column holds 16 * ceil(m / 16) written rows; within a 16-row block the rows
-// may sit in the MFMA's output order, which no dot product of two columns depends on.
-// Rows beyond the last block are padding and are not read.
-template <class T>
-__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int mp, int mrows, const int32_t* __restrict__ vlist,
-                                               const int64_t* __restrict__ nv_dev, int64_t nv_cap,
+// Neighbour cross-covariances cross[slot][dir] = k(x_p, x_q) - v_p . v_q, q = p + dir.
+// A work-group owns a BX x BY x BZ brick of vertices (one thread each) and stages the V
+// columns of the brick and its halo (x and y -1..+1, z +1) through LDS in chunks of R
+// rows; each thread accumulates its 13 (3D) or 4 (2D) dot products in binary64.
+// Each V column holds 16 * ceil(m / 16) written rows; within a 16-row block the rows may
+// sit in the MFMA's output order, which no dot product of two columns depends on.
+constexpr int CBX = 8, CBY = 8, CBZ = 4;
+constexpr int CHX = CBX + 2, CHY = CBY + 2, CHZ = CBZ + 1;
+
+template <class T, int R>
+__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int mp, int mrows,
                                                const int32_t* __restrict__ slot, const T* __restrict__ V,
                                                double* __restrict__ cross)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    int64_t nv = nv_dev ? *nv_dev : nv_cap;
-    if (nv > nv_cap) nv = nv_cap;
+    __shared__ T sv[CHX * CHY * CHZ][R + 1];
+    __shared__ int32_t hs[CHX * CHY * CHZ];
+    __shared__ int any;
     const int D = g.dim;
     const int ndir = D == 3 ? 13 : 4;
-    constexpr int PER = kMaxM / 64;
-    for (int64_t p = wid; p < nv; p += nw) {
-        const int64_t vid = vlist ? (int64_t)vlist[p] : p;
-        int64_t c[3];
-        c[0] = vid % g.n[0];
-        c[1] = (vid / g.n[0]) % g.n[1];
-        c[2] = vid / (g.n[0] * g.n[1]);
-        double xp[3] = {vertex_coord(g, 0, c[0]), vertex_coord(g, 1, c[1]), D == 3 ? vertex_coord(g, 2, c[2]) : 0.0};
-        double vp[PER];
-        const T* Vp = V + (size_t)p * mp;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            int j = lane + 64 * k;
-            vp[k] = j < mrows ? (double)Vp[j] : 0.0;
+    const int tid = threadIdx.x;
+    const int64_t nbx = (g.n[0] + CBX - 1) / CBX, nby = (g.n[1] + CBY - 1) / CBY;
+    const int64_t nbz = D == 3 ? (g.n[2] + CBZ - 1) / CBZ : 1;
+    const int hz_n = D == 3 ? CHZ : 1;
+    const int nh = CHX * CHY * hz_n;
+    for (int64_t brick = blockIdx.x; brick < nbx * nby * nbz; brick += gridDim.x) {
+        const int64_t bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
+        const int64_t x0 = bx * CBX, y0 = by * CBY, z0 = bz * (D == 3 ? CBZ : 1);
+        __syncthreads();
+        if (tid == 0) any = 0;
+        __syncthreads();
+        // slots of the halo vertices
+        for (int h = tid; h < nh; h += blockDim.x) {
+            const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
+            const int64_t x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 + hz;
+            int32_t sl = -1;
+            if (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z < g.n[2]) {
+                const int64_t vid = x + g.n[0] * (y + g.n[1] * z);
+                sl = slot ? slot[vid] : (int32_t)vid;
+            }
+            hs[h] = sl;
         }
+        __syncthreads();
+        // owner of this thread
+        const int ox = tid % CBX, oy = (tid / CBX) % CBY, oz = D == 3 ? tid / (CBX * CBY) : 0;
+        const bool owner_thread = D == 3 || tid < CBX * CBY;
+        const int oh = (ox + 1) + CHX * ((oy + 1) + CHY * oz);
+        const int32_t my = owner_thread ? hs[oh] : -1;
+        if (my >= 0) any = 1;
+        __syncthreads();
+        if (!any) continue;
+        int nbh[13];
         for (int dir = 0; dir < ndir; ++dir) {
             int dx, dy, dz;
             dir_offset(D, dir, dx, dy, dz);
-            int64_t q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-            bool in = q[0] >= 0 && q[0] < g.n[0] && q[1] >= 0 && q[1] < g.n[1] && q[2] >= 0 && q[2] < g.n[2];
-            int64_t sq = -1;
-            if (in) {
-                int64_t vq = q[0] + g.n[0] * (q[1] + g.n[1] * q[2]);
-                sq = slot ? (int64_t)slot[vq] : vq;
-            }
-            double out = __builtin_nan("");
-            if (sq >= 0) {
-                const T* Vq = V + (size_t)sq * mp;
-                double s = 0.0;
+            nbh[dir] = (ox + 1 + dx) + CHX * ((oy + 1 + dy) + CHY * (oz + dz));
+        }
+        double acc[13];
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    int j = lane + 64 * k;
-                    if (j < mrows) s = fma(vp[k], (double)Vq[j], s);
+        for (int dir = 0; dir < 13; ++dir) acc[dir] = 0.0;
+        // staging: 16-byte loads, all of a thread's loads issued before any LDS store
+        constexpr int PV = 16 / sizeof(T);                 // elements per 16-byte load
+        constexpr int NV = CHX * CHY * CHZ * R / PV;       // 16-byte pieces per chunk (3D)
+        constexpr int PER = (NV + 255) / 256;
+        using V4 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+        for (int r0 = 0; r0 < mrows; r0 += R) {
+            V4 buf[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int e = tid + 256 * k;
+                const int h = e / (R / PV), r = (e % (R / PV)) * PV;
+                V4 v = V4{};
+                if (h < nh) {
+                    const int32_t sl = hs[h];
+                    if (sl >= 0 && r0 + r < mrows) v = *(const V4*)(V + (size_t)sl * mp + r0 + r);
                 }
-                for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-                double xq[3] = {vertex_coord(g, 0, q[0]), vertex_coord(g, 1, q[1]),
-                                D == 3 ? vertex_coord(g, 2, q[2]) : 0.0};
-                out = kernel_val(kp, kernel_r2(kp, xp, xq)) - s;
+                buf[k] = v;
             }
-            if (lane == 0) cross[(size_t)p * ndir + dir] = out;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int e = tid + 256 * k;
+                const int h = e / (R / PV), r = (e % (R / PV)) * PV;
+                if (h < nh)
+#pragma unroll
+                    for (int i = 0; i < PV; ++i) sv[h][r + i] = buf[k][i];
+            }
+            __syncthreads();
+            if (my >= 0) {
+#pragma unroll 4
+                for (int r = 0; r < R; ++r) {
+                    const double vp = (double)sv[oh][r];
+#pragma unroll
+                    for (int dir = 0; dir < 13; ++dir)
+                        if (dir < ndir) acc[dir] = fma(vp, (double)sv[nbh[dir]][r], acc[dir]);
+                }
+            }
+        }
+        if (my >= 0) {
+            const int64_t px = x0 + ox, py = y0 + oy, pz = z0 + oz;
+            const double xp[3] = {vertex_coord(g, 0, px), vertex_coord(g, 1, py), D == 3 ? vertex_coord(g, 2, pz) : 0.0};
+            for (int dir = 0; dir < ndir; ++dir) {
+                int dx, dy, dz;
+                dir_offset(D, dir, dx, dy, dz);
+                double out = __builtin_nan("");
+                if (hs[nbh[dir]] >= 0) {
+                    const double xq[3] = {vertex_coord(g, 0, px + dx), vertex_coord(g, 1, py + dy),
+                                          D == 3 ? vertex_coord(g, 2, pz + dz) : 0.0};
+                    out = kernel_val(kp, kernel_r2(kp, xp, xq)) - acc[dir];
+                }
+                cross[(size_t)my * ndir + dir] = out;
+            }
         }
     }
 }
@@ -254,15 +308,18 @@ inline unsigned grid_for(int64_t n, int per)
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s)
 {
+    (void)vlist;
+    (void)nv_dev;
     if (nv_cap <= 0) return hipSuccess;
     StageScope sc(s, ST_CROSS);
-    unsigned grid = grid_for(nv_cap * 64, 256);
+    const int64_t nb = ceil_div(g.n[0], CBX) * ceil_div(g.n[1], CBY) * (g.dim == 3 ? ceil_div(g.n[2], CBZ) : 1);
+    const unsigned grid = (unsigned)(nb < 65536 ? nb : 65536);
     if (prec == LCP_FP64)
-        hipLaunchKernelGGL(k_cross<double>, dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, vlist, nv_dev, nv_cap,
-                           slot, (const double*)V, cross);
+        hipLaunchKernelGGL((k_cross<double, 16>), dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, slot,
+                           (const double*)V, cross);
     else
-        hipLaunchKernelGGL(k_cross<float>, dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, vlist, nv_dev, nv_cap,
-                           slot, (const float*)V, cross);
+        hipLaunchKernelGGL((k_cross<float, 32>), dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, slot,
+                           (const float*)V, cross);
     return hipGetLastError();
 }
 

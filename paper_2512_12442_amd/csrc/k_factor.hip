@@ -7,7 +7,7 @@ namespace lcp {
 
 size_t model_bytes(int m)
 {
-    int mp = (m + 31) / 32 * 32;
+    int mp = (m + 127) / 128 * 128;
     size_t b = 0;
     b += align256(sizeof(double) * mp * 4);          // X
     b += align256(sizeof(double) * mp);              // a

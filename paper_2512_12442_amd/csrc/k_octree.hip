@@ -164,21 +164,43 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
     }
 }
 
+// Region bound of Sec. 4.1 in three stages with the decision of the full search:
+// UB = 1 - B^d is non-increasing in g_min and every evaluated point can only lower g_min,
+// so a node is subdivided as soon as one evaluated point gives UB > alpha.
+//   stage 1: the box centre (also the side for nodes without observations);
+//   stage 2: the {lo, mid, hi}^D lattice for nodes stage 1 left open;
+//   stage 3: projected-gradient steps for nodes the lattice left open.
 struct BoundBufs {
-    int32_t* bnode;     // bound-node -> frontier index
+    int32_t* bnode;     // stage-1 node -> frontier index
     double* side;
     double* gmin;
-    double* x;          // current search point, 3 per node
-    int32_t* done;
-    double* lat_pts;    // 3^D points per node, 3 doubles each
+    double* cpts;       // stage-1 centres, 3 per node
+    double* cmean;
+    double* cvar;
+    int32_t* flag;      // per stage-1 node: needs the next stage
+    int32_t* fidx;      // prefix sum of flag
+    int32_t* lnode;     // stage-2 node -> stage-1 node
+    double* lat_pts;    // 3^D points per stage-2 node, 3 doubles each
     double* lat_mean;
     double* lat_var;
-    double* gp_mean;    // posterior with gradient at the current point
+    int32_t* dnode;     // stage-3 node -> stage-1 node
+    double* x;          // stage-3 search point, 3 per node
+    int32_t* done;
+    double* gp_mean;    // posterior (and gradient) at the stage-3 points
     double* gp_var;
     double* gp_dmean;
     double* gp_dvar;
-    int64_t* cnt;       // [0] bound nodes, [1] lattice points
+    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] lattice points, [3] stage-3 nodes
 };
+
+__device__ __forceinline__ double upper_bound(double gmin, int64_t dp)
+{
+    double t;
+    if (gmin == __builtin_inf()) t = 0.0;
+    else if (gmin == -__builtin_inf()) t = 1.0;
+    else t = 0.5 * erfc(gmin / 1.41421356237309504880168872421);
+    return t >= 1.0 ? 1.0 : -expm1((double)dp * log1p(-t));
+}
 
 __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
                               int64_t cap, const int32_t* __restrict__ need, const int32_t* __restrict__ nidx,
@@ -186,7 +208,6 @@ __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ key
 {
     int64_t nf = *nf_dev;
     if (nf > cap) nf = cap;
-    const int npt = o.D == 3 ? 27 : 9;
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
         if (!need[f]) continue;
         const int64_t b = nidx[f];
@@ -196,64 +217,132 @@ __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ key
         double blo[3], bhi[3];
         key_coords(o.D, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        for (int d = 0; d < 3; ++d) B.cpts[b * 3 + d] = d < o.D ? 0.5 * (blo[d] + bhi[d]) : 0.0;
+    }
+}
+
+// Stage 1: side choice and the centre's bound.
+__global__ void k_bound_centre(Oct o, int level, const uint64_t* __restrict__ keys, const int32_t* __restrict__ path,
+                               BoundBufs B, int32_t* __restrict__ sub)
+{
+    const int64_t nb = B.cnt[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f = B.bnode[b];
+        const int p = path[f];
+        const double side = p == 1 ? 1.0 : (p == 2 ? -1.0 : (B.cmean[b] < o.theta ? 1.0 : -1.0));
+        const double g = margin(side, o.theta, B.cmean[b], B.cvar[b]);
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        B.side[b] = side;
+        B.gmin[b] = g;
+        const bool open = !(upper_bound(g, dp) > o.alpha);
+        if (!open) sub[f] = 1;
+        B.flag[b] = open ? 1 : 0;
+    }
+}
+
+// Stage 2 set-up: the 3^D lattice points of the open nodes.
+__global__ void k_lattice_setup(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
+{
+    const int64_t nb = B.cnt[0];
+    const int npt = o.D == 3 ? 27 : 9;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        if (!B.flag[b]) continue;
+        const int64_t l = B.fidx[b];
+        B.lnode[l] = (int32_t)b;
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[B.bnode[b]], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
         for (int i = 0; i < npt; ++i) {
             int r = i;
             for (int d = 0; d < 3; ++d) {
                 double x = 0.0;
                 if (d < o.D) {
-                    int digit = r % 3;
+                    const int digit = r % 3;
                     r /= 3;
                     x = digit == 0 ? blo[d] : (digit == 1 ? 0.5 * (blo[d] + bhi[d]) : bhi[d]);
                 }
-                B.lat_pts[(b * npt + i) * 3 + d] = x;
+                B.lat_pts[(l * npt + i) * 3 + d] = x;
             }
         }
     }
 }
 
-// Side choice (centre mean for nodes without observations), lattice minimum, start point.
-__global__ void k_lattice(Oct o, const int32_t* __restrict__ path, BoundBufs B)
+// Stage 2: lattice minimum (lowest index wins ties), start point, bound; nodes left open
+// go to the descent (or are skipped when the search has no steps).
+__global__ void k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B, int32_t* __restrict__ sub)
 {
-    const int64_t nb = B.cnt[0];
+    const int64_t nl = B.cnt[1];
     const int npt = o.D == 3 ? 27 : 9;
-    const int centre = o.D == 3 ? 13 : 4;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        const int p = path[B.bnode[b]];
-        double side;
-        if (p == 1) side = 1.0;
-        else if (p == 2) side = -1.0;
-        else side = (B.lat_mean[b * npt + centre] < o.theta) ? 1.0 : -1.0;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = B.lnode[l];
+        const double side = B.side[b];
         double best = __builtin_inf();
         int ib = 0;
         for (int i = 0; i < npt; ++i) {
-            double gv = margin(side, o.theta, B.lat_mean[b * npt + i], B.lat_var[b * npt + i]);
+            const double gv = margin(side, o.theta, B.lat_mean[l * npt + i], B.lat_var[l * npt + i]);
             if (gv < best) {
                 best = gv;
                 ib = i;
             }
         }
-        B.side[b] = side;
+        const int32_t f = B.bnode[b];
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
         B.gmin[b] = best;
-        B.done[b] = 0;
-        for (int d = 0; d < 3; ++d) B.x[b * 3 + d] = B.lat_pts[(b * npt + ib) * 3 + d];
+        const bool open = !(upper_bound(best, dp) > o.alpha);
+        if (!open) sub[f] = 1;
+        B.flag[b] = (open && o.steps > 0) ? 2 : 0;       // 2: enters the descent
+        for (int d = 0; d < 3; ++d) B.x[(int64_t)b * 3 + d] = B.lat_pts[(l * npt + ib) * 3 + d];
+    }
+}
+
+// Clear the flags of nodes stage 2 did not see (resolved at stage 1).
+__global__ void k_flag_stage3(BoundBufs B)
+{
+    const int64_t nb = B.cnt[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x)
+        B.flag[b] = B.flag[b] == 2 ? 1 : 0;
+}
+
+// Stage 3 set-up: compact the open nodes; their points move to the stage-3 arrays.
+__global__ void k_descent_setup(BoundBufs B, double* __restrict__ gx)
+{
+    const int64_t nb = B.cnt[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        if (!B.flag[b]) continue;
+        const int64_t d = B.fidx[b];
+        B.dnode[d] = (int32_t)b;
+        B.done[d] = 0;
+        for (int k = 0; k < 3; ++k) gx[d * 3 + k] = B.x[(int64_t)b * 3 + k];
     }
 }
 
 // One projected step of the bound search at the current point x_k (posterior and its
 // gradient already evaluated).  For k >= 1 the value at x_k also enters the minimum.
-__global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ keys, BoundBufs B)
+__global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ keys, BoundBufs B,
+                          double* __restrict__ gx)
 {
-    const int64_t nb = B.cnt[0];
+    const int64_t nd = B.cnt[3];
     double eta = 0.5;
     for (int i = 0; i < k; ++i) eta *= 0.5;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        if (B.done[b]) continue;
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
+        if (B.done[d]) continue;
+        const int32_t b = B.dnode[d];
         const double side = B.side[b];
-        const double mu = B.gp_mean[b], var = B.gp_var[b];
+        const double mu = B.gp_mean[d], var = B.gp_var[d];
         const double g = margin(side, o.theta, mu, var);
         if (k >= 1 && g < B.gmin[b]) B.gmin[b] = g;
         if (!(var > 0.0)) {
-            B.done[b] = 1;
+            B.done[d] = 1;
             continue;
         }
         int lv;
@@ -263,34 +352,35 @@ __global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ 
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         const double sd = sqrt(var);
         double u[3], nrm = 0.0;
-        for (int d = 0; d < o.D; ++d) {
-            const double dsd = B.gp_dvar[b * 3 + d] / (2.0 * sd);
-            const double gr = side * (-B.gp_dmean[b * 3 + d] * sd - (o.theta - mu) * dsd) / var;
-            u[d] = (bhi[d] - blo[d]) * gr;
-            nrm += u[d] * u[d];
+        for (int a = 0; a < o.D; ++a) {
+            const double dsd = B.gp_dvar[d * 3 + a] / (2.0 * sd);
+            const double gr = side * (-B.gp_dmean[d * 3 + a] * sd - (o.theta - mu) * dsd) / var;
+            u[a] = (bhi[a] - blo[a]) * gr;
+            nrm += u[a] * u[a];
         }
         nrm = sqrt(nrm);
         if (!(nrm > 0.0) || !isfinite(nrm)) {
-            B.done[b] = 1;
+            B.done[d] = 1;
             continue;
         }
-        for (int d = 0; d < o.D; ++d) {
-            const double w = bhi[d] - blo[d];
-            double xn = B.x[b * 3 + d] - eta * w * u[d] / nrm;
-            B.x[b * 3 + d] = xn < blo[d] ? blo[d] : (xn > bhi[d] ? bhi[d] : xn);
+        for (int a = 0; a < o.D; ++a) {
+            const double w = bhi[a] - blo[a];
+            const double xn = gx[d * 3 + a] - eta * w * u[a] / nrm;
+            gx[d * 3 + a] = xn < blo[a] ? blo[a] : (xn > bhi[a] ? bhi[a] : xn);
         }
     }
 }
 
 // Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)), and the decision.
 __global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
-                              int32_t* __restrict__ sub, double* __restrict__ ub_out)
+                              int32_t* __restrict__ sub)
 {
-    const int64_t nb = B.cnt[0];
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nd = B.cnt[3];
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = B.dnode[d];
         double gmin = B.gmin[b];
-        if (!B.done[b] && o.steps > 0) {
-            double g = margin(B.side[b], o.theta, B.gp_mean[b], B.gp_var[b]);
+        if (!B.done[d]) {
+            const double g = margin(B.side[b], o.theta, B.gp_mean[d], B.gp_var[d]);
             if (g < gmin) gmin = g;
         }
         const int32_t f = B.bnode[b];
@@ -299,13 +389,7 @@ __global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ key
         double blo[3], bhi[3];
         key_coords(o.D, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
-        double t;
-        if (gmin == __builtin_inf()) t = 0.0;
-        else if (gmin == -__builtin_inf()) t = 1.0;
-        else t = 0.5 * erfc(gmin / 1.41421356237309504880168872421);
-        double ub = t >= 1.0 ? 1.0 : -expm1((double)dp * log1p(-t));
-        sub[f] = ub > o.alpha ? 1 : 0;
-        if (ub_out) ub_out[f] = ub;
+        sub[f] = upper_bound(gmin, dp) > o.alpha ? 1 : 0;
     }
 }
 
@@ -456,6 +540,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_x, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
+    size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb;
     int64_t capF, nv;
 };
@@ -496,6 +581,14 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_eoff = take(4 * capF);
     L.o_ub = take(8 * capF);
     L.o_bnode = take(4 * capF);
+    L.o_cpts = take(24 * capF);
+    L.o_cmean = take(8 * capF);
+    L.o_cvar = take(8 * capF);
+    L.o_flag = take(4 * capF);
+    L.o_fidx = take(4 * capF);
+    L.o_lnode = take(4 * capF);
+    L.o_dnode = take(4 * capF);
+    L.o_gx = take(24 * capF);
     L.o_side = take(8 * capF);
     L.o_gmin = take(8 * capF);
     L.o_x = take(24 * capF);
@@ -565,6 +658,14 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     char* scanws = (char*)P(L.o_scan);
     BoundBufs B;
     B.bnode = (int32_t*)P(L.o_bnode);
+    B.cpts = (double*)P(L.o_cpts);
+    B.cmean = (double*)P(L.o_cmean);
+    B.cvar = (double*)P(L.o_cvar);
+    B.flag = (int32_t*)P(L.o_flag);
+    B.fidx = (int32_t*)P(L.o_fidx);
+    B.lnode = (int32_t*)P(L.o_lnode);
+    B.dnode = (int32_t*)P(L.o_dnode);
+    double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
     B.gmin = (double*)P(L.o_gmin);
     B.x = (double*)P(L.o_x);
@@ -609,60 +710,59 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         e = launch_scan(need, nidx, cap, nf, B.cnt + 0, scanws, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_bound_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, need, nidx, B);
-        hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, B.cnt + 1, B.cnt + 0, (int64_t)npt);
         }
-        // lattice values (binary64)
-        PostTask t{};
-        t.mode = COL_POINTS;
-        t.group = 1;
-        t.count = B.cnt + 1;
-        t.n_points = cap * npt;
-        t.pts = B.lat_pts;
-        t.pstride = 3;
-        t.mean = B.lat_mean;
-        t.var = B.lat_var;
-        t.stage = ST_BOUND;
-        e = launch_posterior(M, LCP_FP64, t, s);
+        auto post = [&](int64_t* count, int64_t cap_pts, const double* pts, double* mean, double* var, double* dmean,
+                        double* dvar, int group) {
+            PostTask t{};
+            t.mode = COL_POINTS;
+            t.group = group;
+            t.count = count;
+            t.n_points = cap_pts;
+            t.pts = pts;
+            t.pstride = 3;
+            t.mean = mean;
+            t.var = var;
+            t.dmean = dmean;
+            t.dvar = dvar;
+            t.stage = ST_BOUND;
+            return launch_posterior(M, LCP_FP64, t, s);
+        };
+        // stage 1: centres
+        e = post(B.cnt + 0, cap, B.cpts, B.cmean, B.cvar, nullptr, nullptr, 1);
         if (e != hipSuccess) return e;
         {
             StageScope sc(s, ST_OCTREE);
-            hipLaunchKernelGGL(k_lattice, dim3(gsz(cap, 256)), dim3(256), 0, s, o, path, B);
+            hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
+            e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 1, scanws, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, B.cnt + 2, B.cnt + 1, (int64_t)npt);
+            hipLaunchKernelGGL(k_lattice_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
         }
+        // stage 2: lattice
+        e = post(B.cnt + 2, cap * npt, B.lat_pts, B.lat_mean, B.lat_var, nullptr, nullptr, 1);
+        if (e != hipSuccess) return e;
+        {
+            StageScope sc(s, ST_OCTREE);
+            hipLaunchKernelGGL(k_lattice, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
+            hipLaunchKernelGGL(k_flag_stage3, dim3(gsz(cap, 256)), dim3(256), 0, s, B);
+            e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 3, scanws, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_descent_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, B, gx);
+        }
+        // stage 3: projected-gradient steps
         for (int k = 0; k < A.descent_steps; ++k) {
-            PostTask tg{};
-            tg.mode = COL_POINTS;
-            tg.group = 4;
-            tg.count = B.cnt + 0;
-            tg.n_points = cap;
-            tg.pts = B.x;
-            tg.pstride = 3;
-            tg.mean = B.gp_mean;
-            tg.var = B.gp_var;
-            tg.dmean = B.gp_dmean;
-            tg.dvar = B.gp_dvar;
-            tg.stage = ST_BOUND;
-            e = launch_posterior(M, LCP_FP64, tg, s);
+            e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
             if (e != hipSuccess) return e;
             StageScope sc(s, ST_OCTREE);
-            hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B);
+            hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B, gx);
         }
         if (A.descent_steps > 0) {
-            PostTask tv{};
-            tv.mode = COL_POINTS;
-            tv.group = 1;
-            tv.count = B.cnt + 0;
-            tv.n_points = cap;
-            tv.pts = B.x;
-            tv.pstride = 3;
-            tv.mean = B.gp_mean;
-            tv.var = B.gp_var;
-            tv.stage = ST_BOUND;
-            e = launch_posterior(M, LCP_FP64, tv, s);
+            e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
             if (e != hipSuccess) return e;
         }
         StageScope sc(s, ST_OCTREE);
-        hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub,
-                           (double*)P(L.o_ub));
+        if (A.descent_steps > 0)
+            hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
         hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
         int64_t* nout = (l == Lmax) ? n_leaves : cnt + l + 1;
         e = launch_scan(ecnt, eoff, cap, nf, nout, scanws, s);
@@ -686,7 +786,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     int32_t* voff = (int32_t*)P(L.o_voff);
     int32_t* slot = (int32_t*)P(L.o_slot);
     int32_t* vlist = (int32_t*)P(L.o_vlist);
-    int64_t* nvd = cnt + 18;
+    int64_t* nvd = cnt + 24;
     e = launch_fill_i32(vmask, 0, L.nv, s);
     if (e != hipSuccess) return e;
     int64_t per = 1;

@@ -19,18 +19,20 @@ constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 
 // Precision traits: operand types, MFMA k-step, fragment arrays and LDS element type.
+// LDS column stride of B = m_pad + LPAD elements, chosen so the lanes of one LDS pass of the
+// B-fragment reads fall on distinct banks (b64: 16 lanes, b32: 32 lanes, b128: 8 lanes).
 struct P64 {
     using Acc = d4;
     using Elem = double;
     static constexpr int KS = 4;
-    static constexpr int LPAD = 4;   // LDS column stride = m_pad + LPAD elements
+    static constexpr int LPAD = 1;
     static constexpr bool kScaled = false;
 };
 struct P32 {
     using Acc = f4;
     using Elem = float;
     static constexpr int KS = 4;
-    static constexpr int LPAD = 4;
+    static constexpr int LPAD = 2;
     static constexpr bool kScaled = false;
 };
 // 16-bit split product: x = hi + lo in T16, V += lo_A hi_B + hi_A lo_B + hi_A hi_B.
@@ -41,11 +43,27 @@ struct P16 {
     using Elem = T16;
     using Vec = T16 __attribute__((ext_vector_type(8)));
     static constexpr int KS = 32;
-    static constexpr int LPAD = 32;
+    static constexpr int LPAD = 8;
     static constexpr bool kScaled = SCALED;
 };
 using PB3 = P16<__bf16, false>;
 using PH3 = P16<_Float16, true>;
+
+// x = hi + lo in 16-bit halves, formed in binary32 with hardware conversions: the
+// residual x32 - hi is exact in binary32, so hi + lo carries about 2 x 11 (FP16) or
+// 2 x 8 (BF16) significant bits of x.
+__device__ __forceinline__ void split16(double x, _Float16& hi, _Float16& lo)
+{
+    const float f = (float)x;
+    hi = __builtin_amdgcn_cvt_pkrtz(f, 0.0f)[0];
+    lo = __builtin_amdgcn_cvt_pkrtz(f - (float)hi, 0.0f)[0];
+}
+__device__ __forceinline__ void split16(double x, __bf16& hi, __bf16& lo)
+{
+    const float f = (float)x;
+    hi = (__bf16)f;
+    lo = (__bf16)(f - (float)hi);
+}
 
 __device__ __forceinline__ f4 mfma16(bf8 a, bf8 b, f4 c)
 {
@@ -92,13 +110,13 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     using Elem = typename P::Elem;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar)
     const int mp = A.mp;
     const int ldb = lds_ld<P>(mp);
     Elem* Bt = (Elem*)smem;                                   // [plane][NT][ldb]
-    double* red = (double*)(smem + sizeof(Elem) * (size_t)lds_planes<P>() * NT * ldb);  // [kWaves][NT]
-    double* mucol = red + kWaves * NT;                        // [NT]
-    double* pts = mucol + NT;                                 // [NT/G][3]
+    double* red = (double*)(smem + sizeof(Elem) * (size_t)lds_planes<P>() * NT * ldb);  // [256 / NP][NT]
+    double* mucol = red + kThreads * G;                       // [NT]
 
     const PostTask& T = A.t;
     int64_t npts = T.count ? *T.count : T.n_points;
@@ -107,102 +125,81 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
     const int64_t ntiles = (ncols + NT - 1) / NT;
     const int dim = A.kp.dim;
 
-    // rows of X owned by this thread for B generation (m_pad <= 1024 -> <= 4 rows)
-    constexpr int RPT = kMaxM / kThreads;
-    double xr[RPT][3], ar[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        int j = tid + r * kThreads;
-        bool ok = j < A.m;
-        for (int d = 0; d < 3; ++d) xr[r][d] = ok ? A.X[j * 4 + d] : 0.0;
-        ar[r] = ok ? A.a[j] : 0.0;
-    }
+    // B generation layout: thread t serves point pc = t % NP of the tile (NP = NT / G points)
+    // for the rows j = t / NP + k * (256 / NP); its mean partials cover its own columns only
+    // and are combined through LDS once per tile.
+    constexpr int NP = NT / G;
+    constexpr int RSTEP = kThreads / NP;
+    const int pc = tid % NP, jg = tid / NP;
+    const double ie0 = A.kp.inv_ell[0], ie1 = A.kp.inv_ell[1], ie2 = A.kp.inv_ell[2];
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t col0 = tile * NT;
         __syncthreads();   // previous tile fully consumed
-        // ---- point coordinates of this tile
-        if (tid < NT / G) {
-            int64_t p = col0 / G + tid;
-            double x[3] = {0.0, 0.0, 0.0};
-            if (p < npts) {
-                if (T.mode == COL_GRID) {
-                    int64_t v = T.vlist ? (int64_t)T.vlist[p] : p;
-                    int64_t i0 = v % T.grid.n[0];
-                    int64_t r = v / T.grid.n[0];
-                    int64_t i1 = r % T.grid.n[1];
-                    int64_t i2 = r / T.grid.n[1];
-                    x[0] = vertex_coord(T.grid, 0, i0);
-                    x[1] = vertex_coord(T.grid, 1, i1);
-                    x[2] = dim > 2 ? vertex_coord(T.grid, 2, i2) : 0.0;
-                } else {
-                    for (int d = 0; d < dim; ++d) x[d] = T.pts[p * T.pstride + d];
-                }
+        // ---- this thread's point
+        const int64_t p = col0 / G + pc;
+        const bool valid = p < npts;
+        double px = 0.0, py = 0.0, pz = 0.0;
+        if (valid) {
+            if (T.mode == COL_GRID) {
+                const int64_t v = T.vlist ? (int64_t)T.vlist[p] : p;
+                const int64_t i0 = v % T.grid.n[0];
+                const int64_t r = v / T.grid.n[0];
+                const int64_t i1 = r % T.grid.n[1];
+                const int64_t i2 = r / T.grid.n[1];
+                px = vertex_coord(T.grid, 0, i0);
+                py = vertex_coord(T.grid, 1, i1);
+                pz = dim > 2 ? vertex_coord(T.grid, 2, i2) : 0.0;
+            } else {
+                px = T.pts[p * T.pstride + 0];
+                py = T.pts[p * T.pstride + 1];
+                pz = dim > 2 ? T.pts[p * T.pstride + 2] : 0.0;
             }
-            pts[tid * 3 + 0] = x[0];
-            pts[tid * 3 + 1] = x[1];
-            pts[tid * 3 + 2] = x[2];
         }
-        __syncthreads();
-        // ---- generate B (transposed: Bt[c][j]) and the per-column mean partials
-        for (int pc = 0; pc < NT / G; ++pc) {
-            const int64_t p = col0 / G + pc;
-            const bool valid = p < npts;
-            const double px = pts[pc * 3 + 0], py = pts[pc * 3 + 1], pz = pts[pc * 3 + 2];
-            double part[G];
+        // ---- generate B (transposed: Bt[c][j]) and the mean partials of this thread's columns
+        double part[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) part[g] = 0.0;
+        for (int g = 0; g < G; ++g) part[g] = 0.0;
+        for (int j = jg; j < mp; j += RSTEP) {
+            const bool live = valid && j < A.m;
+            const double* xj = A.X + (size_t)j * 4;
+            const double dx = px - xj[0], dy = py - xj[1], dz = pz - xj[2];
+            const double t0 = dx * ie0, t1 = dy * ie1, t2 = dz * ie2;
+            const double r2 = fma(t2, t2, fma(t1, t1, t0 * t0));
+            const double aj = A.a[j];
+            double b[G];
+            if (G == 1) {
+                b[0] = live ? kernel_val(A.kp, r2) : 0.0;
+            } else {
+                double kv = 0.0, f = 0.0;
+                if (live) kernel_val_dfac(A.kp, r2, &kv, &f);
+                b[0] = kv;
+                const double dd[3] = {dx * ie0 * ie0, dy * ie1 * ie1, dz * ie2 * ie2};
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int j = tid + r * kThreads;
-                if (j >= mp) break;
-                double b[G];
-                double dx[3] = {px - xr[r][0], py - xr[r][1], pz - xr[r][2]};
-                double r2 = 0.0;
-                for (int d = 0; d < dim; ++d) {
-                    double tt = dx[d] * A.kp.inv_ell[d];
-                    r2 = fma(tt, tt, r2);
-                }
-                const bool live = valid && j < A.m;
-                if (G == 1) {
-                    b[0] = live ? kernel_val(A.kp, r2) : 0.0;
-                } else {
-                    double kv = 0.0, f = 0.0;
-                    if (live) {
-                        kv = kernel_val(A.kp, r2);
-                        f = kernel_dfac(A.kp, r2);
-                    }
-                    b[0] = kv;
-#pragma unroll
-                    for (int d = 0; d < G - 1; ++d)
-                        b[d + 1] = (d < dim) ? f * dx[d] * A.kp.inv_ell[d] * A.kp.inv_ell[d] : 0.0;
-                }
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    part[g] = fma(b[g], ar[r], part[g]);
-                    const int c = pc * G + g;
-                    if constexpr (P::KS == 32) {
-                        double bs = b[g];
-                        if constexpr (P::kScaled) bs *= A.sB;
-                        Elem hi = (Elem)(float)bs;
-                        Elem lo = (Elem)(float)(bs - (double)(float)hi);
-                        Bt[(size_t)c * ldb + j] = hi;
-                        Bt[(size_t)(NT + c) * ldb + j] = lo;
-                    } else {
-                        Bt[(size_t)c * ldb + j] = (Elem)b[g];
-                    }
-                }
+                for (int d = 0; d < G - 1; ++d) b[d + 1] = (d < 3) ? f * dd[d] : 0.0;
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                double s = wave_sum(part[g]);
-                if (lane == 0) red[wave * NT + pc * G + g] = s;
+                part[g] = fma(b[g], aj, part[g]);
+                const int c = pc * G + g;
+                if constexpr (P::KS == 32) {
+                    double bs = b[g];
+                    if constexpr (P::kScaled) bs *= A.sB;
+                    Elem hi, lo;
+                    split16(bs, hi, lo);
+                    Bt[(size_t)c * ldb + j] = hi;
+                    Bt[(size_t)(NT + c) * ldb + j] = lo;
+                } else {
+                    Bt[(size_t)c * ldb + j] = (Elem)b[g];
+                }
             }
         }
+#pragma unroll
+        for (int g = 0; g < G; ++g) red[jg * NT + pc * G + g] = part[g];
         __syncthreads();
         if (tid < NT) {
             double s = 0.0;
-            for (int w = 0; w < kWaves; ++w) s += red[w * NT + tid];
+            for (int w = 0; w < RSTEP; ++w) s += red[w * NT + tid];
             mucol[tid] = s;
         }
 
@@ -215,76 +212,191 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
             for (int r = 0; r < 4; ++r) dacc[ct][r] = 0.0;
         const int gl = lane >> 4, cl = lane & 15;
         const int nks_total = mp / P::KS;
-        for (int q = 0; q * 8 < A.nrb; ++q) {
-            for (int h = 0; h < 2; ++h) {
-                const int rb = 8 * q + (h == 0 ? wave : 7 - wave);
-                if (rb >= A.nrb) continue;
-                const int nks = (16 * (rb + 1) + P::KS - 1) / P::KS;
-                typename P::Acc acc[NCT];
+        // epilogue of one finished 16-row block: norm / gradient dot partials and V stores
+        auto epilogue = [&](int rb, typename P::Acc (&acc)[NCT]) {
+            if constexpr (P::KS == 32 && P::kScaled) {
+                const float inv = (float)(1.0 / (A.amax[1] * A.sB));   // exact power of two
 #pragma unroll
-                for (int ct = 0; ct < NCT; ++ct) acc[ct] = typename P::Acc{0, 0, 0, 0};
-                if constexpr (P::KS == 4) {
-                    const Elem* Af = (const Elem*)A.A0 + ((size_t)rb * nks_total) * 64 + lane;
-#pragma unroll 4
-                    for (int s = 0; s < nks; ++s) {
-                        Elem av = Af[(size_t)s * 64];
+                for (int ct = 0; ct < NCT; ++ct) acc[ct] *= inv;
+            }
 #pragma unroll
-                        for (int ct = 0; ct < NCT; ++ct) {
-                            Elem bv = Bt[(size_t)(16 * ct + cl) * ldb + 4 * s + gl];
-                            if constexpr (sizeof(Elem) == 8)
-                                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
-                            else
-                                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ct], 0, 0, 0);
-                        }
-                    }
-                } else {
-                    using Vec = typename P::Vec;
-                    const Vec* Ah = (const Vec*)A.A0 + ((size_t)rb * nks_total) * 64 + lane;
-                    const Vec* Al = (const Vec*)A.A1 + ((size_t)rb * nks_total) * 64 + lane;
-#pragma unroll 2
-                    for (int s = 0; s < nks; ++s) {
-                        Vec ah = Ah[(size_t)s * 64];
-                        Vec al = Al[(size_t)s * 64];
+            for (int ct = 0; ct < NCT; ++ct) {
 #pragma unroll
-                        for (int ct = 0; ct < NCT; ++ct) {
-                            const size_t off = (size_t)(16 * ct + cl) * ldb + 32 * s + 8 * gl;
-                            Vec bh = *(const Vec*)(Bt + off);
-                            Vec bl = *(const Vec*)(Bt + (size_t)NT * ldb + off);
-                            acc[ct] = mfma16(al, bh, acc[ct]);
-                            acc[ct] = mfma16(ah, bl, acc[ct]);
-                            acc[ct] = mfma16(ah, bh, acc[ct]);
-                        }
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    double v = (double)acc[ct][r];
+                    double base = (G == 1) ? v : __shfl(v, lane & ~3, 64);
+                    dacc[ct][r] = fma(v, base, dacc[ct][r]);
                 }
-                // epilogue: one 16-row block of V for columns 16 ct + cl
-                if constexpr (P::KS == 32 && P::kScaled) {
-                    const float inv = (float)(1.0 / (A.amax[1] * A.sB));   // exact power of two
-#pragma unroll
-                    for (int ct = 0; ct < NCT; ++ct) acc[ct] *= inv;
-                }
-#pragma unroll
-                for (int ct = 0; ct < NCT; ++ct) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        double v = (double)acc[ct][r];
-                        double base = (G == 1) ? v : __shfl(v, lane & ~3, 64);
-                        dacc[ct][r] = fma(v, base, dacc[ct][r]);
-                    }
-                    if (G == 1 && T.V) {
-                        const int64_t p = col0 + 16 * ct + cl;
-                        if (p < npts) {
-                            if constexpr (sizeof(Elem) == 8) {
-                                double* Vp = (double*)T.V + (size_t)p * mp + 16 * rb + 4 * gl;
-                                *(d4*)Vp = acc[ct];
-                            } else {
-                                float* Vp = (float*)T.V + (size_t)p * mp + 16 * rb + 4 * gl;
-                                *(f4*)Vp = f4{(float)acc[ct][0], (float)acc[ct][1], (float)acc[ct][2],
-                                              (float)acc[ct][3]};
-                            }
+                if (G == 1 && T.V) {
+                    const int64_t p = col0 + 16 * ct + cl;
+                    if (p < npts) {
+                        if constexpr (sizeof(Elem) == 8) {
+                            double* Vp = (double*)T.V + (size_t)p * mp + 16 * rb + 4 * gl;
+                            *(d4*)Vp = acc[ct];
+                        } else {
+                            float* Vp = (float*)T.V + (size_t)p * mp + 16 * rb + 4 * gl;
+                            *(f4*)Vp = f4{(float)acc[ct][0], (float)acc[ct][1], (float)acc[ct][2],
+                                          (float)acc[ct][3]};
                         }
                     }
                 }
             }
+        };
+        // Each wave owns the row-block pair (8q + w, 8q + 7 - w) of every group of eight
+        // (equal triangular work per wave) and runs both in one k loop, so each B fragment
+        // read from LDS feeds both.  k-steps run in groups of U with two fragment buffers in
+        // ping-pong: the L^-1 fragments of group g + U are requested before group g is
+        // multiplied.  Loop bounds are rounded up to 2U k-steps (m_pad is a multiple of 128,
+        // so no group leaves the padded matrix; steps past the diagonal multiply zeros).
+        for (int q = 0; q * 8 < A.nrb; ++q) {
+            const int ra = 8 * q + wave, rbb = 8 * q + 7 - wave;
+            if (ra >= A.nrb) continue;                 // then rbb >= nrb as well
+            const bool hasB = rbb < A.nrb;
+            typename P::Acc accA[NCT], accB[NCT];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                accA[ct] = typename P::Acc{0, 0, 0, 0};
+                accB[ct] = typename P::Acc{0, 0, 0, 0};
+            }
+            constexpr int U = P::KS == 4 ? 4 : 2;
+            const int needA = (16 * (ra + 1) + P::KS - 1) / P::KS;
+            const int needB = (16 * (rbb + 1) + P::KS - 1) / P::KS;
+            const int gA = (needA + 2 * U - 1) / (2 * U) * (2 * U);
+            const int gB = hasB ? (needB + 2 * U - 1) / (2 * U) * (2 * U) : gA;
+            const int glast = nks_total - U;
+            if constexpr (P::KS == 4) {
+                const Elem* AfA = (const Elem*)A.A0 + ((size_t)ra * nks_total) * 64 + lane;
+                const Elem* AfB = (const Elem*)A.A0 + ((size_t)(hasB ? rbb : ra) * nks_total) * 64 + lane;
+                auto mf = [&](Elem a, Elem b, typename P::Acc c) {
+                    if constexpr (sizeof(Elem) == 8) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+                    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+                };
+                auto ld = [&](Elem (&d)[U], const Elem* Af, int g) {
+                    g = g < glast ? g : glast;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) d[u] = Af[(size_t)(g + u) * 64];
+                };
+                auto mul2 = [&](int g, const Elem (&xa)[U], const Elem (&xb)[U]) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int ct = 0; ct < NCT; ++ct) {
+                            const Elem bv = Bt[(size_t)(16 * ct + cl) * ldb + 4 * (g + u) + gl];
+                            accB[ct] = mf(xb[u], bv, accB[ct]);
+                            accA[ct] = mf(xa[u], bv, accA[ct]);
+                        }
+                };
+                auto mul1 = [&](int g, const Elem (&x)[U], typename P::Acc (&acc)[NCT]) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int ct = 0; ct < NCT; ++ct) {
+                            const Elem bv = Bt[(size_t)(16 * ct + cl) * ldb + 4 * (g + u) + gl];
+                            acc[ct] = mf(x[u], bv, acc[ct]);
+                        }
+                };
+                Elem a0[U], a1[U], b0[U], b1[U];
+                if (hasB) {
+                    ld(a0, AfA, 0);
+                    ld(b0, AfB, 0);
+                    for (int g = 0; g < gA; g += 2 * U) {
+                        ld(a1, AfA, g + U);
+                        ld(b1, AfB, g + U);
+                        mul2(g, a0, b0);
+                        ld(a0, AfA, g + 2 * U);
+                        ld(b0, AfB, g + 2 * U);
+                        mul2(g + U, a1, b1);
+                    }
+                    for (int g = gA; g < gB; g += 2 * U) {     // b0 holds group g
+                        ld(b1, AfB, g + U);
+                        mul1(g, b0, accB);
+                        ld(b0, AfB, g + 2 * U);
+                        mul1(g + U, b1, accB);
+                    }
+                } else {
+                    ld(a0, AfA, 0);
+                    for (int g = 0; g < gA; g += 2 * U) {
+                        ld(a1, AfA, g + U);
+                        mul1(g, a0, accA);
+                        ld(a0, AfA, g + 2 * U);
+                        mul1(g + U, a1, accA);
+                    }
+                }
+            } else {
+                using Vec = typename P::Vec;
+                const size_t oA = ((size_t)ra * nks_total) * 64 + lane;
+                const size_t oB = ((size_t)(hasB ? rbb : ra) * nks_total) * 64 + lane;
+                const Vec* AhA = (const Vec*)A.A0 + oA;
+                const Vec* AlA = (const Vec*)A.A1 + oA;
+                const Vec* AhB = (const Vec*)A.A0 + oB;
+                const Vec* AlB = (const Vec*)A.A1 + oB;
+                auto ld = [&](Vec (&h)[U], Vec (&l)[U], const Vec* Ah, const Vec* Al, int g) {
+                    g = g < glast ? g : glast;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        h[u] = Ah[(size_t)(g + u) * 64];
+                        l[u] = Al[(size_t)(g + u) * 64];
+                    }
+                };
+                auto mulg = [&](int g, const Vec (&ha)[U], const Vec (&la)[U], const Vec (&hb)[U],
+                                const Vec (&lb)[U], bool doA, bool doB) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        Vec bh[NCT], bl[NCT];
+#pragma unroll
+                        for (int ct = 0; ct < NCT; ++ct) {
+                            const size_t off = (size_t)(16 * ct + cl) * ldb + 32 * (g + u) + 8 * gl;
+                            bh[ct] = *(const Vec*)(Bt + off);
+                            bl[ct] = *(const Vec*)(Bt + (size_t)NT * ldb + off);
+                        }
+                        if (doB) {
+#pragma unroll
+                            for (int ct = 0; ct < NCT; ++ct) {
+                                accB[ct] = mfma16(lb[u], bh[ct], accB[ct]);
+                                accB[ct] = mfma16(hb[u], bl[ct], accB[ct]);
+                                accB[ct] = mfma16(hb[u], bh[ct], accB[ct]);
+                            }
+                        }
+                        if (doA) {
+#pragma unroll
+                            for (int ct = 0; ct < NCT; ++ct) {
+                                accA[ct] = mfma16(la[u], bh[ct], accA[ct]);
+                                accA[ct] = mfma16(ha[u], bl[ct], accA[ct]);
+                                accA[ct] = mfma16(ha[u], bh[ct], accA[ct]);
+                            }
+                        }
+                    }
+                };
+                Vec ha0[U], la0[U], hb0[U], lb0[U], ha1[U], la1[U], hb1[U], lb1[U];
+                if (hasB) {
+                    ld(ha0, la0, AhA, AlA, 0);
+                    ld(hb0, lb0, AhB, AlB, 0);
+                    for (int g = 0; g < gA; g += 2 * U) {
+                        ld(ha1, la1, AhA, AlA, g + U);
+                        ld(hb1, lb1, AhB, AlB, g + U);
+                        mulg(g, ha0, la0, hb0, lb0, true, true);
+                        ld(ha0, la0, AhA, AlA, g + 2 * U);
+                        ld(hb0, lb0, AhB, AlB, g + 2 * U);
+                        mulg(g + U, ha1, la1, hb1, lb1, true, true);
+                    }
+                    for (int g = gA; g < gB; g += 2 * U) {
+                        ld(hb1, lb1, AhB, AlB, g + U);
+                        mulg(g, ha0, la0, hb0, lb0, false, true);
+                        ld(hb0, lb0, AhB, AlB, g + 2 * U);
+                        mulg(g + U, ha1, la1, hb1, lb1, false, true);
+                    }
+                } else {
+                    ld(ha0, la0, AhA, AlA, 0);
+                    for (int g = 0; g < gA; g += 2 * U) {
+                        ld(ha1, la1, AhA, AlA, g + U);
+                        mulg(g, ha0, la0, hb0, lb0, true, false);
+                        ld(ha0, la0, AhA, AlA, g + 2 * U);
+                        mulg(g + U, ha1, la1, hb1, lb1, true, false);
+                    }
+                }
+            }
+            epilogue(ra, accA);
+            if (hasB) epilogue(rbb, accB);
         }
         // ---- reduce the dot partials: rows within lane, lane groups, waves
         __syncthreads();   // red[] reuse
@@ -336,7 +448,7 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
     }
     A.t = t;
     int ldb = (P::KS == 32) ? (M.m_pad + 63) / 64 * 64 + P::LPAD : M.m_pad + P::LPAD;
-    size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (kWaves * NT + NT + 3 * NT);
+    size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (kThreads * G + NT);
     hipError_t e = hipFuncSetAttribute((const void*)k_post<P, NT, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
@@ -362,16 +474,18 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
         if (grad) return small ? launch_t<P64, 32, 4>(M, t, s, M.A64, nullptr) : launch_t<P64, 16, 4>(M, t, s, M.A64, nullptr);
         return small ? launch_t<P64, 32, 1>(M, t, s, M.A64, nullptr) : launch_t<P64, 16, 1>(M, t, s, M.A64, nullptr);
     }
+    // 16-bit and FP32 operands: 64-column tiles while B fits in LDS (m_pad <= 512), else 32
+    const bool wide = M.m_pad <= 512;
     if (prec == LCP_FP32) {
         if (grad) return launch_t<P32, 32, 4>(M, t, s, M.A32, nullptr);
-        return launch_t<P32, 32, 1>(M, t, s, M.A32, nullptr);
+        return wide ? launch_t<P32, 64, 1>(M, t, s, M.A32, nullptr) : launch_t<P32, 32, 1>(M, t, s, M.A32, nullptr);
     }
     if (prec == LCP_MIXED_F16X3) {
         if (grad) return launch_t<PH3, 32, 4>(M, t, s, M.Hhi, M.Hlo);
-        return launch_t<PH3, 32, 1>(M, t, s, M.Hhi, M.Hlo);
+        return wide ? launch_t<PH3, 64, 1>(M, t, s, M.Hhi, M.Hlo) : launch_t<PH3, 32, 1>(M, t, s, M.Hhi, M.Hlo);
     }
     if (grad) return launch_t<PB3, 32, 4>(M, t, s, M.Ahi, M.Alo);
-    return launch_t<PB3, 32, 1>(M, t, s, M.Ahi, M.Alo);
+    return wide ? launch_t<PB3, 64, 1>(M, t, s, M.Ahi, M.Alo) : launch_t<PB3, 32, 1>(M, t, s, M.Ahi, M.Alo);
 }
 
 }  // namespace lcp

@@ -175,7 +175,7 @@ int gp_fit_factor(const lcp_kernel* k, int m, const double* X, const double* y, 
     M->k = *k;
     M->dim = k->dim;
     M->m = m;
-    M->m_pad = (m + 31) / 32 * 32;
+    M->m_pad = (m + 127) / 128 * 128;
     M->nrb = (m + 15) / 16;
     M->kp.kind = k->kind;
     M->kp.dim = k->dim;

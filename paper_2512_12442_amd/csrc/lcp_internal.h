@@ -53,22 +53,81 @@ __device__ __forceinline__ double kernel_r2(const KParams& p, const double* x, c
     return r2;
 }
 
+// e^x for x <= 0 in binary64: Cody-Waite reduction x = n ln2 + r (ln2 split so that n * hi
+// is exact for |n| < 2^21), |r| <= ln2 / 2, then the degree-12 Taylor polynomial of e^r
+// (truncation below 2e-16 relative) and the exact scaling by 2^n; x < -745 gives 0.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    x = fmax(x, -746.0);
+    const double n = rint(x * 1.4426950408889634);
+    double r = fma(n, -0.6931471803691238, x);
+    r = fma(n, -1.9082149292705877e-10, r);
+    double p = 2.08767569878681e-09;
+    p = fma(p, r, 2.505210838544172e-08);
+    p = fma(p, r, 2.755731922398589e-07);
+    p = fma(p, r, 2.7557319223985893e-06);
+    p = fma(p, r, 2.48015873015873e-05);
+    p = fma(p, r, 0.0001984126984126984);
+    p = fma(p, r, 0.001388888888888889);
+    p = fma(p, r, 0.008333333333333333);
+    p = fma(p, r, 0.041666666666666664);
+    p = fma(p, r, 0.16666666666666666);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+// sqrt(x) for x >= 0 in binary64: hardware reciprocal square root refined by two coupled
+// Newton steps and a final residual correction (x = 0 gives 0).
+__device__ __forceinline__ double sqrt_nonneg(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    double e = fma(-h, s, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    e = fma(-h, s, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    const double d = fma(-s, s, x);
+    s = fma(d, h, s);
+    return x > 0.0 ? s : 0.0;
+}
+
 // k(x, z) for the squared-exponential and Matern-5/2 covariances.
 __device__ __forceinline__ double kernel_val(const KParams& p, double r2)
 {
-    if (p.kind == LCP_KERNEL_SE) return p.s2 * exp(-0.5 * r2);
+    if (p.kind == LCP_KERNEL_SE) return p.s2 * exp_nonpos(-0.5 * r2);
     const double s5 = 2.23606797749978969640917366873;
-    double r = sqrt(r2);
-    return p.s2 * fma(5.0 / 3.0, r2, fma(s5, r, 1.0)) * exp(-s5 * r);
+    const double r = sqrt_nonneg(r2);
+    return p.s2 * fma(5.0 / 3.0, r2, fma(s5, r, 1.0)) * exp_nonpos(-s5 * r);
 }
 
 // d k(x, z) / d x_d = f(r) * (x_d - z_d) / ell_d^2; returns f(r).
 __device__ __forceinline__ double kernel_dfac(const KParams& p, double r2)
 {
-    if (p.kind == LCP_KERNEL_SE) return -p.s2 * exp(-0.5 * r2);
+    if (p.kind == LCP_KERNEL_SE) return -p.s2 * exp_nonpos(-0.5 * r2);
     const double s5 = 2.23606797749978969640917366873;
-    double r = sqrt(r2);
-    return -(5.0 / 3.0) * p.s2 * fma(s5, r, 1.0) * exp(-s5 * r);
+    const double r = sqrt_nonneg(r2);
+    return -(5.0 / 3.0) * p.s2 * fma(s5, r, 1.0) * exp_nonpos(-s5 * r);
+}
+
+// Value and derivative factor sharing one exponential.
+__device__ __forceinline__ void kernel_val_dfac(const KParams& p, double r2, double* k, double* f)
+{
+    if (p.kind == LCP_KERNEL_SE) {
+        const double e = p.s2 * exp_nonpos(-0.5 * r2);
+        *k = e;
+        *f = -e;
+        return;
+    }
+    const double s5 = 2.23606797749978969640917366873;
+    const double r = sqrt_nonneg(r2);
+    const double e = p.s2 * exp_nonpos(-s5 * r);
+    const double a = fma(s5, r, 1.0);
+    *k = fma(5.0 / 3.0, r2, a) * e;
+    *f = -(5.0 / 3.0) * a * e;
 }
 
 // ------------------------------------------------------------- posterior GEMM (K1)
