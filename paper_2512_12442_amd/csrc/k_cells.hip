@@ -27,13 +27,14 @@ __device__ __forceinline__ void dir_offset(int D, int dir, int& dx, int& dy, int
 // A work-group owns a BX x BY x BZ brick of vertices (one thread each) and stages the V
 // columns of the brick and its halo (x and y -1..+1, z +1) through LDS in chunks of R
 // rows; each thread accumulates its 13 (3D) or 4 (2D) dot products in binary64.
-// Each V column holds 16 * ceil(m / 16) written rows; within a 16-row block the rows may
-// sit in the MFMA's output order, which no dot product of two columns depends on.
+// V is row-block-major (block rb of column s at (rb * ldv + s) * 16) with 16 * ceil(m / 16)
+// written rows; within a 16-row block the rows may sit in the MFMA's output order, which no
+// dot product of two columns depends on.
 constexpr int CBX = 8, CBY = 8, CBZ = 4;
 constexpr int CHX = CBX + 2, CHY = CBY + 2, CHZ = CBZ + 1;
 
 template <class T, int R>
-__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int mp, int mrows,
+__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv, int mrows,
                                                const int32_t* __restrict__ slot, const T* __restrict__ V,
                                                double* __restrict__ cross)
 {
@@ -96,7 +97,8 @@ __global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int mp, int 
                 V4 v = V4{};
                 if (h < nh) {
                     const int32_t sl = hs[h];
-                    if (sl >= 0 && r0 + r < mrows) v = *(const V4*)(V + (size_t)sl * mp + r0 + r);
+                    const int row = r0 + r;
+                    if (sl >= 0 && row < mrows) v = *(const V4*)(V + ((size_t)(row >> 4) * ldv + sl) * 16 + (row & 15));
                 }
                 buf[k] = v;
             }
@@ -315,10 +317,10 @@ hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t*
     const int64_t nb = ceil_div(g.n[0], CBX) * ceil_div(g.n[1], CBY) * (g.dim == 3 ? ceil_div(g.n[2], CBZ) : 1);
     const unsigned grid = (unsigned)(nb < 65536 ? nb : 65536);
     if (prec == LCP_FP64)
-        hipLaunchKernelGGL((k_cross<double, 16>), dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, slot,
+        hipLaunchKernelGGL((k_cross<double, 16>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, 16 * M.nrb, slot,
                            (const double*)V, cross);
     else
-        hipLaunchKernelGGL((k_cross<float, 32>), dim3(grid), dim3(256), 0, s, M.kp, g, M.m_pad, 16 * M.nrb, slot,
+        hipLaunchKernelGGL((k_cross<float, 32>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, 16 * M.nrb, slot,
                            (const float*)V, cross);
     return hipGetLastError();
 }

@@ -3,9 +3,10 @@
 //   mean_c = sum_j B_jc a_j                                    (binary64),
 //   V = L^-1 B as a lower-triangular GEMM on MFMA with L^-1 precomputed,
 //   dot_c = sum_i V_ic V_i,base(c)  (||v||^2, or v . w_d for gradient columns), binary64 sums,
-// and optionally V itself (for the cell cross-covariances).  V is stored per column with
-// its 16-row blocks in order; inside a block the rows follow the MFMA result registers,
-// a fixed permutation that dot products of V columns do not see.
+// and optionally V itself (for the cell cross-covariances).  V is stored row-block-major:
+// the 16 rows of block rb of column p sit at (rb * n_points + p) * 16, so a wave writes
+// whole 1 KB (FP32) or 2 KB (binary64) runs; inside a block the rows follow the MFMA
+// result registers, a fixed permutation that dot products of V columns do not see.
 // Row blocks of 16 are dealt to the four waves in a balanced (snake) order; every column's
 // result depends only on that column, so a vertex gets bitwise the same numbers whatever
 // tile or launch it is computed in.
@@ -52,15 +53,13 @@ using PH3 = P16<_Float16, true>;
 // x = hi + lo in 16-bit halves, formed in binary32 with hardware conversions: the
 // residual x32 - hi is exact in binary32, so hi + lo carries about 2 x 11 (FP16) or
 // 2 x 8 (BF16) significant bits of x.
-__device__ __forceinline__ void split16(double x, _Float16& hi, _Float16& lo)
+__device__ __forceinline__ void split16(float f, _Float16& hi, _Float16& lo)
 {
-    const float f = (float)x;
     hi = __builtin_amdgcn_cvt_pkrtz(f, 0.0f)[0];
     lo = __builtin_amdgcn_cvt_pkrtz(f - (float)hi, 0.0f)[0];
 }
-__device__ __forceinline__ void split16(double x, __bf16& hi, __bf16& lo)
+__device__ __forceinline__ void split16(float f, __bf16& hi, __bf16& lo)
 {
-    const float f = (float)x;
     hi = (__bf16)f;
     lo = (__bf16)(f - (float)hi);
 }
@@ -130,6 +129,8 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
     // and are combined through LDS once per tile.
     constexpr int NP = NT / G;
     constexpr int RSTEP = kThreads / NP;
+    // value columns of the reduced-precision paths generate B in binary32
+    constexpr bool kGen32 = G == 1 && sizeof(Elem) < 8;
     const int pc = tid % NP, jg = tid / NP;
     const double ie0 = A.kp.inv_ell[0], ie1 = A.kp.inv_ell[1], ie2 = A.kp.inv_ell[2];
 
@@ -160,6 +161,29 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
         double part[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) part[g] = 0.0;
+        if constexpr (kGen32) {
+            // binary32 kernel values (binary64 coordinate differences and mean sums)
+            const float fie0 = (float)ie0, fie1 = (float)ie1, fie2 = (float)ie2;
+            const float fs2 = (float)A.kp.s2;
+            const float fsB = (float)A.sB;
+            for (int j = jg; j < mp; j += RSTEP) {
+                const bool live = valid && j < A.m;
+                const double* xj = A.X + (size_t)j * 4;
+                const float t0 = (float)(px - xj[0]) * fie0, t1 = (float)(py - xj[1]) * fie1,
+                            t2 = (float)(pz - xj[2]) * fie2;
+                const float r2 = fmaf(t2, t2, fmaf(t1, t1, t0 * t0));
+                const float b = live ? kernel_val32(A.kp.kind, fs2, r2) : 0.0f;
+                part[0] = fma((double)b, A.a[j], part[0]);
+                if constexpr (P::KS == 32) {
+                    Elem hi, lo;
+                    split16(P::kScaled ? b * fsB : b, hi, lo);
+                    Bt[(size_t)pc * ldb + j] = hi;
+                    Bt[(size_t)(NT + pc) * ldb + j] = lo;
+                } else {
+                    Bt[(size_t)pc * ldb + j] = (Elem)b;
+                }
+            }
+        } else
         for (int j = jg; j < mp; j += RSTEP) {
             const bool live = valid && j < A.m;
             const double* xj = A.X + (size_t)j * 4;
@@ -186,7 +210,7 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
                     double bs = b[g];
                     if constexpr (P::kScaled) bs *= A.sB;
                     Elem hi, lo;
-                    split16(bs, hi, lo);
+                    split16((float)bs, hi, lo);
                     Bt[(size_t)c * ldb + j] = hi;
                     Bt[(size_t)(NT + c) * ldb + j] = lo;
                 } else {
@@ -228,15 +252,15 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
                     dacc[ct][r] = fma(v, base, dacc[ct][r]);
                 }
                 if (G == 1 && T.V) {
+                    // row-block-major V: element (row 16 rb + i, column p) at (rb * ldv + p) * 16 + i
                     const int64_t p = col0 + 16 * ct + cl;
                     if (p < npts) {
+                        const size_t o = ((size_t)rb * T.n_points + p) * 16 + 4 * gl;
                         if constexpr (sizeof(Elem) == 8) {
-                            double* Vp = (double*)T.V + (size_t)p * mp + 16 * rb + 4 * gl;
-                            *(d4*)Vp = acc[ct];
+                            *(d4*)((double*)T.V + o) = acc[ct];
                         } else {
-                            float* Vp = (float*)T.V + (size_t)p * mp + 16 * rb + 4 * gl;
-                            *(f4*)Vp = f4{(float)acc[ct][0], (float)acc[ct][1], (float)acc[ct][2],
-                                          (float)acc[ct][3]};
+                            *(f4*)((float*)T.V + o) = f4{(float)acc[ct][0], (float)acc[ct][1], (float)acc[ct][2],
+                                                         (float)acc[ct][3]};
                         }
                     }
                 }
@@ -468,24 +492,22 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
     if (t.n_points <= 0) return hipSuccess;
     StageScope sc(s, t.stage);
     const bool grad = t.group == 4;
-    // LDS: binary64 with 32 columns needs 32 * (m_pad + 4) * 8 bytes (<= 160 KB for m_pad <= 608)
-    const bool small = M.m_pad <= 576;
+    // Tile widths keep B at <= 80 KB of LDS (m_pad <= 1024 / 1152), so two work-groups share
+    // a CU and one's B generation (VALU) overlaps the other's MFMA sweep.
     if (prec == LCP_FP64) {
-        if (grad) return small ? launch_t<P64, 32, 4>(M, t, s, M.A64, nullptr) : launch_t<P64, 16, 4>(M, t, s, M.A64, nullptr);
-        return small ? launch_t<P64, 32, 1>(M, t, s, M.A64, nullptr) : launch_t<P64, 16, 1>(M, t, s, M.A64, nullptr);
+        if (grad) return launch_t<P64, 16, 4>(M, t, s, M.A64, nullptr);
+        return launch_t<P64, 16, 1>(M, t, s, M.A64, nullptr);
     }
-    // 16-bit and FP32 operands: 64-column tiles while B fits in LDS (m_pad <= 512), else 32
-    const bool wide = M.m_pad <= 512;
     if (prec == LCP_FP32) {
         if (grad) return launch_t<P32, 32, 4>(M, t, s, M.A32, nullptr);
-        return wide ? launch_t<P32, 64, 1>(M, t, s, M.A32, nullptr) : launch_t<P32, 32, 1>(M, t, s, M.A32, nullptr);
+        return launch_t<P32, 32, 1>(M, t, s, M.A32, nullptr);
     }
     if (prec == LCP_MIXED_F16X3) {
         if (grad) return launch_t<PH3, 32, 4>(M, t, s, M.Hhi, M.Hlo);
-        return wide ? launch_t<PH3, 64, 1>(M, t, s, M.Hhi, M.Hlo) : launch_t<PH3, 32, 1>(M, t, s, M.Hhi, M.Hlo);
+        return launch_t<PH3, 32, 1>(M, t, s, M.Hhi, M.Hlo);
     }
     if (grad) return launch_t<PB3, 32, 4>(M, t, s, M.Ahi, M.Alo);
-    return wide ? launch_t<PB3, 64, 1>(M, t, s, M.Ahi, M.Alo) : launch_t<PB3, 32, 1>(M, t, s, M.Ahi, M.Alo);
+    return launch_t<PB3, 32, 1>(M, t, s, M.Ahi, M.Alo);
 }
 
 }  // namespace lcp

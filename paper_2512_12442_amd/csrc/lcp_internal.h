@@ -104,6 +104,17 @@ __device__ __forceinline__ double kernel_val(const KParams& p, double r2)
     return p.s2 * fma(5.0 / 3.0, r2, fma(s5, r, 1.0)) * exp_nonpos(-s5 * r);
 }
 
+// k in binary32 for the reduced-precision operand paths (binary32 and split 16-bit MFMA
+// products carry 22-24 significant bits, which this evaluation matches): hardware exp2 and
+// square root, r2 already scaled by the lengthscales.
+__device__ __forceinline__ float kernel_val32(int kind, float s2, float r2)
+{
+    constexpr float kLog2e = 1.44269504088896341f;
+    if (kind == LCP_KERNEL_SE) return s2 * __builtin_amdgcn_exp2f((-0.5f * kLog2e) * r2);
+    const float t = 2.23606797749978970f * __builtin_amdgcn_sqrtf(r2);
+    return s2 * fmaf(5.0f / 3.0f, r2, t + 1.0f) * __builtin_amdgcn_exp2f(-kLog2e * t);
+}
+
 // d k(x, z) / d x_d = f(r) * (x_d - z_d) / ell_d^2; returns f(r).
 __device__ __forceinline__ double kernel_dfac(const KParams& p, double r2)
 {
@@ -153,7 +164,8 @@ struct PostTask {
     double* var;
     double* dmean;
     double* dvar;
-    void* V;                  // optional: V column per point (value column only), ldv = m_pad
+    void* V;                  // optional: V per point (value column only), row-block-major with
+                              // n_points columns: (rb * n_points + p) * 16 + row_in_block
     int stage;                // stage-timer stage of this launch
 };
 
@@ -184,6 +196,7 @@ struct CellTask {
     float* lcp;               // whole cell field
 };
 
+// V: row-block-major with nv_cap columns (as written by the posterior kernel).
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s);
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s);

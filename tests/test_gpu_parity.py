@@ -1,7 +1,9 @@
 """Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
 
 Tolerances:
-  * posterior mean (always accumulated in binary64): 1e-9 absolute on fields of O(1);
+  * posterior mean (always accumulated in binary64): binary64 path 1e-9 absolute on fields
+    of O(1); reduced-precision paths evaluate k in binary32, bounded per point by
+    mean_error_bound32;
   * posterior variance, binary64 path: 1e-10 absolute (s2 <= 1): the explicit inverse
     L^-1 adds a cond(L) * eps * |L^-1||k| error, about 1e-13 here;
   * LCP, binary64 path: identical Monte Carlo counts (a sample flips only when a corner
@@ -71,9 +73,29 @@ def test_posterior_fp64_matches_oracle(kind, dim, m):
     assert np.abs(var - var_ref).max() <= 1e-10
 
 
+def mean_error_bound32(W, M, P):
+    """First-order bound on the mean error when each k(x_j, p) is evaluated in binary32.
+
+    A binary32 kernel value carries a relative error of a few units of 2^-24 from the
+    coordinate differences, the square root and exp2, plus one growing with the magnitude u
+    of the exponent argument (its absolute error is u times a few units); summed with the
+    weights |a_j| of the binary64 mean accumulation this gives
+    sum_j (8 + 4 u_j) 2^-24 |k_j a_j|.
+    """
+    d = (P[:, None, :] - W.X[None, :, :]) / np.asarray(W.lengthscale)[:W.dim]
+    r2 = (d * d).sum(-1)
+    if W.kind == workloads.SE:
+        u = 0.5 * r2
+        k = W.signal_var * np.exp(-u)
+    else:
+        u = np.sqrt(5.0 * r2)
+        k = W.signal_var * (1 + u + u * u / 3) * np.exp(-u)
+    return ((8 + 4 * u) * np.abs(k * M.a)).sum(1) * 2.0 ** -24 + 1e-15
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16x3", 2e-4), ("f16x3", 2e-5)])
 def test_posterior_mixed_precision_error(prec, tol):
-    """Mean stays binary64; the variance error is bounded by the precision of V."""
+    """Mean: binary64 sums of binary32 kernel values; variance: bounded by the precision of V."""
     W = workloads.field3d_trig(0, m=500, npts=8)
     M = oracle.fit(W)
     P = np.random.default_rng(5).random((2000, 3))
@@ -82,8 +104,10 @@ def test_posterior_mixed_precision_error(prec, tol):
     mu, var = G.posterior(torch.as_tensor(P, device=DEV), prec)
     mu, var = mu.cpu().numpy(), var.cpu().numpy()
     rel = np.abs(var - var_ref).max() / W.signal_var
-    say(f"posterior {prec}: max|dmu|={np.abs(mu - mu_ref).max():.2e} max|dvar|/s2={rel:.2e}")
-    assert np.abs(mu - mu_ref).max() <= 1e-9
+    bound = mean_error_bound32(W, M, P)
+    say(f"posterior {prec}: max|dmu|={np.abs(mu - mu_ref).max():.2e} (bound median {np.median(bound):.1e}) "
+        f"max|dvar|/s2={rel:.2e}")
+    assert np.all(np.abs(mu - mu_ref) <= bound)
     assert rel <= tol
 
 
