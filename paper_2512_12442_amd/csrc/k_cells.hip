@@ -15,126 +15,132 @@ __device__ __forceinline__ int dir_index(int D, int dx, int dy, int dz)
     return (dx + 1) + 3 * (dy + 1) - 5;
 }
 
-__device__ __forceinline__ void dir_offset(int D, int dir, int& dx, int& dy, int& dz)
+// Neighbour cross-covariances cross[slot][dir] = k(x_p, x_q) - v_p . v_q, q = p + dir.
+//
+// One wave owns a run of 62 consecutive vertices of the grid flattened with one padding
+// vertex at each end of every x-line (index F = (x + 1) + (n0 + 2) * (y + n1 * z)); lanes
+// 1..62 are the outputs, lanes 0 and 63 carry the neighbours just outside the run.  Each
+// lane streams the V columns of its own vertex and of the vertices at (y+1, z) and
+// (y-1..y+1, z+1), four rows at a time; the x +-1 neighbours of those columns are the
+// adjacent lanes, read with wavefront DPP shifts, so every V element is fetched by five
+// lanes (not 14) and no LDS is used.  Dot products accumulate in binary64.
+//
+// V is quad-major: rows 4q..4q+3 of column s sit at (q * ldv + s) * 4 (rows 16 rb .. 16 rb
+// + 15 of each column hold the MFMA result order of that row block, a fixed permutation
+// no dot product of two columns depends on).  Padding vertices and vertices without a
+// slot read as zero columns; their pairs are written as NaN.
+constexpr int kCrossRun = 62;
+
+// Wavefront DPP shifts: lane i receives lane i + 1 (kFromNext) or lane i - 1 (kFromPrev);
+// the lane without a source receives 0.
+constexpr int kFromNext = 0x130;   // wave_shl:1
+constexpr int kFromPrev = 0x138;   // wave_shr:1
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v)
 {
-    int code = dir + (D == 3 ? 14 : 5);
-    dx = code % 3 - 1;
-    dy = (code / 3) % 3 - 1;
-    dz = D == 3 ? code / 9 - 1 : 0;
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-// Neighbour cross-covariances cross[slot][dir] = k(x_p, x_q) - v_p . v_q, q = p + dir.
-// A work-group owns a BX x BY x BZ brick of vertices (one thread each) and stages the V
-// columns of the brick and its halo (x and y -1..+1, z +1) through LDS in chunks of R
-// rows; each thread accumulates its 13 (3D) or 4 (2D) dot products in binary64.
-// V is row-block-major (block rb of column s at (rb * ldv + s) * 16) with 16 * ceil(m / 16)
-// written rows; within a 16-row block the rows may sit in the MFMA's output order, which no
-// dot product of two columns depends on.
-constexpr int CBX = 8, CBY = 8, CBZ = 4;
-constexpr int CHX = CBX + 2, CHY = CBY + 2, CHZ = CBZ + 1;
+__device__ __forceinline__ int32_t slot_at(const GridP& g, const int32_t* slot, int64_t x, int64_t y, int64_t z)
+{
+    if (x < 0 || x >= g.n[0] || y < 0 || y >= g.n[1] || z < 0 || z >= g.n[2]) return -1;
+    const int64_t vid = x + g.n[0] * (y + g.n[1] * z);
+    return slot ? slot[vid] : (int32_t)vid;
+}
 
-template <class T, int R>
-__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv, int mrows,
+template <class T, int D>
+__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv, int nquads,
                                                const int32_t* __restrict__ slot, const T* __restrict__ V,
                                                double* __restrict__ cross)
 {
-    __shared__ T sv[CHX * CHY * CHZ][R + 1];
-    __shared__ int32_t hs[CHX * CHY * CHZ];
-    __shared__ int any;
-    const int D = g.dim;
-    const int ndir = D == 3 ? 13 : 4;
-    const int tid = threadIdx.x;
-    const int64_t nbx = (g.n[0] + CBX - 1) / CBX, nby = (g.n[1] + CBY - 1) / CBY;
-    const int64_t nbz = D == 3 ? (g.n[2] + CBZ - 1) / CBZ : 1;
-    const int hz_n = D == 3 ? CHZ : 1;
-    const int nh = CHX * CHY * hz_n;
-    for (int64_t brick = blockIdx.x; brick < nbx * nby * nbz; brick += gridDim.x) {
-        const int64_t bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
-        const int64_t x0 = bx * CBX, y0 = by * CBY, z0 = bz * (D == 3 ? CBZ : 1);
-        __syncthreads();
-        if (tid == 0) any = 0;
-        __syncthreads();
-        // slots of the halo vertices
-        for (int h = tid; h < nh; h += blockDim.x) {
-            const int hx = h % CHX, hy = (h / CHX) % CHY, hz = h / (CHX * CHY);
-            const int64_t x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 + hz;
-            int32_t sl = -1;
-            if (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z < g.n[2]) {
-                const int64_t vid = x + g.n[0] * (y + g.n[1] * z);
-                sl = slot ? slot[vid] : (int32_t)vid;
-            }
-            hs[h] = sl;
+    constexpr int NDIR = D == 3 ? 13 : 4;
+    constexpr int NPEN = D == 3 ? 5 : 2;     // own column, (y+1, z), (y-1, z+1), (y, z+1), (y+1, z+1)
+    using V4 = T __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t xw = g.n[0] + 2;
+    const int64_t nflat = xw * g.n[1] * (D == 3 ? g.n[2] : 1);
+    const int64_t nwaves = (nflat + kCrossRun - 1) / kCrossRun;
+    for (int64_t w = wave0; w < nwaves; w += (int64_t)gridDim.x * 4) {
+        const int64_t F = w * kCrossRun + lane - 1;
+        int64_t x = -1, y = 0, z = 0;
+        if (F >= 0 && F < nflat) {
+            x = F % xw - 1;
+            const int64_t r = F / xw;
+            y = r % g.n[1];
+            z = r / g.n[1];
         }
-        __syncthreads();
-        // owner of this thread
-        const int ox = tid % CBX, oy = (tid / CBX) % CBY, oz = D == 3 ? tid / (CBX * CBY) : 0;
-        const bool owner_thread = D == 3 || tid < CBX * CBY;
-        const int oh = (ox + 1) + CHX * ((oy + 1) + CHY * oz);
-        const int32_t my = owner_thread ? hs[oh] : -1;
-        if (my >= 0) any = 1;
-        __syncthreads();
-        if (!any) continue;
-        int nbh[13];
-        for (int dir = 0; dir < ndir; ++dir) {
-            int dx, dy, dz;
-            dir_offset(D, dir, dx, dy, dz);
-            nbh[dir] = (ox + 1 + dx) + CHX * ((oy + 1 + dy) + CHY * (oz + dz));
+        int32_t sl[NPEN];
+        sl[0] = slot_at(g, slot, x, y, z);
+        sl[1] = slot_at(g, slot, x, y + 1, z);
+        if constexpr (D == 3) {
+            sl[2] = slot_at(g, slot, x, y - 1, z + 1);
+            sl[3] = slot_at(g, slot, x, y, z + 1);
+            sl[4] = slot_at(g, slot, x, y + 1, z + 1);
         }
-        double acc[13];
+        const bool out = lane >= 1 && lane <= kCrossRun && sl[0] >= 0;
+        if (__ballot(out) == 0) continue;        // wave-uniform
+
+        double acc[NDIR];
 #pragma unroll
-        for (int dir = 0; dir < 13; ++dir) acc[dir] = 0.0;
-        // staging: 16-byte loads, all of a thread's loads issued before any LDS store
-        constexpr int PV = 16 / sizeof(T);                 // elements per 16-byte load
-        constexpr int NV = CHX * CHY * CHZ * R / PV;       // 16-byte pieces per chunk (3D)
-        constexpr int PER = (NV + 255) / 256;
-        using V4 = T __attribute__((ext_vector_type(16 / sizeof(T))));
-        for (int r0 = 0; r0 < mrows; r0 += R) {
-            V4 buf[PER];
+        for (int d = 0; d < NDIR; ++d) acc[d] = 0.0;
+        auto load = [&](V4 (&b)[NPEN], int q) {
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = tid + 256 * k;
-                const int h = e / (R / PV), r = (e % (R / PV)) * PV;
-                V4 v = V4{};
-                if (h < nh) {
-                    const int32_t sl = hs[h];
-                    const int row = r0 + r;
-                    if (sl >= 0 && row < mrows) v = *(const V4*)(V + ((size_t)(row >> 4) * ldv + sl) * 16 + (row & 15));
-                }
-                buf[k] = v;
-            }
-            __syncthreads();
+            for (int k = 0; k < NPEN; ++k)
+                b[k] = sl[k] >= 0 ? *(const V4*)(V + ((size_t)q * ldv + sl[k]) * 4) : V4{0, 0, 0, 0};
+        };
+        auto accumulate = [&](const V4 (&b)[NPEN]) {
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = tid + 256 * k;
-                const int h = e / (R / PV), r = (e % (R / PV)) * PV;
-                if (h < nh)
+            for (int i = 0; i < 4; ++i) {
+                const double a = (double)b[0][i];
+                acc[0] = fma(a, (double)lane_shift<kFromNext>(b[0][i]), acc[0]);              // (+1, 0, 0)
 #pragma unroll
-                    for (int i = 0; i < PV; ++i) sv[h][r + i] = buf[k][i];
-            }
-            __syncthreads();
-            if (my >= 0) {
-#pragma unroll 4
-                for (int r = 0; r < R; ++r) {
-                    const double vp = (double)sv[oh][r];
-#pragma unroll
-                    for (int dir = 0; dir < 13; ++dir)
-                        if (dir < ndir) acc[dir] = fma(vp, (double)sv[nbh[dir]][r], acc[dir]);
+                for (int k = 1; k < NPEN; ++k) {
+                    // pencil k covers directions 1 + 3 (k - 1) + (dx + 1)
+                    const T u = b[k][i];
+                    const int d0 = 1 + 3 * (k - 1);
+                    acc[d0 + 0] = fma(a, (double)lane_shift<kFromPrev>(u), acc[d0 + 0]);
+                    acc[d0 + 1] = fma(a, (double)u, acc[d0 + 1]);
+                    acc[d0 + 2] = fma(a, (double)lane_shift<kFromNext>(u), acc[d0 + 2]);
                 }
             }
+        };
+        V4 b0[NPEN], b1[NPEN];
+        load(b0, 0);
+        int q = 0;
+        for (; q + 2 <= nquads; q += 2) {
+            load(b1, q + 1);
+            accumulate(b0);
+            if (q + 2 < nquads) load(b0, q + 2);
+            accumulate(b1);
         }
-        if (my >= 0) {
-            const int64_t px = x0 + ox, py = y0 + oy, pz = z0 + oz;
-            const double xp[3] = {vertex_coord(g, 0, px), vertex_coord(g, 1, py), D == 3 ? vertex_coord(g, 2, pz) : 0.0};
-            for (int dir = 0; dir < ndir; ++dir) {
+        if (q < nquads) accumulate(b0);
+
+        if (out) {
+            const double xp[3] = {vertex_coord(g, 0, x), vertex_coord(g, 1, y), D == 3 ? vertex_coord(g, 2, z) : 0.0};
+#pragma unroll
+            for (int d = 0; d < NDIR; ++d) {
+                // direction d: offset (dx, dy, dz) with last non-zero component +1
                 int dx, dy, dz;
-                dir_offset(D, dir, dx, dy, dz);
-                double out = __builtin_nan("");
-                if (hs[nbh[dir]] >= 0) {
-                    const double xq[3] = {vertex_coord(g, 0, px + dx), vertex_coord(g, 1, py + dy),
-                                          D == 3 ? vertex_coord(g, 2, pz + dz) : 0.0};
-                    out = kernel_val(kp, kernel_r2(kp, xp, xq)) - acc[dir];
+                if (d == 0) { dx = 1; dy = 0; dz = 0; }
+                else if (d < 4) { dx = d - 2; dy = 1; dz = 0; }
+                else { dx = (d - 4) % 3 - 1; dy = (d - 4) / 3 - 1; dz = 1; }
+                double res = __builtin_nan("");
+                if (slot_at(g, slot, x + dx, y + dy, z + dz) >= 0) {
+                    const double xq[3] = {vertex_coord(g, 0, x + dx), vertex_coord(g, 1, y + dy),
+                                          D == 3 ? vertex_coord(g, 2, z + dz) : 0.0};
+                    res = kernel_val(kp, kernel_r2(kp, xp, xq)) - acc[d];
                 }
-                cross[(size_t)my * ndir + dir] = out;
+                cross[(size_t)sl[0] * NDIR + d] = res;
             }
         }
     }
@@ -314,14 +320,25 @@ hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t*
     (void)nv_dev;
     if (nv_cap <= 0) return hipSuccess;
     StageScope sc(s, ST_CROSS);
-    const int64_t nb = ceil_div(g.n[0], CBX) * ceil_div(g.n[1], CBY) * (g.dim == 3 ? ceil_div(g.n[2], CBZ) : 1);
-    const unsigned grid = (unsigned)(nb < 65536 ? nb : 65536);
-    if (prec == LCP_FP64)
-        hipLaunchKernelGGL((k_cross<double, 16>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, 16 * M.nrb, slot,
-                           (const double*)V, cross);
-    else
-        hipLaunchKernelGGL((k_cross<float, 32>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, 16 * M.nrb, slot,
-                           (const float*)V, cross);
+    const int64_t nflat = (g.n[0] + 2) * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    const int64_t nwaves = ceil_div(nflat, kCrossRun);
+    const unsigned grid = grid_for(nwaves, 4);
+    const int nquads = 4 * M.nrb;
+    if (prec == LCP_FP64) {
+        if (g.dim == 3)
+            hipLaunchKernelGGL((k_cross<double, 3>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
+                               (const double*)V, cross);
+        else
+            hipLaunchKernelGGL((k_cross<double, 2>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
+                               (const double*)V, cross);
+    } else {
+        if (g.dim == 3)
+            hipLaunchKernelGGL((k_cross<float, 3>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
+                               (const float*)V, cross);
+        else
+            hipLaunchKernelGGL((k_cross<float, 2>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
+                               (const float*)V, cross);
+    }
     return hipGetLastError();
 }
 

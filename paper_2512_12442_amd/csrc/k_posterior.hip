@@ -3,10 +3,12 @@
 //   mean_c = sum_j B_jc a_j                                    (binary64),
 //   V = L^-1 B as a lower-triangular GEMM on MFMA with L^-1 precomputed,
 //   dot_c = sum_i V_ic V_i,base(c)  (||v||^2, or v . w_d for gradient columns), binary64 sums,
-// and optionally V itself (for the cell cross-covariances).  V is stored row-block-major:
-// the 16 rows of block rb of column p sit at (rb * n_points + p) * 16, so a wave writes
-// whole 1 KB (FP32) or 2 KB (binary64) runs; inside a block the rows follow the MFMA
-// result registers, a fixed permutation that dot products of V columns do not see.
+// and optionally V itself (for the cell cross-covariances).  V is stored quad-major: rows
+// 4q .. 4q + 3 of column p sit at (q * n_points + p) * 4, so the 16 lanes of one MFMA
+// result quad write 256 B (FP32) or 512 B (binary64) runs, and a consumer reading four
+// rows of consecutive columns reads contiguous memory; inside a 16-row block the rows
+// follow the MFMA result registers, a fixed permutation that dot products of V columns
+// do not see.
 // Row blocks of 16 are dealt to the four waves in a balanced (snake) order; every column's
 // result depends only on that column, so a vertex gets bitwise the same numbers whatever
 // tile or launch it is computed in.
@@ -252,10 +254,10 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
                     dacc[ct][r] = fma(v, base, dacc[ct][r]);
                 }
                 if (G == 1 && T.V) {
-                    // row-block-major V: element (row 16 rb + i, column p) at (rb * ldv + p) * 16 + i
+                    // quad-major V: rows 4 q .. 4 q + 3 of column p at (q * n_points + p) * 4
                     const int64_t p = col0 + 16 * ct + cl;
                     if (p < npts) {
-                        const size_t o = ((size_t)rb * T.n_points + p) * 16 + 4 * gl;
+                        const size_t o = ((size_t)(4 * rb + gl) * T.n_points + p) * 4;
                         if constexpr (sizeof(Elem) == 8) {
                             *(d4*)((double*)T.V + o) = acc[ct];
                         } else {

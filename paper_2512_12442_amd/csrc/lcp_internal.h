@@ -164,8 +164,8 @@ struct PostTask {
     double* var;
     double* dmean;
     double* dvar;
-    void* V;                  // optional: V per point (value column only), row-block-major with
-                              // n_points columns: (rb * n_points + p) * 16 + row_in_block
+    void* V;                  // optional: V per point (value column only), quad-major with
+                              // n_points columns: rows 4q..4q+3 of column p at (q * n_points + p) * 4
     int stage;                // stage-timer stage of this launch
 };
 
@@ -196,7 +196,7 @@ struct CellTask {
     float* lcp;               // whole cell field
 };
 
-// V: row-block-major with nv_cap columns (as written by the posterior kernel).
+// V: quad-major with nv_cap columns (as written by the posterior kernel).
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s);
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s);
