@@ -21,15 +21,18 @@ __device__ __forceinline__ int dir_index(int D, int dx, int dy, int dz)
 // vertex at each end of every x-line (index F = (x + 1) + (n0 + 2) * (y + n1 * z)); lanes
 // 1..62 are the outputs, lanes 0 and 63 carry the neighbours just outside the run.  Each
 // lane streams the V columns of its own vertex and of the vertices at (y+1, z) and
-// (y-1..y+1, z+1), four rows at a time; the x +-1 neighbours of those columns are the
-// adjacent lanes, read with wavefront DPP shifts, so every V element is fetched by five
-// lanes (not 14) and no LDS is used.  Dot products accumulate in binary64.
+// (y-1..y+1, z+1), four rows at a time; the x +-1 neighbours are the adjacent lanes,
+// reached with wavefront DPP shifts of the own value, so every V element is fetched by
+// five lanes and no LDS is used.  Dot products accumulate in binary64.
 //
 // V is quad-major: rows 4q..4q+3 of column s sit at (q * ldv + s) * 4 (rows 16 rb .. 16 rb
 // + 15 of each column hold the MFMA result order of that row block, a fixed permutation
 // no dot product of two columns depends on).  Padding vertices and vertices without a
 // slot read as zero columns; their pairs are written as NaN.
 constexpr int kCrossRun = 62;
+// Buffer descriptor word 3 for raw (untyped, unswizzled) buffer access on gfx9-family GPUs.
+constexpr int kBufferFlags = 0x00020000;
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
 // Wavefront DPP shifts: lane i receives lane i + 1 (kFromNext) or lane i - 1 (kFromPrev);
 // the lane without a source receives 0.
@@ -93,37 +96,80 @@ __global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv,
         double acc[NDIR];
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) acc[d] = 0.0;
-        auto load = [&](V4 (&b)[NPEN], int q) {
+        // V through buffer loads: the descriptor covers one quad plane (ldv columns); a
+        // missing column gets an offset past its end, which the hardware reads as zeros.
+        const unsigned plane = (unsigned)(ldv * 4 * sizeof(T));
+        unsigned voff[NPEN];
 #pragma unroll
-            for (int k = 0; k < NPEN; ++k)
-                b[k] = sl[k] >= 0 ? *(const V4*)(V + ((size_t)q * ldv + sl[k]) * 4) : V4{0, 0, 0, 0};
+        for (int k = 0; k < NPEN; ++k) voff[k] = sl[k] >= 0 ? (unsigned)sl[k] * (unsigned)(4 * sizeof(T)) : plane;
+        auto load = [&](V4 (&b)[NPEN], int q) {
+            __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)(V + (size_t)q * ldv * 4), 0,
+                                                                          (int)plane, kBufferFlags);
+#pragma unroll
+            for (int k = 0; k < NPEN; ++k) {
+                if constexpr (sizeof(T) == 4) {
+                    b[k] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff[k], 0, 0));
+                } else {
+                    const u4 lo = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[k], 0, 0);
+                    const u4 hi = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[k] + 16, 0, 0);
+                    b[k] = V4{__builtin_bit_cast(double, ((unsigned long long)lo[1] << 32) | lo[0]),
+                              __builtin_bit_cast(double, ((unsigned long long)lo[3] << 32) | lo[2]),
+                              __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | hi[0]),
+                              __builtin_bit_cast(double, ((unsigned long long)hi[3] << 32) | hi[2])};
+                }
+            }
         };
+        // Binary32 operands: four-row products summed in binary32 over one 16-row block, then
+        // added to the binary64 accumulators (the partial sums carry ~2^-24 relative error,
+        // well below that of the binary32 V itself).  Binary64 operands: binary64 throughout.
+        using PT = T;
+        PT part[NDIR];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) part[d] = 0;
+        // Row i of a quad: the x-neighbour products use the own value shifted by one lane
+        // (a(x - 1), a(x + 1)), so lane y accumulates a(y + 1) u(y) for the dx = -1 pair of
+        // vertex y + 1 and a(y - 1) u(y) for the dx = +1 pair of vertex y - 1; those sums
+        // move back to their owners with one lane shift after the row loop.
         auto accumulate = [&](const V4 (&b)[NPEN]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const double a = (double)b[0][i];
-                acc[0] = fma(a, (double)lane_shift<kFromNext>(b[0][i]), acc[0]);              // (+1, 0, 0)
+                const T a = b[0][i];
+                const T an = lane_shift<kFromNext>(a), ap = lane_shift<kFromPrev>(a);
+                part[0] = fma(a, an, part[0]);                                   // (+1, 0, 0)
 #pragma unroll
                 for (int k = 1; k < NPEN; ++k) {
                     // pencil k covers directions 1 + 3 (k - 1) + (dx + 1)
                     const T u = b[k][i];
                     const int d0 = 1 + 3 * (k - 1);
-                    acc[d0 + 0] = fma(a, (double)lane_shift<kFromPrev>(u), acc[d0 + 0]);
-                    acc[d0 + 1] = fma(a, (double)u, acc[d0 + 1]);
-                    acc[d0 + 2] = fma(a, (double)lane_shift<kFromNext>(u), acc[d0 + 2]);
+                    part[d0 + 0] = fma(an, u, part[d0 + 0]);
+                    part[d0 + 1] = fma(a, u, part[d0 + 1]);
+                    part[d0 + 2] = fma(ap, u, part[d0 + 2]);
                 }
             }
         };
+        auto flush = [&]() {
+#pragma unroll
+            for (int d = 0; d < NDIR; ++d) {
+                acc[d] += (double)part[d];
+                part[d] = 0;
+            }
+        };
+        // nquads is a multiple of 4: pairs of quads, flushed after every second pair
         V4 b0[NPEN], b1[NPEN];
         load(b0, 0);
-        int q = 0;
-        for (; q + 2 <= nquads; q += 2) {
+        for (int q = 0; q < nquads; q += 2) {
             load(b1, q + 1);
             accumulate(b0);
-            if (q + 2 < nquads) load(b0, q + 2);
+            load(b0, q + 2 < nquads ? q + 2 : q + 1);   // the last prefetch re-reads a quad
             accumulate(b1);
+            if (sizeof(T) == 8 || (q & 2)) flush();
         }
-        if (q < nquads) accumulate(b0);
+#pragma unroll
+        for (int k = 1; k < NPEN; ++k) {
+            const int d0 = 1 + 3 * (k - 1);
+            acc[d0 + 0] = lane_shift<kFromPrev>(acc[d0 + 0]);
+            acc[d0 + 2] = lane_shift<kFromNext>(acc[d0 + 2]);
+        }
 
         if (out) {
             const double xp[3] = {vertex_coord(g, 0, x), vertex_coord(g, 1, y), D == 3 ? vertex_coord(g, 2, z) : 0.0};
@@ -324,6 +370,8 @@ hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t*
     const int64_t nwaves = ceil_div(nflat, kCrossRun);
     const unsigned grid = grid_for(nwaves, 4);
     const int nquads = 4 * M.nrb;
+    // one quad plane of V must stay addressable by a 32-bit buffer offset
+    if ((double)nv_cap * 4 * (prec == LCP_FP64 ? 8 : 4) >= 2147483648.0) return hipErrorInvalidValue;
     if (prec == LCP_FP64) {
         if (g.dim == 3)
             hipLaunchKernelGGL((k_cross<double, 3>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
