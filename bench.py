@@ -2,7 +2,8 @@
 """Headline benchmark: LCP grid points per second at 128^3 with m = 500 observations.
 
 One step = one lcp_adaptive call in mixed precision (FP16x3 split MFMA for the posterior
-GEMM; binary64 factor, mean, region bound and cell factor; FP32 Monte Carlo) over the
+GEMM on binary32 kernel values; binary64 factor, mean and norm sums, region bound and cell
+factor; FP32 Monte Carlo) over the
 whole 128^3 grid: octree query of Alg. 1 plus reconstruction and Monte Carlo LCP of the
 emitted nodes.  The same GPU also runs the dense binary64 baseline (every cell,
 Sec. 4) for the speed ratio and as the accuracy reference (RMSE of the LCP field).
@@ -39,6 +40,44 @@ def leaf_cell_mask(keys, W, edge):
     return mask
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_post_f16x3_128cube_m500_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_12442_amd", "csrc", "k_posterior.hip")
+
+
+def source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch(prec, npts):
+    """HBM bytes per posterior launch from the committed rocprofv3 counter summary: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch) divided by what the same counters read per KiB moved by a
+    plain device copy.  None when the summary is missing, is for another workload, or the
+    kernel source changed since the counters were taken."""
+    if prec != "f16x3" or npts != 128 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("TRAFFIC_JSON "):
+                rec = json.loads(line[len("TRAFFIC_JSON "):])
+    if rec is None or rec.get("source_sha256_16") != source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size: the reference for the traffic counters."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: {reps} copies of {nbytes} bytes", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,15 +86,22 @@ def main():
     ap.add_argument("--prec", default="f16x3", choices=["fp64", "fp32", "f16x3", "bf16x3"])
     ap.add_argument("--npts", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-layers", type=int, default=24, help="cell layers of the bounded oracle sample")
+    ap.add_argument("--cpu-layers", type=int, default=0,
+                    help="cell layers (z) of the oracle sample; 0 = all (the whole grid, ~10 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense FP64 baseline (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for rocprofv3 traffic counters)")
+    ap.add_argument("--print-source-hash", action="store_true", help="print the posterior kernel source hash")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
                                    "DESIGN.md but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.print_source_hash:
+        print(source_hash())
+        return
     import numpy as np
     import torch
 
@@ -63,6 +109,8 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration()
     W = workloads.field3d_trig(args.seed, m=500, npts=args.npts)
     grid = lcp.grid_of(W)
     adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4)
@@ -104,10 +152,9 @@ def main():
             G.lcp_adaptive(grid, W.theta, adapt, zb, args.prec, **kw)
     nw = max(args.warmup, 1)
     stage_ms = {k: v / nw for k, v in st_all.ms.items()}
-    dominant = max(("posterior", "bound", "cross", "cells"), key=lambda k: stage_ms[k])
-    # timed steps: wall clock for the headline, events around the dominant stage only
+    # timed steps: wall clock for the headline, events around the posterior kernel only
     torch.cuda.synchronize()
-    with lcp.StageTimer([dominant]) as st_dom:
+    with lcp.StageTimer(["posterior"]) as st_dom:
         t0 = time.perf_counter()
         for _ in range(args.steps):
             G.lcp_adaptive(grid, W.theta, adapt, zb, args.prec, **kw)
@@ -137,37 +184,38 @@ def main():
                "flipped_samples": int(flips), "cells_nonzero_dense": int((ref > 0).sum().item())}
 
     # ------------------------------------------------------------------- roofline
+    # Dominant kernel: the posterior GEMM k_post of the reconstruction (one launch per step),
+    # timed with HIP events on the library's stream inside the timed steps.
     m = W.m
-    dur_ms = st_dom.ms[dominant] / max(st_dom.launches[dominant], 1)
-    per_step_launches = st_dom.launches[dominant] / args.steps
-    if dominant == "posterior":
-        flops = leaf_vertices * m * (m + 1)
-        peak = PEAK["fp16_mfma"] if args.prec in ("f16x3", "bf16x3") else (
-            PEAK["fp32_mfma"] if args.prec == "fp32" else PEAK["fp64_mfma"])
-        roof = {"bound": "mfma", "kernel": "k_post (posterior GEMM, leaf vertices)"}
-    elif dominant == "cells":
-        flops = leaf_cells * W.n_samples * 2 * 36
-        peak = PEAK["alu"]
-        roof = {"bound": "alu", "kernel": "k_cells (cell factor + Monte Carlo)"}
-    elif dominant == "bound":
-        flops = None
-        peak = PEAK["fp64_mfma"]
-        roof = {"bound": "mfma", "kernel": "k_post binary64 bound probes"}
-    else:
-        flops = leaf_vertices * 13 * 2 * m
-        peak = PEAK["alu"]
-        roof = {"bound": "alu", "kernel": "k_cross"}
-    achieved = (flops / per_step_launches) / (dur_ms * 1e-3) / 1e12 if flops else None
-    roof.update({"achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
-                 "frac": (achieved * 1e12 / peak) if achieved else None, "traffic": None,
-                 "avg_launch_ms": dur_ms, "launches_per_step": per_step_launches})
+    dur_ms = st_dom.ms["posterior"] / max(st_dom.launches["posterior"], 1)
+    per_step_launches = st_dom.launches["posterior"] / args.steps
+    flops = leaf_vertices * m * (m + 1) / per_step_launches
+    peak = {"f16x3": PEAK["fp16_mfma"], "bf16x3": PEAK["fp16_mfma"], "fp32": PEAK["fp32_mfma"],
+            "fp64": PEAK["fp64_mfma"]}[args.prec]
+    achieved = flops / (dur_ms * 1e-3)
+    roof = {"bound": "mfma", "kernel": f"k_post ({args.prec} posterior GEMM over leaf vertices)",
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic_per_launch(args.prec, args.npts),
+            "avg_launch_ms": dur_ms, "launches_per_step": per_step_launches,
+            "algorithmic_flop_per_launch": flops,
+            "note": "algorithmic flop = leaf vertices x m(m+1); the 16-bit split runs 3 MFMA passes per flop"}
+    # the other reconstruction kernels, from the per-stage warm-up timing (one launch each)
+    other = {
+        "k_cross": {"bound": "alu", "achieved": leaf_vertices * 26 * m / (stage_ms["cross"] * 1e-3) / 1e12,
+                    "peak": PEAK["alu"] / 1e12, "unit": "TFLOP/s", "ms": stage_ms["cross"],
+                    "hbm_gbs": leaf_vertices * (4 * 16 * ((m + 15) // 16) + 104) / (stage_ms["cross"] * 1e-3) / 1e9},
+        "k_cells": {"bound": "alu", "achieved": leaf_cells * W.n_samples * 80 / (stage_ms["cells"] * 1e-3) / 1e12,
+                    "peak": PEAK["alu"] / 1e12, "unit": "TFLOP/s", "ms": stage_ms["cells"]},
+    }
+    for v in other.values():
+        v["frac"] = v["achieved"] / v["peak"]
 
     # --------------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         M = oracle.fit(W)
-        L = args.cpu_layers
+        L = args.cpu_layers if 0 < args.cpu_layers < W.npts[2] - 1 else int(W.npts[2] - 1)
         c0 = (W.npts[2] - 1 - L) // 2
         t0 = time.perf_counter()
         oracle.lcp_dense(M, W, c0, c0 + L)
@@ -195,7 +243,7 @@ def main():
         "n_leaves": nl, "leaf_cells": leaf_cells, "leaf_vertices": leaf_vertices,
         "leaf_cell_frac": leaf_cells / W.n_cells,
         "stage_ms": stage_ms, "fit_ms": fit_ms,
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "roofline_other": other, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

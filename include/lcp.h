@@ -49,9 +49,10 @@ typedef enum {
 
 typedef enum {
     LCP_FP64 = 0,            /* every step in binary64 */
-    LCP_FP32 = 1,            /* V = L^-1 K*^T on FP32 MFMA; mean, norms, cell factor in FP64; MC in FP32 */
-    LCP_MIXED_BF16X3 = 2,    /* V on BF16 MFMA with a 3-term split product (hi*hi + hi*lo + lo*hi), FP32
-                                accumulation; mean, norms, cell factor in FP64; MC in FP32 */
+    LCP_FP32 = 1,            /* K* in binary32; V = L^-1 K*^T on FP32 MFMA; mean sums, norms, cell factor
+                                in FP64; MC in FP32.  Region bound of lcp_adaptive always FP64 */
+    LCP_MIXED_BF16X3 = 2,    /* as LCP_FP32 with V on BF16 MFMA as a 3-term split product
+                                (hi*hi + hi*lo + lo*hi) with FP32 accumulation */
     LCP_MIXED_F16X3 = 3      /* as LCP_MIXED_BF16X3 with FP16 halves (22-bit split) on power-of-two scaled
                                 operands; about FP32 accuracy at 16-bit MFMA rate */
 } lcp_precision;

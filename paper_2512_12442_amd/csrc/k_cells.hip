@@ -119,42 +119,30 @@ __global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv,
                 }
             }
         };
-        // Binary32 operands: four-row products summed in binary32 over one 16-row block, then
-        // added to the binary64 accumulators (the partial sums carry ~2^-24 relative error,
-        // well below that of the binary32 V itself).  Binary64 operands: binary64 throughout.
-        using PT = T;
-        PT part[NDIR];
-#pragma unroll
-        for (int d = 0; d < NDIR; ++d) part[d] = 0;
         // Row i of a quad: the x-neighbour products use the own value shifted by one lane
         // (a(x - 1), a(x + 1)), so lane y accumulates a(y + 1) u(y) for the dx = -1 pair of
         // vertex y + 1 and a(y - 1) u(y) for the dx = +1 pair of vertex y - 1; those sums
-        // move back to their owners with one lane shift after the row loop.
+        // move back to their owners with one lane shift after the row loop.  Products of
+        // binary32 operands are exact in binary64, and every sum is binary64.
         auto accumulate = [&](const V4 (&b)[NPEN]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const T a = b[0][i];
-                const T an = lane_shift<kFromNext>(a), ap = lane_shift<kFromPrev>(a);
-                part[0] = fma(a, an, part[0]);                                   // (+1, 0, 0)
+                const T a32 = b[0][i];
+                const double a = (double)a32;
+                const double an = (double)lane_shift<kFromNext>(a32), ap = (double)lane_shift<kFromPrev>(a32);
+                acc[0] = fma(a, an, acc[0]);                                     // (+1, 0, 0)
 #pragma unroll
                 for (int k = 1; k < NPEN; ++k) {
                     // pencil k covers directions 1 + 3 (k - 1) + (dx + 1)
-                    const T u = b[k][i];
+                    const double u = (double)b[k][i];
                     const int d0 = 1 + 3 * (k - 1);
-                    part[d0 + 0] = fma(an, u, part[d0 + 0]);
-                    part[d0 + 1] = fma(a, u, part[d0 + 1]);
-                    part[d0 + 2] = fma(ap, u, part[d0 + 2]);
+                    acc[d0 + 0] = fma(an, u, acc[d0 + 0]);
+                    acc[d0 + 1] = fma(a, u, acc[d0 + 1]);
+                    acc[d0 + 2] = fma(ap, u, acc[d0 + 2]);
                 }
             }
         };
-        auto flush = [&]() {
-#pragma unroll
-            for (int d = 0; d < NDIR; ++d) {
-                acc[d] += (double)part[d];
-                part[d] = 0;
-            }
-        };
-        // nquads is a multiple of 4: pairs of quads, flushed after every second pair
+        // nquads is a multiple of 4: pairs of quads, the next one prefetched
         V4 b0[NPEN], b1[NPEN];
         load(b0, 0);
         for (int q = 0; q < nquads; q += 2) {
@@ -162,7 +150,6 @@ __global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv,
             accumulate(b0);
             load(b0, q + 2 < nquads ? q + 2 : q + 1);   // the last prefetch re-reads a quad
             accumulate(b1);
-            if (sizeof(T) == 8 || (q & 2)) flush();
         }
 #pragma unroll
         for (int k = 1; k < NPEN; ++k) {

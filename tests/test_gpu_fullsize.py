@@ -1,0 +1,97 @@
+"""Parity at the benchmarked size: the 128^3 trig field with m = 500 observations, run in
+the launch configuration the benchmark times (lcp_adaptive in FP16x3 with the binary64
+bound, lcp_dense in binary64).  The oracle checks the leaf set of Alg. 1 in full and the
+posterior and cell LCP on sampled vertices and cells it computes one by one."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_2512_12442_amd as lcp
+from parity_util import DEV, counts, gpu_model, mean_error_bound32, near_tie_keys, say, zbank
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLED = 1500
+
+
+@pytest.fixture(scope="module")
+def full():
+    W = workloads.field3d_trig(0, m=500, npts=128)
+    return W, oracle.fit(W), gpu_model(W)
+
+
+def _vertex_coords(W, idx):
+    h = (W.hi - W.lo) / (W.npts - 1)
+    return W.lo[None, :] + idx * h[None, :]      # lo + i h, as the grid convention states
+
+
+def _oracle_cells(M, W, cells):
+    out = np.empty(len(cells))
+    for i, c in enumerate(cells):
+        mu, S = oracle.cell_moments(M, W, c)
+        out[i] = oracle.cell_lcp(mu, S, W.theta, W.zbank)
+    return out
+
+
+def test_full_size_posterior_on_sampled_vertices(full):
+    W, M, G = full
+    idx = np.random.default_rng(11).integers(0, W.npts, size=(4000, 3))
+    P = _vertex_coords(W, idx)
+    mu_ref, var_ref = oracle.posterior(M, P)
+    mu, var = (t.cpu().numpy() for t in G.posterior(torch.as_tensor(P, device=DEV), "fp64"))
+    say(f"128^3 fp64 vertices: max|dmu|={np.abs(mu - mu_ref).max():.2e} max|dvar|={np.abs(var - var_ref).max():.2e}")
+    assert np.abs(mu - mu_ref).max() <= 1e-9
+    assert np.abs(var - var_ref).max() <= 1e-10
+    mu, var = (t.cpu().numpy() for t in G.posterior(torch.as_tensor(P, device=DEV), "f16x3"))
+    rel = np.abs(var - var_ref).max() / W.signal_var
+    say(f"128^3 f16x3 vertices: max|dmu|={np.abs(mu - mu_ref).max():.2e} max|dvar|/s2={rel:.2e}")
+    assert np.all(np.abs(mu - mu_ref) <= mean_error_bound32(W, M, P))
+    assert rel <= 2e-5
+
+
+def test_full_size_dense_fp64_on_sampled_cells(full):
+    W, M, G = full
+    out, _ = G.lcp_dense(lcp.grid_of(W), W.theta, zbank(W), "fp64")
+    got = out.cpu().numpy().reshape(W.cell_shape)
+    rng = np.random.default_rng(12)
+    cells = rng.integers(0, W.npts - 1, size=(N_SAMPLED, 3))
+    ref = _oracle_cells(M, W, cells)
+    g = got[cells[:, 2], cells[:, 1], cells[:, 0]]
+    mism = np.count_nonzero(counts(g, W.n_samples) != counts(ref, W.n_samples))
+    say(f"128^3 dense fp64: {N_SAMPLED} sampled cells, nonzero {np.count_nonzero(ref)}, mismatched counts {mism}")
+    assert mism == 0
+
+
+def test_full_size_adaptive_f16x3_leaf_set_and_sampled_cells(full):
+    W, M, G = full
+    adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4)
+    out, leaves, nl, lf, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, adapt, zbank(W), "f16x3")
+    n = int(nl.item())
+    got_keys = leaves[:n].cpu().numpy().astype(np.uint64)
+    leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4)
+    ties = near_tie_keys(recs, W.alpha)
+    sym = set(map(int, got_keys)) ^ set(map(int, leaves_ref))
+    say(f"128^3 adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)}")
+    assert np.all(np.diff(got_keys.astype(np.int64)) > 0)
+    for k in sym:
+        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
+
+    # every cell outside the GPU's leaves is zero; sampled leaf cells match the oracle
+    inleaf = oracle.level_field(W, got_keys) != 255
+    field = out.cpu().numpy().reshape(W.cell_shape)
+    assert np.all(field[~inleaf] == 0)
+    if not sym:
+        lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref]))
+        assert np.array_equal(lf.cpu().numpy().reshape(W.cell_shape), lev_ref)
+    cand = np.argwhere(inleaf)                       # (z, y, x)
+    pick = cand[np.random.default_rng(13).choice(len(cand), size=N_SAMPLED, replace=False)]
+    cells = pick[:, ::-1]
+    ref = _oracle_cells(M, W, cells)
+    g = field[pick[:, 0], pick[:, 1], pick[:, 2]]
+    dc = np.abs(counts(g, W.n_samples) - counts(ref, W.n_samples))
+    rmse = float(np.sqrt(np.mean((g - ref) ** 2)))
+    say(f"128^3 adaptive f16x3: {N_SAMPLED} sampled leaf cells, rmse={rmse:.2e}, max flipped samples={dc.max()}")
+    assert rmse <= 1e-4
+    assert dc.max() <= 8

@@ -19,27 +19,9 @@ import torch
 import oracle
 import workloads
 import paper_2512_12442_amd as lcp
+from parity_util import DEV, counts, gpu_model, mean_error_bound32, near_tie_keys, say, zbank
 
 pytestmark = pytest.mark.gpu
-
-DEV = "cuda:0"
-
-
-def say(*a):
-    print(*a, flush=True)
-
-
-def gpu_model(W):
-    return lcp.GPModel.from_workload(W, DEV)
-
-
-def zbank(W):
-    return torch.as_tensor(W.zbank, device=DEV)
-
-
-def counts(x, ns):
-    return np.rint(np.asarray(x, np.float64) * ns).astype(np.int64)
-
 
 CASES = {
     "trig17": lambda: workloads.field3d_trig(0, m=120, npts=17),
@@ -71,26 +53,6 @@ def test_posterior_fp64_matches_oracle(kind, dim, m):
     say(f"  max|dmu|={np.abs(mu - mu_ref).max():.2e} max|dvar|={np.abs(var - var_ref).max():.2e}")
     assert np.abs(mu - mu_ref).max() <= 1e-9 * max(1.0, np.abs(mu_ref).max())
     assert np.abs(var - var_ref).max() <= 1e-10
-
-
-def mean_error_bound32(W, M, P):
-    """First-order bound on the mean error when each k(x_j, p) is evaluated in binary32.
-
-    A binary32 kernel value carries a relative error of a few units of 2^-24 from the
-    coordinate differences, the square root and exp2, plus one growing with the magnitude u
-    of the exponent argument (its absolute error is u times a few units); summed with the
-    weights |a_j| of the binary64 mean accumulation this gives
-    sum_j (8 + 4 u_j) 2^-24 |k_j a_j|.
-    """
-    d = (P[:, None, :] - W.X[None, :, :]) / np.asarray(W.lengthscale)[:W.dim]
-    r2 = (d * d).sum(-1)
-    if W.kind == workloads.SE:
-        u = 0.5 * r2
-        k = W.signal_var * np.exp(-u)
-    else:
-        u = np.sqrt(5.0 * r2)
-        k = W.signal_var * (1 + u + u * u / 3) * np.exp(-u)
-    return ((8 + 4 * u) * np.abs(k * M.a)).sum(1) * 2.0 ** -24 + 1e-15
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16x3", 2e-4), ("f16x3", 2e-5)])
@@ -157,19 +119,6 @@ def test_dense_is_deterministic():
 
 # -------------------------------------------------------------- adaptive LCP
 
-def _near_tie_keys(recs, alpha):
-    """Nodes whose decision depends on rounding: UB within 1e-8 relative of alpha, p1/p2
-    within 1e-12 of alpha, or two lattice minima within 1e-9 of each other."""
-    bad = set()
-    for r in recs:
-        if r["path"] in (1, 2) or (r["path"] != 0 and not np.isnan(r["ub"])):
-            if abs(r["ub"] - alpha) <= 1e-8 * alpha or abs(r["lattice_gap"]) <= 1e-9 * max(1, abs(r["gmin"])):
-                bad.add(int(r["key"]))
-        if r["n_obs"] > 0 and (abs(r["p1"] - alpha) <= 1e-12 or abs(r["p2"] - alpha) <= 1e-12):
-            bad.add(int(r["key"]))
-    return bad
-
-
 ADAPT_CASES = {
     "trig33": lambda: workloads.field3d_trig(0, m=200, npts=33),
     "aniso33": lambda: workloads.field3d_aniso(0, m=200, npts=33),
@@ -201,7 +150,7 @@ def test_adaptive_fp64_matches_oracle(case):
     out, leaves, nl, lf, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, lcp.adapt_of(W), zbank(W), "fp64")
     n = int(nl.item())
     got = leaves[:n].cpu().numpy().astype(np.uint64)
-    ties = _near_tie_keys(recs, W.alpha)
+    ties = near_tie_keys(recs, W.alpha)
     sym = set(map(int, got)) ^ set(map(int, leaves_ref))
     say(f"  leaves gpu={n} oracle={len(leaves_ref)} skipped={len(skipped_ref)} differ={len(sym)} near-ties={len(ties)}")
     assert np.all(np.diff(got.astype(np.int64)) > 0)          # canonical ascending order
