@@ -454,6 +454,247 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
     }
 }
 
+// ------------------------------------------------------------------------------------
+// k-outer form for value columns (G = 1) with 16-bit split operands.  A work-group of
+// eight waves owns NT columns and keeps every 16-row block of V for them in registers:
+// wave w owns row blocks rb = w + 8 r, r < RBW.  B is generated just in time in chunks of
+// 32 rows (one 16x16x32 k-step) into a double-buffered LDS slice, so chunk c + 1 is
+// generated while the MFMAs of chunk c run; each B fragment read from LDS feeds all of the
+// wave's row blocks, and each L^-1 fragment is read once per tile.
+//
+// Row block rb takes chunks 0 .. rb / 2.  The chunk loop of a wave therefore runs in
+// phases: in phase K its row blocks r >= K are the live ones, and row block K is final
+// when the phase ends.  Each phase's loop body is branch-free (a single basic block), so
+// the compiler can interleave the generation of the next chunk with the current MFMAs.
+// Per column the k-steps accumulate in the same increasing order as in k_post, so V is
+// bitwise the same; only the binary64 norm partials are summed in another fixed order.
+// Calls f(integral_constant<int, K>) for K = B .. E - 1 in order.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int kThreadsKO = 512;
+constexpr int kWavesKO = 8;
+constexpr int kChunk = 32;
+
+template <class P, int NT, int RBW>
+__global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
+{
+    static_assert(P::KS == 32, "k-outer form is for the 16-bit split operands");
+    using Elem = typename P::Elem;
+    using Vec = typename P::Vec;
+    constexpr int NCT = NT / 16;
+    constexpr int LDC = kChunk + 8;     // halves; 8 lanes of a b128 fragment read hit distinct banks
+    __shared__ __align__(16) Elem Bs[2][2][NT][LDC];
+    __shared__ double red[kWavesKO][NT];
+    __shared__ double redm[kThreadsKO];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int gl = lane >> 4, cl = lane & 15;
+    const PostTask& T = A.t;
+    int64_t npts = T.count ? *T.count : T.n_points;
+    if (npts > T.n_points) npts = T.n_points;
+    const int64_t ntiles = (npts + NT - 1) / NT;
+    const int dim = A.kp.dim;
+    const int nks_total = A.mp / P::KS;
+    const int nch = (A.nrb + 1) / 2;                      // chunks covering the 16 nrb rows
+
+    // generation layout: thread -> column gc = tid % NT, rows gr .. gr + RPT - 1 of a chunk
+    constexpr int RPT = kChunk * NT / kThreadsKO;
+    const int gc = tid % NT, gr = (tid / NT) * RPT;
+    const float fie0 = (float)A.kp.inv_ell[0], fie1 = (float)A.kp.inv_ell[1], fie2 = (float)A.kp.inv_ell[2];
+    const float fs2 = (float)A.kp.s2, fsB = (float)A.sB;
+    const float inv = P::kScaled ? (float)(1.0 / (A.amax[1] * A.sB)) : 1.0f;   // a power of two
+    const Vec* __restrict__ Ahi = (const Vec*)A.A0;
+    const Vec* __restrict__ Alo = (const Vec*)A.A1;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t col0 = tile * NT;
+        const int64_t p = col0 + gc;
+        const bool valid = p < npts;
+        double px = 0.0, py = 0.0, pz = 0.0;
+        if (valid) {
+            if (T.mode == COL_GRID) {
+                const int64_t v = T.vlist ? (int64_t)T.vlist[p] : p;
+                const int64_t i0 = v % T.grid.n[0];
+                const int64_t r = v / T.grid.n[0];
+                px = vertex_coord(T.grid, 0, i0);
+                py = vertex_coord(T.grid, 1, r % T.grid.n[1]);
+                pz = dim > 2 ? vertex_coord(T.grid, 2, r / T.grid.n[1]) : 0.0;
+            } else {
+                px = T.pts[p * T.pstride + 0];
+                py = T.pts[p * T.pstride + 1];
+                pz = dim > 2 ? T.pts[p * T.pstride + 2] : 0.0;
+            }
+        }
+        double mpart = 0.0;
+        // B rows 32 c + gr .. + RPT - 1 of this thread's column into buffer b; branch-free
+        // (rows past the padded model are clamped and written as zeros)
+        auto generate = [&](int c, int b) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int j = kChunk * c + gr + i;
+                const int jj = j < A.mp ? j : A.mp - 1;
+                const bool live = valid && j < A.m;
+                const double* xj = A.X + (size_t)jj * 4;
+                const float t0 = (float)(px - xj[0]) * fie0, t1 = (float)(py - xj[1]) * fie1,
+                            t2 = (float)(pz - xj[2]) * fie2;
+                const float r2 = fmaf(t2, t2, fmaf(t1, t1, t0 * t0));
+                const float kv = kernel_val32(A.kp.kind, fs2, r2);
+                const float bv = live ? kv : 0.0f;
+                mpart = fma((double)bv, A.a[jj], mpart);
+                Elem hi, lo;
+                split16(P::kScaled ? bv * fsB : bv, hi, lo);
+                Bs[b][0][gc][gr + i] = hi;
+                Bs[b][1][gc][gr + i] = lo;
+            }
+        };
+
+        f4 acc[RBW][NCT];
+#pragma unroll
+        for (int r = 0; r < RBW; ++r)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
+        double dacc[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) dacc[ct] = 0.0;
+
+        auto epilogue = [&](int rb, f4 (&ac)[NCT]) {
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                if constexpr (P::kScaled) ac[ct] *= inv;
+                const double v0 = (double)ac[ct][0], v1 = (double)ac[ct][1];
+                const double v2 = (double)ac[ct][2], v3 = (double)ac[ct][3];
+                dacc[ct] += fma(v0, v0, v1 * v1) + fma(v2, v2, v3 * v3);
+                if (T.V) {
+                    const int64_t pc = col0 + 16 * ct + cl;
+                    if (pc < npts) {
+                        const size_t o = ((size_t)(4 * rb + gl) * T.n_points + pc) * 4;
+                        *(f4*)((float*)T.V + o) = ac[ct];
+                    }
+                }
+            }
+        };
+
+        // one chunk with row blocks r >= K live: fragments, next chunk's generation, MFMAs
+        auto body = [&](auto Kc, int c) {
+            constexpr int K = decltype(Kc)::value;
+            const int b = c & 1;
+            Vec bh[NCT], bl[NCT];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                bh[ct] = *(const Vec*)&Bs[b][0][16 * ct + cl][8 * gl];
+                bl[ct] = *(const Vec*)&Bs[b][1][16 * ct + cl][8 * gl];
+            }
+            Vec ah[RBW], al[RBW];
+#pragma unroll
+            for (int r = K; r < RBW; ++r) {
+                int rb = wave + kWavesKO * r;
+                rb = rb < A.nrb ? rb : A.nrb - 1;          // a missing row block is never stored
+                const size_t o = ((size_t)rb * nks_total + c) * 64 + lane;
+                ah[r] = Ahi[o];
+                al[r] = Alo[o];
+            }
+            generate(c + 1, b ^ 1);
+#pragma unroll
+            for (int r = K; r < RBW; ++r)
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct) {
+                    acc[r][ct] = mfma16(al[r], bh[ct], acc[r][ct]);
+                    acc[r][ct] = mfma16(ah[r], bl[ct], acc[r][ct]);
+                    acc[r][ct] = mfma16(ah[r], bh[ct], acc[r][ct]);
+                }
+            __syncthreads();
+        };
+        // phase K: chunks after row block K - 1 finished, up to the last chunk of row block K
+        auto phase = [&](auto Kc, int& c) {
+            constexpr int K = decltype(Kc)::value;
+            const int rbK = wave + kWavesKO * K;
+            const int cend = rbK / 2 < nch - 1 ? rbK / 2 : nch - 1;
+            for (; c <= cend; ++c) body(Kc, c);
+            if (rbK < A.nrb) epilogue(rbK, acc[K]);
+        };
+
+        __syncthreads();                 // previous tile's LDS reads are complete
+        generate(0, 0);
+        __syncthreads();
+        int c = 0;
+        static_for<0, RBW>([&](auto Kc) { phase(Kc, c); });
+        // chunks after this wave's last row block: generation and barriers only
+        for (; c < nch; ++c) {
+            generate(c + 1, (c & 1) ^ 1);
+            __syncthreads();
+        }
+
+        // ---- reductions: mean partials over the row groups, norm partials over lanes and waves
+        redm[tid] = mpart;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            double sum = dacc[ct];
+            sum += __shfl_xor(sum, 16, 64);
+            sum += __shfl_xor(sum, 32, 64);
+            if (gl == 0) red[wave][16 * ct + cl] = sum;
+        }
+        __syncthreads();
+        if (tid < NT) {
+            double mu = 0.0, dot = 0.0;
+            for (int g = 0; g < kThreadsKO / NT; ++g) mu += redm[g * NT + tid];
+            for (int w = 0; w < kWavesKO; ++w) dot += red[w][tid];
+            const int64_t pc = col0 + tid;
+            if (pc < npts) {
+                T.mean[pc] = mu;
+                const double v = A.kp.s2 - dot;
+                T.var[pc] = v > 0.0 ? v : 0.0;
+            }
+        }
+    }
+}
+
+template <class P, int NT, int RBW>
+hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
+{
+    KArgs A;
+    A.kp = M.kp;
+    A.m = M.m;
+    A.mp = M.m_pad;
+    A.nrb = (M.m + 15) / 16;
+    A.X = M.X;
+    A.a = M.a;
+    A.A0 = A0;
+    A.A1 = A1;
+    A.amax = M.amax;
+    {
+        int e;
+        frexp(M.k.signal_var, &e);
+        A.sB = ldexp(1.0, 15 - e);          // k* <= s2, so sB * k* < 2^15
+    }
+    A.t = t;
+    if (A.nrb > kWavesKO * RBW) return hipErrorInvalidValue;
+    const int64_t ntiles = (t.n_points + NT - 1) / NT;
+    int64_t grid = ntiles < 256 * 8 ? ntiles : 256 * 8;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_post_ko<P, NT, RBW>), dim3((unsigned)grid), dim3(kThreadsKO), 0, s, A);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_ko_split(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
+{
+    switch ((M.nrb + kWavesKO - 1) / kWavesKO) {
+    case 1: return launch_ko<P, 64, 1>(M, t, s, A0, A1);
+    case 2: return launch_ko<P, 64, 2>(M, t, s, A0, A1);
+    case 3: return launch_ko<P, 64, 3>(M, t, s, A0, A1);
+    case 4: return launch_ko<P, 64, 4>(M, t, s, A0, A1);
+    default: return launch_ko<P, 32, 8>(M, t, s, A0, A1);
+    }
+}
+
 template <class P, int NT, int G>
 hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
 {
@@ -504,12 +745,13 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
         if (grad) return launch_t<P32, 32, 4>(M, t, s, M.A32, nullptr);
         return launch_t<P32, 32, 1>(M, t, s, M.A32, nullptr);
     }
+    // 16-bit split value columns: k-outer kernel with RBW = ceil(nrb / 8) row blocks per wave
     if (prec == LCP_MIXED_F16X3) {
         if (grad) return launch_t<PH3, 32, 4>(M, t, s, M.Hhi, M.Hlo);
-        return launch_t<PH3, 32, 1>(M, t, s, M.Hhi, M.Hlo);
+        return launch_ko_split<PH3>(M, t, s, M.Hhi, M.Hlo);
     }
     if (grad) return launch_t<PB3, 32, 4>(M, t, s, M.Ahi, M.Alo);
-    return launch_t<PB3, 32, 1>(M, t, s, M.Ahi, M.Alo);
+    return launch_ko_split<PB3>(M, t, s, M.Ahi, M.Alo);
 }
 
 }  // namespace lcp

@@ -107,12 +107,16 @@ __device__ __forceinline__ double kernel_val(const KParams& p, double r2)
 // k in binary32 for the reduced-precision operand paths (binary32 and split 16-bit MFMA
 // products carry 22-24 significant bits, which this evaluation matches): hardware exp2 and
 // square root, r2 already scaled by the lengthscales.
+// Branch-free in the kernel kind, so generation loops stay single basic blocks:
+// SE: s2 exp(-r2 / 2); Matern-5/2: s2 (1 + t + t^2 / 3) exp(-t) with t = sqrt(5 r2).
 __device__ __forceinline__ float kernel_val32(int kind, float s2, float r2)
 {
     constexpr float kLog2e = 1.44269504088896341f;
-    if (kind == LCP_KERNEL_SE) return s2 * __builtin_amdgcn_exp2f((-0.5f * kLog2e) * r2);
+    const bool se = kind == LCP_KERNEL_SE;
     const float t = 2.23606797749978970f * __builtin_amdgcn_sqrtf(r2);
-    return s2 * fmaf(5.0f / 3.0f, r2, t + 1.0f) * __builtin_amdgcn_exp2f(-kLog2e * t);
+    const float u = se ? 0.5f * r2 : t;
+    const float poly = se ? 1.0f : fmaf(t, fmaf(t, 1.0f / 3.0f, 1.0f), 1.0f);
+    return s2 * poly * __builtin_amdgcn_exp2f(-kLog2e * u);
 }
 
 // d k(x, z) / d x_d = f(r) * (x_d - z_d) / ell_d^2; returns f(r).
