@@ -493,6 +493,7 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
     __shared__ __align__(16) Elem Bs[2][2][NT][LDC];
     __shared__ double red[kWavesKO][NT];
     __shared__ double redm[kThreadsKO];
+    __shared__ double4 Xs[kMaxM];                           // observations (x, y, z, a_j)
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -513,6 +514,8 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
     const float inv = P::kScaled ? (float)(1.0 / (A.amax[1] * A.sB)) : 1.0f;   // a power of two
     const Vec* __restrict__ Ahi = (const Vec*)A.A0;
     const Vec* __restrict__ Alo = (const Vec*)A.A1;
+    for (int j = tid; j < A.mp; j += kThreadsKO)
+        Xs[j] = double4{A.X[4 * j + 0], A.X[4 * j + 1], A.X[4 * j + 2], A.a[j]};
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t col0 = tile * NT;
@@ -542,13 +545,13 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
                 const int j = kChunk * c + gr + i;
                 const int jj = j < A.mp ? j : A.mp - 1;
                 const bool live = valid && j < A.m;
-                const double* xj = A.X + (size_t)jj * 4;
-                const float t0 = (float)(px - xj[0]) * fie0, t1 = (float)(py - xj[1]) * fie1,
-                            t2 = (float)(pz - xj[2]) * fie2;
+                const double4 xj = Xs[jj];
+                const float t0 = (float)(px - xj.x) * fie0, t1 = (float)(py - xj.y) * fie1,
+                            t2 = (float)(pz - xj.z) * fie2;
                 const float r2 = fmaf(t2, t2, fmaf(t1, t1, t0 * t0));
                 const float kv = kernel_val32(A.kp.kind, fs2, r2);
                 const float bv = live ? kv : 0.0f;
-                mpart = fma((double)bv, A.a[jj], mpart);
+                mpart = fma((double)bv, xj.w, mpart);
                 Elem hi, lo;
                 split16(P::kScaled ? bv * fsB : bv, hi, lo);
                 Bs[b][0][gc][gr + i] = hi;
