@@ -180,7 +180,11 @@ struct BoundBufs {
     int32_t* flag;      // per stage-1 node: needs the next stage
     int32_t* fidx;      // prefix sum of flag
     int32_t* lnode;     // stage-2 node -> stage-1 node
-    double* lat_pts;    // 3^D points per stage-2 node, 3 doubles each
+    int32_t* ngrid;     // node lattice of this level -> stage-2 node (-1: not in stage 2)
+    int32_t* lmask;     // per stage-2 node: lattice points it evaluates (owns), bit i = point i
+    int32_t* lcnt;      // popcount of lmask
+    int32_t* loff;      // prefix sum of lcnt: first slot of the node's owned points
+    double* lat_pts;    // unique lattice points, 3 doubles each
     double* lat_mean;
     double* lat_var;
     int32_t* dnode;     // stage-3 node -> stage-1 node
@@ -190,7 +194,7 @@ struct BoundBufs {
     double* gp_var;
     double* gp_dmean;
     double* gp_dvar;
-    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] lattice points, [3] stage-3 nodes
+    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes
 };
 
 __device__ __forceinline__ double upper_bound(double gmin, int64_t dp)
@@ -244,64 +248,185 @@ __global__ void k_bound_centre(Oct o, int level, const uint64_t* __restrict__ ke
     }
 }
 
-// Stage 2 set-up: the 3^D lattice points of the open nodes.
-__global__ void k_lattice_setup(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
+// Stage 2 shares lattice points between neighbouring open nodes.  A lattice point with
+// digit (0 lo, 1 mid, 2 hi) per axis lies in the nodes offset by 0 or -1 (lo) / +1 (hi)
+// along the axes where it sits on the box boundary; those nodes compute bitwise the same
+// coordinates for it (the shared face has the same vertex, the mid of a shared edge the
+// same two vertices).  It is evaluated once, by the open node with the lowest linear index
+// in the node lattice, and every node reads it from there.
+__device__ __forceinline__ int64_t node_lin(const Oct& o, int level, const int64_t* c)
+{
+    return c[0] + o.nodes[level * 3 + 0] * (c[1] + o.nodes[level * 3 + 1] * c[2]);
+}
+
+// Owner of point i (digits base 3, x fastest) of the node at c: its node lattice coords
+// and the point's index in the owner's lattice.  The node itself is always a candidate.
+__device__ __forceinline__ void lattice_owner(const Oct& o, int level, const int32_t* __restrict__ ngrid,
+                                              const int64_t* c, int i, int64_t* oc, int* oi)
+{
+    int dig[3] = {1, 1, 1};
+    int r = i;
+    for (int d = 0; d < o.D; ++d) {
+        dig[d] = r % 3;
+        r /= 3;
+    }
+    int64_t best = node_lin(o, level, c);
+    int64_t bc[3] = {c[0], c[1], c[2]};
+    int bdig[3] = {dig[0], dig[1], dig[2]};
+    const int nalt = 1 << o.D;
+    for (int mask = 1; mask < nalt; ++mask) {
+        int64_t q[3] = {c[0], c[1], c[2]};
+        int qd[3] = {dig[0], dig[1], dig[2]};
+        bool ok = true;
+        for (int d = 0; d < o.D && ok; ++d) {
+            if (!((mask >> d) & 1)) continue;
+            if (dig[d] == 0) { q[d] = c[d] - 1; qd[d] = 2; }
+            else if (dig[d] == 2) { q[d] = c[d] + 1; qd[d] = 0; }
+            else ok = false;
+            if (ok && (q[d] < 0 || q[d] >= o.nodes[level * 3 + d])) ok = false;
+        }
+        if (!ok) continue;
+        const int64_t lin = node_lin(o, level, q);
+        if (ngrid[lin] >= 0 && lin < best) {
+            best = lin;
+            for (int d = 0; d < 3; ++d) { bc[d] = q[d]; bdig[d] = qd[d]; }
+        }
+    }
+    for (int d = 0; d < 3; ++d) oc[d] = bc[d];
+    *oi = bdig[0] + 3 * bdig[1] + (o.D == 3 ? 9 * bdig[2] : 0);
+}
+
+// Stage-2 nodes into the node lattice of this level.
+__global__ void k_lattice_grid(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
 {
     const int64_t nb = B.cnt[0];
-    const int npt = o.D == 3 ? 27 : 9;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
         if (!B.flag[b]) continue;
-        const int64_t l = B.fidx[b];
+        const int32_t l = B.fidx[b];
         B.lnode[l] = (int32_t)b;
+        int lv;
+        int64_t c[3];
+        key_coords(o.D, keys[B.bnode[b]], lv, c);
+        B.ngrid[node_lin(o, level, c)] = l;
+    }
+}
+
+// Which lattice points each stage-2 node owns: 32 lanes per node, lane i = point i.
+__global__ void k_lattice_own(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
+{
+    const int64_t nl = B.cnt[1];
+    const int npt = o.D == 3 ? 27 : 9;
+    const int sub_lane = threadIdx.x & 31;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 32);
+    // every lane of a wave runs the same number of iterations (ballot below)
+    for (int64_t base = (int64_t)blockIdx.x * (blockDim.x / 32) + (threadIdx.x >> 6) * 2; base < nl; base += stride) {
+        const int64_t l = base + ((threadIdx.x >> 5) & 1);
+        bool own = false;
+        if (l < nl && sub_lane < npt) {
+            int lv;
+            int64_t c[3], oc[3];
+            key_coords(o.D, keys[B.bnode[B.lnode[l]]], lv, c);
+            int oi;
+            lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
+            own = node_lin(o, level, oc) == node_lin(o, level, c);
+        }
+        const uint64_t bal = __ballot(own);
+        const int32_t mask = (int32_t)((bal >> (threadIdx.x & 32)) & 0xffffffffu);
+        if (l < nl && sub_lane == 0) {
+            B.lmask[l] = mask;
+            B.lcnt[l] = __builtin_popcount(mask);
+        }
+    }
+}
+
+__device__ __forceinline__ void lattice_point(const Oct& o, const double* blo, const double* bhi, int i, double* x)
+{
+    int r = i;
+    for (int d = 0; d < 3; ++d) {
+        x[d] = 0.0;
+        if (d < o.D) {
+            const int digit = r % 3;
+            r /= 3;
+            x[d] = digit == 0 ? blo[d] : (digit == 1 ? 0.5 * (blo[d] + bhi[d]) : bhi[d]);
+        }
+    }
+}
+
+// Stage 2 set-up: the owned lattice points, compacted.
+__global__ void k_lattice_setup(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
+{
+    const int64_t nl = B.cnt[1];
+    const int npt = o.D == 3 ? 27 : 9;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x) {
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[B.bnode[b]], lv, c);
+        key_coords(o.D, keys[B.bnode[B.lnode[l]]], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        const int32_t mask = B.lmask[l];
+        int64_t slot = B.loff[l];
         for (int i = 0; i < npt; ++i) {
-            int r = i;
-            for (int d = 0; d < 3; ++d) {
-                double x = 0.0;
-                if (d < o.D) {
-                    const int digit = r % 3;
-                    r /= 3;
-                    x = digit == 0 ? blo[d] : (digit == 1 ? 0.5 * (blo[d] + bhi[d]) : bhi[d]);
-                }
-                B.lat_pts[(l * npt + i) * 3 + d] = x;
-            }
+            if (!((mask >> i) & 1)) continue;
+            double x[3];
+            lattice_point(o, blo, bhi, i, x);
+            for (int d = 0; d < 3; ++d) B.lat_pts[slot * 3 + d] = x[d];
+            ++slot;
         }
     }
 }
 
 // Stage 2: lattice minimum (lowest index wins ties), start point, bound; nodes left open
-// go to the descent (or are skipped when the search has no steps).
+// go to the descent (or are skipped when the search has no steps).  32 lanes per node,
+// lane i reads point i from its owner's slot.
 __global__ void k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B, int32_t* __restrict__ sub)
 {
     const int64_t nl = B.cnt[1];
     const int npt = o.D == 3 ? 27 : 9;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t b = B.lnode[l];
-        const double side = B.side[b];
-        double best = __builtin_inf();
-        int ib = 0;
-        for (int i = 0; i < npt; ++i) {
-            const double gv = margin(side, o.theta, B.lat_mean[l * npt + i], B.lat_var[l * npt + i]);
-            if (gv < best) {
-                best = gv;
-                ib = i;
+    const int sub_lane = threadIdx.x & 31;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 32);
+    for (int64_t base = (int64_t)blockIdx.x * (blockDim.x / 32) + (threadIdx.x >> 6) * 2; base < nl; base += stride) {
+        const int64_t l = base + ((threadIdx.x >> 5) & 1);
+        const bool live = l < nl;
+        int32_t b = 0, f = 0;
+        int64_t c[3] = {0, 0, 0};
+        double gv = __builtin_inf();
+        if (live) {
+            b = B.lnode[l];
+            f = B.bnode[b];
+            int lv;
+            key_coords(o.D, keys[f], lv, c);
+            if (sub_lane < npt) {
+                int64_t oc[3];
+                int oi;
+                lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
+                const int32_t ol = B.ngrid[node_lin(o, level, oc)];
+                const int64_t slot = B.loff[ol] + __builtin_popcount(B.lmask[ol] & ((1 << oi) - 1));
+                gv = margin(B.side[b], o.theta, B.lat_mean[slot], B.lat_var[slot]);
             }
         }
-        const int32_t f = B.bnode[b];
-        int lv;
-        int64_t c[3], clo[3], chi[3], dp;
-        double blo[3], bhi[3];
-        key_coords(o.D, keys[f], lv, c);
-        node_box(o, level, c, clo, chi, blo, bhi, &dp);
-        B.gmin[b] = best;
-        const bool open = !(upper_bound(best, dp) > o.alpha);
-        if (!open) sub[f] = 1;
-        B.flag[b] = (open && o.steps > 0) ? 2 : 0;       // 2: enters the descent
-        for (int d = 0; d < 3; ++d) B.x[(int64_t)b * 3 + d] = B.lat_pts[(l * npt + ib) * 3 + d];
+        // minimum over the 32 lanes of the node, lowest point index on ties
+        double best = gv;
+        int ib = sub_lane;
+        for (int off = 16; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oib = __shfl_xor(ib, off, 64);
+            if (ob < best || (ob == best && oib < ib)) {
+                best = ob;
+                ib = oib;
+            }
+        }
+        if (live && sub_lane == 0) {
+            int64_t clo[3], chi[3], dp;
+            double blo[3], bhi[3];
+            node_box(o, level, c, clo, chi, blo, bhi, &dp);
+            B.gmin[b] = best;
+            const bool open = !(upper_bound(best, dp) > o.alpha);
+            if (!open) sub[f] = 1;
+            B.flag[b] = (open && o.steps > 0) ? 2 : 0;       // 2: enters the descent
+            double x[3];
+            lattice_point(o, blo, bhi, best == __builtin_inf() ? 0 : ib, x);
+            for (int d = 0; d < 3; ++d) B.x[(int64_t)b * 3 + d] = x[d];
+        }
     }
 }
 
@@ -540,7 +665,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_x, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx;
+    size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_lcnt, o_loff;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb;
     int64_t capF, nv;
 };
@@ -593,6 +718,10 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_gmin = take(8 * capF);
     L.o_x = take(24 * capF);
     L.o_done = take(4 * capF);
+    L.o_ngrid = take(4 * capF);
+    L.o_lmask = take(4 * capF);
+    L.o_lcnt = take(4 * capF);
+    L.o_loff = take(4 * capF);
     L.o_latp = take(24 * capF * npt);
     L.o_latm = take(8 * capF * npt);
     L.o_latv = take(8 * capF * npt);
@@ -664,6 +793,10 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.flag = (int32_t*)P(L.o_flag);
     B.fidx = (int32_t*)P(L.o_fidx);
     B.lnode = (int32_t*)P(L.o_lnode);
+    B.ngrid = (int32_t*)P(L.o_ngrid);
+    B.lmask = (int32_t*)P(L.o_lmask);
+    B.lcnt = (int32_t*)P(L.o_lcnt);
+    B.loff = (int32_t*)P(L.o_loff);
     B.dnode = (int32_t*)P(L.o_dnode);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
@@ -735,7 +868,12 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
             e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 1, scanws, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, B.cnt + 2, B.cnt + 1, (int64_t)npt);
+            e = launch_fill_i32(B.ngrid, -1, cap, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_lattice_grid, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
+            hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B);
+            e = launch_scan(B.lcnt, B.loff, cap, B.cnt + 1, B.cnt + 2, scanws, s);
+            if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_lattice_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
         }
         // stage 2: lattice
@@ -743,7 +881,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         if (e != hipSuccess) return e;
         {
             StageScope sc(s, ST_OCTREE);
-            hipLaunchKernelGGL(k_lattice, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
+            hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B, sub);
             hipLaunchKernelGGL(k_flag_stage3, dim3(gsz(cap, 256)), dim3(256), 0, s, B);
             e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 3, scanws, s);
             if (e != hipSuccess) return e;
