@@ -210,86 +210,197 @@ __device__ __forceinline__ void chol_sd(double (&S)[N][N], double (&C)[N][N])
     }
 }
 
-template <int D, class TM>
-__global__ void __launch_bounds__(256) k_cells(CellTask t, int64_t ncells_cap)
+// Cell e of the enumeration (dense: all cells, x fastest; adaptive: leaf by leaf): its
+// linear index and the slots of its corners.  Returns 0 (cell outside the domain), 1 (a
+// corner has no posterior data: the cell's LCP is NaN) or 2.
+template <int D>
+__device__ __forceinline__ int cell_corners(const CellTask& t, int64_t e, int64_t& lin, int64_t (&sl)[1 << D])
 {
     constexpr int N = 1 << D;
     constexpr int NDIR = D == 3 ? 13 : 4;
     const GridP& g = t.grid;
-    int64_t total;
-    int64_t nleaf = 0;
-    int64_t cpl = 1;
+    int64_t cell[3] = {0, 0, 0};
     if (t.leaves) {
-        nleaf = *t.n_leaves;
-        if (nleaf > t.leaf_cap) return;          // overflow: reconstruction skipped
+        int64_t cpl = 1;
+        for (int d = 0; d < D; ++d) cpl *= t.leaf_edge;
+        const int64_t lf = e / cpl;
+        int64_t loc = e % cpl;
+        const uint64_t key = t.leaves[lf];
+        const int level = (int)(key >> 58);
+        const uint64_t mc = key & ((1ull << 58) - 1);
+        int64_t nc[3] = {0, 0, 0};
+        for (int b = 0; b < level; ++b)
+            for (int d = 0; d < D; ++d) nc[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
+        const int64_t sz = t.S0 >> level;
+        bool in = true;
+        for (int d = 0; d < D; ++d) {
+            cell[d] = nc[d] * sz + loc % t.leaf_edge;
+            loc /= t.leaf_edge;
+            in = in && cell[d] < g.nc[d];
+        }
+        if (!in) return 0;
+    } else {
+        int64_t r = e;
+        cell[0] = r % g.nc[0];
+        r /= g.nc[0];
+        cell[1] = r % g.nc[1];
+        cell[2] = r / g.nc[1];
+    }
+    lin = cell[0] + g.nc[0] * (cell[1] + g.nc[1] * cell[2]);
+    bool have = true;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const int64_t vx = cell[0] + (q & 1), vy = cell[1] + ((q >> 1) & 1), vz = cell[2] + ((q >> 2) & 1);
+        const int64_t vid = vx + g.n[0] * (vy + g.n[1] * (D == 3 ? vz : 0));
+        sl[q] = t.slot ? (int64_t)t.slot[vid] : vid;
+        have = have && sl[q] >= 0;
+    }
+    return have ? 2 : 1;
+}
+
+// Corner moments of a cell: mu - theta and the semidefinite Cholesky factor of the corner
+// covariance (sl from cell_corners).
+template <int D>
+__device__ __forceinline__ void cell_factor(const CellTask& t, const int64_t (&sl)[1 << D], double (&mu)[1 << D],
+                                            double (&Cd)[1 << D][1 << D])
+{
+    constexpr int N = 1 << D;
+    constexpr int NDIR = D == 3 ? 13 : 4;
+    double S[N][N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        mu[q] = t.mean[sl[q]] - t.theta;
+        S[q][q] = t.var[sl[q]];
+    }
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int q = p + 1; q < N; ++q) {
+            const int dx = (q & 1) - (p & 1), dy = ((q >> 1) & 1) - ((p >> 1) & 1),
+                      dz = ((q >> 2) & 1) - ((p >> 2) & 1);
+            const double c = t.cross[(size_t)sl[p] * NDIR + dir_index(D, dx, dy, dz)];
+            S[q][p] = c;
+            S[p][q] = c;
+        }
+    chol_sd<N>(S, Cd);
+}
+
+// Number of enumerated cells (dense grid, or the cells of the emitted leaves).
+template <int D>
+__device__ __forceinline__ int64_t cell_total(const CellTask& t, int64_t ncells_cap)
+{
+    int64_t total;
+    if (t.leaves) {
+        const int64_t nleaf = *t.n_leaves;
+        if (nleaf > t.leaf_cap) return 0;          // overflow: reconstruction skipped
+        int64_t cpl = 1;
         for (int d = 0; d < D; ++d) cpl *= t.leaf_edge;
         total = nleaf * cpl;
     } else {
-        total = g.nc[0] * g.nc[1] * g.nc[2];
+        total = t.grid.nc[0] * t.grid.nc[1] * t.grid.nc[2];
     }
+    return total < ncells_cap ? total : ncells_cap;
+}
+
+// max_s ||z_s||_2 over the z-bank (one work-group).
+__global__ void __launch_bounds__(256) k_zmax(const double* __restrict__ zb, int ns, int n, double* __restrict__ out)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int s = threadIdx.x; s < ns; s += 256) {
+        double q = 0.0;
+        for (int r = 0; r < n; ++r) q = fma(zb[(size_t)s * n + r], zb[(size_t)s * n + r], q);
+        m = fmax(m, sqrt(q));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Certified skip of the Monte Carlo loop.  Every sample value of corner q is
+// y_q = m_q + C_q . z_s with |C_q . z_s| <= ||C_q||_2 ||z_s||_2 <= ||C_q||_2 zmax, so when
+// m_q - ||C_q|| zmax > 0 for every corner (or m_q + ||C_q|| zmax < 0 for every corner) no
+// sample can cross: the count is exactly 0.  The margin covers the rounding of the Monte
+// Carlo loop in its own precision (relative 1e-5 for binary32, 1e-12 for binary64).
+// Cells that cannot be certified go to the work list (order immaterial: each cell's
+// result depends on that cell only).
+template <int D, class TM>
+__global__ void __launch_bounds__(256) k_cells_cert(CellTask t, int64_t ncells_cap)
+{
+    constexpr int N = 1 << D;
+    const int64_t total = cell_total<D>(t, ncells_cap);
+    const double zm = *t.zmax;
+    const double rel = std::is_same<TM, double>::value ? 1e-12 : 1e-5;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = base + threadIdx.x;
+        bool work = false;
+        if (e < total) {
+            int64_t lin = 0;
+            int64_t sl[N];
+            const int st = cell_corners<D>(t, e, lin, sl);
+            if (st == 1) {
+                t.lcp[lin] = __builtin_nanf("");
+            } else if (st == 2) {
+                // pre-filter on the corner standard deviations (row norms of an exact factor);
+                // only cells that pass it are factored for the exact test
+                bool above = true, below = true;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    const double m = t.mean[sl[q]] - t.theta;
+                    const double b = 1.001 * sqrt(fmax(t.var[sl[q]], 0.0)) * zm;
+                    above = above && (m > b);
+                    below = below && (m < -b);
+                }
+                if (above || below) {
+                    double mu[N], Cd[N][N];
+                    cell_factor<D>(t, sl, mu, Cd);
+                    above = below = true;
+#pragma unroll
+                    for (int q = 0; q < N; ++q) {
+                        double rn = 0.0;
+#pragma unroll
+                        for (int r = 0; r <= q; ++r) rn = fma(Cd[q][r], Cd[q][r], rn);
+                        const double b = sqrt(rn) * zm;
+                        const double pad = rel * (fabs(mu[q]) + b) + 1e-300;
+                        above = above && (mu[q] - b > pad);
+                        below = below && (mu[q] + b < -pad);
+                    }
+                }
+                if (above || below) t.lcp[lin] = 0.0f;
+                else work = true;
+            }
+        }
+        // wave-aggregated append
+        const uint64_t bal = __ballot(work);
+        if (bal) {
+            int64_t pos = 0;
+            if (lane == 0) pos = atomicAdd((unsigned long long*)t.wcount, (unsigned long long)__popcll(bal));
+            pos = __shfl(pos, 0, 64);
+            if (work) t.work[pos + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)e;
+        }
+    }
+}
+
+// Monte Carlo LCP of the listed cells (count = *wcount).
+template <int D, class TM>
+__global__ void __launch_bounds__(256) k_cells(CellTask t, int64_t ncells_cap)
+{
+    constexpr int N = 1 << D;
+    int64_t total = *t.wcount;
     if (total > ncells_cap) total = ncells_cap;
     const TM* zb = std::is_same<TM, double>::value ? (const TM*)t.zb64 : (const TM*)t.zb32;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
-        int64_t cell[3] = {0, 0, 0};
-        if (t.leaves) {
-            const int64_t lf = it / cpl;
-            int64_t loc = it % cpl;
-            const uint64_t key = t.leaves[lf];
-            const int level = (int)(key >> 58);
-            const uint64_t mc = key & ((1ull << 58) - 1);
-            int64_t nc[3] = {0, 0, 0};
-            for (int b = 0; b < level; ++b)
-                for (int d = 0; d < D; ++d) nc[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
-            const int64_t s = t.S0 >> level;
-            bool in = true;
-            for (int d = 0; d < D; ++d) {
-                cell[d] = nc[d] * s + loc % t.leaf_edge;
-                loc /= t.leaf_edge;
-                in = in && cell[d] < g.nc[d];
-            }
-            if (!in) continue;
-        } else {
-            int64_t r = it;
-            cell[0] = r % g.nc[0];
-            r /= g.nc[0];
-            cell[1] = r % g.nc[1];
-            cell[2] = r / g.nc[1];
-        }
-        // gather corner data
+        int64_t lin = 0;
         int64_t sl[N];
-        double mu[N];
-        double S[N][N];
-        bool have = true;
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            const int64_t vx = cell[0] + (q & 1), vy = cell[1] + ((q >> 1) & 1), vz = cell[2] + ((q >> 2) & 1);
-            const int64_t vid = vx + g.n[0] * (vy + g.n[1] * (D == 3 ? vz : 0));
-            sl[q] = t.slot ? (int64_t)t.slot[vid] : vid;
-            have = have && sl[q] >= 0;
-        }
-        const int64_t lin = cell[0] + g.nc[0] * (cell[1] + g.nc[1] * cell[2]);
-        if (!have) {                      // a corner without posterior data: no estimate
-            t.lcp[lin] = __builtin_nanf("");
-            continue;
-        }
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            mu[q] = t.mean[sl[q]] - t.theta;
-            S[q][q] = t.var[sl[q]];
-        }
-#pragma unroll
-        for (int p = 0; p < N; ++p)
-#pragma unroll
-            for (int q = p + 1; q < N; ++q) {
-                const int dx = (q & 1) - (p & 1), dy = ((q >> 1) & 1) - ((p >> 1) & 1),
-                          dz = ((q >> 2) & 1) - ((p >> 2) & 1);
-                const double c = t.cross[(size_t)sl[p] * NDIR + dir_index(D, dx, dy, dz)];
-                S[q][p] = c;
-                S[p][q] = c;
-            }
-        double Cd[N][N];
-        chol_sd<N>(S, Cd);
+        if (cell_corners<D>(t, t.work[it], lin, sl) != 2) continue;
+        double mu[N], Cd[N][N];
+        cell_factor<D>(t, sl, mu, Cd);
         TM C[N][N], m[N];
 #pragma unroll
         for (int q = 0; q < N; ++q) {
@@ -383,12 +494,24 @@ hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s)
     StageScope sc(s, ST_CELLS);
     unsigned grid = grid_for(ncells_cap, 256);
     const bool f64 = t.prec == LCP_FP64;
+    hipLaunchKernelGGL(k_zmax, dim3(1), dim3(256), 0, s, t.zb64, t.ns, 1 << t.grid.dim, t.zmax);
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, t.wcount, (int64_t)0, (int64_t)1);
     if (t.grid.dim == 3) {
-        if (f64) hipLaunchKernelGGL((k_cells<3, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-        else hipLaunchKernelGGL((k_cells<3, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+        if (f64) {
+            hipLaunchKernelGGL((k_cells_cert<3, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+            hipLaunchKernelGGL((k_cells<3, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+        } else {
+            hipLaunchKernelGGL((k_cells_cert<3, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+            hipLaunchKernelGGL((k_cells<3, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+        }
     } else {
-        if (f64) hipLaunchKernelGGL((k_cells<2, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-        else hipLaunchKernelGGL((k_cells<2, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+        if (f64) {
+            hipLaunchKernelGGL((k_cells_cert<2, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+            hipLaunchKernelGGL((k_cells<2, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+        } else {
+            hipLaunchKernelGGL((k_cells_cert<2, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+            hipLaunchKernelGGL((k_cells<2, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
+        }
     }
     return hipGetLastError();
 }

@@ -666,7 +666,7 @@ struct AdaptLayout {
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_x, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
     size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_lcnt, o_loff;
-    size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb;
+    size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     int64_t capF, nv;
 };
 
@@ -741,6 +741,11 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_V = take(vb * (size_t)nv * M.m_pad);
     L.o_cross = take(8 * (size_t)nv * ndir);
     L.o_zb = take(4 * (size_t)ns * (1 << D));
+    {
+        int64_t cpl = 1;
+        for (int d = 0; d < D; ++d) cpl *= S0 >> Lmax;
+        L.o_cellws = take(cells_scratch_bytes(caps[Lmax] * cpl));
+    }
     L.total = o;
     L.capF = capF;
     L.nv = nv;
@@ -979,6 +984,14 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     ct.Lmax = Lmax;
     ct.leaf_edge = leaf_edge;
     ct.lcp = lcp;
+    {
+        int64_t cpl_all = 1;
+        for (int d = 0; d < D; ++d) cpl_all *= leaf_edge;
+        char* cw = (char*)P(L.o_cellws);
+        ct.work = (int32_t*)cw;
+        ct.wcount = (int64_t*)(cw + align256(4 * (size_t)(caps[Lmax] * cpl_all)));
+        ct.zmax = (double*)((char*)ct.wcount + 64);
+    }
     int64_t cpl = 1;
     for (int d = 0; d < D; ++d) cpl *= leaf_edge;
     return launch_cells(ct, leaf_cap * cpl, s);

@@ -99,6 +99,7 @@ size_t dense_ws(const lcp_model* M, const GridP& g, int prec, int ns)
     b += align256(vb * (size_t)nv * M->m_pad);               // V
     b += align256(sizeof(double) * (size_t)nv * ndir(g.dim)); // cross
     b += align256(sizeof(float) * (size_t)ns * (1 << g.dim)); // FP32 z-bank
+    b += cells_scratch_bytes(g.nc[0] * g.nc[1] * g.nc[2]);   // Monte Carlo work list
     return b;
 }
 
@@ -290,6 +291,12 @@ int lcp_dense(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_
     double* cross = (double*)p;
     p += align256(sizeof(double) * (size_t)nv * ndir(g.dim));
     float* zb32 = (float*)p;
+    p += align256(sizeof(float) * (size_t)mc->n_samples * (1 << g.dim));
+    const int64_t ncells = g.nc[0] * g.nc[1] * g.nc[2];
+    int32_t* work = (int32_t*)p;
+    p += align256(4 * (size_t)ncells);
+    int64_t* wcount = (int64_t*)p;
+    double* zmax = (double*)(p + 64);
     hipError_t e;
     if (prec != LCP_FP64) {
         e = launch_zbank32(mc->zbank, zb32, (int64_t)mc->n_samples << g.dim, s);
@@ -323,7 +330,10 @@ int lcp_dense(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_
     ct.slot = nullptr;
     ct.leaves = nullptr;
     ct.lcp = lcp;
-    e = launch_cells(ct, g.nc[0] * g.nc[1] * g.nc[2], s);
+    ct.work = work;
+    ct.wcount = wcount;
+    ct.zmax = zmax;
+    e = launch_cells(ct, ncells, s);
     if (e != hipSuccess) return dev_fail(e, "cells");
     return ok();
 }

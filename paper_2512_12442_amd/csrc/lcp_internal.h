@@ -198,7 +198,14 @@ struct CellTask {
     int Lmax;
     int leaf_edge;            // cells per leaf edge
     float* lcp;               // whole cell field
+    // scratch (device): Monte Carlo work list of enumeration indices, its count, max ||z||
+    int32_t* work;            // >= ncells_cap entries
+    int64_t* wcount;
+    double* zmax;
 };
+
+// Scratch bytes launch_cells needs for ncells_cap enumerated cells.
+inline size_t cells_scratch_bytes(int64_t ncells_cap) { return ((4 * (size_t)ncells_cap + 255) & ~size_t(255)) + 256; }
 
 // V: quad-major with nv_cap columns (as written by the posterior kernel).
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
