@@ -106,9 +106,11 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <class P, int NT, int G>
-__global__ void __launch_bounds__(kThreads) k_post(KArgs A)
+template <class P, int NT, int G, int NW>
+__global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
 {
+    constexpr int kThreads = NW * 64;
+    constexpr int kWaves = NW;
     extern __shared__ __align__(16) unsigned char smem[];
     using Elem = typename P::Elem;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -268,14 +270,14 @@ __global__ void __launch_bounds__(kThreads) k_post(KArgs A)
                 }
             }
         };
-        // Each wave owns the row-block pair (8q + w, 8q + 7 - w) of every group of eight
-        // (equal triangular work per wave) and runs both in one k loop, so each B fragment
+        // Each wave owns the row-block pair (2NW q + w, 2NW q + 2NW - 1 - w) of every group of
+        // 2NW (equal triangular work per wave) and runs both in one k loop, so each B fragment
         // read from LDS feeds both.  k-steps run in groups of U with two fragment buffers in
         // ping-pong: the L^-1 fragments of group g + U are requested before group g is
         // multiplied.  Loop bounds are rounded up to 2U k-steps (m_pad is a multiple of 128,
         // so no group leaves the padded matrix; steps past the diagonal multiply zeros).
-        for (int q = 0; q * 8 < A.nrb; ++q) {
-            const int ra = 8 * q + wave, rbb = 8 * q + 7 - wave;
+        for (int q = 0; q * 2 * NW < A.nrb; ++q) {
+            const int ra = 2 * NW * q + wave, rbb = 2 * NW * q + 2 * NW - 1 - wave;
             if (ra >= A.nrb) continue;                 // then rbb >= nrb as well
             const bool hasB = rbb < A.nrb;
             typename P::Acc accA[NCT], accB[NCT];
@@ -698,7 +700,7 @@ hipError_t launch_ko_split(const Model& M, const PostTask& t, hipStream_t s, con
     }
 }
 
-template <class P, int NT, int G>
+template <class P, int NT, int G, int NW = kWaves>
 hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
 {
     KArgs A;
@@ -718,8 +720,8 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
     }
     A.t = t;
     int ldb = (P::KS == 32) ? (M.m_pad + 63) / 64 * 64 + P::LPAD : M.m_pad + P::LPAD;
-    size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (kThreads * G + NT);
-    hipError_t e = hipFuncSetAttribute((const void*)k_post<P, NT, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (NW * 64 * G + NT);
+    hipError_t e = hipFuncSetAttribute((const void*)k_post<P, NT, G, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
     int64_t ncols = t.n_points * G;
@@ -727,7 +729,7 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
     int dev_cus = 256;
     int64_t grid = ntiles < (int64_t)dev_cus * 8 ? ntiles : (int64_t)dev_cus * 8;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_post<P, NT, G>), dim3((unsigned)grid), dim3(kThreads), lds, s, A);
+    hipLaunchKernelGGL((k_post<P, NT, G, NW>), dim3((unsigned)grid), dim3(NW * 64), lds, s, A);
     return hipGetLastError();
 }
 
@@ -741,6 +743,12 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
     // Tile widths keep B at <= 80 KB of LDS (m_pad <= 1024 / 1152), so two work-groups share
     // a CU and one's B generation (VALU) overlaps the other's MFMA sweep.
     if (prec == LCP_FP64) {
+        // launches of at most 256 tiles (the region bound's probes at coarse levels) run
+        // sixteen waves per tile: a quarter of the per-tile latency, one tile per CU
+        if (t.n_points * t.group <= 256 * 16) {
+            if (grad) return launch_t<P64, 16, 4, 16>(M, t, s, M.A64, nullptr);
+            return launch_t<P64, 16, 1, 16>(M, t, s, M.A64, nullptr);
+        }
         if (grad) return launch_t<P64, 16, 4>(M, t, s, M.A64, nullptr);
         return launch_t<P64, 16, 1>(M, t, s, M.A64, nullptr);
     }
