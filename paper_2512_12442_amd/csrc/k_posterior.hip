@@ -743,9 +743,9 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
     // Tile widths keep B at <= 80 KB of LDS (m_pad <= 1024 / 1152), so two work-groups share
     // a CU and one's B generation (VALU) overlaps the other's MFMA sweep.
     if (prec == LCP_FP64) {
-        // launches of at most 256 tiles (the region bound's probes at coarse levels) run
+        // launches of at most 2048 tiles (the region bound's probes at coarse levels) run
         // sixteen waves per tile: a quarter of the per-tile latency, one tile per CU
-        if (t.n_points * t.group <= 256 * 16) {
+        if (t.n_points * t.group <= 2048 * 16) {
             if (grad) return launch_t<P64, 16, 4, 16>(M, t, s, M.A64, nullptr);
             return launch_t<P64, 16, 1, 16>(M, t, s, M.A64, nullptr);
         }
