@@ -78,6 +78,57 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(f"# copy calibration: {reps} copies of {nbytes} bytes", file=sys.stderr, flush=True)
 
 
+def run_local_blocks(args):
+    """Batched local GP models (256 blocks, m ~ U{64..1024}, grids 16^3..64^3, SE kernels,
+    FP32): one lcp_dense_batch call per step, all posterior GEMMs in one launch."""
+    import torch
+    import paper_2512_12442_amd as lcp
+    import workloads
+    dev = torch.device("cuda:0")
+    prec = args.prec if args.prec != "f16x3" or args.batch_prec_given else "fp32"
+    Ws = workloads.local_blocks(args.seed, nblocks=args.blocks)
+    grids = [lcp.grid_of(W) for W in Ws]
+    thetas = [W.theta for W in Ws]
+    zb = torch.as_tensor(Ws[0].zbank, device=dev)
+    nvert = sum(W.n_vertices for W in Ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = lcp.GPModelBatch.from_workloads(Ws, dev)
+    torch.cuda.synchronize()
+    fit_ms = (time.perf_counter() - t0) * 1e3
+    print(f"# batched fit of {len(Ws)} models: {fit_ms:.1f} ms", file=sys.stderr, flush=True)
+    out, ws = B.lcp_dense(grids, thetas, zb, prec)
+    with lcp.StageTimer() as st_all:
+        for _ in range(max(args.warmup, 1)):
+            B.lcp_dense(grids, thetas, zb, prec, out=out, ws=ws)
+    stage_ms = {k: v / max(args.warmup, 1) for k, v in st_all.ms.items()}
+    torch.cuda.synchronize()
+    with lcp.StageTimer(["posterior"]) as st:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            B.lcp_dense(grids, thetas, zb, prec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    flops = sum(W.n_vertices * W.m * (W.m + 1) for W in Ws)
+    dur = st.ms["posterior"] / max(st.launches["posterior"], 1)
+    peak = {"fp32": PEAK["fp32_mfma"], "fp64": PEAK["fp64_mfma"]}.get(prec, PEAK["fp16_mfma"])
+    line = {
+        "metric": "batched local GP LCP grid pts/s (256 uneven blocks, dense)", "value": nvert / (step_ms * 1e-3),
+        "unit": "grid pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32+f64"}.get(prec, prec),
+        "data": "synthetic",
+        "config": {"workload": f"{len(Ws)} local SE GP blocks, m~U{{64..1024}}, cubic grids 16^3..64^3, "
+                               f"l~U[0.05,0.2], s2=1, noise 1e-4, theta=median per block, N_s=1600",
+                   "blocks": len(Ws), "vertices": nvert, "m_total": sum(W.m for W in Ws), "precision": prec,
+                   "parallelism": "1 GPU"},
+        "fit_ms": fit_ms, "stage_ms": stage_ms,
+        "roofline": {"bound": "mfma", "kernel": "k_post_batch (all blocks' posterior GEMMs, one launch)",
+                     "achieved": flops / (dur * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / (dur * 1e-3) / peak, "traffic": None, "avg_launch_ms": dur},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +144,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for rocprofv3 traffic counters)")
     ap.add_argument("--print-source-hash", action="store_true", help="print the posterior kernel source hash")
+    ap.add_argument("--workload", default="trig128", choices=["trig128", "local_blocks"],
+                    help="trig128: the headline adaptive LCP; local_blocks: batched local GP models")
+    ap.add_argument("--blocks", type=int, default=256, help="number of models for --workload local_blocks")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
@@ -101,6 +155,10 @@ def main():
 
     if args.print_source_hash:
         print(source_hash())
+        return
+    if args.workload == "local_blocks":
+        args.batch_prec_given = "--prec" in sys.argv
+        run_local_blocks(args)
         return
     import numpy as np
     import torch

@@ -162,6 +162,46 @@ int lcp_adaptive(const lcp_model* model, const lcp_grid* grid, double theta, con
                  uint8_t* level_field, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batches of independent models (local GP models of subdomains, each with its own
+ * observations, kernel and grid, as the local models M' of Sec. 4.1 generalise): every
+ * model's Cholesky factor runs in one launch (a work-group each), and the posterior GEMMs
+ * of all models run in one launch that walks the batch's tiles, so small models share the
+ * GPU with large ones.
+ *
+ * lcp_batch_model_bytes -- device memory for nb models with m[b] observations (host array);
+ *   0 if nb < 1 or some m[b] is outside 1..1024.
+ *
+ * gp_fit_factor_batch -- gp_fit_factor for each model of the batch.
+ *   k, m     (host) nb kernel descriptions (same dim) and observation counts
+ *   X, y     (device) the models' observations concatenated in model order: model b's
+ *            m[b] x dim rows of X (and m[b] values of y) follow model b - 1's
+ *   model_mem, model_bytes   caller-owned device memory of >= lcp_batch_model_bytes bytes,
+ *            256-byte aligned, alive as long as the handle
+ *   out      (host) receives the batch handle; free it with gp_model_batch_free
+ * Synchronises `stream` once.  LCP_ENOTPD if any model's K + noise I is numerically
+ * singular (lcp_last_error names the first).  The posterior at the observations that
+ * lcp_adaptive uses is not computed: a batch serves lcp_dense_batch.
+ */
+typedef struct lcp_model_batch lcp_model_batch;   /* opaque host handle */
+
+size_t lcp_batch_model_bytes(int nb, const int* m, int dim);
+int gp_fit_factor_batch(int nb, const lcp_kernel* k, const int* m, const double* X, const double* y,
+                        void* model_mem, size_t model_bytes, void* stream, lcp_model_batch** out);
+void gp_model_batch_free(lcp_model_batch* batch);
+
+/*
+ * lcp_dense_batch -- lcp_dense for every model of the batch on its own grid (grids[b],
+ * host array) and iso-value (theta[b], host array), with one shared z-bank.
+ *   lcp   the models' cell fields concatenated in model order (each x fastest, binary32)
+ * The workspace size comes from lcp_dense_batch_workspace.  Synchronises `stream` once
+ * (upload of the per-model descriptors).
+ */
+int lcp_dense_batch_workspace(const lcp_model_batch* batch, const lcp_grid* grids, int prec, int n_samples,
+                              size_t* bytes);
+int lcp_dense_batch(const lcp_model_batch* batch, const lcp_grid* grids, const double* theta, const lcp_mc* mc,
+                    int prec, float* lcp, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * lcp_backward -- adjoint of the LCP field with respect to the observation values and
  * log-lengthscales.  Not provided by this build: the Monte Carlo estimator of Sec. 4 is
  * piecewise constant in its inputs.  Always returns LCP_ENOTSUPPORTED.

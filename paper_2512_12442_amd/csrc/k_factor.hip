@@ -1,6 +1,8 @@
 // Model factorisation on the GPU (binary64): K = k(X, X) + noise I, its Cholesky factor,
 // the explicit inverse L^-1 in the MFMA fragment orders used by the posterior kernel,
 // and a = K^-1 y.  Sec. 3 of the paper with the inducing set equal to the observations.
+#include <vector>
+
 #include "lcp_internal.h"
 
 namespace lcp {
@@ -50,8 +52,8 @@ __global__ void k_build_K(KParams kp, const double* __restrict__ Xp, int m, int 
 // Left-looking Cholesky of the leading m x m block of K (row-major, leading dim mp), in
 // place: on exit row j of the array holds row j of U = L^T (U[j][i] = L[i][j], i >= j).
 // One work-group; thread i owns column i's running diagonal d_i = K_ii - sum_k U[k][i]^2.
-__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ U, int m, int mp, double piv_min,
-                                                   int* __restrict__ info)
+__device__ __forceinline__ void cholesky_body(double* __restrict__ U, int m, int mp, double piv_min,
+                                              int* __restrict__ info)
 {
     __shared__ double d[kMaxM];
     __shared__ double ucol[kMaxM];
@@ -86,9 +88,15 @@ __global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ U, int m
     }
 }
 
+__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ U, int m, int mp, double piv_min,
+                                                   int* __restrict__ info)
+{
+    cholesky_body(U, m, mp, piv_min, info);
+}
+
 // Explicit inverse of L = U^T row by row: Linv[i][c] = -(sum_{k=c}^{i-1} L[i][k] Linv[k][c]) / L[i][i].
-__global__ void __launch_bounds__(1024) k_trinv(const double* __restrict__ U, double* __restrict__ Li, int m,
-                                                int mp, double* __restrict__ amax)
+__device__ __forceinline__ void trinv_body(const double* __restrict__ U, double* __restrict__ Li, int m, int mp,
+                                           double* __restrict__ amax)
 {
     __shared__ double lrow[kMaxM];
     __shared__ double wmax[16];
@@ -126,9 +134,15 @@ __global__ void __launch_bounds__(1024) k_trinv(const double* __restrict__ U, do
     }
 }
 
+__global__ void __launch_bounds__(1024) k_trinv(const double* __restrict__ U, double* __restrict__ Li, int m,
+                                                int mp, double* __restrict__ amax)
+{
+    trinv_body(U, Li, m, mp, amax);
+}
+
 // a = Linv^T (Linv y): w = Linv y, then a_i = sum_{k >= i} Linv[k][i] w_k.
-__global__ void __launch_bounds__(1024) k_alpha(const double* __restrict__ Li, const double* __restrict__ y,
-                                                double* __restrict__ a, int m, int mp)
+__device__ __forceinline__ void alpha_body(const double* __restrict__ Li, const double* __restrict__ y,
+                                           double* __restrict__ a, int m, int mp)
 {
     __shared__ double w[kMaxM];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -144,6 +158,45 @@ __global__ void __launch_bounds__(1024) k_alpha(const double* __restrict__ Li, c
             for (int k = i; k < m; ++k) s = fma(Li[(int64_t)k * mp + i], w[k], s);
         a[i] = s;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_alpha(const double* __restrict__ Li, const double* __restrict__ y,
+                                                double* __restrict__ a, int m, int mp)
+{
+    alpha_body(Li, y, a, m, mp);
+}
+
+// One work-group per model of a batch.
+struct FactorDesc {
+    double* U;
+    double* Linv;
+    double* a;
+    const double* y;
+    double* amax;
+    int* info;
+    double piv_min;
+    int m, mp;
+};
+
+__global__ void __launch_bounds__(1024) k_cholesky_batch(const FactorDesc* __restrict__ D)
+{
+    const FactorDesc& d = D[blockIdx.x];
+    cholesky_body(d.U, d.m, d.mp, d.piv_min, d.info);
+}
+
+__global__ void k_gather_info(const FactorDesc* __restrict__ D, int nb, int* __restrict__ out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) out[b] = *D[b].info;
+}
+
+__global__ void __launch_bounds__(1024) k_trinv_alpha_batch(const FactorDesc* __restrict__ D)
+{
+    const FactorDesc& d = D[blockIdx.x];
+    if (*d.info != 0) return;
+    trinv_body(d.U, d.Linv, d.m, d.mp, d.amax);
+    __syncthreads();
+    alpha_body(d.Linv, d.y, d.a, d.m, d.mp);
 }
 
 // Fragment orders of Linv.
@@ -248,6 +301,55 @@ hipError_t launch_factor_finish(Model& M, hipStream_t s)
     t.mean = M.obs_mu;
     t.var = M.obs_var;
     return launch_posterior(M, LCP_FP64, t, s);
+}
+
+size_t factor_batch_scratch(int nb)
+{
+    return align256(sizeof(FactorDesc) * (size_t)nb) + align256(sizeof(int) * (size_t)nb);
+}
+
+// Batched factorisation, part 1: pack and build K per model, then every model's Cholesky in
+// one launch (a work-group each); the statuses land in info_dev[b] (0 = positive definite).
+// X[b], y[b] are the models' device inputs; scratch holds factor_batch_scratch(nb) bytes.
+hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
+                               int* info_dev, hipStream_t s)
+{
+    StageScope sc(s, ST_FACTOR);
+    std::vector<FactorDesc> D(nb);
+    for (int b = 0; b < nb; ++b) {
+        Model& M = *Ms[b];
+        carve(M, (char*)M.X);
+        const int mp = M.m_pad;
+        double* w = ybuf(M);
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, X[b], y[b], M.m, mp, M.dim,
+                           M.X, w);
+        const int64_t n2 = (int64_t)mp * mp;
+        hipLaunchKernelGGL(k_build_K, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.kp, M.X, M.m, mp,
+                           M.k.noise_var, M.U);
+        D[b] = FactorDesc{M.U, M.Linv, M.a, w, M.amax, M.info,
+                          (double)M.m * 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var), M.m, mp};
+    }
+    FactorDesc* Dd = (FactorDesc*)scratch;
+    hipError_t e = hipMemcpyAsync(Dd, D.data(), sizeof(FactorDesc) * nb, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cholesky_batch, dim3(nb), dim3(1024), 0, s, Dd);
+    hipLaunchKernelGGL(k_gather_info, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, s, Dd, nb, info_dev);
+    return hipGetLastError();
+}
+
+// Part 2 (statuses read): inverse and a for every model in one launch, then the fragment
+// orders per model.  The observation posteriors are not computed (dense use only).
+hipError_t launch_factor_batch_finish(Model* const* Ms, int nb, char* scratch, hipStream_t s)
+{
+    StageScope sc(s, ST_FACTOR);
+    hipLaunchKernelGGL(k_trinv_alpha_batch, dim3(nb), dim3(1024), 0, s, (const FactorDesc*)scratch);
+    for (int b = 0; b < nb; ++b) {
+        Model& M = *Ms[b];
+        const int64_t n2 = (int64_t)M.m_pad * M.m_pad;
+        hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, M.m_pad, M.A64, M.A32,
+                           M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace lcp

@@ -12,6 +12,8 @@
 // Row blocks of 16 are dealt to the four waves in a balanced (snake) order; every column's
 // result depends only on that column, so a vertex gets bitwise the same numbers whatever
 // tile or launch it is computed in.
+#include <vector>
+
 #include "lcp_internal.h"
 
 namespace lcp {
@@ -106,8 +108,9 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Tiles t_first, t_first + t_stride, ... (below t_limit and the column count) of one model.
 template <class P, int NT, int G, int NW>
-__global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
+__device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int64_t t_stride, int64_t t_limit)
 {
     constexpr int kThreads = NW * 64;
     constexpr int kWaves = NW;
@@ -125,7 +128,8 @@ __global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
     int64_t npts = T.count ? *T.count : T.n_points;
     if (npts > T.n_points) npts = T.n_points;
     const int64_t ncols = npts * G;
-    const int64_t ntiles = (ncols + NT - 1) / NT;
+    int64_t ntiles = (ncols + NT - 1) / NT;
+    if (ntiles > t_limit) ntiles = t_limit;
     const int dim = A.kp.dim;
 
     // B generation layout: thread t serves point pc = t % NP of the tile (NP = NT / G points)
@@ -138,7 +142,7 @@ __global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
     const int pc = tid % NP, jg = tid / NP;
     const double ie0 = A.kp.inv_ell[0], ie1 = A.kp.inv_ell[1], ie2 = A.kp.inv_ell[2];
 
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = t_first; tile < ntiles; tile += t_stride) {
         const int64_t col0 = tile * NT;
         __syncthreads();   // previous tile fully consumed
         // ---- this thread's point
@@ -456,6 +460,31 @@ __global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
     }
 }
 
+template <class P, int NT, int G, int NW>
+__global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
+{
+    post_tiles<P, NT, G, NW>(A, blockIdx.x, gridDim.x, INT64_MAX);
+}
+
+// Many models in one launch: model b owns tiles tile_off[b] .. tile_off[b + 1] - 1 of the
+// batch; work-groups walk the batch's tiles, so small models share the GPU with large ones.
+template <class P, int NT, int NW>
+__global__ void __launch_bounds__(NW * 64) k_post_batch(const KArgs* __restrict__ As,
+                                                        const int64_t* __restrict__ tile_off, int nb)
+{
+    const int64_t total = tile_off[nb];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        int lo = 0, hi = nb - 1;                // last b with tile_off[b] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_off[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t t = item - tile_off[lo];
+        post_tiles<P, NT, 1, NW>(As[lo], t, 1, t + 1);
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // k-outer form for value columns (G = 1) with 16-bit split operands.  A work-group of
 // eight waves owns NT columns and keeps every 16-row block of V for them in registers:
@@ -700,8 +729,7 @@ hipError_t launch_ko_split(const Model& M, const PostTask& t, hipStream_t s, con
     }
 }
 
-template <class P, int NT, int G, int NW = kWaves>
-hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
+static KArgs kargs_of(const Model& M, const PostTask& t, const void* A0, const void* A1)
 {
     KArgs A;
     A.kp = M.kp;
@@ -719,6 +747,13 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
         A.sB = ldexp(1.0, 15 - e);          // k* <= s2, so sB * k* < 2^15
     }
     A.t = t;
+    return A;
+}
+
+template <class P, int NT, int G, int NW = kWaves>
+hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
+{
+    KArgs A = kargs_of(M, t, A0, A1);
     int ldb = (P::KS == 32) ? (M.m_pad + 63) / 64 * 64 + P::LPAD : M.m_pad + P::LPAD;
     size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (NW * 64 * G + NT);
     hipError_t e = hipFuncSetAttribute((const void*)k_post<P, NT, G, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -734,6 +769,59 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
 }
 
 }  // namespace
+
+template <class P, int NT>
+static hipError_t launch_batch_t(const Model* const* Ms, const PostTask* tasks, int nb, char* scratch, hipStream_t s,
+                          const void* const* A0, const void* const* A1)
+{
+    std::vector<KArgs> KA(nb);
+    std::vector<int64_t> toff(nb + 1, 0);
+    int mpmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        KA[b] = kargs_of(*Ms[b], tasks[b], A0[b], A1[b]);
+        toff[b + 1] = toff[b] + (tasks[b].n_points + NT - 1) / NT;
+        if (Ms[b]->m_pad > mpmax) mpmax = Ms[b]->m_pad;
+    }
+    KArgs* KAd = (KArgs*)scratch;
+    int64_t* toffd = (int64_t*)(scratch + align256(sizeof(KArgs) * (size_t)nb));
+    hipError_t e = hipMemcpyAsync(KAd, KA.data(), sizeof(KArgs) * nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(toffd, toff.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s);
+    // pageable sources: wait for the copies so the host vectors may go
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (toff[nb] == 0) return hipSuccess;
+    const int ldb = (P::KS == 32) ? (mpmax + 63) / 64 * 64 + P::LPAD : mpmax + P::LPAD;
+    const size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (kThreads + NT);
+    e = hipFuncSetAttribute((const void*)k_post_batch<P, NT, kWaves>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t grid = toff[nb] < 256 * 8 ? toff[nb] : 256 * 8;
+    hipLaunchKernelGGL((k_post_batch<P, NT, kWaves>), dim3((unsigned)grid), dim3(kThreads), lds, s, KAd, toffd, nb);
+    return hipGetLastError();
+}
+
+size_t posterior_batch_scratch(int nb)
+{
+    return align256(sizeof(KArgs) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1));
+}
+
+hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks, int nb, int prec, char* scratch,
+                                  hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    StageScope sc(s, ST_POSTERIOR);
+    std::vector<const void*> A0(nb), A1(nb);
+    for (int b = 0; b < nb; ++b) {
+        const Model& M = *Ms[b];
+        A0[b] = prec == LCP_FP64 ? (const void*)M.A64 : prec == LCP_FP32 ? (const void*)M.A32
+              : prec == LCP_MIXED_F16X3 ? (const void*)M.Hhi : (const void*)M.Ahi;
+        A1[b] = prec == LCP_MIXED_F16X3 ? (const void*)M.Hlo : prec == LCP_MIXED_BF16X3 ? (const void*)M.Alo : nullptr;
+    }
+    if (prec == LCP_FP64) return launch_batch_t<P64, 16>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
+    if (prec == LCP_FP32) return launch_batch_t<P32, 32>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
+    if (prec == LCP_MIXED_F16X3) return launch_batch_t<PH3, 32>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
+    return launch_batch_t<PB3, 32>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
+}
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s)
 {

@@ -6,10 +6,16 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "lcp_internal.h"
 
 struct lcp_model : lcp::Model {};
+
+struct lcp_model_batch {
+    std::vector<lcp_model> models;
+    char* scratch;            // factor descriptors and statuses (end of the model memory)
+};
 
 using namespace lcp;
 
@@ -46,6 +52,34 @@ int check_prec(int prec)
     if (prec != LCP_FP64 && prec != LCP_FP32 && prec != LCP_MIXED_BF16X3 && prec != LCP_MIXED_F16X3)
         return fail(LCP_EINVAL, "unknown precision %d", prec);
     return LCP_OK;
+}
+
+int check_kernel(const lcp_kernel* k, int m)
+{
+    if (k->dim != 2 && k->dim != 3) return fail(LCP_EINVAL, "dim must be 2 or 3 (got %d)", k->dim);
+    if (k->kind != LCP_KERNEL_SE && k->kind != LCP_KERNEL_MATERN52) return fail(LCP_EINVAL, "unknown kernel %d", k->kind);
+    if (!(k->signal_var > 0.0) || !is_finite(k->signal_var)) return fail(LCP_EINVAL, "signal_var must be finite and > 0");
+    if (!(k->noise_var >= 0.0) || !is_finite(k->noise_var)) return fail(LCP_EINVAL, "noise_var must be finite and >= 0");
+    for (int d = 0; d < k->dim; ++d)
+        if (!(k->lengthscale[d] > 0.0) || !is_finite(k->lengthscale[d]))
+            return fail(LCP_EINVAL, "lengthscale[%d] must be finite and > 0", d);
+    if (m < 1 || m > kMaxM) return fail(LCP_EINVAL, "m = %d outside 1..%d", m, kMaxM);
+    return LCP_OK;
+}
+
+void init_model(Model& M, const lcp_kernel& k, int m, void* mem)
+{
+    M.k = k;
+    M.dim = k.dim;
+    M.m = m;
+    M.m_pad = (m + 127) / 128 * 128;
+    M.nrb = (m + 15) / 16;
+    M.kp.kind = k.kind;
+    M.kp.dim = k.dim;
+    M.kp.s2 = k.signal_var;
+    for (int d = 0; d < 3; ++d) M.kp.inv_ell[d] = d < k.dim ? 1.0 / k.lengthscale[d] : 0.0;
+    M.X = (double*)mem;
+    if (hipGetDevice(&M.device) != hipSuccess) M.device = -1;
 }
 
 int check_grid(const lcp_model* M, const lcp_grid* g, GridP* out)
@@ -160,30 +194,13 @@ int gp_fit_factor(const lcp_kernel* k, int m, const double* X, const double* y, 
 {
     if (!k || !out) return fail(LCP_EINVAL, "kernel and out must not be NULL");
     *out = nullptr;
-    if (k->dim != 2 && k->dim != 3) return fail(LCP_EINVAL, "dim must be 2 or 3 (got %d)", k->dim);
-    if (k->kind != LCP_KERNEL_SE && k->kind != LCP_KERNEL_MATERN52) return fail(LCP_EINVAL, "unknown kernel %d", k->kind);
-    if (!(k->signal_var > 0.0) || !is_finite(k->signal_var)) return fail(LCP_EINVAL, "signal_var must be finite and > 0");
-    if (!(k->noise_var >= 0.0) || !is_finite(k->noise_var)) return fail(LCP_EINVAL, "noise_var must be finite and >= 0");
-    for (int d = 0; d < k->dim; ++d)
-        if (!(k->lengthscale[d] > 0.0) || !is_finite(k->lengthscale[d]))
-            return fail(LCP_EINVAL, "lengthscale[%d] must be finite and > 0", d);
-    if (m < 1 || m > kMaxM) return fail(LCP_EINVAL, "m = %d outside 1..%d", m, kMaxM);
+    if (int r = check_kernel(k, m)) return r;
     if (!X || !y || !model_mem) return fail(LCP_EINVAL, "X, y and model_mem must not be NULL");
     if (!aligned256(model_mem)) return fail(LCP_EINVAL, "model_mem must be 256-byte aligned");
     if (model_bytes_ < model_bytes(m)) return fail(LCP_ENOMEM, "model memory %zu < %zu bytes", model_bytes_, model_bytes(m));
     lcp_model* M = new (std::nothrow) lcp_model();
     if (!M) return fail(LCP_ENOMEM, "host allocation failed");
-    M->k = *k;
-    M->dim = k->dim;
-    M->m = m;
-    M->m_pad = (m + 127) / 128 * 128;
-    M->nrb = (m + 15) / 16;
-    M->kp.kind = k->kind;
-    M->kp.dim = k->dim;
-    M->kp.s2 = k->signal_var;
-    for (int d = 0; d < 3; ++d) M->kp.inv_ell[d] = d < k->dim ? 1.0 / k->lengthscale[d] : 0.0;
-    M->X = (double*)model_mem;
-    if (hipGetDevice(&M->device) != hipSuccess) M->device = -1;
+    init_model(*M, *k, m, model_mem);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_factor(*M, X, y, s);
     if (e != hipSuccess) { delete M; return dev_fail(e, "factor"); }
@@ -265,6 +282,90 @@ int gp_posterior(const lcp_model* M, int64_t n, const double* Xq, int prec, doub
     return ok();
 }
 
+namespace {
+
+// Workspace of one dense evaluation (layout of dense_ws).
+struct DenseWs {
+    double* mean;
+    double* var;
+    void* V;
+    double* cross;
+    float* zb32;
+    int32_t* work;
+    int64_t* wcount;
+    double* zmax;
+};
+
+DenseWs carve_dense(const lcp_model* M, const GridP& g, int prec, int ns, char* p)
+{
+    DenseWs w;
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    const size_t vb = prec == LCP_FP64 ? 8 : 4;
+    w.mean = (double*)p;
+    p += align256(sizeof(double) * nv);
+    w.var = (double*)p;
+    p += align256(sizeof(double) * nv);
+    w.V = p;
+    p += align256(vb * (size_t)nv * M->m_pad);
+    w.cross = (double*)p;
+    p += align256(sizeof(double) * (size_t)nv * ndir(g.dim));
+    w.zb32 = (float*)p;
+    p += align256(sizeof(float) * (size_t)ns * (1 << g.dim));
+    const int64_t ncells = g.nc[0] * g.nc[1] * g.nc[2];
+    w.work = (int32_t*)p;
+    p += align256(4 * (size_t)ncells);
+    w.wcount = (int64_t*)p;
+    w.zmax = (double*)(p + 64);
+    return w;
+}
+
+PostTask dense_task(const GridP& g, const DenseWs& w)
+{
+    PostTask t{};
+    t.mode = COL_GRID;
+    t.group = 1;
+    t.count = nullptr;
+    t.n_points = g.n[0] * g.n[1] * g.n[2];
+    t.grid = g;
+    t.vlist = nullptr;
+    t.mean = w.mean;
+    t.var = w.var;
+    t.V = w.V;
+    t.stage = ST_POSTERIOR;
+    return t;
+}
+
+// Cross-covariances and cell Monte Carlo of a dense evaluation whose posterior (mean, var, V)
+// is in w; zb32 is the FP32 z-bank (unused for binary64).
+int dense_cells(const lcp_model* M, const GridP& g, double theta, const lcp_mc* mc, int prec, const DenseWs& w,
+                const float* zb32, float* lcp, hipStream_t s)
+{
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    hipError_t e = launch_cross(*M, prec, g, nullptr, nullptr, nv, nullptr, w.V, w.cross, s);
+    if (e != hipSuccess) return dev_fail(e, "cross");
+    CellTask ct{};
+    ct.grid = g;
+    ct.prec = prec;
+    ct.theta = theta;
+    ct.ns = mc->n_samples;
+    ct.zb64 = mc->zbank;
+    ct.zb32 = zb32;
+    ct.mean = w.mean;
+    ct.var = w.var;
+    ct.cross = w.cross;
+    ct.slot = nullptr;
+    ct.leaves = nullptr;
+    ct.lcp = lcp;
+    ct.work = w.work;
+    ct.wcount = w.wcount;
+    ct.zmax = w.zmax;
+    e = launch_cells(ct, g.nc[0] * g.nc[1] * g.nc[2], s);
+    if (e != hipSuccess) return dev_fail(e, "cells");
+    return LCP_OK;
+}
+
+}  // namespace
+
 int lcp_dense(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec, float* lcp, void* ws,
               size_t ws_bytes, void* stream)
 {
@@ -279,62 +380,15 @@ int lcp_dense(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_
     const size_t need = dense_ws(M, g, prec, mc->n_samples);
     if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
-    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
-    const size_t vb = prec == LCP_FP64 ? 8 : 4;
-    char* p = (char*)ws;
-    double* mean = (double*)p;
-    p += align256(sizeof(double) * nv);
-    double* var = (double*)p;
-    p += align256(sizeof(double) * nv);
-    void* V = p;
-    p += align256(vb * (size_t)nv * M->m_pad);
-    double* cross = (double*)p;
-    p += align256(sizeof(double) * (size_t)nv * ndir(g.dim));
-    float* zb32 = (float*)p;
-    p += align256(sizeof(float) * (size_t)mc->n_samples * (1 << g.dim));
-    const int64_t ncells = g.nc[0] * g.nc[1] * g.nc[2];
-    int32_t* work = (int32_t*)p;
-    p += align256(4 * (size_t)ncells);
-    int64_t* wcount = (int64_t*)p;
-    double* zmax = (double*)(p + 64);
+    const DenseWs w = carve_dense(M, g, prec, mc->n_samples, (char*)ws);
     hipError_t e;
     if (prec != LCP_FP64) {
-        e = launch_zbank32(mc->zbank, zb32, (int64_t)mc->n_samples << g.dim, s);
+        e = launch_zbank32(mc->zbank, w.zb32, (int64_t)mc->n_samples << g.dim, s);
         if (e != hipSuccess) return dev_fail(e, "z-bank");
     }
-    PostTask t{};
-    t.mode = COL_GRID;
-    t.group = 1;
-    t.count = nullptr;
-    t.n_points = nv;
-    t.grid = g;
-    t.vlist = nullptr;
-    t.mean = mean;
-    t.var = var;
-    t.V = V;
-    t.stage = ST_POSTERIOR;
-    e = launch_posterior(*M, prec, t, s);
+    e = launch_posterior(*M, prec, dense_task(g, w), s);
     if (e != hipSuccess) return dev_fail(e, "posterior");
-    e = launch_cross(*M, prec, g, nullptr, nullptr, nv, nullptr, V, cross, s);
-    if (e != hipSuccess) return dev_fail(e, "cross");
-    CellTask ct{};
-    ct.grid = g;
-    ct.prec = prec;
-    ct.theta = theta;
-    ct.ns = mc->n_samples;
-    ct.zb64 = mc->zbank;
-    ct.zb32 = zb32;
-    ct.mean = mean;
-    ct.var = var;
-    ct.cross = cross;
-    ct.slot = nullptr;
-    ct.leaves = nullptr;
-    ct.lcp = lcp;
-    ct.work = work;
-    ct.wcount = wcount;
-    ct.zmax = zmax;
-    e = launch_cells(ct, ncells, s);
-    if (e != hipSuccess) return dev_fail(e, "cells");
+    if (int r = dense_cells(M, g, theta, mc, prec, w, w.zb32, lcp, s)) return r;
     return ok();
 }
 
@@ -373,3 +427,165 @@ int lcp_backward(const lcp_model* M, const lcp_grid* grid, double theta, const l
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- batches of models
+
+namespace {
+
+size_t batch_model_layout(int nb, const int* m, std::vector<size_t>* off)
+{
+    size_t o = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (off) off->push_back(o);
+        o += align256(model_bytes(m[b]));
+    }
+    return o + align256(factor_batch_scratch(nb));
+}
+
+}  // namespace
+
+size_t lcp_batch_model_bytes(int nb, const int* m, int dim)
+{
+    (void)dim;
+    if (nb < 1 || !m) return 0;
+    for (int b = 0; b < nb; ++b)
+        if (m[b] < 1 || m[b] > kMaxM) return 0;
+    return batch_model_layout(nb, m, nullptr);
+}
+
+int gp_fit_factor_batch(int nb, const lcp_kernel* k, const int* m, const double* X, const double* y, void* model_mem,
+                        size_t model_bytes_, void* stream, lcp_model_batch** out)
+{
+    if (!k || !m || !out) return fail(LCP_EINVAL, "k, m and out must not be NULL");
+    *out = nullptr;
+    if (nb < 1) return fail(LCP_EINVAL, "nb = %d < 1", nb);
+    for (int b = 0; b < nb; ++b) {
+        if (int r = check_kernel(&k[b], m[b])) {
+            char msg[512];
+            snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(r, "model %d: %s", b, msg);
+        }
+        if (k[b].dim != k[0].dim) return fail(LCP_EINVAL, "model %d: dim %d differs from model 0", b, k[b].dim);
+    }
+    if (!X || !y || !model_mem) return fail(LCP_EINVAL, "X, y and model_mem must not be NULL");
+    if (!aligned256(model_mem)) return fail(LCP_EINVAL, "model_mem must be 256-byte aligned");
+    std::vector<size_t> off;
+    const size_t need = batch_model_layout(nb, m, &off);
+    if (model_bytes_ < need) return fail(LCP_ENOMEM, "model memory %zu < %zu bytes", model_bytes_, need);
+    lcp_model_batch* B = new (std::nothrow) lcp_model_batch();
+    if (!B) return fail(LCP_ENOMEM, "host allocation failed");
+    B->models.resize(nb);
+    B->scratch = (char*)model_mem + need - align256(factor_batch_scratch(nb));
+    std::vector<Model*> Ms(nb);
+    std::vector<const double*> Xb(nb), yb(nb);
+    int64_t mo = 0;
+    const int dim = k[0].dim;
+    for (int b = 0; b < nb; ++b) {
+        init_model(B->models[b], k[b], m[b], (char*)model_mem + off[b]);
+        Ms[b] = &B->models[b];
+        Xb[b] = X + mo * dim;
+        yb[b] = y + mo;
+        mo += m[b];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int* info_dev = (int*)(B->scratch + align256(factor_batch_scratch(nb)) - align256(sizeof(int) * (size_t)nb));
+    hipError_t e = launch_factor_batch(Ms.data(), nb, Xb.data(), yb.data(), B->scratch, info_dev, s);
+    std::vector<int> info(nb, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(info.data(), info_dev, sizeof(int) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { delete B; return dev_fail(e, "batched factor"); }
+    for (int b = 0; b < nb; ++b)
+        if (info[b] != 0) {
+            delete B;
+            return fail(LCP_ENOTPD, "model %d: Cholesky pivot %d is not above m * eps * max K_ii", b, info[b]);
+        }
+    e = launch_factor_batch_finish(Ms.data(), nb, B->scratch, s);
+    if (e != hipSuccess) { delete B; return dev_fail(e, "batched factor finish"); }
+    *out = B;
+    return ok();
+}
+
+void gp_model_batch_free(lcp_model_batch* batch) { delete batch; }
+
+namespace {
+
+int batch_grids(const lcp_model_batch* B, const lcp_grid* grids, std::vector<GridP>* gs)
+{
+    if (!B) return fail(LCP_EINVAL, "batch is NULL");
+    if (!grids) return fail(LCP_EINVAL, "grids is NULL");
+    const int nb = (int)B->models.size();
+    gs->resize(nb);
+    for (int b = 0; b < nb; ++b)
+        if (int r = check_grid(&B->models[b], &grids[b], &(*gs)[b])) {
+            char msg[512];
+            snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(r, "grid %d: %s", b, msg);
+        }
+    return LCP_OK;
+}
+
+size_t batch_dense_ws(const lcp_model_batch* B, const std::vector<GridP>& gs, int prec, int ns,
+                      std::vector<size_t>* off)
+{
+    size_t o = 0;
+    for (size_t b = 0; b < gs.size(); ++b) {
+        if (off) off->push_back(o);
+        o += dense_ws(&B->models[b], gs[b], prec, ns);
+    }
+    return o + align256(posterior_batch_scratch((int)gs.size()));
+}
+
+}  // namespace
+
+int lcp_dense_batch_workspace(const lcp_model_batch* B, const lcp_grid* grids, int prec, int n_samples, size_t* bytes)
+{
+    if (!bytes) return fail(LCP_EINVAL, "bytes must not be NULL");
+    if (check_prec(prec)) return LCP_EINVAL;
+    if (n_samples < 1) return fail(LCP_EINVAL, "n_samples must be >= 1");
+    std::vector<GridP> gs;
+    if (int r = batch_grids(B, grids, &gs)) return r;
+    *bytes = batch_dense_ws(B, gs, prec, n_samples, nullptr);
+    return ok();
+}
+
+int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const double* theta, const lcp_mc* mc, int prec,
+                    float* lcp, void* ws, size_t ws_bytes, void* stream)
+{
+    if (check_prec(prec)) return LCP_EINVAL;
+    std::vector<GridP> gs;
+    if (int r = batch_grids(B, grids, &gs)) return r;
+    const int nb = (int)gs.size();
+    if (!theta) return fail(LCP_EINVAL, "theta is NULL");
+    for (int b = 0; b < nb; ++b) {
+        if (int r = check_mc(&B->models[b], mc)) return r;
+        if (!is_finite(theta[b])) return fail(LCP_EINVAL, "theta[%d] must be finite", b);
+    }
+    if (!lcp || !ws) return fail(LCP_EINVAL, "lcp and ws must not be NULL");
+    if (!aligned256(ws)) return fail(LCP_EINVAL, "workspace must be 256-byte aligned");
+    std::vector<size_t> off;
+    const size_t need = batch_dense_ws(B, gs, prec, mc->n_samples, &off);
+    if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<DenseWs> w(nb);
+    std::vector<PostTask> tasks(nb);
+    std::vector<const Model*> Ms(nb);
+    for (int b = 0; b < nb; ++b) {
+        w[b] = carve_dense(&B->models[b], gs[b], prec, mc->n_samples, (char*)ws + off[b]);
+        tasks[b] = dense_task(gs[b], w[b]);
+        Ms[b] = &B->models[b];
+    }
+    hipError_t e;
+    if (prec != LCP_FP64) {
+        e = launch_zbank32(mc->zbank, w[0].zb32, (int64_t)mc->n_samples << gs[0].dim, s);
+        if (e != hipSuccess) return dev_fail(e, "z-bank");
+    }
+    char* pscratch = (char*)ws + need - align256(posterior_batch_scratch(nb));
+    e = launch_posterior_batch(Ms.data(), tasks.data(), nb, prec, pscratch, s);
+    if (e != hipSuccess) return dev_fail(e, "batched posterior");
+    int64_t cell0 = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (int r = dense_cells(&B->models[b], gs[b], theta[b], mc, prec, w[b], w[0].zb32, lcp + cell0, s)) return r;
+        cell0 += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
+    }
+    return ok();
+}

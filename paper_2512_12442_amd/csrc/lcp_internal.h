@@ -239,6 +239,15 @@ struct Model {
 size_t model_bytes(int m);
 hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t s);
 hipError_t launch_factor_finish(Model& M, hipStream_t s);
+size_t factor_batch_scratch(int nb);
+hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
+                               int* info_dev, hipStream_t s);
+hipError_t launch_factor_batch_finish(Model* const* Ms, int nb, char* scratch, hipStream_t s);
+// Value columns of many models in one launch: KArgs-equivalent records built from tasks[b]
+// (COL_GRID or COL_POINTS, no device count) into scratch (posterior_batch_scratch bytes).
+size_t posterior_batch_scratch(int nb);
+hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks, int nb, int prec, char* scratch,
+                                  hipStream_t s);
 
 // ------------------------------------------------------------- octree (K4/K5)
 

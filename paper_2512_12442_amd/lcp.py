@@ -48,7 +48,9 @@ class MC(C.Structure):
 
 EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor", "gp_model_free",
            "lcp_posterior_workspace", "lcp_dense_workspace", "lcp_adaptive_workspace", "gp_posterior",
-           "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end"]
+           "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
+           "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
+           "lcp_dense_batch"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -82,8 +84,16 @@ def lib():
     L.lcp_backward.argtypes = [P, P, C.c_double, P, P, P, P, P, SZ, P]
     L.lcp_profile_begin.argtypes = [C.c_uint]
     L.lcp_profile_end.argtypes = [P, P, C.c_int]
+    L.lcp_batch_model_bytes.restype = SZ
+    L.lcp_batch_model_bytes.argtypes = [C.c_int, P, C.c_int]
+    L.gp_fit_factor_batch.argtypes = [C.c_int, P, P, P, P, P, SZ, P, C.POINTER(P)]
+    L.gp_model_batch_free.argtypes = [P]
+    L.gp_model_batch_free.restype = None
+    L.lcp_dense_batch_workspace.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(SZ)]
+    L.lcp_dense_batch.argtypes = [P, P, P, P, C.c_int, P, P, SZ, P]
     for name in EXPORTS:
-        if name not in ("lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_model_free"):
+        if name not in ("lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_model_free",
+                        "lcp_batch_model_bytes", "gp_model_batch_free"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -257,3 +267,67 @@ def grid_of(W) -> Grid:
 def adapt_of(W, min_leaf=None, bound_at_max_depth=1, steps=4, alpha=None) -> Adapt:
     return Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf), int(bound_at_max_depth),
                  int(steps))
+
+
+class GPModelBatch:
+    """Independent GP models factored together (gp_fit_factor_batch), for lcp_dense_batch."""
+
+    def __init__(self, kernels, Xs, ys, device="cuda"):
+        L = lib()
+        nb = len(kernels)
+        assert nb == len(Xs) == len(ys) and nb > 0
+        dim = kernels[0][1]
+        K = (Kernel * nb)()
+        for b, (kind, kd, s2, ell, noise) in enumerate(kernels):
+            K[b] = Kernel(kind, kd, float(s2), (C.c_double * 3)(*[float(v) for v in list(ell)[:3]]), float(noise))
+        ms = (C.c_int * nb)(*[int(len(y)) for y in ys])
+        X = torch.cat([torch.as_tensor(x, dtype=torch.float64).reshape(-1, dim) for x in Xs]).to(device).contiguous()
+        y = torch.cat([torch.as_tensor(v, dtype=torch.float64).reshape(-1) for v in ys]).to(device).contiguous()
+        nbytes = L.lcp_batch_model_bytes(nb, ms, dim)
+        if nbytes == 0:
+            raise LcpError(LCP_EINVAL, "unsupported batch (each m must be 1..1024)")
+        self.mem = _buffer(nbytes, device)
+        self.device, self.nb, self.dim = torch.device(device), nb, dim
+        self._X, self._y, self._K, self._m = X, y, K, ms
+        h = C.c_void_p()
+        _check(L.gp_fit_factor_batch(nb, C.byref(K), ms, _ptr(X), _ptr(y), _ptr(self.mem), nbytes, _stream(),
+                                     C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gp_model_batch_free(h)
+            self.h = None
+
+    @classmethod
+    def from_workloads(cls, Ws, device="cuda"):
+        return cls([(W.kind, W.dim, W.signal_var, list(W.lengthscale), W.noise_var) for W in Ws],
+                   [W.X for W in Ws], [W.y for W in Ws], device)
+
+    def dense_workspace(self, grids, prec, n_samples):
+        G = (Grid * self.nb)(*grids)
+        b = C.c_size_t()
+        _check(lib().lcp_dense_batch_workspace(self.h, G, _prec(prec), int(n_samples), C.byref(b)))
+        return b.value
+
+    def lcp_dense(self, grids, thetas, zbank: torch.Tensor, prec="fp32", out=None, ws=None):
+        """Cell fields of every model, concatenated in model order."""
+        G = (Grid * self.nb)(*grids)
+        th = (C.c_double * self.nb)(*[float(t) for t in thetas])
+        zbank = zbank.to(torch.float64).contiguous()
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr())
+        nbytes = self.dense_workspace(grids, prec, mc.n_samples)
+        if ws is None or ws.numel() < nbytes:
+            ws = _buffer(nbytes, self.device)
+        ncell = 0
+        for g in grids:
+            c = 1
+            for d in range(g.dim):
+                c *= g.npts[d] - 1
+            ncell += c
+        if out is None:
+            out = torch.empty(ncell, dtype=torch.float32, device=self.device)
+        _check(lib().lcp_dense_batch(self.h, G, th, C.byref(mc), _prec(prec), _ptr(out), _ptr(ws), ws.numel(),
+                                     _stream()))
+        return out, ws

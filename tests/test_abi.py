@@ -75,3 +75,38 @@ def test_null_model_rejected_everywhere():
     assert L.gp_posterior(None, 1, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
     assert L.lcp_dense(None, None, 0.0, None, 0, None, None, 0, None) == lcp.lcp.LCP_EINVAL
     assert L.lcp_adaptive(None, None, 0.0, None, None, 0, None, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+
+
+def _fit_batch(kernels, ms, X=None, y=None, mem=None, nbytes=0):
+    L = lcp.lib()
+    nb = len(kernels)
+    K = (lcp.lcp.Kernel * max(nb, 1))()
+    for b, (kind, dim, s2, ell, noise) in enumerate(kernels):
+        K[b] = lcp.lcp.Kernel(kind, dim, s2, (C.c_double * 3)(*ell), noise)
+    m = (C.c_int * max(nb, 1))(*ms)
+    h = C.c_void_p()
+    rc = L.gp_fit_factor_batch(nb, K, m, X, y, mem, nbytes, None, C.byref(h))
+    return rc, L.lcp_last_error().decode(), h
+
+
+def test_batch_model_bytes_and_validation():
+    L = lcp.lib()
+    ok_k = (0, 3, 1.0, (0.1, 0.1, 0.1), 1e-4)
+    m2 = (C.c_int * 2)(10, 700)
+    assert L.lcp_batch_model_bytes(2, m2, 3) >= L.lcp_model_bytes(10, 3) + L.lcp_model_bytes(700, 3)
+    assert L.lcp_batch_model_bytes(2, (C.c_int * 2)(10, 0), 3) == 0
+    assert L.lcp_batch_model_bytes(0, m2, 3) == 0
+    rc, msg, h = _fit_batch([], [])
+    assert rc == lcp.lcp.LCP_EINVAL and "nb" in msg and not h.value
+    rc, msg, _ = _fit_batch([ok_k, (0, 3, 1.0, (0.1, 0.1, 0.1), -1.0)], [10, 10])
+    assert rc == lcp.lcp.LCP_EINVAL and "model 1" in msg and "noise_var" in msg
+    rc, msg, _ = _fit_batch([ok_k, (0, 2, 1.0, (0.1, 0.1, 0.1), 1e-4)], [10, 10])
+    assert rc == lcp.lcp.LCP_EINVAL and "dim" in msg
+    rc, msg, _ = _fit_batch([ok_k, ok_k], [10, 2000])
+    assert rc == lcp.lcp.LCP_EINVAL and "model 1" in msg
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation fails first
+    rc, msg, _ = _fit_batch([ok_k, ok_k], [10, 10], X=fake, y=fake, mem=fake, nbytes=16)
+    assert rc == lcp.lcp.LCP_ENOMEM and "model memory" in msg
+    b = C.c_size_t()
+    assert L.lcp_dense_batch_workspace(None, None, 0, 1600, C.byref(b)) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_dense_batch(None, None, None, None, 0, None, None, 0, None) == lcp.lcp.LCP_EINVAL

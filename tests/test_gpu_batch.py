@@ -1,0 +1,80 @@
+"""Batches of independent local GP models (gp_fit_factor_batch, lcp_dense_batch) against
+the oracle run model by model: binary64 counts identical, binary32 within the LCP target,
+and each model of a batch bitwise equal to the same model evaluated alone (FP32)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_2512_12442_amd as lcp
+from parity_util import DEV, counts, say, zbank
+
+pytestmark = pytest.mark.gpu
+
+
+def _blocks():
+    """Uneven batch: m from 1 to 700 (1 to 6 MFMA row-block groups), SE and Matern, ARD
+    lengthscales, ragged grids, one shared z-bank."""
+    spec = [(1, (5, 7, 6), workloads.SE), (40, (9, 9, 9), workloads.MATERN52), (129, (12, 8, 5), workloads.SE),
+            (200, (6, 6, 6), workloads.MATERN52), (300, (10, 5, 7), workloads.SE), (513, (7, 7, 7), workloads.SE),
+            (700, (5, 6, 8), workloads.MATERN52)]
+    zb = workloads.local_blocks(0, nblocks=1, m_range=(4, 4), side_range=(4, 4))[0].zbank
+    out = []
+    for i, (m, npts, kind) in enumerate(spec):
+        W = workloads.random_small(20 + i, 3, m, 4, kind=kind, ell=0.2 + 0.03 * i, signal_var=0.5 + 0.1 * i,
+                                   noise_var=1e-4)
+        W.lengthscale[:] = [W.lengthscale[0], 1.2 * W.lengthscale[0], 0.9 * W.lengthscale[0]]
+        W.npts[:] = npts
+        W.zbank = zb
+        out.append(W)
+    return out
+
+
+def _split(field, Ws):
+    out, o = [], 0
+    for W in Ws:
+        n = W.n_cells
+        out.append(field[o:o + n])
+        o += n
+    return out
+
+
+def test_batch_dense_fp64_matches_oracle_per_model():
+    Ws = _blocks()
+    B = lcp.GPModelBatch.from_workloads(Ws, DEV)
+    got, _ = B.lcp_dense([lcp.grid_of(W) for W in Ws], [W.theta for W in Ws], zbank(Ws[0]), "fp64")
+    got = _split(got.cpu().numpy(), Ws)
+    for b, W in enumerate(Ws):
+        ref = oracle.lcp_dense(oracle.fit(W), W).reshape(-1)
+        mism = np.count_nonzero(counts(got[b], W.n_samples) != counts(ref, W.n_samples))
+        say(f"batch fp64 model {b}: m={W.m} npts={tuple(W.npts)} nonzero={np.count_nonzero(ref)} mismatched={mism}")
+        assert mism == 0
+
+
+# These random blocks have noise / signal variance down to 1e-4 (K conditioned up to ~1e6),
+# where a binary32 V keeps about 3 digits of the smallest variances: the reduced precisions
+# are held to 1e-3 RMSE here (the 1e-4 target is tested on the benchmark's fields).
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_batch_dense_mixed_rmse_and_equal_to_single(prec):
+    Ws = _blocks()
+    B = lcp.GPModelBatch.from_workloads(Ws, DEV)
+    got, _ = B.lcp_dense([lcp.grid_of(W) for W in Ws], [W.theta for W in Ws], zbank(Ws[0]), prec)
+    got = _split(got.cpu().numpy(), Ws)
+    for b, W in enumerate(Ws):
+        ref = oracle.lcp_dense(oracle.fit(W), W).reshape(-1)
+        rmse = float(np.sqrt(np.mean((got[b] - ref) ** 2)))
+        say(f"batch {prec} model {b}: rmse={rmse:.2e}")
+        assert rmse <= 1e-3
+        if prec == "fp32":           # the batched and the single launch share the tile code
+            single, _ = lcp.GPModel.from_workload(W, DEV).lcp_dense(lcp.grid_of(W), W.theta, zbank(W), prec)
+            assert np.array_equal(single.cpu().numpy(), got[b])
+
+
+def test_batch_rejects_singular_model():
+    Ws = _blocks()[:3]
+    Ws[1].X[1] = Ws[1].X[0]
+    Ws[1].noise_var = 0.0
+    with pytest.raises(lcp.LcpError) as e:
+        lcp.GPModelBatch.from_workloads(Ws, DEV)
+    assert e.value.status == lcp.lcp.LCP_ENOTPD and "model 1" in str(e.value)

@@ -141,6 +141,30 @@ def field3d_trig(seed: int, m: int = 500, npts: int = 128, n_samples: int = 1600
                     _zbank(seed, n_samples, 3), seed)
 
 
+def local_blocks(seed: int, nblocks: int = 256, m_range=(64, 1024), side_range=(16, 64), n_samples: int = 1600,
+                 signal_var: float = 1.0, noise_var: float = 1e-4, ell_range=(0.05, 0.2), nbumps: int = 4):
+    """Batch of independent local GP models: block b has m_b ~ U{m_range} uniform
+    observations on [0,1]^3 of its own field (nbumps isotropic bumps), an SE kernel with
+    lengthscale ~ U[ell_range], a cubic grid of side s_b ~ U{side_range} vertices and its
+    iso-value at the median of its observations.  All blocks share one z-bank."""
+    r = _rng(seed, 10)
+    zb = _zbank(seed, n_samples, 3)
+    out = []
+    for b in range(nblocks):
+        m = int(r.integers(m_range[0], m_range[1] + 1))
+        side = int(r.integers(side_range[0], side_range[1] + 1))
+        ell = float(r.uniform(*ell_range))
+        X = r.random((m, 3))
+        amp = r.uniform(0.5, 1.0, nbumps)
+        wid = r.uniform(0.05, 0.2, nbumps)
+        ctr = r.random((nbumps, 3))
+        y = _bumps(X, amp, ctr, wid)
+        out.append(Workload(f"block{b}", 3, SE, signal_var, np.array([ell] * 3), noise_var, X, y,
+                            np.zeros(3), np.ones(3), np.array([side] * 3, np.int64),
+                            float(np.median(y)), 1e-3, 4, zb, seed))
+    return out
+
+
 def random_small(seed: int, dim: int, m: int, npts, kind: int = SE, n_samples: int = 1600,
                  signal_var: float = 1.0, ell: float = 0.25, noise_var: float = 1e-4,
                  min_leaf: int = 1, alpha: float = 1e-3) -> Workload:
