@@ -1,6 +1,8 @@
 // Cell stage of Sec. 4: cross-covariances between neighbouring vertices, the 2^D-corner
 // covariance of each cell, its semidefinite Cholesky factor (binary64), and the Monte
 // Carlo crossing count over the shared bank of standard normals.
+#include <vector>
+
 #include "lcp_internal.h"
 
 namespace lcp {
@@ -60,20 +62,69 @@ __device__ __forceinline__ int32_t slot_at(const GridP& g, const int32_t* slot, 
     return slot ? slot[vid] : (int32_t)vid;
 }
 
-template <class T, int D>
-__global__ void __launch_bounds__(256) k_cross(KParams kp, GridP g, int64_t ldv, int nquads,
-                                               const int32_t* __restrict__ slot, const T* __restrict__ V,
-                                               double* __restrict__ cross)
+// A cross-covariance task (one model and grid) and the sources of a kernel's waves: one
+// task, or a batch whose waves are numbered consecutively (task b owns woff[b] ..).
+struct CrossTask {
+    KParams kp;
+    GridP g;
+    int64_t ldv;
+    int nquads;
+    const int32_t* slot;
+    const void* V;
+    double* cross;
+};
+
+__host__ __device__ inline int64_t cross_waves(const GridP& g)
+{
+    return ((g.n[0] + 2) * g.n[1] * (g.dim == 3 ? g.n[2] : 1) + kCrossRun - 1) / kCrossRun;
+}
+
+struct CrossOne {
+    CrossTask c;
+    int64_t nw;
+    __device__ int64_t total() const { return nw; }
+    __device__ const CrossTask& resolve(int64_t w, int64_t& lw) const { lw = w; return c; }
+};
+
+struct CrossBatch {
+    const CrossTask* tasks;
+    const int64_t* woff;
+    int nb;
+    __device__ int64_t total() const { return woff[nb]; }
+    __device__ const CrossTask& resolve(int64_t w, int64_t& lw) const
+    {
+        int lo = 0, hi = nb - 1;                // last b with woff[b] <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (woff[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        lw = w - woff[lo];
+        return tasks[lo];
+    }
+};
+
+template <class T, int D, class R>
+__global__ void __launch_bounds__(256) k_cross(R src)
 {
     constexpr int NDIR = D == 3 ? 13 : 4;
     constexpr int NPEN = D == 3 ? 5 : 2;     // own column, (y+1, z), (y-1, z+1), (y, z+1), (y+1, z+1)
     using V4 = T __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t xw = g.n[0] + 2;
-    const int64_t nflat = xw * g.n[1] * (D == 3 ? g.n[2] : 1);
-    const int64_t nwaves = (nflat + kCrossRun - 1) / kCrossRun;
-    for (int64_t w = wave0; w < nwaves; w += (int64_t)gridDim.x * 4) {
+    const int64_t nwaves = src.total();
+    for (int64_t wg = wave0; wg < nwaves; wg += (int64_t)gridDim.x * 4) {
+        int64_t w;
+        const CrossTask& ct = src.resolve(wg, w);
+        const KParams& kp = ct.kp;
+        const GridP& g = ct.g;
+        const int64_t ldv = ct.ldv;
+        const int nquads = ct.nquads;
+        const int32_t* __restrict__ slot = ct.slot;
+        const T* __restrict__ V = (const T*)ct.V;
+        double* __restrict__ cross = ct.cross;
+        const int64_t xw = g.n[0] + 2;
+        const int64_t nflat = xw * g.n[1] * (D == 3 ? g.n[2] : 1);
         const int64_t F = w * kCrossRun + lane - 1;
         int64_t x = -1, y = 0, z = 0;
         if (F >= 0 && F < nflat) {
@@ -217,7 +268,6 @@ template <int D>
 __device__ __forceinline__ int cell_corners(const CellTask& t, int64_t e, int64_t& lin, int64_t (&sl)[1 << D])
 {
     constexpr int N = 1 << D;
-    constexpr int NDIR = D == 3 ? 13 : 4;
     const GridP& g = t.grid;
     int64_t cell[3] = {0, 0, 0};
     if (t.leaves) {
@@ -321,6 +371,36 @@ __global__ void __launch_bounds__(256) k_zmax(const double* __restrict__ zb, int
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// Where a kernel's cells come from: one task (its enumeration), or a batch of dense tasks
+// whose cells are numbered consecutively (task b owns coff[b] .. coff[b + 1] - 1).  Work
+// lists hold these global numbers; a batch shares one list, count and zmax (task 0's).
+template <int D>
+struct CellsOne {
+    CellTask t;
+    __device__ int64_t total(int64_t cap) const { return cell_total<D>(t, cap); }
+    __device__ const CellTask& first() const { return t; }
+    __device__ const CellTask& resolve(int64_t e, int64_t& le) const { le = e; return t; }
+};
+
+struct CellsBatch {
+    const CellTask* tasks;
+    const int64_t* coff;
+    int nb;
+    __device__ int64_t total(int64_t cap) const { return coff[nb] < cap ? coff[nb] : cap; }
+    __device__ const CellTask& first() const { return tasks[0]; }
+    __device__ const CellTask& resolve(int64_t e, int64_t& le) const
+    {
+        int lo = 0, hi = nb - 1;                // last b with coff[b] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (coff[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        le = e - coff[lo];
+        return tasks[lo];
+    }
+};
+
 // Certified skip of the Monte Carlo loop.  Every sample value of corner q is
 // y_q = m_q + C_q . z_s with |C_q . z_s| <= ||C_q||_2 ||z_s||_2 <= ||C_q||_2 zmax, so when
 // m_q - ||C_q|| zmax > 0 for every corner (or m_q + ||C_q|| zmax < 0 for every corner) no
@@ -328,21 +408,23 @@ __global__ void __launch_bounds__(256) k_zmax(const double* __restrict__ zb, int
 // Carlo loop in its own precision (relative 1e-5 for binary32, 1e-12 for binary64).
 // Cells that cannot be certified go to the work list (order immaterial: each cell's
 // result depends on that cell only).
-template <int D, class TM>
-__global__ void __launch_bounds__(256) k_cells_cert(CellTask t, int64_t ncells_cap)
+template <int D, class TM, class R>
+__global__ void __launch_bounds__(256) k_cells_cert(R src, int64_t ncells_cap)
 {
     constexpr int N = 1 << D;
-    const int64_t total = cell_total<D>(t, ncells_cap);
-    const double zm = *t.zmax;
+    const int64_t total = src.total(ncells_cap);
+    const CellTask& t0 = src.first();
+    const double zm = *t0.zmax;
     const double rel = std::is_same<TM, double>::value ? 1e-12 : 1e-5;
     const int lane = threadIdx.x & 63;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t e = base + threadIdx.x;
         bool work = false;
         if (e < total) {
-            int64_t lin = 0;
+            int64_t le = 0, lin = 0;
+            const CellTask& t = src.resolve(e, le);
             int64_t sl[N];
-            const int st = cell_corners<D>(t, e, lin, sl);
+            const int st = cell_corners<D>(t, le, lin, sl);
             if (st == 1) {
                 t.lcp[lin] = __builtin_nanf("");
             } else if (st == 2) {
@@ -379,26 +461,29 @@ __global__ void __launch_bounds__(256) k_cells_cert(CellTask t, int64_t ncells_c
         const uint64_t bal = __ballot(work);
         if (bal) {
             int64_t pos = 0;
-            if (lane == 0) pos = atomicAdd((unsigned long long*)t.wcount, (unsigned long long)__popcll(bal));
+            if (lane == 0) pos = atomicAdd((unsigned long long*)t0.wcount, (unsigned long long)__popcll(bal));
             pos = __shfl(pos, 0, 64);
-            if (work) t.work[pos + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)e;
+            if (work) t0.work[pos + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)e;
         }
     }
 }
 
 // Monte Carlo LCP of the listed cells (count = *wcount).
-template <int D, class TM>
-__global__ void __launch_bounds__(256) k_cells(CellTask t, int64_t ncells_cap)
+template <int D, class TM, class R>
+__global__ void __launch_bounds__(256) k_cells(R src, int64_t ncells_cap)
 {
     constexpr int N = 1 << D;
-    int64_t total = *t.wcount;
+    const CellTask& t0 = src.first();
+    int64_t total = *t0.wcount;
     if (total > ncells_cap) total = ncells_cap;
-    const TM* zb = std::is_same<TM, double>::value ? (const TM*)t.zb64 : (const TM*)t.zb32;
+    const TM* zb = std::is_same<TM, double>::value ? (const TM*)t0.zb64 : (const TM*)t0.zb32;
+    const int ns = t0.ns;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
-        int64_t lin = 0;
+        int64_t le = 0, lin = 0;
+        const CellTask& t = src.resolve(t0.work[it], le);
         int64_t sl[N];
-        if (cell_corners<D>(t, t.work[it], lin, sl) != 2) continue;
+        if (cell_corners<D>(t, le, lin, sl) != 2) continue;
         double mu[N], Cd[N][N];
         cell_factor<D>(t, sl, mu, Cd);
         TM C[N][N], m[N];
@@ -409,7 +494,7 @@ __global__ void __launch_bounds__(256) k_cells(CellTask t, int64_t ncells_cap)
             for (int r = 0; r < N; ++r) C[q][r] = (TM)Cd[q][r];
         }
         int cnt = 0;
-        for (int s = 0; s < t.ns; ++s) {
+        for (int s = 0; s < ns; ++s) {
             TM z[N];
 #pragma unroll
             for (int r = 0; r < N; ++r) z[r] = zb[(size_t)s * N + r];
@@ -430,7 +515,7 @@ __global__ void __launch_bounds__(256) k_cells(CellTask t, int64_t ncells_cap)
             // crossed unless all corners are below theta (ymax < 0) or all above (ymin > 0)
             cnt += (!(ymax < (TM)0) && !(ymin > (TM)0)) ? 1 : 0;
         }
-        t.lcp[lin] = (float)cnt / (float)t.ns;
+        t.lcp[lin] = (float)cnt / (float)ns;
     }
 }
 
@@ -457,6 +542,28 @@ inline unsigned grid_for(int64_t n, int per)
 
 }  // namespace
 
+namespace {
+
+template <class R>
+void cross_dispatch(R src, int dim, bool f64, unsigned grid, hipStream_t s)
+{
+    if (f64) {
+        if (dim == 3) hipLaunchKernelGGL((k_cross<double, 3, R>), dim3(grid), dim3(256), 0, s, src);
+        else hipLaunchKernelGGL((k_cross<double, 2, R>), dim3(grid), dim3(256), 0, s, src);
+    } else {
+        if (dim == 3) hipLaunchKernelGGL((k_cross<float, 3, R>), dim3(grid), dim3(256), 0, s, src);
+        else hipLaunchKernelGGL((k_cross<float, 2, R>), dim3(grid), dim3(256), 0, s, src);
+    }
+}
+
+bool cross_addressable(int64_t nv_cap, int prec)
+{
+    // one quad plane of V must stay addressable by a 32-bit buffer offset
+    return (double)nv_cap * 4 * (prec == LCP_FP64 ? 8 : 4) < 2147483648.0;
+}
+
+}  // namespace
+
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s)
 {
@@ -464,55 +571,95 @@ hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t*
     (void)nv_dev;
     if (nv_cap <= 0) return hipSuccess;
     StageScope sc(s, ST_CROSS);
-    const int64_t nflat = (g.n[0] + 2) * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
-    const int64_t nwaves = ceil_div(nflat, kCrossRun);
-    const unsigned grid = grid_for(nwaves, 4);
-    const int nquads = 4 * M.nrb;
-    // one quad plane of V must stay addressable by a 32-bit buffer offset
-    if ((double)nv_cap * 4 * (prec == LCP_FP64 ? 8 : 4) >= 2147483648.0) return hipErrorInvalidValue;
-    if (prec == LCP_FP64) {
-        if (g.dim == 3)
-            hipLaunchKernelGGL((k_cross<double, 3>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
-                               (const double*)V, cross);
-        else
-            hipLaunchKernelGGL((k_cross<double, 2>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
-                               (const double*)V, cross);
-    } else {
-        if (g.dim == 3)
-            hipLaunchKernelGGL((k_cross<float, 3>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
-                               (const float*)V, cross);
-        else
-            hipLaunchKernelGGL((k_cross<float, 2>), dim3(grid), dim3(256), 0, s, M.kp, g, nv_cap, nquads, slot,
-                               (const float*)V, cross);
-    }
+    if (!cross_addressable(nv_cap, prec)) return hipErrorInvalidValue;
+    const int64_t nw = cross_waves(g);
+    CrossOne src{CrossTask{M.kp, g, nv_cap, 4 * M.nrb, slot, V, cross}, nw};
+    cross_dispatch(src, g.dim, prec == LCP_FP64, grid_for(nw, 4), s);
     return hipGetLastError();
 }
+
+size_t cross_batch_scratch(int nb)
+{
+    return align256(sizeof(CrossTask) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1));
+}
+
+hipError_t launch_cross_batch(const Model* const* Ms, const GridP* grids, const void* const* V, double* const* cross,
+                              int nb, int prec, char* scratch, hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    StageScope sc(s, ST_CROSS);
+    std::vector<CrossTask> T(nb);
+    std::vector<int64_t> woff(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        const GridP& g = grids[b];
+        const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+        if (!cross_addressable(nv, prec)) return hipErrorInvalidValue;
+        T[b] = CrossTask{Ms[b]->kp, g, nv, 4 * Ms[b]->nrb, nullptr, V[b], cross[b]};
+        woff[b + 1] = woff[b] + cross_waves(g);
+    }
+    CrossTask* Td = (CrossTask*)scratch;
+    int64_t* wd = (int64_t*)(scratch + align256(sizeof(CrossTask) * (size_t)nb));
+    hipError_t e = hipMemcpyAsync(Td, T.data(), sizeof(CrossTask) * nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(wd, woff.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);       // pageable sources
+    if (e != hipSuccess) return e;
+    cross_dispatch(CrossBatch{Td, wd, nb}, grids[0].dim, prec == LCP_FP64, grid_for(woff[nb], 4), s);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int D, class TM, class R>
+void cells_pair(R src, unsigned grid, int64_t cap, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cells_cert<D, TM, R>), dim3(grid), dim3(256), 0, s, src, cap);
+    hipLaunchKernelGGL((k_cells<D, TM, R>), dim3(grid), dim3(256), 0, s, src, cap);
+}
+
+template <int D, class R>
+void cells_dispatch(R src, bool f64, unsigned grid, int64_t cap, hipStream_t s)
+{
+    if (f64) cells_pair<D, double>(src, grid, cap, s);
+    else cells_pair<D, float>(src, grid, cap, s);
+}
+
+}  // namespace
 
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s)
 {
     if (ncells_cap <= 0) return hipSuccess;
     StageScope sc(s, ST_CELLS);
-    unsigned grid = grid_for(ncells_cap, 256);
-    const bool f64 = t.prec == LCP_FP64;
     hipLaunchKernelGGL(k_zmax, dim3(1), dim3(256), 0, s, t.zb64, t.ns, 1 << t.grid.dim, t.zmax);
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, t.wcount, (int64_t)0, (int64_t)1);
-    if (t.grid.dim == 3) {
-        if (f64) {
-            hipLaunchKernelGGL((k_cells_cert<3, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-            hipLaunchKernelGGL((k_cells<3, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-        } else {
-            hipLaunchKernelGGL((k_cells_cert<3, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-            hipLaunchKernelGGL((k_cells<3, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-        }
-    } else {
-        if (f64) {
-            hipLaunchKernelGGL((k_cells_cert<2, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-            hipLaunchKernelGGL((k_cells<2, double>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-        } else {
-            hipLaunchKernelGGL((k_cells_cert<2, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-            hipLaunchKernelGGL((k_cells<2, float>), dim3(grid), dim3(256), 0, s, t, ncells_cap);
-        }
-    }
+    const unsigned grid = grid_for(ncells_cap, 256);
+    if (t.grid.dim == 3) cells_dispatch<3>(CellsOne<3>{t}, t.prec == LCP_FP64, grid, ncells_cap, s);
+    else cells_dispatch<2>(CellsOne<2>{t}, t.prec == LCP_FP64, grid, ncells_cap, s);
+    return hipGetLastError();
+}
+
+size_t cells_batch_scratch(int nb)
+{
+    return align256(sizeof(CellTask) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1));
+}
+
+hipError_t launch_cells_batch(const CellTask* tasks, int nb, char* scratch, hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    StageScope sc(s, ST_CELLS);
+    std::vector<int64_t> coff(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) coff[b + 1] = coff[b] + tasks[b].grid.nc[0] * tasks[b].grid.nc[1] * tasks[b].grid.nc[2];
+    CellTask* Td = (CellTask*)scratch;
+    int64_t* cd = (int64_t*)(scratch + align256(sizeof(CellTask) * (size_t)nb));
+    hipError_t e = hipMemcpyAsync(Td, tasks, sizeof(CellTask) * nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cd, coff.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);       // pageable sources
+    if (e != hipSuccess) return e;
+    const CellTask& t = tasks[0];
+    hipLaunchKernelGGL(k_zmax, dim3(1), dim3(256), 0, s, t.zb64, t.ns, 1 << t.grid.dim, t.zmax);
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, t.wcount, (int64_t)0, (int64_t)1);
+    const unsigned grid = grid_for(coff[nb], 256);
+    if (t.grid.dim == 3) cells_dispatch<3>(CellsBatch{Td, cd, nb}, t.prec == LCP_FP64, grid, coff[nb], s);
+    else cells_dispatch<2>(CellsBatch{Td, cd, nb}, t.prec == LCP_FP64, grid, coff[nb], s);
     return hipGetLastError();
 }
 

@@ -770,16 +770,20 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
 
 }  // namespace
 
+// One launch over the listed models (idx) with tiles of NT columns.
 template <class P, int NT>
-static hipError_t launch_batch_t(const Model* const* Ms, const PostTask* tasks, int nb, char* scratch, hipStream_t s,
-                          const void* const* A0, const void* const* A1)
+static hipError_t launch_batch_t(const Model* const* Ms, const PostTask* tasks, const std::vector<int>& idx,
+                                 char* scratch, hipStream_t s, const void* const* A0, const void* const* A1)
 {
+    const int nb = (int)idx.size();
+    if (nb == 0) return hipSuccess;
     std::vector<KArgs> KA(nb);
     std::vector<int64_t> toff(nb + 1, 0);
     int mpmax = 0;
-    for (int b = 0; b < nb; ++b) {
-        KA[b] = kargs_of(*Ms[b], tasks[b], A0[b], A1[b]);
-        toff[b + 1] = toff[b] + (tasks[b].n_points + NT - 1) / NT;
+    for (int i = 0; i < nb; ++i) {
+        const int b = idx[i];
+        KA[i] = kargs_of(*Ms[b], tasks[b], A0[b], A1[b]);
+        toff[i + 1] = toff[i] + (tasks[b].n_points + NT - 1) / NT;
         if (Ms[b]->m_pad > mpmax) mpmax = Ms[b]->m_pad;
     }
     KArgs* KAd = (KArgs*)scratch;
@@ -802,7 +806,8 @@ static hipError_t launch_batch_t(const Model* const* Ms, const PostTask* tasks, 
 
 size_t posterior_batch_scratch(int nb)
 {
-    return align256(sizeof(KArgs) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1));
+    // two launches (models up to 512 observations, and larger ones), each with its records
+    return 2 * (align256(sizeof(KArgs) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1)));
 }
 
 hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks, int nb, int prec, char* scratch,
@@ -817,10 +822,26 @@ hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks,
               : prec == LCP_MIXED_F16X3 ? (const void*)M.Hhi : (const void*)M.Ahi;
         A1[b] = prec == LCP_MIXED_F16X3 ? (const void*)M.Hlo : prec == LCP_MIXED_BF16X3 ? (const void*)M.Alo : nullptr;
     }
-    if (prec == LCP_FP64) return launch_batch_t<P64, 16>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
-    if (prec == LCP_FP32) return launch_batch_t<P32, 32>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
-    if (prec == LCP_MIXED_F16X3) return launch_batch_t<PH3, 32>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
-    return launch_batch_t<PB3, 32>(Ms, tasks, nb, scratch, s, A0.data(), A1.data());
+    // Models up to 512 observations take 32-column tiles (binary64: 16), larger ones half
+    // that, so B stays within 80 KB of LDS and two work-groups share a CU in both launches.
+    std::vector<int> small, large;
+    for (int b = 0; b < nb; ++b) (Ms[b]->m_pad <= 512 ? small : large).push_back(b);
+    char* sc2 = scratch + posterior_batch_scratch(nb) / 2;
+    hipError_t e;
+    if (prec == LCP_FP64) {
+        e = launch_batch_t<P64, 16>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
+        if (e == hipSuccess) e = launch_batch_t<P64, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
+    } else if (prec == LCP_FP32) {
+        e = launch_batch_t<P32, 32>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
+        if (e == hipSuccess) e = launch_batch_t<P32, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
+    } else if (prec == LCP_MIXED_F16X3) {
+        e = launch_batch_t<PH3, 32>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
+        if (e == hipSuccess) e = launch_batch_t<PH3, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
+    } else {
+        e = launch_batch_t<PB3, 32>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
+        if (e == hipSuccess) e = launch_batch_t<PB3, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
+    }
+    return e;
 }
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s)

@@ -524,15 +524,27 @@ int batch_grids(const lcp_model_batch* B, const lcp_grid* grids, std::vector<Gri
     return LCP_OK;
 }
 
+// Per model a dense workspace, then the batch records (posterior, cross, cells) and one
+// Monte Carlo work list for all models' cells.
 size_t batch_dense_ws(const lcp_model_batch* B, const std::vector<GridP>& gs, int prec, int ns,
                       std::vector<size_t>* off)
 {
+    const int nb = (int)gs.size();
     size_t o = 0;
-    for (size_t b = 0; b < gs.size(); ++b) {
+    int64_t cells = 0;
+    for (int b = 0; b < nb; ++b) {
         if (off) off->push_back(o);
         o += dense_ws(&B->models[b], gs[b], prec, ns);
+        cells += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
     }
-    return o + align256(posterior_batch_scratch((int)gs.size()));
+    if (off) off->push_back(o);
+    o += align256(posterior_batch_scratch(nb));
+    if (off) off->push_back(o);
+    o += align256(cross_batch_scratch(nb));
+    if (off) off->push_back(o);
+    o += align256(cells_batch_scratch(nb));
+    if (off) off->push_back(o);
+    return o + cells_scratch_bytes(cells);
 }
 
 }  // namespace
@@ -579,13 +591,47 @@ int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const doubl
         e = launch_zbank32(mc->zbank, w[0].zb32, (int64_t)mc->n_samples << gs[0].dim, s);
         if (e != hipSuccess) return dev_fail(e, "z-bank");
     }
-    char* pscratch = (char*)ws + need - align256(posterior_batch_scratch(nb));
-    e = launch_posterior_batch(Ms.data(), tasks.data(), nb, prec, pscratch, s);
+    char* base = (char*)ws;
+    e = launch_posterior_batch(Ms.data(), tasks.data(), nb, prec, base + off[nb], s);
     if (e != hipSuccess) return dev_fail(e, "batched posterior");
+    std::vector<const void*> Vs(nb);
+    std::vector<double*> crosses(nb);
+    for (int b = 0; b < nb; ++b) {
+        Vs[b] = w[b].V;
+        crosses[b] = w[b].cross;
+    }
+    e = launch_cross_batch(Ms.data(), gs.data(), Vs.data(), crosses.data(), nb, prec, base + off[nb + 1], s);
+    if (e != hipSuccess) return dev_fail(e, "batched cross");
+    // one work list for every model's cells
+    int64_t cells = 0;
+    for (int b = 0; b < nb; ++b) cells += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
+    char* list = base + off[nb + 3];
+    int32_t* work = (int32_t*)list;
+    int64_t* wcount = (int64_t*)(list + align256(4 * (size_t)cells));
+    double* zmax = (double*)((char*)wcount + 64);
+    std::vector<CellTask> cts(nb);
     int64_t cell0 = 0;
     for (int b = 0; b < nb; ++b) {
-        if (int r = dense_cells(&B->models[b], gs[b], theta[b], mc, prec, w[b], w[0].zb32, lcp + cell0, s)) return r;
+        CellTask& ct = cts[b];
+        ct = CellTask{};
+        ct.grid = gs[b];
+        ct.prec = prec;
+        ct.theta = theta[b];
+        ct.ns = mc->n_samples;
+        ct.zb64 = mc->zbank;
+        ct.zb32 = w[0].zb32;
+        ct.mean = w[b].mean;
+        ct.var = w[b].var;
+        ct.cross = w[b].cross;
+        ct.slot = nullptr;
+        ct.leaves = nullptr;
+        ct.lcp = lcp + cell0;
+        ct.work = work;
+        ct.wcount = wcount;
+        ct.zmax = zmax;
         cell0 += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
     }
+    e = launch_cells_batch(cts.data(), nb, base + off[nb + 2], s);
+    if (e != hipSuccess) return dev_fail(e, "batched cells");
     return ok();
 }

@@ -211,6 +211,14 @@ inline size_t cells_scratch_bytes(int64_t ncells_cap) { return ((4 * (size_t)nce
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s);
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s);
+// Dense cells of nb tasks in one pass; every task's work/wcount/zmax must point to one
+// shared list (>= total cells), count and zmax; scratch holds cells_batch_scratch(nb) bytes.
+size_t cells_batch_scratch(int nb);
+// Dense cross-covariances of nb models in one launch (V quad-major with nv_b columns).
+size_t cross_batch_scratch(int nb);
+hipError_t launch_cross_batch(const Model* const* Ms, const GridP* grids, const void* const* V, double* const* cross,
+                              int nb, int prec, char* scratch, hipStream_t s);
+hipError_t launch_cells_batch(const CellTask* tasks, int nb, char* scratch, hipStream_t s);
 hipError_t launch_zbank32(const double* zb, float* zb32, int64_t n, hipStream_t s);
 
 // --------------------------------------------------------------- model (K2)
