@@ -22,7 +22,7 @@ ORC_OK, ORC_ENOTPD, ORC_ECAP, ORC_ENOMEM = 0, 2, 3, 4
 class Model(C.Structure):
     _fields_ = [("kind", C.c_int), ("dim", C.c_int), ("m", C.c_int), ("s2", C.c_double),
                 ("ell", C.c_double * 3), ("noise", C.c_double), ("X", C.c_void_p),
-                ("L", C.c_void_p), ("a", C.c_void_p)]
+                ("L", C.c_void_p), ("a", C.c_void_p), ("A", C.c_void_p), ("muM", C.c_void_p)]
 
 
 class Grid(C.Structure):
@@ -112,13 +112,29 @@ class FitModel:
                            _p(self.a))
         self.rc = rc
         self.s = Model(kind, dim, m, s2, (C.c_double * 3)(*self.ell), noise, self.X.ctypes.data,
-                       self.L.ctypes.data, self.a.ctypes.data)
+                       self.L.ctypes.data, self.a.ctypes.data, None, None)
         self.kind, self.dim, self.m, self.s2, self.noise = kind, dim, m, s2, noise
+        self.A = None
+        self.vwidth = m
+
+
+class SparseModel(FitModel):
+    """General eq. (sgp): inducing points Z with stored N(mu_M, A_M); K_MM + jitter I."""
+
+    def __init__(self, kind, dim, s2, ell, jitter, Z, mu_M, A_M):
+        super().__init__(kind, dim, s2, ell, jitter, Z, mu_M)
+        self.A = _f64(A_M).reshape(self.m, self.m)
+        self.s.A = self.A.ctypes.data
+        self.s.muM = self.y.ctypes.data
+        self.vwidth = 3 * self.m
 
 
 def fit(W):
-    """Factor the model of a workloads.Workload."""
-    M = FitModel(W.kind, W.dim, W.signal_var, W.lengthscale, W.noise_var, W.X, W.y)
+    """Factor the model of a workloads.Workload (sparse when it carries A_M)."""
+    if getattr(W, "A_M", None) is not None:
+        M = SparseModel(W.kind, W.dim, W.signal_var, W.lengthscale, W.noise_var, W.X, W.y, W.A_M)
+    else:
+        M = FitModel(W.kind, W.dim, W.signal_var, W.lengthscale, W.noise_var, W.X, W.y)
     if M.rc != ORC_OK:
         raise np.linalg.LinAlgError(f"oracle fit failed with status {M.rc}")
     return M
@@ -132,7 +148,7 @@ def posterior(M: FitModel, P, want_v=False):
     P = _f64(P).reshape(-1, M.dim)
     n = P.shape[0]
     mean, var = np.zeros(n), np.zeros(n)
-    V = np.zeros((n, M.m)) if want_v else None
+    V = np.zeros((n, M.vwidth)) if want_v else None
     rc = lib().orc_posterior(C.byref(M.s), n, _p(P), _p(mean), _p(var), _p(V))
     assert rc == ORC_OK
     return (mean, var, V) if want_v else (mean, var)

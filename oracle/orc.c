@@ -13,7 +13,10 @@
  *
  * Readings of the paper taken here (all listed in the design notes):
  *  - GP model: the exact-GP special case of eq. (sgp) (inducing set = observations),
- *    so mu(x) = k*^T (K + s_n^2 I)^-1 y and var(x) = k(x,x) - ||L^-1 k*||^2, latent f.
+ *    so mu(x) = k*^T (K + s_n^2 I)^-1 y and var(x) = k(x,x) - ||L^-1 k*||^2, latent f;
+ *    or the general eq. (sgp) with stored mu_M and A_M, K_MM taking the model's noise
+ *    term as a diagonal jitter.  The preliminary node test of Alg. 1 then reads the
+ *    inducing marginals N(mu_M_i, A_M_ii) directly (Sec. 4.3).
  *  - F_M uses the standard deviation, not the variance (Sec. 4.1 prints Sigma).
  *  - Cell covariance is factored with a semidefinite Cholesky (tolerance 1e-12 of the
  *    largest diagonal entry); a sample equal to the iso-value counts as crossed.
@@ -44,6 +47,11 @@ typedef struct {
     const double* X;  /* m x dim observation locations, row-major */
     const double* L;  /* m x m lower Cholesky factor of K + noise I, row-major */
     const double* a;  /* m: (K + noise I)^-1 y */
+    const double* A;  /* NULL: exact GP.  Else the sparse model of eq. (sgp): X are the
+                         inducing points M, L factors K_MM (+ jitter I, the field noise),
+                         a = K_MM^-1 mu_M, and A is the m x m covariance A_M of the
+                         inducing values */
+    const double* muM; /* sparse model only: the m inducing means mu_M */
 } orc_model;
 
 typedef struct {
@@ -110,6 +118,10 @@ void orc_kernel_grad(int kind, int dim, double s2, const double* ell, const doub
 }
 
 /* ---------------------------------------------------------- model factor -- */
+
+/* Per-point vector kept for the cross-covariances: v = L^-1 k* (m) for the exact GP; for
+ * the sparse model [k*, w = K_MM^-1 k*, A_M w] (3m). */
+static int vwidth(const orc_model* M) { return M->A ? 3 * M->m : M->m; }
 
 /* Solve L v = b by forward substitution (L row-major lower, m x m). */
 static void forward_sub(int m, const double* L, const double* b, double* v)
@@ -180,6 +192,30 @@ static void posterior_point(const orc_model* M, const double* x, double* mean, d
                             double* kbuf, double* v)
 {
     int m = M->m;
+    if (M->A) {
+        /* eq. (sgp): mu = K_IM K_MM^-1 mu_M, Sigma = K_II - K_IM K_MM^-1 K_MI
+         *                                            + K_IM K_MM^-1 A_M K_MM^-1 K_MI */
+        double* k = v;
+        double* w = v + m;
+        double* Aw = v + 2 * m;
+        for (int j = 0; j < m; ++j) k[j] = orc_kernel(M->kind, M->dim, M->s2, M->ell, M->X + (int64_t)j * M->dim, x);
+        double mu = 0.0;
+        for (int j = 0; j < m; ++j) mu += k[j] * M->a[j];
+        forward_sub(m, M->L, k, kbuf);
+        backward_sub_t(m, M->L, kbuf, w);
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += M->A[(int64_t)i * m + j] * w[j];
+            Aw[i] = s;
+        }
+        double t1 = 0.0, t2 = 0.0;
+        for (int j = 0; j < m; ++j) t1 += k[j] * w[j];
+        for (int j = 0; j < m; ++j) t2 += w[j] * Aw[j];
+        double s = M->s2 - t1 + t2;
+        *mean = mu;
+        *var = s > 0.0 ? s : 0.0;
+        return;
+    }
     for (int j = 0; j < m; ++j) kbuf[j] = orc_kernel(M->kind, M->dim, M->s2, M->ell, M->X + (int64_t)j * M->dim, x);
     double mu = 0.0;
     for (int j = 0; j < m; ++j) mu += kbuf[j] * M->a[j];
@@ -191,7 +227,8 @@ static void posterior_point(const orc_model* M, const double* x, double* mean, d
     *var = s > 0.0 ? s : 0.0;
 }
 
-/* Posterior mean and variance at n points; optionally v = L^-1 k* per point (n x m). */
+/* Posterior mean and variance at n points; optionally the per-point vector of vwidth
+ * entries (v = L^-1 k* for the exact GP) per point. */
 int orc_posterior(const orc_model* M, int64_t n, const double* P, double* mean, double* var, double* V)
 {
     int m = M->m;
@@ -199,14 +236,14 @@ int orc_posterior(const orc_model* M, int64_t n, const double* P, double* mean, 
 #pragma omp parallel
     {
         double* kb = (double*)malloc(sizeof(double) * (size_t)m);
-        double* vb = (double*)malloc(sizeof(double) * (size_t)m);
+        double* vb = (double*)malloc(sizeof(double) * (size_t)vwidth(M));
         if (!kb || !vb) {
 #pragma omp atomic write
             rc = ORC_ENOMEM;
         } else {
 #pragma omp for schedule(static)
             for (int64_t i = 0; i < n; ++i) {
-                double* v = V ? V + i * m : vb;
+                double* v = V ? V + i * vwidth(M) : vb;
                 posterior_point(M, P + i * M->dim, &mean[i], &var[i], kb, v);
             }
         }
@@ -227,6 +264,20 @@ static void posterior_grad_point(const orc_model* M, const double* x, double* me
         orc_kernel_grad(M->kind, D, M->s2, M->ell, x, M->X + (int64_t)j * D, g);
         for (int d = 0; d < D; ++d) dkb[(int64_t)d * m + j] = g[d];
     }
+    if (M->A) {
+        /* d Sigma / dx_d = -2 dk^T w + 2 dk^T K_MM^-1 A_M w = -2 dk^T (w - K_MM^-1 A_M w) */
+        const double* wv = v + m;
+        forward_sub(m, M->L, v + 2 * m, kb);
+        backward_sub_t(m, M->L, kb, w);
+        for (int d = 0; d < D; ++d) {
+            double dm = 0.0, s = 0.0;
+            for (int j = 0; j < m; ++j) dm += dkb[(int64_t)d * m + j] * M->a[j];
+            for (int j = 0; j < m; ++j) s += dkb[(int64_t)d * m + j] * (wv[j] - w[j]);
+            dmean[d] = dm;
+            dvar[d] = -2.0 * s;
+        }
+        return;
+    }
     for (int d = 0; d < D; ++d) {
         double dm = 0.0;
         for (int j = 0; j < m; ++j) dm += dkb[(int64_t)d * m + j] * M->a[j];
@@ -241,9 +292,9 @@ static void posterior_grad_point(const orc_model* M, const double* x, double* me
 int orc_posterior_grad(const orc_model* M, const double* x, double* mean, double* var, double* dmean, double* dvar)
 {
     int m = M->m;
-    double* buf = (double*)malloc(sizeof(double) * (size_t)m * 6);
+    double* buf = (double*)malloc(sizeof(double) * ((size_t)m * 5 + (size_t)vwidth(M)));
     if (!buf) return ORC_ENOMEM;
-    posterior_grad_point(M, x, mean, var, dmean, dvar, buf, buf + m, buf + 4 * (size_t)m, buf + 5 * (size_t)m);
+    posterior_grad_point(M, x, mean, var, dmean, dvar, buf, buf + m, buf + 5 * (size_t)m, buf + 4 * (size_t)m);
     free(buf);
     return ORC_OK;
 }
@@ -305,9 +356,18 @@ static void cell_cov(const orc_model* M, int nc, const double* xc, const double*
     for (int p = 0; p < nc; ++p) {
         S[p * nc + p] = varc[p];
         for (int q = 0; q < p; ++q) {
-            double dot = 0.0;
-            for (int j = 0; j < m; ++j) dot += vc[p][j] * vc[q][j];
-            double c = orc_kernel(M->kind, D, M->s2, M->ell, xc + p * D, xc + q * D) - dot;
+            double c = orc_kernel(M->kind, D, M->s2, M->ell, xc + p * D, xc + q * D);
+            if (M->A) {
+                /* eq. (sgp) off the diagonal: - k_p^T K_MM^-1 k_q + k_p^T K_MM^-1 A_M K_MM^-1 k_q */
+                double t1 = 0.0, t2 = 0.0;
+                for (int j = 0; j < m; ++j) t1 += vc[p][j] * vc[q][m + j];
+                for (int j = 0; j < m; ++j) t2 += vc[p][2 * m + j] * vc[q][m + j];
+                c = c - t1 + t2;
+            } else {
+                double dot = 0.0;
+                for (int j = 0; j < m; ++j) dot += vc[p][j] * vc[q][j];
+                c -= dot;
+            }
             S[p * nc + q] = c;
             S[q * nc + p] = c;
         }
@@ -320,7 +380,7 @@ static int64_t cell_count(const orc_model* M, const orc_grid* G, double theta, i
                           const int64_t* cell, const int64_t* box_lo, const int64_t* box_n,
                           const double* bmean, const double* bvar, const double* bV)
 {
-    int D = G->dim, nc = 1 << D, m = M->m;
+    int D = G->dim, nc = 1 << D;
     double mu[8], var[8], xc[24], S[64], C[64];
     const double* vc[8];
     for (int q = 0; q < nc; ++q) {
@@ -333,7 +393,7 @@ static int64_t cell_count(const orc_model* M, const orc_grid* G, double theta, i
         }
         mu[q] = bmean[idx];
         var[q] = bvar[idx];
-        vc[q] = bV + idx * m;
+        vc[q] = bV + idx * vwidth(M);
     }
     cell_cov(M, nc, xc, var, vc, S);
     orc_chol_sd(nc, S, C, 1e-12);
@@ -350,7 +410,7 @@ static int box_posterior(const orc_model* M, const orc_grid* G, const int64_t* b
     double* P = (double*)malloc(sizeof(double) * (size_t)nv * D);
     *mean = (double*)malloc(sizeof(double) * (size_t)nv);
     *var = (double*)malloc(sizeof(double) * (size_t)nv);
-    *V = (double*)malloc(sizeof(double) * (size_t)nv * M->m);
+    *V = (double*)malloc(sizeof(double) * (size_t)nv * vwidth(M));
     if (!P || !*mean || !*var || !*V) { free(P); return ORC_ENOMEM; }
     for (int64_t t = 0; t < nv; ++t) {
         int64_t r = t;
@@ -432,7 +492,7 @@ int orc_cell_moments(const orc_model* M, const orc_grid* G, const int64_t* cell,
             for (int d = 0; d < D; ++d) xc[q * D + d] = vertex_coord(G, d, cell[d] + ((q >> d) & 1));
             mu[q] = mean[q];
             vr[q] = var[q];
-            vc[q] = V + (int64_t)q * M->m;
+            vc[q] = V + (int64_t)q * vwidth(M);
         }
         cell_cov(M, nc, xc, vr, vc, S);
     }
@@ -552,9 +612,9 @@ int orc_bound(const orc_model* M, double theta, double side, const double* blo, 
               double* gmin, double* gap)
 {
     int m = M->m;
-    double* buf = (double*)malloc(sizeof(double) * (size_t)m * 6);
+    double* buf = (double*)malloc(sizeof(double) * ((size_t)m * 5 + (size_t)vwidth(M)));
     if (!buf) return ORC_ENOMEM;
-    bound_ws B = {M, theta, buf, buf + m, buf + 4 * (size_t)m, buf + 5 * (size_t)m};
+    bound_ws B = {M, theta, buf, buf + m, buf + 5 * (size_t)m, buf + 4 * (size_t)m};
     *gmin = bound_search(&B, side, blo, bhi, steps, gap);
     free(buf);
     return ORC_OK;
@@ -652,7 +712,7 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
                 side = (p2 <= alpha) ? 1.0 : -1.0;
             } else {
                 double xc[3], mu, var;
-                double* kb = (double*)malloc(sizeof(double) * (size_t)M->m * 2);
+                double* kb = (double*)malloc(sizeof(double) * ((size_t)M->m + (size_t)vwidth(M)));
                 for (int d = 0; d < D; ++d) xc[d] = 0.5 * (blo[d] + bhi[d]);
                 posterior_point(M, xc, &mu, &var, kb, kb + M->m);
                 free(kb);
@@ -737,7 +797,15 @@ int orc_adaptive(const orc_model* M, const orc_grid* G, double theta, const orc_
     double* mu = (double*)malloc(sizeof(double) * (size_t)m);
     double* var = (double*)malloc(sizeof(double) * (size_t)m);
     if (!qlo || !qhi || !mu || !var) { free(qlo); free(qhi); free(mu); free(var); return ORC_ENOMEM; }
-    orc_posterior(M, m, M->X, mu, var, NULL);
+    if (M->A) {
+        /* Sec. 4.3: the inducing values are N(mu_M, A_M); their marginals are stored */
+        for (int i = 0; i < m; ++i) {
+            mu[i] = M->muM[i];
+            var[i] = M->A[(int64_t)i * m + i] > 0.0 ? M->A[(int64_t)i * m + i] : 0.0;
+        }
+    } else {
+        orc_posterior(M, m, M->X, mu, var, NULL);
+    }
     for (int i = 0; i < m; ++i) {
         if (var[i] > 0.0) {
             double z = (theta - mu[i]) / sqrt(var[i]);

@@ -6,6 +6,13 @@ standard-normal draws used by the Monte Carlo cell estimate.  It contains none o
 the method's arithmetic (no covariance, posterior, probability or bound), so the
 oracle and the HIP path can both consume its arrays without sharing any code.
 
+One generator, sgpr_field, also stands in for the SGPR fitting step that the paper
+delegates to an external library (Sec. 3): for fixed inducing points and kernel
+parameters it forms the optimal Gaussian N(mu_M, A_M) of the inducing values from a
+noisy synthetic training grid (Titsias' closed form).  That step is model training,
+not part of the method; the method's own arithmetic (eq. (sgp), the cell
+probability, the bound) stays out of this module.
+
 The paper evaluates on two datasets (Tangle, Ethanediol, Sec. 5.3) that are not
 available here; the workloads below stand in for them at the paper's scale
 (m = 50 / 500 observations, 128^3 target grid, Sec. 5.3 and Sec. 6.1), with the
@@ -42,6 +49,9 @@ class Workload:
     min_leaf: int                # finest octree node edge, in cells
     zbank: np.ndarray            # (n_samples, 2**dim) float64 N(0,1) draws
     seed: int = 0
+    A_M: Optional[np.ndarray] = None  # sparse model: (m, m) covariance of the inducing
+                                      # values; X are then the inducing points, y = mu_M and
+                                      # noise_var the jitter added to K_MM's diagonal
 
     @property
     def m(self) -> int:
@@ -165,6 +175,60 @@ def local_blocks(seed: int, nblocks: int = 256, m_range=(64, 1024), side_range=(
     return out
 
 
+def _trig_field(P, seed):
+    r = _rng(seed, 2)
+    amp = r.uniform(0.5, 1.0, 8)
+    wid = r.uniform(0.05, 0.2, 8)
+    ctr = r.random((8, 3))
+    f = np.sin(6 * P[:, 0]) * np.cos(5 * P[:, 1]) * np.sin(4 * P[:, 2])
+    return f + 0.3 * _bumps(P, amp, ctr, wid)
+
+
+def _se_gram(A, B, s2, ell):
+    """s2 exp(-|a - b|^2 / (2 ell^2)), row blocks of A at a time (training only)."""
+    out = np.empty((A.shape[0], B.shape[0]))
+    for i0 in range(0, A.shape[0], 256):
+        d = (A[i0:i0 + 256, None, :] - B[None, :, :]) / ell
+        out[i0:i0 + 256] = s2 * np.exp(-0.5 * (d * d).sum(-1))
+    return out
+
+
+def sgpr_field(seed: int, m: int = 500, npts: int = 128, train_npts: int = 32, n_samples: int = 1600,
+               signal_var: float = 0.5, ell: float = 0.12, noise_var: float = 1e-4, jitter: float = 1e-6,
+               name: Optional[str] = None) -> Workload:
+    """Sparse GP model of eq. (sgp) standing in for the paper's fitted SGPR models
+    (Sec. 5.3: 50 or 500 inducing points, RBF kernel, a training grid of the field).
+
+    Inducing points: one in each of m cells drawn without replacement from a c^3
+    lattice (c = ceil(m^(1/3))), uniform in the central half of its cell.  Training data:
+    the trig field of field3d_trig on a train_npts^3 grid plus N(0, noise_var) noise.
+    N(mu_M, A_M) is Titsias' optimal distribution of the inducing values for an SE kernel
+    (signal_var, ell) and that noise, with K_MM + jitter I in place of K_MM; the
+    reconstruction grid is npts^3 on [0, 1]^3 and the iso-value the median of the data."""
+    from scipy.linalg import cho_solve, cholesky, solve_triangular
+    c = int(np.ceil(m ** (1.0 / 3.0) - 1e-9))
+    r = _rng(seed, 1)
+    cells = r.choice(c ** 3, m, replace=False)
+    ijk = np.stack([cells % c, (cells // c) % c, cells // (c * c)], 1).astype(np.float64)
+    Z = (ijk + 0.25 + 0.5 * r.random((m, 3))) / c
+    g = np.linspace(0.0, 1.0, train_npts)
+    gz, gy, gx = np.meshgrid(g, g, g, indexing="ij")
+    P = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1)
+    y = _trig_field(P, seed) + np.sqrt(noise_var) * _rng(seed, 3).standard_normal(P.shape[0])
+    Kmm = _se_gram(Z, Z, signal_var, ell) + jitter * np.eye(m)
+    L = cholesky(Kmm, lower=True)
+    Phi = solve_triangular(L, _se_gram(Z, P, signal_var, ell), lower=True)   # L^-1 K_MN
+    B = np.eye(m) + (Phi @ Phi.T) / noise_var
+    LB = cholesky(B, lower=True)
+    R = solve_triangular(LB, L.T, lower=True)                                # LB^-1 L^T
+    A_M = R.T @ R                                                            # L B^-1 L^T
+    A_M = 0.5 * (A_M + A_M.T)
+    mu_M = L @ cho_solve((LB, True), Phi @ y) / noise_var
+    return Workload(name or f"sgpr{m}_{npts}", 3, SE, signal_var, np.array([ell] * 3), jitter, Z, mu_M,
+                    np.zeros(3), np.ones(3), np.array([npts] * 3, np.int64), float(np.median(y)), 1e-3, 4,
+                    _zbank(seed, n_samples, 3), seed, A_M)
+
+
 def random_small(seed: int, dim: int, m: int, npts, kind: int = SE, n_samples: int = 1600,
                  signal_var: float = 1.0, ell: float = 0.25, noise_var: float = 1e-4,
                  min_leaf: int = 1, alpha: float = 1e-3) -> Workload:
@@ -190,6 +254,9 @@ def make(name: str, seed: int = 0, **kw) -> Workload:
         return field3d_trig(seed, npts=128, **kw)
     if name == "cfg3_256":
         return field3d_trig(seed, npts=256, **kw)
+    if name.startswith("sgpr"):        # sgpr<m>_<npts>, e.g. sgpr500_128
+        mm, nn = name[4:].split("_")
+        return sgpr_field(seed, m=int(mm), npts=int(nn), **kw)
     if name.startswith("cfg3_"):
         return field3d_trig(seed, npts=int(name.split("_")[1]), **kw)
     raise KeyError(name)
