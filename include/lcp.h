@@ -13,7 +13,7 @@
  *  - Floating-point inputs are IEEE binary64.  Arrays are dense and row-major;
  *    grid vertices and cells are ordered with x fastest, then y, then z.
  *  - `stream` is a hipStream_t (NULL = the default stream).  All work is enqueued
- *    on it; only gp_fit_factor synchronises it (once, to read the factorisation
+ *    on it; only the gp_fit_* calls synchronise it (to read the factorisation
  *    status).  Calls that share a model or workspace must not run concurrently.
  *  - The library never allocates device memory: the caller passes the model
  *    memory and a workspace, sized by lcp_model_bytes / lcp_workspace_bytes, and
@@ -113,6 +113,32 @@ size_t lcp_model_bytes(int m, int dim);
  */
 int gp_fit_factor(const lcp_kernel* k, int m, const double* X, const double* y, void* model_mem,
                   size_t model_bytes, void* stream, lcp_model** out);
+
+/*
+ * gp_fit_sgpr -- factor a sparse GP model as eq. (sgp) gives it: inducing points M and the
+ * Gaussian N(mu_M, A_M) of the inducing values stored after SGPR fitting (Sec. 3).  The
+ * posterior at a set I is then mu = K_IM K_MM^-1 mu_M and
+ * Sigma = K_II - K_IM K_MM^-1 K_MI + K_IM K_MM^-1 A_M K_MM^-1 K_MI, and the preliminary
+ * node test of Alg. 1 reads the marginals N(mu_M_i, A_M_ii) (Sec. 4.3).
+ *   k        (host) kernel; k->noise_var is the jitter added to the diagonal of K_MM
+ *   m        number of inducing points, 1 <= m <= 1024
+ *   Z        m x dim inducing locations (device, binary64)
+ *   mu_M     m inducing means (device, binary64)
+ *   A_M      m x m inducing covariance, row-major, symmetric (device, binary64); only
+ *            read during the call
+ *   model_mem, model_bytes, out   as for gp_fit_factor (same lcp_model_bytes)
+ *   shift    (host, may be NULL) receives delta below
+ * The third term is folded into the stored factor: with K_MM + jitter I = L L^T and
+ * E = I - L^-1 A_M L^-T = F^T F (F lower), the model keeps T = F L^-1 in place of L^-1,
+ * so every LCP routine applies unchanged.  E is PSD whenever A_M <= K_MM + jitter I (a
+ * posterior covariance never exceeds its prior).  If a pivot of E is not above m eps the
+ * factorisation is repeated on E + delta I, delta = 16 m eps and then 100 times larger
+ * up to 1e-6; this raises each variance by delta ||L^-1 k*||^2 <= delta s2 and each
+ * covariance by delta (L^-1 k_p).(L^-1 k_q).  Synchronises `stream` once per attempt.
+ * Returns LCP_ENOTPD if K_MM + jitter I is numerically singular or E is not PSD to 1e-6.
+ */
+int gp_fit_sgpr(const lcp_kernel* k, int m, const double* Z, const double* mu_M, const double* A_M,
+                void* model_mem, size_t model_bytes, void* stream, double* shift, lcp_model** out);
 
 void gp_model_free(lcp_model* model);
 

@@ -95,11 +95,12 @@ __global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ U, int m
 }
 
 // Explicit inverse of L = U^T row by row: Linv[i][c] = -(sum_{k=c}^{i-1} L[i][k] Linv[k][c]) / L[i][i].
+__device__ __forceinline__ void amax_body(const double* __restrict__ Li, int mp, double* __restrict__ amax);
+
 __device__ __forceinline__ void trinv_body(const double* __restrict__ U, double* __restrict__ Li, int m, int mp,
                                            double* __restrict__ amax)
 {
     __shared__ double lrow[kMaxM];
-    __shared__ double wmax[16];
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int64_t t = tid; t < (int64_t)mp * mp; t += nt) Li[t] = 0.0;
     __syncthreads();
@@ -118,7 +119,14 @@ __device__ __forceinline__ void trinv_body(const double* __restrict__ U, double*
         }
         __syncthreads();
     }
-    // largest |Linv| and the power-of-two scale sA that brings it to [2^14, 2^15) (FP16 max is 65504)
+    amax_body(Li, mp, amax);
+}
+
+// Largest |Linv| and the power-of-two scale sA that brings it to [2^14, 2^15) (FP16 max is 65504).
+__device__ __forceinline__ void amax_body(const double* __restrict__ Li, int mp, double* __restrict__ amax)
+{
+    __shared__ double wmax[16];
+    const int tid = threadIdx.x, nt = blockDim.x;
     double mx = 0.0;
     for (int64_t t = tid; t < (int64_t)mp * mp; t += nt) mx = fmax(mx, fabs(Li[t]));
     for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
@@ -138,6 +146,11 @@ __global__ void __launch_bounds__(1024) k_trinv(const double* __restrict__ U, do
                                                 int mp, double* __restrict__ amax)
 {
     trinv_body(U, Li, m, mp, amax);
+}
+
+__global__ void __launch_bounds__(1024) k_amax(const double* __restrict__ Li, int mp, double* __restrict__ amax)
+{
+    amax_body(Li, mp, amax);
 }
 
 // a = Linv^T (Linv y): w = Linv y, then a_i = sum_{k >= i} Linv[k][i] w_k.
@@ -236,6 +249,91 @@ __global__ void k_frag(const double* __restrict__ Li, int mp, double* __restrict
     }
 }
 
+// ------------------------------------------------------------ sparse model (eq. (sgp))
+//
+// The third term of eq. (sgp) folds into the stored factor.  With K = K_MM + jitter I = L L^T,
+//   Q = K^-1 - K^-1 A_M K^-1 = L^-T E L^-1,   E = I - L^-1 A_M L^-T,
+// and E = F^T F with F lower triangular (the Cholesky factor of E taken in reversed index
+// order), Q = T^T T with T = F L^-1, again lower triangular.  The model keeps T where the
+// exact GP keeps L^-1, so var = s2 - ||T k*||^2 and the corner covariances
+// k(p,q) - (T k_p).(T k_q) come out of the unchanged posterior and cell kernels.
+
+// C = A B over mp x mp operands given by index functors; one 16 x 16 tile per work-group,
+// k staged through LDS 16 at a time.  Binary64; runs once per fit.
+template <class LA, class LB, class ST>
+__global__ void __launch_bounds__(256) k_gemm64(int mp, LA la, LB lb, ST st)
+{
+    __shared__ double As[16][17], Bs[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+    double c = 0.0;
+    for (int k0 = 0; k0 < mp; k0 += 16) {
+        As[ty][tx] = la(i, k0 + tx);
+        Bs[ty][tx] = lb(k0 + ty, j);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c = fma(As[ty][k], Bs[k][tx], c);
+        __syncthreads();
+    }
+    st(i, j, c);
+}
+
+struct RowMajor {
+    const double* p;
+    int ld;
+    __device__ double operator()(int i, int k) const { return p[(int64_t)i * ld + k]; }
+};
+struct Transposed {
+    const double* p;
+    int ld;
+    __device__ double operator()(int k, int j) const { return p[(int64_t)j * ld + k]; }
+};
+// F[i][k] = G[m-1-k][m-1-i] where the array holds G^T (row r = row r of G^T) after cholesky_body.
+struct ReversedFactor {
+    const double* p;
+    int ld, m;
+    __device__ double operator()(int i, int k) const
+    {
+        return (i < m && k < m) ? p[(int64_t)(m - 1 - i) * ld + (m - 1 - k)] : 0.0;
+    }
+};
+struct Store {
+    double* p;
+    int ld;
+    __device__ void operator()(int i, int j, double c) const { p[(int64_t)i * ld + j] = c; }
+};
+// E + delta I = I + delta I - W stored in reversed index order (zero outside the m x m block).
+struct StoreReversedE {
+    double* p;
+    int ld, m;
+    double delta;
+    __device__ void operator()(int i, int j, double w) const
+    {
+        if (i < m && j < m)
+            p[(int64_t)(m - 1 - i) * ld + (m - 1 - j)] = (i == j ? 1.0 + delta : 0.0) - w;
+        else
+            p[(int64_t)i * ld + j] = 0.0;
+    }
+};
+
+__global__ void k_pack_square(const double* __restrict__ A, int m, int mp, double* __restrict__ dst)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    int i = (int)(t / mp), j = (int)(t % mp);
+    dst[t] = (i < m && j < m) ? A[(int64_t)i * m + j] : 0.0;
+}
+
+// Sec. 4.3 with stored inducing values: the node test reads N(mu_M_i, A_M_ii).
+__global__ void k_obs_sparse(const double* __restrict__ mu, const double* __restrict__ A, int m,
+                             double* __restrict__ obs_mu, double* __restrict__ obs_var)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    obs_mu[i] = mu[i];
+    obs_var[i] = fmax(A[(int64_t)i * m + i], 0.0);
+}
+
 static void carve(Model& M, char* base)
 {
     int mp = M.m_pad;
@@ -301,6 +399,50 @@ hipError_t launch_factor_finish(Model& M, hipStream_t s)
     t.mean = M.obs_mu;
     t.var = M.obs_var;
     return launch_posterior(M, LCP_FP64, t, s);
+}
+
+// Sparse model, after launch_factor (K_MM + jitter I, mu_M in place of y) succeeded:
+// L^-1, a = K^-1 mu_M, the inducing marginals, then P = reversed(E + delta I) in A64 and
+// its Cholesky factor with status in info[1].
+hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, hipStream_t s)
+{
+    StageScope sc(s, ST_FACTOR);
+    const int mp = M.m_pad, m = M.m;
+    const int64_t n2 = (int64_t)mp * mp;
+    const dim3 tiles((unsigned)(mp / 16), (unsigned)(mp / 16));
+    if (first) {
+        hipLaunchKernelGGL(k_trinv, dim3(1), dim3(1024), 0, s, M.U, M.Linv, m, mp, M.amax);
+        hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, s, M.Linv, ybuf(M), M.a, m, mp);
+        hipLaunchKernelGGL(k_obs_sparse, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, ybuf(M), A, m,
+                           M.obs_mu, M.obs_var);
+        hipLaunchKernelGGL(k_pack_square, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, A, m, mp, M.A64);
+        // U <- L^-1 A_M (U held L^T, no longer needed)
+        hipLaunchKernelGGL((k_gemm64<RowMajor, RowMajor, Store>), tiles, dim3(256), 0, s, mp,
+                           RowMajor{M.Linv, mp}, RowMajor{M.A64, mp}, Store{M.U, mp});
+    }
+    // A64 <- reversed(I + delta I - (L^-1 A_M) L^-T)
+    hipLaunchKernelGGL((k_gemm64<RowMajor, Transposed, StoreReversedE>), tiles, dim3(256), 0, s, mp,
+                       RowMajor{M.U, mp}, Transposed{M.Linv, mp}, StoreReversedE{M.A64, mp, m, delta});
+    const double piv_min = (double)m * 2.220446049250313e-16;
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, M.A64, m, mp, piv_min, M.info + 1);
+    return hipGetLastError();
+}
+
+// After E factored: T = F L^-1 replaces L^-1, then scale and fragments.
+hipError_t launch_sparse_finish(Model& M, hipStream_t s)
+{
+    StageScope sc(s, ST_FACTOR);
+    const int mp = M.m_pad;
+    const int64_t n2 = (int64_t)mp * mp;
+    const dim3 tiles((unsigned)(mp / 16), (unsigned)(mp / 16));
+    hipLaunchKernelGGL((k_gemm64<ReversedFactor, RowMajor, Store>), tiles, dim3(256), 0, s, mp,
+                       ReversedFactor{M.A64, mp, M.m}, RowMajor{M.Linv, mp}, Store{M.U, mp});
+    hipError_t e = hipMemcpyAsync(M.Linv, M.U, sizeof(double) * (size_t)n2, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amax, dim3(1), dim3(1024), 0, s, M.Linv, mp, M.amax);
+    hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, mp, M.A64, M.A32,
+                       M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
+    return hipGetLastError();
 }
 
 size_t factor_batch_scratch(int nb)

@@ -218,6 +218,55 @@ int gp_fit_factor(const lcp_kernel* k, int m, const double* X, const double* y, 
     return ok();
 }
 
+int gp_fit_sgpr(const lcp_kernel* k, int m, const double* Z, const double* mu_M, const double* A_M,
+                void* model_mem, size_t model_bytes_, void* stream, double* shift, lcp_model** out)
+{
+    if (!k || !out) return fail(LCP_EINVAL, "kernel and out must not be NULL");
+    *out = nullptr;
+    if (shift) *shift = 0.0;
+    if (int r = check_kernel(k, m)) return r;
+    if (!Z || !mu_M || !A_M || !model_mem) return fail(LCP_EINVAL, "Z, mu_M, A_M and model_mem must not be NULL");
+    if (!aligned256(model_mem)) return fail(LCP_EINVAL, "model_mem must be 256-byte aligned");
+    if (model_bytes_ < model_bytes(m)) return fail(LCP_ENOMEM, "model memory %zu < %zu bytes", model_bytes_, model_bytes(m));
+    lcp_model* M = new (std::nothrow) lcp_model();
+    if (!M) return fail(LCP_ENOMEM, "host allocation failed");
+    init_model(*M, *k, m, model_mem);
+    hipStream_t s = (hipStream_t)stream;
+    auto status = [&](int idx, int* info) {
+        hipError_t e = hipMemcpyAsync(info, M->info + idx, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    };
+    hipError_t e = launch_factor(*M, Z, mu_M, s);
+    int info = 0;
+    if (e == hipSuccess) e = status(0, &info);
+    if (e != hipSuccess) { delete M; return dev_fail(e, "sparse factor"); }
+    if (info != 0) {
+        delete M;
+        return fail(LCP_ENOTPD, "K_MM + jitter I: Cholesky pivot %d is not above m * eps * max K_ii", info);
+    }
+    // E = I - L^-1 A_M L^-T is PSD when A_M <= K_MM + jitter I; a pivot at rounding level is
+    // met by factoring E + delta I, delta from 16 m eps up to 1e-6 in steps of 100.
+    double delta = 0.0;
+    for (;;) {
+        e = launch_sparse_e(*M, A_M, delta, delta == 0.0, s);
+        if (e == hipSuccess) e = status(1, &info);
+        if (e != hipSuccess) { delete M; return dev_fail(e, "sparse factor"); }
+        if (info == 0) break;
+        if (delta >= 1e-6) {
+            delete M;
+            return fail(LCP_ENOTPD, "A_M is not below K_MM + jitter I: I - L^-1 A_M L^-T has pivot %d at or "
+                        "below m * eps even when shifted by 1e-6", info);
+        }
+        delta = delta == 0.0 ? 16.0 * m * 2.220446049250313e-16 : fmin(delta * 100.0, 1e-6);
+    }
+    e = launch_sparse_finish(*M, s);
+    if (e != hipSuccess) { delete M; return dev_fail(e, "sparse factor finish"); }
+    if (shift) *shift = delta;
+    *out = M;
+    return ok();
+}
+
 void gp_model_free(lcp_model* model) { delete model; }
 
 int lcp_posterior_workspace(const lcp_model* M, int64_t n, int prec, size_t* bytes)

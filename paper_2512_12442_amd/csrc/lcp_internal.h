@@ -247,6 +247,9 @@ struct Model {
 size_t model_bytes(int m);
 hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t s);
 hipError_t launch_factor_finish(Model& M, hipStream_t s);
+// Sparse model of eq. (sgp), after launch_factor on K_MM + jitter I with mu_M as y.
+hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, hipStream_t s);
+hipError_t launch_sparse_finish(Model& M, hipStream_t s);
 size_t factor_batch_scratch(int nb);
 hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
                                int* info_dev, hipStream_t s);

@@ -46,7 +46,7 @@ class MC(C.Structure):
     _fields_ = [("n_samples", C.c_int), ("zbank", C.c_void_p)]
 
 
-EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor", "gp_model_free",
+EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor", "gp_fit_sgpr", "gp_model_free",
            "lcp_posterior_workspace", "lcp_dense_workspace", "lcp_adaptive_workspace", "gp_posterior",
            "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
@@ -73,6 +73,7 @@ def lib():
     L.lcp_model_bytes.restype = SZ
     L.lcp_model_bytes.argtypes = [C.c_int, C.c_int]
     L.gp_fit_factor.argtypes = [P, C.c_int, P, P, P, SZ, P, C.POINTER(P)]
+    L.gp_fit_sgpr.argtypes = [P, C.c_int, P, P, P, P, SZ, P, C.POINTER(C.c_double), C.POINTER(P)]
     L.gp_model_free.argtypes = [P]
     L.gp_model_free.restype = None
     L.lcp_posterior_workspace.argtypes = [P, I64, C.c_int, C.POINTER(SZ)]
@@ -134,9 +135,12 @@ def make_grid(dim, lo, hi, npts) -> Grid:
 
 
 class GPModel:
-    """A factored GP model (gp_fit_factor) living in caller-owned device memory."""
+    """A factored GP model living in caller-owned device memory: gp_fit_factor for
+    observations (X, y), or gp_fit_sgpr when A_M (the inducing covariance of eq. (sgp))
+    is given, with X the inducing points, y = mu_M and noise_var the jitter of K_MM."""
 
-    def __init__(self, kind, dim, signal_var, lengthscale, noise_var, X: torch.Tensor, y: torch.Tensor):
+    def __init__(self, kind, dim, signal_var, lengthscale, noise_var, X: torch.Tensor, y: torch.Tensor,
+                 A_M: torch.Tensor = None):
         L = lib()
         X = X.to(torch.float64).contiguous()
         y = y.to(torch.float64).contiguous()
@@ -151,8 +155,17 @@ class GPModel:
         self.device = X.device
         self._X, self._y = X, y
         h = C.c_void_p()
-        _check(L.gp_fit_factor(C.byref(self.k), self.m, _ptr(X), _ptr(y), _ptr(self.mem), nb, _stream(),
-                               C.byref(h)))
+        self.shift = 0.0
+        if A_M is None:
+            _check(L.gp_fit_factor(C.byref(self.k), self.m, _ptr(X), _ptr(y), _ptr(self.mem), nb, _stream(),
+                                   C.byref(h)))
+        else:
+            A_M = A_M.to(torch.float64).contiguous()
+            assert A_M.is_cuda and A_M.shape == (self.m, self.m)
+            sh = C.c_double()
+            _check(L.gp_fit_sgpr(C.byref(self.k), self.m, _ptr(X), _ptr(y), _ptr(A_M), _ptr(self.mem), nb,
+                                 _stream(), C.byref(sh), C.byref(h)))
+            self.shift = sh.value
         self.h = h
 
     def __del__(self):
@@ -165,7 +178,9 @@ class GPModel:
     def from_workload(cls, W, device="cuda"):
         X = torch.as_tensor(W.X, dtype=torch.float64, device=device)
         y = torch.as_tensor(W.y, dtype=torch.float64, device=device)
-        return cls(W.kind, W.dim, W.signal_var, list(W.lengthscale), W.noise_var, X, y)
+        A = getattr(W, "A_M", None)
+        A = None if A is None else torch.as_tensor(A, dtype=torch.float64, device=device)
+        return cls(W.kind, W.dim, W.signal_var, list(W.lengthscale), W.noise_var, X, y, A)
 
     # -------------------------------------------------------------- operations
     def posterior(self, Xq: torch.Tensor, prec="fp64"):

@@ -194,7 +194,7 @@ def _se_gram(A, B, s2, ell):
 
 
 def sgpr_field(seed: int, m: int = 500, npts: int = 128, train_npts: int = 32, n_samples: int = 1600,
-               signal_var: float = 0.5, ell: float = 0.12, noise_var: float = 1e-4, jitter: float = 1e-6,
+               signal_var: float = 1e-3, ell: float = 0.12, noise_var: float = 1e-4, jitter: float = 1e-6,
                name: Optional[str] = None) -> Workload:
     """Sparse GP model of eq. (sgp) standing in for the paper's fitted SGPR models
     (Sec. 5.3: 50 or 500 inducing points, RBF kernel, a training grid of the field).
