@@ -144,7 +144,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for rocprofv3 traffic counters)")
     ap.add_argument("--print-source-hash", action="store_true", help="print the posterior kernel source hash")
-    ap.add_argument("--workload", default="trig128", choices=["trig128", "local_blocks"],
+    ap.add_argument("--workload", default="trig128", choices=["trig128", "sgpr500", "local_blocks"],
                     help="trig128: the headline adaptive LCP; local_blocks: batched local GP models")
     ap.add_argument("--blocks", type=int, default=256, help="number of models for --workload local_blocks")
     args = ap.parse_args()
@@ -169,7 +169,15 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration()
-    W = workloads.field3d_trig(args.seed, m=500, npts=args.npts)
+    if args.workload == "sgpr500":
+        W = workloads.sgpr_field(args.seed, m=500, npts=args.npts)
+        wl = (f"sparse GP (eq. sgp) {args.npts}^3 grid, 500 inducing points on a jittered 8^3 lattice, "
+              f"mu_M/A_M from a 32^3 noisy training grid (noise 1e-4), SE l=0.12, s2=1e-3, jitter 1e-6, "
+              f"theta=median(data), alpha=1e-3, min leaf 4^3, N_s=1600")
+    else:
+        W = workloads.field3d_trig(args.seed, m=500, npts=args.npts)
+        wl = (f"trig field {args.npts}^3 grid, m=500 uniform observations, Matern-5/2 l=0.1, "
+              f"s2=1e-3, noise 1e-5, theta=median(y), alpha=1e-3, min leaf 4^3, N_s=1600")
     grid = lcp.grid_of(W)
     adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4)
     zb = torch.as_tensor(W.zbank, device=dev)
@@ -253,7 +261,7 @@ def main():
     achieved = flops / (dur_ms * 1e-3)
     roof = {"bound": "mfma", "kernel": f"k_post ({args.prec} posterior GEMM over leaf vertices)",
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": traffic_per_launch(args.prec, args.npts),
+            "traffic": traffic_per_launch(args.prec, args.npts) if args.workload == "trig128" else None,
             "avg_launch_ms": dur_ms, "launches_per_step": per_step_launches,
             "algorithmic_flop_per_launch": flops,
             "note": "algorithmic flop = leaf vertices x m(m+1); the 16-bit split runs 3 MFMA passes per flop"}
@@ -290,9 +298,7 @@ def main():
         "vs_baseline": None, "dtype": {"f16x3": "f16x3+f64", "bf16x3": "bf16x3+f64", "fp32": "f32+f64",
                                        "fp64": "f64"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": f"trig field {args.npts}^3 grid, m=500 uniform observations, Matern-5/2 l=0.1, "
-                               f"s2=1e-3, noise 1e-5, theta=median(y), alpha=1e-3, min leaf 4^3, N_s=1600",
-                   "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha, "precision": args.prec,
+        "config": {"workload": wl, "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha, "precision": args.prec,
                    "parallelism": "1 GPU"},
         "dense_fp64_ms_per_step": dense_ms,
         "dense_fp64_pts_per_s": (nvert / (dense_ms * 1e-3)) if dense_ms else None,

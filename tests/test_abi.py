@@ -61,6 +61,19 @@ def test_fit_rejects_small_or_misaligned_model_memory():
     assert rc == lcp.lcp.LCP_EINVAL and "aligned" in msg
 
 
+def test_sparse_fit_validates_on_the_host():
+    L = lcp.lib()
+    k = lcp.lcp.Kernel(0, 3, 1.0, (C.c_double * 3)(0.1, 0.1, 0.1), 1e-6)
+    fake = C.c_void_p(0x1000)     # never dereferenced: validation fails first
+    h, sh = C.c_void_p(), C.c_double(-1.0)
+    rc = L.gp_fit_sgpr(C.byref(k), 10, fake, fake, None, fake, 1 << 30, None, C.byref(sh), C.byref(h))
+    assert rc == lcp.lcp.LCP_EINVAL and "A_M" in L.lcp_last_error().decode() and not h.value and sh.value == 0.0
+    rc = L.gp_fit_sgpr(C.byref(k), 0, fake, fake, fake, fake, 1 << 30, None, None, C.byref(h))
+    assert rc == lcp.lcp.LCP_EINVAL and "m = 0" in L.lcp_last_error().decode()
+    rc = L.gp_fit_sgpr(C.byref(k), 10, fake, fake, fake, fake, 16, None, None, C.byref(h))
+    assert rc == lcp.lcp.LCP_ENOMEM
+
+
 def test_backward_reports_not_supported():
     L = lcp.lib()
     rc = L.lcp_backward(None, None, 0.0, None, None, None, None, None, 0, None)
