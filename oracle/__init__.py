@@ -60,6 +60,8 @@ def lib():
         _lib.orc_fit.argtypes = [C.c_int, C.c_int, C.c_double, P, C.c_double, C.c_int, P, P, P, P]
         _lib.orc_posterior.argtypes = [P, C.c_int64, P, P, P, P]
         _lib.orc_posterior_grad.argtypes = [P, P, P, P, P, P]
+        _lib.orc_kernel_dlogell.argtypes = [C.c_int, C.c_int, C.c_double, P, P, P, P]
+        _lib.orc_posterior_backward.argtypes = [P, C.c_int64, P, P, P, P, P]
         _lib.orc_grid_posterior.argtypes = [P, P, P, P]
         _lib.orc_chol_sd.argtypes = [C.c_int, P, P, C.c_double]
         _lib.orc_mc_count.restype = C.c_int64
@@ -160,6 +162,25 @@ def posterior_grad(M: FitModel, x):
     dm, dv = np.zeros(M.dim), np.zeros(M.dim)
     lib().orc_posterior_grad(C.byref(M.s), _p(x), C.byref(mean), C.byref(var), _p(dm), _p(dv))
     return mean.value, var.value, dm, dv
+
+
+def posterior_backward(M: FitModel, P, gmean=None, gvar=None):
+    """Adjoint of the posterior at points P: (dL/dy, dL/dlog(ell)) for upstream dL/dmean, dL/dvar."""
+    P = _f64(P).reshape(-1, M.dim)
+    n = P.shape[0]
+    gm = None if gmean is None else _f64(gmean)
+    gv = None if gvar is None else _f64(gvar)
+    dy, dl = np.zeros(M.m), np.zeros(M.dim)
+    rc = lib().orc_posterior_backward(C.byref(M.s), n, _p(P), _p(gm), _p(gv), _p(dy), _p(dl))
+    assert rc == ORC_OK, rc
+    return dy, dl
+
+
+def kernel_dlogell(kind, dim, s2, ell, x, z):
+    ell = _f64(np.resize(np.asarray(ell, float), 3))
+    g = np.zeros(dim)
+    lib().orc_kernel_dlogell(kind, dim, s2, _p(ell), _p(_f64(x)), _p(_f64(z)), _p(g))
+    return g
 
 
 def grid_posterior(M: FitModel, W):

@@ -33,6 +33,7 @@
 #include <omp.h>
 
 #define ORC_OK 0
+#define ORC_EINVAL 1
 #define ORC_ENOTPD 2
 #define ORC_ECAP 3
 #define ORC_ENOMEM 4
@@ -287,6 +288,97 @@ static void posterior_grad_point(const orc_model* M, const double* x, double* me
         for (int j = 0; j < m; ++j) s += v[j] * w[j];
         dvar[d] = -2.0 * s;
     }
+}
+
+/* d k(x, z) / d log(ell_d): with r^2 = sum_d (x_d - z_d)^2 / ell_d^2, d r^2 / d log(ell_d) =
+ * -2 (x_d - z_d)^2 / ell_d^2, times dk/d(r^2) (-k/2 for SE, -(5/6) s2 (1 + sqrt5 r) e^(-sqrt5 r)
+ * for Matern-5/2). */
+void orc_kernel_dlogell(int kind, int dim, double s2, const double* ell, const double* x, const double* z,
+                        double* g)
+{
+    double r2 = scaled_r2(dim, ell, x, z);
+    double dk_dr2;
+    if (kind == 0) {
+        dk_dr2 = -0.5 * s2 * exp(-0.5 * r2);
+    } else {
+        double r = sqrt(r2);
+        dk_dr2 = -(5.0 / 6.0) * s2 * (1.0 + sqrt(5.0) * r) * exp(-sqrt(5.0) * r);
+    }
+    for (int d = 0; d < dim; ++d) {
+        double t = (x[d] - z[d]) / ell[d];
+        g[d] = dk_dr2 * (-2.0 * t * t);
+    }
+}
+
+/*
+ * Adjoint of the exact-GP posterior (eq. (sgp) with the inducing set equal to the
+ * observations) at n query points, for upstream gradients gm = dL/dmean and gv = dL/dvar
+ * (either may be NULL for zero).  With K = k(X, X) + noise I, a = K^-1 y, w = K^-1 k*:
+ *   dmean/dy = w,                       dvar/dy = 0,
+ *   dmean/dlog(ell_d) = dk*_d . a - w^T dK_d a,
+ *   dvar/dlog(ell_d)  = -2 dk*_d . w + w^T dK_d w,
+ * where dk*_d and dK_d are the derivatives of k* and K with respect to log(ell_d).
+ * Point by point, in that form; dy (m) and dlogell (dim) receive the sums.
+ */
+int orc_posterior_backward(const orc_model* M, int64_t n, const double* P, const double* gm, const double* gv,
+                           double* dy, double* dlogell)
+{
+    if (M->A) return ORC_EINVAL;
+    int m = M->m, D = M->dim;
+    double* dK = (double*)malloc(sizeof(double) * (size_t)D * m * m);
+    double* dKa = (double*)malloc(sizeof(double) * (size_t)D * m);
+    double* k = (double*)malloc(sizeof(double) * (size_t)m);
+    double* t = (double*)malloc(sizeof(double) * (size_t)m);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    double* dk = (double*)malloc(sizeof(double) * (size_t)D * m);
+    if (!dK || !dKa || !k || !t || !w || !dk) {
+        free(dK); free(dKa); free(k); free(t); free(w); free(dk);
+        return ORC_ENOMEM;
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double g[3];
+            orc_kernel_dlogell(M->kind, D, M->s2, M->ell, M->X + (int64_t)i * D, M->X + (int64_t)j * D, g);
+            for (int d = 0; d < D; ++d) dK[((int64_t)d * m + i) * m + j] = g[d];
+        }
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += dK[((int64_t)d * m + i) * m + j] * M->a[j];
+            dKa[(int64_t)d * m + i] = s;
+        }
+    for (int j = 0; j < m; ++j) dy[j] = 0.0;
+    for (int d = 0; d < D; ++d) dlogell[d] = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        const double* x = P + p * D;
+        double g1 = gm ? gm[p] : 0.0, g2 = gv ? gv[p] : 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double* xj = M->X + (int64_t)j * D;
+            double g[3];
+            k[j] = orc_kernel(M->kind, D, M->s2, M->ell, x, xj);
+            orc_kernel_dlogell(M->kind, D, M->s2, M->ell, x, xj, g);
+            for (int d = 0; d < D; ++d) dk[(int64_t)d * m + j] = g[d];
+        }
+        forward_sub(m, M->L, k, t);
+        backward_sub_t(m, M->L, t, w);
+        for (int j = 0; j < m; ++j) dy[j] += g1 * w[j];
+        for (int d = 0; d < D; ++d) {
+            const double* dkd = dk + (int64_t)d * m;
+            const double* dKd = dK + (int64_t)d * m * m;
+            double dka = 0.0, wdKa = 0.0, dkw = 0.0, wdKw = 0.0;
+            for (int j = 0; j < m; ++j) dka += dkd[j] * M->a[j];
+            for (int j = 0; j < m; ++j) wdKa += w[j] * dKa[(int64_t)d * m + j];
+            for (int j = 0; j < m; ++j) dkw += dkd[j] * w[j];
+            for (int i = 0; i < m; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < m; ++j) s += dKd[(int64_t)i * m + j] * w[j];
+                wdKw += w[i] * s;
+            }
+            dlogell[d] += g1 * (dka - wdKa) + g2 * (-2.0 * dkw + wdKw);
+        }
+    }
+    free(dK); free(dKa); free(k); free(t); free(w); free(dk);
+    return ORC_OK;
 }
 
 int orc_posterior_grad(const orc_model* M, const double* x, double* mean, double* var, double* dmean, double* dvar)
