@@ -228,6 +228,30 @@ int lcp_dense_batch(const lcp_model_batch* batch, const lcp_grid* grids, const d
                     int prec, float* lcp, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * gp_posterior_backward -- adjoint of gp_posterior (Sec. 3, eq. (sgp) in its exact-GP form)
+ * with respect to the observation values y and the log-lengthscales log(ell_d).  Given
+ * upstream gradients g = dL/dmean and h = dL/dvar at n query points, with K = k(X, X) +
+ * noise I, a = K^-1 y and w_p = K^-1 k*_p:
+ *   dL/dy          = sum_p g_p w_p
+ *   dL/dlog(ell_d) = sum_p g_p (dk*_p,d . a - w_p^T dK_d a) + h_p (-2 dk*_p,d . w_p + w_p^T dK_d w_p)
+ * where dk*_d, dK_d are derivatives of k* and K with respect to log(ell_d).  K* is
+ * regenerated, never stored; W = K^-1 K*^T runs on MFMA in `prec` (LCP_FP64 or LCP_FP32,
+ * FP64 sums either way).
+ *   model      from gp_fit_factor (LCP_ENOTSUPPORTED for a gp_fit_sgpr model)
+ *   n, Xq      n >= 0 query points, n x dim binary64 (device)
+ *   dL_dmean, dL_dvar   n binary64 each (device); either may be NULL (zero)
+ *   dL_dy      m binary64 (device), overwritten
+ *   dL_dloglen dim binary64 (device), overwritten
+ *   ws, ws_bytes   256-byte aligned workspace of gp_posterior_backward_workspace bytes
+ *                  (about n * m_pad * 8 (FP64) or 4 (FP32) bytes plus O(m^2))
+ * Results are reproducible bit for bit (every sum runs in a fixed order).  Enqueued only.
+ */
+int gp_posterior_backward_workspace(const lcp_model* model, int64_t n, int prec, size_t* bytes);
+int gp_posterior_backward(const lcp_model* model, int64_t n, const double* Xq, int prec, const double* dL_dmean,
+                          const double* dL_dvar, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
  * lcp_backward -- adjoint of the LCP field with respect to the observation values and
  * log-lengthscales.  Not provided by this build: the Monte Carlo estimator of Sec. 4 is
  * piecewise constant in its inputs.  Always returns LCP_ENOTSUPPORTED.

@@ -7,5 +7,5 @@ runs in the HIP library liblcp.so (C ABI in include/lcp.h); this package only ma
 arguments.
 """
 from .lcp import (FP32, FP64, MATERN52, MIXED_BF16X3, MIXED_F16X3, PRECISIONS, SE, Adapt, GPModel, GPModelBatch,  # noqa: F401
-                  Grid, LcpError,
-                  StageTimer, adapt_of, grid_of, lib, make_grid)
+                  GPPosterior, Grid, LcpError,
+                  StageTimer, adapt_of, grid_of, lib, make_grid, posterior_fn)

@@ -1,0 +1,369 @@
+// Adjoint of the posterior (exact-GP form of eq. (sgp)) with respect to the observation
+// values y and the log-lengthscales.  With K = k(X, X) + noise I, a = K^-1 y, w_p = K^-1 k*_p
+// and upstream gradients g_p = dL/dmean_p, h_p = dL/dvar_p at n query points:
+//
+//   dL/dy             = b = sum_p g_p w_p
+//   dL/dlog(ell_d)    = sum_p sum_j dk_pj,d (g_p a_j - 2 h_p w_pj)            (T_d)
+//                     + sum_jl dK_d[j][l] (G[j][l] - b_j a_l)                  (P_d)
+//   G                 = sum_p h_p w_p w_p^T
+//
+// where dk and dK are derivatives with respect to log(ell_d).  The pass runs:
+//   1. K^-1 = L^-T L^-1 (binary64) in the posterior kernel's fragment order;
+//   2. W = K^-1 K*^T for all points on MFMA (the posterior kernel with a full operand,
+//      K* generated on the fly and never stored), W column-major;
+//   3. per point chunk: T_d partials and b partials, kernel derivatives recomputed;
+//   4. G by a binary64 symmetric rank-n product over point splits (upper blocks);
+//   5. P_d over all (j, l) pairs, then the ordered sums of every partial.
+// Every sum runs in a fixed order, so results are reproducible bit for bit.
+#include "lcp_internal.h"
+
+namespace lcp {
+
+namespace {
+
+constexpr int kBwdChunk = 64;       // points per chunk of the points pass
+constexpr int kBwdGridP = 1024;     // work-groups of the points pass (partials)
+constexpr int kBwdGridQ = 1024;     // work-groups of the pairs pass (partials)
+constexpr int kBwdSplitPts = 4096;  // points per split of the rank-n product
+constexpr int kBwdMaxSplit = 32;
+
+// K^-1[i][j] = sum_k Linv[k][i] Linv[k][j], 16 x 16 tiles through LDS.
+__global__ void __launch_bounds__(256) k_kinv(const double* __restrict__ Li, int mp, double* __restrict__ Ki)
+{
+    __shared__ double As[16][17], Bs[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+    double c = 0.0;
+    for (int k0 = 0; k0 < mp; k0 += 16) {
+        As[ty][tx] = Li[(int64_t)(k0 + tx) * mp + blockIdx.y * 16 + ty];   // Linv^T[i][k]
+        Bs[ty][tx] = Li[(int64_t)(k0 + ty) * mp + j];                      // Linv[k][j]
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c = fma(As[ty][k], Bs[k][tx], c);
+        __syncthreads();
+    }
+    Ki[(int64_t)i * mp + j] = c;
+}
+
+// 16 x 16 x 4 fragment order: fragment (i, s), lane l holds X[16 i + l % 16][4 s + l / 16].
+__global__ void k_frag_full(const double* __restrict__ Ki, int mp, double* __restrict__ F64, float* __restrict__ F32)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    const int64_t frag = t / 64;
+    const int l = (int)(t % 64);
+    const int ks = mp / 4;
+    const int i = (int)(frag / ks), s = (int)(frag % ks);
+    const double x = Ki[(int64_t)(16 * i + l % 16) * mp + 4 * s + l / 16];
+    F64[t] = x;
+    F32[t] = (float)x;
+}
+
+struct BwdArgs {
+    KParams kp;
+    int m, mp, dim;
+    const double* X;       // m_pad x 4
+    const double* alpha;   // a = K^-1 y
+    const void* W;         // column p at p * ldw (binary64 or binary32)
+    int64_t ldw;
+    int64_t n;
+    const double* P;       // n x dim query points
+    const double* gm;      // dL/dmean (may be null)
+    const double* gv;      // dL/dvar (may be null)
+    double* bpart;         // [kBwdGridP][mp]
+    double* tpart;         // [kBwdGridP][4]
+};
+
+__device__ __forceinline__ double block_sum256(double v, double* red)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Each work-group walks point chunks blockIdx.x, blockIdx.x + gridDim.x, ...; thread t owns
+// observations j = t, t + 256, ... (m <= 1024) and keeps their b partials in registers.
+template <class T>
+__global__ void __launch_bounds__(256) k_bwd_points(BwdArgs A)
+{
+    __shared__ double red[4];
+    constexpr int J = 4;
+    const int tid = threadIdx.x;
+    const T* __restrict__ W = (const T*)A.W;
+    const double ie0 = A.kp.inv_ell[0], ie1 = A.kp.inv_ell[1], ie2 = A.kp.inv_ell[2];
+    double xj[J][3], aj[J], bacc[J];
+#pragma unroll
+    for (int u = 0; u < J; ++u) {
+        const int j = tid + 256 * u;
+        const bool live = j < A.m;
+        xj[u][0] = live ? A.X[(size_t)j * 4 + 0] : 0.0;
+        xj[u][1] = live ? A.X[(size_t)j * 4 + 1] : 0.0;
+        xj[u][2] = live ? A.X[(size_t)j * 4 + 2] : 0.0;
+        aj[u] = live ? A.alpha[j] : 0.0;
+        bacc[u] = 0.0;
+    }
+    double tacc[3] = {0.0, 0.0, 0.0};
+    const int64_t nchunks = (A.n + kBwdChunk - 1) / kBwdChunk;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t p1 = (c + 1) * kBwdChunk < A.n ? (c + 1) * kBwdChunk : A.n;
+        for (int64_t p = c * kBwdChunk; p < p1; ++p) {
+            const double px = A.P[p * A.dim + 0], py = A.P[p * A.dim + 1];
+            const double pz = A.dim > 2 ? A.P[p * A.dim + 2] : 0.0;
+            const double g1 = A.gm ? A.gm[p] : 0.0, g2 = A.gv ? A.gv[p] : 0.0;
+#pragma unroll
+            for (int u = 0; u < J; ++u) {
+                const int j = tid + 256 * u;
+                if (j >= A.m) continue;
+                const double t0 = (px - xj[u][0]) * ie0, t1 = (py - xj[u][1]) * ie1, t2 = (pz - xj[u][2]) * ie2;
+                const double r2 = fma(t2, t2, fma(t1, t1, t0 * t0));
+                double kv, f;
+                kernel_val_dfac(A.kp, r2, &kv, &f);
+                const double w = (double)W[p * A.ldw + j];
+                // dk/dlog(ell_d) = -f t_d^2 (f = 2 dk/d(r^2))
+                const double coef = -f * fma(-2.0 * g2, w, g1 * aj[u]);
+                tacc[0] = fma(coef, t0 * t0, tacc[0]);
+                tacc[1] = fma(coef, t1 * t1, tacc[1]);
+                tacc[2] = fma(coef, t2 * t2, tacc[2]);
+                bacc[u] = fma(g1, w, bacc[u]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < J; ++u) {
+        const int j = tid + 256 * u;
+        if (j < A.mp) A.bpart[(size_t)blockIdx.x * A.mp + j] = bacc[u];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double s = block_sum256(tacc[d], red);
+        if (tid == 0) A.tpart[(size_t)blockIdx.x * 4 + d] = s;
+    }
+}
+
+// b_j = sum over the points pass's work-groups, in order.
+__global__ void k_bwd_reduce_b(const double* __restrict__ bpart, int nparts, int mp, double* __restrict__ b)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= mp) return;
+    double s = 0.0;
+    for (int q = 0; q < nparts; ++q) s += bpart[(size_t)q * mp + j];
+    b[j] = s;
+}
+
+// G partial of split blockIdx.y over the upper 64 x 64 block pair blockIdx.x:
+// Gpart[s][j][l] = sum_{p in split} h_p W[p][j] W[p][l].
+template <class T>
+__global__ void __launch_bounds__(256) k_bwd_syrk(const T* __restrict__ W, int64_t ldw, int64_t n,
+                                                  const double* __restrict__ h, int mp, int64_t split_pts,
+                                                  double* __restrict__ Gpart)
+{
+    __shared__ double As[16][68], Bs[16][68];
+    const int nb = mp / 64;
+    // block pair index -> (jb, lb), jb <= lb
+    int rem = blockIdx.x, jb = 0;
+    while (rem >= nb - jb) { rem -= nb - jb; ++jb; }
+    const int lb = jb + rem;
+    const int j0 = jb * 64, l0 = lb * 64;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int64_t pbeg = (int64_t)blockIdx.y * split_pts;
+    const int64_t pend = pbeg + split_pts < n ? pbeg + split_pts : n;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    const int lk = tid >> 4, lc = (tid & 15) * 4;     // loader: point row lk, columns lc..lc+3
+    for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+        const int64_t p = p0 + lk;
+        const bool live = p < pend;
+        const double hp = live ? h[p] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            As[lk][lc + e] = live ? (double)W[p * ldw + j0 + lc + e] : 0.0;
+            Bs[lk][lc + e] = live ? hp * (double)W[p * ldw + l0 + lc + e] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[k][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[k][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+    double* G = Gpart + (size_t)blockIdx.y * mp * mp;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) G[(size_t)(j0 + ty * 4 + r) * mp + l0 + tx * 4 + c] = acc[r][c];
+}
+
+// P_d partials over all (j, l): dK_d[j][l] (G[j][l] - b_j a_l).
+__global__ void __launch_bounds__(256) k_bwd_pairs(KParams kp, int m, int mp, const double* __restrict__ X,
+                                                   const double* __restrict__ alpha, const double* __restrict__ b,
+                                                   const double* __restrict__ Gpart, int nsplit,
+                                                   double* __restrict__ ppart)
+{
+    __shared__ double red[4];
+    double pacc[3] = {0.0, 0.0, 0.0};
+    const int64_t npairs = (int64_t)m * m;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < npairs; t += (int64_t)gridDim.x * 256) {
+        const int j = (int)(t / m), l = (int)(t % m);
+        const double t0 = (X[j * 4 + 0] - X[l * 4 + 0]) * kp.inv_ell[0];
+        const double t1 = (X[j * 4 + 1] - X[l * 4 + 1]) * kp.inv_ell[1];
+        const double t2 = (X[j * 4 + 2] - X[l * 4 + 2]) * kp.inv_ell[2];
+        const double r2 = fma(t2, t2, fma(t1, t1, t0 * t0));
+        double kv, f;
+        kernel_val_dfac(kp, r2, &kv, &f);
+        // G is stored in the upper block pairs only
+        const size_t gi = (j / 64 <= l / 64) ? (size_t)j * mp + l : (size_t)l * mp + j;
+        double g = 0.0;
+        for (int s = 0; s < nsplit; ++s) g += Gpart[(size_t)s * mp * mp + gi];
+        const double coef = -f * fma(-b[j], alpha[l], g);
+        pacc[0] = fma(coef, t0 * t0, pacc[0]);
+        pacc[1] = fma(coef, t1 * t1, pacc[1]);
+        pacc[2] = fma(coef, t2 * t2, pacc[2]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double s = block_sum256(pacc[d], red);
+        if (threadIdx.x == 0) ppart[(size_t)blockIdx.x * 4 + d] = s;
+    }
+}
+
+__global__ void k_bwd_finish(const double* __restrict__ b, int m, const double* __restrict__ tpart, int ntp,
+                             const double* __restrict__ ppart, int npp, int dim, double* __restrict__ dy,
+                             double* __restrict__ dlogell)
+{
+    for (int j = threadIdx.x; j < m; j += blockDim.x) dy[j] = b[j];
+    if (threadIdx.x < dim) {
+        const int d = threadIdx.x;
+        double t = 0.0, p = 0.0;
+        for (int q = 0; q < ntp; ++q) t += tpart[(size_t)q * 4 + d];
+        for (int q = 0; q < npp; ++q) p += ppart[(size_t)q * 4 + d];
+        dlogell[d] = t + p;
+    }
+}
+
+struct BwdLayout {
+    size_t kinv, f64, f32, w, mean, var, bpart, tpart, b, gpart, ppart, total;
+    int nsplit;
+};
+
+BwdLayout bwd_layout(const Model& M, int64_t n, int prec)
+{
+    BwdLayout L{};
+    const size_t mp = (size_t)M.m_pad;
+    const size_t es = prec == LCP_FP64 ? 8 : 4;
+    L.nsplit = (int)((n + kBwdSplitPts - 1) / kBwdSplitPts);
+    if (L.nsplit > kBwdMaxSplit) L.nsplit = kBwdMaxSplit;
+    if (L.nsplit < 1) L.nsplit = 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+    L.kinv = take(8 * mp * mp);
+    L.f64 = take(8 * mp * mp);
+    L.f32 = take(4 * mp * mp);
+    L.w = take(es * mp * (size_t)(n > 0 ? n : 1));
+    L.mean = take(8 * (size_t)(n > 0 ? n : 1));
+    L.var = take(8 * (size_t)(n > 0 ? n : 1));
+    L.bpart = take(8 * mp * kBwdGridP);
+    L.tpart = take(8 * 4 * kBwdGridP);
+    L.b = take(8 * mp);
+    L.gpart = take(8 * mp * mp * (size_t)L.nsplit);
+    L.ppart = take(8 * 4 * kBwdGridQ);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+size_t posterior_backward_ws(const Model& M, int64_t n, int prec) { return bwd_layout(M, n, prec).total; }
+
+hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq, int prec, const double* gm,
+                                     const double* gv, double* dy, double* dlogell, char* ws, hipStream_t s)
+{
+    const BwdLayout L = bwd_layout(M, n, prec);
+    const int mp = M.m_pad;
+    const int64_t n2 = (int64_t)mp * mp;
+    double* Kinv = (double*)(ws + L.kinv);
+    double* F64 = (double*)(ws + L.f64);
+    float* F32 = (float*)(ws + L.f32);
+    void* W = ws + L.w;
+    double* bpart = (double*)(ws + L.bpart);
+    double* tpart = (double*)(ws + L.tpart);
+    double* b = (double*)(ws + L.b);
+    double* gpart = (double*)(ws + L.gpart);
+    double* ppart = (double*)(ws + L.ppart);
+    {
+        StageScope sc(s, ST_FACTOR);
+        hipLaunchKernelGGL(k_kinv, dim3((unsigned)(mp / 16), (unsigned)(mp / 16)), dim3(256), 0, s, M.Linv, mp, Kinv);
+        hipLaunchKernelGGL(k_frag_full, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, Kinv, mp, F64, F32);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        PostTask t{};
+        t.mode = COL_POINTS;
+        t.group = 1;
+        t.n_points = n;
+        t.pts = Xq;
+        t.pstride = M.dim;
+        t.mean = (double*)(ws + L.mean);
+        t.var = (double*)(ws + L.var);
+        t.V = W;
+        t.vld = mp;
+        t.dense = 1;
+        t.stage = ST_POSTERIOR;
+        e = launch_posterior_operand(M, prec, t, prec == LCP_FP64 ? (const void*)F64 : (const void*)F32, s);
+        if (e != hipSuccess) return e;
+    }
+    StageScope sc(s, ST_MISC);
+    BwdArgs A{};
+    A.kp = M.kp;
+    A.m = M.m;
+    A.mp = mp;
+    A.dim = M.dim;
+    A.X = M.X;
+    A.alpha = M.a;
+    A.W = W;
+    A.ldw = mp;
+    A.n = n;
+    A.P = Xq;
+    A.gm = gm;
+    A.gv = gv;
+    A.bpart = bpart;
+    A.tpart = tpart;
+    if (prec == LCP_FP64) hipLaunchKernelGGL(k_bwd_points<double>, dim3(kBwdGridP), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(k_bwd_points<float>, dim3(kBwdGridP), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_bwd_reduce_b, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, bpart, kBwdGridP, mp, b);
+    const int nb = mp / 64;
+    const unsigned npairs_blk = (unsigned)(nb * (nb + 1) / 2);
+    if (gv && n > 0) {
+        const int64_t split_pts = (n + L.nsplit - 1) / L.nsplit;
+        if (prec == LCP_FP64)
+            hipLaunchKernelGGL(k_bwd_syrk<double>, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
+                               (const double*)W, (int64_t)mp, n, gv, mp, split_pts, gpart);
+        else
+            hipLaunchKernelGGL(k_bwd_syrk<float>, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
+                               (const float*)W, (int64_t)mp, n, gv, mp, split_pts, gpart);
+    } else {
+        e = launch_fill_f64(gpart, 0.0, n2, s);
+        if (e != hipSuccess) return e;
+    }
+    const int nsplit = (gv && n > 0) ? L.nsplit : 1;
+    hipLaunchKernelGGL(k_bwd_pairs, dim3(kBwdGridQ), dim3(256), 0, s, M.kp, M.m, mp, M.X, M.a, b, gpart, nsplit,
+                       ppart);
+    hipLaunchKernelGGL(k_bwd_finish, dim3(1), dim3(256), 0, s, b, M.m, tpart, kBwdGridP, ppart, kBwdGridQ, M.dim, dy,
+                       dlogell);
+    return hipGetLastError();
+}
+
+}  // namespace lcp

@@ -677,6 +677,13 @@ hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s)
+{
+    StageScope sc(s, ST_MISC);
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s)
 {
     StageScope sc(s, ST_MISC);

@@ -260,12 +260,22 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
                     dacc[ct][r] = fma(v, base, dacc[ct][r]);
                 }
                 if (G == 1 && T.V) {
-                    // quad-major V: rows 4 q .. 4 q + 3 of column p at (q * n_points + p) * 4
+                    // quad-major V: rows 4 q .. 4 q + 3 of column p at (q * n_points + p) * 4.
+                    // The binary64 MFMA leaves row gl + 4 r of the block in register r (binary32:
+                    // row 4 gl + r); quad-major binary64 V keeps that order, a permutation of the
+                    // rows inside each 16-row block that no dot product of two columns sees.
                     const int64_t p = col0 + 16 * ct + cl;
                     if (p < npts) {
-                        const size_t o = ((size_t)(4 * rb + gl) * T.n_points + p) * 4;
+                        const size_t o = T.vld ? (size_t)p * T.vld + 4 * (4 * rb + gl)
+                                               : ((size_t)(4 * rb + gl) * T.n_points + p) * 4;
                         if constexpr (sizeof(Elem) == 8) {
-                            *(d4*)((double*)T.V + o) = acc[ct];
+                            if (T.vld) {
+                                double* c = (double*)T.V + (size_t)p * T.vld + 16 * rb + gl;
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) c[4 * r] = acc[ct][r];
+                            } else {
+                                *(d4*)((double*)T.V + o) = acc[ct];
+                            }
                         } else {
                             *(f4*)((float*)T.V + o) = f4{(float)acc[ct][0], (float)acc[ct][1], (float)acc[ct][2],
                                                          (float)acc[ct][3]};
@@ -291,8 +301,8 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
                 accB[ct] = typename P::Acc{0, 0, 0, 0};
             }
             constexpr int U = P::KS == 4 ? 4 : 2;
-            const int needA = (16 * (ra + 1) + P::KS - 1) / P::KS;
-            const int needB = (16 * (rbb + 1) + P::KS - 1) / P::KS;
+            const int needA = T.dense ? nks_total : (16 * (ra + 1) + P::KS - 1) / P::KS;
+            const int needB = T.dense ? nks_total : (16 * (rbb + 1) + P::KS - 1) / P::KS;
             const int gA = (needA + 2 * U - 1) / (2 * U) * (2 * U);
             const int gB = hasB ? (needB + 2 * U - 1) / (2 * U) * (2 * U) : gA;
             const int glast = nks_total - U;
@@ -842,6 +852,16 @@ hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks,
         if (e == hipSuccess) e = launch_batch_t<PB3, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
     }
     return e;
+}
+
+hipError_t launch_posterior_operand(const Model& M, int prec, const PostTask& t, const void* A0, hipStream_t s)
+{
+    if (t.n_points <= 0) return hipSuccess;
+    StageScope sc(s, t.stage);
+    if (t.group != 1) return hipErrorInvalidValue;
+    if (prec == LCP_FP64) return launch_t<P64, 16, 1>(M, t, s, A0, nullptr);
+    if (prec == LCP_FP32) return launch_t<P32, 32, 1>(M, t, s, A0, nullptr);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s)

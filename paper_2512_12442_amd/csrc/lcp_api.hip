@@ -262,6 +262,7 @@ int gp_fit_sgpr(const lcp_kernel* k, int m, const double* Z, const double* mu_M,
     }
     e = launch_sparse_finish(*M, s);
     if (e != hipSuccess) { delete M; return dev_fail(e, "sparse factor finish"); }
+    M->sparse = 1;
     if (shift) *shift = delta;
     *out = M;
     return ok();
@@ -328,6 +329,34 @@ int gp_posterior(const lcp_model* M, int64_t n, const double* Xq, int prec, doub
     t.stage = ST_POSTERIOR;
     hipError_t e = launch_posterior(*M, prec, t, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, "gp_posterior");
+    return ok();
+}
+
+int gp_posterior_backward_workspace(const lcp_model* M, int64_t n, int prec, size_t* bytes)
+{
+    if (!M || !bytes) return fail(LCP_EINVAL, "model and bytes must not be NULL");
+    if (n < 0) return fail(LCP_EINVAL, "n < 0");
+    if (prec != LCP_FP64 && prec != LCP_FP32) return fail(LCP_EINVAL, "prec must be LCP_FP64 or LCP_FP32");
+    *bytes = posterior_backward_ws(*M, n, prec);
+    return ok();
+}
+
+int gp_posterior_backward(const lcp_model* M, int64_t n, const double* Xq, int prec, const double* dL_dmean,
+                          const double* dL_dvar, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
+                          void* stream)
+{
+    if (!M) return fail(LCP_EINVAL, "model is NULL");
+    if (M->sparse) return fail(LCP_ENOTSUPPORTED, "gp_posterior_backward: the model comes from gp_fit_sgpr");
+    if (n < 0) return fail(LCP_EINVAL, "n < 0");
+    if (prec != LCP_FP64 && prec != LCP_FP32) return fail(LCP_EINVAL, "prec must be LCP_FP64 or LCP_FP32");
+    if (!dL_dy || !dL_dloglen) return fail(LCP_EINVAL, "dL_dy and dL_dloglen must not be NULL");
+    if (n > 0 && !Xq) return fail(LCP_EINVAL, "Xq must not be NULL");
+    const size_t need = posterior_backward_ws(*M, n, prec);
+    if (!ws || !aligned256(ws)) return fail(LCP_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipError_t e = launch_posterior_backward(*M, n, Xq, prec, n > 0 ? dL_dmean : nullptr, n > 0 ? dL_dvar : nullptr,
+                                             dL_dy, dL_dloglen, (char*)ws, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "gp_posterior_backward");
     return ok();
 }
 

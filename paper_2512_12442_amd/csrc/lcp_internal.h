@@ -171,11 +171,16 @@ struct PostTask {
     void* V;                  // optional: V per point (value column only), quad-major with
                               // n_points columns: rows 4q..4q+3 of column p at (q * n_points + p) * 4
     int stage;                // stage-timer stage of this launch
+    int64_t vld;              // > 0: V column-major instead, column p at p * vld (vld >= m_pad)
+    int dense;                // 1: the operand is a full (not lower-triangular) m_pad x m_pad matrix
 };
 
 struct Model;  // defined below
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s);
+// Value columns against another operand in the fragment order of the binary64 (prec
+// LCP_FP64) or binary32 (LCP_FP32) posterior: A0 = m_pad x m_pad in 16 x 16 x 4 fragments.
+hipError_t launch_posterior_operand(const Model& M, int prec, const PostTask& t, const void* A0, hipStream_t s);
 
 // ------------------------------------------------------------------- cells (K3)
 
@@ -227,6 +232,7 @@ struct Model {
     lcp_kernel k;
     KParams kp;
     int m, m_pad, nrb, dim;
+    int sparse;       // 1: factored by gp_fit_sgpr (T = F L^-1 stored in place of L^-1)
     double* X;        // m_pad x 4 (zero padded)
     double* a;        // m_pad
     double* U;        // m_pad x m_pad, upper factor L^T (row-major); scratch K before factoring
@@ -250,6 +256,10 @@ hipError_t launch_factor_finish(Model& M, hipStream_t s);
 // Sparse model of eq. (sgp), after launch_factor on K_MM + jitter I with mu_M as y.
 hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, hipStream_t s);
 hipError_t launch_sparse_finish(Model& M, hipStream_t s);
+// Adjoint of the posterior at n points (binary64 or binary32 W); ws of posterior_backward_ws bytes.
+size_t posterior_backward_ws(const Model& M, int64_t n, int prec);
+hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq, int prec, const double* gm,
+                                     const double* gv, double* dy, double* dlogell, char* ws, hipStream_t s);
 size_t factor_batch_scratch(int nb);
 hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
                                int* info_dev, hipStream_t s);
@@ -272,6 +282,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 // Exclusive scan of n int32 flags (device count or host n) into offsets, total into *total.
 size_t scan_workspace(int64_t n);

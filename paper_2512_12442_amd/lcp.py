@@ -50,7 +50,7 @@ EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor
            "lcp_posterior_workspace", "lcp_dense_workspace", "lcp_adaptive_workspace", "gp_posterior",
            "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
-           "lcp_dense_batch"]
+           "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -83,6 +83,8 @@ def lib():
     L.lcp_dense.argtypes = [P, P, C.c_double, P, C.c_int, P, P, SZ, P]
     L.lcp_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int, P, P, I64, P, P, P, SZ, P]
     L.lcp_backward.argtypes = [P, P, C.c_double, P, P, P, P, P, SZ, P]
+    L.gp_posterior_backward_workspace.argtypes = [P, I64, C.c_int, C.POINTER(SZ)]
+    L.gp_posterior_backward.argtypes = [P, I64, P, C.c_int, P, P, P, P, P, SZ, P]
     L.lcp_profile_begin.argtypes = [C.c_uint]
     L.lcp_profile_end.argtypes = [P, P, C.c_int]
     L.lcp_batch_model_bytes.restype = SZ
@@ -191,6 +193,22 @@ class GPModel:
         _check(lib().gp_posterior(self.h, n, _ptr(Xq), _prec(prec), _ptr(mean), _ptr(var), None, 0, _stream()))
         return mean, var
 
+    def posterior_backward(self, Xq: torch.Tensor, dmean=None, dvar=None, prec="fp64", ws=None):
+        """Adjoint of posterior(Xq): (dL/dy, dL/dlog(lengthscale)) for upstream dL/dmean, dL/dvar."""
+        Xq = Xq.to(torch.float64).contiguous()
+        n = int(Xq.shape[0])
+        b = C.c_size_t()
+        _check(lib().gp_posterior_backward_workspace(self.h, n, _prec(prec), C.byref(b)))
+        if ws is None or ws.numel() < b.value:
+            ws = _buffer(b.value, self.device)
+        gm = None if dmean is None else dmean.to(torch.float64).contiguous()
+        gv = None if dvar is None else dvar.to(torch.float64).contiguous()
+        dy = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        dl = torch.empty(self.dim, dtype=torch.float64, device=self.device)
+        _check(lib().gp_posterior_backward(self.h, n, _ptr(Xq), _prec(prec), _ptr(gm), _ptr(gv), _ptr(dy), _ptr(dl),
+                                           _ptr(ws), b.value, _stream()))
+        return dy, dl
+
     def dense_workspace(self, grid: Grid, prec, n_samples):
         b = C.c_size_t()
         _check(lib().lcp_dense_workspace(self.h, C.byref(grid), _prec(prec), int(n_samples), C.byref(b)))
@@ -248,6 +266,33 @@ class GPModel:
         _check(lib().lcp_backward(self.h, C.byref(grid), float(theta), C.byref(mc), _ptr(dL_dlcp), _ptr(dy),
                                   _ptr(dl), None, 0, _stream()))
         return dy, dl
+
+
+class GPPosterior(torch.autograd.Function):
+    """Posterior mean and variance at Xq as a differentiable function of the observation
+    values y and the log-lengthscales: forward fits the model (gp_fit_factor) and evaluates
+    gp_posterior; backward runs gp_posterior_backward (K* regenerated, not stored)."""
+
+    @staticmethod
+    def forward(ctx, y, log_ell, X, Xq, kind, signal_var, noise_var, prec):
+        ell = torch.exp(log_ell.detach()).cpu().tolist()
+        ell = ell + [1.0] * (3 - len(ell))
+        G = GPModel(kind, X.shape[1], signal_var, ell, noise_var, X, y.detach())
+        mean, var = G.posterior(Xq, prec)
+        ctx.G, ctx.prec = G, prec
+        ctx.save_for_backward(Xq)
+        return mean, var
+
+    @staticmethod
+    def backward(ctx, gmean, gvar):
+        (Xq,) = ctx.saved_tensors
+        dy, dl = ctx.G.posterior_backward(Xq, gmean, gvar, ctx.prec)
+        return dy, dl, None, None, None, None, None, None
+
+
+def posterior_fn(y, log_ell, X, Xq, kind=SE, signal_var=1.0, noise_var=1e-4, prec="fp64"):
+    """Differentiable (mean, var) at Xq; gradients flow to y and log_ell."""
+    return GPPosterior.apply(y, log_ell, X, Xq, kind, signal_var, noise_var, prec)
 
 
 class StageTimer:
