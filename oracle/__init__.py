@@ -62,6 +62,13 @@ def lib():
         _lib.orc_posterior_grad.argtypes = [P, P, P, P, P, P]
         _lib.orc_kernel_dlogell.argtypes = [C.c_int, C.c_int, C.c_double, P, P, P, P]
         _lib.orc_posterior_backward.argtypes = [P, C.c_int64, P, P, P, P, P]
+        _lib.orc_sov_lcp.restype = C.c_double
+        _lib.orc_sov_lcp.argtypes = [C.c_int, P, P, C.c_double, C.c_int, P]
+        _lib.orc_sov_lcp_grad.restype = C.c_double
+        _lib.orc_sov_lcp_grad.argtypes = [C.c_int, P, P, C.c_double, C.c_int, P, P, P]
+        _lib.orc_chol_sd_rev.argtypes = [C.c_int, P, P, P]
+        _lib.orc_lcp_sov_cells.argtypes = [P, P, C.c_double, C.c_int, P, P]
+        _lib.orc_lcp_backward.argtypes = [P, P, C.c_double, C.c_int, P, P, P, P]
         _lib.orc_grid_posterior.argtypes = [P, P, P, P]
         _lib.orc_chol_sd.argtypes = [C.c_int, P, P, C.c_double]
         _lib.orc_mc_count.restype = C.c_int64
@@ -234,6 +241,47 @@ def lcp_dense(M: FitModel, W, c0=0, c1=None):
     rc = lib().orc_lcp_cells(C.byref(M.s), C.byref(g), W.theta, zb.shape[0], _p(zb), c0, c1, _p(out))
     assert rc == ORC_OK
     return out.reshape(shape)
+
+
+def sov_lcp(mu, Cm, theta, zb):
+    """Smooth (separation-of-variables) LCP of one cell from its mean and factor."""
+    mu, Cm, zb = _f64(mu), _f64(Cm), _f64(zb)
+    return lib().orc_sov_lcp(mu.shape[0], _p(mu), _p(Cm), theta, zb.shape[0], _p(zb))
+
+
+def sov_lcp_grad(mu, Cm, theta, zb):
+    mu, Cm, zb = _f64(mu), _f64(Cm), _f64(zb)
+    n = mu.shape[0]
+    gmu, gC = np.zeros(n), np.zeros((n, n))
+    v = lib().orc_sov_lcp_grad(n, _p(mu), _p(Cm), theta, zb.shape[0], _p(zb), _p(gmu), _p(gC))
+    return v, gmu, gC
+
+
+def chol_sd_rev(Cm, gC):
+    Cm, gC = _f64(Cm), _f64(gC)
+    gS = np.zeros_like(Cm)
+    lib().orc_chol_sd_rev(Cm.shape[0], _p(Cm), _p(gC), _p(gS))
+    return gS
+
+
+def lcp_sov_dense(M: FitModel, W):
+    """Smooth LCP of every cell (cell-array shape)."""
+    g = grid_of(W)
+    out = np.zeros(W.n_cells)
+    zb = _f64(W.zbank)
+    assert lib().orc_lcp_sov_cells(C.byref(M.s), C.byref(g), W.theta, zb.shape[0], _p(zb), _p(out)) == ORC_OK
+    return out.reshape(W.cell_shape)
+
+
+def lcp_backward(M: FitModel, W, gl):
+    """Adjoint of the smooth LCP field: (dL/dy, dL/dlog(ell)) for upstream dL/dLCP per cell."""
+    g = grid_of(W)
+    zb = _f64(W.zbank)
+    gl = _f64(gl).reshape(-1)
+    dy, dl = np.zeros(M.m), np.zeros(M.dim)
+    rc = lib().orc_lcp_backward(C.byref(M.s), C.byref(g), W.theta, zb.shape[0], _p(zb), _p(gl), _p(dy), _p(dl))
+    assert rc == ORC_OK, rc
+    return dy, dl
 
 
 def upper_bound(gmin, d):

@@ -435,6 +435,155 @@ int64_t orc_mc_count(int n, const double* mu, const double* C, double theta, int
     return cnt;
 }
 
+/* ------------------------------------------- smooth cell LCP and its adjoint -- */
+
+/*
+ * The Monte Carlo estimate of Sec. 4 counts crossings, so it is piecewise constant in the
+ * cell's mean and covariance.  For differentiation the same probability,
+ * LCP = 1 - P(all Y_q < theta) - P(all Y_q > theta), is estimated by Genz's separation of
+ * variables (Genz 1992): with the factor C of the corner covariance and uniforms
+ * w_i = Phi(z_i) from the first n - 1 normals of each z-bank row, each orthant probability
+ * is a product of conditional probabilities, smooth in the mean and in C.
+ */
+static double norm_cdf(double t) { return 0.5 * erfc(-t / sqrt(2.0)); }
+static double norm_pdf(double t) { return exp(-0.5 * t * t) * 0.39894228040143267794; }
+
+/* Phi^-1 by Newton's method on Phi from the rational start of Abramowitz-Stegun 26.2.23. */
+static double norm_inv(double u)
+{
+    if (u < 1e-300) u = 1e-300;
+    if (u > 1.0 - 1e-16) u = 1.0 - 1e-16;
+    double q = u < 0.5 ? u : 1.0 - u;
+    double t = sqrt(-2.0 * log(q));
+    double x = t - (2.515517 + 0.802853 * t + 0.010328 * t * t) /
+                   (1.0 + 1.432788 * t + 0.189269 * t * t + 0.001308 * t * t * t);
+    if (u < 0.5) x = -x;
+    for (int it = 0; it < 6; ++it) {
+        double f = norm_pdf(x);
+        if (!(f > 0.0)) break;
+        x -= (norm_cdf(x) - u) / f;
+    }
+    return x;
+}
+
+/* One sample of one orthant: upper = 0 estimates P(all Y < theta), 1 P(all Y > theta).
+ * Y = mu + C y with y standard normal; factor i is the probability of the orthant for
+ * Y_i given y_0 .. y_{i-1}, and y_i is drawn inside it by inversion of w_i.  Zero pivots
+ * (C_ii = 0) make factor i a step.  t, e, y receive the per-step values (for the adjoint). */
+static double sov_sample(int n, const double* mu, const double* C, double theta, int upper, const double* w,
+                         double* t, double* e, double* y)
+{
+    double f = 1.0;
+    for (int i = 0; i < n; ++i) {
+        double si = 0.0;
+        for (int j = 0; j < i; ++j) si += C[i * n + j] * y[j];
+        double r = theta - mu[i] - si;
+        double cii = C[i * n + i];
+        if (cii > 0.0) {
+            t[i] = r / cii;
+            e[i] = upper ? norm_cdf(-t[i]) : norm_cdf(t[i]);
+        } else {
+            t[i] = 0.0;
+            e[i] = upper ? (r < 0.0 ? 1.0 : 0.0) : (r > 0.0 ? 1.0 : 0.0);
+        }
+        f *= e[i];
+        y[i] = 0.0;
+        if (i < n - 1 && cii > 0.0) {
+            double u = upper ? 1.0 - e[i] + w[i] * e[i] : w[i] * e[i];
+            y[i] = norm_inv(u);
+        }
+    }
+    return f;
+}
+
+/* Smooth LCP of one cell (n corners, factor C) over ns samples of the z-bank. */
+double orc_sov_lcp(int n, const double* mu, const double* C, double theta, int ns, const double* zb)
+{
+    double t[8], e[8], y[8], w[8], acc = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        for (int i = 0; i < n; ++i) w[i] = norm_cdf(zb[(int64_t)s * n + i]);
+        acc += sov_sample(n, mu, C, theta, 0, w, t, e, y) + sov_sample(n, mu, C, theta, 1, w, t, e, y);
+    }
+    return 1.0 - acc / (double)ns;
+}
+
+/* Reverse pass of one orthant sample: adds d f / d mu to gmu and d f / d C (lower) to gC,
+ * each times scale.  With r_i = theta - mu_i - sum_j C_ij y_j and t_i = r_i / C_ii,
+ * e_i = Phi(t_i) (lower orthant) or Phi(-t_i) (upper), y_i = Phi^-1(u_i(e_i)). */
+static void sov_sample_rev(int n, const double* C, int upper, const double* w, const double* t, const double* e,
+                           const double* y, double scale, double* gmu, double* gC)
+{
+    double pre[9], suf[9], ybar[8];
+    pre[0] = 1.0;
+    for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] * e[i];
+    suf[n] = 1.0;
+    for (int i = n - 1; i >= 0; --i) suf[i] = suf[i + 1] * e[i];
+    for (int i = 0; i < n; ++i) ybar[i] = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+        double cii = C[i * n + i];
+        if (!(cii > 0.0)) continue;                       /* a step: no gradient */
+        double ebar = scale * pre[i] * suf[i + 1];        /* d f / d e_i */
+        if (i < n - 1) {
+            /* y_i = Phi^-1(u), u = w e_i (lower) or 1 - e_i + w e_i (upper) */
+            double du = upper ? (w[i] - 1.0) : w[i];
+            double py = norm_pdf(y[i]);
+            if (py > 0.0) ebar += ybar[i] * du / py;
+        }
+        double tbar = ebar * norm_pdf(t[i]) * (upper ? -1.0 : 1.0);
+        double rbar = tbar / cii;
+        gC[i * n + i] += -tbar * t[i] / cii;
+        gmu[i] += -rbar;
+        for (int j = 0; j < i; ++j) {
+            gC[i * n + j] += -rbar * y[j];
+            ybar[j] += -rbar * C[i * n + j];
+        }
+    }
+}
+
+/* Smooth cell LCP and its gradient with respect to the mean and the factor C (lower). */
+double orc_sov_lcp_grad(int n, const double* mu, const double* C, double theta, int ns, const double* zb,
+                        double* gmu, double* gC)
+{
+    double t[8], e[8], y[8], w[8], acc = 0.0;
+    for (int i = 0; i < n; ++i) gmu[i] = 0.0;
+    for (int i = 0; i < n * n; ++i) gC[i] = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        for (int i = 0; i < n; ++i) w[i] = norm_cdf(zb[(int64_t)s * n + i]);
+        for (int up = 0; up < 2; ++up) {
+            acc += sov_sample(n, mu, C, theta, up, w, t, e, y);
+            sov_sample_rev(n, C, up, w, t, e, y, -1.0 / (double)ns, gmu, gC);
+        }
+    }
+    return 1.0 - acc / (double)ns;
+}
+
+/* Reverse pass of orc_chol_sd: from dL/dC (lower) to dL/dS for the entries the factor
+ * reads (the lower triangle, diagonal included).  Columns the factorisation zeroed are
+ * locally constant: they pass no gradient. */
+void orc_chol_sd_rev(int n, const double* C, const double* gC_in, double* gS)
+{
+    double gC[64];
+    for (int i = 0; i < n * n; ++i) { gC[i] = gC_in[i]; gS[i] = 0.0; }
+    for (int k = n - 1; k >= 0; --k) {
+        double ckk = C[k * n + k];
+        if (!(ckk > 0.0)) continue;
+        /* C_ik = (S_ik - sum_{j<k} C_ij C_kj) / C_kk, i > k (computed after the diagonal) */
+        for (int i = n - 1; i > k; --i) {
+            double g = gC[i * n + k];
+            gS[i * n + k] += g / ckk;
+            for (int j = 0; j < k; ++j) {
+                gC[i * n + j] -= g * C[k * n + j] / ckk;
+                gC[k * n + j] -= g * C[i * n + j] / ckk;
+            }
+            gC[k * n + k] -= g * C[i * n + k] / ckk;
+        }
+        /* C_kk = sqrt(S_kk - sum_{j<k} C_kj^2) */
+        double g = gC[k * n + k];
+        gS[k * n + k] += g / (2.0 * ckk);
+        for (int j = 0; j < k; ++j) gC[k * n + j] -= g * C[k * n + j] / ckk;
+    }
+}
+
 static double vertex_coord(const orc_grid* G, int d, int64_t i)
 {
     return G->lo[d] + (double)i * ((G->hi[d] - G->lo[d]) / (double)(G->n[d] - 1));
@@ -468,6 +617,29 @@ static void cell_cov(const orc_model* M, int nc, const double* xc, const double*
 
 /* Corner mean vector and covariance of one cell from vertex arrays of a box of vertices
  * (vertex (i,j,k) of the box at offset i + bx*(j + by*k)). */
+/* Corner means and covariance of one cell from the posterior of a vertex box. */
+static void cell_mu_cov(const orc_model* M, const orc_grid* G, const int64_t* cell, const int64_t* box_lo,
+                        const int64_t* box_n, const double* bmean, const double* bvar, const double* bV,
+                        double* mu, double* S)
+{
+    int D = G->dim, nc = 1 << D;
+    double var[8], xc[24];
+    const double* vc[8];
+    for (int q = 0; q < nc; ++q) {
+        int64_t idx = 0, stride = 1;
+        for (int d = 0; d < D; ++d) {
+            int64_t vi = cell[d] + ((q >> d) & 1);
+            xc[q * D + d] = vertex_coord(G, d, vi);
+            idx += (vi - box_lo[d]) * stride;
+            stride *= box_n[d];
+        }
+        mu[q] = bmean[idx];
+        var[q] = bvar[idx];
+        vc[q] = bV + idx * vwidth(M);
+    }
+    cell_cov(M, nc, xc, var, vc, S);
+}
+
 static int64_t cell_count(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb,
                           const int64_t* cell, const int64_t* box_lo, const int64_t* box_n,
                           const double* bmean, const double* bvar, const double* bV)
@@ -566,6 +738,133 @@ int orc_lcp_cells(const orc_model* M, const orc_grid* G, double theta, int ns, c
     free(var);
     free(V);
     return rc;
+}
+
+/* Smooth (separation-of-variables) LCP of every cell, x fastest. */
+int orc_lcp_sov_cells(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb, double* lcp)
+{
+    int D = G->dim, nc = 1 << D;
+    int64_t box_lo[3] = {0, 0, 0}, box_n[3] = {1, 1, 1}, cn[3] = {1, 1, 1}, ncell = 1;
+    for (int d = 0; d < D; ++d) { box_n[d] = G->n[d]; cn[d] = G->n[d] - 1; ncell *= cn[d]; }
+    double *mean = NULL, *var = NULL, *V = NULL;
+    int64_t nv;
+    int rc = box_posterior(M, G, box_lo, box_n, &mean, &var, &V, &nv);
+    if (rc == ORC_OK) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t t = 0; t < ncell; ++t) {
+            int64_t cell[3] = {0, 0, 0}, r = t;
+            for (int d = 0; d < D; ++d) { cell[d] = r % cn[d]; r /= cn[d]; }
+            double mu[8], S[64], C[64];
+            cell_mu_cov(M, G, cell, box_lo, box_n, mean, var, V, mu, S);
+            orc_chol_sd(nc, S, C, 1e-12);
+            lcp[t] = orc_sov_lcp(nc, mu, C, theta, ns, zb);
+        }
+    }
+    free(mean);
+    free(var);
+    free(V);
+    return rc;
+}
+
+/*
+ * Adjoint of the smooth LCP field with respect to the observation values and the
+ * log-lengthscales, for upstream gradients gl (one per cell).  Cell by cell: the cell's
+ * gradient with respect to its corner means and covariance (factor adjoint included),
+ * then through eq. (sgp) corner by corner with w_q = K^-1 k_q:
+ *   dmu_q / dy = w_q,   dmu_q / dlog(ell_d) = dk_q . a - w_q^T dK a,
+ *   dS_qr / dlog(ell_d) = dk(x_q, x_r) - dk_q . w_r - dk_r . w_q + w_q^T dK w_r.
+ * Exact GP only.
+ */
+int orc_lcp_backward(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb,
+                     const double* gl, double* dy, double* dlogell)
+{
+    if (M->A) return ORC_EINVAL;
+    int D = G->dim, nc = 1 << D, m = M->m;
+    int64_t box_lo[3] = {0, 0, 0}, box_n[3] = {1, 1, 1}, cn[3] = {1, 1, 1}, ncell = 1;
+    for (int d = 0; d < D; ++d) { box_n[d] = G->n[d]; cn[d] = G->n[d] - 1; ncell *= cn[d]; }
+    double *mean = NULL, *var = NULL, *V = NULL;
+    int64_t nv;
+    int rc = box_posterior(M, G, box_lo, box_n, &mean, &var, &V, &nv);
+    double* dK = (double*)malloc(sizeof(double) * (size_t)D * m * m);
+    double* dKa = (double*)malloc(sizeof(double) * (size_t)D * m);
+    double* w = (double*)malloc(sizeof(double) * (size_t)nc * m);
+    double* dk = (double*)malloc(sizeof(double) * (size_t)nc * D * m);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)m);
+    double* kq = (double*)malloc(sizeof(double) * (size_t)m);
+    if (rc != ORC_OK || !dK || !dKa || !w || !dk || !tmp || !kq) {
+        free(mean); free(var); free(V); free(dK); free(dKa); free(w); free(dk); free(tmp); free(kq);
+        return rc != ORC_OK ? rc : ORC_ENOMEM;
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double g[3];
+            orc_kernel_dlogell(M->kind, D, M->s2, M->ell, M->X + (int64_t)i * D, M->X + (int64_t)j * D, g);
+            for (int d = 0; d < D; ++d) dK[((int64_t)d * m + i) * m + j] = g[d];
+        }
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < m; ++i) {
+            double sum = 0.0;
+            for (int j = 0; j < m; ++j) sum += dK[((int64_t)d * m + i) * m + j] * M->a[j];
+            dKa[(int64_t)d * m + i] = sum;
+        }
+    for (int j = 0; j < m; ++j) dy[j] = 0.0;
+    for (int d = 0; d < D; ++d) dlogell[d] = 0.0;
+    for (int64_t t = 0; t < ncell; ++t) {
+        if (gl[t] == 0.0) continue;
+        int64_t cell[3] = {0, 0, 0}, r = t;
+        for (int d = 0; d < D; ++d) { cell[d] = r % cn[d]; r /= cn[d]; }
+        double mu[8], S[64], C[64], gmu[8], gC[64], gS[64], xc[24];
+        cell_mu_cov(M, G, cell, box_lo, box_n, mean, var, V, mu, S);
+        orc_chol_sd(nc, S, C, 1e-12);
+        orc_sov_lcp_grad(nc, mu, C, theta, ns, zb, gmu, gC);
+        orc_chol_sd_rev(nc, C, gC, gS);
+        for (int q = 0; q < nc; ++q) {
+            for (int d = 0; d < D; ++d) xc[q * D + d] = vertex_coord(G, d, cell[d] + ((q >> d) & 1));
+            for (int j = 0; j < m; ++j) {
+                double g[3];
+                kq[j] = orc_kernel(M->kind, D, M->s2, M->ell, xc + q * D, M->X + (int64_t)j * D);
+                orc_kernel_dlogell(M->kind, D, M->s2, M->ell, xc + q * D, M->X + (int64_t)j * D, g);
+                for (int d = 0; d < D; ++d) dk[((int64_t)q * D + d) * m + j] = g[d];
+            }
+            forward_sub(m, M->L, kq, tmp);
+            backward_sub_t(m, M->L, tmp, w + (int64_t)q * m);
+        }
+        const double up = gl[t];
+        for (int q = 0; q < nc; ++q) {
+            const double* wq = w + (int64_t)q * m;
+            for (int j = 0; j < m; ++j) dy[j] += up * gmu[q] * wq[j];
+            for (int d = 0; d < D; ++d) {
+                const double* dkq = dk + ((int64_t)q * D + d) * m;
+                double dka = 0.0, wdKa = 0.0;
+                for (int j = 0; j < m; ++j) dka += dkq[j] * M->a[j];
+                for (int j = 0; j < m; ++j) wdKa += wq[j] * dKa[(int64_t)d * m + j];
+                dlogell[d] += up * gmu[q] * (dka - wdKa);
+            }
+            for (int rr = 0; rr <= q; ++rr) {
+                double gs = gS[q * nc + rr];
+                if (gs == 0.0) continue;
+                const double* wr = w + (int64_t)rr * m;
+                double g2[3];
+                orc_kernel_dlogell(M->kind, D, M->s2, M->ell, xc + q * D, xc + rr * D, g2);
+                for (int d = 0; d < D; ++d) {
+                    const double* dkq = dk + ((int64_t)q * D + d) * m;
+                    const double* dkr = dk + ((int64_t)rr * D + d) * m;
+                    const double* dKd = dK + (int64_t)d * m * m;
+                    double a1 = 0.0, a2 = 0.0, quad = 0.0;
+                    for (int j = 0; j < m; ++j) a1 += dkq[j] * wr[j];
+                    for (int j = 0; j < m; ++j) a2 += dkr[j] * wq[j];
+                    for (int i = 0; i < m; ++i) {
+                        double sum = 0.0;
+                        for (int j = 0; j < m; ++j) sum += dKd[(int64_t)i * m + j] * wr[j];
+                        quad += wq[i] * sum;
+                    }
+                    dlogell[d] += up * gs * (g2[d] - a1 - a2 + quad);
+                }
+            }
+        }
+    }
+    free(mean); free(var); free(V); free(dK); free(dKa); free(w); free(dk); free(tmp); free(kq);
+    return ORC_OK;
 }
 
 /* Corner mean and covariance of one cell (exposed for the tests). */
