@@ -79,9 +79,18 @@ typedef struct {
     int descent_steps;       /* projected-gradient steps of the bound search after the 3^D lattice, 0..16 */
 } lcp_adapt;
 
+typedef enum {
+    LCP_EST_COUNT = 0,       /* the paper's estimate (Sec. 4): fraction of samples mu + C z that cross */
+    LCP_EST_SOV = 1          /* the same probability by Genz's separation of variables, with uniforms
+                                Phi(z) from the first 2^dim - 1 normals of each row: smooth in the
+                                cell's mean and covariance, so it has an adjoint (lcp_backward);
+                                lcp_dense only */
+} lcp_estimator;
+
 typedef struct {
     int n_samples;           /* N_s >= 1 (the paper uses 1600, Sec. 5.4) */
     const double* zbank;     /* n_samples x 2^dim standard normals, shared by every cell (device) */
+    int estimator;           /* lcp_estimator (0 = the paper's counting estimate) */
 } lcp_mc;
 
 typedef struct lcp_model lcp_model;   /* opaque host handle over caller-owned device memory */
@@ -252,12 +261,27 @@ int gp_posterior_backward(const lcp_model* model, int64_t n, const double* Xq, i
                           void* stream);
 
 /*
- * lcp_backward -- adjoint of the LCP field with respect to the observation values and
- * log-lengthscales.  Not provided by this build: the Monte Carlo estimator of Sec. 4 is
- * piecewise constant in its inputs.  Always returns LCP_ENOTSUPPORTED.
+ * lcp_backward -- adjoint of the smooth LCP field of lcp_dense (estimator LCP_EST_SOV) with
+ * respect to the observation values y and the log-lengthscales, for upstream gradients
+ * dL_dlcp (one per cell, x fastest).  The counting estimate of Sec. 4 is piecewise constant
+ * in the model; the separation-of-variables estimate of the same probability is smooth, and
+ * this call differentiates it exactly (for the fixed z-bank): the cell's gradient with
+ * respect to its corner means and factor, the factor's adjoint, then eq. (sgp) through the
+ * vertex means, variances and neighbour covariances (the posterior adjoint with
+ * neighbour terms; K* regenerated, never stored).
+ *   model   from gp_fit_factor (LCP_ENOTSUPPORTED for a gp_fit_sgpr model)
+ *   grid, theta, mc   as for lcp_dense; mc->estimator must be LCP_EST_SOV
+ *   prec    LCP_FP64 or LCP_FP32: precision of V and W = K^-1 K*^T (the cell gradients,
+ *           factors and every sum are binary64)
+ *   dL_dlcp cells binary64 (device)
+ *   dL_dy   m binary64 (device), overwritten;  dL_dloglen  dim binary64 (device), overwritten
+ *   ws, ws_bytes   256-byte aligned, >= lcp_backward_workspace bytes (about 4 n m_pad
+ *                  elements of prec for n grid vertices, plus O(cells + m^2))
+ * Reproducible bit for bit.  Enqueued only.
  */
-int lcp_backward(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_mc* mc,
-                 const float* dL_dlcp, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
+int lcp_backward_workspace(const lcp_model* model, const lcp_grid* grid, int prec, int n_samples, size_t* bytes);
+int lcp_backward(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec,
+                 const double* dL_dlcp, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
                  void* stream);
 
 /*

@@ -6,6 +6,6 @@ regional upper bound driving the octree query of Alg. 1 (Sec. 4.1-4.3).  The com
 runs in the HIP library liblcp.so (C ABI in include/lcp.h); this package only marshals
 arguments.
 """
-from .lcp import (FP32, FP64, MATERN52, MIXED_BF16X3, MIXED_F16X3, PRECISIONS, SE, Adapt, GPModel, GPModelBatch,  # noqa: F401
-                  GPPosterior, Grid, LcpError,
+from .lcp import (EST_COUNT, EST_SOV, FP32, FP64, MATERN52, MIXED_BF16X3, MIXED_F16X3, PRECISIONS, SE, Adapt, GPModel, GPModelBatch,  # noqa: F401
+                  GPLcp, GPPosterior, Grid, LcpError, lcp_fn,
                   StageTimer, adapt_of, grid_of, lib, make_grid, posterior_fn)

@@ -15,6 +15,14 @@
 //   4. G by a binary64 symmetric rank-n product over point splits (upper blocks);
 //   5. P_d over all (j, l) pairs, then the ordered sums of every partial.
 // Every sum runs in a fixed order, so results are reproducible bit for bit.
+//
+// The adjoint of the smooth LCP field adds, per grid vertex p, the gradient c_p,e with
+// respect to the cross-covariance of p and its neighbour p + e (canonical directions e).
+// With cross = k(p, q) - k_p^T K^-1 k_q and z_p = sum over neighbours q of c_pq w_q (both
+// directions), the same passes apply with
+//   T_d  += -sum_p dk_p,d . z_p + sum_(p,e) c_p,e dk(x_p, x_p+e)/dlog(ell_d)   (direct term)
+//   G    += (1/2) sum_p w_p z_p^T,
+// so the rank-n product runs on U_p = h_p w_p + z_p / 2 in place of h_p w_p.
 #include "lcp_internal.h"
 
 namespace lcp {
@@ -59,15 +67,36 @@ __global__ void k_frag_full(const double* __restrict__ Ki, int mp, double* __res
     F32[t] = (float)x;
 }
 
+// Query points: n x dim binary64 coordinates, or the vertices of a grid (x fastest).
+struct BwdPts {
+    const double* P;
+    int dim;
+    int grid_mode;
+    GridP grid;
+    int64_t n;
+    __device__ __forceinline__ void at(int64_t p, double& x, double& y, double& z) const
+    {
+        if (grid_mode) {
+            x = vertex_coord(grid, 0, p % grid.n[0]);
+            y = vertex_coord(grid, 1, (p / grid.n[0]) % grid.n[1]);
+            z = dim > 2 ? vertex_coord(grid, 2, p / (grid.n[0] * grid.n[1])) : 0.0;
+        } else {
+            x = P[p * dim + 0];
+            y = P[p * dim + 1];
+            z = dim > 2 ? P[p * dim + 2] : 0.0;
+        }
+    }
+};
+
 struct BwdArgs {
     KParams kp;
     int m, mp, dim;
     const double* X;       // m_pad x 4
     const double* alpha;   // a = K^-1 y
     const void* W;         // column p at p * ldw (binary64 or binary32)
+    const void* Z;         // optional, as W: neighbour term z_p
     int64_t ldw;
-    int64_t n;
-    const double* P;       // n x dim query points
+    BwdPts pts;
     const double* gm;      // dL/dmean (may be null)
     const double* gv;      // dL/dvar (may be null)
     double* bpart;         // [kBwdGridP][mp]
@@ -92,6 +121,7 @@ __global__ void __launch_bounds__(256) k_bwd_points(BwdArgs A)
     constexpr int J = 4;
     const int tid = threadIdx.x;
     const T* __restrict__ W = (const T*)A.W;
+    const T* __restrict__ Z = (const T*)A.Z;
     const double ie0 = A.kp.inv_ell[0], ie1 = A.kp.inv_ell[1], ie2 = A.kp.inv_ell[2];
     double xj[J][3], aj[J], bacc[J];
 #pragma unroll
@@ -105,12 +135,13 @@ __global__ void __launch_bounds__(256) k_bwd_points(BwdArgs A)
         bacc[u] = 0.0;
     }
     double tacc[3] = {0.0, 0.0, 0.0};
-    const int64_t nchunks = (A.n + kBwdChunk - 1) / kBwdChunk;
+    const int64_t n = A.pts.n;
+    const int64_t nchunks = (n + kBwdChunk - 1) / kBwdChunk;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const int64_t p1 = (c + 1) * kBwdChunk < A.n ? (c + 1) * kBwdChunk : A.n;
+        const int64_t p1 = (c + 1) * kBwdChunk < n ? (c + 1) * kBwdChunk : n;
         for (int64_t p = c * kBwdChunk; p < p1; ++p) {
-            const double px = A.P[p * A.dim + 0], py = A.P[p * A.dim + 1];
-            const double pz = A.dim > 2 ? A.P[p * A.dim + 2] : 0.0;
+            double px, py, pz;
+            A.pts.at(p, px, py, pz);
             const double g1 = A.gm ? A.gm[p] : 0.0, g2 = A.gv ? A.gv[p] : 0.0;
 #pragma unroll
             for (int u = 0; u < J; ++u) {
@@ -121,8 +152,9 @@ __global__ void __launch_bounds__(256) k_bwd_points(BwdArgs A)
                 double kv, f;
                 kernel_val_dfac(A.kp, r2, &kv, &f);
                 const double w = (double)W[p * A.ldw + j];
+                const double zj = Z ? (double)Z[p * A.ldw + j] : 0.0;
                 // dk/dlog(ell_d) = -f t_d^2 (f = 2 dk/d(r^2))
-                const double coef = -f * fma(-2.0 * g2, w, g1 * aj[u]);
+                const double coef = -f * (fma(-2.0 * g2, w, g1 * aj[u]) - zj);
                 tacc[0] = fma(coef, t0 * t0, tacc[0]);
                 tacc[1] = fma(coef, t1 * t1, tacc[1]);
                 tacc[2] = fma(coef, t2 * t2, tacc[2]);
@@ -154,10 +186,11 @@ __global__ void k_bwd_reduce_b(const double* __restrict__ bpart, int nparts, int
 
 // G partial of split blockIdx.y over the upper 64 x 64 block pair blockIdx.x:
 // Gpart[s][j][l] = sum_{p in split} h_p W[p][j] W[p][l].
+// With U non-null the second operand is U[p][l] instead of h_p W[p][l].
 template <class T>
-__global__ void __launch_bounds__(256) k_bwd_syrk(const T* __restrict__ W, int64_t ldw, int64_t n,
-                                                  const double* __restrict__ h, int mp, int64_t split_pts,
-                                                  double* __restrict__ Gpart)
+__global__ void __launch_bounds__(256) k_bwd_syrk(const T* __restrict__ W, const T* __restrict__ U, int64_t ldw,
+                                                  int64_t n, const double* __restrict__ h, int mp,
+                                                  int64_t split_pts, double* __restrict__ Gpart)
 {
     __shared__ double As[16][68], Bs[16][68];
     const int nb = mp / 64;
@@ -178,11 +211,12 @@ __global__ void __launch_bounds__(256) k_bwd_syrk(const T* __restrict__ W, int64
     for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
         const int64_t p = p0 + lk;
         const bool live = p < pend;
-        const double hp = live ? h[p] : 0.0;
+        const double hp = (live && !U) ? h[p] : 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             As[lk][lc + e] = live ? (double)W[p * ldw + j0 + lc + e] : 0.0;
-            Bs[lk][lc + e] = live ? hp * (double)W[p * ldw + l0 + lc + e] : 0.0;
+            Bs[lk][lc + e] = live ? (U ? (double)U[p * ldw + l0 + lc + e] : hp * (double)W[p * ldw + l0 + lc + e])
+                                  : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -240,29 +274,102 @@ __global__ void __launch_bounds__(256) k_bwd_pairs(KParams kp, int m, int mp, co
 }
 
 __global__ void k_bwd_finish(const double* __restrict__ b, int m, const double* __restrict__ tpart, int ntp,
-                             const double* __restrict__ ppart, int npp, int dim, double* __restrict__ dy,
-                             double* __restrict__ dlogell)
+                             const double* __restrict__ ppart, int npp, const double* __restrict__ dpart, int ndp,
+                             int dim, double* __restrict__ dy, double* __restrict__ dlogell)
 {
     for (int j = threadIdx.x; j < m; j += blockDim.x) dy[j] = b[j];
     if (threadIdx.x < dim) {
         const int d = threadIdx.x;
-        double t = 0.0, p = 0.0;
+        double t = 0.0, p = 0.0, q2 = 0.0;
         for (int q = 0; q < ntp; ++q) t += tpart[(size_t)q * 4 + d];
         for (int q = 0; q < npp; ++q) p += ppart[(size_t)q * 4 + d];
-        dlogell[d] = t + p;
+        for (int q = 0; q < ndp; ++q) q2 += dpart[(size_t)q * 4 + d];
+        dlogell[d] = (t + p) + q2;
+    }
+}
+
+// Neighbour terms of the LCP adjoint over grid vertices (W, Z, U column-major, ldw):
+// z_p = sum_e c_p,e w_p+e + c_p-e,e w_p-e, U_p = h_p w_p + z_p / 2, and the direct term
+// sum_e c_p,e dk(x_p, x_p+e)/dlog(ell_d) (partials per work-group).  One work-group per
+// vertex chunk; threads over the observation index j.
+template <class T, int D>
+__global__ void __launch_bounds__(256) k_bwd_stencil(KParams kp, GridP g, int mp, const T* __restrict__ W,
+                                                     const double* __restrict__ gvar,
+                                                     const double* __restrict__ gcross, T* __restrict__ Z,
+                                                     T* __restrict__ U, double* __restrict__ dpart)
+{
+    constexpr int NDIR = D == 3 ? 13 : 4;
+    __shared__ double red[4];
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    const int64_t nchunks = (nv + kBwdChunk - 1) / kBwdChunk;
+    double dacc[3] = {0.0, 0.0, 0.0};
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t p1 = (c + 1) * kBwdChunk < nv ? (c + 1) * kBwdChunk : nv;
+        for (int64_t p = c * kBwdChunk; p < p1; ++p) {
+            const int64_t x[3] = {p % g.n[0], (p / g.n[0]) % g.n[1], p / (g.n[0] * g.n[1])};
+            int64_t nb[2 * NDIR];
+            double cf[2 * NDIR];
+            for (int e = 0; e < NDIR; ++e) {
+                int off[3];
+                if (D == 3) { off[0] = (e + 14) % 3 - 1; off[1] = ((e + 14) / 3) % 3 - 1; off[2] = (e + 14) / 9 - 1; }
+                else { off[0] = (e + 5) % 3 - 1; off[1] = (e + 5) / 3 - 1; off[2] = 0; }
+                bool fw = true, bw = true;
+                int64_t qf = 0, qb = 0, sf = 1;
+                for (int d = 0; d < 3; ++d) {
+                    const int64_t a = x[d] + off[d], b = x[d] - off[d];
+                    fw = fw && a >= 0 && a < g.n[d];
+                    bw = bw && b >= 0 && b < g.n[d];
+                    qf += a * sf;
+                    qb += b * sf;
+                    sf *= g.n[d];
+                }
+                nb[e] = fw ? qf : -1;
+                cf[e] = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
+                nb[NDIR + e] = bw ? qb : -1;
+                cf[NDIR + e] = bw ? gcross[(size_t)qb * NDIR + e] : 0.0;
+                if (fw && threadIdx.x == 0 && cf[e] != 0.0) {
+                    double t[3];
+                    for (int d = 0; d < 3; ++d) t[d] = (off[d] == 0 || d >= D) ? 0.0
+                        : (vertex_coord(g, d, x[d] + off[d]) - vertex_coord(g, d, x[d])) * kp.inv_ell[d];
+                    const double r2 = fma(t[2], t[2], fma(t[1], t[1], t[0] * t[0]));
+                    double kv, f;
+                    kernel_val_dfac(kp, r2, &kv, &f);
+                    for (int d = 0; d < 3; ++d) dacc[d] = fma(-f * cf[e], t[d] * t[d], dacc[d]);
+                }
+            }
+            const double hp = gvar[p];
+            for (int j = threadIdx.x; j < mp; j += 256) {
+                double z = 0.0;
+                for (int e = 0; e < 2 * NDIR; ++e)
+                    if (nb[e] >= 0) z = fma(cf[e], (double)W[(size_t)nb[e] * mp + j], z);
+                const double w = (double)W[(size_t)p * mp + j];
+                Z[(size_t)p * mp + j] = (T)z;
+                U[(size_t)p * mp + j] = (T)fma(hp, w, 0.5 * z);
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double sres = block_sum256(dacc[d], red);
+        if (threadIdx.x == 0) dpart[(size_t)blockIdx.x * 4 + d] = sres;
     }
 }
 
 struct BwdLayout {
     size_t kinv, f64, f32, w, mean, var, bpart, tpart, b, gpart, ppart, total;
+    // LCP adjoint only
+    size_t V, cross, wbank, gout, gmean, gvar, gcross, z, u, dpart;
     int nsplit;
 };
 
-BwdLayout bwd_layout(const Model& M, int64_t n, int prec)
+// lcp: also the forward moments, the cell and vertex gradients and the neighbour terms of
+// a dense grid with n vertices, ncell cells and ns samples.
+BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64_t ncell, int ns)
 {
     BwdLayout L{};
     const size_t mp = (size_t)M.m_pad;
     const size_t es = prec == LCP_FP64 ? 8 : 4;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
     L.nsplit = (int)((n + kBwdSplitPts - 1) / kBwdSplitPts);
     if (L.nsplit > kBwdMaxSplit) L.nsplit = kBwdMaxSplit;
     if (L.nsplit < 1) L.nsplit = 1;
@@ -271,61 +378,80 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec)
     L.kinv = take(8 * mp * mp);
     L.f64 = take(8 * mp * mp);
     L.f32 = take(4 * mp * mp);
-    L.w = take(es * mp * (size_t)(n > 0 ? n : 1));
-    L.mean = take(8 * (size_t)(n > 0 ? n : 1));
-    L.var = take(8 * (size_t)(n > 0 ? n : 1));
+    L.w = take(es * mp * nn);
+    L.mean = take(8 * nn);
+    L.var = take(8 * nn);
     L.bpart = take(8 * mp * kBwdGridP);
     L.tpart = take(8 * 4 * kBwdGridP);
     L.b = take(8 * mp);
     L.gpart = take(8 * mp * mp * (size_t)L.nsplit);
     L.ppart = take(8 * 4 * kBwdGridQ);
+    if (lcp) {
+        const int N = 1 << D, ndir = D == 3 ? 13 : 4;
+        L.V = take(es * mp * nn);
+        L.cross = take(8 * (size_t)ndir * nn);
+        L.wbank = take(8 * (size_t)ns * N);
+        L.gout = take(8 * (size_t)(N + N * (N + 1) / 2) * (size_t)(ncell > 0 ? ncell : 1));
+        L.gmean = take(8 * nn);
+        L.gvar = take(8 * nn);
+        L.gcross = take(8 * (size_t)ndir * nn);
+        L.z = take(es * mp * nn);
+        L.u = take(es * mp * nn);
+        L.dpart = take(8 * 4 * kBwdGridP);
+    }
     L.total = o;
     return L;
 }
 
-}  // namespace
-
-size_t posterior_backward_ws(const Model& M, int64_t n, int prec) { return bwd_layout(M, n, prec).total; }
-
-hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq, int prec, const double* gm,
-                                     const double* gv, double* dy, double* dlogell, char* ws, hipStream_t s)
+// K^-1 fragments, then W = K^-1 K*^T for the points (plain columns of m_pad).
+hipError_t bwd_w(const Model& M, const BwdLayout& L, const BwdPts& P, int prec, char* ws, hipStream_t s)
 {
-    const BwdLayout L = bwd_layout(M, n, prec);
     const int mp = M.m_pad;
     const int64_t n2 = (int64_t)mp * mp;
     double* Kinv = (double*)(ws + L.kinv);
     double* F64 = (double*)(ws + L.f64);
     float* F32 = (float*)(ws + L.f32);
-    void* W = ws + L.w;
-    double* bpart = (double*)(ws + L.bpart);
-    double* tpart = (double*)(ws + L.tpart);
-    double* b = (double*)(ws + L.b);
-    double* gpart = (double*)(ws + L.gpart);
-    double* ppart = (double*)(ws + L.ppart);
     {
         StageScope sc(s, ST_FACTOR);
         hipLaunchKernelGGL(k_kinv, dim3((unsigned)(mp / 16), (unsigned)(mp / 16)), dim3(256), 0, s, M.Linv, mp, Kinv);
         hipLaunchKernelGGL(k_frag_full, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, Kinv, mp, F64, F32);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (n > 0) {
-        PostTask t{};
+    if (e != hipSuccess || P.n <= 0) return e;
+    PostTask t{};
+    t.group = 1;
+    t.n_points = P.n;
+    if (P.grid_mode) {
+        t.mode = COL_GRID;
+        t.grid = P.grid;
+    } else {
         t.mode = COL_POINTS;
-        t.group = 1;
-        t.n_points = n;
-        t.pts = Xq;
-        t.pstride = M.dim;
-        t.mean = (double*)(ws + L.mean);
-        t.var = (double*)(ws + L.var);
-        t.V = W;
-        t.vld = mp;
-        t.dense = 1;
-        t.stage = ST_POSTERIOR;
-        e = launch_posterior_operand(M, prec, t, prec == LCP_FP64 ? (const void*)F64 : (const void*)F32, s);
-        if (e != hipSuccess) return e;
+        t.pts = P.P;
+        t.pstride = P.dim;
     }
+    t.mean = (double*)(ws + L.mean);
+    t.var = (double*)(ws + L.var);
+    t.V = ws + L.w;
+    t.vld = mp;
+    t.dense = 1;
+    t.stage = ST_POSTERIOR;
+    return launch_posterior_operand(M, prec, t, prec == LCP_FP64 ? (const void*)F64 : (const void*)F32, s);
+}
+
+// Points pass, b, the rank-n product (on U when given), pairs and the final sums.
+hipError_t bwd_tail(const Model& M, const BwdLayout& L, const BwdPts& P, int prec, const double* gm, const double* gv,
+                    const void* Z, const void* U, const double* dpart, int ndp, double* dy, double* dlogell,
+                    char* ws, hipStream_t s)
+{
     StageScope sc(s, ST_MISC);
+    const int mp = M.m_pad;
+    const int64_t n = P.n;
+    const void* W = ws + L.w;
+    double* bpart = (double*)(ws + L.bpart);
+    double* tpart = (double*)(ws + L.tpart);
+    double* b = (double*)(ws + L.b);
+    double* gpart = (double*)(ws + L.gpart);
+    double* ppart = (double*)(ws + L.ppart);
     BwdArgs A{};
     A.kp = M.kp;
     A.m = M.m;
@@ -334,9 +460,9 @@ hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq
     A.X = M.X;
     A.alpha = M.a;
     A.W = W;
+    A.Z = Z;
     A.ldw = mp;
-    A.n = n;
-    A.P = Xq;
+    A.pts = P;
     A.gm = gm;
     A.gv = gv;
     A.bpart = bpart;
@@ -346,24 +472,122 @@ hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq
     hipLaunchKernelGGL(k_bwd_reduce_b, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, bpart, kBwdGridP, mp, b);
     const int nb = mp / 64;
     const unsigned npairs_blk = (unsigned)(nb * (nb + 1) / 2);
-    if (gv && n > 0) {
+    const bool rank_n = (gv || U) && n > 0;
+    if (rank_n) {
         const int64_t split_pts = (n + L.nsplit - 1) / L.nsplit;
         if (prec == LCP_FP64)
             hipLaunchKernelGGL(k_bwd_syrk<double>, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
-                               (const double*)W, (int64_t)mp, n, gv, mp, split_pts, gpart);
+                               (const double*)W, (const double*)U, (int64_t)mp, n, gv, mp, split_pts, gpart);
         else
             hipLaunchKernelGGL(k_bwd_syrk<float>, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
-                               (const float*)W, (int64_t)mp, n, gv, mp, split_pts, gpart);
+                               (const float*)W, (const float*)U, (int64_t)mp, n, gv, mp, split_pts, gpart);
     } else {
-        e = launch_fill_f64(gpart, 0.0, n2, s);
+        hipError_t e = launch_fill_f64(gpart, 0.0, (int64_t)mp * mp, s);
         if (e != hipSuccess) return e;
     }
-    const int nsplit = (gv && n > 0) ? L.nsplit : 1;
-    hipLaunchKernelGGL(k_bwd_pairs, dim3(kBwdGridQ), dim3(256), 0, s, M.kp, M.m, mp, M.X, M.a, b, gpart, nsplit,
-                       ppart);
-    hipLaunchKernelGGL(k_bwd_finish, dim3(1), dim3(256), 0, s, b, M.m, tpart, kBwdGridP, ppart, kBwdGridQ, M.dim, dy,
-                       dlogell);
+    hipLaunchKernelGGL(k_bwd_pairs, dim3(kBwdGridQ), dim3(256), 0, s, M.kp, M.m, mp, M.X, M.a, b, gpart,
+                       rank_n ? L.nsplit : 1, ppart);
+    hipLaunchKernelGGL(k_bwd_finish, dim3(1), dim3(256), 0, s, b, M.m, tpart, kBwdGridP, ppart, kBwdGridQ, dpart, ndp,
+                       M.dim, dy, dlogell);
     return hipGetLastError();
+}
+
+}  // namespace
+
+size_t posterior_backward_ws(const Model& M, int64_t n, int prec)
+{
+    return bwd_layout(M, n, prec, false, M.dim, 0, 0).total;
+}
+
+hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq, int prec, const double* gm,
+                                     const double* gv, double* dy, double* dlogell, char* ws, hipStream_t s)
+{
+    const BwdLayout L = bwd_layout(M, n, prec, false, M.dim, 0, 0);
+    BwdPts P{};
+    P.P = Xq;
+    P.dim = M.dim;
+    P.n = n;
+    hipError_t e = bwd_w(M, L, P, prec, ws, s);
+    if (e != hipSuccess) return e;
+    return bwd_tail(M, L, P, prec, gm, gv, nullptr, nullptr, nullptr, 0, dy, dlogell, ws, s);
+}
+
+size_t lcp_backward_ws(const Model& M, const GridP& g, int prec, int ns)
+{
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
+    return bwd_layout(M, nv, prec, true, g.dim, nc, ns).total;
+}
+
+hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int ns, const double* zb, int prec,
+                               const double* gl, double* dy, double* dlogell, char* ws, hipStream_t s)
+{
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
+    const BwdLayout L = bwd_layout(M, nv, prec, true, g.dim, nc, ns);
+    // forward moments: mean, variance, V (quad-major) and the neighbour cross-covariances
+    PostTask t{};
+    t.mode = COL_GRID;
+    t.group = 1;
+    t.n_points = nv;
+    t.grid = g;
+    t.mean = (double*)(ws + L.mean);
+    t.var = (double*)(ws + L.var);
+    t.V = ws + L.V;
+    t.stage = ST_POSTERIOR;
+    hipError_t e = launch_posterior(M, prec, t, s);
+    if (e != hipSuccess) return e;
+    double* cross = (double*)(ws + L.cross);
+    e = launch_cross(M, prec, g, nullptr, nullptr, nv, nullptr, ws + L.V, cross, s);
+    if (e != hipSuccess) return e;
+    // cell gradients of the smooth LCP, gathered per vertex
+    CellTask ct{};
+    ct.grid = g;
+    ct.prec = LCP_FP64;
+    ct.theta = theta;
+    ct.ns = ns;
+    ct.zb64 = zb;
+    ct.mean = t.mean;
+    ct.var = t.var;
+    ct.cross = cross;
+    double* gmean = (double*)(ws + L.gmean);
+    double* gvar = (double*)(ws + L.gvar);
+    double* gcross = (double*)(ws + L.gcross);
+    e = launch_cells_sov_grad(ct, (double*)(ws + L.wbank), gl, (double*)(ws + L.gout), gmean, gvar, gcross, s);
+    if (e != hipSuccess) return e;
+    // W, the neighbour terms, then the shared tail
+    BwdPts P{};
+    P.dim = M.dim;
+    P.grid_mode = 1;
+    P.grid = g;
+    P.n = nv;
+    e = bwd_w(M, L, P, prec, ws, s);
+    if (e != hipSuccess) return e;
+    double* dpart = (double*)(ws + L.dpart);
+    {
+        StageScope sc(s, ST_MISC);
+        const int mp = M.m_pad;
+        if (prec == LCP_FP64) {
+            if (g.dim == 3)
+                hipLaunchKernelGGL((k_bwd_stencil<double, 3>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                                   (const double*)(ws + L.w), gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u),
+                                   dpart);
+            else
+                hipLaunchKernelGGL((k_bwd_stencil<double, 2>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                                   (const double*)(ws + L.w), gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u),
+                                   dpart);
+        } else {
+            if (g.dim == 3)
+                hipLaunchKernelGGL((k_bwd_stencil<float, 3>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                                   (const float*)(ws + L.w), gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u),
+                                   dpart);
+            else
+                hipLaunchKernelGGL((k_bwd_stencil<float, 2>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                                   (const float*)(ws + L.w), gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u),
+                                   dpart);
+        }
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return bwd_tail(M, L, P, prec, gmean, gvar, ws + L.z, ws + L.u, dpart, kBwdGridP, dy, dlogell, ws, s);
 }
 
 }  // namespace lcp

@@ -532,6 +532,253 @@ __global__ void k_fill(T* __restrict__ p, T v, int64_t n)
         p[i] = v;
 }
 
+// ---------------------------------------------------------------- smooth cell LCP
+//
+// For differentiation, the cell probability 1 - P(all Y < theta) - P(all Y > theta) is
+// estimated by Genz's separation of variables: with the corner factor C and uniforms
+// w_i = Phi(z_i) from the first 2^D - 1 normals of each z-bank row, each orthant is a
+// product of conditional probabilities e_i = Phi(+-t_i), t_i = (theta - mu_i - sum_j C_ij
+// y_j) / C_ii, and y_i is drawn inside orthant i by inversion.  Smooth in mu and C; a zero
+// pivot makes its factor a step.  Binary64 throughout, one lane per cell.
+
+__device__ __forceinline__ double phi_pdf(double t) { return exp(-0.5 * t * t) * 0.39894228040143267794; }
+__device__ __forceinline__ double phi_inv(double u) { return normcdfinv(fmin(fmax(u, 1e-300), 1.0 - 1e-16)); }
+
+// Lower-triangular N x N matrices packed by rows: (i, j), j <= i, at i (i + 1) / 2 + j.
+template <int N>
+constexpr int kTri = N * (N + 1) / 2;
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// One sample of one orthant (upper = 1: all above theta); mt = mu - theta.
+template <int N>
+__device__ __forceinline__ double sov_orthant(const double (&mt)[N], const double (&C)[kTri<N>], bool upper,
+                                              const double* __restrict__ w, double (&t)[N], double (&e)[N],
+                                              double (&y)[N])
+{
+    double f = 1.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double si = 0.0;
+#pragma unroll
+        for (int j = 0; j < i; ++j) si = fma(C[tri(i, j)], y[j], si);
+        const double r = -mt[i] - si;
+        const double cii = C[tri(i, i)];
+        if (cii > 0.0) {
+            t[i] = r / cii;
+            e[i] = normcdf(upper ? -t[i] : t[i]);
+        } else {
+            t[i] = 0.0;
+            e[i] = upper ? (r < 0.0 ? 1.0 : 0.0) : (r > 0.0 ? 1.0 : 0.0);
+        }
+        f *= e[i];
+        y[i] = 0.0;
+        if (i < N - 1 && cii > 0.0) y[i] = phi_inv(upper ? 1.0 - e[i] + w[i] * e[i] : w[i] * e[i]);
+    }
+    return f;
+}
+
+// Reverse pass of one orthant sample, scaled: adds d f / d mu to gmu and d f / d C to gC.
+template <int N>
+__device__ __forceinline__ void sov_orthant_rev(const double (&C)[kTri<N>], bool upper, const double* __restrict__ w,
+                                                const double (&t)[N], const double (&e)[N], const double (&y)[N],
+                                                double scale, double (&gmu)[N], double (&gC)[kTri<N>])
+{
+    double suf[N + 1], ybar[N];
+    suf[N] = 1.0;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) suf[i] = suf[i + 1] * e[i];
+    double pre[N];
+    pre[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i < N; ++i) pre[i] = pre[i - 1] * e[i - 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) ybar[i] = 0.0;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        const double cii = C[tri(i, i)];
+        if (!(cii > 0.0)) continue;
+        double ebar = scale * pre[i] * suf[i + 1];
+        if (i < N - 1) {
+            const double py = phi_pdf(y[i]);
+            if (py > 0.0) ebar += ybar[i] * (upper ? w[i] - 1.0 : w[i]) / py;
+        }
+        const double tbar = ebar * phi_pdf(t[i]) * (upper ? -1.0 : 1.0);
+        const double rbar = tbar / cii;
+        gC[tri(i, i)] -= tbar * t[i] / cii;
+        gmu[i] -= rbar;
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            gC[tri(i, j)] -= rbar * y[j];
+            ybar[j] -= rbar * C[tri(i, j)];
+        }
+    }
+}
+
+// Reverse pass of the semidefinite Cholesky chol_sd: dL/dC (lower, packed, consumed) to
+// dL/dS on the lower triangle the factor reads.  Zeroed columns pass no gradient.
+template <int N>
+__device__ __forceinline__ void chol_sd_rev(const double (&C)[kTri<N>], double (&gC)[kTri<N>], double (&gS)[kTri<N>])
+{
+#pragma unroll
+    for (int i = 0; i < kTri<N>; ++i) gS[i] = 0.0;
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        const double ckk = C[tri(k, k)];
+        if (!(ckk > 0.0)) continue;
+        const double inv = 1.0 / ckk;
+#pragma unroll
+        for (int i = N - 1; i > k; --i) {
+            const double g = gC[tri(i, k)] * inv;
+            gS[tri(i, k)] += g;
+#pragma unroll
+            for (int j = 0; j < k; ++j) {
+                gC[tri(i, j)] -= g * C[tri(k, j)];
+                gC[tri(k, j)] -= g * C[tri(i, j)];
+            }
+            gC[tri(k, k)] -= g * C[tri(i, k)];
+        }
+        const double g = gC[tri(k, k)];
+        gS[tri(k, k)] += 0.5 * g * inv;
+#pragma unroll
+        for (int j = 0; j < k; ++j) gC[tri(k, j)] -= g * C[tri(k, j)] * inv;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void pack_lower(const double (&Cd)[N][N], double (&C)[kTri<N>])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) C[tri(i, j)] = Cd[i][j];
+}
+
+__global__ void k_wbank(const double* __restrict__ zb, double* __restrict__ wb, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        wb[i] = normcdf(zb[i]);
+}
+
+// Smooth LCP of every cell of the dense grid.
+template <int D>
+__global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __restrict__ wb, int64_t ncell)
+{
+    constexpr int N = 1 << D;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lin, sl[N];
+        const int st = cell_corners<D>(t, c, lin, sl);
+        if (st == 0) continue;
+        if (st == 1) { t.lcp[lin] = __builtin_nanf(""); continue; }
+        double mt[N], Cd[N][N], C[kTri<N>], tt[N], e[N], y[N];
+        cell_factor<D>(t, sl, mt, Cd);
+        pack_lower<N>(Cd, C);
+        double acc = 0.0;
+        for (int sIdx = 0; sIdx < t.ns; ++sIdx) {
+            const double* w = wb + (size_t)sIdx * N;
+            acc += sov_orthant<N>(mt, C, false, w, tt, e, y);
+            acc += sov_orthant<N>(mt, C, true, w, tt, e, y);
+        }
+        t.lcp[lin] = (float)(1.0 - acc / (double)t.ns);
+    }
+}
+
+// Gradient of gl[cell] * LCP_cell with respect to the cell's corner means (N values) and
+// the lower triangle of its corner covariance (N (N + 1) / 2, packed) -> gout[cell].
+template <int D>
+__global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double* __restrict__ wb,
+                                                        const double* __restrict__ gl, double* __restrict__ gout,
+                                                        int64_t ncell)
+{
+    constexpr int N = 1 << D;
+    constexpr int NO = N + kTri<N>;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lin, sl[N];
+        const int st = cell_corners<D>(t, c, lin, sl);
+        if (st == 0) continue;
+        double* out = gout + (size_t)lin * NO;
+        const double up = gl[lin];
+        if (st == 1 || up == 0.0) {
+#pragma unroll
+            for (int i = 0; i < NO; ++i) out[i] = 0.0;
+            continue;
+        }
+        double mt[N], Cd[N][N], C[kTri<N>], tt[N], e[N], y[N], gmu[N], gC[kTri<N>], gS[kTri<N>];
+        cell_factor<D>(t, sl, mt, Cd);
+        pack_lower<N>(Cd, C);
+#pragma unroll
+        for (int i = 0; i < N; ++i) gmu[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < kTri<N>; ++i) gC[i] = 0.0;
+        const double scale = -up / (double)t.ns;       // LCP = 1 - mean(f_lo + f_hi)
+        for (int sIdx = 0; sIdx < t.ns; ++sIdx) {
+            const double* w = wb + (size_t)sIdx * N;
+            sov_orthant<N>(mt, C, false, w, tt, e, y);
+            sov_orthant_rev<N>(C, false, w, tt, e, y, scale, gmu, gC);
+            sov_orthant<N>(mt, C, true, w, tt, e, y);
+            sov_orthant_rev<N>(C, true, w, tt, e, y, scale, gmu, gC);
+        }
+        chol_sd_rev<N>(C, gC, gS);
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = gmu[i];
+#pragma unroll
+        for (int i = 0; i < kTri<N>; ++i) out[N + i] = gS[i];
+    }
+}
+
+// Per vertex: dL/dmean, dL/dvar and dL/dcross (its canonical directions) gathered from
+// the cells that contain it (cell gradients from k_cells_sov_grad).
+template <int D>
+__global__ void __launch_bounds__(256) k_sov_gather(GridP g, const double* __restrict__ gout,
+                                                    double* __restrict__ gmean, double* __restrict__ gvar,
+                                                    double* __restrict__ gcross)
+{
+    constexpr int N = 1 << D;
+    constexpr int NO = N + kTri<N>;
+    constexpr int NDIR = D == 3 ? 13 : 4;
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x[3] = {v % g.n[0], (v / g.n[0]) % g.n[1], v / (g.n[0] * g.n[1])};
+        auto cell_of = [&](int q, int64_t& lin) {
+            int64_t c[3] = {0, 0, 0};
+            for (int d = 0; d < D; ++d) {
+                c[d] = x[d] - ((q >> d) & 1);
+                if (c[d] < 0 || c[d] >= g.nc[d]) return false;
+            }
+            lin = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+            return true;
+        };
+        double gm = 0.0, gv = 0.0;
+        for (int q = 0; q < N; ++q) {
+            int64_t lin;
+            if (!cell_of(q, lin)) continue;
+            gm += gout[(size_t)lin * NO + q];
+            gv += gout[(size_t)lin * NO + N + tri(q, q)];
+        }
+        gmean[v] = gm;
+        gvar[v] = gv;
+        for (int dir = 0; dir < NDIR; ++dir) {
+            int off[3];
+            if (D == 3) { off[0] = (dir + 14) % 3 - 1; off[1] = ((dir + 14) / 3) % 3 - 1; off[2] = (dir + 14) / 9 - 1; }
+            else { off[0] = (dir + 5) % 3 - 1; off[1] = (dir + 5) / 3 - 1; off[2] = 0; }
+            double gc = 0.0;
+            // cells holding v at corner q and v + off at corner r
+            for (int q = 0; q < N; ++q) {
+                int r = 0;
+                bool ok = true;
+                for (int d = 0; d < D; ++d) {
+                    const int b = ((q >> d) & 1) + off[d];
+                    ok = ok && b >= 0 && b <= 1;
+                    r |= (b & 1) << d;
+                }
+                int64_t lin;
+                if (!ok || !cell_of(q, lin)) continue;
+                gc += gout[(size_t)lin * NO + N + tri(r, q)];   // r > q: the lower entry
+            }
+            gcross[(size_t)v * NDIR + dir] = gc;
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t n, int per)
 {
     int64_t b = (n + per - 1) / per;
@@ -624,6 +871,42 @@ void cells_dispatch(R src, bool f64, unsigned grid, int64_t cap, hipStream_t s)
 }
 
 }  // namespace
+
+hipError_t launch_cells_sov(const CellTask& t, double* wb, hipStream_t s)
+{
+    const int D = t.grid.dim;
+    const int64_t ncell = t.grid.nc[0] * t.grid.nc[1] * t.grid.nc[2];
+    if (ncell <= 0) return hipSuccess;
+    StageScope sc(s, ST_CELLS);
+    hipLaunchKernelGGL(k_wbank, dim3(grid_for((int64_t)t.ns << D, 256)), dim3(256), 0, s, t.zb64, wb,
+                       (int64_t)t.ns << D);
+    if (D == 3) hipLaunchKernelGGL(k_cells_sov<3>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+    else hipLaunchKernelGGL(k_cells_sov<2>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells_sov_grad(const CellTask& t, double* wb, const double* gl, double* gout, double* gmean,
+                                 double* gvar, double* gcross, hipStream_t s)
+{
+    const int D = t.grid.dim;
+    const int64_t ncell = t.grid.nc[0] * t.grid.nc[1] * t.grid.nc[2];
+    const int64_t nv = t.grid.n[0] * t.grid.n[1] * t.grid.n[2];
+    StageScope sc(s, ST_CELLS);
+    hipLaunchKernelGGL(k_wbank, dim3(grid_for((int64_t)t.ns << D, 256)), dim3(256), 0, s, t.zb64, wb,
+                       (int64_t)t.ns << D);
+    if (D == 3) {
+        if (ncell > 0)
+            hipLaunchKernelGGL(k_cells_sov_grad<3>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, gl, gout, ncell);
+        hipLaunchKernelGGL(k_sov_gather<3>, dim3(grid_for(nv, 256)), dim3(256), 0, s, t.grid, gout, gmean, gvar,
+                           gcross);
+    } else {
+        if (ncell > 0)
+            hipLaunchKernelGGL(k_cells_sov_grad<2>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, gl, gout, ncell);
+        hipLaunchKernelGGL(k_sov_gather<2>, dim3(grid_for(nv, 256)), dim3(256), 0, s, t.grid, gout, gmean, gvar,
+                           gcross);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s)
 {

@@ -117,6 +117,8 @@ int check_mc(const lcp_model* M, const lcp_mc* mc)
     if (!mc) return fail(LCP_EINVAL, "mc is NULL");
     if (mc->n_samples < 1 || mc->n_samples > (1 << 24)) return fail(LCP_EINVAL, "n_samples = %d", mc->n_samples);
     if (!mc->zbank) return fail(LCP_EINVAL, "zbank is NULL");
+    if (mc->estimator != LCP_EST_COUNT && mc->estimator != LCP_EST_SOV)
+        return fail(LCP_EINVAL, "estimator = %d", mc->estimator);
     (void)M;
     return LCP_OK;
 }
@@ -133,6 +135,7 @@ size_t dense_ws(const lcp_model* M, const GridP& g, int prec, int ns)
     b += align256(vb * (size_t)nv * M->m_pad);               // V
     b += align256(sizeof(double) * (size_t)nv * ndir(g.dim)); // cross
     b += align256(sizeof(float) * (size_t)ns * (1 << g.dim)); // FP32 z-bank
+    b += align256(sizeof(double) * (size_t)ns * (1 << g.dim)); // uniforms of the smooth estimator
     b += cells_scratch_bytes(g.nc[0] * g.nc[1] * g.nc[2]);   // Monte Carlo work list
     return b;
 }
@@ -369,6 +372,7 @@ struct DenseWs {
     void* V;
     double* cross;
     float* zb32;
+    double* wb;
     int32_t* work;
     int64_t* wcount;
     double* zmax;
@@ -389,6 +393,8 @@ DenseWs carve_dense(const lcp_model* M, const GridP& g, int prec, int ns, char* 
     p += align256(sizeof(double) * (size_t)nv * ndir(g.dim));
     w.zb32 = (float*)p;
     p += align256(sizeof(float) * (size_t)ns * (1 << g.dim));
+    w.wb = (double*)p;
+    p += align256(sizeof(double) * (size_t)ns * (1 << g.dim));
     const int64_t ncells = g.nc[0] * g.nc[1] * g.nc[2];
     w.work = (int32_t*)p;
     p += align256(4 * (size_t)ncells);
@@ -437,7 +443,12 @@ int dense_cells(const lcp_model* M, const GridP& g, double theta, const lcp_mc* 
     ct.work = w.work;
     ct.wcount = w.wcount;
     ct.zmax = w.zmax;
-    e = launch_cells(ct, g.nc[0] * g.nc[1] * g.nc[2], s);
+    if (mc->estimator == LCP_EST_SOV) {
+        ct.prec = LCP_FP64;
+        e = launch_cells_sov(ct, w.wb, s);
+    } else {
+        e = launch_cells(ct, g.nc[0] * g.nc[1] * g.nc[2], s);
+    }
     if (e != hipSuccess) return dev_fail(e, "cells");
     return LCP_OK;
 }
@@ -479,6 +490,7 @@ int lcp_adaptive(const lcp_model* M, const lcp_grid* grid, double theta, const l
     GridP g;
     if (int r = check_grid(M, grid, &g)) return r;
     if (int r = check_mc(M, mc)) return r;
+    if (mc->estimator != LCP_EST_COUNT) return fail(LCP_ENOTSUPPORTED, "lcp_adaptive: counting estimator only");
     if (int r = check_adapt(A)) return r;
     if (!is_finite(theta)) return fail(LCP_EINVAL, "theta must be finite");
     if (!lcp || !ws || !n_leaves) return fail(LCP_EINVAL, "lcp, n_leaves and ws must not be NULL");
@@ -496,12 +508,37 @@ int lcp_adaptive(const lcp_model* M, const lcp_grid* grid, double theta, const l
     return ok();
 }
 
-int lcp_backward(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_mc* mc, const float* dL_dlcp,
-                 double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes, void* stream)
+int lcp_backward_workspace(const lcp_model* M, const lcp_grid* grid, int prec, int n_samples, size_t* bytes)
 {
-    (void)M; (void)grid; (void)theta; (void)mc; (void)dL_dlcp; (void)dL_dy; (void)dL_dloglen; (void)ws;
-    (void)ws_bytes; (void)stream;
-    return fail(LCP_ENOTSUPPORTED, "lcp_backward: the Monte Carlo LCP estimator is piecewise constant; no adjoint");
+    if (!M || !bytes) return fail(LCP_EINVAL, "model and bytes must not be NULL");
+    if (prec != LCP_FP64 && prec != LCP_FP32) return fail(LCP_EINVAL, "prec must be LCP_FP64 or LCP_FP32");
+    if (n_samples < 1) return fail(LCP_EINVAL, "n_samples < 1");
+    GridP g;
+    if (int r = check_grid(M, grid, &g)) return r;
+    *bytes = lcp_backward_ws(*M, g, prec, n_samples);
+    return ok();
+}
+
+int lcp_backward(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec,
+                 const double* dL_dlcp, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!M) return fail(LCP_EINVAL, "model is NULL");
+    if (M->sparse) return fail(LCP_ENOTSUPPORTED, "lcp_backward: the model comes from gp_fit_sgpr");
+    if (prec != LCP_FP64 && prec != LCP_FP32) return fail(LCP_EINVAL, "prec must be LCP_FP64 or LCP_FP32");
+    GridP g;
+    if (int r = check_grid(M, grid, &g)) return r;
+    if (int r = check_mc(M, mc)) return r;
+    if (mc->estimator != LCP_EST_SOV)
+        return fail(LCP_ENOTSUPPORTED, "lcp_backward: the counting estimator is piecewise constant (use LCP_EST_SOV)");
+    if (!is_finite(theta)) return fail(LCP_EINVAL, "theta must be finite");
+    if (!dL_dlcp || !dL_dy || !dL_dloglen || !ws) return fail(LCP_EINVAL, "dL_dlcp, dL_dy, dL_dloglen and ws must not be NULL");
+    if (!aligned256(ws)) return fail(LCP_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = lcp_backward_ws(*M, g, prec, mc->n_samples);
+    if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipError_t e = launch_lcp_backward(*M, g, theta, mc->n_samples, mc->zbank, prec, dL_dlcp, dL_dy, dL_dloglen,
+                                       (char*)ws, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "lcp_backward");
+    return ok();
 }
 
 }  // extern "C"
@@ -648,6 +685,7 @@ int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const doubl
     if (!theta) return fail(LCP_EINVAL, "theta is NULL");
     for (int b = 0; b < nb; ++b) {
         if (int r = check_mc(&B->models[b], mc)) return r;
+        if (mc->estimator != LCP_EST_COUNT) return fail(LCP_ENOTSUPPORTED, "lcp_dense_batch: counting estimator only");
         if (!is_finite(theta[b])) return fail(LCP_EINVAL, "theta[%d] must be finite", b);
     }
     if (!lcp || !ws) return fail(LCP_EINVAL, "lcp and ws must not be NULL");

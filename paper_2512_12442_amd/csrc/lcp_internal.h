@@ -216,6 +216,12 @@ inline size_t cells_scratch_bytes(int64_t ncells_cap) { return ((4 * (size_t)nce
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s);
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s);
+// Smooth (separation-of-variables) LCP of every cell of a dense grid; wb: ns x 2^D doubles.
+hipError_t launch_cells_sov(const CellTask& t, double* wb, hipStream_t s);
+// Its adjoint for upstream gl (per cell): per-cell gradients gout (2^D + 2^D (2^D + 1) / 2
+// doubles each), then per vertex gmean, gvar and gcross (13 / 4 directions).
+hipError_t launch_cells_sov_grad(const CellTask& t, double* wb, const double* gl, double* gout, double* gmean,
+                                 double* gvar, double* gcross, hipStream_t s);
 // Dense cells of nb tasks in one pass; every task's work/wcount/zmax must point to one
 // shared list (>= total cells), count and zmax; scratch holds cells_batch_scratch(nb) bytes.
 size_t cells_batch_scratch(int nb);
@@ -260,6 +266,10 @@ hipError_t launch_sparse_finish(Model& M, hipStream_t s);
 size_t posterior_backward_ws(const Model& M, int64_t n, int prec);
 hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq, int prec, const double* gm,
                                      const double* gv, double* dy, double* dlogell, char* ws, hipStream_t s);
+// Adjoint of the smooth LCP field of a dense grid (upstream gl per cell).
+size_t lcp_backward_ws(const Model& M, const GridP& g, int prec, int ns);
+hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int ns, const double* zb, int prec,
+                               const double* gl, double* dy, double* dlogell, char* ws, hipStream_t s);
 size_t factor_batch_scratch(int nb);
 hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
                                int* info_dev, hipStream_t s);

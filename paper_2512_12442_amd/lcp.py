@@ -43,14 +43,18 @@ class Adapt(C.Structure):
 
 
 class MC(C.Structure):
-    _fields_ = [("n_samples", C.c_int), ("zbank", C.c_void_p)]
+    _fields_ = [("n_samples", C.c_int), ("zbank", C.c_void_p), ("estimator", C.c_int)]
+
+
+EST_COUNT, EST_SOV = 0, 1
 
 
 EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor", "gp_fit_sgpr", "gp_model_free",
            "lcp_posterior_workspace", "lcp_dense_workspace", "lcp_adaptive_workspace", "gp_posterior",
            "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
-           "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward"]
+           "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward",
+           "lcp_backward_workspace"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -82,7 +86,8 @@ def lib():
     L.gp_posterior.argtypes = [P, I64, P, C.c_int, P, P, P, SZ, P]
     L.lcp_dense.argtypes = [P, P, C.c_double, P, C.c_int, P, P, SZ, P]
     L.lcp_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int, P, P, I64, P, P, P, SZ, P]
-    L.lcp_backward.argtypes = [P, P, C.c_double, P, P, P, P, P, SZ, P]
+    L.lcp_backward.argtypes = [P, P, C.c_double, P, C.c_int, P, P, P, P, SZ, P]
+    L.lcp_backward_workspace.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(SZ)]
     L.gp_posterior_backward_workspace.argtypes = [P, I64, C.c_int, C.POINTER(SZ)]
     L.gp_posterior_backward.argtypes = [P, I64, P, C.c_int, P, P, P, P, P, SZ, P]
     L.lcp_profile_begin.argtypes = [C.c_uint]
@@ -220,9 +225,10 @@ class GPModel:
                                             C.byref(b)))
         return b.value
 
-    def lcp_dense(self, grid: Grid, theta: float, zbank: torch.Tensor, prec="fp64", out=None, ws=None):
+    def lcp_dense(self, grid: Grid, theta: float, zbank: torch.Tensor, prec="fp64", out=None, ws=None,
+                  estimator=EST_COUNT):
         zbank = zbank.to(torch.float64).contiguous()
-        mc = MC(int(zbank.shape[0]), zbank.data_ptr())
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr(), int(estimator))
         nb = self.dense_workspace(grid, prec, mc.n_samples)
         if ws is None or ws.numel() < nb:
             ws = _buffer(nb, self.device)
@@ -259,12 +265,20 @@ class GPModel:
                                   ws.numel(), _stream()))
         return out, leaves, n_leaves, lf, ws
 
-    def lcp_backward(self, grid: Grid, theta: float, zbank: torch.Tensor, dL_dlcp: torch.Tensor):
-        mc = MC(int(zbank.shape[0]), zbank.data_ptr())
-        dy = torch.zeros(self.m, dtype=torch.float64, device=self.device)
-        dl = torch.zeros(3, dtype=torch.float64, device=self.device)
-        _check(lib().lcp_backward(self.h, C.byref(grid), float(theta), C.byref(mc), _ptr(dL_dlcp), _ptr(dy),
-                                  _ptr(dl), None, 0, _stream()))
+    def lcp_backward(self, grid: Grid, theta: float, zbank: torch.Tensor, dL_dlcp: torch.Tensor, prec="fp64",
+                     ws=None):
+        """Adjoint of the smooth LCP field (lcp_dense with EST_SOV): (dL/dy, dL/dlog(lengthscale))."""
+        zbank = zbank.to(torch.float64).contiguous()
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr(), EST_SOV)
+        b = C.c_size_t()
+        _check(lib().lcp_backward_workspace(self.h, C.byref(grid), _prec(prec), mc.n_samples, C.byref(b)))
+        if ws is None or ws.numel() < b.value:
+            ws = _buffer(b.value, self.device)
+        g = dL_dlcp.to(torch.float64).contiguous()
+        dy = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        dl = torch.empty(self.dim, dtype=torch.float64, device=self.device)
+        _check(lib().lcp_backward(self.h, C.byref(grid), float(theta), C.byref(mc), _prec(prec), _ptr(g), _ptr(dy),
+                                  _ptr(dl), _ptr(ws), b.value, _stream()))
         return dy, dl
 
 
@@ -288,6 +302,31 @@ class GPPosterior(torch.autograd.Function):
         (Xq,) = ctx.saved_tensors
         dy, dl = ctx.G.posterior_backward(Xq, gmean, gvar, ctx.prec)
         return dy, dl, None, None, None, None, None, None
+
+
+class GPLcp(torch.autograd.Function):
+    """Smooth LCP field (separation-of-variables estimate) of a dense grid as a
+    differentiable function of y and the log-lengthscales: forward fits the model and runs
+    lcp_dense with EST_SOV; backward runs lcp_backward."""
+
+    @staticmethod
+    def forward(ctx, y, log_ell, X, grid, theta, zbank, kind, signal_var, noise_var, prec):
+        ell = torch.exp(log_ell.detach()).cpu().tolist()
+        ell = ell + [1.0] * (3 - len(ell))
+        G = GPModel(kind, X.shape[1], signal_var, ell, noise_var, X, y.detach())
+        out, _ = G.lcp_dense(grid, theta, zbank, prec, estimator=EST_SOV)
+        ctx.G, ctx.grid, ctx.theta, ctx.zbank, ctx.prec = G, grid, theta, zbank, prec
+        return out.to(torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        dy, dl = ctx.G.lcp_backward(ctx.grid, ctx.theta, ctx.zbank, g, ctx.prec)
+        return dy, dl, None, None, None, None, None, None, None, None
+
+
+def lcp_fn(y, log_ell, X, grid, theta, zbank, kind=SE, signal_var=1.0, noise_var=1e-4, prec="fp64"):
+    """Differentiable smooth LCP field; gradients flow to y and log_ell."""
+    return GPLcp.apply(y, log_ell, X, grid, theta, zbank, kind, signal_var, noise_var, prec)
 
 
 def posterior_fn(y, log_ell, X, Xq, kind=SE, signal_var=1.0, noise_var=1e-4, prec="fp64"):

@@ -74,10 +74,14 @@ def test_sparse_fit_validates_on_the_host():
     assert rc == lcp.lcp.LCP_ENOMEM
 
 
-def test_backward_reports_not_supported():
+def test_backward_validates_on_the_host():
     L = lcp.lib()
-    rc = L.lcp_backward(None, None, 0.0, None, None, None, None, None, 0, None)
-    assert rc == lcp.lcp.LCP_ENOTSUPPORTED
+    rc = L.lcp_backward(None, None, 0.0, None, 0, None, None, None, None, 0, None)
+    assert rc == lcp.lcp.LCP_EINVAL and "model" in L.lcp_last_error().decode()
+    b = C.c_size_t()
+    assert L.lcp_backward_workspace(None, None, 0, 16, C.byref(b)) == lcp.lcp.LCP_EINVAL
+    rc = L.gp_posterior_backward(None, 4, None, 0, None, None, None, None, None, 0, None)
+    assert rc == lcp.lcp.LCP_EINVAL
 
 
 def test_null_model_rejected_everywhere():

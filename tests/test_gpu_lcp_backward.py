@@ -1,0 +1,129 @@
+"""Parity of the smooth LCP field (lcp_dense with the separation-of-variables estimator) and
+of its adjoint (lcp_backward) with the FP64 oracle.
+
+Tolerances:
+  * smooth field, binary64 arithmetic: 1e-6 absolute, the field being stored in binary32
+    (both sides evaluate the same products of normal probabilities; observed 3e-8);
+  * adjoint, binary64: 1e-7 relative to the largest component (cell gradients through the
+    factor's adjoint amplify the posterior's rounding by the cell covariance's condition);
+  * adjoint, binary32 V and W: 2e-2 relative (binary32 cross-covariances of neighbouring
+    vertices lose about cond(Sigma_cell) 2^-24 relative accuracy in the cell covariance).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_2512_12442_amd as lcp
+from parity_util import DEV, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(dim=3, npts=9, m=30, kind=workloads.SE, seed=90, ns=200):
+    W = workloads.random_small(seed, dim, m, npts, kind=kind, ell=0.35, signal_var=0.05, noise_var=1e-3)
+    W.zbank = W.zbank[:ns]
+    return W
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("dim,npts,kind", [(3, 9, workloads.SE), (3, 7, workloads.MATERN52), (2, 17, workloads.SE)])
+def test_smooth_field_matches_oracle(dim, npts, kind):
+    W = _case(dim, npts, kind=kind)
+    ref = oracle.lcp_sov_dense(oracle.fit(W), W).reshape(-1)
+    G = lcp.GPModel.from_workload(W, DEV)
+    out, _ = G.lcp_dense(lcp.grid_of(W), W.theta, torch.as_tensor(W.zbank, device=DEV), "fp64",
+                         estimator=lcp.EST_SOV)
+    got = out.cpu().numpy().astype(np.float64)
+    say(f"smooth field dim={dim} npts={npts}: max diff {np.abs(got - ref).max():.2e}, mean LCP {ref.mean():.3f}")
+    assert (ref > 1e-3).sum() > 10
+    assert np.abs(got - ref).max() <= 1e-6       # the field is stored in binary32
+
+
+@pytest.mark.parametrize("dim,npts,kind,m", [(3, 9, workloads.SE, 30), (3, 7, workloads.MATERN52, 45),
+                                             (2, 17, workloads.SE, 20), (3, 6, workloads.SE, 1)])
+def test_lcp_backward_fp64_matches_oracle(dim, npts, kind, m):
+    W = _case(dim, npts, m=m, kind=kind)
+    u = np.random.default_rng(91).random(W.n_cells)
+    dy_ref, dl_ref = oracle.lcp_backward(oracle.fit(W), W, u)
+    G = lcp.GPModel.from_workload(W, DEV)
+    dy, dl = G.lcp_backward(lcp.grid_of(W), W.theta, torch.as_tensor(W.zbank, device=DEV),
+                            torch.as_tensor(u, device=DEV), "fp64")
+    dy, dl = dy.cpu().numpy(), dl.cpu().numpy()
+    say(f"lcp backward fp64 dim={dim} npts={npts} m={m}: rel dy={_rel(dy, dy_ref):.2e} "
+        f"rel dlogell={_rel(dl, dl_ref):.2e} dlogell={dl}")
+    assert np.abs(dy_ref).max() > 0
+    assert _rel(dy, dy_ref) <= 1e-7
+    assert _rel(dl, dl_ref) <= 1e-7
+
+
+def test_lcp_backward_fp32_error():
+    W = _case(3, 9, m=60, seed=92)
+    u = np.random.default_rng(93).random(W.n_cells)
+    dy_ref, dl_ref = oracle.lcp_backward(oracle.fit(W), W, u)
+    G = lcp.GPModel.from_workload(W, DEV)
+    dy, dl = G.lcp_backward(lcp.grid_of(W), W.theta, torch.as_tensor(W.zbank, device=DEV),
+                            torch.as_tensor(u, device=DEV), "fp32")
+    dy, dl = dy.cpu().numpy(), dl.cpu().numpy()
+    say(f"lcp backward fp32: rel dy={_rel(dy, dy_ref):.2e} rel dlogell={_rel(dl, dl_ref):.2e}")
+    assert _rel(dy, dy_ref) <= 2e-2
+    assert _rel(dl, dl_ref) <= 2e-2
+
+
+def test_autograd_lcp_matches_gpu_finite_differences():
+    """torch.autograd through lcp_fn against central differences of the GPU smooth field
+    (binary64 arithmetic, re-fitted at each perturbed input, h = 1e-4)."""
+    W = _case(3, 8, m=20, seed=94, ns=300)
+    X = torch.as_tensor(W.X, device=DEV)
+    zb = torch.as_tensor(W.zbank, device=DEV)
+    grid = lcp.grid_of(W)
+    u = torch.as_tensor(np.random.default_rng(95).random(W.n_cells), device=DEV)
+
+    def loss(y, log_ell):
+        field = lcp.lcp_fn(y, log_ell, X, grid, W.theta, zb, W.kind, W.signal_var, W.noise_var, "fp64")
+        return (u * field).sum()
+
+    y = torch.as_tensor(W.y, device=DEV).requires_grad_(True)
+    log_ell = torch.log(torch.as_tensor(W.lengthscale[:3], device=DEV)).requires_grad_(True)
+    loss(y, log_ell).backward()
+    # The forward field is stored in binary32 (2^-24 relative per cell); over the 343 cells
+    # the loss carries about sqrt(343) * 3e-8 of rounding, i.e. ~2e-3 in a central difference
+    # with h = 1e-4, while the truncation error of the difference stays below 1e-6.  The
+    # binary64 finite-difference check at h = 1e-6 is the oracle's (test_oracle_sov).
+    h = 1e-4
+    with torch.no_grad():
+        for j in (0, 9, 19):
+            e = torch.zeros_like(y)
+            e[j] = h
+            fd = (loss(y + e, log_ell) - loss(y - e, log_ell)).item() / (2 * h)
+            say(f"autograd y[{j}]: {y.grad[j].item():.7e} fd {fd:.7e}")
+            assert abs(y.grad[j].item() - fd) <= 5e-3
+        for d in range(3):
+            e = torch.zeros_like(log_ell)
+            e[d] = h
+            fd = (loss(y, log_ell + e) - loss(y, log_ell - e)).item() / (2 * h)
+            say(f"autograd log_ell[{d}]: {log_ell.grad[d].item():.7e} fd {fd:.7e}")
+            assert abs(log_ell.grad[d].item() - fd) <= 5e-3
+
+
+def test_lcp_backward_rejects_counting_estimator_and_sparse_models():
+    W = _case(3, 5, m=10)
+    G = lcp.GPModel.from_workload(W, DEV)
+    L = lcp.lib()
+    import ctypes as C
+    zb = torch.as_tensor(W.zbank, device=DEV)
+    mc = lcp.lcp.MC(int(zb.shape[0]), zb.data_ptr(), lcp.EST_COUNT)
+    g = torch.zeros(W.n_cells, dtype=torch.float64, device=DEV)
+    dy = torch.zeros(W.m, dtype=torch.float64, device=DEV)
+    dl = torch.zeros(3, dtype=torch.float64, device=DEV)
+    grid = lcp.grid_of(W)
+    rc = L.lcp_backward(G.h, C.byref(grid), W.theta, C.byref(mc), 0, g.data_ptr(), dy.data_ptr(), dl.data_ptr(),
+                        None, 0, None)
+    assert rc == lcp.lcp.LCP_ENOTSUPPORTED and "counting" in L.lcp_last_error().decode()
+    S = lcp.GPModel.from_workload(workloads.sgpr_field(96, m=27, npts=5, train_npts=8, ell=0.3), DEV)
+    with pytest.raises(lcp.LcpError):
+        S.lcp_backward(grid, W.theta, zb, g, "fp64")
