@@ -129,6 +129,60 @@ def run_local_blocks(args):
     print(json.dumps(line), flush=True)
 
 
+def run_grad(args):
+    """Differentiation step: smooth LCP field of a 96^3 grid and the posterior at 2000 held-out
+    points from one fit (m = 1000, SE, learnable log-lengthscales), loss = sum_c u_c LCP_c +
+    MSE of the held-out mean, then the adjoint with respect to y and log(ell)."""
+    import numpy as np
+    import torch
+
+    import paper_2512_12442_amd as lcp
+    import workloads
+
+    dev = torch.device("cuda:0")
+    W, u, Ph, fh = workloads.grad_field(args.seed, npts=args.npts if args.npts != 128 else 96)
+    prec = "fp32" if not args.batch_prec_given else args.prec
+    X = torch.as_tensor(W.X, device=dev)
+    zb = torch.as_tensor(W.zbank, device=dev)
+    grid = lcp.grid_of(W)
+    ut = torch.as_tensor(u, device=dev)
+    Pt = torch.as_tensor(Ph, device=dev)
+    ft = torch.as_tensor(fh, device=dev)
+
+    def step():
+        y = torch.as_tensor(W.y, device=dev).requires_grad_(True)
+        log_ell = torch.log(torch.as_tensor(W.lengthscale, device=dev)).requires_grad_(True)
+        field, mean, _ = lcp.lcp_posterior_fn(y, log_ell, X, grid, W.theta, zb, Pt, W.kind, W.signal_var,
+                                              W.noise_var, prec)
+        loss = (ut * field).sum() + ((mean - ft) ** 2).mean()
+        loss.backward()
+        return loss, y.grad, log_ell.grad
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    with lcp.StageTimer() as st:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            loss, gy, gl = step()
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    stage_ms = {k: v / args.steps for k, v in st.ms.items()}
+    line = {
+        "metric": "differentiable LCP grid pts/s (forward + adjoint, 96^3, m=1000)",
+        "value": W.n_vertices / (step_ms * 1e-3), "unit": "grid pts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32+f64", "fp64": "f64"}.get(prec, prec), "data": "synthetic",
+        "config": {"workload": f"{W.npts[0]}^3 grid, m={W.m} uniform observations of the trig field (noise 1e-5), "
+                               f"SE l=0.1 (learnable log-lengthscales), s2=1e-3, loss = sum u_c LCP_c (u~U[0,1], "
+                               f"separation-of-variables LCP, N_s={W.n_samples}) + held-out mean MSE (2000 points)",
+                   "precision": prec, "parallelism": "1 GPU"},
+        "stage_ms": stage_ms, "loss": float(loss.item()), "grad_loglen": gl.cpu().tolist(),
+        "grad_y_norm": float(gy.norm().item()),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +198,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for rocprofv3 traffic counters)")
     ap.add_argument("--print-source-hash", action="store_true", help="print the posterior kernel source hash")
-    ap.add_argument("--workload", default="trig128", choices=["trig128", "sgpr500", "local_blocks"],
+    ap.add_argument("--workload", default="trig128", choices=["trig128", "sgpr500", "local_blocks", "grad96"],
                     help="trig128: the headline adaptive LCP; local_blocks: batched local GP models")
     ap.add_argument("--blocks", type=int, default=256, help="number of models for --workload local_blocks")
     args = ap.parse_args()
@@ -159,6 +213,10 @@ def main():
     if args.workload == "local_blocks":
         args.batch_prec_given = "--prec" in sys.argv
         run_local_blocks(args)
+        return
+    if args.workload == "grad96":
+        args.batch_prec_given = "--prec" in sys.argv
+        run_grad(args)
         return
     import numpy as np
     import torch

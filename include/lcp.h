@@ -84,7 +84,8 @@ typedef enum {
     LCP_EST_SOV = 1          /* the same probability by Genz's separation of variables, with uniforms
                                 Phi(z) from the first 2^dim - 1 normals of each row: smooth in the
                                 cell's mean and covariance, so it has an adjoint (lcp_backward);
-                                lcp_dense only */
+                                lcp_dense only; binary64 samples for LCP_FP64, binary32 samples
+                                with binary64 sums otherwise */
 } lcp_estimator;
 
 typedef struct {
@@ -271,8 +272,8 @@ int gp_posterior_backward(const lcp_model* model, int64_t n, const double* Xq, i
  * neighbour terms; K* regenerated, never stored).
  *   model   from gp_fit_factor (LCP_ENOTSUPPORTED for a gp_fit_sgpr model)
  *   grid, theta, mc   as for lcp_dense; mc->estimator must be LCP_EST_SOV
- *   prec    LCP_FP64 or LCP_FP32: precision of V and W = K^-1 K*^T (the cell gradients,
- *           factors and every sum are binary64)
+ *   prec    LCP_FP64 or LCP_FP32: precision of V, W = K^-1 K*^T and the estimator's samples
+ *           (cell factors, their adjoint and every sum are binary64)
  *   dL_dlcp cells binary64 (device)
  *   dL_dy   m binary64 (device), overwritten;  dL_dloglen  dim binary64 (device), overwritten
  *   ws, ws_bytes   256-byte aligned, >= lcp_backward_workspace bytes (about 4 n m_pad

@@ -7,5 +7,5 @@ runs in the HIP library liblcp.so (C ABI in include/lcp.h); this package only ma
 arguments.
 """
 from .lcp import (EST_COUNT, EST_SOV, FP32, FP64, MATERN52, MIXED_BF16X3, MIXED_F16X3, PRECISIONS, SE, Adapt, GPModel, GPModelBatch,  # noqa: F401
-                  GPLcp, GPPosterior, Grid, LcpError, lcp_fn,
+                  GPLcp, GPLcpPosterior, GPPosterior, Grid, LcpError, lcp_fn, lcp_posterior_fn,
                   StageTimer, adapt_of, grid_of, lib, make_grid, posterior_fn)

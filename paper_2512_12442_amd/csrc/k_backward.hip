@@ -541,7 +541,7 @@ hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int
     // cell gradients of the smooth LCP, gathered per vertex
     CellTask ct{};
     ct.grid = g;
-    ct.prec = LCP_FP64;
+    ct.prec = prec;
     ct.theta = theta;
     ct.ns = ns;
     ct.zb64 = zb;

@@ -541,74 +541,90 @@ __global__ void k_fill(T* __restrict__ p, T v, int64_t n)
 // y_j) / C_ii, and y_i is drawn inside orthant i by inversion.  Smooth in mu and C; a zero
 // pivot makes its factor a step.  Binary64 throughout, one lane per cell.
 
-__device__ __forceinline__ double phi_pdf(double t) { return exp(-0.5 * t * t) * 0.39894228040143267794; }
-__device__ __forceinline__ double phi_inv(double u) { return normcdfinv(fmin(fmax(u, 1e-300), 1.0 - 1e-16)); }
+template <class T>
+struct SovMath;
+template <>
+struct SovMath<double> {
+    static __device__ __forceinline__ double cdf(double t) { return normcdf(t); }
+    static __device__ __forceinline__ double pdf(double t) { return exp(-0.5 * t * t) * 0.39894228040143267794; }
+    static __device__ __forceinline__ double inv(double u) { return normcdfinv(fmin(fmax(u, 1e-300), 1.0 - 1e-16)); }
+};
+template <>
+struct SovMath<float> {
+    static __device__ __forceinline__ float cdf(float t) { return normcdff(t); }
+    static __device__ __forceinline__ float pdf(float t) { return expf(-0.5f * t * t) * 0.398942280f; }
+    static __device__ __forceinline__ float inv(float u) { return normcdfinvf(fminf(fmaxf(u, 1e-37f), 1.0f - 1e-7f)); }
+};
 
 // Lower-triangular N x N matrices packed by rows: (i, j), j <= i, at i (i + 1) / 2 + j.
 template <int N>
 constexpr int kTri = N * (N + 1) / 2;
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// One sample of one orthant (upper = 1: all above theta); mt = mu - theta.
-template <int N>
-__device__ __forceinline__ double sov_orthant(const double (&mt)[N], const double (&C)[kTri<N>], bool upper,
-                                              const double* __restrict__ w, double (&t)[N], double (&e)[N],
-                                              double (&y)[N])
+// One sample of one orthant (upper = 1: all above theta); mt = mu - theta.  T is the
+// arithmetic of the sample (binary64, or binary32 for the binary32 paths).
+template <int N, class T>
+__device__ __forceinline__ T sov_orthant(const T (&mt)[N], const T (&C)[kTri<N>], bool upper,
+                                         const double* __restrict__ w, T (&t)[N], T (&e)[N], T (&y)[N])
 {
-    double f = 1.0;
+    using M = SovMath<T>;
+    T f = 1;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        double si = 0.0;
+        T si = 0;
 #pragma unroll
         for (int j = 0; j < i; ++j) si = fma(C[tri(i, j)], y[j], si);
-        const double r = -mt[i] - si;
-        const double cii = C[tri(i, i)];
-        if (cii > 0.0) {
+        const T r = -mt[i] - si;
+        const T cii = C[tri(i, i)];
+        if (cii > T(0)) {
             t[i] = r / cii;
-            e[i] = normcdf(upper ? -t[i] : t[i]);
+            e[i] = M::cdf(upper ? -t[i] : t[i]);
         } else {
-            t[i] = 0.0;
-            e[i] = upper ? (r < 0.0 ? 1.0 : 0.0) : (r > 0.0 ? 1.0 : 0.0);
+            t[i] = 0;
+            e[i] = upper ? (r < T(0) ? T(1) : T(0)) : (r > T(0) ? T(1) : T(0));
         }
         f *= e[i];
-        y[i] = 0.0;
-        if (i < N - 1 && cii > 0.0) y[i] = phi_inv(upper ? 1.0 - e[i] + w[i] * e[i] : w[i] * e[i]);
+        y[i] = 0;
+        const T wi = (T)w[i];
+        if (i < N - 1 && cii > T(0)) y[i] = M::inv(upper ? T(1) - e[i] + wi * e[i] : wi * e[i]);
     }
     return f;
 }
 
-// Reverse pass of one orthant sample, scaled: adds d f / d mu to gmu and d f / d C to gC.
-template <int N>
-__device__ __forceinline__ void sov_orthant_rev(const double (&C)[kTri<N>], bool upper, const double* __restrict__ w,
-                                                const double (&t)[N], const double (&e)[N], const double (&y)[N],
-                                                double scale, double (&gmu)[N], double (&gC)[kTri<N>])
+// Reverse pass of one orthant sample, scaled: adds d f / d mu to gmu and d f / d C to gC
+// (binary64 accumulators).
+template <int N, class T>
+__device__ __forceinline__ void sov_orthant_rev(const T (&C)[kTri<N>], bool upper, const double* __restrict__ w,
+                                                const T (&t)[N], const T (&e)[N], const T (&y)[N], T scale,
+                                                double (&gmu)[N], double (&gC)[kTri<N>])
 {
-    double suf[N + 1], ybar[N];
-    suf[N] = 1.0;
+    using M = SovMath<T>;
+    T suf[N + 1], ybar[N], pre[N];
+    suf[N] = 1;
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) suf[i] = suf[i + 1] * e[i];
-    double pre[N];
-    pre[0] = 1.0;
+    pre[0] = 1;
 #pragma unroll
     for (int i = 1; i < N; ++i) pre[i] = pre[i - 1] * e[i - 1];
 #pragma unroll
-    for (int i = 0; i < N; ++i) ybar[i] = 0.0;
+    for (int i = 0; i < N; ++i) ybar[i] = 0;
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-        const double cii = C[tri(i, i)];
-        if (!(cii > 0.0)) continue;
-        double ebar = scale * pre[i] * suf[i + 1];
+        const T cii = C[tri(i, i)];
+        if (!(cii > T(0))) continue;
+        T ebar = scale * pre[i] * suf[i + 1];
         if (i < N - 1) {
-            const double py = phi_pdf(y[i]);
-            if (py > 0.0) ebar += ybar[i] * (upper ? w[i] - 1.0 : w[i]) / py;
+            const T py = M::pdf(y[i]);
+            const T wi = (T)w[i];
+            if (py > T(0)) ebar += ybar[i] * (upper ? wi - T(1) : wi) / py;
         }
-        const double tbar = ebar * phi_pdf(t[i]) * (upper ? -1.0 : 1.0);
-        const double rbar = tbar / cii;
-        gC[tri(i, i)] -= tbar * t[i] / cii;
-        gmu[i] -= rbar;
+        const T tbar = ebar * M::pdf(t[i]) * (upper ? T(-1) : T(1));
+        const T rbar = tbar / cii;
+        gC[tri(i, i)] -= (double)(tbar * t[i] / cii);
+        gmu[i] -= (double)rbar;
 #pragma unroll
         for (int j = 0; j < i; ++j) {
-            gC[tri(i, j)] -= rbar * y[j];
+            gC[tri(i, j)] -= (double)(rbar * y[j]);
             ybar[j] -= rbar * C[tri(i, j)];
         }
     }
@@ -644,13 +660,13 @@ __device__ __forceinline__ void chol_sd_rev(const double (&C)[kTri<N>], double (
     }
 }
 
-template <int N>
-__device__ __forceinline__ void pack_lower(const double (&Cd)[N][N], double (&C)[kTri<N>])
+template <int N, class T>
+__device__ __forceinline__ void pack_lower(const double (&Cd)[N][N], T (&C)[kTri<N>])
 {
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int j = 0; j <= i; ++j) C[tri(i, j)] = Cd[i][j];
+        for (int j = 0; j <= i; ++j) C[tri(i, j)] = (T)Cd[i][j];
 }
 
 __global__ void k_wbank(const double* __restrict__ zb, double* __restrict__ wb, int64_t n)
@@ -660,7 +676,7 @@ __global__ void k_wbank(const double* __restrict__ zb, double* __restrict__ wb, 
 }
 
 // Smooth LCP of every cell of the dense grid.
-template <int D>
+template <int D, class T>
 __global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __restrict__ wb, int64_t ncell)
 {
     constexpr int N = 1 << D;
@@ -669,14 +685,17 @@ __global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __r
         const int st = cell_corners<D>(t, c, lin, sl);
         if (st == 0) continue;
         if (st == 1) { t.lcp[lin] = __builtin_nanf(""); continue; }
-        double mt[N], Cd[N][N], C[kTri<N>], tt[N], e[N], y[N];
-        cell_factor<D>(t, sl, mt, Cd);
+        double md[N], Cd[N][N];
+        T mt[N], C[kTri<N>], tt[N], e[N], y[N];
+        cell_factor<D>(t, sl, md, Cd);
+#pragma unroll
+        for (int q = 0; q < N; ++q) mt[q] = (T)md[q];
         pack_lower<N>(Cd, C);
         double acc = 0.0;
         for (int sIdx = 0; sIdx < t.ns; ++sIdx) {
             const double* w = wb + (size_t)sIdx * N;
-            acc += sov_orthant<N>(mt, C, false, w, tt, e, y);
-            acc += sov_orthant<N>(mt, C, true, w, tt, e, y);
+            acc += (double)sov_orthant<N, T>(mt, C, false, w, tt, e, y);
+            acc += (double)sov_orthant<N, T>(mt, C, true, w, tt, e, y);
         }
         t.lcp[lin] = (float)(1.0 - acc / (double)t.ns);
     }
@@ -684,7 +703,7 @@ __global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __r
 
 // Gradient of gl[cell] * LCP_cell with respect to the cell's corner means (N values) and
 // the lower triangle of its corner covariance (N (N + 1) / 2, packed) -> gout[cell].
-template <int D>
+template <int D, class T>
 __global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double* __restrict__ wb,
                                                         const double* __restrict__ gl, double* __restrict__ gout,
                                                         int64_t ncell)
@@ -702,22 +721,32 @@ __global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double
             for (int i = 0; i < NO; ++i) out[i] = 0.0;
             continue;
         }
-        double mt[N], Cd[N][N], C[kTri<N>], tt[N], e[N], y[N], gmu[N], gC[kTri<N>], gS[kTri<N>];
-        cell_factor<D>(t, sl, mt, Cd);
+        double md[N], Cd[N][N], C64[kTri<N>], gmu[N], gC[kTri<N>], gS[kTri<N>];
+        T mt[N], C[kTri<N>], tt[N], e[N], y[N];
+        cell_factor<D>(t, sl, md, Cd);
+#pragma unroll
+        for (int q = 0; q < N; ++q) mt[q] = (T)md[q];
         pack_lower<N>(Cd, C);
+        pack_lower<N>(Cd, C64);
 #pragma unroll
         for (int i = 0; i < N; ++i) gmu[i] = 0.0;
 #pragma unroll
         for (int i = 0; i < kTri<N>; ++i) gC[i] = 0.0;
-        const double scale = -up / (double)t.ns;       // LCP = 1 - mean(f_lo + f_hi)
+        // LCP = 1 - mean(f_lo + f_hi): each sample's reverse pass runs with weight -1 and the
+        // binary64 sums are scaled once at the end
         for (int sIdx = 0; sIdx < t.ns; ++sIdx) {
             const double* w = wb + (size_t)sIdx * N;
-            sov_orthant<N>(mt, C, false, w, tt, e, y);
-            sov_orthant_rev<N>(C, false, w, tt, e, y, scale, gmu, gC);
-            sov_orthant<N>(mt, C, true, w, tt, e, y);
-            sov_orthant_rev<N>(C, true, w, tt, e, y, scale, gmu, gC);
+            sov_orthant<N, T>(mt, C, false, w, tt, e, y);
+            sov_orthant_rev<N, T>(C, false, w, tt, e, y, T(-1), gmu, gC);
+            sov_orthant<N, T>(mt, C, true, w, tt, e, y);
+            sov_orthant_rev<N, T>(C, true, w, tt, e, y, T(-1), gmu, gC);
         }
-        chol_sd_rev<N>(C, gC, gS);
+        const double scale = up / (double)t.ns;
+#pragma unroll
+        for (int i = 0; i < N; ++i) gmu[i] *= scale;
+#pragma unroll
+        for (int i = 0; i < kTri<N>; ++i) gC[i] *= scale;
+        chol_sd_rev<N>(C64, gC, gS);
 #pragma unroll
         for (int i = 0; i < N; ++i) out[i] = gmu[i];
 #pragma unroll
@@ -880,8 +909,14 @@ hipError_t launch_cells_sov(const CellTask& t, double* wb, hipStream_t s)
     StageScope sc(s, ST_CELLS);
     hipLaunchKernelGGL(k_wbank, dim3(grid_for((int64_t)t.ns << D, 256)), dim3(256), 0, s, t.zb64, wb,
                        (int64_t)t.ns << D);
-    if (D == 3) hipLaunchKernelGGL(k_cells_sov<3>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
-    else hipLaunchKernelGGL(k_cells_sov<2>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+    const bool f64 = t.prec == LCP_FP64;
+    if (D == 3) {
+        if (f64) hipLaunchKernelGGL((k_cells_sov<3, double>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+        else hipLaunchKernelGGL((k_cells_sov<3, float>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_cells_sov<2, double>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+        else hipLaunchKernelGGL((k_cells_sov<2, float>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
+    }
     return hipGetLastError();
 }
 
@@ -894,14 +929,16 @@ hipError_t launch_cells_sov_grad(const CellTask& t, double* wb, const double* gl
     StageScope sc(s, ST_CELLS);
     hipLaunchKernelGGL(k_wbank, dim3(grid_for((int64_t)t.ns << D, 256)), dim3(256), 0, s, t.zb64, wb,
                        (int64_t)t.ns << D);
+    const bool f64 = t.prec == LCP_FP64;
+    const unsigned gc = grid_for(ncell, 256);
     if (D == 3) {
-        if (ncell > 0)
-            hipLaunchKernelGGL(k_cells_sov_grad<3>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, gl, gout, ncell);
+        if (ncell > 0 && f64) hipLaunchKernelGGL((k_cells_sov_grad<3, double>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
+        if (ncell > 0 && !f64) hipLaunchKernelGGL((k_cells_sov_grad<3, float>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
         hipLaunchKernelGGL(k_sov_gather<3>, dim3(grid_for(nv, 256)), dim3(256), 0, s, t.grid, gout, gmean, gvar,
                            gcross);
     } else {
-        if (ncell > 0)
-            hipLaunchKernelGGL(k_cells_sov_grad<2>, dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, gl, gout, ncell);
+        if (ncell > 0 && f64) hipLaunchKernelGGL((k_cells_sov_grad<2, double>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
+        if (ncell > 0 && !f64) hipLaunchKernelGGL((k_cells_sov_grad<2, float>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
         hipLaunchKernelGGL(k_sov_gather<2>, dim3(grid_for(nv, 256)), dim3(256), 0, s, t.grid, gout, gmean, gvar,
                            gcross);
     }

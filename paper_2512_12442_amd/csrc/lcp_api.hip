@@ -444,7 +444,6 @@ int dense_cells(const lcp_model* M, const GridP& g, double theta, const lcp_mc* 
     ct.wcount = w.wcount;
     ct.zmax = w.zmax;
     if (mc->estimator == LCP_EST_SOV) {
-        ct.prec = LCP_FP64;
         e = launch_cells_sov(ct, w.wb, s);
     } else {
         e = launch_cells(ct, g.nc[0] * g.nc[1] * g.nc[2], s);

@@ -329,6 +329,35 @@ def lcp_fn(y, log_ell, X, grid, theta, zbank, kind=SE, signal_var=1.0, noise_var
     return GPLcp.apply(y, log_ell, X, grid, theta, zbank, kind, signal_var, noise_var, prec)
 
 
+class GPLcpPosterior(torch.autograd.Function):
+    """The smooth LCP field of a grid and the posterior at points Xq from one fit, as a
+    differentiable function of y and the log-lengthscales (backward: lcp_backward plus
+    gp_posterior_backward, summed)."""
+
+    @staticmethod
+    def forward(ctx, y, log_ell, X, grid, theta, zbank, Xq, kind, signal_var, noise_var, prec):
+        ell = torch.exp(log_ell.detach()).cpu().tolist()
+        ell = ell + [1.0] * (3 - len(ell))
+        G = GPModel(kind, X.shape[1], signal_var, ell, noise_var, X, y.detach())
+        field, _ = G.lcp_dense(grid, theta, zbank, prec, estimator=EST_SOV)
+        mean, var = G.posterior(Xq, prec)
+        ctx.G, ctx.grid, ctx.theta, ctx.zbank, ctx.prec = G, grid, theta, zbank, prec
+        ctx.save_for_backward(Xq)
+        return field.to(torch.float64), mean, var
+
+    @staticmethod
+    def backward(ctx, gfield, gmean, gvar):
+        (Xq,) = ctx.saved_tensors
+        dy, dl = ctx.G.lcp_backward(ctx.grid, ctx.theta, ctx.zbank, gfield, ctx.prec)
+        dy2, dl2 = ctx.G.posterior_backward(Xq, gmean, gvar, ctx.prec)
+        return dy + dy2, dl + dl2, None, None, None, None, None, None, None, None, None
+
+
+def lcp_posterior_fn(y, log_ell, X, grid, theta, zbank, Xq, kind=SE, signal_var=1.0, noise_var=1e-4, prec="fp64"):
+    """Differentiable (smooth LCP field, mean at Xq, variance at Xq) from one model fit."""
+    return GPLcpPosterior.apply(y, log_ell, X, grid, theta, zbank, Xq, kind, signal_var, noise_var, prec)
+
+
 def posterior_fn(y, log_ell, X, Xq, kind=SE, signal_var=1.0, noise_var=1e-4, prec="fp64"):
     """Differentiable (mean, var) at Xq; gradients flow to y and log_ell."""
     return GPPosterior.apply(y, log_ell, X, Xq, kind, signal_var, noise_var, prec)

@@ -229,6 +229,21 @@ def sgpr_field(seed: int, m: int = 500, npts: int = 128, train_npts: int = 32, n
                     _zbank(seed, n_samples, 3), seed, A_M)
 
 
+def grad_field(seed: int, m: int = 1000, npts: int = 96, n_heldout: int = 2000, n_samples: int = 1600):
+    """Differentiation workload: the trig field of field3d_trig observed at m uniform points
+    (noise variance 1e-5), an SE kernel with lengthscale 0.1 (the initial value of a learnable
+    log-lengthscale), s2 = 1e-3, an npts^3 grid, per-cell loss weights u ~ U[0, 1] and
+    n_heldout uniform points with their noise-free field values (for a mean-squared error).
+    Returns (workload, weights, held-out points, held-out values)."""
+    X = _rng(seed, 1).random((m, 3))
+    y = _trig_field(X, seed) + np.sqrt(1e-5) * _rng(seed, 3).standard_normal(m)
+    W = Workload(f"grad{npts}", 3, SE, 1e-3, np.array([0.1, 0.1, 0.1]), 1e-5, X, y, np.zeros(3), np.ones(3),
+                 np.array([npts] * 3, np.int64), float(np.median(y)), 1e-3, 4, _zbank(seed, n_samples, 3), seed)
+    u = _rng(seed, 11).random(W.n_cells)
+    P = _rng(seed, 12).random((n_heldout, 3))
+    return W, u, P, _trig_field(P, seed)
+
+
 def random_small(seed: int, dim: int, m: int, npts, kind: int = SE, n_samples: int = 1600,
                  signal_var: float = 1.0, ell: float = 0.25, noise_var: float = 1e-4,
                  min_leaf: int = 1, alpha: float = 1e-3) -> Workload:
