@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(256) k_bwd_stencil(KParams kp, GridP g, int mp
 struct BwdLayout {
     size_t kinv, f64, f32, w, mean, var, bpart, tpart, b, gpart, ppart, total;
     // LCP adjoint only
-    size_t V, cross, wbank, gout, gmean, gvar, gcross, z, u, dpart;
+    size_t V, cross, wbank, gout, gmean, gvar, gcross, z, u, dpart, work;
     int nsplit;
 };
 
@@ -390,7 +390,7 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64
         const int N = 1 << D, ndir = D == 3 ? 13 : 4;
         L.V = take(es * mp * nn);
         L.cross = take(8 * (size_t)ndir * nn);
-        L.wbank = take(8 * (size_t)ns * N);
+        L.wbank = take(8 * ((size_t)ns * N + 1));
         L.gout = take(8 * (size_t)(N + N * (N + 1) / 2) * (size_t)(ncell > 0 ? ncell : 1));
         L.gmean = take(8 * nn);
         L.gvar = take(8 * nn);
@@ -398,6 +398,7 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64
         L.z = take(es * mp * nn);
         L.u = take(es * mp * nn);
         L.dpart = take(8 * 4 * kBwdGridP);
+        L.work = take(4 * (size_t)(ncell > 0 ? ncell : 1) + 256);
     }
     L.total = o;
     return L;
@@ -548,6 +549,8 @@ hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int
     ct.mean = t.mean;
     ct.var = t.var;
     ct.cross = cross;
+    ct.work = (int32_t*)(ws + L.work);
+    ct.wcount = (int64_t*)(ws + L.work + align256(4 * (size_t)(nc > 0 ? nc : 1)));
     double* gmean = (double*)(ws + L.gmean);
     double* gvar = (double*)(ws + L.gvar);
     double* gcross = (double*)(ws + L.gcross);

@@ -675,12 +675,92 @@ __global__ void k_wbank(const double* __restrict__ zb, double* __restrict__ wb, 
         wb[i] = normcdf(zb[i]);
 }
 
-// Smooth LCP of every cell of the dense grid.
-template <int D, class T>
-__global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __restrict__ wb, int64_t ncell)
+// Largest |z| of the bank (one work-group of 256 threads) -> out[0].
+__global__ void k_zabsmax(const double* __restrict__ zb, int64_t n, double* __restrict__ out)
+{
+    __shared__ double red[4];
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) mx = fmax(mx, fabs(zb[i]));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Binary32 samples only: a cell whose corners all lie, with every conditional draw of the
+// bank, more than 6.5 conditional standard deviations on one side of theta has every
+// lower (or upper) orthant factor equal to 1 in binary32 and the other orthant's product
+// below 1e-10: its smooth LCP and gradient are zero at binary32 accuracy and are skipped.
+// In that orthant each draw is y_j = Phi^-1(w_j e_j) with e_j >= Phi(6.5), so |y_j| <= the
+// bank's largest |z| (ymax, plus a margin), and |sum_j C_ij y_j| <= ymax sum_j |C_ij|.
+template <int N>
+__device__ __forceinline__ bool sov_far(const double (&md)[N], const double (&Cd)[N][N], double ymax)
+{
+    bool below = true, above = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double r = 0.0;
+#pragma unroll
+        for (int j = 0; j < i; ++j) r += fabs(Cd[i][j]);
+        const double need = 6.5 * Cd[i][i] + ymax * r;
+        below = below && (-md[i] > need);
+        above = above && (md[i] > need);
+    }
+    return below || above;
+}
+
+// Binary32 smooth estimator: far cells (sov_far) get their zero LCP (lcp non-null) or zero
+// gradient (gout non-null) here; the others are appended to the work list, one atomic per
+// wave, so the sample loop runs on full waves.
+template <int D>
+__global__ void __launch_bounds__(256) k_sov_select(CellTask t, int64_t ncell, const double* __restrict__ zabs,
+                                                    float* __restrict__ lcp, double* __restrict__ gout,
+                                                    int32_t* __restrict__ work, int64_t* __restrict__ wcount)
 {
     constexpr int N = 1 << D;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x) {
+    constexpr int NO = N + kTri<N>;
+    const double ymax = zabs[0] + 0.01;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ncell; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = base + threadIdx.x;
+        bool need = false;
+        if (c < ncell) {
+            int64_t lin, sl[N];
+            const int st = cell_corners<D>(t, c, lin, sl);
+            if (st == 1) {
+                need = true;                         // the sample kernel writes NaN / zeros
+            } else if (st == 2) {
+                double md[N], Cd[N][N];
+                cell_factor<D>(t, sl, md, Cd);
+                if (sov_far<N>(md, Cd, ymax)) {
+                    if (lcp) lcp[lin] = 0.0f;
+                    if (gout)
+#pragma unroll
+                        for (int i = 0; i < NO; ++i) gout[(size_t)lin * NO + i] = 0.0;
+                } else {
+                    need = true;
+                }
+            }
+        }
+        const uint64_t bal = __ballot(need);
+        if (bal) {
+            int64_t pos = 0;
+            if (lane == 0) pos = atomicAdd((unsigned long long*)wcount, (unsigned long long)__popcll(bal));
+            pos = __shfl(pos, 0, 64);
+            if (need) work[pos + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)c;
+        }
+    }
+}
+
+// Smooth LCP of every cell of the dense grid (work == null) or of the listed cells.
+template <int D, class T>
+__global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __restrict__ wb, int64_t ncell,
+                                                   const int32_t* __restrict__ work, const int64_t* __restrict__ wcount)
+{
+    constexpr int N = 1 << D;
+    const int64_t total = work ? *wcount : ncell;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total; it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = work ? (int64_t)work[it] : it;
         int64_t lin, sl[N];
         const int st = cell_corners<D>(t, c, lin, sl);
         if (st == 0) continue;
@@ -706,11 +786,14 @@ __global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __r
 template <int D, class T>
 __global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double* __restrict__ wb,
                                                         const double* __restrict__ gl, double* __restrict__ gout,
-                                                        int64_t ncell)
+                                                        int64_t ncell, const int32_t* __restrict__ work,
+                                                        const int64_t* __restrict__ wcount)
 {
     constexpr int N = 1 << D;
     constexpr int NO = N + kTri<N>;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t total = work ? *wcount : ncell;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total; it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = work ? (int64_t)work[it] : it;
         int64_t lin, sl[N];
         const int st = cell_corners<D>(t, c, lin, sl);
         if (st == 0) continue;
@@ -901,22 +984,42 @@ void cells_dispatch(R src, bool f64, unsigned grid, int64_t cap, hipStream_t s)
 
 }  // namespace
 
+namespace {
+
+// Binary64: every cell.  Binary32: far cells first (k_sov_select), then the listed ones.
+template <int D>
+void sov_dispatch(const CellTask& t, double* wb, const double* gl, double* gout, int32_t* work, int64_t* wcount,
+                  hipStream_t s)
+{
+    const int64_t ncell = t.grid.nc[0] * t.grid.nc[1] * t.grid.nc[2];
+    const int64_t nz = (int64_t)t.ns << D;
+    double* zabs = wb + nz;
+    const unsigned gc = grid_for(ncell, 256);
+    hipLaunchKernelGGL(k_wbank, dim3(grid_for(nz, 256)), dim3(256), 0, s, t.zb64, wb, nz);
+    if (t.prec == LCP_FP64) {
+        if (gl) hipLaunchKernelGGL((k_cells_sov_grad<D, double>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell,
+                                   nullptr, nullptr);
+        else hipLaunchKernelGGL((k_cells_sov<D, double>), dim3(gc), dim3(256), 0, s, t, wb, ncell, nullptr, nullptr);
+        return;
+    }
+    hipLaunchKernelGGL(k_zabsmax, dim3(1), dim3(256), 0, s, t.zb64, nz, zabs);
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, wcount, (int64_t)0, (int64_t)1);
+    hipLaunchKernelGGL(k_sov_select<D>, dim3(gc), dim3(256), 0, s, t, ncell, zabs, gl ? nullptr : t.lcp, gout, work,
+                       wcount);
+    if (gl) hipLaunchKernelGGL((k_cells_sov_grad<D, float>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell, work,
+                               wcount);
+    else hipLaunchKernelGGL((k_cells_sov<D, float>), dim3(gc), dim3(256), 0, s, t, wb, ncell, work, wcount);
+}
+
+}  // namespace
+
 hipError_t launch_cells_sov(const CellTask& t, double* wb, hipStream_t s)
 {
-    const int D = t.grid.dim;
     const int64_t ncell = t.grid.nc[0] * t.grid.nc[1] * t.grid.nc[2];
     if (ncell <= 0) return hipSuccess;
     StageScope sc(s, ST_CELLS);
-    hipLaunchKernelGGL(k_wbank, dim3(grid_for((int64_t)t.ns << D, 256)), dim3(256), 0, s, t.zb64, wb,
-                       (int64_t)t.ns << D);
-    const bool f64 = t.prec == LCP_FP64;
-    if (D == 3) {
-        if (f64) hipLaunchKernelGGL((k_cells_sov<3, double>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
-        else hipLaunchKernelGGL((k_cells_sov<3, float>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
-    } else {
-        if (f64) hipLaunchKernelGGL((k_cells_sov<2, double>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
-        else hipLaunchKernelGGL((k_cells_sov<2, float>), dim3(grid_for(ncell, 256)), dim3(256), 0, s, t, wb, ncell);
-    }
+    if (t.grid.dim == 3) sov_dispatch<3>(t, wb, nullptr, nullptr, t.work, t.wcount, s);
+    else sov_dispatch<2>(t, wb, nullptr, nullptr, t.work, t.wcount, s);
     return hipGetLastError();
 }
 
@@ -927,21 +1030,16 @@ hipError_t launch_cells_sov_grad(const CellTask& t, double* wb, const double* gl
     const int64_t ncell = t.grid.nc[0] * t.grid.nc[1] * t.grid.nc[2];
     const int64_t nv = t.grid.n[0] * t.grid.n[1] * t.grid.n[2];
     StageScope sc(s, ST_CELLS);
-    hipLaunchKernelGGL(k_wbank, dim3(grid_for((int64_t)t.ns << D, 256)), dim3(256), 0, s, t.zb64, wb,
-                       (int64_t)t.ns << D);
-    const bool f64 = t.prec == LCP_FP64;
-    const unsigned gc = grid_for(ncell, 256);
-    if (D == 3) {
-        if (ncell > 0 && f64) hipLaunchKernelGGL((k_cells_sov_grad<3, double>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
-        if (ncell > 0 && !f64) hipLaunchKernelGGL((k_cells_sov_grad<3, float>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
+    if (ncell > 0) {
+        if (D == 3) sov_dispatch<3>(t, wb, gl, gout, t.work, t.wcount, s);
+        else sov_dispatch<2>(t, wb, gl, gout, t.work, t.wcount, s);
+    }
+    if (D == 3)
         hipLaunchKernelGGL(k_sov_gather<3>, dim3(grid_for(nv, 256)), dim3(256), 0, s, t.grid, gout, gmean, gvar,
                            gcross);
-    } else {
-        if (ncell > 0 && f64) hipLaunchKernelGGL((k_cells_sov_grad<2, double>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
-        if (ncell > 0 && !f64) hipLaunchKernelGGL((k_cells_sov_grad<2, float>), dim3(gc), dim3(256), 0, s, t, wb, gl, gout, ncell);
+    else
         hipLaunchKernelGGL(k_sov_gather<2>, dim3(grid_for(nv, 256)), dim3(256), 0, s, t.grid, gout, gmean, gvar,
                            gcross);
-    }
     return hipGetLastError();
 }
 

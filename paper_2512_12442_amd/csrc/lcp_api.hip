@@ -135,7 +135,7 @@ size_t dense_ws(const lcp_model* M, const GridP& g, int prec, int ns)
     b += align256(vb * (size_t)nv * M->m_pad);               // V
     b += align256(sizeof(double) * (size_t)nv * ndir(g.dim)); // cross
     b += align256(sizeof(float) * (size_t)ns * (1 << g.dim)); // FP32 z-bank
-    b += align256(sizeof(double) * (size_t)ns * (1 << g.dim)); // uniforms of the smooth estimator
+    b += align256(sizeof(double) * ((size_t)ns * (1 << g.dim) + 1)); // uniforms of the smooth estimator, max |z|
     b += cells_scratch_bytes(g.nc[0] * g.nc[1] * g.nc[2]);   // Monte Carlo work list
     return b;
 }
@@ -394,7 +394,7 @@ DenseWs carve_dense(const lcp_model* M, const GridP& g, int prec, int ns, char* 
     w.zb32 = (float*)p;
     p += align256(sizeof(float) * (size_t)ns * (1 << g.dim));
     w.wb = (double*)p;
-    p += align256(sizeof(double) * (size_t)ns * (1 << g.dim));
+    p += align256(sizeof(double) * ((size_t)ns * (1 << g.dim) + 1));
     const int64_t ncells = g.nc[0] * g.nc[1] * g.nc[2];
     w.work = (int32_t*)p;
     p += align256(4 * (size_t)ncells);

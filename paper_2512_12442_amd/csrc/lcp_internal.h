@@ -216,10 +216,11 @@ inline size_t cells_scratch_bytes(int64_t ncells_cap) { return ((4 * (size_t)nce
 hipError_t launch_cross(const Model& M, int prec, const GridP& g, const int32_t* vlist, const int64_t* nv_dev,
                         int64_t nv_cap, const int32_t* slot, const void* V, double* cross, hipStream_t s);
 hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s);
-// Smooth (separation-of-variables) LCP of every cell of a dense grid; wb: ns x 2^D doubles.
+// Smooth (separation-of-variables) LCP of every cell of a dense grid; wb: ns x 2^D + 1 doubles;
+// t.work / t.wcount: a work list of >= cells entries and its counter (binary32 path).
 hipError_t launch_cells_sov(const CellTask& t, double* wb, hipStream_t s);
 // Its adjoint for upstream gl (per cell): per-cell gradients gout (2^D + 2^D (2^D + 1) / 2
-// doubles each), then per vertex gmean, gvar and gcross (13 / 4 directions).
+// doubles each), then per vertex gmean, gvar and gcross (13 / 4 directions).  Same work list.
 hipError_t launch_cells_sov_grad(const CellTask& t, double* wb, const double* gl, double* gout, double* gmean,
                                  double* gvar, double* gcross, hipStream_t s);
 // Dense cells of nb tasks in one pass; every task's work/wcount/zmax must point to one
