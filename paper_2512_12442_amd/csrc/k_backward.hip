@@ -288,10 +288,17 @@ __global__ void k_bwd_finish(const double* __restrict__ b, int m, const double* 
     }
 }
 
-// Neighbour terms of the LCP adjoint over grid vertices (W, Z, U column-major, ldw):
-// z_p = sum_e c_p,e w_p+e + c_p-e,e w_p-e, U_p = h_p w_p + z_p / 2, and the direct term
-// sum_e c_p,e dk(x_p, x_p+e)/dlog(ell_d) (partials per work-group).  One work-group per
-// vertex chunk; threads over the observation index j.
+// Neighbour terms of the LCP adjoint over grid vertices (W, Z, U column-major, ld m_pad):
+// z_p = sum_e c_p,e w_p+e + c_p-e,e w_p-e, U_p = h_p w_p + z_p / 2, and (first j-block only)
+// the direct term sum_e c_p,e dk(x_p, x_p+e)/dlog(ell_d) (partials per work-group).
+// A work-group owns a 64 x 4 (x 1) vertex tile and JB observation rows: the tile's W block
+// with its one-vertex halo is staged in LDS once, so every W element is read from HBM about
+// (66 * 6 * 3) / 256 times instead of 27.  Thread = vertex.
+constexpr int kStX = 64, kStY = 4;
+__host__ __device__ inline int64_t stencil_tiles(const GridP& g)
+{
+    return ((g.n[0] + kStX - 1) / kStX) * ((g.n[1] + kStY - 1) / kStY) * (g.dim == 3 ? g.n[2] : 1);
+}
 template <class T, int D>
 __global__ void __launch_bounds__(256) k_bwd_stencil(KParams kp, GridP g, int mp, const T* __restrict__ W,
                                                      const double* __restrict__ gvar,
@@ -299,59 +306,75 @@ __global__ void __launch_bounds__(256) k_bwd_stencil(KParams kp, GridP g, int mp
                                                      T* __restrict__ U, double* __restrict__ dpart)
 {
     constexpr int NDIR = D == 3 ? 13 : 4;
+    constexpr int JB = 64 / (int)sizeof(T);          // observation rows per block (LDS <= 76 KB)
+    constexpr int HX = kStX + 2, HY = kStY + 2, HZ = D == 3 ? 3 : 1;
+    constexpr int NCOL = HX * HY * HZ;
+    __shared__ T tile[NCOL * JB];
     __shared__ double red[4];
-    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
-    const int64_t nchunks = (nv + kBwdChunk - 1) / kBwdChunk;
+    const int tid = threadIdx.x;
+    const int64_t xch = (g.n[0] + kStX - 1) / kStX, ych = (g.n[1] + kStY - 1) / kStY;
+    const int64_t tl = blockIdx.x;
+    const int64_t x0 = (tl % xch) * kStX, y0 = ((tl / xch) % ych) * kStY, z0 = D == 3 ? tl / (xch * ych) : 0;
+    const int j0 = blockIdx.y * JB;
+    // stage W[q][j0 .. j0 + JB) for the tile and its halo (zero outside the grid)
+    for (int e = tid; e < NCOL * JB; e += 256) {
+        const int c = e / JB, jj = e % JB;
+        const int hx = c % HX, hy = (c / HX) % HY, hz = c / (HX * HY);
+        const int64_t x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + (D == 3 ? hz - 1 : 0);
+        T v = T(0);
+        if (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2] && j0 + jj < mp)
+            v = W[(size_t)(x + g.n[0] * (y + g.n[1] * z)) * mp + j0 + jj];
+        tile[e] = v;
+    }
+    __syncthreads();
+    const int tx = tid % kStX, ty = tid / kStX;
+    const int64_t x = x0 + tx, y = y0 + ty, z = z0;
+    const bool live = x < g.n[0] && y < g.n[1];
     double dacc[3] = {0.0, 0.0, 0.0};
-    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const int64_t p1 = (c + 1) * kBwdChunk < nv ? (c + 1) * kBwdChunk : nv;
-        for (int64_t p = c * kBwdChunk; p < p1; ++p) {
-            const int64_t x[3] = {p % g.n[0], (p / g.n[0]) % g.n[1], p / (g.n[0] * g.n[1])};
-            int64_t nb[2 * NDIR];
-            double cf[2 * NDIR];
-            for (int e = 0; e < NDIR; ++e) {
-                int off[3];
-                if (D == 3) { off[0] = (e + 14) % 3 - 1; off[1] = ((e + 14) / 3) % 3 - 1; off[2] = (e + 14) / 9 - 1; }
-                else { off[0] = (e + 5) % 3 - 1; off[1] = (e + 5) / 3 - 1; off[2] = 0; }
-                bool fw = true, bw = true;
-                int64_t qf = 0, qb = 0, sf = 1;
-                for (int d = 0; d < 3; ++d) {
-                    const int64_t a = x[d] + off[d], b = x[d] - off[d];
-                    fw = fw && a >= 0 && a < g.n[d];
-                    bw = bw && b >= 0 && b < g.n[d];
-                    qf += a * sf;
-                    qb += b * sf;
-                    sf *= g.n[d];
-                }
-                nb[e] = fw ? qf : -1;
-                cf[e] = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
-                nb[NDIR + e] = bw ? qb : -1;
-                cf[NDIR + e] = bw ? gcross[(size_t)qb * NDIR + e] : 0.0;
-                if (fw && threadIdx.x == 0 && cf[e] != 0.0) {
-                    double t[3];
-                    for (int d = 0; d < 3; ++d) t[d] = (off[d] == 0 || d >= D) ? 0.0
-                        : (vertex_coord(g, d, x[d] + off[d]) - vertex_coord(g, d, x[d])) * kp.inv_ell[d];
-                    const double r2 = fma(t[2], t[2], fma(t[1], t[1], t[0] * t[0]));
-                    double kv, f;
-                    kernel_val_dfac(kp, r2, &kv, &f);
-                    for (int d = 0; d < 3; ++d) dacc[d] = fma(-f * cf[e], t[d] * t[d], dacc[d]);
-                }
-            }
-            const double hp = gvar[p];
-            for (int j = threadIdx.x; j < mp; j += 256) {
-                double z = 0.0;
-                for (int e = 0; e < 2 * NDIR; ++e)
-                    if (nb[e] >= 0) z = fma(cf[e], (double)W[(size_t)nb[e] * mp + j], z);
-                const double w = (double)W[(size_t)p * mp + j];
-                Z[(size_t)p * mp + j] = (T)z;
-                U[(size_t)p * mp + j] = (T)fma(hp, w, 0.5 * z);
+    if (live) {
+        const int64_t p = x + g.n[0] * (y + g.n[1] * z);
+        double cf[2 * NDIR];
+        int col[2 * NDIR];
+        for (int e = 0; e < NDIR; ++e) {
+            int off[3];
+            if (D == 3) { off[0] = (e + 14) % 3 - 1; off[1] = ((e + 14) / 3) % 3 - 1; off[2] = (e + 14) / 9 - 1; }
+            else { off[0] = (e + 5) % 3 - 1; off[1] = (e + 5) / 3 - 1; off[2] = 0; }
+            const int64_t a[3] = {x + off[0], y + off[1], z + off[2]};
+            const int64_t b[3] = {x - off[0], y - off[1], z - off[2]};
+            const bool fw = a[0] >= 0 && a[0] < g.n[0] && a[1] >= 0 && a[1] < g.n[1] && a[2] >= 0 && a[2] < g.n[2];
+            const bool bw = b[0] >= 0 && b[0] < g.n[0] && b[1] >= 0 && b[1] < g.n[1] && b[2] >= 0 && b[2] < g.n[2];
+            cf[e] = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
+            cf[NDIR + e] = bw ? gcross[(size_t)(b[0] + g.n[0] * (b[1] + g.n[1] * b[2])) * NDIR + e] : 0.0;
+            col[e] = ((D == 3 ? off[2] + 1 : 0) * HY + ty + 1 + off[1]) * HX + tx + 1 + off[0];
+            col[NDIR + e] = ((D == 3 ? 1 - off[2] : 0) * HY + ty + 1 - off[1]) * HX + tx + 1 - off[0];
+            if (blockIdx.y == 0 && fw && cf[e] != 0.0) {
+                double t[3];
+                for (int d = 0; d < 3; ++d)
+                    t[d] = (off[d] == 0 || d >= D) ? 0.0
+                         : (vertex_coord(g, d, a[d]) - vertex_coord(g, d, d == 0 ? x : (d == 1 ? y : z))) * kp.inv_ell[d];
+                const double r2 = fma(t[2], t[2], fma(t[1], t[1], t[0] * t[0]));
+                double kv, f;
+                kernel_val_dfac(kp, r2, &kv, &f);
+                for (int d = 0; d < 3; ++d) dacc[d] = fma(-f * cf[e], t[d] * t[d], dacc[d]);
             }
         }
-    }
+        const double hp = gvar[p];
+        const int cself = ((D == 3 ? 1 : 0) * HY + ty + 1) * HX + tx + 1;
+        for (int jj = 0; jj < JB && j0 + jj < mp; ++jj) {
+            double zz = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double sres = block_sum256(dacc[d], red);
-        if (threadIdx.x == 0) dpart[(size_t)blockIdx.x * 4 + d] = sres;
+            for (int e = 0; e < 2 * NDIR; ++e) zz = fma(cf[e], (double)tile[col[e] * JB + jj], zz);
+            const double w = (double)tile[cself * JB + jj];
+            Z[(size_t)p * mp + j0 + jj] = (T)zz;
+            U[(size_t)p * mp + j0 + jj] = (T)fma(hp, w, 0.5 * zz);
+        }
+    }
+    if (blockIdx.y == 0) {                          // uniform per work-group
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double sres = block_sum256(dacc[d], red);
+            if (tid == 0) dpart[(size_t)blockIdx.x * 4 + d] = sres;
+        }
     }
 }
 
@@ -364,7 +387,7 @@ struct BwdLayout {
 
 // lcp: also the forward moments, the cell and vertex gradients and the neighbour terms of
 // a dense grid with n vertices, ncell cells and ns samples.
-BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64_t ncell, int ns)
+BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64_t ncell, int ns, int64_t ntiles)
 {
     BwdLayout L{};
     const size_t mp = (size_t)M.m_pad;
@@ -397,7 +420,7 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64
         L.gcross = take(8 * (size_t)ndir * nn);
         L.z = take(es * mp * nn);
         L.u = take(es * mp * nn);
-        L.dpart = take(8 * 4 * kBwdGridP);
+        L.dpart = take(8 * 4 * (size_t)(ntiles > 0 ? ntiles : 1));
         L.work = take(4 * (size_t)(ncell > 0 ? ncell : 1) + 256);
     }
     L.total = o;
@@ -497,13 +520,13 @@ hipError_t bwd_tail(const Model& M, const BwdLayout& L, const BwdPts& P, int pre
 
 size_t posterior_backward_ws(const Model& M, int64_t n, int prec)
 {
-    return bwd_layout(M, n, prec, false, M.dim, 0, 0).total;
+    return bwd_layout(M, n, prec, false, M.dim, 0, 0, 0).total;
 }
 
 hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq, int prec, const double* gm,
                                      const double* gv, double* dy, double* dlogell, char* ws, hipStream_t s)
 {
-    const BwdLayout L = bwd_layout(M, n, prec, false, M.dim, 0, 0);
+    const BwdLayout L = bwd_layout(M, n, prec, false, M.dim, 0, 0, 0);
     BwdPts P{};
     P.P = Xq;
     P.dim = M.dim;
@@ -516,14 +539,14 @@ hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq
 size_t lcp_backward_ws(const Model& M, const GridP& g, int prec, int ns)
 {
     const int64_t nv = g.n[0] * g.n[1] * g.n[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
-    return bwd_layout(M, nv, prec, true, g.dim, nc, ns).total;
+    return bwd_layout(M, nv, prec, true, g.dim, nc, ns, stencil_tiles(g)).total;
 }
 
 hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int ns, const double* zb, int prec,
                                const double* gl, double* dy, double* dlogell, char* ws, hipStream_t s)
 {
     const int64_t nv = g.n[0] * g.n[1] * g.n[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
-    const BwdLayout L = bwd_layout(M, nv, prec, true, g.dim, nc, ns);
+    const BwdLayout L = bwd_layout(M, nv, prec, true, g.dim, nc, ns, stencil_tiles(g));
     // forward moments: mean, variance, V (quad-major) and the neighbour cross-covariances
     PostTask t{};
     t.mode = COL_GRID;
@@ -568,29 +591,32 @@ hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int
     {
         StageScope sc(s, ST_MISC);
         const int mp = M.m_pad;
+        const unsigned nt = (unsigned)stencil_tiles(g);
         if (prec == LCP_FP64) {
+            const dim3 grd(nt, (unsigned)(mp / 8));
             if (g.dim == 3)
-                hipLaunchKernelGGL((k_bwd_stencil<double, 3>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                hipLaunchKernelGGL((k_bwd_stencil<double, 3>), grd, dim3(256), 0, s, M.kp, g, mp,
                                    (const double*)(ws + L.w), gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u),
                                    dpart);
             else
-                hipLaunchKernelGGL((k_bwd_stencil<double, 2>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                hipLaunchKernelGGL((k_bwd_stencil<double, 2>), grd, dim3(256), 0, s, M.kp, g, mp,
                                    (const double*)(ws + L.w), gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u),
                                    dpart);
         } else {
+            const dim3 grd(nt, (unsigned)(mp / 16));
             if (g.dim == 3)
-                hipLaunchKernelGGL((k_bwd_stencil<float, 3>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                hipLaunchKernelGGL((k_bwd_stencil<float, 3>), grd, dim3(256), 0, s, M.kp, g, mp,
                                    (const float*)(ws + L.w), gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u),
                                    dpart);
             else
-                hipLaunchKernelGGL((k_bwd_stencil<float, 2>), dim3(kBwdGridP), dim3(256), 0, s, M.kp, g, mp,
+                hipLaunchKernelGGL((k_bwd_stencil<float, 2>), grd, dim3(256), 0, s, M.kp, g, mp,
                                    (const float*)(ws + L.w), gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u),
                                    dpart);
         }
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return bwd_tail(M, L, P, prec, gmean, gvar, ws + L.z, ws + L.u, dpart, kBwdGridP, dy, dlogell, ws, s);
+    return bwd_tail(M, L, P, prec, gmean, gvar, ws + L.z, ws + L.u, dpart, stencil_tiles(g), dy, dlogell, ws, s);
 }
 
 }  // namespace lcp

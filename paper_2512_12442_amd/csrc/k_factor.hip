@@ -88,11 +88,6 @@ __device__ __forceinline__ void cholesky_body(double* __restrict__ U, int m, int
     }
 }
 
-__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ U, int m, int mp, double piv_min,
-                                                   int* __restrict__ info)
-{
-    cholesky_body(U, m, mp, piv_min, info);
-}
 
 // Explicit inverse of L = U^T row by row: Linv[i][c] = -(sum_{k=c}^{i-1} L[i][k] Linv[k][c]) / L[i][i].
 __device__ __forceinline__ void amax_body(const double* __restrict__ Li, int mp, double* __restrict__ amax);
@@ -142,11 +137,6 @@ __device__ __forceinline__ void amax_body(const double* __restrict__ Li, int mp,
     }
 }
 
-__global__ void __launch_bounds__(1024) k_trinv(const double* __restrict__ U, double* __restrict__ Li, int m,
-                                                int mp, double* __restrict__ amax)
-{
-    trinv_body(U, Li, m, mp, amax);
-}
 
 __global__ void __launch_bounds__(1024) k_amax(const double* __restrict__ Li, int mp, double* __restrict__ amax)
 {
@@ -177,6 +167,197 @@ __global__ void __launch_bounds__(1024) k_alpha(const double* __restrict__ Li, c
                                                 double* __restrict__ a, int m, int mp)
 {
     alpha_body(Li, y, a, m, mp);
+}
+
+// ----------------------------------------------------- blocked factorisation (one model)
+//
+// Right-looking Cholesky in 64 x 64 blocks over the upper triangle (U = L^T, row-major),
+// then the blocked inverse of L: the diagonal blocks first, then each block diagonal d from
+// the previous ones, Linv_ij = -Linv_ii sum_{k=j}^{i-1} L_ik Linv_kj.  Every block product
+// is one work-group of 256 threads with both operands in LDS (4 x 4 outputs per thread).
+// Columns >= m (padding) are skipped and left zero.
+constexpr int kFB = 64;
+
+// acc[r][c] += sum_k a(ty*4+r, k) * b(k, tx*4+c) over a 64 x 64 block in LDS.
+__device__ __forceinline__ void blk_mma(const double (*a)[kFB + 1], const double (*b)[kFB + 1], double (&acc)[4][4],
+                                        bool transpose_a)
+{
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll 4
+    for (int k = 0; k < kFB; ++k) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[r] = transpose_a ? a[k][ty * 4 + r] : a[ty * 4 + r][k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = b[k][tx * 4 + c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+    }
+}
+
+__device__ __forceinline__ void blk_load(double (*dst)[kFB + 1], const double* __restrict__ src, int mp, int r0, int c0)
+{
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256) {
+        const int r = t / kFB, c = t % kFB;
+        dst[r][c] = src[(int64_t)(r0 + r) * mp + c0 + c];
+    }
+}
+
+// Invert the lower-triangular block lo (in LDS) into inv (in LDS): column by column,
+// inv[i][c] = -(sum_{k=c}^{i-1} lo[i][k] inv[k][c]) / lo[i][i]; rows with lo[i][i] = 0
+// (padding) stay zero.
+__device__ __forceinline__ void blk_trinv(const double (*lo)[kFB + 1], double (*inv)[kFB + 1])
+{
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256) inv[t / kFB][t % kFB] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < kFB; ++i) {
+        const double lii = lo[i][i];
+        for (int c = threadIdx.x; c <= i; c += 256) {
+            if (!(lii > 0.0)) continue;
+            if (c == i) {
+                inv[i][i] = 1.0 / lii;
+            } else {
+                double sum = 0.0;
+                for (int k = c; k < i; ++k) sum = fma(lo[i][k], inv[k][c], sum);
+                inv[i][c] = -sum / lii;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Step k, diagonal block: factor A_kk (upper, in U) in LDS, write U_kk and Linv_kk.
+__global__ void __launch_bounds__(256) k_chol_diag(double* __restrict__ U, int m, int mp, int kb, double piv_min,
+                                                   int* __restrict__ info, double* __restrict__ Lkk_inv)
+{
+    __shared__ double a[kFB][kFB + 1], lo[kFB][kFB + 1];
+    const int k0 = kb * kFB;
+    if (kb == 0 && threadIdx.x == 0) *info = 0;
+    blk_load(a, U, mp, k0, k0);
+    __syncthreads();
+    for (int c = 0; c < kFB; ++c) {
+        const bool real = k0 + c < m;
+        double d = a[c][c];
+        if (real && !(d > piv_min) && threadIdx.x == 0 && *info == 0) *info = k0 + c + 1;
+        const double ucc = real && d > 0.0 ? sqrt(d) : 0.0;
+        const double inv = ucc > 0.0 ? 1.0 / ucc : 0.0;
+        __syncthreads();
+        // row c of U_kk, then the trailing update of the block
+        for (int j = c + 1 + threadIdx.x; j < kFB; j += 256) a[c][j] *= inv;
+        __syncthreads();
+        for (int t = threadIdx.x; t < kFB * kFB; t += 256) {
+            const int i = t / kFB, j = t % kFB;
+            if (i > c && j >= i) a[i][j] = fma(-a[c][i], a[c][j], a[i][j]);
+        }
+        if (threadIdx.x == 0) a[c][c] = ucc;
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256) {
+        const int i = t / kFB, j = t % kFB;
+        const double u = j >= i ? a[i][j] : 0.0;
+        U[(int64_t)(k0 + i) * mp + k0 + j] = u;
+        lo[j][i] = u;                                   // L_kk = U_kk^T
+    }
+    __syncthreads();
+    blk_trinv(lo, a);
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256) Lkk_inv[t] = a[t / kFB][t % kFB];
+}
+
+// Step k, panel: U_kj = Linv_kk A_kj for every block column j > k.
+__global__ void __launch_bounds__(256) k_chol_panel(double* __restrict__ U, int mp, int kb,
+                                                    const double* __restrict__ Lkk_inv)
+{
+    __shared__ double li[kFB][kFB + 1], b[kFB][kFB + 1];
+    const int jb = kb + 1 + blockIdx.x;
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256) li[t / kFB][t % kFB] = Lkk_inv[t];
+    blk_load(b, U, mp, kb * kFB, jb * kFB);
+    __syncthreads();
+    double acc[4][4] = {};
+    blk_mma(li, b, acc, false);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) U[(int64_t)(kb * kFB + ty * 4 + r) * mp + jb * kFB + tx * 4 + c] = acc[r][c];
+}
+
+// Step k, trailing update of the upper blocks: A_ij -= U_ki^T U_kj, k < i <= j.
+__global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ U, int mp, int kb, int nblk)
+{
+    __shared__ double a[kFB][kFB + 1], b[kFB][kFB + 1];
+    const int T = nblk - kb - 1;
+    int rem = blockIdx.x, ii = 0;
+    while (rem >= T - ii) { rem -= T - ii; ++ii; }
+    const int ib = kb + 1 + ii, jb = ib + rem;
+    blk_load(a, U, mp, kb * kFB, ib * kFB);
+    blk_load(b, U, mp, kb * kFB, jb * kFB);
+    __syncthreads();
+    double acc[4][4] = {};
+    blk_mma(a, b, acc, true);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double* p = U + (int64_t)(ib * kFB + ty * 4 + r) * mp + jb * kFB + tx * 4 + c;
+            *p -= acc[r][c];
+        }
+}
+
+// Clear the strictly lower part of U (it still holds K) and of the padding.
+__global__ void k_clear_lower(double* __restrict__ U, int mp)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    if (t % mp < t / mp) U[t] = 0.0;
+}
+
+// Inverse, diagonal blocks: Linv_ii = L_ii^-1 with L_ii = U_ii^T.
+__global__ void __launch_bounds__(256) k_trinv_diag(const double* __restrict__ U, double* __restrict__ Li, int mp)
+{
+    __shared__ double lo[kFB][kFB + 1], inv[kFB][kFB + 1];
+    const int i0 = blockIdx.x * kFB;
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256) {
+        const int r = t / kFB, c = t % kFB;
+        lo[c][r] = U[(int64_t)(i0 + r) * mp + i0 + c];
+    }
+    __syncthreads();
+    blk_trinv(lo, inv);
+    for (int t = threadIdx.x; t < kFB * kFB; t += 256)
+        Li[(int64_t)(i0 + t / kFB) * mp + i0 + t % kFB] = inv[t / kFB][t % kFB];
+}
+
+// Inverse, block diagonal d: Linv_ij = -Linv_ii sum_{k=j}^{i-1} L_ik Linv_kj, i = j + d.
+__global__ void __launch_bounds__(256) k_trinv_off(const double* __restrict__ U, double* __restrict__ Li, int mp,
+                                                   int d)
+{
+    __shared__ double a[kFB][kFB + 1], b[kFB][kFB + 1];
+    const int jb = blockIdx.x, ib = jb + d;
+    double acc[4][4] = {};
+    for (int kb = jb; kb < ib; ++kb) {
+        // a = L_ik = (U_ki)^T: load U_ki and use it transposed
+        blk_load(a, U, mp, kb * kFB, ib * kFB);
+        blk_load(b, Li, mp, kb * kFB, jb * kFB);
+        __syncthreads();
+        blk_mma(a, b, acc, true);
+        __syncthreads();
+    }
+    // b = the sum, a = Linv_ii; Linv_ij = -a b
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[ty * 4 + r][tx * 4 + c] = acc[r][c];
+    blk_load(a, Li, mp, ib * kFB, ib * kFB);
+    __syncthreads();
+    double out[4][4] = {};
+    blk_mma(a, b, out, false);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Li[(int64_t)(ib * kFB + ty * 4 + r) * mp + jb * kFB + tx * 4 + c] = -out[r][c];
 }
 
 // One work-group per model of a batch.
@@ -334,6 +515,36 @@ __global__ void k_obs_sparse(const double* __restrict__ mu, const double* __rest
     obs_var[i] = fmax(A[(int64_t)i * m + i], 0.0);
 }
 
+// Cholesky of the leading m x m block of A (row-major, ld mp): on exit the upper triangle of
+// A holds U = L^T and the lower part is zero; info (device) = first failing column + 1 or 0.
+// scratch: 64 x 64 doubles.
+static void launch_chol_blocked(double* A, int m, int mp, double piv_min, int* info, double* scratch, hipStream_t s)
+{
+    const int nblk = mp / kFB;
+    for (int kb = 0; kb < nblk; ++kb) {
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, m, mp, kb, piv_min, info, scratch);
+        const int T = nblk - kb - 1;
+        if (T == 0) break;
+        hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)T), dim3(256), 0, s, A, mp, kb, (const double*)scratch);
+        hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, A, mp, kb, nblk);
+    }
+    const int64_t n2 = (int64_t)mp * mp;
+    hipLaunchKernelGGL(k_clear_lower, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, A, mp);
+}
+
+// Li = (U^T)^-1 (lower, zero above the diagonal) and its scale (amax).
+static hipError_t launch_trinv_blocked(const double* U, double* Li, int mp, double* amax, hipStream_t s)
+{
+    const int nblk = mp / kFB;
+    hipError_t e = launch_fill_f64(Li, 0.0, (int64_t)mp * mp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trinv_diag, dim3((unsigned)nblk), dim3(256), 0, s, U, Li, mp);
+    for (int d = 1; d < nblk; ++d)
+        hipLaunchKernelGGL(k_trinv_off, dim3((unsigned)(nblk - d)), dim3(256), 0, s, U, Li, mp, d);
+    hipLaunchKernelGGL(k_amax, dim3(1), dim3(1024), 0, s, (const double*)Li, mp, amax);
+    return hipGetLastError();
+}
+
 static void carve(Model& M, char* base)
 {
     int mp = M.m_pad;
@@ -373,7 +584,7 @@ hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t
     hipLaunchKernelGGL(k_build_K, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.kp, M.X, M.m, mp,
                        M.k.noise_var, M.U);
     double piv_min = (double)M.m * 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var);
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, M.U, M.m, mp, piv_min, M.info);
+    launch_chol_blocked(M.U, M.m, mp, piv_min, M.info, (double*)M.A32, s);
     return hipGetLastError();
 }
 
@@ -383,7 +594,8 @@ hipError_t launch_factor_finish(Model& M, hipStream_t s)
     StageScope sc(s, ST_FACTOR);
     int mp = M.m_pad;
     int64_t n2 = (int64_t)mp * mp;
-    hipLaunchKernelGGL(k_trinv, dim3(1), dim3(1024), 0, s, M.U, M.Linv, M.m, mp, M.amax);
+    hipError_t e0 = launch_trinv_blocked(M.U, M.Linv, mp, M.amax, s);
+    if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, s, M.Linv, ybuf(M), M.a, M.m, mp);
     hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, mp, M.A64, M.A32,
                        M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
@@ -411,7 +623,8 @@ hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, 
     const int64_t n2 = (int64_t)mp * mp;
     const dim3 tiles((unsigned)(mp / 16), (unsigned)(mp / 16));
     if (first) {
-        hipLaunchKernelGGL(k_trinv, dim3(1), dim3(1024), 0, s, M.U, M.Linv, m, mp, M.amax);
+        hipError_t e0 = launch_trinv_blocked(M.U, M.Linv, mp, M.amax, s);
+        if (e0 != hipSuccess) return e0;
         hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, s, M.Linv, ybuf(M), M.a, m, mp);
         hipLaunchKernelGGL(k_obs_sparse, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, ybuf(M), A, m,
                            M.obs_mu, M.obs_var);
@@ -424,7 +637,7 @@ hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, 
     hipLaunchKernelGGL((k_gemm64<RowMajor, Transposed, StoreReversedE>), tiles, dim3(256), 0, s, mp,
                        RowMajor{M.U, mp}, Transposed{M.Linv, mp}, StoreReversedE{M.A64, mp, m, delta});
     const double piv_min = (double)m * 2.220446049250313e-16;
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, M.A64, m, mp, piv_min, M.info + 1);
+    launch_chol_blocked(M.A64, m, mp, piv_min, M.info + 1, (double*)M.A32, s);
     return hipGetLastError();
 }
 
