@@ -5,8 +5,8 @@
  * Probability Calculation for Gaussian Process Modeled Data" (arXiv 2512.12442):
  * the GP posterior at grid vertices (Sec. 3, eq. (sgp) in its exact-GP form), the
  * per-cell level-crossing probability by Monte Carlo (Sec. 4), and the regional
- * upper bound of eq. (upper_bound) driving the octree query of Alg. 1 (Sec. 4.1,
- * 4.3), with reconstruction only inside the emitted nodes (end of Sec. 4.3).
+ * upper bound of eq. (upper_bound) driving the octree query of Alg. 1 (Sec. 5.1,
+ * 4.3), with reconstruction only inside the emitted nodes (end of Sec. 5.3).
  *
  * Conventions
  *  - Every pointer argument is a DEVICE pointer unless its comment says "host".
@@ -72,7 +72,7 @@ typedef struct {
 } lcp_grid;
 
 typedef struct {
-    double alpha;            /* skip threshold of Alg. 1, 0 < alpha < 0.5 (the paper uses 1e-3, Sec. 6.3) */
+    double alpha;            /* skip threshold of Alg. 1, 0 < alpha < 0.5 (the paper uses 1e-3, Sec. 7.3) */
     int min_leaf_cells;      /* finest node edge in cells, a power of two >= 1 (max depth of Alg. 1);
                                 the octree may have at most 8 levels (root edge / min_leaf_cells <= 128) */
     int bound_at_max_depth;  /* 1: region test at the finest level too (Alg. 1 as printed); 0: emit */
@@ -89,7 +89,7 @@ typedef enum {
 } lcp_estimator;
 
 typedef struct {
-    int n_samples;           /* N_s >= 1 (the paper uses 1600, Sec. 5.4) */
+    int n_samples;           /* N_s >= 1 (the paper uses 1600, Sec. 6.4) */
     const double* zbank;     /* n_samples x 2^dim standard normals, shared by every cell (device) */
     int estimator;           /* lcp_estimator (0 = the paper's counting estimate) */
 } lcp_mc;
@@ -129,7 +129,7 @@ int gp_fit_factor(const lcp_kernel* k, int m, const double* X, const double* y, 
  * Gaussian N(mu_M, A_M) of the inducing values stored after SGPR fitting (Sec. 3).  The
  * posterior at a set I is then mu = K_IM K_MM^-1 mu_M and
  * Sigma = K_II - K_IM K_MM^-1 K_MI + K_IM K_MM^-1 A_M K_MM^-1 K_MI, and the preliminary
- * node test of Alg. 1 reads the marginals N(mu_M_i, A_M_ii) (Sec. 4.3).
+ * node test of Alg. 1 reads the marginals N(mu_M_i, A_M_ii) (Sec. 5.3).
  *   k        (host) kernel; k->noise_var is the jitter added to the diagonal of K_MM
  *   m        number of inducing points, 1 <= m <= 1024
  *   Z        m x dim inducing locations (device, binary64)
@@ -180,7 +180,7 @@ int lcp_dense(const lcp_model* model, const lcp_grid* grid, double theta, const 
 
 /*
  * lcp_adaptive -- Alg. 1 (octree adaptive query) on the full model followed by the
- * reconstruction of Sec. 4.3's last paragraph: cells inside the emitted nodes get the
+ * reconstruction of Sec. 5.3's last paragraph: cells inside the emitted nodes get the
  * same Monte Carlo LCP as lcp_dense (same precision, same z-bank); all other cells get 0.
  * The region test (preliminary decision on the observations inside the closed node box,
  * then the bound 1 - B^d of eq. (upper_bound) with B from a bounded search of F_M) runs
@@ -199,7 +199,7 @@ int lcp_adaptive(const lcp_model* model, const lcp_grid* grid, double theta, con
 
 /*
  * Batches of independent models (local GP models of subdomains, each with its own
- * observations, kernel and grid, as the local models M' of Sec. 4.1 generalise): every
+ * observations, kernel and grid, as the local models M' of Sec. 5.1 generalise): every
  * model's Cholesky factor runs in one launch (a work-group each), and the posterior GEMMs
  * of all models run in one launch that walks the batch's tiles, so small models share the
  * GPU with large ones.

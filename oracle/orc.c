@@ -16,11 +16,11 @@
  *    so mu(x) = k*^T (K + s_n^2 I)^-1 y and var(x) = k(x,x) - ||L^-1 k*||^2, latent f;
  *    or the general eq. (sgp) with stored mu_M and A_M, K_MM taking the model's noise
  *    term as a diagonal jitter.  The preliminary node test of Alg. 1 then reads the
- *    inducing marginals N(mu_M_i, A_M_ii) directly (Sec. 4.3).
- *  - F_M uses the standard deviation, not the variance (Sec. 4.1 prints Sigma).
+ *    inducing marginals N(mu_M_i, A_M_ii) directly (Sec. 5.3).
+ *  - F_M uses the standard deviation, not the variance (Sec. 5.1 prints Sigma).
  *  - Cell covariance is factored with a semidefinite Cholesky (tolerance 1e-12 of the
  *    largest diagonal entry); a sample equal to the iso-value counts as crossed.
- *  - The L-BFGS-B search of Sec. 4.1 is replaced by a fixed-budget bounded search:
+ *  - The L-BFGS-B search of Sec. 5.1 is replaced by a fixed-budget bounded search:
  *    a {lo,mid,hi}^D lattice followed by T normalised projected-gradient steps.
  *  - Alg. 1 is run on the full model F_M (no local model M'); p = alpha counts as
  *    "not larger than alpha"; a node without observations takes its side from the
@@ -896,7 +896,7 @@ int orc_cell_moments(const orc_model* M, const orc_grid* G, const int64_t* cell,
 /* ------------------------------------------------------- region bound -- */
 
 /* Standardised margin g = side (theta - mu) / sigma; its minimum over a region gives
- * B = Phi(g_min) = min F_M (side +1) or min (1 - F_M) (side -1), Sec. 4.1. */
+ * B = Phi(g_min) = min F_M (side +1) or min (1 - F_M) (side -1), Sec. 5.1. */
 static double margin(double side, double theta, double mu, double var)
 {
     double num = side * (theta - mu);
@@ -1189,7 +1189,7 @@ int orc_adaptive(const orc_model* M, const orc_grid* G, double theta, const orc_
     double* var = (double*)malloc(sizeof(double) * (size_t)m);
     if (!qlo || !qhi || !mu || !var) { free(qlo); free(qhi); free(mu); free(var); return ORC_ENOMEM; }
     if (M->A) {
-        /* Sec. 4.3: the inducing values are N(mu_M, A_M); their marginals are stored */
+        /* Sec. 5.3: the inducing values are N(mu_M, A_M); their marginals are stored */
         for (int i = 0; i < m; ++i) {
             mu[i] = M->muM[i];
             var[i] = M->A[(int64_t)i * m + i] > 0.0 ? M->A[(int64_t)i * m + i] : 0.0;

@@ -2,7 +2,7 @@
 
 The hot path of Li, Michaud, Biswas, Shen (arXiv 2512.12442): GP posterior at grid
 vertices (Sec. 3), per-cell Monte Carlo level-crossing probability (Sec. 4), and the
-regional upper bound driving the octree query of Alg. 1 (Sec. 4.1-4.3).  The compute
+regional upper bound driving the octree query of Alg. 1 (Sec. 5.1-4.3).  The compute
 runs in the HIP library liblcp.so (C ABI in include/lcp.h); this package only marshals
 arguments.
 """

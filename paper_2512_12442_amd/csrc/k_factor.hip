@@ -505,7 +505,7 @@ __global__ void k_pack_square(const double* __restrict__ A, int m, int mp, doubl
     dst[t] = (i < m && j < m) ? A[(int64_t)i * m + j] : 0.0;
 }
 
-// Sec. 4.3 with stored inducing values: the node test reads N(mu_M_i, A_M_ii).
+// Sec. 5.3 with stored inducing values: the node test reads N(mu_M_i, A_M_ii).
 __global__ void k_obs_sparse(const double* __restrict__ mu, const double* __restrict__ A, int m,
                              double* __restrict__ obs_mu, double* __restrict__ obs_var)
 {

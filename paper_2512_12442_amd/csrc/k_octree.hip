@@ -1,5 +1,5 @@
 // Octree adaptive query (Alg. 1) run level-synchronously on the GPU, followed by the
-// reconstruction of the emitted nodes only (Sec. 4.3, last paragraph).
+// reconstruction of the emitted nodes only (Sec. 5.3, last paragraph).
 //
 // Per level: a wave per frontier node tests the observations inside the closed node box
 // (p1, p2 of Alg. 1); nodes that need the region bound are compacted by a prefix sum and
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
     }
 }
 
-// Region bound of Sec. 4.1 in three stages with the decision of the full search:
+// Region bound of Sec. 5.1 in three stages with the decision of the full search:
 // UB = 1 - B^d is non-increasing in g_min and every evaluated point can only lower g_min,
 // so a node is subdivided as soon as one evaluated point gives UB > alpha.
 //   stage 1: the box centre (also the side for nodes without observations);
@@ -923,7 +923,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                            level_field);
     }
 
-    // ---- reconstruction of the emitted nodes (Sec. 4.3, last paragraph)
+    // ---- reconstruction of the emitted nodes (Sec. 5.3, last paragraph)
     const int leaf_edge = (int)(S0 >> Lmax);
     int32_t* vmask = (int32_t*)P(L.o_vmask);
     int32_t* voff = (int32_t*)P(L.o_voff);

@@ -169,7 +169,7 @@ def test_adaptive_fp64_matches_oracle(case):
 
 @pytest.mark.parametrize("prec", ["fp64", "f16x3", "bf16x3"])
 def test_adaptive_equals_dense_inside_leaves(prec):
-    """Sec. 4.3: cells inside emitted nodes get exactly the dense estimate (same precision,
+    """Sec. 5.3: cells inside emitted nodes get exactly the dense estimate (same precision,
     same z-bank); all other cells are zero."""
     W = ADAPT_CASES["trig33"]()
     G = gpu_model(W)

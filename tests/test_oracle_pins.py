@@ -288,7 +288,7 @@ def test_cell_lcp_matches_brute_force_joint_sampling(dim):
     assert (np.abs(lcp - freq) <= tol).all()
 
 
-# --------------------------------------------------------- region bound (Sec. 4.1)
+# --------------------------------------------------------- region bound (Sec. 5.1)
 
 def test_upper_bound_formula_and_stability():
     from decimal import Decimal, getcontext
@@ -305,7 +305,7 @@ def test_upper_bound_formula_and_stability():
 
 @pytest.mark.parametrize("kind", [workloads.SE, workloads.MATERN52])
 def test_bound_search_not_worse_than_any_grid_vertex(kind):
-    """The paper's failure mode (Sec. 8): a local search can miss the region's minimum,
+    """The paper's failure mode (Sec. 9): a local search can miss the region's minimum,
     so UB_method may fall below UB_discrete = 1 - (min over grid vertices of P)^d.
     Count the failures that change a decision at alpha = 1e-3 over 800 random boxes."""
     bad = total = 0

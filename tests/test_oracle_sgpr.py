@@ -129,7 +129,7 @@ def test_sgpr_generator_gives_a_valid_inducing_distribution():
 
 
 def test_sparse_adaptive_decisions_use_the_inducing_marginals():
-    """Sec. 4.3 on the sparse model: p1, p2 are the largest marginal probabilities of the
+    """Sec. 5.3 on the sparse model: p1, p2 are the largest marginal probabilities of the
     inducing values N(mu_M_i, A_M_ii) inside the node; leaves reproduce the dense field."""
     W = workloads.sgpr_field(42, m=27, npts=17, train_npts=12, signal_var=0.5, ell=0.3)
     W.min_leaf = 2

@@ -13,11 +13,11 @@ noisy synthetic training grid (Titsias' closed form).  That step is model traini
 not part of the method; the method's own arithmetic (eq. (sgp), the cell
 probability, the bound) stays out of this module.
 
-The paper evaluates on two datasets (Tangle, Ethanediol, Sec. 5.3) that are not
+The paper evaluates on two datasets (Tangle, Ethanediol, Sec. 6.3) that are not
 available here; the workloads below stand in for them at the paper's scale
-(m = 50 / 500 observations, 128^3 target grid, Sec. 5.3 and Sec. 6.1), with the
-Monte Carlo sample count of Sec. 5.4 (1600) and the threshold alpha = 1e-3 of
-Sec. 6.3.  Every random number the method consumes (the z-bank) is drawn here
+(m = 50 / 500 observations, 128^3 target grid, Sec. 6.3 and Sec. 7.1), with the
+Monte Carlo sample count of Sec. 6.4 (1600) and the threshold alpha = 1e-3 of
+Sec. 7.3.  Every random number the method consumes (the z-bank) is drawn here
 and passed in as an input.
 """
 from __future__ import annotations
@@ -197,7 +197,7 @@ def sgpr_field(seed: int, m: int = 500, npts: int = 128, train_npts: int = 32, n
                signal_var: float = 1e-3, ell: float = 0.12, noise_var: float = 1e-4, jitter: float = 1e-6,
                name: Optional[str] = None) -> Workload:
     """Sparse GP model of eq. (sgp) standing in for the paper's fitted SGPR models
-    (Sec. 5.3: 50 or 500 inducing points, RBF kernel, a training grid of the field).
+    (Sec. 6.3: 50 or 500 inducing points, RBF kernel, a training grid of the field).
 
     Inducing points: one in each of m cells drawn without replacement from a c^3
     lattice (c = ceil(m^(1/3))), uniform in the central half of its cell.  Training data:
