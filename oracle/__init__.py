@@ -31,7 +31,10 @@ class Grid(C.Structure):
 
 class Adapt(C.Structure):
     _fields_ = [("alpha", C.c_double), ("min_leaf", C.c_int), ("bound_at_max_depth", C.c_int),
-                ("steps", C.c_int)]
+                ("steps", C.c_int), ("bound_kind", C.c_int)]
+
+
+BOUND_SEARCH, BOUND_CERTIFIED = 0, 1
 
 
 class NodeRec(C.Structure):
@@ -78,6 +81,12 @@ def lib():
         _lib.orc_upper_bound.restype = C.c_double
         _lib.orc_upper_bound.argtypes = [C.c_double, C.c_int64]
         _lib.orc_bound.argtypes = [P, C.c_double, C.c_double, P, P, C.c_int, P, P]
+        _lib.orc_curv3_env.restype = C.c_double
+        _lib.orc_curv3_env.argtypes = [C.c_int, C.c_double]
+        _lib.orc_kernel_hess.argtypes = [C.c_int, C.c_int, C.c_double, P, P, P, P]
+        _lib.orc_bound_certified.argtypes = [P, P, P, P]
+        _lib.orc_certified_margin.restype = C.c_double
+        _lib.orc_certified_margin.argtypes = [C.c_double, C.c_double, P]
         _lib.orc_octree_shape.argtypes = [P, C.c_int, P, P]
         _lib.orc_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int64, P, P, C.c_int64, P, P,
                                       C.c_int64, P]
@@ -295,6 +304,31 @@ def bound(M: FitModel, theta, side, blo, bhi, steps=4):
     return gmin.value, gap.value
 
 
+def curv3_env(kind, r2):
+    """Sup over scaled distances >= sqrt(r2) of the largest third directional derivative of
+    the kernel along a unit scaled direction (unit signal variance)."""
+    return lib().orc_curv3_env(int(kind), float(r2))
+
+
+def kernel_hess(kind, dim, s2, ell, x, z):
+    ell = _f64(np.resize(np.asarray(ell, float), 3))
+    Hm = np.zeros(dim * dim)
+    lib().orc_kernel_hess(kind, dim, s2, _p(ell), _p(_f64(x)), _p(_f64(z)), _p(Hm))
+    return Hm.reshape(dim, dim)
+
+
+def bound_certified(M: FitModel, blo, bhi):
+    """Certified box bounds: (mu(centre), mu_lo, mu_hi, var_hi) over the box [blo, bhi]."""
+    out = np.zeros(4)
+    rc = lib().orc_bound_certified(C.byref(M.s), _p(_f64(blo)), _p(_f64(bhi)), _p(out))
+    assert rc == ORC_OK, rc
+    return out
+
+
+def certified_margin(side, theta, cb):
+    return lib().orc_certified_margin(float(side), float(theta), _p(_f64(cb)))
+
+
 def octree_shape(W, min_leaf=None):
     g = grid_of(W)
     S0, L = C.c_int64(), C.c_int()
@@ -302,11 +336,12 @@ def octree_shape(W, min_leaf=None):
     return S0.value, L.value
 
 
-def adaptive(M: FitModel, W, alpha=None, min_leaf=None, bound_at_max_depth=1, steps=4, cap=1 << 22):
+def adaptive(M: FitModel, W, alpha=None, min_leaf=None, bound_at_max_depth=1, steps=4, cap=1 << 22,
+             bound_kind=BOUND_SEARCH):
     """Alg. 1: returns (leaves, skipped, node records), each sorted by key."""
     g = grid_of(W)
     A = Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf),
-              int(bound_at_max_depth), int(steps))
+              int(bound_at_max_depth), int(steps), int(bound_kind))
     leaves = np.zeros(cap, np.uint64)
     skipped = np.zeros(cap, np.uint64)
     recs = np.zeros(cap, NODE_DTYPE)

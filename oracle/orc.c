@@ -25,6 +25,8 @@
  *  - Alg. 1 is run on the full model F_M (no local model M'); p = alpha counts as
  *    "not larger than alpha"; a node without observations takes its side from the
  *    sign of theta - mu(box centre).
+ *  - The certified variant of the region bound (guaranteed in exact arithmetic, which
+ *    Sec. 9 leaves open) bounds mu and var over the whole box instead of searching.
  */
 #include <math.h>
 #include <stdint.h>
@@ -67,6 +69,7 @@ typedef struct {
     int min_leaf;           /* finest node edge in cells (power of two) */
     int bound_at_max_depth; /* 1: Alg. 1 as printed (region test at every level) */
     int steps;              /* projected-gradient steps after the lattice */
+    int bound_kind;         /* 0: bounded search (lattice + steps), 1: certified box bounds */
 } orc_adapt;
 
 typedef struct {
@@ -1011,6 +1014,215 @@ int orc_bound(const orc_model* M, double theta, double side, const double* blo, 
     return ORC_OK;
 }
 
+/* ------------------------------------------ certified region bound -- */
+/*
+ * Box bounds of the posterior that hold for every point of the box, so that the bound of
+ * eq. (upper_bound) is guaranteed rather than found by a search (the search of Sec. 5.1 can
+ * miss the minimum; Sec. 9 leaves a guaranteed bound as future work).  They hold in exact
+ * arithmetic for the stored model; the binary64 rounding of the sums below is not bounded.
+ *
+ * Second-order Taylor model with the Lagrange remainder.  For the box with centre c and
+ * half-widths h, u = x - c, v = u / ell (scaled), |v|^2 <= H = sum_d (h_d / ell_d)^2, and r_i
+ * the scaled distance from x_i to the box: for any weights b, the function
+ * phi(x) = sum_i b_i k_i(x) satisfies
+ *   phi(x) = phi(c) + grad.u + u^T Hess u / 2 + R,  |R| <= s2 H^(3/2) sum_i |b_i| C3(r_i) / 6,
+ * where s2 C3(r) bounds the third directional derivative of k along a unit scaled direction
+ * at every scaled distance >= r (curv3_env); gradient and Hessian are taken at c, where
+ * the cancellations of the weights are exact.  Over the box the quadratic part lies within
+ * sum_d [min, max of grad_d u_d + Hess_dd u_d^2 / 2] -/+ sum_{d != e} |Hess_de| h_d h_e / 2.
+ *  - mean: phi = mu (b = a).
+ *  - variance: var(x) = s2 - q(k(x)) with q(k) = k^T Q k, Q = K^-1 (exact GP) or
+ *    K^-1 - K^-1 A_M K^-1 (sparse model; positive semidefinite when A_M <= K).  q is convex,
+ *    so with w = Q k(c):  q(k(x)) >= q(k(c)) + 2 w^T (k(x) - k(c)).  With nu(x) = w^T k(x)
+ *    (b = w) and q(k(c)) = nu(c):  var(x) <= s2 - nu(c) - 2 min_box (nu(x) - nu(c)),
+ *    clamped to [0, s2].
+ */
+
+/* Hessian of k(x, z) in x (dim x dim, row-major).  With t = (x - z) / ell, r = |t| and
+ * k = s2 f(r):  d2k / dx_d dx_e = s2 (g delta_de + gam t_d t_e) / (ell_d ell_e), where g = f'/r
+ * and gam = (f'/r)' / r:  SE: g = -e^(-r^2/2), gam = e^(-r^2/2);  Matern-5/2:
+ * g = -(5/3) (1 + sqrt5 r) e^(-sqrt5 r), gam = (25/3) e^(-sqrt5 r). */
+void orc_kernel_hess(int kind, int dim, double s2, const double* ell, const double* x, const double* z,
+                     double* Hm)
+{
+    double t[3], r2 = scaled_r2(dim, ell, x, z), g, gam;
+    for (int d = 0; d < dim; ++d) t[d] = (x[d] - z[d]) / ell[d];
+    if (kind == 0) {
+        double e = exp(-0.5 * r2);
+        g = -e;
+        gam = e;
+    } else {
+        double r = sqrt(r2), e = exp(-sqrt(5.0) * r);
+        g = -(5.0 / 3.0) * (1.0 + sqrt(5.0) * r) * e;
+        gam = (25.0 / 3.0) * e;
+    }
+    for (int d = 0; d < dim; ++d)
+        for (int f = 0; f < dim; ++f)
+            Hm[d * dim + f] = s2 * ((d == f ? g : 0.0) + gam * t[d] * t[f]) / (ell[d] * ell[f]);
+}
+
+/* kappa3(rho) = max over unit v of |D^3 f[v, v, v]| at scaled distance rho (s2 = 1).  With
+ * p = v . t / rho in [-1, 1]:  D^3 f = 3 g' p + rho^2 (g'/rho)' p^3 (g = f'/rho).
+ * SE: e^(-rho^2/2) (3 s - s^3), s = rho p: the maximum of |3 s - s^3| over |s| <= rho is
+ *   3 rho - rho^3 (rho <= 1), 2 (rho <= 2), rho^3 - 3 rho.
+ * Matern-5/2, t = sqrt5 rho: (5 sqrt5 / 3) e^-t (3 t p - t^2 p^3), whose maximum over p is
+ *   3 t - t^2 (t <= 1), 2 sqrt t (t <= 4), t^2 - 3 t. */
+static double kappa3(int kind, double rho)
+{
+    if (kind == 0) {
+        double e = exp(-0.5 * rho * rho);
+        if (rho <= 1.0) return e * (3.0 * rho - rho * rho * rho);
+        if (rho <= 2.0) return 2.0 * e;
+        return e * (rho * rho * rho - 3.0 * rho);
+    }
+    double t = sqrt(5.0) * rho, c = (5.0 * sqrt(5.0) / 3.0) * exp(-t);
+    if (t <= 1.0) return c * (3.0 * t - t * t);
+    if (t <= 4.0) return c * 2.0 * sqrt(t);
+    return c * (t * t - 3.0 * t);
+}
+
+/* C3(r) = sup over rho >= r of kappa3(rho).  kappa3 rises to a peak, falls, rises to a
+ * second, lower peak and then falls for good:
+ *   SE: peaks at rho^2 = 3 - sqrt6 and 3 + sqrt6 (stationary points of e^(-rho^2/2)(3rho - rho^3)
+ *       and of e^(-rho^2/2)(rho^3 - 3rho)); the middle piece 2 e^(-rho^2/2) falls.
+ *   Matern-5/2: peaks at t = (5 -/+ sqrt13) / 2 (stationary points of e^-t (3t - t^2) and of
+ *       e^-t (t^2 - 3t)); the middle piece 2 sqrt t e^-t falls for t > 1/2. */
+static double curv3_env(int kind, double r2)
+{
+    double rho = sqrt(r2);
+    double p1, p2, q1, q2;   /* peak positions (in rho) and values */
+    if (kind == 0) {
+        p1 = sqrt(3.0 - sqrt(6.0));
+        p2 = sqrt(3.0 + sqrt(6.0));
+    } else {
+        p1 = (5.0 - sqrt(13.0)) / 2.0 / sqrt(5.0);
+        p2 = (5.0 + sqrt(13.0)) / 2.0 / sqrt(5.0);
+    }
+    q1 = kappa3(kind, p1);
+    q2 = kappa3(kind, p2);
+    if (rho <= p1) return q1;
+    if (rho >= p2) return kappa3(kind, rho);
+    double k = kappa3(kind, rho);
+    return k > q2 ? k : q2;
+}
+
+double orc_curv3_env(int kind, double r2) { return curv3_env(kind, r2); }
+
+/* Range [lo, hi] over |u| <= h of g u + q u^2 / 2 (ends, and the vertex when inside). */
+static void quad_range(double g, double q, double h, double* lo, double* hi)
+{
+    double a = -g * h + 0.5 * q * h * h, b = g * h + 0.5 * q * h * h;
+    *lo = a < b ? a : b;
+    *hi = a > b ? a : b;
+    if (q != 0.0 && fabs(g) <= fabs(q) * h) {
+        double v = -0.5 * g * g / q;
+        if (v < *lo) *lo = v;
+        if (v > *hi) *hi = v;
+    }
+}
+
+/* Range of the second-order model of phi over the box, relative to phi(c). */
+static void model_range(int D, const double* g, const double* Hm, const double* h, double R, double* lo,
+                        double* hi)
+{
+    double l = -R, u = R;
+    for (int d = 0; d < D; ++d) {
+        double a, b;
+        quad_range(g[d], Hm[d * D + d], h[d], &a, &b);
+        l += a;
+        u += b;
+        for (int e = 0; e < D; ++e) {
+            if (e == d) continue;
+            double x = 0.5 * fabs(Hm[d * D + e]) * h[d] * h[e];
+            l -= x;
+            u += x;
+        }
+    }
+    *lo = l;
+    *hi = u;
+}
+
+/* out[0] = mu(c), out[1] = lower bound of mu, out[2] = upper bound of mu, out[3] = upper
+ * bound of var over the closed box [blo, bhi]. */
+int orc_bound_certified(const orc_model* M, const double* blo, const double* bhi, double* out)
+{
+    const int m = M->m, D = M->dim;
+    double* buf = (double*)malloc(sizeof(double) * 5 * (size_t)m);
+    if (!buf) return ORC_ENOMEM;
+    double *k = buf, *t = buf + m, *w = buf + 2 * m, *u = buf + 3 * m, *v = buf + 4 * m;
+    double c[3], h[3], H = 0.0;
+    for (int d = 0; d < D; ++d) {
+        c[d] = 0.5 * (blo[d] + bhi[d]);
+        h[d] = 0.5 * (bhi[d] - blo[d]);
+        H += (h[d] / M->ell[d]) * (h[d] / M->ell[d]);
+    }
+    for (int i = 0; i < m; ++i) k[i] = orc_kernel(M->kind, D, M->s2, M->ell, c, M->X + (int64_t)i * D);
+    /* w = Q k(c) */
+    forward_sub(m, M->L, k, t);
+    backward_sub_t(m, M->L, t, M->A ? u : w);
+    if (M->A) {
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += M->A[(int64_t)i * m + j] * u[j];
+            v[i] = s;
+        }
+        forward_sub(m, M->L, v, t);
+        backward_sub_t(m, M->L, t, v);
+        for (int i = 0; i < m; ++i) w[i] = u[i] - v[i];
+    }
+    double mu = 0.0, nu = 0.0, gmu[3] = {0, 0, 0}, gnu[3] = {0, 0, 0}, Ra = 0.0, Rw = 0.0;
+    double Hmu[9] = {0}, Hnu[9] = {0};
+    for (int i = 0; i < m; ++i) {
+        const double* xi = M->X + (int64_t)i * D;
+        double g[3], Hk[9], r2 = 0.0;
+        orc_kernel_grad(M->kind, D, M->s2, M->ell, c, xi, g);
+        orc_kernel_hess(M->kind, D, M->s2, M->ell, c, xi, Hk);
+        for (int d = 0; d < D; ++d) {
+            double e = blo[d] - xi[d];
+            if (xi[d] - bhi[d] > e) e = xi[d] - bhi[d];
+            if (e < 0.0) e = 0.0;
+            r2 += (e / M->ell[d]) * (e / M->ell[d]);
+        }
+        double C3 = curv3_env(M->kind, r2);
+        mu += M->a[i] * k[i];
+        nu += w[i] * k[i];
+        for (int d = 0; d < D; ++d) {
+            gmu[d] += M->a[i] * g[d];
+            gnu[d] += w[i] * g[d];
+        }
+        for (int q = 0; q < D * D; ++q) {
+            Hmu[q] += M->a[i] * Hk[q];
+            Hnu[q] += w[i] * Hk[q];
+        }
+        Ra += fabs(M->a[i]) * C3;
+        Rw += fabs(w[i]) * C3;
+    }
+    const double r3 = M->s2 * H * sqrt(H) / 6.0;
+    double mlo, mhi, nlo, nhi;
+    model_range(D, gmu, Hmu, h, r3 * Ra, &mlo, &mhi);
+    model_range(D, gnu, Hnu, h, r3 * Rw, &nlo, &nhi);
+    double vhi = M->s2 - nu - 2.0 * nlo;
+    if (vhi > M->s2) vhi = M->s2;
+    if (vhi < 0.0) vhi = 0.0;
+    out[0] = mu;
+    out[1] = mu + mlo;
+    out[2] = mu + mhi;
+    out[3] = vhi;
+    free(buf);
+    return ORC_OK;
+}
+
+/* Lower bound of the standardised margin side (theta - mu(x)) / sigma(x) over the box from
+ * the certified box bounds: num / sigma_hi when num = side (theta - mu) at the box's worst
+ * mean is >= 0, else -infinity (no lower bound of sigma is kept). */
+double orc_certified_margin(double side, double theta, const double* cb)
+{
+    double mu = side > 0 ? cb[2] : cb[1];
+    double num = side * (theta - mu);
+    if (num < 0.0) return -INFINITY;
+    return margin(side, theta, mu, cb[3]);
+}
+
 /* ---------------------------------------------------- octree (Alg. 1) -- */
 
 static uint64_t morton(int D, const int64_t* c, int level)
@@ -1110,9 +1322,15 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
                 side = (mu < T->theta) ? 1.0 : -1.0;
             }
             rec.path = side > 0 ? 1 : 2;
-            double gap;
-            orc_bound(M, T->theta, side, blo, bhi, T->A->steps, &rec.gmin, &gap);
-            rec.lattice_gap = gap;
+            if (T->A->bound_kind == 1) {
+                double cb[4];
+                orc_bound_certified(M, blo, bhi, cb);
+                rec.gmin = orc_certified_margin(side, T->theta, cb);
+            } else {
+                double gap;
+                orc_bound(M, T->theta, side, blo, bhi, T->A->steps, &rec.gmin, &gap);
+                rec.lattice_gap = gap;
+            }
             rec.ub = orc_upper_bound(rec.gmin, d_pts);
             subdivide = rec.ub > alpha;
         }
