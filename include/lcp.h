@@ -77,7 +77,17 @@ typedef struct {
                                 the octree may have at most 8 levels (root edge / min_leaf_cells <= 128) */
     int bound_at_max_depth;  /* 1: region test at the finest level too (Alg. 1 as printed); 0: emit */
     int descent_steps;       /* projected-gradient steps of the bound search after the 3^D lattice, 0..16 */
+    int bound_kind;          /* lcp_bound_kind (0 = the paper's search) */
 } lcp_adapt;
+
+typedef enum {
+    LCP_BOUND_SEARCH = 0,    /* B from a bounded search of F_M over the node (Sec. 5.1; the paper's
+                                L-BFGS-B replaced by the 3^D lattice and descent_steps steps) */
+    LCP_BOUND_CERTIFIED = 1  /* B from certified box bounds of mean and variance (lcp_bound_certified):
+                                a node is skipped only if every point of it satisfies the bound, the
+                                guarantee Sec. 9 leaves open; more nodes are refined than with the
+                                search, and every leaf of the search is also a leaf here */
+} lcp_bound_kind;
 
 typedef enum {
     LCP_EST_COUNT = 0,       /* the paper's estimate (Sec. 4): fraction of samples mu + C z that cross */
@@ -183,8 +193,9 @@ int lcp_dense(const lcp_model* model, const lcp_grid* grid, double theta, const 
  * reconstruction of Sec. 5.3's last paragraph: cells inside the emitted nodes get the
  * same Monte Carlo LCP as lcp_dense (same precision, same z-bank); all other cells get 0.
  * The region test (preliminary decision on the observations inside the closed node box,
- * then the bound 1 - B^d of eq. (upper_bound) with B from a bounded search of F_M) runs
- * in binary64 regardless of `prec`.
+ * then the bound 1 - B^d of eq. (upper_bound) with B from a bounded search of F_M, or from
+ * certified box bounds when adapt->bound_kind is LCP_BOUND_CERTIFIED) runs in binary64
+ * regardless of `prec`.
  *   lcp          prod(npts - 1) cells (binary32)
  *   leaves       leaf_cap keys of the emitted nodes, key = level << 58 | Morton(node), ascending
  *   n_leaves     (device) receives the number of emitted nodes
@@ -196,6 +207,28 @@ int lcp_dense(const lcp_model* model, const lcp_grid* grid, double theta, const 
 int lcp_adaptive(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_adapt* adapt,
                  const lcp_mc* mc, int prec, float* lcp, uint64_t* leaves, int64_t leaf_cap, int64_t* n_leaves,
                  uint8_t* level_field, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * lcp_bound_certified -- box bounds of the latent posterior that hold at every point of
+ * each box, which make the region bound of eq. (upper_bound) guaranteed (the bounded search
+ * of Sec. 5.1 can miss the minimum, Sec. 9).  For box b with centre c and half-widths h:
+ *   out[4b + 0] = mu(c)
+ *   out[4b + 1], out[4b + 2] = lower and upper bound of mu over the box
+ *   out[4b + 3] = upper bound of var over the box (within [0, s2])
+ * from a second-order Taylor model at c with a third-order remainder bound: mu = a^T k and
+ * nu = w^T k with w = Q k(c) (Q = (K + noise I)^-1, or K^-1 - K^-1 A_M K^-1 for a sparse
+ * model), using var(x) <= s2 - nu(c) - 2 (nu(x) - nu(c)) (convexity of k^T Q k).  The bounds
+ * hold in exact arithmetic for the stored model; the binary64 rounding of their own sums is
+ * not bounded.
+ *   boxes  n x (2 dim): lo[0..dim-1], hi[0..dim-1] per box (device, binary64); lo <= hi on
+ *          every axis is required and not checked (the device data is not read on the host):
+ *          otherwise the results are unspecified
+ *   out    n x 4 (device, binary64)
+ *   ws     lcp_bound_workspace bytes
+ */
+int lcp_bound_workspace(const lcp_model* model, int64_t n, size_t* bytes);
+int lcp_bound_certified(const lcp_model* model, int64_t n, const double* boxes, double* out, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /*
  * Batches of independent models (local GP models of subdomains, each with its own

@@ -427,20 +427,28 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64
     return L;
 }
 
+}  // namespace
+
+hipError_t launch_kinv_frag(const Model& M, double* Kinv, double* F64, float* F32, hipStream_t s)
+{
+    const int mp = M.m_pad;
+    const int64_t n2 = (int64_t)mp * mp;
+    StageScope sc(s, ST_FACTOR);
+    hipLaunchKernelGGL(k_kinv, dim3((unsigned)(mp / 16), (unsigned)(mp / 16)), dim3(256), 0, s, M.Linv, mp, Kinv);
+    hipLaunchKernelGGL(k_frag_full, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, Kinv, mp, F64, F32);
+    return hipGetLastError();
+}
+
+namespace {
+
 // K^-1 fragments, then W = K^-1 K*^T for the points (plain columns of m_pad).
 hipError_t bwd_w(const Model& M, const BwdLayout& L, const BwdPts& P, int prec, char* ws, hipStream_t s)
 {
     const int mp = M.m_pad;
-    const int64_t n2 = (int64_t)mp * mp;
     double* Kinv = (double*)(ws + L.kinv);
     double* F64 = (double*)(ws + L.f64);
     float* F32 = (float*)(ws + L.f32);
-    {
-        StageScope sc(s, ST_FACTOR);
-        hipLaunchKernelGGL(k_kinv, dim3((unsigned)(mp / 16), (unsigned)(mp / 16)), dim3(256), 0, s, M.Linv, mp, Kinv);
-        hipLaunchKernelGGL(k_frag_full, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, Kinv, mp, F64, F32);
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_kinv_frag(M, Kinv, F64, F32, s);
     if (e != hipSuccess || P.n <= 0) return e;
     PostTask t{};
     t.group = 1;

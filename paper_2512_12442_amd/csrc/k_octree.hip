@@ -195,6 +195,8 @@ struct BoundBufs {
     double* gp_dmean;
     double* gp_dvar;
     int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes
+    double* box;        // certified bound: node box lo[D], hi[D] per stage-1 node (null: search)
+    double* cert;       //   mu(c), mu_lo, mu_hi, var_hi per stage-1 node
 };
 
 __device__ __forceinline__ double upper_bound(double gmin, int64_t dp)
@@ -222,6 +224,37 @@ __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ key
         key_coords(o.D, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         for (int d = 0; d < 3; ++d) B.cpts[b * 3 + d] = d < o.D ? 0.5 * (blo[d] + bhi[d]) : 0.0;
+        if (B.box) {
+            for (int d = 0; d < o.D; ++d) {
+                B.box[b * 2 * o.D + d] = blo[d];
+                B.box[b * 2 * o.D + o.D + d] = bhi[d];
+            }
+        }
+    }
+}
+
+// Certified bound: the side (nodes without observations: from the centre mean), the lower
+// bound of the margin over the box -- (theta - mu_hi) / sigma_hi below, (mu_lo - theta) /
+// sigma_hi above, -infinity when theta lies within the mean's bounds -- and UB = 1 - B^d.
+__global__ void k_cert_decide(Oct o, int level, const uint64_t* __restrict__ keys, const int32_t* __restrict__ path,
+                              BoundBufs B, int32_t* __restrict__ sub)
+{
+    const int64_t nb = B.cnt[0];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f = B.bnode[b];
+        const int p = path[f];
+        const double* cb = B.cert + b * 4;
+        const double side = p == 1 ? 1.0 : (p == 2 ? -1.0 : (cb[0] < o.theta ? 1.0 : -1.0));
+        const double mu = side > 0 ? cb[2] : cb[1];
+        const double g = side * (o.theta - mu) < 0.0 ? -__builtin_inf() : margin(side, o.theta, mu, cb[3]);
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o.D, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        B.side[b] = side;
+        B.gmin[b] = g;
+        sub[f] = upper_bound(g, dp) > o.alpha ? 1 : 0;
     }
 }
 
@@ -667,10 +700,11 @@ struct AdaptLayout {
     size_t o_bnode, o_side, o_gmin, o_x, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
     size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_lcnt, o_loff;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
+    size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
     int64_t capF, nv;
 };
 
-static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns,
+static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind,
                                 int64_t* caps, int64_t* nodes)
 {
     AdaptLayout L{};
@@ -746,16 +780,22 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         for (int d = 0; d < D; ++d) cpl *= S0 >> Lmax;
         L.o_cellws = take(cells_scratch_bytes(caps[Lmax] * cpl));
     }
+    if (bound_kind == LCP_BOUND_CERTIFIED) {
+        L.o_cop = take(cert_operand_bytes(M));
+        L.o_cw = take(8 * (size_t)M.m_pad * capF);
+        L.o_box = take(8 * 2 * (size_t)D * capF);
+        L.o_cert = take(32 * (size_t)capF);
+    }
     L.total = o;
     L.capF = capF;
     L.nv = nv;
     return L;
 }
 
-size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns)
+size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind)
 {
     int64_t caps[8], nodes[24];
-    return adapt_layout(M, g, S0, Lmax, prec, ns, caps, nodes).total;
+    return adapt_layout(M, g, S0, Lmax, prec, ns, bound_kind, caps, nodes).total;
 }
 
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
@@ -763,7 +803,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                         int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s)
 {
     int64_t caps[8], nodes[24];
-    AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, caps, nodes);
+    const bool cert = A.bound_kind == LCP_BOUND_CERTIFIED;
+    AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, caps, nodes);
     const int D = g.dim;
     const int npt = D == 3 ? 27 : 9;
     Oct o{};
@@ -816,8 +857,16 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.gp_dmean = (double*)P(L.o_gdm);
     B.gp_dvar = (double*)P(L.o_gdv);
     B.cnt = cnt + 16;
+    B.box = cert ? (double*)P(L.o_box) : nullptr;
+    B.cert = cert ? (double*)P(L.o_cert) : nullptr;
+    double* certW = cert ? (double*)P(L.o_cw) : nullptr;
 
     hipError_t e;
+    double* certF64 = nullptr;
+    if (cert) {
+        e = launch_cert_operand(M, (char*)P(L.o_cop), &certF64, s);
+        if (e != hipSuccess) return e;
+    }
     {
         int64_t acc = 0;
         for (int l = 0; l < 8; ++l) {
@@ -865,47 +914,57 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             t.stage = ST_BOUND;
             return launch_posterior(M, LCP_FP64, t, s);
         };
-        // stage 1: centres
-        e = post(B.cnt + 0, cap, B.cpts, B.cmean, B.cvar, nullptr, nullptr, 1);
-        if (e != hipSuccess) return e;
-        {
-            StageScope sc(s, ST_OCTREE);
-            hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
-            e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 1, scanws, s);
+        if (cert) {
+            // certified box bounds: w = Q k(c) on MFMA, moments per node, decision
+            e = launch_cert_w(M, certF64, B.cpts, B.cnt + 0, cap, certW, B.cmean, B.cvar, s);
             if (e != hipSuccess) return e;
-            e = launch_fill_i32(B.ngrid, -1, cap, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_lattice_grid, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
-            hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B);
-            e = launch_scan(B.lcnt, B.loff, cap, B.cnt + 1, B.cnt + 2, scanws, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_lattice_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
-        }
-        // stage 2: lattice
-        e = post(B.cnt + 2, cap * npt, B.lat_pts, B.lat_mean, B.lat_var, nullptr, nullptr, 1);
-        if (e != hipSuccess) return e;
-        {
-            StageScope sc(s, ST_OCTREE);
-            hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B, sub);
-            hipLaunchKernelGGL(k_flag_stage3, dim3(gsz(cap, 256)), dim3(256), 0, s, B);
-            e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 3, scanws, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_descent_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, B, gx);
-        }
-        // stage 3: projected-gradient steps
-        for (int k = 0; k < A.descent_steps; ++k) {
-            e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
+            e = launch_cert(M, B.box, B.cnt + 0, cap, certW, B.cert, s);
             if (e != hipSuccess) return e;
             StageScope sc(s, ST_OCTREE);
-            hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B, gx);
-        }
-        if (A.descent_steps > 0) {
-            e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
+            hipLaunchKernelGGL(k_cert_decide, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
+        } else {
+            // stage 1: centres
+            e = post(B.cnt + 0, cap, B.cpts, B.cmean, B.cvar, nullptr, nullptr, 1);
             if (e != hipSuccess) return e;
+            {
+                StageScope sc(s, ST_OCTREE);
+                hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
+                e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 1, scanws, s);
+                if (e != hipSuccess) return e;
+                e = launch_fill_i32(B.ngrid, -1, cap, s);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_lattice_grid, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
+                hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B);
+                e = launch_scan(B.lcnt, B.loff, cap, B.cnt + 1, B.cnt + 2, scanws, s);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_lattice_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
+            }
+            // stage 2: lattice
+            e = post(B.cnt + 2, cap * npt, B.lat_pts, B.lat_mean, B.lat_var, nullptr, nullptr, 1);
+            if (e != hipSuccess) return e;
+            {
+                StageScope sc(s, ST_OCTREE);
+                hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B, sub);
+                hipLaunchKernelGGL(k_flag_stage3, dim3(gsz(cap, 256)), dim3(256), 0, s, B);
+                e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 3, scanws, s);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_descent_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, B, gx);
+            }
+            // stage 3: projected-gradient steps
+            for (int k = 0; k < A.descent_steps; ++k) {
+                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
+                if (e != hipSuccess) return e;
+                StageScope sc(s, ST_OCTREE);
+                hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B, gx);
+            }
+            if (A.descent_steps > 0) {
+                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
+                if (e != hipSuccess) return e;
+                StageScope sc(s, ST_OCTREE);
+                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
+            }
         }
         StageScope sc(s, ST_OCTREE);
-        if (A.descent_steps > 0)
-            hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
         hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
         int64_t* nout = (l == Lmax) ? n_leaves : cnt + l + 1;
         e = launch_scan(ecnt, eoff, cap, nf, nout, scanws, s);

@@ -162,6 +162,8 @@ int check_adapt(const lcp_adapt* A)
     if (A->bound_at_max_depth != 0 && A->bound_at_max_depth != 1)
         return fail(LCP_EINVAL, "bound_at_max_depth must be 0 or 1");
     if (A->descent_steps < 0 || A->descent_steps > 16) return fail(LCP_EINVAL, "descent_steps must be in 0..16");
+    if (A->bound_kind != LCP_BOUND_SEARCH && A->bound_kind != LCP_BOUND_CERTIFIED)
+        return fail(LCP_EINVAL, "bound_kind must be LCP_BOUND_SEARCH or LCP_BOUND_CERTIFIED");
     return LCP_OK;
 }
 
@@ -306,7 +308,7 @@ int lcp_adaptive_workspace(const lcp_model* M, const lcp_grid* grid, const lcp_a
     int Lmax;
     octree_shape(g, A->min_leaf_cells, &S0, &Lmax);
     if (Lmax > 7) return fail(LCP_EINVAL, "octree deeper than 8 levels (raise min_leaf_cells)");
-    *bytes = adaptive_workspace(*M, g, S0, Lmax, prec, n_samples);
+    *bytes = adaptive_workspace(*M, g, S0, Lmax, prec, n_samples, A->bound_kind);
     return ok();
 }
 
@@ -360,6 +362,28 @@ int gp_posterior_backward(const lcp_model* M, int64_t n, const double* Xq, int p
     hipError_t e = launch_posterior_backward(*M, n, Xq, prec, n > 0 ? dL_dmean : nullptr, n > 0 ? dL_dvar : nullptr,
                                              dL_dy, dL_dloglen, (char*)ws, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, "gp_posterior_backward");
+    return ok();
+}
+
+int lcp_bound_workspace(const lcp_model* M, int64_t n, size_t* bytes)
+{
+    if (!M || !bytes) return fail(LCP_EINVAL, "model and bytes must not be NULL");
+    if (n < 0) return fail(LCP_EINVAL, "n < 0");
+    *bytes = bound_certified_ws(*M, n);
+    return ok();
+}
+
+int lcp_bound_certified(const lcp_model* M, int64_t n, const double* boxes, double* out, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    if (!M) return fail(LCP_EINVAL, "model is NULL");
+    if (n < 0) return fail(LCP_EINVAL, "n < 0");
+    if (n > 0 && (!boxes || !out)) return fail(LCP_EINVAL, "boxes and out must not be NULL");
+    const size_t need = bound_certified_ws(*M, n);
+    if (!ws || !aligned256(ws)) return fail(LCP_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipError_t e = launch_bound_certified(*M, n, boxes, out, (char*)ws, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "lcp_bound_certified");
     return ok();
 }
 
@@ -499,7 +523,7 @@ int lcp_adaptive(const lcp_model* M, const lcp_grid* grid, double theta, const l
     int Lmax;
     octree_shape(g, A->min_leaf_cells, &S0, &Lmax);
     if (Lmax > 7) return fail(LCP_EINVAL, "octree deeper than 8 levels (raise min_leaf_cells)");
-    const size_t need = adaptive_workspace(*M, g, S0, Lmax, prec, mc->n_samples);
+    const size_t need = adaptive_workspace(*M, g, S0, Lmax, prec, mc->n_samples, A->bound_kind);
     if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     hipError_t e = run_adaptive(*M, g, theta, *A, S0, Lmax, prec, mc->n_samples, mc->zbank, lcp, leaves, leaf_cap,
                                 n_leaves, level_field, (char*)ws, (hipStream_t)stream);

@@ -271,6 +271,20 @@ hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq
 size_t lcp_backward_ws(const Model& M, const GridP& g, int prec, int ns);
 hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int ns, const double* zb, int prec,
                                const double* gl, double* dy, double* dlogell, char* ws, hipStream_t s);
+// K^-1 = Linv^T Linv (row-major) and its 16 x 16 x 4 fragment copies (binary64, binary32).
+hipError_t launch_kinv_frag(const Model& M, double* Kinv, double* F64, float* F32, hipStream_t s);
+// Certified region bound (k_bound.hip).  The operand Q = Linv^T Linv in fragment order
+// (cert_operand_bytes of ws; *F64 receives its binary64 copy); w = Q k(c) for box centres
+// (3 doubles per point, device count or cap), W column b at b * m_pad; then per box
+// (lo[dim], hi[dim]) the bounds mu(c), mu_lo, mu_hi, var_hi.
+size_t cert_operand_bytes(const Model& M);
+hipError_t launch_cert_operand(const Model& M, char* ws, double** F64, hipStream_t s);
+hipError_t launch_cert_w(const Model& M, const double* F64, const double* pts, const int64_t* count, int64_t cap,
+                         double* W, double* mean, double* var, hipStream_t s);
+hipError_t launch_cert(const Model& M, const double* box, const int64_t* count, int64_t cap, const double* W,
+                       double* out, hipStream_t s);
+size_t bound_certified_ws(const Model& M, int64_t n);
+hipError_t launch_bound_certified(const Model& M, int64_t n, const double* box, double* out, char* ws, hipStream_t s);
 size_t factor_batch_scratch(int nb);
 hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
                                int* info_dev, hipStream_t s);
@@ -283,7 +297,7 @@ hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks,
 
 // ------------------------------------------------------------- octree (K4/K5)
 
-size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns);
+size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind);
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
                         int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
                         int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s);

@@ -39,7 +39,10 @@ class Grid(C.Structure):
 
 class Adapt(C.Structure):
     _fields_ = [("alpha", C.c_double), ("min_leaf_cells", C.c_int), ("bound_at_max_depth", C.c_int),
-                ("descent_steps", C.c_int)]
+                ("descent_steps", C.c_int), ("bound_kind", C.c_int)]
+
+
+BOUND_SEARCH, BOUND_CERTIFIED = 0, 1
 
 
 class MC(C.Structure):
@@ -54,7 +57,7 @@ EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor
            "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
            "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward",
-           "lcp_backward_workspace"]
+           "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -90,6 +93,8 @@ def lib():
     L.lcp_backward_workspace.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(SZ)]
     L.gp_posterior_backward_workspace.argtypes = [P, I64, C.c_int, C.POINTER(SZ)]
     L.gp_posterior_backward.argtypes = [P, I64, P, C.c_int, P, P, P, P, P, SZ, P]
+    L.lcp_bound_workspace.argtypes = [P, I64, C.POINTER(SZ)]
+    L.lcp_bound_certified.argtypes = [P, I64, P, P, P, SZ, P]
     L.lcp_profile_begin.argtypes = [C.c_uint]
     L.lcp_profile_end.argtypes = [P, P, C.c_int]
     L.lcp_batch_model_bytes.restype = SZ
@@ -213,6 +218,19 @@ class GPModel:
         _check(lib().gp_posterior_backward(self.h, n, _ptr(Xq), _prec(prec), _ptr(gm), _ptr(gv), _ptr(dy), _ptr(dl),
                                            _ptr(ws), b.value, _stream()))
         return dy, dl
+
+    def bound_certified(self, boxes: torch.Tensor, ws=None):
+        """Certified box bounds (lcp_bound_certified): boxes n x (2 dim) as lo then hi per box;
+        returns n x 4 (mu at the centre, mu lower and upper bound, var upper bound)."""
+        boxes = boxes.to(torch.float64).contiguous()
+        n = int(boxes.shape[0])
+        b = C.c_size_t()
+        _check(lib().lcp_bound_workspace(self.h, n, C.byref(b)))
+        if ws is None or ws.numel() < b.value:
+            ws = _buffer(b.value, self.device)
+        out = torch.empty((n, 4), dtype=torch.float64, device=self.device)
+        _check(lib().lcp_bound_certified(self.h, n, _ptr(boxes), _ptr(out), _ptr(ws), b.value, _stream()))
+        return out
 
     def dense_workspace(self, grid: Grid, prec, n_samples):
         b = C.c_size_t()
@@ -392,9 +410,9 @@ def grid_of(W) -> Grid:
     return make_grid(W.dim, W.lo, W.hi, W.npts)
 
 
-def adapt_of(W, min_leaf=None, bound_at_max_depth=1, steps=4, alpha=None) -> Adapt:
+def adapt_of(W, min_leaf=None, bound_at_max_depth=1, steps=4, alpha=None, bound_kind=BOUND_SEARCH) -> Adapt:
     return Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf), int(bound_at_max_depth),
-                 int(steps))
+                 int(steps), int(bound_kind))
 
 
 class GPModelBatch:

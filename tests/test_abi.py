@@ -92,6 +92,15 @@ def test_null_model_rejected_everywhere():
     assert L.gp_posterior(None, 1, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
     assert L.lcp_dense(None, None, 0.0, None, 0, None, None, 0, None) == lcp.lcp.LCP_EINVAL
     assert L.lcp_adaptive(None, None, 0.0, None, None, 0, None, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_bound_workspace(None, 4, C.byref(b)) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_bound_certified(None, 4, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+    assert "model" in L.lcp_last_error().decode()
+
+
+def test_adapt_struct_carries_the_bound_kind():
+    a = lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 4})(), bound_kind=lcp.BOUND_CERTIFIED)
+    assert a.bound_kind == 1 and a.descent_steps == 4 and a.min_leaf_cells == 4
+    assert lcp.lcp.Adapt.bound_kind.offset == 20 and C.sizeof(lcp.lcp.Adapt) == 24
 
 
 def _fit_batch(kernels, ms, X=None, y=None, mem=None, nbytes=0):
