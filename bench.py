@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--workload", default="trig128", choices=["trig128", "sgpr500", "local_blocks", "grad96"],
                     help="trig128: the headline adaptive LCP; local_blocks: batched local GP models")
     ap.add_argument("--blocks", type=int, default=256, help="number of models for --workload local_blocks")
+    ap.add_argument("--bound", default="search", choices=["search", "certified"],
+                    help="region bound of the octree query: the paper's search, or certified box bounds")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
@@ -237,7 +239,8 @@ def main():
         wl = (f"trig field {args.npts}^3 grid, m=500 uniform observations, Matern-5/2 l=0.1, "
               f"s2=1e-3, noise 1e-5, theta=median(y), alpha=1e-3, min leaf 4^3, N_s=1600")
     grid = lcp.grid_of(W)
-    adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4)
+    adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4,
+                         bound_kind=lcp.BOUND_CERTIFIED if args.bound == "certified" else lcp.BOUND_SEARCH)
     zb = torch.as_tensor(W.zbank, device=dev)
     nvert = W.n_vertices
 
@@ -356,8 +359,8 @@ def main():
         "vs_baseline": None, "dtype": {"f16x3": "f16x3+f64", "bf16x3": "bf16x3+f64", "fp32": "f32+f64",
                                        "fp64": "f64"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": wl, "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha, "precision": args.prec,
-                   "parallelism": "1 GPU"},
+        "config": {"workload": wl, "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha,
+                   "precision": args.prec, "region_bound": args.bound, "parallelism": "1 GPU"},
         "dense_fp64_ms_per_step": dense_ms,
         "dense_fp64_pts_per_s": (nvert / (dense_ms * 1e-3)) if dense_ms else None,
         "speedup_vs_dense_fp64": (dense_ms / step_ms) if dense_ms else None,
