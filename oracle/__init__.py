@@ -31,10 +31,11 @@ class Grid(C.Structure):
 
 class Adapt(C.Structure):
     _fields_ = [("alpha", C.c_double), ("min_leaf", C.c_int), ("bound_at_max_depth", C.c_int),
-                ("steps", C.c_int), ("bound_kind", C.c_int)]
+                ("steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int)]
 
 
 BOUND_SEARCH, BOUND_CERTIFIED = 0, 1
+SPLIT_OCTREE, SPLIT_KD = 0, 1
 
 
 class NodeRec(C.Structure):
@@ -92,6 +93,7 @@ def lib():
                                       C.c_int64, P]
         _lib.orc_lcp_leaves.argtypes = [P, P, C.c_double, C.c_int, P, C.c_int64, P, C.c_int64, P]
         _lib.orc_level_field.argtypes = [P, C.c_int64, P, C.c_int64, P]
+        _lib.orc_level_field_kd.argtypes = [P, C.c_int64, P, C.c_int64, P]
         _lib.orc_num_threads.restype = C.c_int
     return _lib
 
@@ -337,11 +339,13 @@ def octree_shape(W, min_leaf=None):
 
 
 def adaptive(M: FitModel, W, alpha=None, min_leaf=None, bound_at_max_depth=1, steps=4, cap=1 << 22,
-             bound_kind=BOUND_SEARCH):
-    """Alg. 1: returns (leaves, skipped, node records), each sorted by key."""
+             bound_kind=BOUND_SEARCH, split=SPLIT_OCTREE):
+    """Alg. 1: returns (leaves, skipped, node records), each sorted by key.  With the K-D
+    tree, records and skipped keys carry the depth (0 .. dim Lmax); leaves keep the octree
+    key of the finest level."""
     g = grid_of(W)
     A = Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf),
-              int(bound_at_max_depth), int(steps), int(bound_kind))
+              int(bound_at_max_depth), int(steps), int(bound_kind), int(split))
     leaves = np.zeros(cap, np.uint64)
     skipped = np.zeros(cap, np.uint64)
     recs = np.zeros(cap, NODE_DTYPE)
@@ -371,6 +375,23 @@ def level_field(W, keys, min_leaf=None):
     out = np.full(W.n_cells, 255, np.uint8)
     k = np.ascontiguousarray(keys, np.uint64)
     lib().orc_level_field(C.byref(g), S0, _p(k), k.shape[0], _p(out))
+    return out.reshape(W.cell_shape)
+
+
+def kd_leaf_keys(W, leaves, min_leaf=None):
+    """Leaves (octree keys of the finest level) as K-D tree keys of depth dim * Lmax."""
+    _, L = octree_shape(W, min_leaf)
+    mask = np.uint64((1 << 58) - 1)
+    return (np.asarray(leaves, np.uint64) & mask) | np.uint64((W.dim * L) << 58)
+
+
+def level_field_kd(W, keys, min_leaf=None):
+    """Depth at which each cell's K-D tree node stopped, from K-D keys."""
+    g = grid_of(W)
+    S0, _ = octree_shape(W, min_leaf)
+    out = np.full(W.n_cells, 255, np.uint8)
+    k = np.ascontiguousarray(keys, np.uint64)
+    lib().orc_level_field_kd(C.byref(g), S0, _p(k), k.shape[0], _p(out))
     return out.reshape(W.cell_shape)
 
 

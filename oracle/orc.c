@@ -70,6 +70,7 @@ typedef struct {
     int bound_at_max_depth; /* 1: Alg. 1 as printed (region test at every level) */
     int steps;              /* projected-gradient steps after the lattice */
     int bound_kind;         /* 0: bounded search (lattice + steps), 1: certified box bounds */
+    int split;              /* 0: octree (Alg. 1), 1: K-D tree splitting the axes in turn (Sec. 9) */
 } orc_adapt;
 
 typedef struct {
@@ -1234,6 +1235,29 @@ static uint64_t morton(int D, const int64_t* c, int level)
     return key;
 }
 
+/*
+ * K-D tree variant (Sec. 9 proposes splitting the axes in turn instead of all at once).
+ * The split at depth L halves axis D - 1 - (L mod D): z, then y, then x in 3D, so after D
+ * splits a node is an octree child and, at depth D l, a node is the octree node of level l
+ * with the same Morton code.  A node at depth L has had kd_splits(D, L, d) halvings along
+ * axis d, and its code lists the split bits in split order (the first split is the most
+ * significant bit).
+ */
+static int kd_axis(int D, int L) { return D - 1 - L % D; }
+
+static int kd_splits(int D, int L, int d) { return L / D + (d >= D - L % D ? 1 : 0); }
+
+static uint64_t kd_code(int D, const int64_t* c, int L)
+{
+    uint64_t code = 0;
+    for (int j = 0; j < L; ++j) {
+        int a = kd_axis(D, j);
+        int bit = (int)((c[a] >> (kd_splits(D, L, a) - 1 - j / D)) & 1);
+        code = (code << 1) | (uint64_t)bit;
+    }
+    return code;
+}
+
 typedef struct {
     const orc_model* M;
     const orc_grid* G;
@@ -1242,7 +1266,9 @@ typedef struct {
     const double* qlo;   /* P(Y_i < theta) per observation */
     const double* qhi;   /* P(Y_i > theta) per observation */
     int64_t S0;          /* root edge in cells (power of two) */
-    int Lmax;
+    int Lmax;            /* octree levels below the root */
+    int kd;              /* K-D tree: depths 0 .. D Lmax */
+    int Ldepth;          /* deepest level: Lmax (octree) or D Lmax (K-D tree) */
     omp_lock_t lock;
     uint64_t* leaves; int64_t leaf_cap; int64_t n_leaves;
     uint64_t* skipped; int64_t skip_cap; int64_t n_skipped;
@@ -1262,11 +1288,11 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
     const orc_model* M = T->M;
     const orc_grid* G = T->G;
     int D = G->dim;
-    int64_t s = T->S0 >> level;
     int64_t clo[3], chi[3];
     double blo[3], bhi[3];
     int64_t d_pts = 1;
     for (int d = 0; d < D; ++d) {
+        int64_t s = T->S0 >> (T->kd ? kd_splits(D, level, d) : level);
         clo[d] = c[d] * s;
         chi[d] = (c[d] + 1) * s;
         if (chi[d] > G->n[d] - 1) chi[d] = G->n[d] - 1;
@@ -1276,7 +1302,7 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
     }
     orc_node_rec rec;
     memset(&rec, 0, sizeof rec);
-    rec.key = ((uint64_t)level << 58) | morton(D, c, level);
+    rec.key = ((uint64_t)level << 58) | (T->kd ? kd_code(D, c, level) : morton(D, c, level));
     rec.level = level;
     rec.d = d_pts;
     rec.gmin = NAN;
@@ -1284,7 +1310,7 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
     rec.lattice_gap = NAN;
 
     int subdivide = 0;
-    if (level == T->Lmax && !T->A->bound_at_max_depth) {
+    if (level == T->Ldepth && !T->A->bound_at_max_depth) {
         rec.path = 3;
         subdivide = 1;
     } else {
@@ -1345,10 +1371,24 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
         push(T, T->skipped, T->skip_cap, &T->n_skipped, rec.key);
         return;
     }
-    if (level == T->Lmax) {
-        push(T, T->leaves, T->leaf_cap, &T->n_leaves, rec.key);
+    if (level == T->Ldepth) {
+        /* leaves keep the octree key (level Lmax); the K-D code at depth D Lmax is the same */
+        push(T, T->leaves, T->leaf_cap, &T->n_leaves, ((uint64_t)T->Lmax << 58) | (rec.key & ((1ull << 58) - 1)));
         return;
     }
+    if (T->kd) {
+        int a = kd_axis(D, level);
+        int64_t hs = T->S0 >> kd_splits(D, level + 1, a);
+        for (int i = 0; i < 2; ++i) {
+            int64_t cc[3] = {c[0], c[1], c[2]};
+            cc[a] = 2 * c[a] + i;
+            if (cc[a] * hs >= G->n[a] - 1) continue;
+#pragma omp task firstprivate(cc) if (level < 12)
+            octree_node(T, level + 1, cc);
+        }
+        return;
+    }
+    int64_t s = T->S0 >> level;
     int nchild = 1 << D;
     for (int i = 0; i < nchild; ++i) {
         int64_t cc[3] = {0, 0, 0};
@@ -1429,6 +1469,8 @@ int orc_adaptive(const orc_model* M, const orc_grid* G, double theta, const orc_
     memset(&T, 0, sizeof T);
     T.M = M; T.G = G; T.A = A; T.theta = theta; T.qlo = qlo; T.qhi = qhi;
     orc_octree_shape(G, A->min_leaf, &T.S0, &T.Lmax);
+    T.kd = A->split == 1;
+    T.Ldepth = T.kd ? G->dim * T.Lmax : T.Lmax;
     T.leaves = leaves; T.leaf_cap = leaf_cap;
     T.skipped = skipped; T.skip_cap = skip_cap;
     T.recs = recs; T.rec_cap = rec_cap;
@@ -1521,6 +1563,31 @@ void orc_level_field(const orc_grid* G, int64_t S0, const uint64_t* keys, int64_
             for (int64_t j = clo[1]; j < chi[1]; ++j)
                 for (int64_t i = clo[0]; i < chi[0]; ++i)
                     field[i + (G->n[0] - 1) * (j + (G->n[1] - 1) * k)] = (uint8_t)level;
+    }
+}
+
+/* Depth at which each cell's node stopped, for K-D tree keys (depth L << 58 | code). */
+void orc_level_field_kd(const orc_grid* G, int64_t S0, const uint64_t* keys, int64_t nkeys, uint8_t* field)
+{
+    int D = G->dim;
+    for (int64_t t = 0; t < nkeys; ++t) {
+        int L = (int)(keys[t] >> 58);
+        uint64_t code = keys[t] & ((1ull << 58) - 1);
+        int64_t c[3] = {0, 0, 0}, clo[3] = {0, 0, 0}, chi[3] = {1, 1, 1};
+        for (int j = 0; j < L; ++j) {
+            int a = kd_axis(D, j);
+            c[a] = 2 * c[a] + (int64_t)((code >> (L - 1 - j)) & 1);
+        }
+        for (int d = 0; d < D; ++d) {
+            int64_t s = S0 >> kd_splits(D, L, d);
+            clo[d] = c[d] * s;
+            chi[d] = (c[d] + 1) * s;
+            if (chi[d] > G->n[d] - 1) chi[d] = G->n[d] - 1;
+        }
+        for (int64_t k = clo[2]; k < (D > 2 ? chi[2] : 1); ++k)
+            for (int64_t j = clo[1]; j < chi[1]; ++j)
+                for (int64_t i = clo[0]; i < chi[0]; ++i)
+                    field[i + (G->n[0] - 1) * (j + (G->n[1] - 1) * k)] = (uint8_t)L;
     }
 }
 
