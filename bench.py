@@ -203,6 +203,8 @@ def main():
     ap.add_argument("--blocks", type=int, default=256, help="number of models for --workload local_blocks")
     ap.add_argument("--bound", default="search", choices=["search", "certified"],
                     help="region bound of the octree query: the paper's search, or certified box bounds")
+    ap.add_argument("--split", default="octree", choices=["octree", "kd"],
+                    help="subdivision of the adaptive query: the paper's octree, or a K-D tree")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
@@ -240,7 +242,8 @@ def main():
               f"s2=1e-3, noise 1e-5, theta=median(y), alpha=1e-3, min leaf 4^3, N_s=1600")
     grid = lcp.grid_of(W)
     adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4,
-                         bound_kind=lcp.BOUND_CERTIFIED if args.bound == "certified" else lcp.BOUND_SEARCH)
+                         bound_kind=lcp.BOUND_CERTIFIED if args.bound == "certified" else lcp.BOUND_SEARCH,
+                         split=lcp.SPLIT_KD if args.split == "kd" else lcp.SPLIT_OCTREE)
     zb = torch.as_tensor(W.zbank, device=dev)
     nvert = W.n_vertices
 
@@ -360,7 +363,8 @@ def main():
                                        "fp64": "f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": wl, "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha,
-                   "precision": args.prec, "region_bound": args.bound, "parallelism": "1 GPU"},
+                   "precision": args.prec, "region_bound": args.bound, "subdivision": args.split,
+                   "parallelism": "1 GPU"},
         "dense_fp64_ms_per_step": dense_ms,
         "dense_fp64_pts_per_s": (nvert / (dense_ms * 1e-3)) if dense_ms else None,
         "speedup_vs_dense_fp64": (dense_ms / step_ms) if dense_ms else None,

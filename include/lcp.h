@@ -78,7 +78,16 @@ typedef struct {
     int bound_at_max_depth;  /* 1: region test at the finest level too (Alg. 1 as printed); 0: emit */
     int descent_steps;       /* projected-gradient steps of the bound search after the 3^D lattice, 0..16 */
     int bound_kind;          /* lcp_bound_kind (0 = the paper's search) */
+    int split;               /* lcp_split (0 = the octree of Alg. 1) */
 } lcp_adapt;
+
+typedef enum {
+    LCP_SPLIT_OCTREE = 0,    /* Alg. 1: every node splits all axes at once (2^dim children) */
+    LCP_SPLIT_KD = 1         /* K-D tree (Sec. 9): a node halves one axis, z, y, x in turn (2 children),
+                                so depth dim * l holds the octree nodes of level l and the same finest
+                                nodes; leaves keep the octree key of the finest level, and level_field
+                                reports the depth (0 .. dim * levels) */
+} lcp_split;
 
 typedef enum {
     LCP_BOUND_SEARCH = 0,    /* B from a bounded search of F_M over the node (Sec. 5.1; the paper's
@@ -199,7 +208,8 @@ int lcp_dense(const lcp_model* model, const lcp_grid* grid, double theta, const 
  *   lcp          prod(npts - 1) cells (binary32)
  *   leaves       leaf_cap keys of the emitted nodes, key = level << 58 | Morton(node), ascending
  *   n_leaves     (device) receives the number of emitted nodes
- *   level_field  optional (may be NULL): per cell, the octree level at which its node stopped
+ *   level_field  optional (may be NULL): per cell, the octree level (K-D tree: depth) at which
+ *                its node stopped
  * If the emitted set exceeds leaf_cap, the first leaf_cap keys are written, *n_leaves
  * receives the true count, and the reconstruction is not performed (LCP stays zero); the
  * caller sees this after synchronising the stream.

@@ -23,11 +23,24 @@ struct Oct {
     double alpha;
     int bound_at_max;
     int steps;
-    int64_t nodes[24];       // node lattice extent per level and axis: nodes[l*3 + d]
-    int64_t statoff[8];      // offset of each level's status grid
+    int kd;                  // 1: K-D tree (one axis halved per level), depths 0 .. D Lmax
+    int Ldepth;              // deepest level: Lmax (octree) or D Lmax (K-D tree)
+    int64_t nodes[72];       // node lattice extent per level and axis: nodes[l*3 + d]
+    int64_t statoff[24];     // offset of each level's status grid
 };
 
-__device__ __forceinline__ void key_coords(int D, uint64_t key, int& level, int64_t* c)
+// K-D tree (Sec. 9: split the axes in turn): the split at depth L halves axis
+// D - 1 - (L mod D), so every D-th depth is an octree level with the same Morton code; the
+// code of a node lists its split bits in split order, the first split most significant.
+__device__ __forceinline__ int kd_axis(int D, int L) { return D - 1 - L % D; }
+
+// Halvings of axis d at this level.
+__device__ __forceinline__ int node_shift(const Oct& o, int level, int d)
+{
+    return o.kd ? level / o.D + (d >= o.D - level % o.D ? 1 : 0) : level;
+}
+
+__device__ __forceinline__ void key_coords_oct(int D, uint64_t key, int& level, int64_t* c)
 {
     level = (int)(key >> 58);
     uint64_t mc = key & ((1ull << 58) - 1);
@@ -36,11 +49,34 @@ __device__ __forceinline__ void key_coords(int D, uint64_t key, int& level, int6
         for (int d = 0; d < D; ++d) c[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
 }
 
-__device__ __forceinline__ uint64_t make_key(int D, int level, const int64_t* c)
+__device__ __forceinline__ void key_coords(const Oct& o, uint64_t key, int& level, int64_t* c)
 {
+    if (!o.kd) {
+        key_coords_oct(o.D, key, level, c);
+        return;
+    }
+    level = (int)(key >> 58);
+    const uint64_t code = key & ((1ull << 58) - 1);
+    c[0] = c[1] = c[2] = 0;
+    for (int j = 0; j < level; ++j) {
+        const int a = kd_axis(o.D, j);
+        c[a] = 2 * c[a] + (int64_t)((code >> (level - 1 - j)) & 1);
+    }
+}
+
+__device__ __forceinline__ uint64_t make_key(const Oct& o, int level, const int64_t* c)
+{
+    const int D = o.D;
     uint64_t k = 0;
-    for (int b = 0; b < level; ++b)
-        for (int d = 0; d < D; ++d) k |= (uint64_t)((c[d] >> b) & 1) << (b * D + d);
+    if (o.kd) {
+        for (int j = 0; j < level; ++j) {
+            const int a = kd_axis(D, j);
+            k = (k << 1) | (uint64_t)((c[a] >> (node_shift(o, level, a) - 1 - j / D)) & 1);
+        }
+    } else {
+        for (int b = 0; b < level; ++b)
+            for (int d = 0; d < D; ++d) k |= (uint64_t)((c[d] >> b) & 1) << (b * D + d);
+    }
     return ((uint64_t)level << 58) | k;
 }
 
@@ -48,10 +84,10 @@ __device__ __forceinline__ uint64_t make_key(int D, int level, const int64_t* c)
 __device__ __forceinline__ void node_box(const Oct& o, int level, const int64_t* c, int64_t* clo, int64_t* chi,
                                          double* blo, double* bhi, int64_t* dpts)
 {
-    const int64_t s = o.S0 >> level;
     int64_t d = 1;
     for (int k = 0; k < 3; ++k) {
         if (k < o.D) {
+            const int64_t s = o.S0 >> node_shift(o, level, k);
             clo[k] = c[k] * s;
             chi[k] = (c[k] + 1) * s;
             if (chi[k] > o.g.nc[k]) chi[k] = o.g.nc[k];
@@ -129,10 +165,10 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[f], lv, c);
+        key_coords(o, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         int pth;
-        if (level == o.Lmax && !o.bound_at_max) {
+        if (level == o.Ldepth && !o.bound_at_max) {
             pth = 3;
         } else {
             int nin = 0;
@@ -221,7 +257,7 @@ __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ key
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[f], lv, c);
+        key_coords(o, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         for (int d = 0; d < 3; ++d) B.cpts[b * 3 + d] = d < o.D ? 0.5 * (blo[d] + bhi[d]) : 0.0;
         if (B.box) {
@@ -250,7 +286,7 @@ __global__ void k_cert_decide(Oct o, int level, const uint64_t* __restrict__ key
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[f], lv, c);
+        key_coords(o, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         B.side[b] = side;
         B.gmin[b] = g;
@@ -271,7 +307,7 @@ __global__ void k_bound_centre(Oct o, int level, const uint64_t* __restrict__ ke
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[f], lv, c);
+        key_coords(o, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         B.side[b] = side;
         B.gmin[b] = g;
@@ -339,7 +375,7 @@ __global__ void k_lattice_grid(Oct o, int level, const uint64_t* __restrict__ ke
         B.lnode[l] = (int32_t)b;
         int lv;
         int64_t c[3];
-        key_coords(o.D, keys[B.bnode[b]], lv, c);
+        key_coords(o, keys[B.bnode[b]], lv, c);
         B.ngrid[node_lin(o, level, c)] = l;
     }
 }
@@ -358,7 +394,7 @@ __global__ void k_lattice_own(Oct o, int level, const uint64_t* __restrict__ key
         if (l < nl && sub_lane < npt) {
             int lv;
             int64_t c[3], oc[3];
-            key_coords(o.D, keys[B.bnode[B.lnode[l]]], lv, c);
+            key_coords(o, keys[B.bnode[B.lnode[l]]], lv, c);
             int oi;
             lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
             own = node_lin(o, level, oc) == node_lin(o, level, c);
@@ -394,7 +430,7 @@ __global__ void k_lattice_setup(Oct o, int level, const uint64_t* __restrict__ k
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[B.bnode[B.lnode[l]]], lv, c);
+        key_coords(o, keys[B.bnode[B.lnode[l]]], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         const int32_t mask = B.lmask[l];
         int64_t slot = B.loff[l];
@@ -427,7 +463,7 @@ __global__ void k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, B
             b = B.lnode[l];
             f = B.bnode[b];
             int lv;
-            key_coords(o.D, keys[f], lv, c);
+            key_coords(o, keys[f], lv, c);
             if (sub_lane < npt) {
                 int64_t oc[3];
                 int oi;
@@ -506,7 +542,7 @@ __global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ 
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[B.bnode[b]], lv, c);
+        key_coords(o, keys[B.bnode[b]], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         const double sd = sqrt(var);
         double u[3], nrm = 0.0;
@@ -545,7 +581,7 @@ __global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ key
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
         double blo[3], bhi[3];
-        key_coords(o.D, keys[f], lv, c);
+        key_coords(o, keys[f], lv, c);
         node_box(o, level, c, clo, chi, blo, bhi, &dp);
         sub[f] = upper_bound(gmin, dp) > o.alpha ? 1 : 0;
     }
@@ -560,17 +596,23 @@ __global__ void k_emit_count(Oct o, int level, const uint64_t* __restrict__ keys
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
         int n = 0;
         if (sub[f]) {
-            if (level == o.Lmax) {
+            if (level == o.Ldepth) {
                 n = 1;
             } else {
                 int lv;
                 int64_t c[3];
-                key_coords(o.D, keys[f], lv, c);
-                const int64_t hs = (o.S0 >> level) >> 1;
-                for (int i = 0; i < (1 << o.D); ++i) {
-                    bool ok = true;
-                    for (int d = 0; d < o.D; ++d) ok = ok && (2 * c[d] + ((i >> d) & 1)) * hs < o.g.nc[d];
-                    n += ok ? 1 : 0;
+                key_coords(o, keys[f], lv, c);
+                if (o.kd) {
+                    const int a = kd_axis(o.D, level);
+                    const int64_t hs = o.S0 >> node_shift(o, level + 1, a);
+                    n = 1 + ((2 * c[a] + 1) * hs < o.g.nc[a] ? 1 : 0);
+                } else {
+                    const int64_t hs = (o.S0 >> level) >> 1;
+                    for (int i = 0; i < (1 << o.D); ++i) {
+                        bool ok = true;
+                        for (int d = 0; d < o.D; ++d) ok = ok && (2 * c[d] + ((i >> d) & 1)) * hs < o.g.nc[d];
+                        n += ok ? 1 : 0;
+                    }
                 }
             }
         }
@@ -587,13 +629,27 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
         int lv;
         int64_t c[3];
-        key_coords(o.D, keys[f], lv, c);
+        key_coords(o, keys[f], lv, c);
         const int64_t* nl = o.nodes + level * 3;
         stat[c[0] + nl[0] * (c[1] + nl[1] * c[2])] = sub[f] ? 2 : 1;
         if (!sub[f]) continue;
         int64_t pos = off[f];
-        if (level == o.Lmax) {
-            if (pos < out_cap) out[pos] = keys[f];
+        if (level == o.Ldepth) {
+            // leaves keep the octree key of the finest level (the K-D code at depth D Lmax is
+            // the same Morton code)
+            if (pos < out_cap) out[pos] = ((uint64_t)o.Lmax << 58) | (keys[f] & ((1ull << 58) - 1));
+            continue;
+        }
+        if (o.kd) {
+            const int a = kd_axis(o.D, level);
+            const int64_t hs = o.S0 >> node_shift(o, level + 1, a);
+            for (int i = 0; i < 2; ++i) {
+                int64_t cc[3] = {c[0], c[1], c[2]};
+                cc[a] = 2 * c[a] + i;
+                if (cc[a] * hs >= o.g.nc[a]) continue;
+                if (pos < out_cap) out[pos] = make_key(o, level + 1, cc);
+                ++pos;
+            }
             continue;
         }
         const int64_t hs = (o.S0 >> level) >> 1;
@@ -605,7 +661,7 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
                 ok = ok && cc[d] * hs < o.g.nc[d];
             }
             if (!ok) continue;
-            if (pos < out_cap) out[pos] = make_key(o.D, level + 1, cc);
+            if (pos < out_cap) out[pos] = make_key(o, level + 1, cc);
             ++pos;
         }
     }
@@ -631,7 +687,7 @@ __global__ void k_mark(Oct o, int leaf_edge, const uint64_t* __restrict__ leaves
         int64_t loc = it % per;
         int lv;
         int64_t c[3];
-        key_coords(o.D, leaves[lf], lv, c);
+        key_coords_oct(o.D, leaves[lf], lv, c);
         const int64_t s = o.S0 >> lv;
         int64_t v[3] = {0, 0, 0};
         bool ok = true;
@@ -668,12 +724,13 @@ __global__ void k_level_field(Oct o, const uint8_t* __restrict__ stat, uint8_t* 
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nc; it += (int64_t)gridDim.x * blockDim.x) {
         int64_t cell[3] = {it % o.g.nc[0], (it / o.g.nc[0]) % o.g.nc[1], it / (o.g.nc[0] * o.g.nc[1])};
         uint8_t out = 255;
-        for (int l = 0; l <= o.Lmax; ++l) {
-            const int64_t s = o.S0 >> l;
+        for (int l = 0; l <= o.Ldepth; ++l) {
             const int64_t* nl = o.nodes + l * 3;
-            int64_t lin = (cell[0] / s) + nl[0] * ((cell[1] / s) + nl[1] * (cell[2] / s));
+            int64_t q[3];
+            for (int d = 0; d < 3; ++d) q[d] = d < o.D ? cell[d] / (o.S0 >> node_shift(o, l, d)) : 0;
+            const int64_t lin = q[0] + nl[0] * (q[1] + nl[1] * q[2]);
             uint8_t st = stat[o.statoff[l] + lin];
-            if (st == 1 || (st == 2 && l == o.Lmax)) {
+            if (st == 1 || (st == 2 && l == o.Ldepth)) {
                 out = (uint8_t)l;
                 break;
             }
@@ -704,16 +761,23 @@ struct AdaptLayout {
     int64_t capF, nv;
 };
 
+// Halvings of axis d at a level of the octree or of the K-D tree (node_shift on the host).
+static int level_shift(int kd, int D, int level, int d)
+{
+    return kd ? level / D + (d >= D - level % D ? 1 : 0) : level;
+}
+
 static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind,
-                                int64_t* caps, int64_t* nodes)
+                                int kd, int64_t* caps, int64_t* nodes)
 {
     AdaptLayout L{};
     const int D = g.dim;
+    const int Ldepth = kd ? D * Lmax : Lmax;
     int64_t capF = 1, stat_total = 0;
-    for (int l = 0; l <= Lmax; ++l) {
-        const int64_t s = S0 >> l;
+    for (int l = 0; l <= Ldepth; ++l) {
         int64_t c = 1;
         for (int d = 0; d < 3; ++d) {
+            const int64_t s = S0 >> level_shift(kd, D, l, d);
             int64_t nd = d < D ? ceil_div(g.nc[d], s) : 1;
             nodes[l * 3 + d] = nd;
             c *= nd;
@@ -764,7 +828,7 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_gdm = take(24 * capF);
     L.o_gdv = take(24 * capF);
     L.o_stat = take(stat_total);
-    L.o_statoff = take(8 * (Lmax + 1));
+    L.o_statoff = take(8 * (Ldepth + 1));
     L.o_scan = take(scan_workspace(nv > capF ? nv : capF));
     L.o_vmask = take(4 * nv);
     L.o_voff = take(4 * nv);
@@ -778,7 +842,7 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     {
         int64_t cpl = 1;
         for (int d = 0; d < D; ++d) cpl *= S0 >> Lmax;
-        L.o_cellws = take(cells_scratch_bytes(caps[Lmax] * cpl));
+        L.o_cellws = take(cells_scratch_bytes(caps[Ldepth] * cpl));
     }
     if (bound_kind == LCP_BOUND_CERTIFIED) {
         L.o_cop = take(cert_operand_bytes(M));
@@ -792,19 +856,22 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     return L;
 }
 
-size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind)
+size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns,
+                          const lcp_adapt& A)
 {
-    int64_t caps[8], nodes[24];
-    return adapt_layout(M, g, S0, Lmax, prec, ns, bound_kind, caps, nodes).total;
+    int64_t caps[24], nodes[72];
+    return adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, A.split == LCP_SPLIT_KD, caps, nodes).total;
 }
 
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
                         int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
                         int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s)
 {
-    int64_t caps[8], nodes[24];
+    int64_t caps[24], nodes[72];
     const bool cert = A.bound_kind == LCP_BOUND_CERTIFIED;
-    AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, caps, nodes);
+    const int kd = A.split == LCP_SPLIT_KD;
+    const int Ldepth = kd ? g.dim * Lmax : Lmax;
+    AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, kd, caps, nodes);
     const int D = g.dim;
     const int npt = D == 3 ? 27 : 9;
     Oct o{};
@@ -812,16 +879,18 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     o.D = D;
     o.S0 = S0;
     o.Lmax = Lmax;
+    o.kd = kd;
+    o.Ldepth = Ldepth;
     o.theta = theta;
     o.alpha = A.alpha;
     o.bound_at_max = A.bound_at_max_depth;
     o.steps = A.descent_steps;
-    for (int i = 0; i < 24; ++i) o.nodes[i] = i < (Lmax + 1) * 3 ? nodes[i] : 1;
+    for (int i = 0; i < 72; ++i) o.nodes[i] = i < (Ldepth + 1) * 3 ? nodes[i] : 1;
 
     auto P = [&](size_t off) { return (void*)(ws + off); };
     double* qlo = (double*)P(L.o_q);
     double* qhi = qlo + M.m_pad;
-    int64_t* cnt = (int64_t*)P(L.o_cnt);   // [0..15] frontier counts, [16] nb, [17] lattice pts, [18] nv
+    int64_t* cnt = (int64_t*)P(L.o_cnt);   // [0..22] frontier counts, [32..35] bound stages, [40] vertices
     uint64_t* keys[2] = {(uint64_t*)P(L.o_keys0), (uint64_t*)P(L.o_keys1)};
     int32_t* path = (int32_t*)P(L.o_path);
     int32_t* need = (int32_t*)P(L.o_need);
@@ -856,7 +925,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.gp_var = (double*)P(L.o_gv);
     B.gp_dmean = (double*)P(L.o_gdm);
     B.gp_dvar = (double*)P(L.o_gdv);
-    B.cnt = cnt + 16;
+    B.cnt = cnt + 32;
     B.box = cert ? (double*)P(L.o_box) : nullptr;
     B.cert = cert ? (double*)P(L.o_cert) : nullptr;
     double* certW = cert ? (double*)P(L.o_cw) : nullptr;
@@ -869,9 +938,9 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     }
     {
         int64_t acc = 0;
-        for (int l = 0; l < 8; ++l) {
+        for (int l = 0; l < 24; ++l) {
             o.statoff[l] = acc;
-            if (l <= Lmax) acc += caps[l];
+            if (l <= Ldepth) acc += caps[l];
         }
         e = launch_fill_u8(stat, 0, acc, s);
         if (e != hipSuccess) return e;
@@ -885,7 +954,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     e = launch_fill_f32(lcp, 0.0f, g.nc[0] * g.nc[1] * g.nc[2], s);
     if (e != hipSuccess) return e;
 
-    for (int l = 0; l <= Lmax; ++l) {
+    for (int l = 0; l <= Ldepth; ++l) {
         uint64_t* kin = keys[l & 1];
         uint64_t* kout = keys[(l + 1) & 1];
         const int64_t cap = caps[l];
@@ -966,11 +1035,11 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         }
         StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
-        int64_t* nout = (l == Lmax) ? n_leaves : cnt + l + 1;
+        int64_t* nout = (l == Ldepth) ? n_leaves : cnt + l + 1;
         e = launch_scan(ecnt, eoff, cap, nf, nout, scanws, s);
         if (e != hipSuccess) return e;
-        uint64_t* dst = (l == Lmax) ? leaves : kout;
-        const int64_t dcap = (l == Lmax) ? leaf_cap : caps[l + 1];
+        uint64_t* dst = (l == Ldepth) ? leaves : kout;
+        const int64_t dcap = (l == Ldepth) ? leaf_cap : caps[l + 1];
         hipLaunchKernelGGL(k_emit, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, eoff, dst, dcap,
                            stat + o.statoff[l]);
         e = hipGetLastError();
@@ -988,7 +1057,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     int32_t* voff = (int32_t*)P(L.o_voff);
     int32_t* slot = (int32_t*)P(L.o_slot);
     int32_t* vlist = (int32_t*)P(L.o_vlist);
-    int64_t* nvd = cnt + 24;
+    int64_t* nvd = cnt + 40;
     e = launch_fill_i32(vmask, 0, L.nv, s);
     if (e != hipSuccess) return e;
     int64_t per = 1;
@@ -1048,7 +1117,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         for (int d = 0; d < D; ++d) cpl_all *= leaf_edge;
         char* cw = (char*)P(L.o_cellws);
         ct.work = (int32_t*)cw;
-        ct.wcount = (int64_t*)(cw + align256(4 * (size_t)(caps[Lmax] * cpl_all)));
+        ct.wcount = (int64_t*)(cw + align256(4 * (size_t)(caps[Ldepth] * cpl_all)));
         ct.zmax = (double*)((char*)ct.wcount + 64);
     }
     int64_t cpl = 1;

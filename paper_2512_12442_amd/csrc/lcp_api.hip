@@ -164,6 +164,8 @@ int check_adapt(const lcp_adapt* A)
     if (A->descent_steps < 0 || A->descent_steps > 16) return fail(LCP_EINVAL, "descent_steps must be in 0..16");
     if (A->bound_kind != LCP_BOUND_SEARCH && A->bound_kind != LCP_BOUND_CERTIFIED)
         return fail(LCP_EINVAL, "bound_kind must be LCP_BOUND_SEARCH or LCP_BOUND_CERTIFIED");
+    if (A->split != LCP_SPLIT_OCTREE && A->split != LCP_SPLIT_KD)
+        return fail(LCP_EINVAL, "split must be LCP_SPLIT_OCTREE or LCP_SPLIT_KD");
     return LCP_OK;
 }
 
@@ -308,7 +310,7 @@ int lcp_adaptive_workspace(const lcp_model* M, const lcp_grid* grid, const lcp_a
     int Lmax;
     octree_shape(g, A->min_leaf_cells, &S0, &Lmax);
     if (Lmax > 7) return fail(LCP_EINVAL, "octree deeper than 8 levels (raise min_leaf_cells)");
-    *bytes = adaptive_workspace(*M, g, S0, Lmax, prec, n_samples, A->bound_kind);
+    *bytes = adaptive_workspace(*M, g, S0, Lmax, prec, n_samples, *A);
     return ok();
 }
 
@@ -523,7 +525,7 @@ int lcp_adaptive(const lcp_model* M, const lcp_grid* grid, double theta, const l
     int Lmax;
     octree_shape(g, A->min_leaf_cells, &S0, &Lmax);
     if (Lmax > 7) return fail(LCP_EINVAL, "octree deeper than 8 levels (raise min_leaf_cells)");
-    const size_t need = adaptive_workspace(*M, g, S0, Lmax, prec, mc->n_samples, A->bound_kind);
+    const size_t need = adaptive_workspace(*M, g, S0, Lmax, prec, mc->n_samples, *A);
     if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     hipError_t e = run_adaptive(*M, g, theta, *A, S0, Lmax, prec, mc->n_samples, mc->zbank, lcp, leaves, leaf_cap,
                                 n_leaves, level_field, (char*)ws, (hipStream_t)stream);

@@ -297,7 +297,7 @@ hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks,
 
 // ------------------------------------------------------------- octree (K4/K5)
 
-size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind);
+size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, const lcp_adapt& A);
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
                         int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
                         int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s);

@@ -100,7 +100,9 @@ def test_null_model_rejected_everywhere():
 def test_adapt_struct_carries_the_bound_kind():
     a = lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 4})(), bound_kind=lcp.BOUND_CERTIFIED)
     assert a.bound_kind == 1 and a.descent_steps == 4 and a.min_leaf_cells == 4
-    assert lcp.lcp.Adapt.bound_kind.offset == 20 and C.sizeof(lcp.lcp.Adapt) == 24
+    assert lcp.lcp.Adapt.bound_kind.offset == 20 and lcp.lcp.Adapt.split.offset == 24
+    assert C.sizeof(lcp.lcp.Adapt) == 32
+    assert lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 2})(), split=lcp.SPLIT_KD).split == 1
 
 
 def _fit_batch(kernels, ms, X=None, y=None, mem=None, nbytes=0):
