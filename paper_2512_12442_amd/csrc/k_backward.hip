@@ -289,92 +289,134 @@ __global__ void k_bwd_finish(const double* __restrict__ b, int m, const double* 
 }
 
 // Neighbour terms of the LCP adjoint over grid vertices (W, Z, U column-major, ld m_pad):
-// z_p = sum_e c_p,e w_p+e + c_p-e,e w_p-e, U_p = h_p w_p + z_p / 2, and (first j-block only)
-// the direct term sum_e c_p,e dk(x_p, x_p+e)/dlog(ell_d) (partials per work-group).
-// A work-group owns a 64 x 4 (x 1) vertex tile and JB observation rows: the tile's W block
-// with its one-vertex halo is staged in LDS once, so every W element is read from HBM about
-// (66 * 6 * 3) / 256 times instead of 27.  Thread = vertex.
-constexpr int kStX = 64, kStY = 4;
-__host__ __device__ inline int64_t stencil_tiles(const GridP& g)
+// z_p = sum_e c_p,e w_p+e + c_p-e,e w_p-e and U_p = h_p w_p + z_p / 2.
+// One wave owns 64 consecutive observation rows of one x-line of vertices (fixed y, z), so
+// every load and store of a column is 64 consecutive elements.  The wave walks the line in
+// x with the W columns of the 3^D neighbourhood in registers: each step loads the column at
+// x + 2 of the 3^(D-1) neighbouring lines, and the coefficients c (the same for all lanes)
+// come through scalar loads.  Consecutive waves take neighbouring lines of the same rows,
+// so the columns they share are served from L2.
+constexpr int kStRows = 64;
+__host__ __device__ inline int64_t stencil_lines(const GridP& g) { return g.n[1] * (g.dim == 3 ? g.n[2] : 1); }
+
+// Direction e: offset with last non-zero component +1 (codes 14..26 of {-1,0,1}^3 in base 3,
+// x fastest; 5..8 of {-1,0,1}^2).
+template <int D>
+__device__ __forceinline__ void stencil_offset(int e, int* off)
 {
-    return ((g.n[0] + kStX - 1) / kStX) * ((g.n[1] + kStY - 1) / kStY) * (g.dim == 3 ? g.n[2] : 1);
+    if (D == 3) { off[0] = (e + 14) % 3 - 1; off[1] = ((e + 14) / 3) % 3 - 1; off[2] = (e + 14) / 9 - 1; }
+    else { off[0] = (e + 5) % 3 - 1; off[1] = (e + 5) / 3 - 1; off[2] = 0; }
 }
+
 template <class T, int D>
-__global__ void __launch_bounds__(256) k_bwd_stencil(KParams kp, GridP g, int mp, const T* __restrict__ W,
+__global__ void __launch_bounds__(256) k_bwd_stencil(GridP g, int mp, const T* __restrict__ W,
                                                      const double* __restrict__ gvar,
                                                      const double* __restrict__ gcross, T* __restrict__ Z,
-                                                     T* __restrict__ U, double* __restrict__ dpart)
+                                                     T* __restrict__ U)
 {
     constexpr int NDIR = D == 3 ? 13 : 4;
-    constexpr int JB = 64 / (int)sizeof(T);          // observation rows per block (LDS <= 76 KB)
-    constexpr int HX = kStX + 2, HY = kStY + 2, HZ = D == 3 ? 3 : 1;
-    constexpr int NCOL = HX * HY * HZ;
-    __shared__ T tile[NCOL * JB];
-    __shared__ double red[4];
-    const int tid = threadIdx.x;
-    const int64_t xch = (g.n[0] + kStX - 1) / kStX, ych = (g.n[1] + kStY - 1) / kStY;
-    const int64_t tl = blockIdx.x;
-    const int64_t x0 = (tl % xch) * kStX, y0 = ((tl / xch) % ych) * kStY, z0 = D == 3 ? tl / (xch * ych) : 0;
-    const int j0 = blockIdx.y * JB;
-    // stage W[q][j0 .. j0 + JB) for the tile and its halo (zero outside the grid)
-    for (int e = tid; e < NCOL * JB; e += 256) {
-        const int c = e / JB, jj = e % JB;
-        const int hx = c % HX, hy = (c / HX) % HY, hz = c / (HX * HY);
-        const int64_t x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + (D == 3 ? hz - 1 : 0);
-        T v = T(0);
-        if (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2] && j0 + jj < mp)
-            v = W[(size_t)(x + g.n[0] * (y + g.n[1] * z)) * mp + j0 + jj];
-        tile[e] = v;
+    constexpr int NL = D == 3 ? 9 : 3;              // neighbouring lines (dy, dz) in {-1,0,1}^(D-1)
+    const int lane = threadIdx.x & 63;
+    const int64_t nlines = stencil_lines(g);
+    const int64_t wv = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wv >= nlines * (mp / kStRows)) return;      // uniform over the wave
+    const int64_t line = wv % nlines;
+    const int j = (int)(wv / nlines) * kStRows + lane;
+    const int64_t y = line % g.n[1], z = D == 3 ? line / g.n[1] : 0;
+    const int64_t n0 = g.n[0];
+    // line l = (dy + 1) + 3 (dz + 1) (2D: dy + 1): its first vertex, or -1 outside the grid
+    int64_t base[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const int64_t yy = y + l % 3 - 1, zz = z + (D == 3 ? l / 3 - 1 : 0);
+        base[l] = (yy >= 0 && yy < g.n[1] && zz >= 0 && zz < g.n[2]) ? n0 * (yy + g.n[1] * zz) : -1;
     }
-    __syncthreads();
-    const int tx = tid % kStX, ty = tid / kStX;
-    const int64_t x = x0 + tx, y = y0 + ty, z = z0;
-    const bool live = x < g.n[0] && y < g.n[1];
-    double dacc[3] = {0.0, 0.0, 0.0};
-    if (live) {
-        const int64_t p = x + g.n[0] * (y + g.n[1] * z);
-        double cf[2 * NDIR];
-        int col[2 * NDIR];
+    auto col = [&](int l, int64_t x) -> T {
+        return (base[l] >= 0 && x >= 0 && x < n0) ? W[(size_t)(base[l] + x) * mp + j] : T(0);
+    };
+    T win[NL][3];                                   // columns at x - 1, x, x + 1
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        win[l][0] = T(0);
+        win[l][1] = col(l, 0);
+        win[l][2] = col(l, 1);
+    }
+    for (int64_t x = 0; x < n0; ++x) {
+        T next[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) next[l] = col(l, x + 2);
+        const int64_t p = base[NL / 2] + x;
+        double zz = 0.0;
+        double cb[NDIR];
+#pragma unroll
         for (int e = 0; e < NDIR; ++e) {
             int off[3];
-            if (D == 3) { off[0] = (e + 14) % 3 - 1; off[1] = ((e + 14) / 3) % 3 - 1; off[2] = (e + 14) / 9 - 1; }
-            else { off[0] = (e + 5) % 3 - 1; off[1] = (e + 5) / 3 - 1; off[2] = 0; }
+            stencil_offset<D>(e, off);
             const int64_t a[3] = {x + off[0], y + off[1], z + off[2]};
+            const bool fw = a[0] >= 0 && a[0] < n0 && a[1] >= 0 && a[1] < g.n[1] && a[2] >= 0 && a[2] < g.n[2];
+            const double cf = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
+            zz = fma(cf, (double)win[(off[1] + 1) + (D == 3 ? 3 * (off[2] + 1) : 0)][off[0] + 1], zz);
             const int64_t b[3] = {x - off[0], y - off[1], z - off[2]};
-            const bool fw = a[0] >= 0 && a[0] < g.n[0] && a[1] >= 0 && a[1] < g.n[1] && a[2] >= 0 && a[2] < g.n[2];
-            const bool bw = b[0] >= 0 && b[0] < g.n[0] && b[1] >= 0 && b[1] < g.n[1] && b[2] >= 0 && b[2] < g.n[2];
-            cf[e] = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
-            cf[NDIR + e] = bw ? gcross[(size_t)(b[0] + g.n[0] * (b[1] + g.n[1] * b[2])) * NDIR + e] : 0.0;
-            col[e] = ((D == 3 ? off[2] + 1 : 0) * HY + ty + 1 + off[1]) * HX + tx + 1 + off[0];
-            col[NDIR + e] = ((D == 3 ? 1 - off[2] : 0) * HY + ty + 1 - off[1]) * HX + tx + 1 - off[0];
-            if (blockIdx.y == 0 && fw && cf[e] != 0.0) {
-                double t[3];
-                for (int d = 0; d < 3; ++d)
-                    t[d] = (off[d] == 0 || d >= D) ? 0.0
-                         : (vertex_coord(g, d, a[d]) - vertex_coord(g, d, d == 0 ? x : (d == 1 ? y : z))) * kp.inv_ell[d];
-                const double r2 = fma(t[2], t[2], fma(t[1], t[1], t[0] * t[0]));
-                double kv, f;
-                kernel_val_dfac(kp, r2, &kv, &f);
-                for (int d = 0; d < 3; ++d) dacc[d] = fma(-f * cf[e], t[d] * t[d], dacc[d]);
-            }
+            const bool bw = b[0] >= 0 && b[0] < n0 && b[1] >= 0 && b[1] < g.n[1] && b[2] >= 0 && b[2] < g.n[2];
+            cb[e] = bw ? gcross[(size_t)(b[0] + n0 * (b[1] + g.n[1] * b[2])) * NDIR + e] : 0.0;
         }
-        const double hp = gvar[p];
-        const int cself = ((D == 3 ? 1 : 0) * HY + ty + 1) * HX + tx + 1;
-        for (int jj = 0; jj < JB && j0 + jj < mp; ++jj) {
-            double zz = 0.0;
 #pragma unroll
-            for (int e = 0; e < 2 * NDIR; ++e) zz = fma(cf[e], (double)tile[col[e] * JB + jj], zz);
-            const double w = (double)tile[cself * JB + jj];
-            Z[(size_t)p * mp + j0 + jj] = (T)zz;
-            U[(size_t)p * mp + j0 + jj] = (T)fma(hp, w, 0.5 * zz);
+        for (int e = 0; e < NDIR; ++e) {
+            int off[3];
+            stencil_offset<D>(e, off);
+            zz = fma(cb[e], (double)win[(1 - off[1]) + (D == 3 ? 3 * (1 - off[2]) : 0)][1 - off[0]], zz);
+        }
+        const double w = (double)win[NL / 2][1];
+        Z[(size_t)p * mp + j] = (T)zz;
+        U[(size_t)p * mp + j] = (T)fma(gvar[p], w, 0.5 * zz);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            win[l][0] = win[l][1];
+            win[l][1] = win[l][2];
+            win[l][2] = next[l];
         }
     }
-    if (blockIdx.y == 0) {                          // uniform per work-group
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double sres = block_sum256(dacc[d], red);
-            if (tid == 0) dpart[(size_t)blockIdx.x * 4 + d] = sres;
+}
+
+// Direct term of the LCP adjoint, sum_e c_p,e dk(x_p, x_p+e)/dlog(ell_d): one thread per
+// vertex, one partial per work-group.
+constexpr int kDirectThreads = 256;
+__host__ __device__ inline int64_t direct_parts(const GridP& g)
+{
+    return (g.n[0] * g.n[1] * g.n[2] + kDirectThreads - 1) / kDirectThreads;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kDirectThreads) k_bwd_direct(KParams kp, GridP g, const double* __restrict__ gcross,
+                                                               double* __restrict__ dpart)
+{
+    constexpr int NDIR = D == 3 ? 13 : 4;
+    __shared__ double red[4];
+    const int64_t p = (int64_t)blockIdx.x * kDirectThreads + threadIdx.x;
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    double dacc[3] = {0.0, 0.0, 0.0};
+    if (p < nv) {
+        const int64_t v[3] = {p % g.n[0], (p / g.n[0]) % g.n[1], p / (g.n[0] * g.n[1])};
+        for (int e = 0; e < NDIR; ++e) {
+            int off[3];
+            stencil_offset<D>(e, off);
+            const int64_t a[3] = {v[0] + off[0], v[1] + off[1], v[2] + off[2]};
+            const bool fw = a[0] >= 0 && a[0] < g.n[0] && a[1] >= 0 && a[1] < g.n[1] && a[2] >= 0 && a[2] < g.n[2];
+            const double cf = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
+            if (cf == 0.0) continue;
+            double t[3];
+            for (int d = 0; d < 3; ++d)
+                t[d] = (off[d] == 0 || d >= D) ? 0.0 : (vertex_coord(g, d, a[d]) - vertex_coord(g, d, v[d])) * kp.inv_ell[d];
+            const double r2 = fma(t[2], t[2], fma(t[1], t[1], t[0] * t[0]));
+            double kv, f;
+            kernel_val_dfac(kp, r2, &kv, &f);
+            for (int d = 0; d < 3; ++d) dacc[d] = fma(-f * cf, t[d] * t[d], dacc[d]);
         }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double sres = block_sum256(dacc[d], red);
+        if (threadIdx.x == 0) dpart[(size_t)blockIdx.x * 4 + d] = sres;
     }
 }
 
@@ -547,14 +589,14 @@ hipError_t launch_posterior_backward(const Model& M, int64_t n, const double* Xq
 size_t lcp_backward_ws(const Model& M, const GridP& g, int prec, int ns)
 {
     const int64_t nv = g.n[0] * g.n[1] * g.n[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
-    return bwd_layout(M, nv, prec, true, g.dim, nc, ns, stencil_tiles(g)).total;
+    return bwd_layout(M, nv, prec, true, g.dim, nc, ns, direct_parts(g)).total;
 }
 
 hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int ns, const double* zb, int prec,
                                const double* gl, double* dy, double* dlogell, char* ws, hipStream_t s)
 {
     const int64_t nv = g.n[0] * g.n[1] * g.n[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
-    const BwdLayout L = bwd_layout(M, nv, prec, true, g.dim, nc, ns, stencil_tiles(g));
+    const BwdLayout L = bwd_layout(M, nv, prec, true, g.dim, nc, ns, direct_parts(g));
     // forward moments: mean, variance, V (quad-major) and the neighbour cross-covariances
     PostTask t{};
     t.mode = COL_GRID;
@@ -599,32 +641,31 @@ hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int
     {
         StageScope sc(s, ST_MISC);
         const int mp = M.m_pad;
-        const unsigned nt = (unsigned)stencil_tiles(g);
+        const unsigned nw = (unsigned)ceil_div(stencil_lines(g) * (mp / kStRows), 4);
+        const unsigned nd = (unsigned)direct_parts(g);
         if (prec == LCP_FP64) {
-            const dim3 grd(nt, (unsigned)(mp / 8));
             if (g.dim == 3)
-                hipLaunchKernelGGL((k_bwd_stencil<double, 3>), grd, dim3(256), 0, s, M.kp, g, mp,
-                                   (const double*)(ws + L.w), gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u),
-                                   dpart);
+                hipLaunchKernelGGL((k_bwd_stencil<double, 3>), dim3(nw), dim3(256), 0, s, g, mp, (const double*)(ws + L.w),
+                                   gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u));
             else
-                hipLaunchKernelGGL((k_bwd_stencil<double, 2>), grd, dim3(256), 0, s, M.kp, g, mp,
-                                   (const double*)(ws + L.w), gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u),
-                                   dpart);
+                hipLaunchKernelGGL((k_bwd_stencil<double, 2>), dim3(nw), dim3(256), 0, s, g, mp, (const double*)(ws + L.w),
+                                   gvar, gcross, (double*)(ws + L.z), (double*)(ws + L.u));
         } else {
-            const dim3 grd(nt, (unsigned)(mp / 16));
             if (g.dim == 3)
-                hipLaunchKernelGGL((k_bwd_stencil<float, 3>), grd, dim3(256), 0, s, M.kp, g, mp,
-                                   (const float*)(ws + L.w), gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u),
-                                   dpart);
+                hipLaunchKernelGGL((k_bwd_stencil<float, 3>), dim3(nw), dim3(256), 0, s, g, mp, (const float*)(ws + L.w),
+                                   gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u));
             else
-                hipLaunchKernelGGL((k_bwd_stencil<float, 2>), grd, dim3(256), 0, s, M.kp, g, mp,
-                                   (const float*)(ws + L.w), gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u),
-                                   dpart);
+                hipLaunchKernelGGL((k_bwd_stencil<float, 2>), dim3(nw), dim3(256), 0, s, g, mp, (const float*)(ws + L.w),
+                                   gvar, gcross, (float*)(ws + L.z), (float*)(ws + L.u));
         }
+        if (g.dim == 3)
+            hipLaunchKernelGGL(k_bwd_direct<3>, dim3(nd), dim3(kDirectThreads), 0, s, M.kp, g, gcross, dpart);
+        else
+            hipLaunchKernelGGL(k_bwd_direct<2>, dim3(nd), dim3(kDirectThreads), 0, s, M.kp, g, gcross, dpart);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return bwd_tail(M, L, P, prec, gmean, gvar, ws + L.z, ws + L.u, dpart, stencil_tiles(g), dy, dlogell, ws, s);
+    return bwd_tail(M, L, P, prec, gmean, gvar, ws + L.z, ws + L.u, dpart, (int)direct_parts(g), dy, dlogell, ws, s);
 }
 
 }  // namespace lcp
