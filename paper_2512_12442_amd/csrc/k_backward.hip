@@ -335,36 +335,56 @@ __global__ void __launch_bounds__(256) k_bwd_stencil(GridP g, int mp, const T* _
         return (base[l] >= 0 && x >= 0 && x < n0) ? W[(size_t)(base[l] + x) * mp + j] : T(0);
     };
     T win[NL][3];                                   // columns at x - 1, x, x + 1
+    T pf[NL];                                       // column x + 2, loaded a step ahead
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         win[l][0] = T(0);
         win[l][1] = col(l, 0);
         win[l][2] = col(l, 1);
+        pf[l] = col(l, 2);
     }
+    // The coefficients of a vertex (the same for all lanes) come through vector loads one
+    // vertex ahead: lane e < NDIR holds the forward c_p,e, lane 16 + e the backward
+    // c_p-e,e (zero where the neighbour is outside the grid), read out with readlane.
+    const int ce = lane & 15;
+    const bool cfw = lane < 16;
+    int coff[3] = {0, 0, 0};
+    if (ce < NDIR) stencil_offset<D>(ce, coff);
+    auto coef = [&](int64_t x) -> double {
+        if (ce >= NDIR || lane >= 32) return 0.0;
+        const int sg = cfw ? 1 : -1;
+        const int64_t b[3] = {x + sg * coff[0], y + sg * coff[1], z + sg * coff[2]};
+        if (!(b[0] >= 0 && b[0] < n0 && b[1] >= 0 && b[1] < g.n[1] && b[2] >= 0 && b[2] < g.n[2])) return 0.0;
+        const int64_t q = cfw ? base[NL / 2] + x : b[0] + n0 * (b[1] + g.n[1] * b[2]);
+        return gcross[(size_t)q * NDIR + ce];
+    };
+    auto bcast = [](double v, int l) -> double {
+        const long long u = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+        return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+    };
+    double cv = coef(0);
     for (int64_t x = 0; x < n0; ++x) {
         T next[NL];
 #pragma unroll
-        for (int l = 0; l < NL; ++l) next[l] = col(l, x + 2);
+        for (int l = 0; l < NL; ++l) {
+            next[l] = pf[l];
+            pf[l] = col(l, x + 3);
+        }
+        const double cvn = coef(x + 1 < n0 ? x + 1 : x);
         const int64_t p = base[NL / 2] + x;
         double zz = 0.0;
-        double cb[NDIR];
 #pragma unroll
         for (int e = 0; e < NDIR; ++e) {
             int off[3];
             stencil_offset<D>(e, off);
-            const int64_t a[3] = {x + off[0], y + off[1], z + off[2]};
-            const bool fw = a[0] >= 0 && a[0] < n0 && a[1] >= 0 && a[1] < g.n[1] && a[2] >= 0 && a[2] < g.n[2];
-            const double cf = fw ? gcross[(size_t)p * NDIR + e] : 0.0;
-            zz = fma(cf, (double)win[(off[1] + 1) + (D == 3 ? 3 * (off[2] + 1) : 0)][off[0] + 1], zz);
-            const int64_t b[3] = {x - off[0], y - off[1], z - off[2]};
-            const bool bw = b[0] >= 0 && b[0] < n0 && b[1] >= 0 && b[1] < g.n[1] && b[2] >= 0 && b[2] < g.n[2];
-            cb[e] = bw ? gcross[(size_t)(b[0] + n0 * (b[1] + g.n[1] * b[2])) * NDIR + e] : 0.0;
+            zz = fma(bcast(cv, e), (double)win[(off[1] + 1) + (D == 3 ? 3 * (off[2] + 1) : 0)][off[0] + 1], zz);
         }
 #pragma unroll
         for (int e = 0; e < NDIR; ++e) {
             int off[3];
             stencil_offset<D>(e, off);
-            zz = fma(cb[e], (double)win[(1 - off[1]) + (D == 3 ? 3 * (1 - off[2]) : 0)][1 - off[0]], zz);
+            zz = fma(bcast(cv, 16 + e), (double)win[(1 - off[1]) + (D == 3 ? 3 * (1 - off[2]) : 0)][1 - off[0]], zz);
         }
         const double w = (double)win[NL / 2][1];
         Z[(size_t)p * mp + j] = (T)zz;
@@ -375,6 +395,7 @@ __global__ void __launch_bounds__(256) k_bwd_stencil(GridP g, int mp, const T* _
             win[l][1] = win[l][2];
             win[l][2] = next[l];
         }
+        cv = cvn;
     }
 }
 
