@@ -141,7 +141,7 @@ def run_grad(args):
 
     dev = torch.device("cuda:0")
     W, u, Ph, fh = workloads.grad_field(args.seed, npts=args.npts if args.npts != 128 else 96)
-    prec = "fp32" if not args.batch_prec_given else args.prec
+    prec = "f16x3" if not args.batch_prec_given else args.prec
     X = torch.as_tensor(W.X, device=dev)
     zb = torch.as_tensor(W.zbank, device=dev)
     grid = lcp.grid_of(W)
@@ -172,7 +172,9 @@ def run_grad(args):
         "metric": "differentiable LCP grid pts/s (forward + adjoint, 96^3, m=1000)",
         "value": W.n_vertices / (step_ms * 1e-3), "unit": "grid pts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32+f64", "fp64": "f64"}.get(prec, prec), "data": "synthetic",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "f16x3": "f16x3+f32+f64", "bf16x3": "bf16x3+f32+f64"}[prec],
+        "data": "synthetic",
         "config": {"workload": f"{W.npts[0]}^3 grid, m={W.m} uniform observations of the trig field (noise 1e-5), "
                                f"SE l=0.1 (learnable log-lengthscales), s2=1e-3, loss = sum u_c LCP_c (u~U[0,1], "
                                f"separation-of-variables LCP, N_s={W.n_samples}) + held-out mean MSE (2000 points)",

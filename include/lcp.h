@@ -316,7 +316,8 @@ int gp_posterior_backward(const lcp_model* model, int64_t n, const double* Xq, i
  *   model   from gp_fit_factor (LCP_ENOTSUPPORTED for a gp_fit_sgpr model)
  *   grid, theta, mc   as for lcp_dense; mc->estimator must be LCP_EST_SOV
  *   prec    LCP_FP64 or LCP_FP32: precision of V, W = K^-1 K*^T and the estimator's samples
- *           (cell factors, their adjoint and every sum are binary64)
+ *           (cell factors, their adjoint and every sum are binary64); LCP_MIXED_F16X3 or
+ *           LCP_MIXED_BF16X3: V by that split product (as in lcp_dense), the rest as LCP_FP32
  *   dL_dlcp cells binary64 (device)
  *   dL_dy   m binary64 (device), overwritten;  dL_dloglen  dim binary64 (device), overwritten
  *   ws, ws_bytes   256-byte aligned, >= lcp_backward_workspace bytes (about 4 n m_pad

@@ -530,7 +530,9 @@ hipError_t bwd_w(const Model& M, const BwdLayout& L, const BwdPts& P, int prec, 
     t.vld = mp;
     t.dense = 1;
     t.stage = ST_POSTERIOR;
-    return launch_posterior_operand(M, prec, t, prec == LCP_FP64 ? (const void*)F64 : (const void*)F32, s);
+    // the full operand runs in binary64 or binary32 (the split 16-bit forms serve V only)
+    const int wprec = prec == LCP_FP64 ? LCP_FP64 : LCP_FP32;
+    return launch_posterior_operand(M, wprec, t, wprec == LCP_FP64 ? (const void*)F64 : (const void*)F32, s);
 }
 
 // Points pass, b, the rank-n product (on U when given), pairs and the final sums.

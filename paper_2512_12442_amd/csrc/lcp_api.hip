@@ -536,7 +536,7 @@ int lcp_adaptive(const lcp_model* M, const lcp_grid* grid, double theta, const l
 int lcp_backward_workspace(const lcp_model* M, const lcp_grid* grid, int prec, int n_samples, size_t* bytes)
 {
     if (!M || !bytes) return fail(LCP_EINVAL, "model and bytes must not be NULL");
-    if (prec != LCP_FP64 && prec != LCP_FP32) return fail(LCP_EINVAL, "prec must be LCP_FP64 or LCP_FP32");
+    if (check_prec(prec)) return LCP_EINVAL;
     if (n_samples < 1) return fail(LCP_EINVAL, "n_samples < 1");
     GridP g;
     if (int r = check_grid(M, grid, &g)) return r;
@@ -549,7 +549,7 @@ int lcp_backward(const lcp_model* M, const lcp_grid* grid, double theta, const l
 {
     if (!M) return fail(LCP_EINVAL, "model is NULL");
     if (M->sparse) return fail(LCP_ENOTSUPPORTED, "lcp_backward: the model comes from gp_fit_sgpr");
-    if (prec != LCP_FP64 && prec != LCP_FP32) return fail(LCP_EINVAL, "prec must be LCP_FP64 or LCP_FP32");
+    if (check_prec(prec)) return LCP_EINVAL;
     GridP g;
     if (int r = check_grid(M, grid, &g)) return r;
     if (int r = check_mc(M, mc)) return r;

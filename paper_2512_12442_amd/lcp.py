@@ -301,6 +301,12 @@ class GPModel:
         return dy, dl
 
 
+def _operand_prec(p):
+    """gp_posterior_backward's one product has a full operand: binary64 or binary32 (a split
+    16-bit precision of the forward maps to binary32)."""
+    return p if _prec(p) in (FP64, FP32) else "fp32"
+
+
 class GPPosterior(torch.autograd.Function):
     """Posterior mean and variance at Xq as a differentiable function of the observation
     values y and the log-lengthscales: forward fits the model (gp_fit_factor) and evaluates
@@ -319,7 +325,7 @@ class GPPosterior(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gmean, gvar):
         (Xq,) = ctx.saved_tensors
-        dy, dl = ctx.G.posterior_backward(Xq, gmean, gvar, ctx.prec)
+        dy, dl = ctx.G.posterior_backward(Xq, gmean, gvar, _operand_prec(ctx.prec))
         return dy, dl, None, None, None, None, None, None
 
 
@@ -368,7 +374,7 @@ class GPLcpPosterior(torch.autograd.Function):
     def backward(ctx, gfield, gmean, gvar):
         (Xq,) = ctx.saved_tensors
         dy, dl = ctx.G.lcp_backward(ctx.grid, ctx.theta, ctx.zbank, gfield, ctx.prec)
-        dy2, dl2 = ctx.G.posterior_backward(Xq, gmean, gvar, ctx.prec)
+        dy2, dl2 = ctx.G.posterior_backward(Xq, gmean, gvar, _operand_prec(ctx.prec))
         return dy + dy2, dl + dl2, None, None, None, None, None, None, None, None, None
 
 

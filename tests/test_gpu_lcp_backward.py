@@ -74,6 +74,41 @@ def test_lcp_backward_fp32_error():
     assert _rel(dl, dl_ref) <= 2e-2
 
 
+def test_lcp_backward_split_precision_error():
+    """V by the FP16 split product (about binary32 accuracy), the rest as binary32: the same
+    2e-2 relative bound as the binary32 path."""
+    W = _case(3, 9, m=60, seed=92)
+    u = np.random.default_rng(93).random(W.n_cells)
+    dy_ref, dl_ref = oracle.lcp_backward(oracle.fit(W), W, u)
+    G = lcp.GPModel.from_workload(W, DEV)
+    dy, dl = G.lcp_backward(lcp.grid_of(W), W.theta, torch.as_tensor(W.zbank, device=DEV),
+                            torch.as_tensor(u, device=DEV), "f16x3")
+    dy, dl = dy.cpu().numpy(), dl.cpu().numpy()
+    say(f"lcp backward f16x3: rel dy={_rel(dy, dy_ref):.2e} rel dlogell={_rel(dl, dl_ref):.2e}")
+    assert _rel(dy, dy_ref) <= 2e-2
+    assert _rel(dl, dl_ref) <= 2e-2
+
+
+def test_autograd_lcp_posterior_split_precision_runs_and_agrees_with_fp32():
+    W = _case(3, 8, m=20, seed=96, ns=300)
+    X = torch.as_tensor(W.X, device=DEV)
+    zb = torch.as_tensor(W.zbank, device=DEV)
+    P = torch.as_tensor(np.random.default_rng(97).random((50, 3)), device=DEV)
+    u = torch.as_tensor(np.random.default_rng(98).random(W.n_cells), device=DEV)
+    grads = {}
+    for prec in ("fp32", "f16x3"):
+        y = torch.as_tensor(W.y, device=DEV).requires_grad_(True)
+        log_ell = torch.log(torch.as_tensor(W.lengthscale[:3], device=DEV)).requires_grad_(True)
+        field, mean, _ = lcp.lcp_posterior_fn(y, log_ell, X, lcp.grid_of(W), W.theta, zb, P, W.kind, W.signal_var,
+                                              W.noise_var, prec)
+        ((u * field).sum() + (mean ** 2).mean()).backward()
+        grads[prec] = (y.grad.cpu().numpy(), log_ell.grad.cpu().numpy())
+    say(f"autograd f16x3 vs fp32: rel dy={_rel(grads['f16x3'][0], grads['fp32'][0]):.2e} "
+        f"rel dlogell={_rel(grads['f16x3'][1], grads['fp32'][1]):.2e}")
+    assert _rel(grads["f16x3"][0], grads["fp32"][0]) <= 2e-2
+    assert _rel(grads["f16x3"][1], grads["fp32"][1]) <= 2e-2
+
+
 def test_autograd_lcp_matches_gpu_finite_differences():
     """torch.autograd through lcp_fn against central differences of the GPU smooth field
     (binary64 arithmetic, re-fitted at each perturbed input, h = 1e-4)."""
