@@ -443,6 +443,7 @@ __global__ void __launch_bounds__(kDirectThreads) k_bwd_direct(KParams kp, GridP
 
 struct BwdLayout {
     size_t kinv, f64, f32, w, mean, var, bpart, tpart, b, gpart, ppart, total;
+    size_t hhi, hlo, kamax;   // FP16 split operand (LCP_MIXED_F16X3 only)
     // LCP adjoint only
     size_t V, cross, wbank, gout, gmean, gvar, gcross, z, u, dpart, work;
     int nsplit;
@@ -472,6 +473,11 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64
     L.b = take(8 * mp);
     L.gpart = take(8 * mp * mp * (size_t)L.nsplit);
     L.ppart = take(8 * 4 * kBwdGridQ);
+    if (prec == LCP_MIXED_F16X3) {
+        L.hhi = take(2 * mp * mp);
+        L.hlo = take(2 * mp * mp);
+        L.kamax = take(8 * 2);
+    }
     if (lcp) {
         const int N = 1 << D, ndir = D == 3 ? 13 : 4;
         L.V = take(es * mp * nn);
@@ -488,6 +494,42 @@ BwdLayout bwd_layout(const Model& M, int64_t n, int prec, bool lcp, int D, int64
     }
     L.total = o;
     return L;
+}
+
+// Largest |K^-1| and the power-of-two scale that brings it to [2^14, 2^15) (one work-group).
+__global__ void __launch_bounds__(1024) k_kinv_amax(const double* __restrict__ Ki, int mp, double* __restrict__ amax)
+{
+    __shared__ double wmax[16];
+    double mx = 0.0;
+    for (int64_t t = threadIdx.x; t < (int64_t)mp * mp; t += 1024) mx = fmax(mx, fabs(Ki[t]));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < 16; ++w) mx = fmax(mx, wmax[w]);
+        int e;
+        frexp(mx, &e);
+        amax[0] = mx;
+        amax[1] = ldexp(1.0, 15 - e);
+    }
+}
+
+// 16 x 16 x 32 fragment order: fragment (i, s), lane l holds X[16 i + l % 16][32 s + 8 (l / 16) + e],
+// e = 0..7; x * amax[1] split into FP16 halves hi = fp16(x sA), lo = fp16(x sA - hi).
+__global__ void k_kinv_split16(const double* __restrict__ Ki, int mp, const double* __restrict__ amax,
+                               _Float16* __restrict__ hi, _Float16* __restrict__ lo)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    const int64_t frag = t / 512;
+    const int rem = (int)(t % 512);
+    const int l = rem / 8, e = rem % 8;
+    const int ks = mp / 32;
+    const int i = (int)(frag / ks), s = (int)(frag % ks);
+    const double xs = Ki[(int64_t)(16 * i + l % 16) * mp + 32 * s + 8 * (l / 16) + e] * amax[1];
+    const _Float16 h = (_Float16)xs;
+    hi[t] = h;
+    lo[t] = (_Float16)(xs - (double)h);
 }
 
 }  // namespace
@@ -512,7 +554,17 @@ hipError_t bwd_w(const Model& M, const BwdLayout& L, const BwdPts& P, int prec, 
     double* F64 = (double*)(ws + L.f64);
     float* F32 = (float*)(ws + L.f32);
     hipError_t e = launch_kinv_frag(M, Kinv, F64, F32, s);
-    if (e != hipSuccess || P.n <= 0) return e;
+    if (e != hipSuccess) return e;
+    if (prec == LCP_MIXED_F16X3) {
+        StageScope sc(s, ST_FACTOR);
+        const int64_t n2 = (int64_t)mp * mp;
+        hipLaunchKernelGGL(k_kinv_amax, dim3(1), dim3(1024), 0, s, Kinv, mp, (double*)(ws + L.kamax));
+        hipLaunchKernelGGL(k_kinv_split16, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, Kinv, mp,
+                           (const double*)(ws + L.kamax), (_Float16*)(ws + L.hhi), (_Float16*)(ws + L.hlo));
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (P.n <= 0) return hipSuccess;
     PostTask t{};
     t.group = 1;
     t.n_points = P.n;
@@ -530,7 +582,9 @@ hipError_t bwd_w(const Model& M, const BwdLayout& L, const BwdPts& P, int prec, 
     t.vld = mp;
     t.dense = 1;
     t.stage = ST_POSTERIOR;
-    // the full operand runs in binary64 or binary32 (the split 16-bit forms serve V only)
+    if (prec == LCP_MIXED_F16X3)
+        return launch_posterior_operand_f16x3(M, t, ws + L.hhi, ws + L.hlo, (const double*)(ws + L.kamax), s);
+    // the full operand in binary64 or binary32 (the BF16 split serves V only)
     const int wprec = prec == LCP_FP64 ? LCP_FP64 : LCP_FP32;
     return launch_posterior_operand(M, wprec, t, wprec == LCP_FP64 ? (const void*)F64 : (const void*)F32, s);
 }

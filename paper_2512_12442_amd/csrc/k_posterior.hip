@@ -619,7 +619,9 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
                 if (T.V) {
                     const int64_t pc = col0 + 16 * ct + cl;
                     if (pc < npts) {
-                        const size_t o = ((size_t)(4 * rb + gl) * T.n_points + pc) * 4;
+                        // quad-major, or plain columns of vld (rows 16 rb + 4 gl .. + 3)
+                        const size_t o = T.vld ? (size_t)pc * T.vld + 16 * rb + 4 * gl
+                                               : ((size_t)(4 * rb + gl) * T.n_points + pc) * 4;
                         *(f4*)((float*)T.V + o) = ac[ct];
                     }
                 }
@@ -660,7 +662,8 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
         auto phase = [&](auto Kc, int& c) {
             constexpr int K = decltype(Kc)::value;
             const int rbK = wave + kWavesKO * K;
-            const int cend = rbK / 2 < nch - 1 ? rbK / 2 : nch - 1;
+            // a full operand (T.dense) takes every chunk for every row block
+            const int cend = (!T.dense && rbK / 2 < nch - 1) ? rbK / 2 : nch - 1;
             for (; c <= cend; ++c) body(Kc, c);
             if (rbK < A.nrb) epilogue(rbK, acc[K]);
         };
@@ -701,7 +704,8 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
 }
 
 template <class P, int NT, int RBW>
-hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
+hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
+                     const double* amax)
 {
     KArgs A;
     A.kp = M.kp;
@@ -712,7 +716,7 @@ hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const voi
     A.a = M.a;
     A.A0 = A0;
     A.A1 = A1;
-    A.amax = M.amax;
+    A.amax = amax ? amax : M.amax;
     {
         int e;
         frexp(M.k.signal_var, &e);
@@ -728,14 +732,15 @@ hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const voi
 }
 
 template <class P>
-hipError_t launch_ko_split(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1)
+hipError_t launch_ko_split(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
+                           const double* amax = nullptr)
 {
     switch ((M.nrb + kWavesKO - 1) / kWavesKO) {
-    case 1: return launch_ko<P, 64, 1>(M, t, s, A0, A1);
-    case 2: return launch_ko<P, 64, 2>(M, t, s, A0, A1);
-    case 3: return launch_ko<P, 64, 3>(M, t, s, A0, A1);
-    case 4: return launch_ko<P, 64, 4>(M, t, s, A0, A1);
-    default: return launch_ko<P, 32, 8>(M, t, s, A0, A1);
+    case 1: return launch_ko<P, 64, 1>(M, t, s, A0, A1, amax);
+    case 2: return launch_ko<P, 64, 2>(M, t, s, A0, A1, amax);
+    case 3: return launch_ko<P, 64, 3>(M, t, s, A0, A1, amax);
+    case 4: return launch_ko<P, 64, 4>(M, t, s, A0, A1, amax);
+    default: return launch_ko<P, 32, 8>(M, t, s, A0, A1, amax);
     }
 }
 
@@ -862,6 +867,15 @@ hipError_t launch_posterior_operand(const Model& M, int prec, const PostTask& t,
     if (prec == LCP_FP64) return launch_t<P64, 16, 1>(M, t, s, A0, nullptr);
     if (prec == LCP_FP32) return launch_t<P32, 32, 1>(M, t, s, A0, nullptr);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_posterior_operand_f16x3(const Model& M, const PostTask& t, const void* Hhi, const void* Hlo,
+                                          const double* amax, hipStream_t s)
+{
+    if (t.n_points <= 0) return hipSuccess;
+    StageScope sc(s, t.stage);
+    if (t.group != 1) return hipErrorInvalidValue;
+    return launch_ko_split<PH3>(M, t, s, Hhi, Hlo, amax);
 }
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s)

@@ -181,6 +181,10 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
 // Value columns against another operand in the fragment order of the binary64 (prec
 // LCP_FP64) or binary32 (LCP_FP32) posterior: A0 = m_pad x m_pad in 16 x 16 x 4 fragments.
 hipError_t launch_posterior_operand(const Model& M, int prec, const PostTask& t, const void* A0, hipStream_t s);
+// The same with the FP16 split product (value columns): Hhi, Hlo = the operand times amax[1]
+// (a power of two) split into FP16 halves in 16 x 16 x 32 fragment order.
+hipError_t launch_posterior_operand_f16x3(const Model& M, const PostTask& t, const void* Hhi, const void* Hlo,
+                                          const double* amax, hipStream_t s);
 
 // ------------------------------------------------------------------- cells (K3)
 
