@@ -339,7 +339,6 @@ public:
 
 private:
     hipStream_t s_;
-    int stage_;
     int idx_;
 };
 

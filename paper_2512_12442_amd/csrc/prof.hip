@@ -35,7 +35,7 @@ hipEvent_t take_event()
 
 }  // namespace
 
-StageScope::StageScope(hipStream_t s, int stage) : s_(s), stage_(stage), idx_(-1)
+StageScope::StageScope(hipStream_t s, int stage) : s_(s), idx_(-1)
 {
     if (!g_on || !(g_mask & (1u << stage))) return;
     std::lock_guard<std::mutex> lk(g_mu);
