@@ -754,7 +754,7 @@ __global__ void __launch_bounds__(256) k_sov_select(CellTask t, int64_t ncell, c
 
 // Smooth LCP of every cell of the dense grid (work == null) or of the listed cells.
 template <int D, class T>
-__global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __restrict__ wb, int64_t ncell,
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_cells_sov(CellTask t, const double* __restrict__ wb, int64_t ncell,
                                                    const int32_t* __restrict__ work, const int64_t* __restrict__ wcount)
 {
     constexpr int N = 1 << D;
@@ -784,7 +784,7 @@ __global__ void __launch_bounds__(256) k_cells_sov(CellTask t, const double* __r
 // Gradient of gl[cell] * LCP_cell with respect to the cell's corner means (N values) and
 // the lower triangle of its corner covariance (N (N + 1) / 2, packed) -> gout[cell].
 template <int D, class T>
-__global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double* __restrict__ wb,
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) k_cells_sov_grad(CellTask t, const double* __restrict__ wb,
                                                         const double* __restrict__ gl, double* __restrict__ gout,
                                                         int64_t ncell, const int32_t* __restrict__ work,
                                                         const int64_t* __restrict__ wcount)
@@ -804,13 +804,15 @@ __global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double
             for (int i = 0; i < NO; ++i) out[i] = 0.0;
             continue;
         }
-        double md[N], Cd[N][N], C64[kTri<N>], gmu[N], gC[kTri<N>], gS[kTri<N>];
+        double gmu[N], gC[kTri<N>];
         T mt[N], C[kTri<N>], tt[N], e[N], y[N];
-        cell_factor<D>(t, sl, md, Cd);
+        {
+            double md[N], Cd[N][N];
+            cell_factor<D>(t, sl, md, Cd);
 #pragma unroll
-        for (int q = 0; q < N; ++q) mt[q] = (T)md[q];
-        pack_lower<N>(Cd, C);
-        pack_lower<N>(Cd, C64);
+            for (int q = 0; q < N; ++q) mt[q] = (T)md[q];
+            pack_lower<N>(Cd, C);
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) gmu[i] = 0.0;
 #pragma unroll
@@ -829,6 +831,14 @@ __global__ void __launch_bounds__(256) k_cells_sov_grad(CellTask t, const double
         for (int i = 0; i < N; ++i) gmu[i] *= scale;
 #pragma unroll
         for (int i = 0; i < kTri<N>; ++i) gC[i] *= scale;
+        // the binary64 factor again (bitwise the same), rather than kept live through the
+        // sample loop: the registers go to more resident waves
+        double C64[kTri<N>], gS[kTri<N>];
+        {
+            double md[N], Cd[N][N];
+            cell_factor<D>(t, sl, md, Cd);
+            pack_lower<N>(Cd, C64);
+        }
         chol_sd_rev<N>(C64, gC, gS);
 #pragma unroll
         for (int i = 0; i < N; ++i) out[i] = gmu[i];
