@@ -57,12 +57,21 @@ __device__ __forceinline__ void key_coords(const Oct& o, uint64_t key, int& leve
     }
     level = (int)(key >> 58);
     const uint64_t code = key & ((1ull << 58) - 1);
-    c[0] = c[1] = c[2] = 0;
+    // selects rather than c[a] with a run-time a, which would put c in scratch memory
+    int64_t c0 = 0, c1 = 0, c2 = 0;
     for (int j = 0; j < level; ++j) {
         const int a = kd_axis(o.D, j);
-        c[a] = 2 * c[a] + (int64_t)((code >> (level - 1 - j)) & 1);
+        const int64_t bit = (int64_t)((code >> (level - 1 - j)) & 1);
+        c0 = a == 0 ? 2 * c0 + bit : c0;
+        c1 = a == 1 ? 2 * c1 + bit : c1;
+        c2 = a == 2 ? 2 * c2 + bit : c2;
     }
+    c[0] = c0;
+    c[1] = c1;
+    c[2] = c2;
 }
+
+__device__ __forceinline__ int64_t pick3(const int64_t* c, int a) { return a == 0 ? c[0] : (a == 1 ? c[1] : c[2]); }
 
 __device__ __forceinline__ uint64_t make_key(const Oct& o, int level, const int64_t* c)
 {
@@ -71,7 +80,7 @@ __device__ __forceinline__ uint64_t make_key(const Oct& o, int level, const int6
     if (o.kd) {
         for (int j = 0; j < level; ++j) {
             const int a = kd_axis(D, j);
-            k = (k << 1) | (uint64_t)((c[a] >> (node_shift(o, level, a) - 1 - j / D)) & 1);
+            k = (k << 1) | (uint64_t)((pick3(c, a) >> (node_shift(o, level, a) - 1 - j / D)) & 1);
         }
     } else {
         for (int b = 0; b < level; ++b)
@@ -605,7 +614,7 @@ __global__ void k_emit_count(Oct o, int level, const uint64_t* __restrict__ keys
                 if (o.kd) {
                     const int a = kd_axis(o.D, level);
                     const int64_t hs = o.S0 >> node_shift(o, level + 1, a);
-                    n = 1 + ((2 * c[a] + 1) * hs < o.g.nc[a] ? 1 : 0);
+                    n = 1 + ((2 * pick3(c, a) + 1) * hs < pick3(o.g.nc, a) ? 1 : 0);
                 } else {
                     const int64_t hs = (o.S0 >> level) >> 1;
                     for (int i = 0; i < (1 << o.D); ++i) {
@@ -644,9 +653,9 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
             const int a = kd_axis(o.D, level);
             const int64_t hs = o.S0 >> node_shift(o, level + 1, a);
             for (int i = 0; i < 2; ++i) {
-                int64_t cc[3] = {c[0], c[1], c[2]};
-                cc[a] = 2 * c[a] + i;
-                if (cc[a] * hs >= o.g.nc[a]) continue;
+                const int64_t ca = 2 * pick3(c, a) + i;
+                const int64_t cc[3] = {a == 0 ? ca : c[0], a == 1 ? ca : c[1], a == 2 ? ca : c[2]};
+                if (ca * hs >= pick3(o.g.nc, a)) continue;
                 if (pos < out_cap) out[pos] = make_key(o, level + 1, cc);
                 ++pos;
             }
