@@ -78,16 +78,19 @@ __device__ __forceinline__ int sym(int d, int e)
 }
 
 // Range of the second-order model relative to phi(c): g[3], Hs[6], remainder R.
-__device__ __forceinline__ void model_range(int D, const double* g, const double* Hs, const double* h, double R,
+template <int D>
+__device__ __forceinline__ void model_range(const double* g, const double* Hs, const double* h, double R,
                                             double& lo, double& hi)
 {
     lo = -R;
     hi = R;
+#pragma unroll
     for (int d = 0; d < D; ++d) {
         double a, b;
         quad_range(g[d], Hs[sym(d, d)], h[d], a, b);
         lo += a;
         hi += b;
+#pragma unroll
         for (int e = 0; e < D; ++e) {
             if (e == d) continue;
             const double x = 0.5 * fabs(Hs[sym(d, e)]) * h[d] * h[e];
@@ -101,6 +104,7 @@ constexpr int kMom = 11;   // value, gradient (3), Hessian (6), remainder weight
 
 // One wave per box.  box: lo[D], hi[D] per box; W: column b at b * ldw; out: mu(c), mu_lo,
 // mu_hi, var_hi per box.
+template <int D>
 __global__ void __launch_bounds__(256) k_cert(KParams kp, const double* __restrict__ X, const double* __restrict__ a,
                                               int m, const double* __restrict__ W, int64_t ldw,
                                               const double* __restrict__ box, const int64_t* __restrict__ count,
@@ -111,8 +115,8 @@ __global__ void __launch_bounds__(256) k_cert(KParams kp, const double* __restri
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= n) return;   // uniform over the wave
     const int lane = threadIdx.x & 63;
-    const int D = kp.dim;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, c[3] = {0, 0, 0}, h[3] = {0, 0, 0}, H = 0.0;
+#pragma unroll
     for (int d = 0; d < D; ++d) {
         lo[d] = box[b * 2 * D + d];
         hi[d] = box[b * 2 * D + D + d];
@@ -128,6 +132,7 @@ __global__ void __launch_bounds__(256) k_cert(KParams kp, const double* __restri
     const double s5 = 2.23606797749978969640917366873;
     for (int i = lane; i < m; i += 64) {
         double t[3] = {0, 0, 0}, r2 = 0.0, e2 = 0.0;
+#pragma unroll
         for (int d = 0; d < D; ++d) {
             const double xi = X[(int64_t)i * 4 + d];
             t[d] = (c[d] - xi) * kp.inv_ell[d];
@@ -175,8 +180,8 @@ __global__ void __launch_bounds__(256) k_cert(KParams kp, const double* __restri
     if (lane != 0) return;
     const double r3 = kp.s2 * H * sqrt_nonneg(H) / 6.0;
     double mlo, mhi, nlo, nhi;
-    model_range(D, acc + 1, acc + 4, h, r3 * acc[10], mlo, mhi);
-    model_range(D, acc + kMom + 1, acc + kMom + 4, h, r3 * acc[kMom + 10], nlo, nhi);
+    model_range<D>(acc + 1, acc + 4, h, r3 * acc[10], mlo, mhi);
+    model_range<D>(acc + kMom + 1, acc + kMom + 4, h, r3 * acc[kMom + 10], nlo, nhi);
     double vhi = kp.s2 - acc[kMom] - 2.0 * nlo;
     vhi = vhi > kp.s2 ? kp.s2 : vhi;
     vhi = vhi < 0.0 ? 0.0 : vhi;
@@ -253,8 +258,12 @@ hipError_t launch_cert(const Model& M, const double* box, const int64_t* count, 
 {
     if (cap <= 0) return hipSuccess;
     StageScope sc(s, ST_BOUND);
-    hipLaunchKernelGGL(k_cert, dim3((unsigned)ceil_div(cap, 4)), dim3(256), 0, s, M.kp, M.X, M.a, M.m, W,
-                       (int64_t)M.m_pad, box, count, cap, out);
+    if (M.dim == 3)
+        hipLaunchKernelGGL(k_cert<3>, dim3((unsigned)ceil_div(cap, 4)), dim3(256), 0, s, M.kp, M.X, M.a, M.m, W,
+                           (int64_t)M.m_pad, box, count, cap, out);
+    else
+        hipLaunchKernelGGL(k_cert<2>, dim3((unsigned)ceil_div(cap, 4)), dim3(256), 0, s, M.kp, M.X, M.a, M.m, W,
+                           (int64_t)M.m_pad, box, count, cap, out);
     return hipGetLastError();
 }
 
