@@ -240,6 +240,86 @@ __global__ void __launch_bounds__(256) k_bwd_syrk(const T* __restrict__ W, const
         for (int c = 0; c < 4; ++c) G[(size_t)(j0 + ty * 4 + r) * mp + l0 + tx * 4 + c] = acc[r][c];
 }
 
+// The same partial for binary32 W and U on FP32 MFMA (16 x 16 x 4): the products of each run
+// of 256 points are summed in binary32, those sums in binary64.  A 16-point step stages the
+// block's W and U rows in LDS; wave w owns the 32 x 32 quarter (w / 2, w % 2) of the block.
+__global__ void __launch_bounds__(256) k_bwd_syrk_mfma(const float* __restrict__ W, const float* __restrict__ U,
+                                                       int64_t ldw, int64_t n, const double* __restrict__ h, int mp,
+                                                       int64_t split_pts, double* __restrict__ Gpart)
+{
+    __shared__ float As[16][68], Bs[16][68];
+    const int nb = mp / 64;
+    int rem = blockIdx.x, jb = 0;
+    while (rem >= nb - jb) { rem -= nb - jb; ++jb; }
+    const int lb = jb + rem;
+    const int j0 = jb * 64, l0 = lb * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wj = (wave >> 1) * 32, wl = (wave & 1) * 32;
+    const int64_t pbeg = (int64_t)blockIdx.y * split_pts;
+    const int64_t pend = pbeg + split_pts < n ? pbeg + split_pts : n;
+    f4 acc[2][2];
+    double dacc[2][2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            acc[t][u] = f4{0, 0, 0, 0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dacc[t][u][r] = 0.0;
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dacc[t][u][r] += (double)acc[t][u][r];
+                acc[t][u] = f4{0, 0, 0, 0};
+            }
+    };
+    const int lk = tid >> 4, lc = (tid & 15) * 4;     // loader: point row lk, columns lc .. lc + 3
+    int steps = 0;
+    for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+        const int64_t p = p0 + lk;
+        const bool live = p < pend;
+        f4 a = f4{0, 0, 0, 0}, b = f4{0, 0, 0, 0};
+        if (live) {
+            a = *(const f4*)(W + p * ldw + j0 + lc);
+            b = U ? *(const f4*)(U + p * ldw + l0 + lc) : (float)h[p] * *(const f4*)(W + p * ldw + l0 + lc);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            As[lk][lc + e] = a[e];
+            Bs[lk][lc + e] = b[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int k = kk + (lane >> 4);
+            const float av0 = As[k][wj + (lane & 15)], av1 = As[k][wj + 16 + (lane & 15)];
+            const float bv0 = Bs[k][wl + (lane & 15)], bv1 = Bs[k][wl + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av0, bv1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+        if (++steps == 16) {
+            flush();
+            steps = 0;
+        }
+    }
+    flush();
+    double* G = Gpart + (size_t)blockIdx.y * mp * mp;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                G[(size_t)(j0 + wj + 16 * t + 4 * (lane >> 4) + r) * mp + l0 + wl + 16 * u + (lane & 15)] = dacc[t][u][r];
+}
+
 // P_d partials over all (j, l): dK_d[j][l] (G[j][l] - b_j a_l).
 __global__ void __launch_bounds__(256) k_bwd_pairs(KParams kp, int m, int mp, const double* __restrict__ X,
                                                    const double* __restrict__ alpha, const double* __restrict__ b,
@@ -630,7 +710,7 @@ hipError_t bwd_tail(const Model& M, const BwdLayout& L, const BwdPts& P, int pre
             hipLaunchKernelGGL(k_bwd_syrk<double>, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
                                (const double*)W, (const double*)U, (int64_t)mp, n, gv, mp, split_pts, gpart);
         else
-            hipLaunchKernelGGL(k_bwd_syrk<float>, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_bwd_syrk_mfma, dim3(npairs_blk, (unsigned)L.nsplit), dim3(256), 0, s,
                                (const float*)W, (const float*)U, (int64_t)mp, n, gv, mp, split_pts, gpart);
     } else {
         hipError_t e = launch_fill_f64(gpart, 0.0, (int64_t)mp * mp, s);
