@@ -22,7 +22,8 @@ ORC_OK, ORC_ENOTPD, ORC_ECAP, ORC_ENOMEM = 0, 2, 3, 4
 class Model(C.Structure):
     _fields_ = [("kind", C.c_int), ("dim", C.c_int), ("m", C.c_int), ("s2", C.c_double),
                 ("ell", C.c_double * 3), ("noise", C.c_double), ("X", C.c_void_p),
-                ("L", C.c_void_p), ("a", C.c_void_p), ("A", C.c_void_p), ("muM", C.c_void_p)]
+                ("L", C.c_void_p), ("a", C.c_void_p), ("A", C.c_void_p), ("muM", C.c_void_p),
+                ("y", C.c_void_p)]
 
 
 class Grid(C.Structure):
@@ -31,22 +32,22 @@ class Grid(C.Structure):
 
 class Adapt(C.Structure):
     _fields_ = [("alpha", C.c_double), ("min_leaf", C.c_int), ("bound_at_max_depth", C.c_int),
-                ("steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int)]
+                ("steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int), ("beta", C.c_double)]
 
 
-BOUND_SEARCH, BOUND_CERTIFIED = 0, 1
+BOUND_SEARCH, BOUND_CERTIFIED, BOUND_LOCAL = 0, 1, 2
 SPLIT_OCTREE, SPLIT_KD = 0, 1
 
 
 class NodeRec(C.Structure):
     _fields_ = [("key", C.c_uint64), ("level", C.c_int32), ("n_obs", C.c_int32), ("p1", C.c_double),
                 ("p2", C.c_double), ("path", C.c_int32), ("subdivide", C.c_int32), ("gmin", C.c_double),
-                ("ub", C.c_double), ("lattice_gap", C.c_double), ("d", C.c_int64)]
+                ("ub", C.c_double), ("lattice_gap", C.c_double), ("d", C.c_int64), ("n_local", C.c_int64)]
 
 
 NODE_DTYPE = np.dtype([("key", "<u8"), ("level", "<i4"), ("n_obs", "<i4"), ("p1", "<f8"), ("p2", "<f8"),
                        ("path", "<i4"), ("subdivide", "<i4"), ("gmin", "<f8"), ("ub", "<f8"),
-                       ("lattice_gap", "<f8"), ("d", "<i8")])
+                       ("lattice_gap", "<f8"), ("d", "<i8"), ("n_local", "<i8")])
 assert NODE_DTYPE.itemsize == C.sizeof(NodeRec)
 
 
@@ -88,6 +89,8 @@ def lib():
         _lib.orc_bound_certified.argtypes = [P, P, P, P]
         _lib.orc_certified_margin.restype = C.c_double
         _lib.orc_certified_margin.argtypes = [C.c_double, C.c_double, P]
+        _lib.orc_local_posterior.restype = C.c_int64
+        _lib.orc_local_posterior.argtypes = [P, P, P, C.c_double, C.c_int, C.c_int64, P, P, P]
         _lib.orc_octree_shape.argtypes = [P, C.c_int, P, P]
         _lib.orc_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int64, P, P, C.c_int64, P, P,
                                       C.c_int64, P]
@@ -132,7 +135,7 @@ class FitModel:
                            _p(self.a))
         self.rc = rc
         self.s = Model(kind, dim, m, s2, (C.c_double * 3)(*self.ell), noise, self.X.ctypes.data,
-                       self.L.ctypes.data, self.a.ctypes.data, None, None)
+                       self.L.ctypes.data, self.a.ctypes.data, None, None, self.y.ctypes.data)
         self.kind, self.dim, self.m, self.s2, self.noise = kind, dim, m, s2, noise
         self.A = None
         self.vwidth = m
@@ -146,6 +149,7 @@ class SparseModel(FitModel):
         self.A = _f64(A_M).reshape(self.m, self.m)
         self.s.A = self.A.ctypes.data
         self.s.muM = self.y.ctypes.data
+        self.s.y = None
         self.vwidth = 3 * self.m
 
 
@@ -339,13 +343,14 @@ def octree_shape(W, min_leaf=None):
 
 
 def adaptive(M: FitModel, W, alpha=None, min_leaf=None, bound_at_max_depth=1, steps=4, cap=1 << 22,
-             bound_kind=BOUND_SEARCH, split=SPLIT_OCTREE):
+             bound_kind=BOUND_SEARCH, split=SPLIT_OCTREE, beta=6.0):
     """Alg. 1: returns (leaves, skipped, node records), each sorted by key.  With the K-D
     tree, records and skipped keys carry the depth (0 .. dim Lmax); leaves keep the octree
-    key of the finest level."""
+    key of the finest level.  BOUND_LOCAL runs the region test on the local model of
+    Sec. 5.2 (box enlarged by beta lengthscales)."""
     g = grid_of(W)
     A = Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf),
-              int(bound_at_max_depth), int(steps), int(bound_kind), int(split))
+              int(bound_at_max_depth), int(steps), int(bound_kind), int(split), float(beta))
     leaves = np.zeros(cap, np.uint64)
     skipped = np.zeros(cap, np.uint64)
     recs = np.zeros(cap, NODE_DTYPE)
@@ -354,6 +359,18 @@ def adaptive(M: FitModel, W, alpha=None, min_leaf=None, bound_at_max_depth=1, st
                             _p(skipped), cap, C.byref(ns), _p(recs), cap, C.byref(nr))
     assert rc == ORC_OK, rc
     return leaves[: nl.value].copy(), skipped[: ns.value].copy(), recs[: nr.value].copy()
+
+
+def local_posterior(M: FitModel, blo, bhi, beta, P, whole=False):
+    """Posterior of the local model M' of Sec. 5.2 for the box [blo, bhi] at points P:
+    (mean, var, |M'|)."""
+    P = _f64(P).reshape(-1, M.dim)
+    n = P.shape[0]
+    mean, var = np.zeros(n), np.zeros(n)
+    ml = lib().orc_local_posterior(C.byref(M.s), _p(_f64(blo)), _p(_f64(bhi)), float(beta), int(whole), n, _p(P),
+                                   _p(mean), _p(var))
+    assert ml >= 0, ml
+    return mean, var, int(ml)
 
 
 def lcp_leaves(M: FitModel, W, leaves, min_leaf=None):

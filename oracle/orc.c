@@ -22,9 +22,11 @@
  *    largest diagonal entry); a sample equal to the iso-value counts as crossed.
  *  - The L-BFGS-B search of Sec. 5.1 is replaced by a fixed-budget bounded search:
  *    a {lo,mid,hi}^D lattice followed by T normalised projected-gradient steps.
- *  - Alg. 1 is run on the full model F_M (no local model M'); p = alpha counts as
- *    "not larger than alpha"; a node without observations takes its side from the
- *    sign of theta - mu(box centre).
+ *  - Alg. 1 runs on the full model F_M, or (bound_kind 2) with the local model M' of
+ *    Sec. 5.2 in the region test (its box rule and per-model reading are stated at
+ *    local_build); p = alpha counts as "not larger than alpha"; a node without
+ *    observations takes its side from the sign of theta - mu(box centre) under the
+ *    model of its region test.
  *  - The certified variant of the region bound (guaranteed in exact arithmetic, which
  *    Sec. 9 leaves open) bounds mu and var over the whole box instead of searching.
  */
@@ -55,6 +57,8 @@ typedef struct {
                          a = K_MM^-1 mu_M, and A is the m x m covariance A_M of the
                          inducing values */
     const double* muM; /* sparse model only: the m inducing means mu_M */
+    const double* y;   /* exact GP: the m observed values (the local model of Sec. 5.2 refits
+                          on a subset of them); may be NULL when no local model is built */
 } orc_model;
 
 typedef struct {
@@ -71,6 +75,7 @@ typedef struct {
     int steps;              /* projected-gradient steps after the lattice */
     int bound_kind;         /* 0: bounded search (lattice + steps), 1: certified box bounds */
     int split;              /* 0: octree (Alg. 1), 1: K-D tree splitting the axes in turn (Sec. 9) */
+    double beta;            /* bound_kind 2: box enlargement of the local model, in lengthscales */
 } orc_adapt;
 
 typedef struct {
@@ -84,6 +89,7 @@ typedef struct {
     double ub;         /* 1 - B^d */
     double lattice_gap;/* second-smallest minus smallest lattice value */
     int64_t d;         /* grid vertices inside the node */
+    int64_t n_local;   /* bound_kind 2: |M'| of the local model (-1: no region test) */
 } orc_node_rec;
 
 /* ---------------------------------------------------------------- kernels -- */
@@ -1007,12 +1013,101 @@ int orc_bound(const orc_model* M, double theta, double side, const double* blo, 
               double* gmin, double* gap)
 {
     int m = M->m;
-    double* buf = (double*)malloc(sizeof(double) * ((size_t)m * 5 + (size_t)vwidth(M)));
+    double* buf = (double*)malloc(sizeof(double) * ((size_t)m * 5 + (size_t)vwidth(M) + 1));
     if (!buf) return ORC_ENOMEM;
     bound_ws B = {M, theta, buf, buf + m, buf + 5 * (size_t)m, buf + 4 * (size_t)m};
     *gmin = bound_search(&B, side, blo, bhi, steps, gap);
     free(buf);
     return ORC_OK;
+}
+
+/* ---------------------------------------------------- local model (Sec. 5.2) -- */
+/*
+ * The region test of a node may use a local model M' instead of M: the points of M inside
+ * the node box enlarged by beta lengthscales along every axis (Alg. 1 passes each child the
+ * points of its parent's set inside the child box enlarged by the distance threshold; the
+ * enlarged child box lies inside the enlarged parent box, so that is M intersected with the
+ * child's enlarged box; the root keeps all of M).  The threshold is a distance; with a
+ * lengthscale per axis it is beta ell_d along axis d (Sec. 7.3 measures it in units of ell).
+ *  - exact GP: the GP with the same hyperparameters conditioned on the local observations
+ *    alone, L' = chol(K_M'M' + noise I), a' = (K_M'M' + noise I)^-1 y_M';
+ *  - sparse model: eq. (sgp) with mu_M and A_M restricted to M' (the marginal of the
+ *    inducing values), K_M'M' + jitter I.
+ * Points keep their order in M.  With every point selected the local model is M itself,
+ * bit for bit.
+ */
+typedef struct {
+    orc_model M;
+    double *X, *L, *a, *rhs, *A;
+} orc_local;
+
+static void local_free(orc_local* P)
+{
+    free(P->X); free(P->L); free(P->a); free(P->rhs); free(P->A);
+    memset(P, 0, sizeof *P);
+}
+
+static int local_build(const orc_model* M, const double* blo, const double* bhi, double beta, int whole,
+                       orc_local* P)
+{
+    int D = M->dim, m = M->m;
+    memset(P, 0, sizeof *P);
+    int* idx = (int*)malloc(sizeof(int) * (size_t)(m > 0 ? m : 1));
+    if (!idx) return ORC_ENOMEM;
+    int n = 0;
+    for (int i = 0; i < m; ++i) {
+        int in = 1;
+        for (int d = 0; d < D && !whole; ++d) {
+            double xi = M->X[(int64_t)i * D + d];
+            double r = beta * M->ell[d];
+            if (!(xi >= blo[d] - r && xi <= bhi[d] + r)) in = 0;
+        }
+        if (in) idx[n++] = i;
+    }
+    const double* src = M->A ? M->muM : M->y;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    P->X = (double*)malloc(sizeof(double) * nn * D);
+    P->L = (double*)malloc(sizeof(double) * nn * nn);
+    P->a = (double*)malloc(sizeof(double) * nn);
+    P->rhs = (double*)malloc(sizeof(double) * nn);
+    if (M->A) P->A = (double*)malloc(sizeof(double) * nn * nn);
+    if (!src || !P->X || !P->L || !P->a || !P->rhs || (M->A && !P->A)) {
+        free(idx);
+        local_free(P);
+        return src ? ORC_ENOMEM : ORC_ENOTPD;
+    }
+    for (int j = 0; j < n; ++j) {
+        for (int d = 0; d < D; ++d) P->X[(int64_t)j * D + d] = M->X[(int64_t)idx[j] * D + d];
+        P->rhs[j] = src[idx[j]];
+        if (M->A)
+            for (int k = 0; k < n; ++k) P->A[(int64_t)j * n + k] = M->A[(int64_t)idx[j] * m + idx[k]];
+    }
+    free(idx);
+    int rc = n > 0 ? orc_fit(M->kind, D, M->s2, M->ell, M->noise, n, P->X, P->rhs, P->L, P->a) : ORC_OK;
+    if (rc != ORC_OK) { local_free(P); return rc; }
+    P->M = *M;
+    P->M.m = n;
+    P->M.X = P->X;
+    P->M.L = P->L;
+    P->M.a = P->a;
+    P->M.A = P->A;
+    P->M.muM = M->A ? P->rhs : NULL;
+    P->M.y = M->A ? NULL : P->rhs;
+    return ORC_OK;
+}
+
+/* Posterior of the local model of the box [blo, bhi] at n points; returns |M'| (or a
+ * negative status). */
+int64_t orc_local_posterior(const orc_model* M, const double* blo, const double* bhi, double beta, int whole,
+                            int64_t n, const double* P, double* mean, double* var)
+{
+    orc_local LM;
+    int rc = local_build(M, blo, bhi, beta, whole, &LM);
+    if (rc != ORC_OK) return -rc;
+    rc = orc_posterior(&LM.M, n, P, mean, var, NULL);
+    int64_t ml = LM.M.m;
+    local_free(&LM);
+    return rc == ORC_OK ? ml : -rc;
 }
 
 /* ------------------------------------------ certified region bound -- */
@@ -1269,6 +1364,7 @@ typedef struct {
     int Lmax;            /* octree levels below the root */
     int kd;              /* K-D tree: depths 0 .. D Lmax */
     int Ldepth;          /* deepest level: Lmax (octree) or D Lmax (K-D tree) */
+    int rc;              /* first failure of a local model fit */
     omp_lock_t lock;
     uint64_t* leaves; int64_t leaf_cap; int64_t n_leaves;
     uint64_t* skipped; int64_t skip_cap; int64_t n_skipped;
@@ -1308,6 +1404,7 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
     rec.gmin = NAN;
     rec.ub = NAN;
     rec.lattice_gap = NAN;
+    rec.n_local = -1;
 
     int subdivide = 0;
     if (level == T->Ldepth && !T->A->bound_at_max_depth) {
@@ -1336,14 +1433,28 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
             rec.path = 0;
             subdivide = 1;
         } else {
+            /* the region test runs on M, or on the local model M' of Sec. 5.2 */
+            orc_local LM;
+            const orc_model* Mb = M;
+            if (T->A->bound_kind == 2) {
+                int rc = local_build(M, blo, bhi, T->A->beta, level == 0, &LM);
+                if (rc != ORC_OK) {
+                    omp_set_lock(&T->lock);
+                    if (!T->rc) T->rc = rc;
+                    omp_unset_lock(&T->lock);
+                    return;
+                }
+                Mb = &LM.M;
+                rec.n_local = Mb->m;
+            }
             double side;
             if (nobs > 0) {
                 side = (p2 <= alpha) ? 1.0 : -1.0;
             } else {
                 double xc[3], mu, var;
-                double* kb = (double*)malloc(sizeof(double) * ((size_t)M->m + (size_t)vwidth(M)));
+                double* kb = (double*)malloc(sizeof(double) * ((size_t)Mb->m + (size_t)vwidth(Mb) + 1));
                 for (int d = 0; d < D; ++d) xc[d] = 0.5 * (blo[d] + bhi[d]);
-                posterior_point(M, xc, &mu, &var, kb, kb + M->m);
+                posterior_point(Mb, xc, &mu, &var, kb, kb + Mb->m);
                 free(kb);
                 side = (mu < T->theta) ? 1.0 : -1.0;
             }
@@ -1354,9 +1465,10 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
                 rec.gmin = orc_certified_margin(side, T->theta, cb);
             } else {
                 double gap;
-                orc_bound(M, T->theta, side, blo, bhi, T->A->steps, &rec.gmin, &gap);
+                orc_bound(Mb, T->theta, side, blo, bhi, T->A->steps, &rec.gmin, &gap);
                 rec.lattice_gap = gap;
             }
+            if (Mb != M) local_free(&LM);
             rec.ub = orc_upper_bound(rec.gmin, d_pts);
             subdivide = rec.ub > alpha;
         }
@@ -1490,6 +1602,7 @@ int orc_adaptive(const orc_model* M, const orc_grid* G, double theta, const orc_
     *n_skipped = T.n_skipped;
     if (n_recs) *n_recs = T.n_recs;
     free(qlo); free(qhi); free(mu); free(var);
+    if (T.rc) return T.rc;
     if (T.n_leaves > leaf_cap || T.n_skipped > skip_cap || (recs && T.n_recs > rec_cap)) return ORC_ECAP;
     return ORC_OK;
 }
