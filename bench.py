@@ -204,8 +204,11 @@ def main():
     ap.add_argument("--workload", default="trig128", choices=["trig128", "sgpr500", "local_blocks", "grad96"],
                     help="trig128: the headline adaptive LCP; local_blocks: batched local GP models")
     ap.add_argument("--blocks", type=int, default=256, help="number of models for --workload local_blocks")
-    ap.add_argument("--bound", default="search", choices=["search", "certified"],
-                    help="region bound of the octree query: the paper's search, or certified box bounds")
+    ap.add_argument("--bound", default="search", choices=["search", "certified", "local"],
+                    help="region bound of the octree query: the paper's search on the full model, certified "
+                         "box bounds, or the search on per-node local models (Sec. 5.2)")
+    ap.add_argument("--beta", type=float, default=6.0,
+                    help="--bound local: box enlargement of the local models in lengthscales")
     ap.add_argument("--split", default="octree", choices=["octree", "kd"],
                     help="subdivision of the adaptive query: the paper's octree, or a K-D tree")
     args = ap.parse_args()
@@ -245,8 +248,9 @@ def main():
               f"s2=1e-3, noise 1e-5, theta=median(y), alpha=1e-3, min leaf 4^3, N_s=1600")
     grid = lcp.grid_of(W)
     adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4,
-                         bound_kind=lcp.BOUND_CERTIFIED if args.bound == "certified" else lcp.BOUND_SEARCH,
-                         split=lcp.SPLIT_KD if args.split == "kd" else lcp.SPLIT_OCTREE)
+                         bound_kind={"search": lcp.BOUND_SEARCH, "certified": lcp.BOUND_CERTIFIED,
+                                     "local": lcp.BOUND_LOCAL}[args.bound],
+                         split=lcp.SPLIT_KD if args.split == "kd" else lcp.SPLIT_OCTREE, beta=args.beta)
     zb = torch.as_tensor(W.zbank, device=dev)
     nvert = W.n_vertices
 
@@ -371,6 +375,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha,
                    "precision": args.prec, "region_bound": args.bound, "subdivision": args.split,
+                   **({"local_beta": args.beta} if args.bound == "local" else {}),
                    "parallelism": "1 GPU"},
         "dense_fp64_ms_per_step": dense_ms,
         "dense_fp64_pts_per_s": (nvert / (dense_ms * 1e-3)) if dense_ms else None,

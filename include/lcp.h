@@ -79,6 +79,8 @@ typedef struct {
     int descent_steps;       /* projected-gradient steps of the bound search after the 3^D lattice, 0..16 */
     int bound_kind;          /* lcp_bound_kind (0 = the paper's search) */
     int split;               /* lcp_split (0 = the octree of Alg. 1) */
+    double beta;             /* LCP_BOUND_LOCAL only: box enlargement of the local model, in
+                                lengthscales per axis, finite and >= 0 (Sec. 7.3 recommends 6) */
 } lcp_adapt;
 
 typedef enum {
@@ -92,10 +94,17 @@ typedef enum {
 typedef enum {
     LCP_BOUND_SEARCH = 0,    /* B from a bounded search of F_M over the node (Sec. 5.1; the paper's
                                 L-BFGS-B replaced by the 3^D lattice and descent_steps steps) */
-    LCP_BOUND_CERTIFIED = 1  /* B from certified box bounds of mean and variance (lcp_bound_certified):
+    LCP_BOUND_CERTIFIED = 1, /* B from certified box bounds of mean and variance (lcp_bound_certified):
                                 a node is skipped only if every point of it satisfies the bound, the
                                 guarantee Sec. 9 leaves open; more nodes are refined than with the
                                 search, and every leaf of the search is also a leaf here */
+    LCP_BOUND_LOCAL = 2      /* the search of LCP_BOUND_SEARCH on the local model M' of Sec. 5.2 (Alg. 1):
+                                the GP conditioned only on the observations inside the node box
+                                enlarged by beta * lengthscale_d along axis d (the root keeps all),
+                                factored per node in binary64.  An approximation of F_M that
+                                approaches it as beta grows.  Exact-GP models only (a sparse model
+                                does not keep A_M): LCP_EINVAL otherwise.  A node whose local factor
+                                is not positive definite is refined */
 } lcp_bound_kind;
 
 typedef enum {
@@ -198,12 +207,13 @@ int lcp_dense(const lcp_model* model, const lcp_grid* grid, double theta, const 
               float* lcp, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * lcp_adaptive -- Alg. 1 (octree adaptive query) on the full model followed by the
+ * lcp_adaptive -- Alg. 1 (octree adaptive query) on the full model (or its local models) followed by the
  * reconstruction of Sec. 5.3's last paragraph: cells inside the emitted nodes get the
  * same Monte Carlo LCP as lcp_dense (same precision, same z-bank); all other cells get 0.
  * The region test (preliminary decision on the observations inside the closed node box,
- * then the bound 1 - B^d of eq. (upper_bound) with B from a bounded search of F_M, or from
- * certified box bounds when adapt->bound_kind is LCP_BOUND_CERTIFIED) runs in binary64
+ * then the bound 1 - B^d of eq. (upper_bound) with B from a bounded search of F_M, from
+ * certified box bounds when adapt->bound_kind is LCP_BOUND_CERTIFIED, or from the search on
+ * the node's local model when it is LCP_BOUND_LOCAL) runs in binary64
  * regardless of `prec`.
  *   lcp          prod(npts - 1) cells (binary32)
  *   leaves       leaf_cap keys of the emitted nodes, key = level << 58 | Morton(node), ascending

@@ -1436,19 +1436,25 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
             /* the region test runs on M, or on the local model M' of Sec. 5.2 */
             orc_local LM;
             const orc_model* Mb = M;
+            int local_failed = 0;
             if (T->A->bound_kind == 2) {
                 int rc = local_build(M, blo, bhi, T->A->beta, level == 0, &LM);
-                if (rc != ORC_OK) {
+                if (rc == ORC_ENOTPD) {
+                    local_failed = 1;   /* no local model, no bound: the node is refined */
+                } else if (rc != ORC_OK) {
                     omp_set_lock(&T->lock);
                     if (!T->rc) T->rc = rc;
                     omp_unset_lock(&T->lock);
                     return;
+                } else {
+                    Mb = &LM.M;
+                    rec.n_local = Mb->m;
                 }
-                Mb = &LM.M;
-                rec.n_local = Mb->m;
             }
             double side;
-            if (nobs > 0) {
+            if (local_failed) {
+                side = (nobs > 0 && p2 <= alpha) ? 1.0 : -1.0;
+            } else if (nobs > 0) {
                 side = (p2 <= alpha) ? 1.0 : -1.0;
             } else {
                 double xc[3], mu, var;
@@ -1459,7 +1465,9 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
                 side = (mu < T->theta) ? 1.0 : -1.0;
             }
             rec.path = side > 0 ? 1 : 2;
-            if (T->A->bound_kind == 1) {
+            if (local_failed) {
+                rec.gmin = -INFINITY;
+            } else if (T->A->bound_kind == 1) {
                 double cb[4];
                 orc_bound_certified(M, blo, bhi, cb);
                 rec.gmin = orc_certified_margin(side, T->theta, cb);

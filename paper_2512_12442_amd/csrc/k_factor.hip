@@ -573,6 +573,8 @@ static double* ybuf(const Model& M)
     return (double*)((char*)M.a + align256(sizeof(double) * M.m_pad));
 }
 
+const double* model_values(const Model& M) { return ybuf(M); }
+
 hipError_t launch_factor(Model& M, const double* X, const double* y, hipStream_t s)
 {
     carve(M, (char*)M.X);

@@ -757,6 +757,386 @@ inline unsigned gsz(int64_t n, int per)
     return (unsigned)b;
 }
 
+// ------------------------------------------------------- local model bound (Sec. 5.2)
+//
+// Region test on the local model M': the observations inside the node box enlarged by
+// beta lengthscales per axis (the root keeps all of them), conditioned on alone.  One
+// work-group per bound node (persistent over the level's bound list) gathers M' in its
+// order in M, builds K' + noise I in its own slot, factors it (blocked Cholesky, 32-wide
+// panels), and runs the search of the full-model path: the {lo, mid, hi}^D lattice (lowest
+// index wins ties), then the projected steps.  Every value comes from forward solves only:
+// with w = L'^-1 y', v = L'^-1 k(x) and u_d = L'^-1 dk(x)/dx_d,
+//   mu = v.w,  var = s2 - |v|^2,  dmu_d = u_d.w,  dvar_d = -2 v.u_d.
+// A factorisation that fails (pivot at or below m' eps (s2 + noise)) gives no bound: the
+// node is refined.
+constexpr int kLocB = 32;        // panel width; also the most right-hand sides per solve
+constexpr int kLocSlots = 768;   // work-groups of k_local_bound, one slot each
+
+struct LocalBufs {
+    KParams kp;
+    const double* X;     // m_pad x 4
+    const double* y;     // m observed values
+    int m;
+    int ld;              // slot matrix leading dimension (m_pad of the model)
+    double noise;
+    double piv_scale;    // eps (s2 + noise); the pivot floor is m' piv_scale
+    double rad[3];       // beta ell_d
+    double* slots;       // kLocSlots x (ld ld + ld kLocB) doubles
+};
+
+__host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (size_t)ld * ld + (size_t)ld * kLocB; }
+
+// Forward solve L V = V for columns [0, R) of V (rows [0, n)), L lower row-major in Lm.
+__device__ void local_fsolve(const double* __restrict__ Lm, double* __restrict__ V, int ld, int n, int R,
+                             double (*ta)[kLocB + 1], double (*tb)[kLocB + 1])
+{
+    const int tid = threadIdx.x;
+    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    for (int r0 = 0; r0 < n; r0 += kLocB) {
+        const int nb = min(kLocB, n - r0);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j0 = 0; j0 < r0; j0 += kLocB) {
+            for (int t = tid; t < kLocB * kLocB; t += 256) {
+                const int a = t >> 5, b = t & 31;
+                ta[a][b] = a < nb ? Lm[(size_t)(r0 + a) * ld + j0 + b] : 0.0;
+                tb[a][b] = b < R ? V[(size_t)(j0 + a) * kLocB + b] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll 8
+            for (int l = 0; l < kLocB; ++l) {
+                const double x = ta[r][l];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[l][c4 + q], acc[q]);
+            }
+            __syncthreads();
+        }
+        // block right-hand sides minus the sums, then the diagonal block
+        for (int t = tid; t < kLocB * kLocB; t += 256) {
+            const int a = t >> 5, b = t & 31;
+            ta[a][b] = (a < nb && b <= a) ? Lm[(size_t)(r0 + a) * ld + r0 + b] : 0.0;
+        }
+        if (r < nb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                tb[r][c4 + q] = c4 + q < R ? V[(size_t)(r0 + r) * kLocB + c4 + q] - acc[q] : 0.0;
+        __syncthreads();
+        if (tid < R) {
+            for (int a = 0; a < nb; ++a) {
+                double s = tb[a][tid];
+                for (int l = 0; l < a; ++l) s = fma(-ta[a][l], tb[l][tid], s);
+                tb[a][tid] = s / ta[a][a];
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < nb * kLocB; t += 256) {
+            const int a = t >> 5, b = t & 31;
+            if (b < R) V[(size_t)(r0 + a) * kLocB + b] = tb[a][b];
+        }
+        __syncthreads();
+    }
+}
+
+// Column sums over rows [0, n): out[c] = sum_i V[i][c] * (w ? w[i] : V[i][c0]) for c < R.
+__device__ void local_colsum(const double* __restrict__ V, const double* __restrict__ w, int c0, int n, int R,
+                             double (*red)[kLocB + 1], double* __restrict__ out)
+{
+    const int tid = threadIdx.x, c = tid & 31, g = tid >> 5;
+    double s = 0.0;
+    if (c < R)
+        for (int i = g; i < n; i += 8) {
+            const double v = V[(size_t)i * kLocB + c];
+            s = fma(v, w ? w[i] : V[(size_t)i * kLocB + c0], s);
+        }
+    red[g][c] = s;
+    __syncthreads();
+    if (tid < R) {
+        double t = 0.0;
+        for (int k = 0; k < 8; ++k) t += red[k][tid];
+        out[tid] = t;
+    }
+    __syncthreads();
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ path, BoundBufs B, LocalBufs Lb,
+                                                     int32_t* __restrict__ sub)
+{
+    __shared__ double xs[kMaxM * D];
+    __shared__ double wv[kMaxM];
+    __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1];
+    __shared__ double red[8][kLocB + 1];
+    __shared__ double sums[4][kLocB];
+    __shared__ double xcur[3];
+    __shared__ int wcnt[4];
+    __shared__ int state;            // 0 searching, 1 decided
+    __shared__ int fail;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ld = Lb.ld;
+    double* Lm = Lb.slots + (size_t)blockIdx.x * local_slot_doubles(ld);
+    double* V = Lm + (size_t)ld * ld;
+    const int64_t nb_nodes = B.cnt[0];
+    const int npt = D == 3 ? 27 : 9;
+    const double s2 = Lb.kp.s2;
+    for (int64_t b = blockIdx.x; b < nb_nodes; b += gridDim.x) {
+        const int32_t f = B.bnode[b];
+        int lv;
+        int64_t c[3], clo[3], chi[3], dp;
+        double blo[3], bhi[3];
+        key_coords(o, keys[f], lv, c);
+        node_box(o, level, c, clo, chi, blo, bhi, &dp);
+        // M': order-preserving selection, coordinates to LDS, values to column 0 of V
+        int n = 0;
+        for (int i0 = 0; i0 < Lb.m; i0 += 256) {
+            const int i = i0 + tid;
+            bool in = i < Lb.m;
+            double xi[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                xi[d] = in ? Lb.X[(size_t)i * 4 + d] : 0.0;
+                if (level > 0) in = in && xi[d] >= blo[d] - Lb.rad[d] && xi[d] <= bhi[d] + Lb.rad[d];
+            }
+            const unsigned long long bal = __ballot(in);
+            if (lane == 0) wcnt[wave] = __popcll(bal);
+            __syncthreads();
+            int off = n;
+            for (int w = 0; w < wave; ++w) off += wcnt[w];
+            const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+            if (in) {
+                const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
+#pragma unroll
+                for (int d = 0; d < D; ++d) xs[pos * D + d] = xi[d];
+                V[(size_t)pos * kLocB] = Lb.y[i];
+            }
+            __syncthreads();
+            n += tot;
+        }
+        // K' + noise I, lower triangle
+        for (int64_t t = tid; t < (int64_t)n * n; t += 256) {
+            const int i = (int)(t / n), j = (int)(t % n);
+            if (j > i) continue;
+            double r2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const double u = (xs[i * D + d] - xs[j * D + d]) * Lb.kp.inv_ell[d];
+                r2 = fma(u, u, r2);
+            }
+            Lm[(size_t)i * ld + j] = kernel_val(Lb.kp, r2) + (i == j ? Lb.noise : 0.0);
+        }
+        if (tid == 0) {
+            fail = 0;
+            state = 0;
+        }
+        __syncthreads();
+        // blocked Cholesky, lower, in place
+        const double piv_min = (double)n * Lb.piv_scale;
+        for (int k0 = 0; k0 < n && !fail; k0 += kLocB) {
+            const int nb = min(kLocB, n - k0);
+            for (int t = tid; t < kLocB * kLocB; t += 256) {
+                const int a = t >> 5, bb = t & 31;
+                ta[a][bb] = (a < nb && bb <= a) ? Lm[(size_t)(k0 + a) * ld + k0 + bb] : 0.0;
+            }
+            __syncthreads();
+            for (int j = 0; j < nb; ++j) {
+                const double piv = ta[j][j];
+                if (!(piv > piv_min)) {
+                    if (tid == 0) fail = 1;
+                    break;
+                }
+                const double ljj = sqrt(piv);
+                __syncthreads();
+                if (tid == j) ta[j][j] = ljj;
+                if (tid > j && tid < nb) ta[tid][j] /= ljj;
+                __syncthreads();
+                if (tid > j && tid < nb)
+                    for (int cc = j + 1; cc <= tid; ++cc) ta[tid][cc] = fma(-ta[tid][j], ta[cc][j], ta[tid][cc]);
+                __syncthreads();
+            }
+            __syncthreads();
+            if (fail) break;
+            for (int t = tid; t < nb * kLocB; t += 256) {
+                const int a = t >> 5, bb = t & 31;
+                if (bb <= a) Lm[(size_t)(k0 + a) * ld + k0 + bb] = ta[a][bb];
+            }
+            // panel: each row below solves x L_kk^T = a in place (the row stays in this thread)
+            for (int i = k0 + nb + tid; i < n; i += 256) {
+                double* row = Lm + (size_t)i * ld + k0;
+                for (int l = 0; l < nb; ++l) {
+                    double sacc = row[l];
+                    for (int q = 0; q < l; ++q) sacc = fma(-row[q], ta[l][q], sacc);
+                    row[l] = sacc / ta[l][l];
+                }
+            }
+            __syncthreads();
+            // trailing update of the lower triangle: A_ij -= L_ik L_jk^T
+            const int t0 = k0 + nb;
+            const int T = (n - t0 + kLocB - 1) / kLocB;
+            const int r = tid >> 3, c4 = (tid & 7) * 4;
+            for (int tt = 0; tt < T * (T + 1) / 2; ++tt) {
+                int ib = 0, rem = tt;
+                while (rem > ib) { rem -= ib + 1; ++ib; }
+                const int jb = rem;
+                const int ri = t0 + ib * kLocB, cj = t0 + jb * kLocB;
+                for (int t = tid; t < kLocB * kLocB; t += 256) {
+                    const int a = t >> 5, bb = t & 31;
+                    ta[a][bb] = ri + a < n ? Lm[(size_t)(ri + a) * ld + k0 + bb] : 0.0;
+                    tb[a][bb] = cj + a < n ? Lm[(size_t)(cj + a) * ld + k0 + bb] : 0.0;
+                }
+                __syncthreads();
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                for (int l = 0; l < kLocB; ++l) {
+                    const double x = ta[r][l];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[c4 + q][l], acc[q]);
+                }
+                if (ri + r < n)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int col = cj + c4 + q;
+                        if (col < n && (ib > jb || c4 + q <= r)) Lm[(size_t)(ri + r) * ld + col] -= acc[q];
+                    }
+                __syncthreads();
+            }
+        }
+        const int p = path[f];
+        double side = p == 1 ? 1.0 : -1.0;
+        double gmin = -__builtin_inf();
+        if (!fail) {
+            // lattice: column 0 = y', columns 1 .. npt = k(lattice point)
+            for (int t = tid; t < n * npt; t += 256) {
+                const int i = t / npt, q = t % npt;
+                double x[3];
+                lattice_point(o, blo, bhi, q, x);
+                double r2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const double u = (x[d] - xs[i * D + d]) * Lb.kp.inv_ell[d];
+                    r2 = fma(u, u, r2);
+                }
+                V[(size_t)i * kLocB + 1 + q] = kernel_val(Lb.kp, r2);
+            }
+            __syncthreads();
+            local_fsolve(Lm, V, ld, n, 1 + npt, ta, tb);
+            for (int i = tid; i < n; i += 256) wv[i] = V[(size_t)i * kLocB];
+            __syncthreads();
+            local_colsum(V, wv, 0, n, 1 + npt, red, sums[0]);      // means
+            // |v|^2 per column
+            {
+                const int cc = tid & 31, g = tid >> 5;
+                double sacc = 0.0;
+                if (cc < 1 + npt)
+                    for (int i = g; i < n; i += 8) {
+                        const double v = V[(size_t)i * kLocB + cc];
+                        sacc = fma(v, v, sacc);
+                    }
+                red[g][cc] = sacc;
+                __syncthreads();
+                if (tid < 1 + npt) {
+                    double t = 0.0;
+                    for (int k = 0; k < 8; ++k) t += red[k][tid];
+                    sums[1][tid] = t;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                const int ic = (npt - 1) / 2;
+                if (p != 1 && p != 2) {
+                    const double mc = sums[0][1 + ic];
+                    side = mc < o.theta ? 1.0 : -1.0;
+                }
+                double best = __builtin_inf();
+                int ib = 0;
+                for (int q = 0; q < npt; ++q) {
+                    const double var = s2 - sums[1][1 + q];
+                    const double g = margin(side, o.theta, sums[0][1 + q], var > 0.0 ? var : 0.0);
+                    if (g < best) {
+                        best = g;
+                        ib = q;
+                    }
+                }
+                gmin = best;
+                double x[3];
+                lattice_point(o, blo, bhi, ib, x);
+                for (int d = 0; d < 3; ++d) xcur[d] = x[d];
+                red[0][0] = side;
+                red[0][1] = gmin;
+                state = (upper_bound(gmin, dp) > o.alpha || o.steps == 0) ? 1 : 0;
+            }
+            __syncthreads();
+            side = red[0][0];
+            gmin = red[0][1];
+            __syncthreads();
+            // projected steps: value and gradient at x_k, then the step; x_k (k >= 1) enters the minimum
+            double eta = 0.5;
+            for (int k = 0; k <= o.steps && !state; ++k) {
+                const bool last = k == o.steps;
+                const int R = last ? 1 : 1 + D;
+                for (int i = tid; i < n; i += 256) {
+                    double z[D], r2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        z[d] = xcur[d] - xs[i * D + d];
+                        const double u = z[d] * Lb.kp.inv_ell[d];
+                        r2 = fma(u, u, r2);
+                    }
+                    double kv, fv;
+                    kernel_val_dfac(Lb.kp, r2, &kv, &fv);
+                    V[(size_t)i * kLocB] = kv;
+                    if (!last)
+#pragma unroll
+                        for (int d = 0; d < D; ++d)
+                            V[(size_t)i * kLocB + 1 + d] = fv * z[d] * Lb.kp.inv_ell[d] * Lb.kp.inv_ell[d];
+                }
+                __syncthreads();
+                local_fsolve(Lm, V, ld, n, R, ta, tb);
+                local_colsum(V, wv, 0, n, R, red, sums[0]);       // mu, dmu_d
+                local_colsum(V, nullptr, 0, n, R, red, sums[1]);  // |v|^2, v.u_d
+                if (tid == 0) {
+                    const double mu = sums[0][0];
+                    const double vr = s2 - sums[1][0];
+                    const double var = vr > 0.0 ? vr : 0.0;
+                    const double g = margin(side, o.theta, mu, var);
+                    if (k >= 1 && g < gmin) gmin = g;
+                    int stop = last || !(var > 0.0);
+                    if (!stop) {
+                        const double sd = sqrt(var);
+                        double u[3], nrm = 0.0;
+                        for (int a = 0; a < D; ++a) {
+                            const double dsd = -2.0 * sums[1][1 + a] / (2.0 * sd);
+                            const double gr = side * (-sums[0][1 + a] * sd - (o.theta - mu) * dsd) / var;
+                            u[a] = (bhi[a] - blo[a]) * gr;
+                            nrm += u[a] * u[a];
+                        }
+                        nrm = sqrt(nrm);
+                        if (!(nrm > 0.0) || !isfinite(nrm)) {
+                            stop = 1;
+                        } else {
+                            for (int a = 0; a < D; ++a) {
+                                const double w = bhi[a] - blo[a];
+                                const double xn = xcur[a] - eta * w * u[a] / nrm;
+                                xcur[a] = xn < blo[a] ? blo[a] : (xn > bhi[a] ? bhi[a] : xn);
+                            }
+                        }
+                    }
+                    red[0][1] = gmin;
+                    state = (stop || upper_bound(gmin, dp) > o.alpha) ? 1 : 0;
+                }
+                __syncthreads();
+                gmin = red[0][1];
+                eta *= 0.5;
+                __syncthreads();
+            }
+        }
+        if (tid == 0) {
+            B.side[b] = side;
+            B.gmin[b] = gmin;
+            sub[f] = upper_bound(gmin, dp) > o.alpha ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // Workspace layout of lcp_adaptive.
@@ -767,6 +1147,7 @@ struct AdaptLayout {
     size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_lcnt, o_loff;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
+    size_t o_loc;                        // local-model bound only: per-work-group slots
     int64_t capF, nv;
 };
 
@@ -859,6 +1240,7 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         L.o_box = take(8 * 2 * (size_t)D * capF);
         L.o_cert = take(32 * (size_t)capF);
     }
+    if (bound_kind == LCP_BOUND_LOCAL) L.o_loc = take(8 * local_slot_doubles(M.m_pad) * kLocSlots);
     L.total = o;
     L.capF = capF;
     L.nv = nv;
@@ -878,6 +1260,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
 {
     int64_t caps[24], nodes[72];
     const bool cert = A.bound_kind == LCP_BOUND_CERTIFIED;
+    const bool local = A.bound_kind == LCP_BOUND_LOCAL;
     const int kd = A.split == LCP_SPLIT_KD;
     const int Ldepth = kd ? g.dim * Lmax : Lmax;
     AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, kd, caps, nodes);
@@ -992,7 +1375,26 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             t.stage = ST_BOUND;
             return launch_posterior(M, LCP_FP64, t, s);
         };
-        if (cert) {
+        if (local) {
+            // the search on each node's local model, one work-group per node
+            LocalBufs lb{};
+            lb.kp = M.kp;
+            lb.X = M.X;
+            lb.y = model_values(M);
+            lb.m = M.m;
+            lb.ld = M.m_pad;
+            lb.noise = M.k.noise_var;
+            lb.piv_scale = 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var);
+            for (int d = 0; d < 3; ++d) lb.rad[d] = d < D ? A.beta * M.k.lengthscale[d] : 0.0;
+            lb.slots = (double*)P(L.o_loc);
+            StageScope sc(s, ST_BOUND);
+            if (D == 3)
+                hipLaunchKernelGGL(k_local_bound<3>, dim3(kLocSlots), dim3(256), 0, s, o, l, kin, path, B, lb, sub);
+            else
+                hipLaunchKernelGGL(k_local_bound<2>, dim3(kLocSlots), dim3(256), 0, s, o, l, kin, path, B, lb, sub);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        } else if (cert) {
             // certified box bounds: w = Q k(c) on MFMA, moments per node, decision
             e = launch_cert_w(M, certF64, B.cpts, B.cnt + 0, cap, certW, B.cmean, B.cvar, s);
             if (e != hipSuccess) return e;

@@ -153,7 +153,7 @@ void octree_shape(const GridP& g, int min_leaf, int64_t* S0, int* Lmax)
     *Lmax = l;
 }
 
-int check_adapt(const lcp_adapt* A)
+int check_adapt(const Model& M, const lcp_adapt* A)
 {
     if (!A) return fail(LCP_EINVAL, "adapt is NULL");
     if (!(A->alpha > 0.0 && A->alpha < 0.5)) return fail(LCP_EINVAL, "alpha must lie in (0, 0.5)");
@@ -162,8 +162,12 @@ int check_adapt(const lcp_adapt* A)
     if (A->bound_at_max_depth != 0 && A->bound_at_max_depth != 1)
         return fail(LCP_EINVAL, "bound_at_max_depth must be 0 or 1");
     if (A->descent_steps < 0 || A->descent_steps > 16) return fail(LCP_EINVAL, "descent_steps must be in 0..16");
-    if (A->bound_kind != LCP_BOUND_SEARCH && A->bound_kind != LCP_BOUND_CERTIFIED)
-        return fail(LCP_EINVAL, "bound_kind must be LCP_BOUND_SEARCH or LCP_BOUND_CERTIFIED");
+    if (A->bound_kind != LCP_BOUND_SEARCH && A->bound_kind != LCP_BOUND_CERTIFIED && A->bound_kind != LCP_BOUND_LOCAL)
+        return fail(LCP_EINVAL, "bound_kind must be LCP_BOUND_SEARCH, LCP_BOUND_CERTIFIED or LCP_BOUND_LOCAL");
+    if (A->bound_kind == LCP_BOUND_LOCAL) {
+        if (!(is_finite(A->beta) && A->beta >= 0.0)) return fail(LCP_EINVAL, "beta must be finite and >= 0");
+        if (M.sparse) return fail(LCP_EINVAL, "LCP_BOUND_LOCAL needs an exact-GP model (a sparse model keeps no A_M)");
+    }
     if (A->split != LCP_SPLIT_OCTREE && A->split != LCP_SPLIT_KD)
         return fail(LCP_EINVAL, "split must be LCP_SPLIT_OCTREE or LCP_SPLIT_KD");
     return LCP_OK;
@@ -305,7 +309,7 @@ int lcp_adaptive_workspace(const lcp_model* M, const lcp_grid* grid, const lcp_a
     if (n_samples < 1) return fail(LCP_EINVAL, "n_samples < 1");
     GridP g;
     if (int r = check_grid(M, grid, &g)) return r;
-    if (int r = check_adapt(A)) return r;
+    if (int r = check_adapt(*M, A)) return r;
     int64_t S0;
     int Lmax;
     octree_shape(g, A->min_leaf_cells, &S0, &Lmax);
@@ -516,7 +520,7 @@ int lcp_adaptive(const lcp_model* M, const lcp_grid* grid, double theta, const l
     if (int r = check_grid(M, grid, &g)) return r;
     if (int r = check_mc(M, mc)) return r;
     if (mc->estimator != LCP_EST_COUNT) return fail(LCP_ENOTSUPPORTED, "lcp_adaptive: counting estimator only");
-    if (int r = check_adapt(A)) return r;
+    if (int r = check_adapt(*M, A)) return r;
     if (!is_finite(theta)) return fail(LCP_EINVAL, "theta must be finite");
     if (!lcp || !ws || !n_leaves) return fail(LCP_EINVAL, "lcp, n_leaves and ws must not be NULL");
     if (leaf_cap < 0 || (leaf_cap > 0 && !leaves)) return fail(LCP_EINVAL, "leaves must hold leaf_cap >= 0 keys");

@@ -178,6 +178,8 @@ struct PostTask {
 struct Model;  // defined below
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s);
+// The values the model was fitted to (device, m): y of an exact GP, mu_M of a sparse model.
+const double* model_values(const Model& M);
 // Value columns against another operand in the fragment order of the binary64 (prec
 // LCP_FP64) or binary32 (LCP_FP32) posterior: A0 = m_pad x m_pad in 16 x 16 x 4 fragments.
 hipError_t launch_posterior_operand(const Model& M, int prec, const PostTask& t, const void* A0, hipStream_t s);
