@@ -770,7 +770,7 @@ inline unsigned gsz(int64_t n, int per)
 // A factorisation that fails (pivot at or below m' eps (s2 + noise)) gives no bound: the
 // node is refined.
 constexpr int kLocB = 32;        // panel width; also the most right-hand sides per solve
-constexpr int kLocSlots = 768;   // work-groups of k_local_bound, one slot each
+constexpr int kLocSlots = 512;   // work-groups of k_local_bound (two per CU), one slot each
 
 struct LocalBufs {
     KParams kp;
@@ -781,56 +781,54 @@ struct LocalBufs {
     double noise;
     double piv_scale;    // eps (s2 + noise); the pivot floor is m' piv_scale
     double rad[3];       // beta ell_d
-    double* slots;       // kLocSlots x (ld ld + ld kLocB) doubles
+    double* slots;       // kLocSlots x (ld ld + 2 ld kLocB) doubles: L, V, inverted diagonal blocks
 };
 
-__host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (size_t)ld * ld + (size_t)ld * kLocB; }
+__host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (size_t)ld * ld + 2 * (size_t)ld * kLocB; }
 
-// Forward solve L V = V for columns [0, R) of V (rows [0, n)), L lower row-major in Lm.
-__device__ void local_fsolve(const double* __restrict__ Lm, double* __restrict__ V, int ld, int n, int R,
-                             double (*ta)[kLocB + 1], double (*tb)[kLocB + 1])
+// Forward solve L V = V for columns [0, R) of V (rows [0, n)), right-looking by 32-row
+// blocks: y_b = D_b V_b with D_b the inverted diagonal block (Dv), then every row below
+// takes V_i -= L_ib y_b.  L lower row-major in Lm.
+__device__ void local_fsolve(const double* __restrict__ Lm, const double* __restrict__ Dv, double* __restrict__ V,
+                             int ld, int n, int R, double (*ta)[kLocB + 1], double (*tb)[kLocB + 1],
+                             double (*tc)[kLocB + 1])
 {
     const int tid = threadIdx.x;
     const int r = tid >> 3, c4 = (tid & 7) * 4;
     for (int r0 = 0; r0 < n; r0 += kLocB) {
         const int nb = min(kLocB, n - r0);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int j0 = 0; j0 < r0; j0 += kLocB) {
-            for (int t = tid; t < kLocB * kLocB; t += 256) {
-                const int a = t >> 5, b = t & 31;
-                ta[a][b] = a < nb ? Lm[(size_t)(r0 + a) * ld + j0 + b] : 0.0;
-                tb[a][b] = b < R ? V[(size_t)(j0 + a) * kLocB + b] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll 8
-            for (int l = 0; l < kLocB; ++l) {
-                const double x = ta[r][l];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[l][c4 + q], acc[q]);
-            }
-            __syncthreads();
-        }
-        // block right-hand sides minus the sums, then the diagonal block
         for (int t = tid; t < kLocB * kLocB; t += 256) {
             const int a = t >> 5, b = t & 31;
-            ta[a][b] = (a < nb && b <= a) ? Lm[(size_t)(r0 + a) * ld + r0 + b] : 0.0;
+            ta[a][b] = Dv[(size_t)(r0 + a) * kLocB + b];
+            tb[a][b] = (a < nb && b < R) ? V[(size_t)(r0 + a) * kLocB + b] : 0.0;
         }
+        __syncthreads();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+        for (int l = 0; l < kLocB; ++l) {
+            const double x = ta[r][l];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[l][c4 + q], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tc[r][c4 + q] = r < nb ? acc[q] : 0.0;
         if (r < nb)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                tb[r][c4 + q] = c4 + q < R ? V[(size_t)(r0 + r) * kLocB + c4 + q] - acc[q] : 0.0;
+                if (c4 + q < R) V[(size_t)(r0 + r) * kLocB + c4 + q] = acc[q];
         __syncthreads();
-        if (tid < R) {
-            for (int a = 0; a < nb; ++a) {
-                double s = tb[a][tid];
-                for (int l = 0; l < a; ++l) s = fma(-ta[a][l], tb[l][tid], s);
-                tb[a][tid] = s / ta[a][a];
+        for (int i = r0 + nb + r; i < n; i += 32) {
+            const double* Li = Lm + (size_t)i * ld + r0;
+            double u[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+            for (int l = 0; l < kLocB; ++l) {
+                const double x = Li[l];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = fma(x, tc[l][c4 + q], u[q]);
             }
-        }
-        __syncthreads();
-        for (int t = tid; t < nb * kLocB; t += 256) {
-            const int a = t >> 5, b = t & 31;
-            if (b < R) V[(size_t)(r0 + a) * kLocB + b] = tb[a][b];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (c4 + q < R) V[(size_t)i * kLocB + c4 + q] -= u[q];
         }
         __syncthreads();
     }
@@ -858,13 +856,14 @@ __device__ void local_colsum(const double* __restrict__ V, const double* __restr
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
+__global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ path, BoundBufs B, LocalBufs Lb,
                                                      int32_t* __restrict__ sub)
 {
     __shared__ double xs[kMaxM * D];
     __shared__ double wv[kMaxM];
-    __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1];
+    __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1], tc[kLocB][kLocB + 1];
+    __shared__ double ldg[kLocB];
     __shared__ double red[8][kLocB + 1];
     __shared__ double sums[4][kLocB];
     __shared__ double xcur[3];
@@ -875,6 +874,7 @@ __global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uin
     const int ld = Lb.ld;
     double* Lm = Lb.slots + (size_t)blockIdx.x * local_slot_doubles(ld);
     double* V = Lm + (size_t)ld * ld;
+    double* Dv = V + (size_t)ld * kLocB;
     const int64_t nb_nodes = B.cnt[0];
     const int npt = D == 3 ? 27 : 9;
     const double s2 = Lb.kp.s2;
@@ -928,15 +928,17 @@ __global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uin
             state = 0;
         }
         __syncthreads();
-        // blocked Cholesky, lower, in place
+        // blocked Cholesky, lower, in place; the inverted diagonal blocks go to Dv
         const double piv_min = (double)n * Lb.piv_scale;
         for (int k0 = 0; k0 < n && !fail; k0 += kLocB) {
             const int nb = min(kLocB, n - k0);
             for (int t = tid; t < kLocB * kLocB; t += 256) {
                 const int a = t >> 5, bb = t & 31;
-                ta[a][bb] = (a < nb && bb <= a) ? Lm[(size_t)(k0 + a) * ld + k0 + bb] : 0.0;
+                ta[a][bb] = (a < nb && bb <= a) ? Lm[(size_t)(k0 + a) * ld + k0 + bb] : (a == bb ? 1.0 : 0.0);
             }
             __syncthreads();
+            // diagonal block: column j scaled by its pivot's root (kept in ldg), then the
+            // rank-1 update of the rows below; ta[j][j] is not rewritten until the end
             for (int j = 0; j < nb; ++j) {
                 const double piv = ta[j][j];
                 if (!(piv > piv_min)) {
@@ -944,8 +946,7 @@ __global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uin
                     break;
                 }
                 const double ljj = sqrt(piv);
-                __syncthreads();
-                if (tid == j) ta[j][j] = ljj;
+                if (tid == j) ldg[j] = ljj;
                 if (tid > j && tid < nb) ta[tid][j] /= ljj;
                 __syncthreads();
                 if (tid > j && tid < nb)
@@ -954,49 +955,78 @@ __global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uin
             }
             __syncthreads();
             if (fail) break;
-            for (int t = tid; t < nb * kLocB; t += 256) {
-                const int a = t >> 5, bb = t & 31;
-                if (bb <= a) Lm[(size_t)(k0 + a) * ld + k0 + bb] = ta[a][bb];
-            }
-            // panel: each row below solves x L_kk^T = a in place (the row stays in this thread)
-            for (int i = k0 + nb + tid; i < n; i += 256) {
-                double* row = Lm + (size_t)i * ld + k0;
-                for (int l = 0; l < nb; ++l) {
-                    double sacc = row[l];
-                    for (int q = 0; q < l; ++q) sacc = fma(-row[q], ta[l][q], sacc);
-                    row[l] = sacc / ta[l][l];
+            if (tid < nb) ta[tid][tid] = ldg[tid];
+            __syncthreads();
+            // D = L_kk^-1 (identity beyond nb), column c by thread c
+            if (tid < kLocB) {
+                const int cc = tid;
+                for (int a = 0; a < kLocB; ++a) {
+                    double v = 0.0;
+                    if (a >= cc) {
+                        double sacc = a == cc ? 1.0 : 0.0;
+                        for (int q = cc; q < a; ++q) sacc = fma(-ta[a][q], tc[q][cc], sacc);
+                        v = sacc / ta[a][a];
+                    }
+                    tc[a][cc] = v;
                 }
             }
             __syncthreads();
-            // trailing update of the lower triangle: A_ij -= L_ik L_jk^T
-            const int t0 = k0 + nb;
-            const int T = (n - t0 + kLocB - 1) / kLocB;
-            const int r = tid >> 3, c4 = (tid & 7) * 4;
-            for (int tt = 0; tt < T * (T + 1) / 2; ++tt) {
-                int ib = 0, rem = tt;
-                while (rem > ib) { rem -= ib + 1; ++ib; }
-                const int jb = rem;
-                const int ri = t0 + ib * kLocB, cj = t0 + jb * kLocB;
-                for (int t = tid; t < kLocB * kLocB; t += 256) {
-                    const int a = t >> 5, bb = t & 31;
-                    ta[a][bb] = ri + a < n ? Lm[(size_t)(ri + a) * ld + k0 + bb] : 0.0;
-                    tb[a][bb] = cj + a < n ? Lm[(size_t)(cj + a) * ld + k0 + bb] : 0.0;
-                }
-                __syncthreads();
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-                for (int l = 0; l < kLocB; ++l) {
-                    const double x = ta[r][l];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[c4 + q][l], acc[q]);
-                }
-                if (ri + r < n)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int col = cj + c4 + q;
-                        if (col < n && (ib > jb || c4 + q <= r)) Lm[(size_t)(ri + r) * ld + col] -= acc[q];
+            for (int t = tid; t < kLocB * kLocB; t += 256) {
+                const int a = t >> 5, bb = t & 31;
+                Dv[(size_t)(k0 + a) * kLocB + bb] = tc[a][bb];
+                if (a < nb && bb <= a) Lm[(size_t)(k0 + a) * ld + k0 + bb] = ta[a][bb];
+            }
+            // panel: X = A D^T, 32 rows at a time
+            {
+                const int r = tid >> 3, c4 = (tid & 7) * 4;
+                for (int i0 = k0 + nb; i0 < n; i0 += kLocB) {
+                    for (int t = tid; t < kLocB * kLocB; t += 256) {
+                        const int a = t >> 5, bb = t & 31;
+                        tb[a][bb] = (i0 + a < n && bb < nb) ? Lm[(size_t)(i0 + a) * ld + k0 + bb] : 0.0;
                     }
-                __syncthreads();
+                    __syncthreads();
+                    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                    for (int l = 0; l < kLocB; ++l) {
+                        const double x = tb[r][l];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[q] = fma(x, tc[c4 + q][l], acc[q]);
+                    }
+                    if (i0 + r < n)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (c4 + q < nb) Lm[(size_t)(i0 + r) * ld + k0 + c4 + q] = acc[q];
+                    __syncthreads();
+                }
+            }
+            // trailing update of the lower triangle, A_ij -= L_ik L_jk^T: for each 32-row chunk
+            // of the panel (columns j of A), every row i at or below it updates its entries there
+            {
+                const int t0 = k0 + nb;
+                const int r = tid >> 3, c4 = (tid & 7) * 4;
+                for (int j0 = t0; j0 < n; j0 += kLocB) {
+                    for (int t = tid; t < kLocB * kLocB; t += 256) {
+                        const int a = t >> 5, bb = t & 31;
+                        tb[a][bb] = j0 + a < n ? Lm[(size_t)(j0 + a) * ld + k0 + bb] : 0.0;
+                    }
+                    __syncthreads();
+                    for (int i = j0 + r; i < n; i += kLocB) {
+                        const double* Pi = Lm + (size_t)i * ld + k0;
+                        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                        for (int l = 0; l < kLocB; ++l) {
+                            const double x = Pi[l];
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[c4 + q][l], acc[q]);
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int col = j0 + c4 + q;
+                            if (col < n && col <= i) Lm[(size_t)i * ld + col] -= acc[q];
+                        }
+                    }
+                    __syncthreads();
+                }
             }
         }
         const int p = path[f];
@@ -1017,7 +1047,7 @@ __global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uin
                 V[(size_t)i * kLocB + 1 + q] = kernel_val(Lb.kp, r2);
             }
             __syncthreads();
-            local_fsolve(Lm, V, ld, n, 1 + npt, ta, tb);
+            local_fsolve(Lm, Dv, V, ld, n, 1 + npt, ta, tb, tc);
             for (int i = tid; i < n; i += 256) wv[i] = V[(size_t)i * kLocB];
             __syncthreads();
             local_colsum(V, wv, 0, n, 1 + npt, red, sums[0]);      // means
@@ -1089,7 +1119,7 @@ __global__ void __launch_bounds__(256) k_local_bound(Oct o, int level, const uin
                             V[(size_t)i * kLocB + 1 + d] = fv * z[d] * Lb.kp.inv_ell[d] * Lb.kp.inv_ell[d];
                 }
                 __syncthreads();
-                local_fsolve(Lm, V, ld, n, R, ta, tb);
+                local_fsolve(Lm, Dv, V, ld, n, R, ta, tb, tc);
                 local_colsum(V, wv, 0, n, R, red, sums[0]);       // mu, dmu_d
                 local_colsum(V, nullptr, 0, n, R, red, sums[1]);  // |v|^2, v.u_d
                 if (tid == 0) {
