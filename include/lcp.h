@@ -99,11 +99,11 @@ typedef enum {
                                 guarantee Sec. 9 leaves open; more nodes are refined than with the
                                 search, and every leaf of the search is also a leaf here */
     LCP_BOUND_LOCAL = 2      /* the search of LCP_BOUND_SEARCH on the local model M' of Sec. 5.2 (Alg. 1):
-                                the GP conditioned only on the observations inside the node box
-                                enlarged by beta * lengthscale_d along axis d (the root keeps all),
-                                factored per node in binary64.  An approximation of F_M that
-                                approaches it as beta grows.  Exact-GP models only (a sparse model
-                                does not keep A_M): LCP_EINVAL otherwise.  A node whose local factor
+                                the points of M inside the node box enlarged by beta * lengthscale_d
+                                along axis d (the root keeps all).  Exact GP: the GP conditioned on
+                                those observations alone; sparse model: eq. (sgp) with mu_M and A_M
+                                restricted to them.  Factored per node in binary64; an approximation
+                                of F_M that approaches it as beta grows.  A node whose local factor
                                 is not positive definite is refined */
 } lcp_bound_kind;
 

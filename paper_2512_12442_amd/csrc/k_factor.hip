@@ -23,6 +23,7 @@ size_t model_bytes(int m)
     b += 256;                                        // amax, sA
     b += 2 * align256(sizeof(double) * mp);          // obs_mu, obs_var
     b += 256;                                        // info
+    b += align256(sizeof(double) * (size_t)mp * mp); // A_M (sparse model)
     return b;
 }
 
@@ -566,6 +567,7 @@ static void carve(Model& M, char* base)
     M.obs_mu = (double*)take(sizeof(double) * mp);
     M.obs_var = (double*)take(sizeof(double) * mp);
     M.info = (int*)take(256);
+    M.AM = (double*)take(sizeof(double) * (size_t)mp * mp);
 }
 
 static double* ybuf(const Model& M)
@@ -631,6 +633,7 @@ hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, 
         hipLaunchKernelGGL(k_obs_sparse, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, ybuf(M), A, m,
                            M.obs_mu, M.obs_var);
         hipLaunchKernelGGL(k_pack_square, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, A, m, mp, M.A64);
+        hipLaunchKernelGGL(k_pack_square, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, A, m, mp, M.AM);
         // U <- L^-1 A_M (U held L^T, no longer needed)
         hipLaunchKernelGGL((k_gemm64<RowMajor, RowMajor, Store>), tiles, dim3(256), 0, s, mp,
                            RowMajor{M.Linv, mp}, RowMajor{M.A64, mp}, Store{M.U, mp});

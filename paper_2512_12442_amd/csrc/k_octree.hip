@@ -767,6 +767,8 @@ inline unsigned gsz(int64_t n, int per)
 // index wins ties), then the projected steps.  Every value comes from forward solves only:
 // with w = L'^-1 y', v = L'^-1 k(x) and u_d = L'^-1 dk(x)/dx_d,
 //   mu = v.w,  var = s2 - |v|^2,  dmu_d = u_d.w,  dvar_d = -2 v.u_d.
+// A sparse model (eq. (sgp)) restricts mu_M and A_M to M': with W = L'^-T [v, u_d] the
+// variance gains w.A'w and its derivative 2 w.A'(K'^-1 dk/dx_d).
 // A factorisation that fails (pivot at or below m' eps (s2 + noise)) gives no bound: the
 // node is refined.
 constexpr int kLocB = 32;        // panel width; also the most right-hand sides per solve
@@ -781,10 +783,11 @@ struct LocalBufs {
     double noise;
     double piv_scale;    // eps (s2 + noise); the pivot floor is m' piv_scale
     double rad[3];       // beta ell_d
-    double* slots;       // kLocSlots x (ld ld + 2 ld kLocB) doubles: L, V, inverted diagonal blocks
+    const double* AM;    // sparse model: A_M (ld x ld); null for an exact GP
+    double* slots;       // kLocSlots x (ld ld + 4 ld kLocB) doubles: L, V, inverted diagonal blocks, W, T
 };
 
-__host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (size_t)ld * ld + 2 * (size_t)ld * kLocB; }
+__host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (size_t)ld * ld + 4 * (size_t)ld * kLocB; }
 
 // Forward solve L V = V for columns [0, R) of V (rows [0, n)), right-looking by 32-row
 // blocks: y_b = D_b V_b with D_b the inverted diagonal block (Dv), then every row below
@@ -855,6 +858,90 @@ __device__ void local_colsum(const double* __restrict__ V, const double* __restr
     __syncthreads();
 }
 
+// Backward solve L^T W = W for columns [0, R) (rows [0, n)), right-looking from the last
+// block: x_b = D_b^T W_b, then every row above takes W_i -= sum_l L[b + l][i] x_b[l].
+__device__ void local_bsolve(const double* __restrict__ Lm, const double* __restrict__ Dv, double* __restrict__ W,
+                             int ld, int n, int R, double (*ta)[kLocB + 1], double (*tb)[kLocB + 1],
+                             double (*tc)[kLocB + 1])
+{
+    const int tid = threadIdx.x;
+    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    for (int r0 = (n - 1) / kLocB * kLocB; r0 >= 0 && n > 0; r0 -= kLocB) {
+        const int nb = min(kLocB, n - r0);
+        for (int t = tid; t < kLocB * kLocB; t += 256) {
+            const int a = t >> 5, b = t & 31;
+            ta[a][b] = Dv[(size_t)(r0 + b) * kLocB + a];
+            tb[a][b] = (a < nb && b < R) ? W[(size_t)(r0 + a) * kLocB + b] : 0.0;
+        }
+        __syncthreads();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+        for (int l = 0; l < kLocB; ++l) {
+            const double x = ta[r][l];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[l][c4 + q], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tc[r][c4 + q] = r < nb ? acc[q] : 0.0;
+        if (r < nb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (c4 + q < R) W[(size_t)(r0 + r) * kLocB + c4 + q] = acc[q];
+        __syncthreads();
+        for (int i = r; i < r0; i += 32) {
+            double u[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int l = 0; l < nb; ++l) {
+                const double x = Lm[(size_t)(r0 + l) * ld + i];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = fma(x, tc[l][c4 + q], u[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (c4 + q < R) W[(size_t)i * kLocB + c4 + q] -= u[q];
+        }
+        __syncthreads();
+    }
+}
+
+// T = A' W for columns [0, R): A'[i][j] = A_M[idx_i][idx_j], read through the index list.
+__device__ void local_aprod(const double* __restrict__ AM, int lda, const int* __restrict__ idx,
+                            const double* __restrict__ W, double* __restrict__ T, int n, int R)
+{
+    const int tid = threadIdx.x;
+    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    for (int i = r; i < n; i += 32) {
+        const double* Ai = AM + (size_t)idx[i] * lda;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < n; ++j) {
+            const double a = Ai[idx[j]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fma(a, W[(size_t)j * kLocB + c4 + q], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (c4 + q < R) T[(size_t)i * kLocB + c4 + q] = acc[q];
+    }
+    __syncthreads();
+}
+
+// out[c] = sum_i X[i][c] Y[i][same ? c : 0] for c < R.
+__device__ void local_coldot(const double* __restrict__ X, const double* __restrict__ Y, bool same, int n, int R,
+                             double (*red)[kLocB + 1], double* __restrict__ out)
+{
+    const int tid = threadIdx.x, c = tid & 31, g = tid >> 5;
+    double s = 0.0;
+    if (c < R)
+        for (int i = g; i < n; i += 8) s = fma(X[(size_t)i * kLocB + c], Y[(size_t)i * kLocB + (same ? c : 0)], s);
+    red[g][c] = s;
+    __syncthreads();
+    if (tid < R) {
+        double t = 0.0;
+        for (int k = 0; k < 8; ++k) t += red[k][tid];
+        out[tid] = t;
+    }
+    __syncthreads();
+}
+
 template <int D>
 __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ path, BoundBufs B, LocalBufs Lb,
@@ -864,6 +951,7 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
     __shared__ double wv[kMaxM];
     __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1], tc[kLocB][kLocB + 1];
     __shared__ double ldg[kLocB];
+    __shared__ int sidx[kMaxM];
     __shared__ double red[8][kLocB + 1];
     __shared__ double sums[4][kLocB];
     __shared__ double xcur[3];
@@ -875,6 +963,9 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
     double* Lm = Lb.slots + (size_t)blockIdx.x * local_slot_doubles(ld);
     double* V = Lm + (size_t)ld * ld;
     double* Dv = V + (size_t)ld * kLocB;
+    double* Wm = Dv + (size_t)ld * kLocB;
+    double* Tm = Wm + (size_t)ld * kLocB;
+    const bool sparse = Lb.AM != nullptr;
     const int64_t nb_nodes = B.cnt[0];
     const int npt = D == 3 ? 27 : 9;
     const double s2 = Lb.kp.s2;
@@ -907,6 +998,7 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
 #pragma unroll
                 for (int d = 0; d < D; ++d) xs[pos * D + d] = xi[d];
                 V[(size_t)pos * kLocB] = Lb.y[i];
+                sidx[pos] = i;
             }
             __syncthreads();
             n += tot;
@@ -1069,6 +1161,14 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
                 }
                 __syncthreads();
             }
+            if (sparse) {
+                // W = L'^-T V, T = A' W; sums[2][c] = w_c . A' w_c
+                for (int t = tid; t < n * kLocB; t += 256) Wm[t] = V[t];
+                __syncthreads();
+                local_bsolve(Lm, Dv, Wm, ld, n, 1 + npt, ta, tb, tc);
+                local_aprod(Lb.AM, ld, sidx, Wm, Tm, n, 1 + npt);
+                local_coldot(Wm, Tm, true, n, 1 + npt, red, sums[2]);
+            }
             if (tid == 0) {
                 const int ic = (npt - 1) / 2;
                 if (p != 1 && p != 2) {
@@ -1078,7 +1178,7 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
                 double best = __builtin_inf();
                 int ib = 0;
                 for (int q = 0; q < npt; ++q) {
-                    const double var = s2 - sums[1][1 + q];
+                    const double var = s2 - sums[1][1 + q] + (sparse ? sums[2][1 + q] : 0.0);
                     const double g = margin(side, o.theta, sums[0][1 + q], var > 0.0 ? var : 0.0);
                     if (g < best) {
                         best = g;
@@ -1122,9 +1222,17 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
                 local_fsolve(Lm, Dv, V, ld, n, R, ta, tb, tc);
                 local_colsum(V, wv, 0, n, R, red, sums[0]);       // mu, dmu_d
                 local_colsum(V, nullptr, 0, n, R, red, sums[1]);  // |v|^2, v.u_d
+                if (sparse) {
+                    // sums[2][0] = w.A'w, sums[2][1 + d] = (K'^-1 dk_d).A'w
+                    for (int t = tid; t < n * kLocB; t += 256) Wm[t] = V[t];
+                    __syncthreads();
+                    local_bsolve(Lm, Dv, Wm, ld, n, R, ta, tb, tc);
+                    local_aprod(Lb.AM, ld, sidx, Wm, Tm, n, R);
+                    local_coldot(Wm, Tm, false, n, R, red, sums[2]);
+                }
                 if (tid == 0) {
                     const double mu = sums[0][0];
-                    const double vr = s2 - sums[1][0];
+                    const double vr = s2 - sums[1][0] + (sparse ? sums[2][0] : 0.0);
                     const double var = vr > 0.0 ? vr : 0.0;
                     const double g = margin(side, o.theta, mu, var);
                     if (k >= 1 && g < gmin) gmin = g;
@@ -1133,7 +1241,8 @@ __global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const 
                         const double sd = sqrt(var);
                         double u[3], nrm = 0.0;
                         for (int a = 0; a < D; ++a) {
-                            const double dsd = -2.0 * sums[1][1 + a] / (2.0 * sd);
+                            const double dvar = -2.0 * sums[1][1 + a] + (sparse ? 2.0 * sums[2][1 + a] : 0.0);
+                            const double dsd = dvar / (2.0 * sd);
                             const double gr = side * (-sums[0][1 + a] * sd - (o.theta - mu) * dsd) / var;
                             u[a] = (bhi[a] - blo[a]) * gr;
                             nrm += u[a] * u[a];
@@ -1416,6 +1525,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             lb.noise = M.k.noise_var;
             lb.piv_scale = 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var);
             for (int d = 0; d < 3; ++d) lb.rad[d] = d < D ? A.beta * M.k.lengthscale[d] : 0.0;
+            lb.AM = M.sparse ? M.AM : nullptr;
             lb.slots = (double*)P(L.o_loc);
             StageScope sc(s, ST_BOUND);
             if (D == 3)

@@ -166,7 +166,6 @@ int check_adapt(const Model& M, const lcp_adapt* A)
         return fail(LCP_EINVAL, "bound_kind must be LCP_BOUND_SEARCH, LCP_BOUND_CERTIFIED or LCP_BOUND_LOCAL");
     if (A->bound_kind == LCP_BOUND_LOCAL) {
         if (!(is_finite(A->beta) && A->beta >= 0.0)) return fail(LCP_EINVAL, "beta must be finite and >= 0");
-        if (M.sparse) return fail(LCP_EINVAL, "LCP_BOUND_LOCAL needs an exact-GP model (a sparse model keeps no A_M)");
     }
     if (A->split != LCP_SPLIT_OCTREE && A->split != LCP_SPLIT_KD)
         return fail(LCP_EINVAL, "split must be LCP_SPLIT_OCTREE or LCP_SPLIT_KD");

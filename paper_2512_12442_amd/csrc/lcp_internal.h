@@ -259,6 +259,7 @@ struct Model {
     double* amax;     // [0] max |Linv|, [1] sA (power of two), device
     double* obs_mu;   // m
     double* obs_var;  // m
+    double* AM;       // sparse model: A_M (m_pad x m_pad, zero padded), kept for local models
     int* info;
     int device;
 };

@@ -1,7 +1,8 @@
 """Parity of the region test on local models (lcp_adapt.bound_kind = LCP_BOUND_LOCAL, the
-local model M' of Sec. 5.2 used by Alg. 1) with the FP64 oracle: leaf sets (exact, except
-below nodes the oracle flags as near-ties), Monte Carlo counts inside the leaves (exact in
-binary64), the level field, and the identities that do not need the oracle.
+local model M' of Sec. 5.2 used by Alg. 1) with the FP64 oracle, for exact-GP and sparse
+models: leaf sets (exact, except below nodes the oracle flags as near-ties), Monte Carlo
+counts inside the leaves (exact in binary64), the level field, and the identities that do
+not need the oracle.
 """
 import numpy as np
 import pytest
@@ -25,7 +26,12 @@ def _cases():
     # few observations, short lengthscale: many nodes have an empty M' (the prior decides)
     W5 = workloads.random_small(190, 3, 40, 17, ell=0.06, signal_var=0.01, noise_var=1e-4, min_leaf=1)
     W5.theta = 0.45
-    return {"trig33": W1, "ragged": W2, "cfg1_2d": W3, "trig33_m300": W4, "sparse_obs17": W5}
+    W6 = workloads.sgpr_field(154, m=64, npts=17, train_npts=10, ell=0.25)
+    W6.min_leaf = 1
+    W7 = workloads.sgpr_field(155, m=216, npts=25, train_npts=12, ell=0.12)
+    W7.min_leaf = 2
+    return {"trig33": W1, "ragged": W2, "cfg1_2d": W3, "trig33_m300": W4, "sparse_obs17": W5, "sgpr17": W6,
+            "sgpr25": W7}
 
 
 def _run(W, beta, split=oracle.SPLIT_OCTREE, prec="fp64"):
@@ -39,7 +45,9 @@ def _run(W, beta, split=oracle.SPLIT_OCTREE, prec="fp64"):
 @pytest.mark.parametrize("case,beta,split", [("trig33", 6.0, 0), ("trig33", 2.0, 0), ("trig33", 1.0, 0),
                                              ("ragged", 1.5, 0), ("cfg1_2d", 2.0, 0), ("trig33_m300", 6.0, 0),
                                              ("sparse_obs17", 0.0, 0), ("sparse_obs17", 1.0, 0),
-                                             ("trig33", 1.0, 1), ("cfg1_2d", 2.0, 1)])
+                                             ("trig33", 1.0, 1), ("cfg1_2d", 2.0, 1),
+                                             ("sgpr17", 1.0, 0), ("sgpr17", 3.0, 0), ("sgpr25", 2.0, 0),
+                                             ("sgpr25", 1.0, 1)])
 def test_local_bound_matches_oracle(case, beta, split):
     W = _cases()[case]
     say(f"local bound {case} beta={beta} split={split} npts={list(W.npts)} m={W.m} min_leaf={W.min_leaf}")
@@ -92,12 +100,7 @@ def test_local_mixed_precision_reconstruction_matches_fp64_leaves():
     assert np.array_equal(l64, l16)
 
 
-def test_local_bound_rejects_sparse_models_and_bad_beta():
-    Ws = workloads.sgpr_field(154, m=64, npts=17, train_npts=10, ell=0.25)
-    G = gpu_model(Ws)
-    with pytest.raises(lcp.LcpError) as e:
-        G.lcp_adaptive(lcp.grid_of(Ws), Ws.theta, lcp.adapt_of(Ws, bound_kind=lcp.BOUND_LOCAL), zbank(Ws), "fp64")
-    assert e.value.status == lcp.lcp.LCP_EINVAL
+def test_local_bound_rejects_bad_beta():
     W = _cases()["cfg1_2d"]
     G = gpu_model(W)
     for beta in (-1.0, float("inf"), float("nan")):
