@@ -95,3 +95,28 @@ def test_full_size_adaptive_f16x3_leaf_set_and_sampled_cells(full):
     say(f"128^3 adaptive f16x3: {N_SAMPLED} sampled leaf cells, rmse={rmse:.2e}, max flipped samples={dc.max()}")
     assert rmse <= 1e-4
     assert dc.max() <= 8
+
+
+def test_full_size_adaptive_local_bound_leaf_set(full):
+    """The region test on local models (Sec. 5.2, beta = 6) at the benchmarked size: the
+    leaf set against the oracle's local-model run, and the level field."""
+    W, M, G = full
+    adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4, bound_kind=lcp.BOUND_LOCAL, beta=6.0)
+    out, leaves, nl, lf, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, adapt, zbank(W), "f16x3")
+    n = int(nl.item())
+    got_keys = leaves[:n].cpu().numpy().astype(np.uint64)
+    leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4,
+                                                    bound_kind=oracle.BOUND_LOCAL, beta=6.0)
+    ties = near_tie_keys(recs, W.alpha)
+    sym = set(map(int, got_keys)) ^ set(map(int, leaves_ref))
+    tested = recs["n_local"] >= 0
+    say(f"128^3 local bound: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
+        f"region tests={tested.sum()} mean |M'|={recs['n_local'][tested].mean():.1f}")
+    assert np.all(np.diff(got_keys.astype(np.int64)) > 0)
+    for k in sym:
+        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
+    if not sym:
+        lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref]))
+        assert np.array_equal(lf.cpu().numpy().reshape(W.cell_shape), lev_ref)
+    field = out.cpu().numpy().reshape(W.cell_shape)
+    assert np.all(field[oracle.level_field(W, got_keys) == 255] == 0)
