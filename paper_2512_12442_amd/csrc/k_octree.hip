@@ -772,7 +772,7 @@ inline unsigned gsz(int64_t n, int per)
 // A factorisation that fails (pivot at or below m' eps (s2 + noise)) gives no bound: the
 // node is refined.
 constexpr int kLocB = 32;        // panel width; also the most right-hand sides per solve
-constexpr int kLocSlots = 512;   // work-groups of k_local_bound (two per CU), one slot each
+constexpr int kLocSlots = 768;   // most work-groups of k_local_bound (three per CU), one slot each
 
 struct LocalBufs {
     KParams kp;
@@ -943,15 +943,17 @@ __device__ void local_coldot(const double* __restrict__ X, const double* __restr
 }
 
 template <int D>
-__global__ void __launch_bounds__(256, 2) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
+__global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ path, BoundBufs B, LocalBufs Lb,
                                                      int32_t* __restrict__ sub)
 {
-    __shared__ double xs[kMaxM * D];
-    __shared__ double wv[kMaxM];
+    // sized by the model: M' coordinates (ld x D), w (ld), the indices of M' in M (ld)
+    extern __shared__ double lsm[];
+    double* xs = lsm;
+    double* wv = lsm + (size_t)Lb.ld * D;
+    int* sidx = (int*)(wv + Lb.ld);
     __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1], tc[kLocB][kLocB + 1];
     __shared__ double ldg[kLocB];
-    __shared__ int sidx[kMaxM];
     __shared__ double red[8][kLocB + 1];
     __shared__ double sums[4][kLocB];
     __shared__ double xcur[3];
@@ -1528,10 +1530,19 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             lb.AM = M.sparse ? M.AM : nullptr;
             lb.slots = (double*)P(L.o_loc);
             StageScope sc(s, ST_BOUND);
+            // a persistent grid of the work-groups that are resident together (at most kLocSlots)
+            const size_t shm = (size_t)M.m_pad * (D + 1) * sizeof(double) + (size_t)M.m_pad * sizeof(int);
+            int per_cu = 0, dev = 0, ncu = 0;
+            if (D == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_local_bound<3>, 256, shm);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_local_bound<2>, 256, shm);
+            if (e != hipSuccess) return e;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+            if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+            const int grid = std::max(1, std::min(kLocSlots, per_cu * ncu));
             if (D == 3)
-                hipLaunchKernelGGL(k_local_bound<3>, dim3(kLocSlots), dim3(256), 0, s, o, l, kin, path, B, lb, sub);
+                hipLaunchKernelGGL(k_local_bound<3>, dim3(grid), dim3(256), shm, s, o, l, kin, path, B, lb, sub);
             else
-                hipLaunchKernelGGL(k_local_bound<2>, dim3(kLocSlots), dim3(256), 0, s, o, l, kin, path, B, lb, sub);
+                hipLaunchKernelGGL(k_local_bound<2>, dim3(grid), dim3(256), shm, s, o, l, kin, path, B, lb, sub);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         } else if (cert) {
