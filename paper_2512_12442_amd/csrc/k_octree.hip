@@ -777,7 +777,7 @@ constexpr int kLocSlots = 768;   // most work-groups of k_local_bound (three per
 struct LocalBufs {
     KParams kp;
     const double* X;     // m_pad x 4
-    const double* y;     // m observed values
+    const double* y;     // m fitted values: y of an exact GP, mu_M of a sparse model
     int m;
     int ld;              // slot matrix leading dimension (m_pad of the model)
     double noise;
