@@ -120,3 +120,37 @@ def test_full_size_adaptive_local_bound_leaf_set(full):
         assert np.array_equal(lf.cpu().numpy().reshape(W.cell_shape), lev_ref)
     field = out.cpu().numpy().reshape(W.cell_shape)
     assert np.all(field[oracle.level_field(W, got_keys) == 255] == 0)
+
+
+def test_full_size_256_adaptive_leaf_set_and_sampled_cells():
+    """The largest configuration of the mixed-precision workload: 256^3, m = 500, adaptive
+    f16x3 with the binary64 bound.  Leaf set against the oracle's Alg. 1 (about a minute of
+    host time), sampled leaf cells against the oracle's cell LCP."""
+    W = workloads.field3d_trig(0, m=500, npts=256)
+    M = oracle.fit(W)
+    G = gpu_model(W)
+    adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4)
+    out, leaves, nl, _, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, adapt, zbank(W), "f16x3")
+    n = int(nl.item())
+    got_keys = leaves[:n].cpu().numpy().astype(np.uint64)
+    field = out.cpu().numpy().reshape(W.cell_shape)
+    del out
+    say(f"256^3 adaptive: {n} leaves on the GPU; running the oracle's Alg. 1")
+    leaves_ref, _, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4)
+    ties = near_tie_keys(recs, W.alpha)
+    sym = set(map(int, got_keys)) ^ set(map(int, leaves_ref))
+    say(f"256^3 adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)}")
+    assert np.all(np.diff(got_keys.astype(np.int64)) > 0)
+    for k in sym:
+        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
+    inleaf = oracle.level_field(W, got_keys) != 255
+    assert np.all(field[~inleaf] == 0)
+    cand = np.argwhere(inleaf)
+    pick = cand[np.random.default_rng(14).choice(len(cand), size=N_SAMPLED, replace=False)]
+    ref = _oracle_cells(M, W, pick[:, ::-1])
+    g = field[pick[:, 0], pick[:, 1], pick[:, 2]]
+    dc = np.abs(counts(g, W.n_samples) - counts(ref, W.n_samples))
+    rmse = float(np.sqrt(np.mean((g - ref) ** 2)))
+    say(f"256^3 adaptive f16x3: {N_SAMPLED} sampled leaf cells, rmse={rmse:.2e}, max flipped samples={dc.max()}")
+    assert rmse <= 1e-4
+    assert dc.max() <= 8
