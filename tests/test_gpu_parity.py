@@ -27,6 +27,7 @@ CASES = {
     "trig17": lambda: workloads.field3d_trig(0, m=120, npts=17),
     "cfg1_2d": lambda: workloads.make("cfg1_2d"),
     "aniso21": lambda: workloads.field3d_aniso(1, m=200, npts=21),
+    "cfg2_64": lambda: workloads.make("cfg2_3d", m=200, npts=64),     # the 3D FP32 configuration at full size
     "trig_ragged": lambda: _ragged(),
 }
 
@@ -93,7 +94,7 @@ def test_dense_fp64_matches_oracle(case):
 # BF16x3 carries a 16-bit split (2^-16 per product): it misses the 1e-4 target on fields
 # whose posterior variance is a small fraction of s2, so it is held to 1e-3 only.
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("f16x3", 1e-4), ("bf16x3", 1e-3)])
-@pytest.mark.parametrize("case", ["trig17", "aniso21", "cfg1_2d"])
+@pytest.mark.parametrize("case", ["trig17", "aniso21", "cfg1_2d", "cfg2_64"])
 def test_dense_mixed_rmse(case, prec, tol):
     W = CASES[case]()
     M = oracle.fit(W)
@@ -122,6 +123,7 @@ def test_dense_is_deterministic():
 ADAPT_CASES = {
     "trig33": lambda: workloads.field3d_trig(0, m=200, npts=33),
     "aniso33": lambda: workloads.field3d_aniso(0, m=200, npts=33),
+    "cfg2_64": lambda: workloads.make("cfg2_3d", m=200, npts=64),
     "ragged": lambda: _ragged_adapt(),
     "cfg1_2d_leaf2": lambda: _twod(),
 }
