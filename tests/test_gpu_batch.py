@@ -78,3 +78,35 @@ def test_batch_rejects_singular_model():
     with pytest.raises(lcp.LcpError) as e:
         lcp.GPModelBatch.from_workloads(Ws, DEV)
     assert e.value.status == lcp.lcp.LCP_ENOTPD and "model 1" in str(e.value)
+
+
+def test_batch_full_size_sampled_cells():
+    """The batched configuration at full size: 256 models (m ~ U{64..1024}, grids 16^3 to
+    64^3, FP32) in one lcp_dense_batch call; sampled cells of eight models against the
+    oracle's cell LCP (each model fitted by the oracle alone).
+
+    Binary32 bar: these models have noise / signal variance 1e-4 and up to ~1000 dense
+    observations, so corner covariances near 1e-4 come from differences of terms near 1;
+    binary32 V keeps about two digits of them, and the worst block (m = 979) reaches an LCP
+    RMSE of 4.6e-3.  The binary64 batch matches the oracle's counts exactly (above)."""
+    Ws = workloads.local_blocks(0, nblocks=256)
+    B = lcp.GPModelBatch.from_workloads(Ws, DEV)
+    got, _ = B.lcp_dense([lcp.grid_of(W) for W in Ws], [W.theta for W in Ws], zbank(Ws[0]), "fp32")
+    got = _split(got.cpu().numpy(), Ws)
+    rng = np.random.default_rng(21)
+    ms = np.array([W.m for W in Ws])
+    pick = list(rng.choice(len(Ws), size=6, replace=False)) + [int(ms.argmax()), int(ms.argmin())]
+    for b in pick:
+        W = Ws[b]
+        M = oracle.fit(W)
+        cells = np.stack([rng.integers(0, W.npts[d] - 1, size=150) for d in range(3)], 1)
+        ref = np.empty(len(cells))
+        for i, c in enumerate(cells):
+            mu, S = oracle.cell_moments(M, W, c)
+            ref[i] = oracle.cell_lcp(mu, S, W.theta, W.zbank)
+        field = got[b].reshape(W.cell_shape)
+        g = field[cells[:, 2], cells[:, 1], cells[:, 0]]
+        rmse = float(np.sqrt(np.mean((g - ref) ** 2)))
+        flips = int(np.abs(counts(g, W.n_samples) - counts(ref, W.n_samples)).max())
+        say(f"batch full size: model {b} m={W.m} npts={tuple(W.npts)} rmse={rmse:.2e} max flipped samples={flips}")
+        assert rmse <= 1e-2 and flips <= 80
