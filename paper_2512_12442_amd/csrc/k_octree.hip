@@ -772,7 +772,7 @@ inline unsigned gsz(int64_t n, int per)
 // A factorisation that fails (pivot at or below m' eps (s2 + noise)) gives no bound: the
 // node is refined.
 constexpr int kLocB = 32;        // panel width; also the most right-hand sides per solve
-constexpr int kLocSlots = 768;   // most work-groups of k_local_bound (three per CU), one slot each
+constexpr int kLocSlots = 1024;  // most work-groups of k_local_bound (four per CU), one slot each
 
 struct LocalBufs {
     KParams kp;
@@ -793,8 +793,7 @@ __host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (
 // blocks: y_b = D_b V_b with D_b the inverted diagonal block (Dv), then every row below
 // takes V_i -= L_ib y_b.  L lower row-major in Lm.
 __device__ void local_fsolve(const double* __restrict__ Lm, const double* __restrict__ Dv, double* __restrict__ V,
-                             int ld, int n, int R, double (*ta)[kLocB + 1], double (*tb)[kLocB + 1],
-                             double (*tc)[kLocB + 1])
+                             int ld, int n, int R, double (*ta)[kLocB + 1], double (*tb)[kLocB + 1])
 {
     const int tid = threadIdx.x;
     const int r = tid >> 3, c4 = (tid & 7) * 4;
@@ -813,8 +812,9 @@ __device__ void local_fsolve(const double* __restrict__ Lm, const double* __rest
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[l][c4 + q], acc[q]);
         }
+        __syncthreads();   // every thread has read tb; it now holds the block's solution
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tc[r][c4 + q] = r < nb ? acc[q] : 0.0;
+        for (int q = 0; q < 4; ++q) tb[r][c4 + q] = r < nb ? acc[q] : 0.0;
         if (r < nb)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -827,7 +827,7 @@ __device__ void local_fsolve(const double* __restrict__ Lm, const double* __rest
             for (int l = 0; l < kLocB; ++l) {
                 const double x = Li[l];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) u[q] = fma(x, tc[l][c4 + q], u[q]);
+                for (int q = 0; q < 4; ++q) u[q] = fma(x, tb[l][c4 + q], u[q]);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -861,8 +861,7 @@ __device__ void local_colsum(const double* __restrict__ V, const double* __restr
 // Backward solve L^T W = W for columns [0, R) (rows [0, n)), right-looking from the last
 // block: x_b = D_b^T W_b, then every row above takes W_i -= sum_l L[b + l][i] x_b[l].
 __device__ void local_bsolve(const double* __restrict__ Lm, const double* __restrict__ Dv, double* __restrict__ W,
-                             int ld, int n, int R, double (*ta)[kLocB + 1], double (*tb)[kLocB + 1],
-                             double (*tc)[kLocB + 1])
+                             int ld, int n, int R, double (*ta)[kLocB + 1], double (*tb)[kLocB + 1])
 {
     const int tid = threadIdx.x;
     const int r = tid >> 3, c4 = (tid & 7) * 4;
@@ -881,8 +880,9 @@ __device__ void local_bsolve(const double* __restrict__ Lm, const double* __rest
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = fma(x, tb[l][c4 + q], acc[q]);
         }
+        __syncthreads();   // every thread has read tb; it now holds the block's solution
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tc[r][c4 + q] = r < nb ? acc[q] : 0.0;
+        for (int q = 0; q < 4; ++q) tb[r][c4 + q] = r < nb ? acc[q] : 0.0;
         if (r < nb)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -893,7 +893,7 @@ __device__ void local_bsolve(const double* __restrict__ Lm, const double* __rest
             for (int l = 0; l < nb; ++l) {
                 const double x = Lm[(size_t)(r0 + l) * ld + i];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) u[q] = fma(x, tc[l][c4 + q], u[q]);
+                for (int q = 0; q < 4; ++q) u[q] = fma(x, tb[l][c4 + q], u[q]);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -943,7 +943,7 @@ __device__ void local_coldot(const double* __restrict__ X, const double* __restr
 }
 
 template <int D>
-__global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
+__global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const uint64_t* __restrict__ keys,
                                                      const int32_t* __restrict__ path, BoundBufs B, LocalBufs Lb,
                                                      int32_t* __restrict__ sub)
 {
@@ -952,7 +952,7 @@ __global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const 
     double* xs = lsm;
     double* wv = lsm + (size_t)Lb.ld * D;
     int* sidx = (int*)(wv + Lb.ld);
-    __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1], tc[kLocB][kLocB + 1];
+    __shared__ double ta[kLocB][kLocB + 1], tb[kLocB][kLocB + 1];
     __shared__ double ldg[kLocB];
     __shared__ double red[8][kLocB + 1];
     __shared__ double sums[4][kLocB];
@@ -1051,25 +1051,31 @@ __global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const 
             if (fail) break;
             if (tid < nb) ta[tid][tid] = ldg[tid];
             __syncthreads();
-            // D = L_kk^-1 (identity beyond nb), column c by thread c
+            // D = L_kk^-1 (identity beyond nb) into Dv, column c by thread c, then D into ta
             if (tid < kLocB) {
                 const int cc = tid;
+                double* Dk = Dv + (size_t)k0 * kLocB;
                 for (int a = 0; a < kLocB; ++a) {
                     double v = 0.0;
                     if (a >= cc) {
                         double sacc = a == cc ? 1.0 : 0.0;
-                        for (int q = cc; q < a; ++q) sacc = fma(-ta[a][q], tc[q][cc], sacc);
+                        for (int q = cc; q < a; ++q) sacc = fma(-ta[a][q], Dk[(size_t)q * kLocB + cc], sacc);
                         v = sacc / ta[a][a];
                     }
-                    tc[a][cc] = v;
+                    Dk[(size_t)a * kLocB + cc] = v;
                 }
             }
             __syncthreads();
             for (int t = tid; t < kLocB * kLocB; t += 256) {
                 const int a = t >> 5, bb = t & 31;
-                Dv[(size_t)(k0 + a) * kLocB + bb] = tc[a][bb];
                 if (a < nb && bb <= a) Lm[(size_t)(k0 + a) * ld + k0 + bb] = ta[a][bb];
             }
+            __syncthreads();
+            for (int t = tid; t < kLocB * kLocB; t += 256) {
+                const int a = t >> 5, bb = t & 31;
+                ta[a][bb] = Dv[(size_t)(k0 + a) * kLocB + bb];
+            }
+            __syncthreads();
             // panel: X = A D^T, 32 rows at a time
             {
                 const int r = tid >> 3, c4 = (tid & 7) * 4;
@@ -1084,7 +1090,7 @@ __global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const 
                     for (int l = 0; l < kLocB; ++l) {
                         const double x = tb[r][l];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) acc[q] = fma(x, tc[c4 + q][l], acc[q]);
+                        for (int q = 0; q < 4; ++q) acc[q] = fma(x, ta[c4 + q][l], acc[q]);
                     }
                     if (i0 + r < n)
 #pragma unroll
@@ -1141,7 +1147,7 @@ __global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const 
                 V[(size_t)i * kLocB + 1 + q] = kernel_val(Lb.kp, r2);
             }
             __syncthreads();
-            local_fsolve(Lm, Dv, V, ld, n, 1 + npt, ta, tb, tc);
+            local_fsolve(Lm, Dv, V, ld, n, 1 + npt, ta, tb);
             for (int i = tid; i < n; i += 256) wv[i] = V[(size_t)i * kLocB];
             __syncthreads();
             local_colsum(V, wv, 0, n, 1 + npt, red, sums[0]);      // means
@@ -1167,7 +1173,7 @@ __global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const 
                 // W = L'^-T V, T = A' W; sums[2][c] = w_c . A' w_c
                 for (int t = tid; t < n * kLocB; t += 256) Wm[t] = V[t];
                 __syncthreads();
-                local_bsolve(Lm, Dv, Wm, ld, n, 1 + npt, ta, tb, tc);
+                local_bsolve(Lm, Dv, Wm, ld, n, 1 + npt, ta, tb);
                 local_aprod(Lb.AM, ld, sidx, Wm, Tm, n, 1 + npt);
                 local_coldot(Wm, Tm, true, n, 1 + npt, red, sums[2]);
             }
@@ -1221,14 +1227,14 @@ __global__ void __launch_bounds__(256, 3) k_local_bound(Oct o, int level, const 
                             V[(size_t)i * kLocB + 1 + d] = fv * z[d] * Lb.kp.inv_ell[d] * Lb.kp.inv_ell[d];
                 }
                 __syncthreads();
-                local_fsolve(Lm, Dv, V, ld, n, R, ta, tb, tc);
+                local_fsolve(Lm, Dv, V, ld, n, R, ta, tb);
                 local_colsum(V, wv, 0, n, R, red, sums[0]);       // mu, dmu_d
                 local_colsum(V, nullptr, 0, n, R, red, sums[1]);  // |v|^2, v.u_d
                 if (sparse) {
                     // sums[2][0] = w.A'w, sums[2][1 + d] = (K'^-1 dk_d).A'w
                     for (int t = tid; t < n * kLocB; t += 256) Wm[t] = V[t];
                     __syncthreads();
-                    local_bsolve(Lm, Dv, Wm, ld, n, R, ta, tb, tc);
+                    local_bsolve(Lm, Dv, Wm, ld, n, R, ta, tb);
                     local_aprod(Lb.AM, ld, sidx, Wm, Tm, n, R);
                     local_coldot(Wm, Tm, false, n, R, red, sums[2]);
                 }
