@@ -761,7 +761,8 @@ inline unsigned gsz(int64_t n, int per)
 //
 // Region test on the local model M': the observations inside the node box enlarged by
 // beta lengthscales per axis (the root keeps all of them), conditioned on alone.  One
-// work-group per bound node (persistent over the level's bound list) gathers M' in its
+// work-group per bound node (persistent: a work-group takes the next node from a counter
+// when it finishes one, since \|M'\| and the search's length vary by node) gathers M' in its
 // order in M, builds K' + noise I in its own slot, factors it (blocked Cholesky, 32-wide
 // panels), and runs the search of the full-model path: the {lo, mid, hi}^D lattice (lowest
 // index wins ties), then the projected steps.  Every value comes from forward solves only:
@@ -784,6 +785,7 @@ struct LocalBufs {
     double piv_scale;    // eps (s2 + noise); the pivot floor is m' piv_scale
     double rad[3];       // beta ell_d
     const double* AM;    // sparse model: A_M (ld x ld); null for an exact GP
+    int32_t* next;       // work counter: nodes handed out beyond the first gridDim.x (zeroed per launch)
     double* slots;       // kLocSlots x (ld ld + 4 ld kLocB) doubles: L, V, inverted diagonal blocks, W, T
 };
 
@@ -960,6 +962,7 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
     __shared__ int wcnt[4];
     __shared__ int state;            // 0 searching, 1 decided
     __shared__ int fail;
+    __shared__ int64_t cur;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ld = Lb.ld;
     double* Lm = Lb.slots + (size_t)blockIdx.x * local_slot_doubles(ld);
@@ -971,7 +974,11 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
     const int64_t nb_nodes = B.cnt[0];
     const int npt = D == 3 ? 27 : 9;
     const double s2 = Lb.kp.s2;
-    for (int64_t b = blockIdx.x; b < nb_nodes; b += gridDim.x) {
+    if (tid == 0) cur = blockIdx.x;
+    __syncthreads();
+    for (;;) {
+        const int64_t b = cur;
+        if (b >= nb_nodes) break;
         const int32_t f = B.bnode[b];
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
@@ -1279,6 +1286,7 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
             B.side[b] = side;
             B.gmin[b] = gmin;
             sub[f] = upper_bound(gmin, dp) > o.alpha ? 1 : 0;
+            cur = (int64_t)gridDim.x + atomicAdd(Lb.next, 1);
         }
         __syncthreads();
     }
@@ -1294,7 +1302,7 @@ struct AdaptLayout {
     size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_lcnt, o_loff;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
-    size_t o_loc;                        // local-model bound only: per-work-group slots
+    size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
     int64_t capF, nv;
 };
 
@@ -1387,7 +1395,10 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         L.o_box = take(8 * 2 * (size_t)D * capF);
         L.o_cert = take(32 * (size_t)capF);
     }
-    if (bound_kind == LCP_BOUND_LOCAL) L.o_loc = take(8 * local_slot_doubles(M.m_pad) * kLocSlots);
+    if (bound_kind == LCP_BOUND_LOCAL) {
+        L.o_lnext = take(256);
+        L.o_loc = take(8 * local_slot_doubles(M.m_pad) * kLocSlots);
+    }
     L.total = o;
     L.capF = capF;
     L.nv = nv;
@@ -1535,6 +1546,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             for (int d = 0; d < 3; ++d) lb.rad[d] = d < D ? A.beta * M.k.lengthscale[d] : 0.0;
             lb.AM = M.sparse ? M.AM : nullptr;
             lb.slots = (double*)P(L.o_loc);
+            lb.next = (int32_t*)P(L.o_lnext);
+            if ((e = launch_fill_i32(lb.next, 0, 1, s)) != hipSuccess) return e;
             StageScope sc(s, ST_BOUND);
             // a persistent grid of the work-groups that are resident together (at most kLocSlots)
             const size_t shm = (size_t)M.m_pad * (D + 1) * sizeof(double) + (size_t)M.m_pad * sizeof(int);
