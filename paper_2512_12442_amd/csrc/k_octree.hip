@@ -1058,29 +1058,30 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
             if (fail) break;
             if (tid < nb) ta[tid][tid] = ldg[tid];
             __syncthreads();
-            // D = L_kk^-1 (identity beyond nb) into Dv, column c by thread c, then D into ta
+            // D = L_kk^-1 (identity beyond nb) into tb, column c by thread c; then L_kk and D
+            // to the slot, and D into ta for the panel
             if (tid < kLocB) {
                 const int cc = tid;
-                double* Dk = Dv + (size_t)k0 * kLocB;
                 for (int a = 0; a < kLocB; ++a) {
                     double v = 0.0;
                     if (a >= cc) {
                         double sacc = a == cc ? 1.0 : 0.0;
-                        for (int q = cc; q < a; ++q) sacc = fma(-ta[a][q], Dk[(size_t)q * kLocB + cc], sacc);
+                        for (int q = cc; q < a; ++q) sacc = fma(-ta[a][q], tb[q][cc], sacc);
                         v = sacc / ta[a][a];
                     }
-                    Dk[(size_t)a * kLocB + cc] = v;
+                    tb[a][cc] = v;
                 }
             }
             __syncthreads();
             for (int t = tid; t < kLocB * kLocB; t += 256) {
                 const int a = t >> 5, bb = t & 31;
+                Dv[(size_t)(k0 + a) * kLocB + bb] = tb[a][bb];
                 if (a < nb && bb <= a) Lm[(size_t)(k0 + a) * ld + k0 + bb] = ta[a][bb];
             }
             __syncthreads();
             for (int t = tid; t < kLocB * kLocB; t += 256) {
                 const int a = t >> 5, bb = t & 31;
-                ta[a][bb] = Dv[(size_t)(k0 + a) * kLocB + bb];
+                ta[a][bb] = tb[a][bb];
             }
             __syncthreads();
             // panel: X = A D^T, 32 rows at a time
