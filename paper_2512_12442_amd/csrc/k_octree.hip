@@ -1050,8 +1050,18 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
                 if (tid == j) ldg[j] = ljj;
                 if (tid > j && tid < nb) ta[tid][j] /= ljj;
                 __syncthreads();
-                if (tid > j && tid < nb)
-                    for (int cc = j + 1; cc <= tid; ++cc) ta[tid][cc] = fma(-ta[tid][j], ta[cc][j], ta[tid][cc]);
+                {
+                    // rank-1 update of the trailing part of the block: four entries per thread
+                    const int rr = tid >> 3, c4 = (tid & 7) * 4;
+                    if (rr > j && rr < nb) {
+                        const double lr = ta[rr][j];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int cc = c4 + q;
+                            if (cc > j && cc <= rr) ta[rr][cc] = fma(-lr, ta[cc][j], ta[rr][cc]);
+                        }
+                    }
+                }
                 __syncthreads();
             }
             __syncthreads();
