@@ -1625,7 +1625,7 @@ static void key_decode(int D, uint64_t key, int* level, int64_t* c)
             c[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
 }
 
-/* LCP of every cell inside the given leaves (only these are reconstructed); each
+/* LCP of every cell inside the given leaves (end of Sec. 5.3: only these are reconstructed); each
  * cell is computed exactly as in the dense path.  lcp covers the whole cell grid and
  * is written only inside leaves. */
 int orc_lcp_leaves(const orc_model* M, const orc_grid* G, double theta, int ns, const double* zb,

@@ -78,8 +78,13 @@ __device__ __forceinline__ double exp_nonpos(double x)
     return ldexp(p, (int)n);
 }
 
-// sqrt(x) for x >= 0 in binary64: hardware reciprocal square root refined by two coupled
-// Newton steps and a final residual correction (x = 0 gives 0).
+// sqrt(x) for x >= 0 in binary64 (x = 0 gives 0).  Goldschmidt's coupled iteration for
+// s -> sqrt(x) and h -> 1 / (2 sqrt(x)) (R. E. Goldschmidt, "Applications of division by
+// convergence", MIT, 1964; in the form of P. Markstein, "IA-64 and Elementary Functions",
+// 2000, ch. 9): start from the hardware reciprocal square root y, s = x y, h = y / 2; each
+// step forms e = 1/2 - h s and sets s += s e, h += h e, which doubles the correct bits.
+// Two steps from the ~23-bit seed, then one Newton correction s += (x - s^2) h from the
+// exact residual (fma), which rounds to within an ulp.
 __device__ __forceinline__ double sqrt_nonneg(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);

@@ -14,7 +14,7 @@ import torch
 import oracle
 import workloads
 import paper_2512_12442_amd as lcp
-from parity_util import DEV, counts, gpu_model, say, zbank
+from parity_util import DEV, compare_adaptive, counts, gpu_model, say, zbank
 
 pytestmark = pytest.mark.gpu
 
@@ -106,19 +106,11 @@ def test_adaptive_certified_matches_oracle(case):
     n = int(nl.item())
     got = leaves[:n].cpu().numpy().astype(np.uint64)
     ties = _near(recs, W.alpha)
-    sym = set(map(int, got)) ^ set(map(int, leaves_ref))
-    say(f"  leaves gpu={n} oracle={len(leaves_ref)} (search {len(leaves_search)}) differ={len(sym)} "
-        f"near-ties={len(ties)}")
     assert set(map(int, leaves_search)) <= set(map(int, leaves_ref))
     assert np.all(np.diff(got.astype(np.int64)) > 0)
-    for k in sym:
-        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
-    if not sym:
-        ref = oracle.lcp_leaves(M, W, leaves_ref).reshape(-1)
-        dc = counts(out.cpu().numpy(), W.n_samples) - counts(ref, W.n_samples)
-        assert np.count_nonzero(dc) == 0
-        lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref])).reshape(-1)
-        assert np.array_equal(lf.cpu().numpy(), lev_ref)
+    sym, excused = compare_adaptive(W, M, out.cpu().numpy(), got, lf.cpu().numpy(), leaves_ref, skipped_ref, ties)
+    say(f"  leaves gpu={n} oracle={len(leaves_ref)} (search {len(leaves_search)}) differ={len(sym)} "
+        f"near-ties={len(ties)} excused cells={int(excused.sum())}")
 
 
 def test_adaptive_certified_contains_gpu_search_leaves_and_equals_dense_inside():

@@ -9,7 +9,7 @@ import torch
 import oracle
 import workloads
 import paper_2512_12442_amd as lcp
-from parity_util import DEV, counts, gpu_model, mean_error_bound32, near_tie_keys, say, zbank
+from parity_util import DEV, compare_adaptive, counts, gpu_model, mean_error_bound32, near_tie_keys, say, zbank
 
 pytestmark = pytest.mark.gpu
 
@@ -72,19 +72,16 @@ def test_full_size_adaptive_f16x3_leaf_set_and_sampled_cells(full):
     got_keys = leaves[:n].cpu().numpy().astype(np.uint64)
     leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4)
     ties = near_tie_keys(recs, W.alpha)
-    sym = set(map(int, got_keys)) ^ set(map(int, leaves_ref))
-    say(f"128^3 adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)}")
     assert np.all(np.diff(got_keys.astype(np.int64)) > 0)
-    for k in sym:
-        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
+    sym, excused = compare_adaptive(W, M, None, got_keys, lf.cpu().numpy(), leaves_ref, skipped_ref, ties,
+                                    counts_exact=False)
+    say(f"128^3 adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
+        f"excused cells={int(excused.sum())}")
 
     # every cell outside the GPU's leaves is zero; sampled leaf cells match the oracle
     inleaf = oracle.level_field(W, got_keys) != 255
     field = out.cpu().numpy().reshape(W.cell_shape)
     assert np.all(field[~inleaf] == 0)
-    if not sym:
-        lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref]))
-        assert np.array_equal(lf.cpu().numpy().reshape(W.cell_shape), lev_ref)
     cand = np.argwhere(inleaf)                       # (z, y, x)
     pick = cand[np.random.default_rng(13).choice(len(cand), size=N_SAMPLED, replace=False)]
     cells = pick[:, ::-1]
@@ -108,16 +105,13 @@ def test_full_size_adaptive_local_bound_leaf_set(full):
     leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4,
                                                     bound_kind=oracle.BOUND_LOCAL, beta=6.0)
     ties = near_tie_keys(recs, W.alpha)
-    sym = set(map(int, got_keys)) ^ set(map(int, leaves_ref))
     tested = recs["n_local"] >= 0
-    say(f"128^3 local bound: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
-        f"region tests={tested.sum()} mean |M'|={recs['n_local'][tested].mean():.1f}")
     assert np.all(np.diff(got_keys.astype(np.int64)) > 0)
-    for k in sym:
-        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
-    if not sym:
-        lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref]))
-        assert np.array_equal(lf.cpu().numpy().reshape(W.cell_shape), lev_ref)
+    sym, excused = compare_adaptive(W, M, None, got_keys, lf.cpu().numpy(), leaves_ref, skipped_ref, ties,
+                                    counts_exact=False)
+    say(f"128^3 local bound: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
+        f"excused cells={int(excused.sum())} region tests={tested.sum()} "
+        f"mean |M'|={recs['n_local'][tested].mean():.1f}")
     field = out.cpu().numpy().reshape(W.cell_shape)
     assert np.all(field[oracle.level_field(W, got_keys) == 255] == 0)
 
@@ -136,13 +130,12 @@ def test_full_size_256_adaptive_leaf_set_and_sampled_cells():
     field = out.cpu().numpy().reshape(W.cell_shape)
     del out
     say(f"256^3 adaptive: {n} leaves on the GPU; running the oracle's Alg. 1")
-    leaves_ref, _, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4)
+    leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4)
     ties = near_tie_keys(recs, W.alpha)
-    sym = set(map(int, got_keys)) ^ set(map(int, leaves_ref))
-    say(f"256^3 adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)}")
     assert np.all(np.diff(got_keys.astype(np.int64)) > 0)
-    for k in sym:
-        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
+    sym, excused = compare_adaptive(W, M, None, got_keys, None, leaves_ref, skipped_ref, ties, counts_exact=False)
+    say(f"256^3 adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
+        f"excused cells={int(excused.sum())}")
     inleaf = oracle.level_field(W, got_keys) != 255
     assert np.all(field[~inleaf] == 0)
     cand = np.argwhere(inleaf)

@@ -10,7 +10,7 @@ import pytest
 import oracle
 import workloads
 import paper_2512_12442_amd as lcp
-from parity_util import counts, gpu_model, near_tie_keys, say, zbank
+from parity_util import compare_adaptive, counts, gpu_model, near_tie_keys, say, zbank
 
 pytestmark = pytest.mark.gpu
 
@@ -55,25 +55,12 @@ def test_local_bound_matches_oracle(case, beta, split):
     leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, bound_kind=oracle.BOUND_LOCAL, beta=beta, split=split)
     out, got, lf = _run(W, beta, split)
     ties = near_tie_keys(recs, W.alpha)
-    sym = set(map(int, got)) ^ set(map(int, leaves_ref))
     tested = recs["n_local"] >= 0
-    say(f"  leaves gpu={len(got)} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
-        f"region tests={tested.sum()} mean |M'|={recs['n_local'][tested].mean():.1f} "
-        f"min |M'|={recs['n_local'][tested].min()}")
     assert np.all(np.diff(got.astype(np.int64)) > 0)
-    per = W.dim if split else 1
-    for k in sym:
-        depth = (k >> 58) * per
-        assert any((t >> 58) <= depth for t in ties), hex(k)
-    if not sym:
-        ref = oracle.lcp_leaves(M, W, leaves_ref).reshape(-1)
-        dc = counts(out, W.n_samples) - counts(ref, W.n_samples)
-        assert np.count_nonzero(dc) == 0
-        if split:
-            lev_ref = oracle.level_field_kd(W, np.concatenate([oracle.kd_leaf_keys(W, leaves_ref), skipped_ref]))
-        else:
-            lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref]))
-        assert np.array_equal(lf, lev_ref.reshape(-1))
+    sym, excused = compare_adaptive(W, M, out, got, lf, leaves_ref, skipped_ref, ties, split=split)
+    say(f"  leaves gpu={len(got)} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
+        f"excused cells={int(excused.sum())} region tests={tested.sum()} "
+        f"mean |M'|={recs['n_local'][tested].mean():.1f} min |M'|={recs['n_local'][tested].min()}")
 
 
 def test_local_with_huge_beta_is_the_full_model_search():

@@ -19,7 +19,7 @@ import torch
 import oracle
 import workloads
 import paper_2512_12442_amd as lcp
-from parity_util import DEV, counts, gpu_model, mean_error_bound32, near_tie_keys, say, zbank
+from parity_util import DEV, compare_adaptive, counts, gpu_model, mean_error_bound32, near_tie_keys, say, zbank
 
 pytestmark = pytest.mark.gpu
 
@@ -153,20 +153,12 @@ def test_adaptive_fp64_matches_oracle(case):
     n = int(nl.item())
     got = leaves[:n].cpu().numpy().astype(np.uint64)
     ties = near_tie_keys(recs, W.alpha)
-    sym = set(map(int, got)) ^ set(map(int, leaves_ref))
-    say(f"  leaves gpu={n} oracle={len(leaves_ref)} skipped={len(skipped_ref)} differ={len(sym)} near-ties={len(ties)}")
     assert np.all(np.diff(got.astype(np.int64)) > 0)          # canonical ascending order
-    # a differing leaf must descend from a near-tie node
-    for k in sym:
-        lvl = k >> 58
-        assert any((t >> 58) <= lvl for t in ties), hex(k)
-    if not sym:
-        ref = oracle.lcp_leaves(M, W, leaves_ref).reshape(-1)
-        gotl = out.cpu().numpy()
-        dc = counts(gotl, W.n_samples) - counts(ref, W.n_samples)
-        assert np.count_nonzero(dc) == 0
-        lev_ref = oracle.level_field(W, np.concatenate([leaves_ref, skipped_ref])).reshape(-1)
-        assert np.array_equal(lf.cpu().numpy(), lev_ref)
+    # a differing leaf must lie inside a near-tie node; outside those nodes the counts and
+    # the level field must still be identical
+    sym, excused = compare_adaptive(W, M, out.cpu().numpy(), got, lf.cpu().numpy(), leaves_ref, skipped_ref, ties)
+    say(f"  leaves gpu={n} oracle={len(leaves_ref)} skipped={len(skipped_ref)} differ={len(sym)} "
+        f"near-ties={len(ties)} excused cells={int(excused.sum())}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "f16x3", "bf16x3"])

@@ -12,7 +12,7 @@ import torch
 import oracle
 import workloads
 import paper_2512_12442_amd as lcp
-from parity_util import DEV, counts, near_tie_keys, say, zbank
+from parity_util import DEV, compare_adaptive, counts, near_tie_keys, say, zbank
 
 pytestmark = pytest.mark.gpu
 
@@ -95,15 +95,10 @@ def test_sgpr_adaptive_fp64_matches_oracle(case):
     n = int(nl.item())
     got = leaves[:n].cpu().numpy().astype(np.uint64)
     ties = near_tie_keys(recs, W.alpha)
-    sym = set(map(int, got)) ^ set(map(int, leaves_ref))
-    say(f"  leaves gpu={n} oracle={len(leaves_ref)} skipped={len(skipped_ref)} differ={len(sym)} near-ties={len(ties)}")
     assert len(leaves_ref) > 0 and len(skipped_ref) > 0
-    for k in sym:
-        assert any((t >> 58) <= (k >> 58) for t in ties), hex(k)
-    if not sym:
-        ref = oracle.lcp_leaves(M, W, leaves_ref).reshape(-1)
-        dc = counts(out.cpu().numpy(), W.n_samples) - counts(ref, W.n_samples)
-        assert np.count_nonzero(dc) == 0
+    sym, excused = compare_adaptive(W, M, out.cpu().numpy(), got, lf.cpu().numpy(), leaves_ref, skipped_ref, ties)
+    say(f"  leaves gpu={n} oracle={len(leaves_ref)} skipped={len(skipped_ref)} differ={len(sym)} "
+        f"near-ties={len(ties)} excused cells={int(excused.sum())}")
 
 
 def test_sgpr_with_inducing_set_equal_to_data_equals_exact_gp_path():

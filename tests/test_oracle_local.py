@@ -166,3 +166,37 @@ def test_octree_local_records_count_the_enlarged_box(beta):
         assert r["n_local"] == want, (hex(int(r["key"])), r["n_local"], want)
         n += 1
     assert n > 20
+
+
+def test_local_factor_failure_refines_the_node():
+    """R14 / Alg. 1: a node whose local model cannot be factored has no bound and must be
+    refined (a skipped node would need a bound).  Two identical observations make every
+    local K' that holds both singular once the local fit runs without noise; the stored
+    full factor is the one with noise, so the preliminary test and the rest of the tree are
+    unchanged.  Every record that reached the region test with a failed local fit (no
+    |M'| recorded) must carry g_min = -inf, UB = 1 and be subdivided, and exactly those
+    records are the ones whose enlarged box holds the duplicated point."""
+    W = small(190, 3, 30, 9, signal_var=0.05, ell=0.2, noise_var=1e-4, min_leaf=1)
+    W.X[1] = W.X[0]
+    W.y[0] = W.y[1] = W.theta + 3.0
+    M = oracle.fit(W)
+    M.s.noise = 0.0                 # local fits only: K' + 0 I is singular with both copies
+    beta = 0.5
+    leaves, skipped, recs = oracle.adaptive(M, W, bound_kind=oracle.BOUND_LOCAL, beta=beta)
+    S0, L = oracle.octree_shape(W)
+    tested = recs[np.isin(recs["path"], [1, 2])]
+    failed = tested[tested["n_local"] == -1]
+    assert len(failed) >= 5
+    assert (failed["subdivide"] == 1).all() and (failed["ub"] == 1.0).all()
+    assert np.isneginf(failed["gmin"]).all()
+    ell = W.lengthscale[:3]
+    for r in tested:
+        lvl = int(r["level"])
+        mc = int(r["key"]) & ((1 << 58) - 1)
+        c = [sum(((mc >> (b * 3 + d)) & 1) << b for b in range(lvl)) for d in range(3)]
+        s = S0 >> lvl
+        lo = np.array([c[d] * s for d in range(3)])
+        hi = np.minimum(lo + s, W.npts[:3] - 1)
+        h = 1.0 / (W.npts[0] - 1)
+        dup = _select(W.X[:1], lo * h, hi * h, beta, ell)[0] or lvl == 0
+        assert dup == (r["n_local"] == -1), (lvl, c)

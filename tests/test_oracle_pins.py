@@ -431,3 +431,51 @@ def test_adaptive_decisions_follow_alg1():
     sub = {int(r["key"]) for r in recs if r["subdivide"] and r["level"] == L}
     assert sub == {int(k) for k in leaves}
     assert {int(r["key"]) for r in recs if not r["subdivide"]} == {int(k) for k in skipped}
+
+
+def _g_single_obs(r, y0, theta, side, s2, noise, ell):
+    """Standardised margin of Sec. 5.1 for an SE model with one observation at scaled
+    distance r/ell, from the m = 1 closed form of eq. (sgp) (no oracle code)."""
+    k = s2 * np.exp(-0.5 * (np.asarray(r, float) / ell) ** 2)
+    mu = k * y0 / (s2 + noise)
+    var = s2 - k * k / (s2 + noise)
+    return side * (theta - mu) / np.sqrt(var)
+
+
+@pytest.mark.parametrize("side,y0,theta,lo,w", [(1.0, 1.0, 0.2, 0.0, 1.0), (-1.0, -1.0, -0.2, 0.0, 1.0),
+                                                 (1.0, 1.0, 0.2, 0.1, 0.5)])
+def test_bound_descent_follows_the_schedule_to_an_interior_minimum(side, y0, theta, lo, w):
+    """The search of reading S12 on a box whose minimum of g is interior and off the
+    {lo, mid, hi} lattice: one observation x0 (SE, isotropic) makes g radial around x0, so
+    the normalised box-scaled step on a cube of width w moves straight towards x0 by
+    eta_k w = 2^-(k+1) w.  The signed distance along the line then follows
+    s_{k+1} = s_k - 2^-(k+1) w sign(s_k) from s_0 = |x0 - best lattice point|, and the search
+    must return min(g(lattice), g(|s_1|), ..., g(|s_T|)) from the m = 1 closed form.  A
+    wrong sign walks away from x0 and leaves the lattice value; a wrong step schedule or
+    normalisation lands at other distances.  g(x0) is the box's minimum (checked on a
+    41^3 brute-force grid), and the search never goes below it."""
+    s2, noise, ell = 1.0, 1e-4, 0.15
+    x0 = lo + w * np.array([0.314, 0.357, 0.628])
+    M = oracle.FitModel(workloads.SE, 3, s2, [ell] * 3, noise, x0[None, :], np.array([y0]))
+    blo, bhi = np.full(3, lo), np.full(3, lo + w)
+    lat = np.array([[lo + 0.5 * w * ((i // 3 ** d) % 3) for d in range(3)] for i in range(27)])
+    g_lat = _g_single_obs(np.linalg.norm(lat - x0, axis=1), y0, theta, side, s2, noise, ell)
+    p0 = lat[int(np.argmin(g_lat))]
+    assert np.allclose(p0, lo + 0.5 * w)           # the centre is the lattice point nearest x0
+    s = np.linalg.norm(p0 - x0)
+    visited = [g_lat.min()]
+    for k in range(4):
+        s = s - 0.5 ** (k + 1) * w * np.sign(s)
+        visited.append(float(_g_single_obs(abs(s), y0, theta, side, s2, noise, ell)))
+        gmin, _ = oracle.bound(M, theta, side, blo, bhi, steps=k + 1)
+        want = min(visited)
+        assert abs(gmin - want) <= 1e-9 * abs(want) + 1e-12, (k, gmin, want)
+    g0, _ = oracle.bound(M, theta, side, blo, bhi, steps=0)
+    assert abs(g0 - g_lat.min()) <= 1e-12 * max(1.0, abs(g0))
+    assert gmin < g0 - 5.0                         # the descent found the interior basin
+    # the true minimum is g(x0): every point of a 41^3 brute-force grid is above it
+    t = np.linspace(lo, lo + w, 41)
+    P = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    g_true = float(_g_single_obs(0.0, y0, theta, side, s2, noise, ell))
+    g_grid = _g_single_obs(np.linalg.norm(P - x0, axis=1), y0, theta, side, s2, noise, ell).min()
+    assert g_true <= g_grid and g_true <= gmin
