@@ -6,7 +6,7 @@
  * the GP posterior at grid vertices (Sec. 3, eq. (sgp) in its exact-GP form), the
  * per-cell level-crossing probability by Monte Carlo (Sec. 4), and the regional
  * upper bound of eq. (upper_bound) driving the octree query of Alg. 1 (Sec. 5.1,
- * 4.3), with reconstruction only inside the emitted nodes (end of Sec. 5.3).
+ * 5.3), with reconstruction only inside the emitted nodes (end of Sec. 5.3).
  *
  * Conventions
  *  - Every pointer argument is a DEVICE pointer unless its comment says "host".
@@ -16,8 +16,9 @@
  *    on it; only the gp_fit_* calls synchronise it (to read the factorisation
  *    status).  Calls that share a model or workspace must not run concurrently.
  *  - The library never allocates device memory: the caller passes the model
- *    memory and a workspace, sized by lcp_model_bytes / lcp_workspace_bytes, and
- *    keeps them alive while any enqueued work may still use them.
+ *    memory and a workspace, sized by lcp_model_bytes / lcp_*_workspace, and
+ *    keeps them alive while any enqueued work may still use them.  The one fixed
+ *    device array the library holds serves lcp_dense_noalloc only.
  *  - Every call returns an lcp_status.  Arguments are validated on the host before
  *    anything is enqueued; on error nothing is enqueued and lcp_last_error()
  *    describes the problem (thread-local string, valid until the next call).
@@ -340,6 +341,26 @@ int lcp_backward_workspace(const lcp_model* model, const lcp_grid* grid, int pre
 int lcp_backward(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec,
                  const double* dL_dlcp, double* dL_dy, double* dL_dloglen, void* ws, size_t ws_bytes,
                  void* stream);
+
+/*
+ * lcp_dense_noalloc -- lcp_dense without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Arguments and results are those of lcp_dense; the workspace is
+ * a fixed device array inside the library of LCP_NOALLOC_SCRATCH_BYTES bytes per device,
+ * held from library load until the process ends.  Nothing is allocated or freed: the call
+ * takes the array's device address once per device (on its first call there, with that
+ * device current) and then only enqueues work.
+ *   Limit: grids whose lcp_dense_workspace size exceeds LCP_NOALLOC_SCRATCH_BYTES return
+ *   LCP_ENOMEM before anything is enqueued (with FP32 operands and m = 500: about 31^3
+ *   vertices).  The model must live on the current device (LCP_EINVAL otherwise).
+ *   Every call on one device shares that device's array and leaves its contents behind;
+ *   the call itself clears what it needs at zero.  Calls that overlap on one device (two
+ *   streams, or two host threads) race on the array and give undefined results: order them
+ *   on one stream or serialise them.
+ */
+#define LCP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lcp_dense_noalloc(const lcp_model* model, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec,
+                      float* lcp, void* stream);
 
 /*
  * Stage timer (tracing).  lcp_profile_begin(mask) enables it for the stages whose bit is

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -570,6 +571,65 @@ int lcp_backward(const lcp_model* M, const lcp_grid* grid, double theta, const l
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------ allocation-free dense evaluation
+
+namespace {
+
+// Scratch of lcp_dense_noalloc: a file-scope device array that every call on a device
+// shares (each device holds its own copy for the life of the process).  Host code must
+// not pass `scratch` itself to a kernel: its host-side name is not a device address.
+// The device address comes from hipGetSymbolAddress, once per device, with that device
+// current, and only that address is used.
+constexpr size_t kNoallocBytes = LCP_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dev_fail(e, "lcp_dense_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(LCP_EDEVICE, "lcp_dense_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return dev_fail(e, "lcp_dense_noalloc: hipGetSymbolAddress");
+        if (!p || !aligned256(p)) return fail(LCP_EDEVICE, "lcp_dense_noalloc: scratch address not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LCP_OK;
+}
+
+}  // namespace
+
+extern "C" int lcp_dense_noalloc(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_mc* mc, int prec,
+                                 float* lcp, void* stream)
+{
+    if (!M) return fail(LCP_EINVAL, "model is NULL");
+    if (check_prec(prec)) return LCP_EINVAL;
+    GridP g;
+    if (int r = check_grid(M, grid, &g)) return r;
+    if (int r = check_mc(M, mc)) return r;
+    if (M->device >= 0) {
+        int dev = -1;
+        if (hipGetDevice(&dev) == hipSuccess && dev != M->device)
+            return fail(LCP_EINVAL, "lcp_dense_noalloc: the model lives on device %d, device %d is current", M->device,
+                        dev);
+    }
+    const size_t need = dense_ws(M, g, prec, mc->n_samples);
+    if (need > kNoallocBytes)
+        return fail(LCP_ENOMEM, "lcp_dense_noalloc: this grid needs %zu bytes of scratch, the fixed maximum is %zu",
+                    need, kNoallocBytes);
+    void* ws = nullptr;
+    if (int r = scratch_of_current_device(&ws)) return r;
+    return lcp_dense(M, grid, theta, mc, prec, lcp, ws, kNoallocBytes, stream);
+}
 
 // ---------------------------------------------------------------- batches of models
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblcp.so")
 
 LCP_OK, LCP_EINVAL, LCP_ENOTPD, LCP_ECAPACITY, LCP_ENOMEM, LCP_EDEVICE, LCP_ENOTSUPPORTED = range(7)
 FP64, FP32, MIXED_BF16X3, MIXED_F16X3 = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 64 << 20     # LCP_NOALLOC_SCRATCH_BYTES of lcp.h
 SE, MATERN52 = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": MIXED_BF16X3, "f16x3": MIXED_F16X3}
 
@@ -58,7 +59,7 @@ EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor
            "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
            "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward",
-           "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified"]
+           "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified", "lcp_dense_noalloc"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -89,6 +90,7 @@ def lib():
     L.lcp_adaptive_workspace.argtypes = [P, P, P, C.c_int, C.c_int, C.POINTER(SZ)]
     L.gp_posterior.argtypes = [P, I64, P, C.c_int, P, P, P, SZ, P]
     L.lcp_dense.argtypes = [P, P, C.c_double, P, C.c_int, P, P, SZ, P]
+    L.lcp_dense_noalloc.argtypes = [P, P, C.c_double, P, C.c_int, P, P]
     L.lcp_adaptive.argtypes = [P, P, C.c_double, P, P, C.c_int, P, P, I64, P, P, P, SZ, P]
     L.lcp_backward.argtypes = [P, P, C.c_double, P, C.c_int, P, P, P, P, SZ, P]
     L.lcp_backward_workspace.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(SZ)]
@@ -259,6 +261,17 @@ class GPModel:
         _check(lib().lcp_dense(self.h, C.byref(grid), float(theta), C.byref(mc), _prec(prec), _ptr(out), _ptr(ws),
                                ws.numel(), _stream()))
         return out, ws
+
+    def lcp_dense_noalloc(self, grid: Grid, theta: float, zbank: torch.Tensor, out: torch.Tensor, prec="fp64",
+                          estimator=EST_COUNT):
+        """lcp_dense on the library's fixed scratch: no workspace; `out` (one binary32 per
+        cell) and a binary64 z-bank on the device are the caller's."""
+        if zbank.dtype != torch.float64 or not zbank.is_contiguous():
+            raise ValueError("zbank must be a contiguous float64 device tensor")
+        mc = MC(int(zbank.shape[0]), zbank.data_ptr(), int(estimator))
+        _check(lib().lcp_dense_noalloc(self.h, C.byref(grid), float(theta), C.byref(mc), _prec(prec), _ptr(out),
+                                       _stream()))
+        return out
 
     def lcp_adaptive(self, grid: Grid, theta: float, adapt: Adapt, zbank: torch.Tensor, prec="bf16x3", leaf_cap=None,
                      level_field=True, out=None, ws=None, leaves=None, n_leaves=None):

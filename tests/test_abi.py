@@ -140,3 +140,15 @@ def test_batch_model_bytes_and_validation():
     b = C.c_size_t()
     assert L.lcp_dense_batch_workspace(None, None, 0, 1600, C.byref(b)) == lcp.lcp.LCP_EINVAL
     assert L.lcp_dense_batch(None, None, None, None, 0, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+
+
+def test_noalloc_scratch_size_matches_header():
+    src = open(os.path.join(ROOT, "include", "lcp.h")).read()
+    m = re.search(r"#define LCP_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == lcp.lcp.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_null_model_on_the_host():
+    L = lcp.lib()
+    assert L.lcp_dense_noalloc(None, None, 0.0, None, 0, None, None) == lcp.lcp.LCP_EINVAL
+    assert "model is NULL" in L.lcp_last_error().decode()
