@@ -24,6 +24,7 @@ size_t model_bytes(int m)
     b += 2 * align256(sizeof(double) * mp);          // obs_mu, obs_var
     b += 256;                                        // info
     b += align256(sizeof(double) * (size_t)mp * mp); // A_M (sparse model)
+    b += align256(sizeof(double) * mp * 4);          // Xs
     return b;
 }
 
@@ -34,6 +35,20 @@ __global__ void k_pack(const double* __restrict__ X, const double* __restrict__ 
     if (i >= mp) return;
     for (int d = 0; d < 4; ++d) Xp[i * 4 + d] = (i < m && d < dim) ? X[(int64_t)i * dim + d] : 0.0;
     w[i] = i < m ? y[i] : 0.0;
+}
+
+// Observations scaled by the inverse lengthscales, with a_j in the fourth slot: what the
+// split-product posterior reads per row.  Rows past m sit 1e15 lengthscales away on every
+// axis with a_j = 0: their binary32 kernel values underflow to exactly 0 (and stay finite
+// on the way), as the zero rows of B they stand for.
+__global__ void k_scaled_obs(KParams kp, const double* __restrict__ Xp, const double* __restrict__ a, int m, int mp,
+                             double* __restrict__ Xs)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mp) return;
+    for (int d = 0; d < 3; ++d)
+        Xs[i * 4 + d] = i < m ? (d < kp.dim ? mul_rn(Xp[i * 4 + d], kp.inv_ell[d]) : 0.0) : 1e15;
+    Xs[i * 4 + 3] = i < m ? a[i] : 0.0;
 }
 
 __global__ void k_build_K(KParams kp, const double* __restrict__ Xp, int m, int mp, double noise,
@@ -568,6 +583,7 @@ static void carve(Model& M, char* base)
     M.obs_var = (double*)take(sizeof(double) * mp);
     M.info = (int*)take(256);
     M.AM = (double*)take(sizeof(double) * (size_t)mp * mp);
+    M.Xs = (double*)take(sizeof(double) * mp * 4);
 }
 
 static double* ybuf(const Model& M)
@@ -601,6 +617,8 @@ hipError_t launch_factor_finish(Model& M, hipStream_t s)
     hipError_t e0 = launch_trinv_blocked(M.U, M.Linv, mp, M.amax, s);
     if (e0 != hipSuccess) return e0;
     hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, s, M.Linv, ybuf(M), M.a, M.m, mp);
+    hipLaunchKernelGGL(k_scaled_obs, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, M.kp, M.X, M.a, M.m, mp,
+                       M.Xs);
     hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, mp, M.A64, M.A32,
                        M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
     hipError_t e = hipGetLastError();
@@ -630,6 +648,8 @@ hipError_t launch_sparse_e(Model& M, const double* A, double delta, bool first, 
         hipError_t e0 = launch_trinv_blocked(M.U, M.Linv, mp, M.amax, s);
         if (e0 != hipSuccess) return e0;
         hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, s, M.Linv, ybuf(M), M.a, m, mp);
+        hipLaunchKernelGGL(k_scaled_obs, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, M.kp, M.X, M.a, m, mp,
+                           M.Xs);
         hipLaunchKernelGGL(k_obs_sparse, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, ybuf(M), A, m,
                            M.obs_mu, M.obs_var);
         hipLaunchKernelGGL(k_pack_square, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, A, m, mp, M.A64);
@@ -706,6 +726,8 @@ hipError_t launch_factor_batch_finish(Model* const* Ms, int nb, char* scratch, h
     for (int b = 0; b < nb; ++b) {
         Model& M = *Ms[b];
         const int64_t n2 = (int64_t)M.m_pad * M.m_pad;
+        hipLaunchKernelGGL(k_scaled_obs, dim3((unsigned)ceil_div(M.m_pad, 256)), dim3(256), 0, s, M.kp, M.X, M.a, M.m,
+                           M.m_pad, M.Xs);
         hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, M.m_pad, M.A64, M.A32,
                            M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
     }

@@ -9,9 +9,10 @@
 // rows of consecutive columns reads contiguous memory; inside a 16-row block the rows
 // follow the MFMA result registers, a fixed permutation that dot products of V columns
 // do not see.
-// Row blocks of 16 are dealt to the four waves in a balanced (snake) order; every column's
-// result depends only on that column, so a vertex gets bitwise the same numbers whatever
-// tile or launch it is computed in.
+// In k_post, row blocks of 16 are dealt to the four waves in a balanced (snake) order; the
+// 16-bit split value columns run in k_post_ps (below).  In both, every column's result
+// depends only on that column, so a vertex gets bitwise the same numbers whatever tile or
+// launch it is computed in.
 #include <vector>
 
 #include "lcp_internal.h"
@@ -99,6 +100,7 @@ struct KArgs {
     const void* A1;       // low halves for the 16-bit split products
     const double* amax;   // [1] = sA for the FP16 operands
     double sB;            // power-of-two scale of B for the FP16 operands
+    const double* Xs;     // scaled observations and a (Model::Xs), for k_post_ps
     PostTask t;
 };
 
@@ -495,20 +497,6 @@ __global__ void __launch_bounds__(NW * 64) k_post_batch(const KArgs* __restrict_
     }
 }
 
-// ------------------------------------------------------------------------------------
-// k-outer form for value columns (G = 1) with 16-bit split operands.  A work-group of
-// eight waves owns NT columns and keeps every 16-row block of V for them in registers:
-// wave w owns row blocks rb = w + 8 r, r < RBW.  B is generated just in time in chunks of
-// 32 rows (one 16x16x32 k-step) into a double-buffered LDS slice, so chunk c + 1 is
-// generated while the MFMAs of chunk c run; each B fragment read from LDS feeds all of the
-// wave's row blocks, and each L^-1 fragment is read once per tile.
-//
-// Row block rb takes chunks 0 .. rb / 2.  The chunk loop of a wave therefore runs in
-// phases: in phase K its row blocks r >= K are the live ones, and row block K is final
-// when the phase ends.  Each phase's loop body is branch-free (a single basic block), so
-// the compiler can interleave the generation of the next chunk with the current MFMAs.
-// Per column the k-steps accumulate in the same increasing order as in k_post, so V is
-// bitwise the same; only the binary64 norm partials are summed in another fixed order.
 // Calls f(integral_constant<int, K>) for K = B .. E - 1 in order.
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -519,25 +507,67 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-constexpr int kThreadsKO = 512;
-constexpr int kWavesKO = 8;
-constexpr int kChunk = 32;
+constexpr int kChunk = 32;          // B rows per k-step of the 16-bit split product
 
-template <class P, int NT, int RBW>
-__global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
+// ---------------------------------------------------------------- split-product kernel
+//
+// Value columns with the 16-bit split operands (the reconstruction's posterior).  A
+// work-group owns a tile of NT columns and runs two kinds of waves:
+//  - eight consumer waves (two per SIMD) hold V = L^-1 B for the tile in registers, consumer
+//    w owning row blocks w + 8 r.  B arrives in chunks of 32 rows (one MFMA k-step) through
+//    a double-buffered LDS slice; row block rb takes chunks 0 .. rb / 2, so a consumer runs
+//    its chunk loop in phases, with the row blocks r >= K live in phase K (each phase body is
+//    one branch-free basic block).  A row block is final at the end of its phase; its
+//    epilogue undoes the power-of-two scales, adds the binary64 ||v||^2 partial and stores V.
+//    The next chunk's L^-1 fragments are loaded before each barrier, so their L2 latency
+//    overlaps the wait and the B fragment reads.
+//  - four producer waves (one per SIMD) generate the next chunk of B: binary32 kernel values
+//    (the kind is a template parameter, so this is straight-line code), the binary64 mean
+//    partials and the 16-bit split.  A producer wave's rows are the same for all its lanes,
+//    so it reads the observations (pre-scaled by the inverse lengthscales, with a_j) through
+//    scalar loads and feeds them to the vector instructions as scalar operands.  The FP16
+//    scale sB is folded into the kernel's constants and taken out of the mean at the end
+//    (powers of two: exact).
+// A SIMD so runs two instruction streams of MFMAs beside one of vector arithmetic, which
+// overlap between the per-chunk barriers.  Each column's k-steps accumulate in increasing
+// order, three products per step in a fixed order, and its sums run in a fixed order, so a
+// vertex gets bitwise the same numbers in any tile or launch.
+constexpr int kThreadsPS = 768;
+constexpr int kConsPS = 8;        // consumer waves 0..7; producers are waves 8..11
+
+template <int KIND>
+__device__ __forceinline__ float kval32_scaled(float r2, float c0, float c1, float c2)
 {
-    static_assert(P::KS == 32, "k-outer form is for the 16-bit split operands");
+    constexpr float kLog2e = 1.44269504088896341f;
+    if constexpr (KIND == LCP_KERNEL_SE) {
+        (void)c1;
+        (void)c2;
+        return c0 * __builtin_amdgcn_exp2f(-0.5f * kLog2e * r2);
+    } else {
+        const float r = __builtin_amdgcn_sqrtf(r2);
+        const float poly = fmaf(c1, r, fmaf(c2, r2, c0));          // s2' (1 + sqrt5 r + 5 r^2 / 3)
+        return poly * __builtin_amdgcn_exp2f(-2.23606797749978970f * kLog2e * r);
+    }
+}
+
+template <class P, int NT, int RBW, int KIND>
+__global__ void __launch_bounds__(kThreadsPS) k_post_ps(KArgs A)
+{
+    static_assert(P::KS == 32, "split-product operands");
     using Elem = typename P::Elem;
     using Vec = typename P::Vec;
     constexpr int NCT = NT / 16;
-    constexpr int LDC = kChunk + 8;     // halves; 8 lanes of a b128 fragment read hit distinct banks
+    constexpr int LDC = kChunk + 8;
+    constexpr int NPW = 4;                                   // producer waves
+    constexpr int RPT = kChunk / NPW;                        // rows per producer lane per chunk
+    static_assert(NT == 64 || NT == 32, "tile width");
     __shared__ __align__(16) Elem Bs[2][2][NT][LDC];
-    __shared__ double red[kWavesKO][NT];
-    __shared__ double redm[kThreadsKO];
-    __shared__ double4 Xs[kMaxM];                           // observations (x, y, z, a_j)
+    __shared__ double red[kConsPS][NT];
+    __shared__ double redm[NPW][NT];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool consumer = wave < kConsPS;
     const int gl = lane >> 4, cl = lane & 15;
     const PostTask& T = A.t;
     int64_t npts = T.count ? *T.count : T.n_points;
@@ -545,157 +575,176 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
     const int64_t ntiles = (npts + NT - 1) / NT;
     const int dim = A.kp.dim;
     const int nks_total = A.mp / P::KS;
-    const int nch = (A.nrb + 1) / 2;                      // chunks covering the 16 nrb rows
+    const int nch = (A.nrb + 1) / 2;
 
-    // generation layout: thread -> column gc = tid % NT, rows gr .. gr + RPT - 1 of a chunk
-    constexpr int RPT = kChunk * NT / kThreadsKO;
-    const int gc = tid % NT, gr = (tid / NT) * RPT;
-    const float fie0 = (float)A.kp.inv_ell[0], fie1 = (float)A.kp.inv_ell[1], fie2 = (float)A.kp.inv_ell[2];
-    const float fs2 = (float)A.kp.s2, fsB = (float)A.sB;
+    // producer wave pw serves rows 32 c + RPT pw .. + RPT - 1 of every chunk c (the same for
+    // all its lanes) for column gc = lane % NT; with 32-column tiles lanes 32..63 repeat
+    // lanes 0..31 and store nothing
+    const int pw = wave - kConsPS;
+    const int gc = lane & (NT - 1);
+    const bool pstore = lane < NT;
+    const double ie0 = A.kp.inv_ell[0], ie1 = A.kp.inv_ell[1], ie2 = A.kp.inv_ell[2];
+    const double sB = P::kScaled ? A.sB : 1.0;
+    const float c0 = (float)(A.kp.s2 * sB);
+    const float c1 = (float)(2.23606797749978969640917366873 * A.kp.s2 * sB);
+    const float c2 = (float)((5.0 / 3.0) * A.kp.s2 * sB);
     const float inv = P::kScaled ? (float)(1.0 / (A.amax[1] * A.sB)) : 1.0f;   // a power of two
     const Vec* __restrict__ Ahi = (const Vec*)A.A0;
     const Vec* __restrict__ Alo = (const Vec*)A.A1;
-    for (int j = tid; j < A.mp; j += kThreadsKO)
-        Xs[j] = double4{A.X[4 * j + 0], A.X[4 * j + 1], A.X[4 * j + 2], A.a[j]};
+    // constant address space: read-only for the kernel's lifetime, so wave-uniform reads
+    // become scalar loads
+    typedef const __attribute__((address_space(4))) double* ConstD;
+    const ConstD Xs = (ConstD)A.Xs;
 
+    const int cw = wave;                                     // consumer wave: row blocks cw + 8 r
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t col0 = tile * NT;
-        const int64_t p = col0 + gc;
-        const bool valid = p < npts;
-        double px = 0.0, py = 0.0, pz = 0.0;
-        if (valid) {
-            if (T.mode == COL_GRID) {
-                const int64_t v = T.vlist ? (int64_t)T.vlist[p] : p;
-                const int64_t i0 = v % T.grid.n[0];
-                const int64_t r = v / T.grid.n[0];
-                px = vertex_coord(T.grid, 0, i0);
-                py = vertex_coord(T.grid, 1, r % T.grid.n[1]);
-                pz = dim > 2 ? vertex_coord(T.grid, 2, r / T.grid.n[1]) : 0.0;
-            } else {
-                px = T.pts[p * T.pstride + 0];
-                py = T.pts[p * T.pstride + 1];
-                pz = dim > 2 ? T.pts[p * T.pstride + 2] : 0.0;
-            }
-        }
-        double mpart = 0.0;
-        // B rows 32 c + gr .. + RPT - 1 of this thread's column into buffer b; branch-free
-        // (rows past the padded model are clamped and written as zeros)
-        auto generate = [&](int c, int b) {
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int j = kChunk * c + gr + i;
-                const int jj = j < A.mp ? j : A.mp - 1;
-                const bool live = valid && j < A.m;
-                const double4 xj = Xs[jj];
-                const float t0 = (float)(px - xj.x) * fie0, t1 = (float)(py - xj.y) * fie1,
-                            t2 = (float)(pz - xj.z) * fie2;
-                const float r2 = fmaf(t2, t2, fmaf(t1, t1, t0 * t0));
-                const float kv = kernel_val32(A.kp.kind, fs2, r2);
-                const float bv = live ? kv : 0.0f;
-                mpart = fma((double)bv, xj.w, mpart);
-                Elem hi, lo;
-                split16(P::kScaled ? bv * fsB : bv, hi, lo);
-                Bs[b][0][gc][gr + i] = hi;
-                Bs[b][1][gc][gr + i] = lo;
-            }
-        };
-
-        f4 acc[RBW][NCT];
-#pragma unroll
-        for (int r = 0; r < RBW; ++r)
-#pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
-        double dacc[NCT];
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) dacc[ct] = 0.0;
-
-        auto epilogue = [&](int rb, f4 (&ac)[NCT]) {
-#pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                if constexpr (P::kScaled) ac[ct] *= inv;
-                const double v0 = (double)ac[ct][0], v1 = (double)ac[ct][1];
-                const double v2 = (double)ac[ct][2], v3 = (double)ac[ct][3];
-                dacc[ct] += fma(v0, v0, v1 * v1) + fma(v2, v2, v3 * v3);
-                if (T.V) {
-                    const int64_t pc = col0 + 16 * ct + cl;
-                    if (pc < npts) {
-                        // quad-major, or plain columns of vld (rows 16 rb + 4 gl .. + 3)
-                        const size_t o = T.vld ? (size_t)pc * T.vld + 16 * rb + 4 * gl
-                                               : ((size_t)(4 * rb + gl) * T.n_points + pc) * 4;
-                        *(f4*)((float*)T.V + o) = ac[ct];
-                    }
+        __syncthreads();                                     // previous tile's LDS reads are complete
+        if (!consumer) {
+            // ------------------------------------------------------------ producer
+            const int64_t p = col0 + gc;
+            double px = 0.0, py = 0.0, pz = 0.0;             // an invalid column stays finite
+            if (p < npts) {
+                if (T.mode == COL_GRID) {
+                    const int64_t v = T.vlist ? (int64_t)T.vlist[p] : p;
+                    const int64_t i0 = v % T.grid.n[0];
+                    const int64_t r = v / T.grid.n[0];
+                    px = vertex_coord(T.grid, 0, i0);
+                    py = vertex_coord(T.grid, 1, r % T.grid.n[1]);
+                    pz = dim > 2 ? vertex_coord(T.grid, 2, r / T.grid.n[1]) : 0.0;
+                } else {
+                    px = T.pts[p * T.pstride + 0];
+                    py = T.pts[p * T.pstride + 1];
+                    pz = dim > 2 ? T.pts[p * T.pstride + 2] : 0.0;
                 }
             }
-        };
-
-        // one chunk with row blocks r >= K live: fragments, next chunk's generation, MFMAs
-        auto body = [&](auto Kc, int c) {
-            constexpr int K = decltype(Kc)::value;
-            const int b = c & 1;
-            Vec bh[NCT], bl[NCT];
+            px = mul_rn(px, ie0);
+            py = mul_rn(py, ie1);
+            pz = mul_rn(pz, ie2);
+            double mpart = 0.0;
+            auto generate = [&](int c, int b) {
+                // rows j0 .. j0 + RPT - 1 < 32 nch <= m_pad (m_pad is a multiple of 128); rows
+                // past m sit at 1e15 lengthscales with a_j = 0, so their values are exactly 0
+                float kv[RPT];
+                const ConstD Xj = Xs + 4 * (kChunk * c + RPT * pw);
 #pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                bh[ct] = *(const Vec*)&Bs[b][0][16 * ct + cl][8 * gl];
-                bl[ct] = *(const Vec*)&Bs[b][1][16 * ct + cl][8 * gl];
+                for (int i = 0; i < RPT; ++i) {
+                    if (i == RPT / 2) __builtin_amdgcn_sched_barrier(0);   // half the rows' scalars live at once
+                    const double x0 = Xj[4 * i + 0], x1 = Xj[4 * i + 1], x2 = Xj[4 * i + 2], aj = Xj[4 * i + 3];
+                    const float t0 = (float)(px - x0), t1 = (float)(py - x1), t2 = (float)(pz - x2);
+                    const float r2 = fmaf(t2, t2, fmaf(t1, t1, t0 * t0));
+                    kv[i] = kval32_scaled<KIND>(r2, c0, c1, c2);
+                    mpart = fma((double)kv[i], aj, mpart);
+                }
+                typedef Elem EV __attribute__((ext_vector_type(RPT)));
+                EV hi, lo;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    Elem h, l;
+                    split16(kv[i], h, l);
+                    hi[i] = h;
+                    lo[i] = l;
+                }
+                if (pstore) {
+                    *(EV*)&Bs[b][0][gc][RPT * pw] = hi;
+                    *(EV*)&Bs[b][1][gc][RPT * pw] = lo;
+                }
+            };
+            generate(0, 0);
+            __syncthreads();
+            for (int c = 0; c < nch; ++c) {
+                if (c + 1 < nch) generate(c + 1, (c + 1) & 1);
+                __syncthreads();
             }
+            if (pstore) redm[pw][gc] = mpart;
+        } else {
+            // ------------------------------------------------------------ consumer
+            f4 acc[RBW][NCT];
+#pragma unroll
+            for (int r = 0; r < RBW; ++r)
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
+            double dacc[NCT];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) dacc[ct] = 0.0;
             Vec ah[RBW], al[RBW];
+            auto load_a = [&](auto Kc, int c) {
+                constexpr int K = decltype(Kc)::value;
 #pragma unroll
-            for (int r = K; r < RBW; ++r) {
-                int rb = wave + kWavesKO * r;
-                rb = rb < A.nrb ? rb : A.nrb - 1;          // a missing row block is never stored
-                const size_t o = ((size_t)rb * nks_total + c) * 64 + lane;
-                ah[r] = Ahi[o];
-                al[r] = Alo[o];
-            }
-            generate(c + 1, b ^ 1);
-#pragma unroll
-            for (int r = K; r < RBW; ++r)
+                for (int r = K; r < RBW; ++r) {
+                    int rb = cw + kConsPS * r;
+                    rb = rb < A.nrb ? rb : A.nrb - 1;          // a missing row block is never stored
+                    const size_t o = ((size_t)rb * nks_total + c) * 64 + lane;
+                    ah[r] = Ahi[o];
+                    al[r] = Alo[o];
+                }
+            };
+            auto epilogue = [&](int rb, f4 (&ac)[NCT]) {
 #pragma unroll
                 for (int ct = 0; ct < NCT; ++ct) {
-                    acc[r][ct] = mfma16(al[r], bh[ct], acc[r][ct]);
-                    acc[r][ct] = mfma16(ah[r], bl[ct], acc[r][ct]);
-                    acc[r][ct] = mfma16(ah[r], bh[ct], acc[r][ct]);
+                    if constexpr (P::kScaled) ac[ct] *= inv;
+                    const double v0 = (double)ac[ct][0], v1 = (double)ac[ct][1];
+                    const double v2 = (double)ac[ct][2], v3 = (double)ac[ct][3];
+                    dacc[ct] += fma(v0, v0, v1 * v1) + fma(v2, v2, v3 * v3);
+                    if (T.V) {
+                        const int64_t pc = col0 + 16 * ct + cl;
+                        if (pc < npts) {
+                            const size_t o = T.vld ? (size_t)pc * T.vld + 16 * rb + 4 * gl
+                                                   : ((size_t)(4 * rb + gl) * T.n_points + pc) * 4;
+                            *(f4*)((float*)T.V + o) = ac[ct];
+                        }
+                    }
                 }
-            __syncthreads();
-        };
-        // phase K: chunks after row block K - 1 finished, up to the last chunk of row block K
-        auto phase = [&](auto Kc, int& c) {
-            constexpr int K = decltype(Kc)::value;
-            const int rbK = wave + kWavesKO * K;
-            // a full operand (T.dense) takes every chunk for every row block
-            const int cend = (!T.dense && rbK / 2 < nch - 1) ? rbK / 2 : nch - 1;
-            for (; c <= cend; ++c) body(Kc, c);
-            if (rbK < A.nrb) epilogue(rbK, acc[K]);
-        };
-
-        __syncthreads();                 // previous tile's LDS reads are complete
-        generate(0, 0);
-        __syncthreads();
-        int c = 0;
-        static_for<0, RBW>([&](auto Kc) { phase(Kc, c); });
-        // chunks after this wave's last row block: generation and barriers only
-        for (; c < nch; ++c) {
-            generate(c + 1, (c & 1) ^ 1);
-            __syncthreads();
-        }
-
-        // ---- reductions: mean partials over the row groups, norm partials over lanes and waves
-        redm[tid] = mpart;
+            };
+            // chunk c with row blocks r >= K live; then the next chunk's A fragments
+            auto body = [&](auto Kc, int c) {
+                constexpr int K = decltype(Kc)::value;
+                const int b = c & 1;
+                Vec bh[NCT], bl[NCT];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            double sum = dacc[ct];
-            sum += __shfl_xor(sum, 16, 64);
-            sum += __shfl_xor(sum, 32, 64);
-            if (gl == 0) red[wave][16 * ct + cl] = sum;
+                for (int ct = 0; ct < NCT; ++ct) {
+                    bh[ct] = *(const Vec*)&Bs[b][0][16 * ct + cl][8 * gl];
+                    bl[ct] = *(const Vec*)&Bs[b][1][16 * ct + cl][8 * gl];
+                }
+#pragma unroll
+                for (int r = K; r < RBW; ++r)
+#pragma unroll
+                    for (int ct = 0; ct < NCT; ++ct) {
+                        acc[r][ct] = mfma16(al[r], bh[ct], acc[r][ct]);
+                        acc[r][ct] = mfma16(ah[r], bl[ct], acc[r][ct]);
+                        acc[r][ct] = mfma16(ah[r], bh[ct], acc[r][ct]);
+                    }
+                load_a(Kc, c + 1 < nch ? c + 1 : nch - 1);
+                __syncthreads();
+            };
+            auto phase = [&](auto Kc, int& c) {
+                constexpr int K = decltype(Kc)::value;
+                const int rbK = cw + kConsPS * K;
+                const int cend = (!T.dense && rbK / 2 < nch - 1) ? rbK / 2 : nch - 1;
+                for (; c <= cend; ++c) body(Kc, c);
+                if (rbK < A.nrb) epilogue(rbK, acc[K]);
+            };
+            load_a(std::integral_constant<int, 0>{}, 0);
+            __syncthreads();                                 // chunk 0 generated
+            int c = 0;
+            static_for<0, RBW>([&](auto Kc) { phase(Kc, c); });
+            for (; c < nch; ++c) __syncthreads();
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                double sum = dacc[ct];
+                sum += __shfl_xor(sum, 16, 64);
+                sum += __shfl_xor(sum, 32, 64);
+                if (gl == 0) red[cw][16 * ct + cl] = sum;
+            }
         }
         __syncthreads();
         if (tid < NT) {
             double mu = 0.0, dot = 0.0;
-            for (int g = 0; g < kThreadsKO / NT; ++g) mu += redm[g * NT + tid];
-            for (int w = 0; w < kWavesKO; ++w) dot += red[w][tid];
+            for (int g = 0; g < NPW; ++g) mu += redm[g][tid];
+            for (int w = 0; w < kConsPS; ++w) dot += red[w][tid];
             const int64_t pc = col0 + tid;
             if (pc < npts) {
-                T.mean[pc] = mu;
+                T.mean[pc] = mu / sB;
                 const double v = A.kp.s2 - dot;
                 T.var[pc] = v > 0.0 ? v : 0.0;
             }
@@ -703,8 +752,8 @@ __global__ void __launch_bounds__(kThreadsKO) k_post_ko(KArgs A)
     }
 }
 
-template <class P, int NT, int RBW>
-hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
+template <class P, int NT, int RBW, int KIND>
+hipError_t launch_ps(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
                      const double* amax)
 {
     KArgs A;
@@ -722,25 +771,34 @@ hipError_t launch_ko(const Model& M, const PostTask& t, hipStream_t s, const voi
         frexp(M.k.signal_var, &e);
         A.sB = ldexp(1.0, 15 - e);          // k* <= s2, so sB * k* < 2^15
     }
+    A.Xs = M.Xs;
     A.t = t;
-    if (A.nrb > kWavesKO * RBW) return hipErrorInvalidValue;
+    if (A.nrb > kConsPS * RBW) return hipErrorInvalidValue;
     const int64_t ntiles = (t.n_points + NT - 1) / NT;
     int64_t grid = ntiles < 256 * 8 ? ntiles : 256 * 8;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_post_ko<P, NT, RBW>), dim3((unsigned)grid), dim3(kThreadsKO), 0, s, A);
+    hipLaunchKernelGGL((k_post_ps<P, NT, RBW, KIND>), dim3((unsigned)grid), dim3(kThreadsPS), 0, s, A);
     return hipGetLastError();
 }
 
-template <class P>
-hipError_t launch_ko_split(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
-                           const double* amax = nullptr)
+template <class P, int NT, int RBW>
+hipError_t launch_ps_kind(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
+                          const double* amax)
 {
-    switch ((M.nrb + kWavesKO - 1) / kWavesKO) {
-    case 1: return launch_ko<P, 64, 1>(M, t, s, A0, A1, amax);
-    case 2: return launch_ko<P, 64, 2>(M, t, s, A0, A1, amax);
-    case 3: return launch_ko<P, 64, 3>(M, t, s, A0, A1, amax);
-    case 4: return launch_ko<P, 64, 4>(M, t, s, A0, A1, amax);
-    default: return launch_ko<P, 32, 8>(M, t, s, A0, A1, amax);
+    if (M.kp.kind == LCP_KERNEL_SE) return launch_ps<P, NT, RBW, LCP_KERNEL_SE>(M, t, s, A0, A1, amax);
+    return launch_ps<P, NT, RBW, LCP_KERNEL_MATERN52>(M, t, s, A0, A1, amax);
+}
+
+template <class P>
+hipError_t launch_split(const Model& M, const PostTask& t, hipStream_t s, const void* A0, const void* A1,
+                        const double* amax = nullptr)
+{
+    switch ((M.nrb + kConsPS - 1) / kConsPS) {
+    case 1: return launch_ps_kind<P, 64, 1>(M, t, s, A0, A1, amax);
+    case 2: return launch_ps_kind<P, 64, 2>(M, t, s, A0, A1, amax);
+    case 3: return launch_ps_kind<P, 64, 3>(M, t, s, A0, A1, amax);
+    case 4: return launch_ps_kind<P, 64, 4>(M, t, s, A0, A1, amax);
+    default: return launch_ps_kind<P, 32, 8>(M, t, s, A0, A1, amax);
     }
 }
 
@@ -875,7 +933,7 @@ hipError_t launch_posterior_operand_f16x3(const Model& M, const PostTask& t, con
     if (t.n_points <= 0) return hipSuccess;
     StageScope sc(s, t.stage);
     if (t.group != 1) return hipErrorInvalidValue;
-    return launch_ko_split<PH3>(M, t, s, Hhi, Hlo, amax);
+    return launch_split<PH3>(M, t, s, Hhi, Hlo, amax);
 }
 
 hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStream_t s)
@@ -899,13 +957,13 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
         if (grad) return launch_t<P32, 32, 4>(M, t, s, M.A32, nullptr);
         return launch_t<P32, 32, 1>(M, t, s, M.A32, nullptr);
     }
-    // 16-bit split value columns: k-outer kernel with RBW = ceil(nrb / 8) row blocks per wave
+    // 16-bit split value columns: producer/consumer kernel, RBW = ceil(nrb / 8) row blocks per consumer
     if (prec == LCP_MIXED_F16X3) {
         if (grad) return launch_t<PH3, 32, 4>(M, t, s, M.Hhi, M.Hlo);
-        return launch_ko_split<PH3>(M, t, s, M.Hhi, M.Hlo);
+        return launch_split<PH3>(M, t, s, M.Hhi, M.Hlo);
     }
     if (grad) return launch_t<PB3, 32, 4>(M, t, s, M.Ahi, M.Alo);
-    return launch_ko_split<PB3>(M, t, s, M.Ahi, M.Alo);
+    return launch_split<PB3>(M, t, s, M.Ahi, M.Alo);
 }
 
 }  // namespace lcp

@@ -40,7 +40,15 @@ struct GridP {
 // (no fused multiply-add), so every part of the library agrees on box corners.
 __device__ __forceinline__ double vertex_coord(const GridP& g, int d, int64_t i)
 {
-    return __dadd_rn(g.lo[d], __dmul_rn((double)i, g.h[d]));
+#pragma clang fp contract(off)
+    return g.lo[d] + (double)i * g.h[d];
+}
+
+// x * y rounded once, never fused into a following addition.
+__device__ __forceinline__ double mul_rn(double x, double y)
+{
+#pragma clang fp contract(off)
+    return x * y;
 }
 
 __device__ __forceinline__ double kernel_r2(const KParams& p, const double* x, const double* z)
@@ -265,6 +273,8 @@ struct Model {
     double* obs_mu;   // m
     double* obs_var;  // m
     double* AM;       // sparse model: A_M (m_pad x m_pad, zero padded), kept for local models
+    double* Xs;       // m_pad x 4: x_jd / l_d (d < dim, else 0) and a_j, for the split-product
+                      // posterior's generation (zero rows past m)
     int* info;
     int device;
 };
