@@ -232,6 +232,24 @@ int lcp_adaptive(const lcp_model* model, const lcp_grid* grid, double theta, con
                  uint8_t* level_field, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * lcp_cell_moments -- the 2^dim-corner Gaussian of listed cells (Sec. 4: the corner values
+ * of a cell follow a multivariate normal whose mean and covariance come from eq. (sgp)),
+ * computed by the same kernels as lcp_dense and lcp_adaptive in precision `prec`: posterior
+ * mean and variance at the corner vertices and the neighbour cross-covariances
+ * k(x_p, x_q) - v_p . v_q.  For inspection and error reporting; no Monte Carlo.
+ *   cells  n linear cell indices (device, int64; cell (i, j, k) = i + nc0 (j + nc1 k), x
+ *          fastest, nc = npts - 1); an index outside [0, prod(nc)) gives NaN outputs
+ *   mean   n x 2^dim corner means (device, binary64); corner q is at offset
+ *          (q & 1, (q >> 1) & 1, (q >> 2) & 1)
+ *   cov    n x 2^dim x 2^dim corner covariances, row-major per cell (device, binary64)
+ *   ws     lcp_cell_moments_workspace bytes (grid-sized flags plus the corners' posterior)
+ * Asynchronous on `stream`.
+ */
+int lcp_cell_moments_workspace(const lcp_model* model, const lcp_grid* grid, int64_t n, int prec, size_t* bytes);
+int lcp_cell_moments(const lcp_model* model, const lcp_grid* grid, int64_t n, const int64_t* cells, int prec,
+                     double* mean, double* cov, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * lcp_bound_certified -- box bounds of the latent posterior that hold at every point of
  * each box, which make the region bound of eq. (upper_bound) guaranteed (the bounded search
  * of Sec. 5.1 can miss the minimum, Sec. 9).  For box b with centre c and half-widths h:

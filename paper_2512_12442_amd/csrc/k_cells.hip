@@ -1119,6 +1119,114 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ corner moments of listed cells
+namespace {
+
+// Cell index e (x fastest) -> its integer coordinates; false when e is out of range.
+__device__ __forceinline__ bool cell_of(const GridP& g, int64_t e, int64_t (&c)[3])
+{
+    const int64_t nc = g.nc[0] * g.nc[1] * g.nc[2];
+    if (e < 0 || e >= nc) return false;
+    c[0] = e % g.nc[0];
+    c[1] = (e / g.nc[0]) % g.nc[1];
+    c[2] = e / (g.nc[0] * g.nc[1]);
+    return true;
+}
+
+// Flag the 2^D corner vertices of every listed cell.
+__global__ void k_mark_cells(GridP g, const int64_t* __restrict__ cells, int64_t n, int32_t* __restrict__ vmask)
+{
+    const int N = 1 << g.dim;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n * N;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c[3];
+        if (!cell_of(g, cells[it / N], c)) continue;
+        const int q = (int)(it % N);
+        const int64_t vx = c[0] + (q & 1), vy = c[1] + ((q >> 1) & 1), vz = c[2] + ((q >> 2) & 1);
+        vmask[vx + g.n[0] * (vy + g.n[1] * (g.dim == 3 ? vz : 0))] = 1;
+    }
+}
+
+__global__ void k_vertex_slots(const int32_t* __restrict__ vmask, const int32_t* __restrict__ off, int64_t nv,
+                               int32_t* __restrict__ slot, int32_t* __restrict__ vlist)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        slot[i] = vmask[i] ? off[i] : -1;
+        if (vmask[i]) vlist[off[i]] = (int32_t)i;
+    }
+}
+
+// Corner mean (2^D) and covariance (2^D x 2^D, row-major) of each listed cell, gathered
+// exactly as the Monte Carlo kernels gather them: diagonal = posterior variance, the other
+// entries = the neighbour cross-covariances.  An out-of-range cell gets NaN.
+template <int D>
+__global__ void k_cell_moments(GridP g, const int64_t* __restrict__ cells, int64_t n, const int32_t* __restrict__ slot,
+                               const double* __restrict__ mean, const double* __restrict__ var,
+                               const double* __restrict__ cross, double* __restrict__ mu_out,
+                               double* __restrict__ cov_out)
+{
+    constexpr int N = 1 << D;
+    constexpr int NDIR = D == 3 ? 13 : 4;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c[3];
+        double* mo = mu_out + e * N;
+        double* co = cov_out + e * N * N;
+        if (!cell_of(g, cells[e], c)) {
+            for (int q = 0; q < N; ++q) mo[q] = __builtin_nan("");
+            for (int q = 0; q < N * N; ++q) co[q] = __builtin_nan("");
+            continue;
+        }
+        int64_t sl[N];
+        for (int q = 0; q < N; ++q) {
+            const int64_t vx = c[0] + (q & 1), vy = c[1] + ((q >> 1) & 1), vz = c[2] + ((q >> 2) & 1);
+            sl[q] = slot[vx + g.n[0] * (vy + g.n[1] * (D == 3 ? vz : 0))];
+            mo[q] = mean[sl[q]];
+            co[q * N + q] = var[sl[q]];
+        }
+        for (int p = 0; p < N; ++p)
+            for (int q = p + 1; q < N; ++q) {
+                const int dx = (q & 1) - (p & 1), dy = ((q >> 1) & 1) - ((p >> 1) & 1),
+                          dz = ((q >> 2) & 1) - ((p >> 2) & 1);
+                const double v = cross[(size_t)sl[p] * NDIR + dir_index(D, dx, dy, dz)];
+                co[p * N + q] = v;
+                co[q * N + p] = v;
+            }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mark_cells(const GridP& g, const int64_t* cells, int64_t n, int32_t* vmask, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    StageScope sc(s, ST_MISC);
+    hipLaunchKernelGGL(k_mark_cells, dim3(grid_for(n << g.dim, 256)), dim3(256), 0, s, g, cells, n, vmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_slots(const int32_t* vmask, const int32_t* off, int64_t nv, int32_t* slot, int32_t* vlist,
+                               hipStream_t s)
+{
+    StageScope sc(s, ST_MISC);
+    hipLaunchKernelGGL(k_vertex_slots, dim3(grid_for(nv, 256)), dim3(256), 0, s, vmask, off, nv, slot, vlist);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_moments(const GridP& g, const int64_t* cells, int64_t n, const int32_t* slot,
+                               const double* mean, const double* var, const double* cross, double* mu_out,
+                               double* cov_out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    StageScope sc(s, ST_MISC);
+    if (g.dim == 3)
+        hipLaunchKernelGGL(k_cell_moments<3>, dim3(grid_for(n, 256)), dim3(256), 0, s, g, cells, n, slot, mean, var,
+                           cross, mu_out, cov_out);
+    else
+        hipLaunchKernelGGL(k_cell_moments<2>, dim3(grid_for(n, 256)), dim3(256), 0, s, g, cells, n, slot, mean, var,
+                           cross, mu_out, cov_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s)
 {
     StageScope sc(s, ST_MISC);

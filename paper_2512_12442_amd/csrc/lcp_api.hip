@@ -371,6 +371,108 @@ int gp_posterior_backward(const lcp_model* M, int64_t n, const double* Xq, int p
     return ok();
 }
 
+namespace {
+
+struct MomentsWs {
+    int32_t* vmask;
+    int32_t* voff;
+    int32_t* slot;
+    int32_t* vlist;
+    int64_t* count;
+    char* scan;
+    double* mean;
+    double* var;
+    void* V;
+    double* cross;
+};
+
+// Workspace of lcp_cell_moments: per-vertex flags, offsets and slots over the whole grid,
+// then posterior, V (quad-major) and cross terms for at most min(n 2^D, vertices) slots.
+size_t moments_ws(const lcp_model* M, const GridP& g, int64_t n, int prec, MomentsWs* w, char* p)
+{
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    int64_t cap = n << g.dim;
+    if (cap > nv) cap = nv;
+    if (cap < 1) cap = 1;
+    const size_t vb = prec == LCP_FP64 ? 8 : 4;
+    const size_t sizes[10] = {4 * (size_t)nv, 4 * (size_t)nv, 4 * (size_t)nv, 4 * (size_t)cap, 8,
+                              scan_workspace(nv), 8 * (size_t)cap, 8 * (size_t)cap, vb * (size_t)cap * M->m_pad,
+                              8 * (size_t)cap * ndir(g.dim)};
+    size_t o = 0;
+    void* ptrs[10];
+    for (int i = 0; i < 10; ++i) {
+        ptrs[i] = p ? p + o : nullptr;
+        o += align256(sizes[i]);
+    }
+    if (w) {
+        w->vmask = (int32_t*)ptrs[0];
+        w->voff = (int32_t*)ptrs[1];
+        w->slot = (int32_t*)ptrs[2];
+        w->vlist = (int32_t*)ptrs[3];
+        w->count = (int64_t*)ptrs[4];
+        w->scan = (char*)ptrs[5];
+        w->mean = (double*)ptrs[6];
+        w->var = (double*)ptrs[7];
+        w->V = ptrs[8];
+        w->cross = (double*)ptrs[9];
+    }
+    return o;
+}
+
+}  // namespace
+
+int lcp_cell_moments_workspace(const lcp_model* M, const lcp_grid* grid, int64_t n, int prec, size_t* bytes)
+{
+    if (!M || !bytes) return fail(LCP_EINVAL, "model and bytes must not be NULL");
+    if (n < 0) return fail(LCP_EINVAL, "n < 0");
+    if (check_prec(prec)) return LCP_EINVAL;
+    GridP g;
+    if (int r = check_grid(M, grid, &g)) return r;
+    *bytes = moments_ws(M, g, n, prec, nullptr, nullptr);
+    return ok();
+}
+
+int lcp_cell_moments(const lcp_model* M, const lcp_grid* grid, int64_t n, const int64_t* cells, int prec,
+                     double* mean, double* cov, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!M) return fail(LCP_EINVAL, "model is NULL");
+    if (n < 0) return fail(LCP_EINVAL, "n < 0");
+    if (check_prec(prec)) return LCP_EINVAL;
+    GridP g;
+    if (int r = check_grid(M, grid, &g)) return r;
+    if (n == 0) return ok();
+    if (!cells || !mean || !cov || !ws) return fail(LCP_EINVAL, "cells, mean, cov and ws must not be NULL");
+    if (!aligned256(ws)) return fail(LCP_EINVAL, "workspace must be 256-byte aligned");
+    MomentsWs w;
+    const size_t need = moments_ws(M, g, n, prec, &w, (char*)ws);
+    if (ws_bytes < need) return fail(LCP_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nv = g.n[0] * g.n[1] * g.n[2];
+    int64_t cap = n << g.dim;
+    if (cap > nv) cap = nv;
+    hipError_t e = launch_fill_i32(w.vmask, 0, nv, s);
+    if (e == hipSuccess) e = launch_mark_cells(g, cells, n, w.vmask, s);
+    if (e == hipSuccess) e = launch_scan(w.vmask, w.voff, nv, nullptr, w.count, w.scan, s);
+    if (e == hipSuccess) e = launch_vertex_slots(w.vmask, w.voff, nv, w.slot, w.vlist, s);
+    if (e != hipSuccess) return dev_fail(e, "lcp_cell_moments: vertex slots");
+    PostTask t{};
+    t.mode = COL_GRID;
+    t.group = 1;
+    t.count = w.count;
+    t.n_points = cap;
+    t.grid = g;
+    t.vlist = w.vlist;
+    t.mean = w.mean;
+    t.var = w.var;
+    t.V = w.V;
+    t.stage = ST_POSTERIOR;
+    e = launch_posterior(*M, prec, t, s);
+    if (e == hipSuccess) e = launch_cross(*M, prec, g, w.vlist, w.count, cap, w.slot, w.V, w.cross, s);
+    if (e == hipSuccess) e = launch_cell_moments(g, cells, n, w.slot, w.mean, w.var, w.cross, mean, cov, s);
+    if (e != hipSuccess) return dev_fail(e, "lcp_cell_moments");
+    return ok();
+}
+
 int lcp_bound_workspace(const lcp_model* M, int64_t n, size_t* bytes)
 {
     if (!M || !bytes) return fail(LCP_EINVAL, "model and bytes must not be NULL");

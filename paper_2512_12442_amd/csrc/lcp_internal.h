@@ -251,6 +251,15 @@ hipError_t launch_cross_batch(const Model* const* Ms, const GridP* grids, const 
                               int nb, int prec, char* scratch, hipStream_t s);
 hipError_t launch_cells_batch(const CellTask* tasks, int nb, char* scratch, hipStream_t s);
 hipError_t launch_zbank32(const double* zb, float* zb32, int64_t n, hipStream_t s);
+// Corner moments of listed cells (linear cell index, x fastest): flag their corner vertices,
+// number the flagged vertices (slot, vlist from an exclusive scan of vmask), then gather each
+// cell's 2^D means and 2^D x 2^D covariance from the per-slot posterior and cross terms.
+hipError_t launch_mark_cells(const GridP& g, const int64_t* cells, int64_t n, int32_t* vmask, hipStream_t s);
+hipError_t launch_vertex_slots(const int32_t* vmask, const int32_t* off, int64_t nv, int32_t* slot, int32_t* vlist,
+                               hipStream_t s);
+hipError_t launch_cell_moments(const GridP& g, const int64_t* cells, int64_t n, const int32_t* slot,
+                               const double* mean, const double* var, const double* cross, double* mu_out,
+                               double* cov_out, hipStream_t s);
 
 // --------------------------------------------------------------- model (K2)
 

@@ -59,7 +59,8 @@ EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor
            "lcp_dense", "lcp_adaptive", "lcp_backward", "lcp_profile_begin", "lcp_profile_end",
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
            "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward",
-           "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified", "lcp_dense_noalloc"]
+           "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified", "lcp_dense_noalloc",
+           "lcp_cell_moments_workspace", "lcp_cell_moments"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -98,6 +99,8 @@ def lib():
     L.gp_posterior_backward.argtypes = [P, I64, P, C.c_int, P, P, P, P, P, SZ, P]
     L.lcp_bound_workspace.argtypes = [P, I64, C.POINTER(SZ)]
     L.lcp_bound_certified.argtypes = [P, I64, P, P, P, SZ, P]
+    L.lcp_cell_moments_workspace.argtypes = [P, P, I64, C.c_int, C.POINTER(SZ)]
+    L.lcp_cell_moments.argtypes = [P, P, I64, P, C.c_int, P, P, P, SZ, P]
     L.lcp_profile_begin.argtypes = [C.c_uint]
     L.lcp_profile_end.argtypes = [P, P, C.c_int]
     L.lcp_batch_model_bytes.restype = SZ
@@ -234,6 +237,21 @@ class GPModel:
         out = torch.empty((n, 4), dtype=torch.float64, device=self.device)
         _check(lib().lcp_bound_certified(self.h, n, _ptr(boxes), _ptr(out), _ptr(ws), b.value, _stream()))
         return out
+
+    def cell_moments(self, grid: Grid, cells: torch.Tensor, prec="fp64"):
+        """Corner means (n x 2^dim) and covariances (n x 2^dim x 2^dim) of the listed cells
+        (linear indices, x fastest) as the LCP kernels compute them (lcp_cell_moments)."""
+        cells = cells.to(torch.int64).contiguous()
+        n = int(cells.shape[0])
+        nc = 1 << grid.dim
+        b = C.c_size_t()
+        _check(lib().lcp_cell_moments_workspace(self.h, C.byref(grid), n, _prec(prec), C.byref(b)))
+        ws = _buffer(b.value, self.device)
+        mean = torch.empty((n, nc), dtype=torch.float64, device=self.device)
+        cov = torch.empty((n, nc, nc), dtype=torch.float64, device=self.device)
+        _check(lib().lcp_cell_moments(self.h, C.byref(grid), n, _ptr(cells), _prec(prec), _ptr(mean), _ptr(cov),
+                                      _ptr(ws), b.value, _stream()))
+        return mean, cov
 
     def dense_workspace(self, grid: Grid, prec, n_samples):
         b = C.c_size_t()

@@ -94,6 +94,8 @@ def test_null_model_rejected_everywhere():
     assert L.lcp_adaptive(None, None, 0.0, None, None, 0, None, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
     assert L.lcp_bound_workspace(None, 4, C.byref(b)) == lcp.lcp.LCP_EINVAL
     assert L.lcp_bound_certified(None, 4, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_cell_moments_workspace(None, None, 4, 0, C.byref(b)) == lcp.lcp.LCP_EINVAL
+    assert L.lcp_cell_moments(None, None, 4, None, 0, None, None, None, 0, None) == lcp.lcp.LCP_EINVAL
     assert "model" in L.lcp_last_error().decode()
 
 
