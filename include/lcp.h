@@ -312,6 +312,31 @@ int lcp_dense_batch(const lcp_model_batch* batch, const lcp_grid* grids, const d
                     int prec, float* lcp, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Precision per model.  In a reduced precision the error of V = L^-1 K*^T grows with the
+ * conditioning of the model: a binary32 V carries about eps32 |L^-1| |k*|, and the binary32
+ * kernel values alone bound what any refinement of V in the same precision can recover.  On
+ * batches of models with noise / s2 = 1e-4 and up to 1024 dense observations this reaches an
+ * LCP RMSE of several 1e-3, against a target of 1e-4 (Sec. 6.2's accuracy metric).
+ *
+ * lcp_batch_precision -- prec[b] = `reduced` if kappa_b = sqrt(s2_b) max|L_b^-1| <= kappa_max,
+ *   else LCP_FP64.  kappa_max <= 0 takes the library's default: 8 for LCP_FP32 (the largest
+ *   kappa at which binary32 stayed below an LCP RMSE of 1e-4 on every measured model), scaled
+ *   by the unit roundoff for the split forms (2 for LCP_MIXED_F16X3, 1/32 for
+ *   LCP_MIXED_BF16X3).  kappa (host, may be NULL) receives kappa_b.  Reads max|L_b^-1| from
+ *   the device: synchronises `stream` once.
+ *   prec  (host) nb entries
+ * lcp_dense_batch_mixed -- lcp_dense_batch with model b in precision prec[b] (host array);
+ *   each pass runs as one launch per precision present.  Workspace from
+ *   lcp_dense_batch_mixed_workspace.
+ */
+int lcp_batch_precision(const lcp_model_batch* batch, int reduced, double kappa_max, int* prec, double* kappa,
+                        void* stream);
+int lcp_dense_batch_mixed_workspace(const lcp_model_batch* batch, const lcp_grid* grids, const int* prec,
+                                    int n_samples, size_t* bytes);
+int lcp_dense_batch_mixed(const lcp_model_batch* batch, const lcp_grid* grids, const double* theta, const lcp_mc* mc,
+                          const int* prec, float* lcp, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * gp_posterior_backward -- adjoint of gp_posterior (Sec. 3, eq. (sgp) in its exact-GP form)
  * with respect to the observation values y and the log-lengthscales log(ell_d).  Given
  * upstream gradients g = dL/dmean and h = dL/dvar at n query points, with K = k(X, X) +

@@ -829,9 +829,9 @@ int batch_grids(const lcp_model_batch* B, const lcp_grid* grids, std::vector<Gri
     return LCP_OK;
 }
 
-// Per model a dense workspace, then the batch records (posterior, cross, cells) and one
-// Monte Carlo work list for all models' cells.
-size_t batch_dense_ws(const lcp_model_batch* B, const std::vector<GridP>& gs, int prec, int ns,
+// Per model a dense workspace (in that model's precision), then the batch records
+// (posterior, cross, cells) and one Monte Carlo work list for all models' cells.
+size_t batch_dense_ws(const lcp_model_batch* B, const std::vector<GridP>& gs, const int* prec, int ns,
                       std::vector<size_t>* off)
 {
     const int nb = (int)gs.size();
@@ -839,7 +839,7 @@ size_t batch_dense_ws(const lcp_model_batch* B, const std::vector<GridP>& gs, in
     int64_t cells = 0;
     for (int b = 0; b < nb; ++b) {
         if (off) off->push_back(o);
-        o += dense_ws(&B->models[b], gs[b], prec, ns);
+        o += dense_ws(&B->models[b], gs[b], prec[b], ns);
         cells += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
     }
     if (off) off->push_back(o);
@@ -852,26 +852,23 @@ size_t batch_dense_ws(const lcp_model_batch* B, const std::vector<GridP>& gs, in
     return o + cells_scratch_bytes(cells);
 }
 
-}  // namespace
-
-int lcp_dense_batch_workspace(const lcp_model_batch* B, const lcp_grid* grids, int prec, int n_samples, size_t* bytes)
+int check_batch_precs(int nb, const int* prec)
 {
-    if (!bytes) return fail(LCP_EINVAL, "bytes must not be NULL");
-    if (check_prec(prec)) return LCP_EINVAL;
-    if (n_samples < 1) return fail(LCP_EINVAL, "n_samples must be >= 1");
-    std::vector<GridP> gs;
-    if (int r = batch_grids(B, grids, &gs)) return r;
-    *bytes = batch_dense_ws(B, gs, prec, n_samples, nullptr);
-    return ok();
+    if (!prec) return fail(LCP_EINVAL, "prec is NULL");
+    for (int b = 0; b < nb; ++b)
+        if (check_prec(prec[b])) return fail(LCP_EINVAL, "prec[%d] = %d is not an lcp_precision", b, prec[b]);
+    return LCP_OK;
 }
 
-int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const double* theta, const lcp_mc* mc, int prec,
-                    float* lcp, void* ws, size_t ws_bytes, void* stream)
+// lcp_dense on every model of the batch, model b in precision prec[b]: the posterior, cross
+// and cells passes each run as one launch per precision present.
+int dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const double* theta, const lcp_mc* mc,
+                const int* prec, float* lcp, void* ws, size_t ws_bytes, void* stream)
 {
-    if (check_prec(prec)) return LCP_EINVAL;
     std::vector<GridP> gs;
     if (int r = batch_grids(B, grids, &gs)) return r;
     const int nb = (int)gs.size();
+    if (int r = check_batch_precs(nb, prec)) return r;
     if (!theta) return fail(LCP_EINVAL, "theta is NULL");
     for (int b = 0; b < nb; ++b) {
         if (int r = check_mc(&B->models[b], mc)) return r;
@@ -886,28 +883,18 @@ int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const doubl
     hipStream_t s = (hipStream_t)stream;
     std::vector<DenseWs> w(nb);
     std::vector<PostTask> tasks(nb);
-    std::vector<const Model*> Ms(nb);
+    bool reduced = false;
     for (int b = 0; b < nb; ++b) {
-        w[b] = carve_dense(&B->models[b], gs[b], prec, mc->n_samples, (char*)ws + off[b]);
+        w[b] = carve_dense(&B->models[b], gs[b], prec[b], mc->n_samples, (char*)ws + off[b]);
         tasks[b] = dense_task(gs[b], w[b]);
-        Ms[b] = &B->models[b];
+        reduced = reduced || prec[b] != LCP_FP64;
     }
     hipError_t e;
-    if (prec != LCP_FP64) {
+    if (reduced) {
         e = launch_zbank32(mc->zbank, w[0].zb32, (int64_t)mc->n_samples << gs[0].dim, s);
         if (e != hipSuccess) return dev_fail(e, "z-bank");
     }
     char* base = (char*)ws;
-    e = launch_posterior_batch(Ms.data(), tasks.data(), nb, prec, base + off[nb], s);
-    if (e != hipSuccess) return dev_fail(e, "batched posterior");
-    std::vector<const void*> Vs(nb);
-    std::vector<double*> crosses(nb);
-    for (int b = 0; b < nb; ++b) {
-        Vs[b] = w[b].V;
-        crosses[b] = w[b].cross;
-    }
-    e = launch_cross_batch(Ms.data(), gs.data(), Vs.data(), crosses.data(), nb, prec, base + off[nb + 1], s);
-    if (e != hipSuccess) return dev_fail(e, "batched cross");
     // one work list for every model's cells
     int64_t cells = 0;
     for (int b = 0; b < nb; ++b) cells += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
@@ -915,29 +902,121 @@ int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const doubl
     int32_t* work = (int32_t*)list;
     int64_t* wcount = (int64_t*)(list + align256(4 * (size_t)cells));
     double* zmax = (double*)((char*)wcount + 64);
-    std::vector<CellTask> cts(nb);
-    int64_t cell0 = 0;
-    for (int b = 0; b < nb; ++b) {
-        CellTask& ct = cts[b];
-        ct = CellTask{};
-        ct.grid = gs[b];
-        ct.prec = prec;
-        ct.theta = theta[b];
-        ct.ns = mc->n_samples;
-        ct.zb64 = mc->zbank;
-        ct.zb32 = w[0].zb32;
-        ct.mean = w[b].mean;
-        ct.var = w[b].var;
-        ct.cross = w[b].cross;
-        ct.slot = nullptr;
-        ct.leaves = nullptr;
-        ct.lcp = lcp + cell0;
-        ct.work = work;
-        ct.wcount = wcount;
-        ct.zmax = zmax;
-        cell0 += gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
+    std::vector<int64_t> cell0(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) cell0[b + 1] = cell0[b] + gs[b].nc[0] * gs[b].nc[1] * gs[b].nc[2];
+    for (int p = LCP_FP64; p <= LCP_MIXED_F16X3; ++p) {
+        std::vector<int> idx;
+        for (int b = 0; b < nb; ++b)
+            if (prec[b] == p) idx.push_back(b);
+        if (idx.empty()) continue;
+        const int n = (int)idx.size();
+        std::vector<const Model*> Ms(n);
+        std::vector<PostTask> ts(n);
+        std::vector<GridP> gg(n);
+        std::vector<const void*> Vs(n);
+        std::vector<double*> crosses(n);
+        std::vector<CellTask> cts(n);
+        for (int i = 0; i < n; ++i) {
+            const int b = idx[i];
+            Ms[i] = &B->models[b];
+            ts[i] = tasks[b];
+            gg[i] = gs[b];
+            Vs[i] = w[b].V;
+            crosses[i] = w[b].cross;
+            CellTask& ct = cts[i];
+            ct = CellTask{};
+            ct.grid = gs[b];
+            ct.prec = p;
+            ct.theta = theta[b];
+            ct.ns = mc->n_samples;
+            ct.zb64 = mc->zbank;
+            ct.zb32 = w[0].zb32;
+            ct.mean = w[b].mean;
+            ct.var = w[b].var;
+            ct.cross = w[b].cross;
+            ct.slot = nullptr;
+            ct.leaves = nullptr;
+            ct.lcp = lcp + cell0[b];
+            ct.work = work;
+            ct.wcount = wcount;
+            ct.zmax = zmax;
+        }
+        e = launch_posterior_batch(Ms.data(), ts.data(), n, p, base + off[nb], s);
+        if (e != hipSuccess) return dev_fail(e, "batched posterior");
+        e = launch_cross_batch(Ms.data(), gg.data(), Vs.data(), crosses.data(), n, p, base + off[nb + 1], s);
+        if (e != hipSuccess) return dev_fail(e, "batched cross");
+        e = launch_cells_batch(cts.data(), n, base + off[nb + 2], s);
+        if (e != hipSuccess) return dev_fail(e, "batched cells");
     }
-    e = launch_cells_batch(cts.data(), nb, base + off[nb + 2], s);
-    if (e != hipSuccess) return dev_fail(e, "batched cells");
+    return ok();
+}
+
+}  // namespace
+
+int lcp_dense_batch_workspace(const lcp_model_batch* B, const lcp_grid* grids, int prec, int n_samples, size_t* bytes)
+{
+    if (!bytes) return fail(LCP_EINVAL, "bytes must not be NULL");
+    if (check_prec(prec)) return LCP_EINVAL;
+    if (n_samples < 1) return fail(LCP_EINVAL, "n_samples must be >= 1");
+    std::vector<GridP> gs;
+    if (int r = batch_grids(B, grids, &gs)) return r;
+    const std::vector<int> precs(gs.size(), prec);
+    *bytes = batch_dense_ws(B, gs, precs.data(), n_samples, nullptr);
+    return ok();
+}
+
+int lcp_dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const double* theta, const lcp_mc* mc, int prec,
+                    float* lcp, void* ws, size_t ws_bytes, void* stream)
+{
+    if (check_prec(prec)) return LCP_EINVAL;
+    if (!B) return fail(LCP_EINVAL, "batch is NULL");
+    const std::vector<int> precs(B->models.size(), prec);
+    return dense_batch(B, grids, theta, mc, precs.data(), lcp, ws, ws_bytes, stream);
+}
+
+int lcp_dense_batch_mixed_workspace(const lcp_model_batch* B, const lcp_grid* grids, const int* prec, int n_samples,
+                                    size_t* bytes)
+{
+    if (!bytes) return fail(LCP_EINVAL, "bytes must not be NULL");
+    if (n_samples < 1) return fail(LCP_EINVAL, "n_samples must be >= 1");
+    std::vector<GridP> gs;
+    if (int r = batch_grids(B, grids, &gs)) return r;
+    if (int r = check_batch_precs((int)gs.size(), prec)) return r;
+    *bytes = batch_dense_ws(B, gs, prec, n_samples, nullptr);
+    return ok();
+}
+
+int lcp_dense_batch_mixed(const lcp_model_batch* B, const lcp_grid* grids, const double* theta, const lcp_mc* mc,
+                          const int* prec, float* lcp, void* ws, size_t ws_bytes, void* stream)
+{
+    return dense_batch(B, grids, theta, mc, prec, lcp, ws, ws_bytes, stream);
+}
+
+int lcp_batch_precision(const lcp_model_batch* B, int reduced, double kappa_max, int* prec, double* kappa,
+                        void* stream)
+{
+    if (!B) return fail(LCP_EINVAL, "batch is NULL");
+    if (!prec) return fail(LCP_EINVAL, "prec must not be NULL");
+    if (check_prec(reduced)) return LCP_EINVAL;
+    if (!(kappa_max == kappa_max)) return fail(LCP_EINVAL, "kappa_max is NaN");
+    if (kappa_max <= 0.0) {
+        // measured for binary32 (24 bits): 8; scaled by the unit roundoff of the other forms
+        const double unit = reduced == LCP_MIXED_BF16X3 ? 0x1p-16 : reduced == LCP_MIXED_F16X3 ? 0x1p-22 : 0x1p-24;
+        kappa_max = reduced == LCP_FP64 ? INFINITY : 8.0 * 0x1p-24 / unit;
+    }
+    const int nb = (int)B->models.size();
+    std::vector<double> amax(nb);
+    hipStream_t s = (hipStream_t)stream;
+    for (int b = 0; b < nb; ++b) {
+        hipError_t e = hipMemcpyAsync(&amax[b], B->models[b].amax, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return dev_fail(e, "lcp_batch_precision");
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dev_fail(e, "lcp_batch_precision");
+    for (int b = 0; b < nb; ++b) {
+        const double k = sqrt(B->models[b].k.signal_var) * amax[b];
+        if (kappa) kappa[b] = k;
+        prec[b] = k <= kappa_max ? reduced : LCP_FP64;
+    }
     return ok();
 }

@@ -60,7 +60,8 @@ EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor
            "lcp_batch_model_bytes", "gp_fit_factor_batch", "gp_model_batch_free", "lcp_dense_batch_workspace",
            "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward",
            "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified", "lcp_dense_noalloc",
-           "lcp_cell_moments_workspace", "lcp_cell_moments"]
+           "lcp_cell_moments_workspace", "lcp_cell_moments", "lcp_batch_precision",
+           "lcp_dense_batch_mixed_workspace", "lcp_dense_batch_mixed"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -110,6 +111,9 @@ def lib():
     L.gp_model_batch_free.restype = None
     L.lcp_dense_batch_workspace.argtypes = [P, P, C.c_int, C.c_int, C.POINTER(SZ)]
     L.lcp_dense_batch.argtypes = [P, P, P, P, C.c_int, P, P, SZ, P]
+    L.lcp_batch_precision.argtypes = [P, C.c_int, C.c_double, P, P, P]
+    L.lcp_dense_batch_mixed_workspace.argtypes = [P, P, P, C.c_int, C.POINTER(SZ)]
+    L.lcp_dense_batch_mixed.argtypes = [P, P, P, P, P, P, P, SZ, P]
     for name in EXPORTS:
         if name not in ("lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_model_free",
                         "lcp_batch_model_bytes", "gp_model_batch_free"):
@@ -490,14 +494,27 @@ class GPModelBatch:
         return cls([(W.kind, W.dim, W.signal_var, list(W.lengthscale), W.noise_var) for W in Ws],
                    [W.X for W in Ws], [W.y for W in Ws], device)
 
+    def precision(self, reduced="fp32", kappa_max=0.0):
+        """Per-model precision codes (lcp_batch_precision): `reduced` where sqrt(s2) max|L^-1|
+        <= kappa_max (0: the library default), binary64 elsewhere; and the kappa values."""
+        pr = (C.c_int * self.nb)()
+        kap = (C.c_double * self.nb)()
+        _check(lib().lcp_batch_precision(self.h, _prec(reduced), float(kappa_max), pr, kap, _stream()))
+        return list(pr), list(kap)
+
     def dense_workspace(self, grids, prec, n_samples):
         G = (Grid * self.nb)(*grids)
         b = C.c_size_t()
-        _check(lib().lcp_dense_batch_workspace(self.h, G, _prec(prec), int(n_samples), C.byref(b)))
+        if isinstance(prec, str):
+            _check(lib().lcp_dense_batch_workspace(self.h, G, _prec(prec), int(n_samples), C.byref(b)))
+        else:
+            pr = (C.c_int * self.nb)(*[_prec(p) if isinstance(p, str) else int(p) for p in prec])
+            _check(lib().lcp_dense_batch_mixed_workspace(self.h, G, pr, int(n_samples), C.byref(b)))
         return b.value
 
     def lcp_dense(self, grids, thetas, zbank: torch.Tensor, prec="fp32", out=None, ws=None):
-        """Cell fields of every model, concatenated in model order."""
+        """Cell fields of every model, concatenated in model order.  prec: one precision for
+        all models, or a sequence with one per model (lcp_dense_batch_mixed)."""
         G = (Grid * self.nb)(*grids)
         th = (C.c_double * self.nb)(*[float(t) for t in thetas])
         zbank = zbank.to(torch.float64).contiguous()
@@ -513,6 +530,11 @@ class GPModelBatch:
             ncell += c
         if out is None:
             out = torch.empty(ncell, dtype=torch.float32, device=self.device)
-        _check(lib().lcp_dense_batch(self.h, G, th, C.byref(mc), _prec(prec), _ptr(out), _ptr(ws), ws.numel(),
-                                     _stream()))
+        if isinstance(prec, str):
+            _check(lib().lcp_dense_batch(self.h, G, th, C.byref(mc), _prec(prec), _ptr(out), _ptr(ws), ws.numel(),
+                                         _stream()))
+        else:
+            pr = (C.c_int * self.nb)(*[_prec(p) if isinstance(p, str) else int(p) for p in prec])
+            _check(lib().lcp_dense_batch_mixed(self.h, G, th, C.byref(mc), pr, _ptr(out), _ptr(ws), ws.numel(),
+                                               _stream()))
         return out, ws
