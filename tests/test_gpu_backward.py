@@ -62,6 +62,8 @@ def test_posterior_backward_fp32_error(kind):
     dy, dl = G.posterior_backward(t(P), t(gm), t(gv), "fp32")
     dy, dl = dy.cpu().numpy(), dl.cpu().numpy()
     say(f"posterior backward fp32 kind={kind}: rel dy={_rel(dy, dy_ref):.2e} rel dlogell={_rel(dl, dl_ref):.2e}")
+    # measured 7.9e-4 / 3.7e-4 (SE) and 5.9e-5 / 1.1e-4 (Matern): binary32 W of an
+    # ill-conditioned K; the binary64 path is held to 1e-8 above
     assert _rel(dy, dy_ref) <= 1e-3
     assert _rel(dl, dl_ref) <= 1e-3
 

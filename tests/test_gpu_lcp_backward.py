@@ -70,13 +70,14 @@ def test_lcp_backward_fp32_error():
                             torch.as_tensor(u, device=DEV), "fp32")
     dy, dl = dy.cpu().numpy(), dl.cpu().numpy()
     say(f"lcp backward fp32: rel dy={_rel(dy, dy_ref):.2e} rel dlogell={_rel(dl, dl_ref):.2e}")
-    assert _rel(dy, dy_ref) <= 2e-2
-    assert _rel(dl, dl_ref) <= 2e-2
+    # measured 8.8e-6 / 5.2e-6 (binary32 V and samples, binary64 sums)
+    assert _rel(dy, dy_ref) <= 1e-4
+    assert _rel(dl, dl_ref) <= 1e-4
 
 
 def test_lcp_backward_split_precision_error():
-    """V by the FP16 split product (about binary32 accuracy), the rest as binary32: the same
-    2e-2 relative bound as the binary32 path."""
+    """V by the FP16 split product (22 bits, a little under binary32), the rest as binary32:
+    measured 1.4e-5 / 1.8e-5, held to 2e-4."""
     W = _case(3, 9, m=60, seed=92)
     u = np.random.default_rng(93).random(W.n_cells)
     dy_ref, dl_ref = oracle.lcp_backward(oracle.fit(W), W, u)
@@ -85,8 +86,8 @@ def test_lcp_backward_split_precision_error():
                             torch.as_tensor(u, device=DEV), "f16x3")
     dy, dl = dy.cpu().numpy(), dl.cpu().numpy()
     say(f"lcp backward f16x3: rel dy={_rel(dy, dy_ref):.2e} rel dlogell={_rel(dl, dl_ref):.2e}")
-    assert _rel(dy, dy_ref) <= 2e-2
-    assert _rel(dl, dl_ref) <= 2e-2
+    assert _rel(dy, dy_ref) <= 2e-4
+    assert _rel(dl, dl_ref) <= 2e-4
 
 
 def test_autograd_lcp_posterior_split_precision_runs_and_agrees_with_fp32():
@@ -105,8 +106,9 @@ def test_autograd_lcp_posterior_split_precision_runs_and_agrees_with_fp32():
         grads[prec] = (y.grad.cpu().numpy(), log_ell.grad.cpu().numpy())
     say(f"autograd f16x3 vs fp32: rel dy={_rel(grads['f16x3'][0], grads['fp32'][0]):.2e} "
         f"rel dlogell={_rel(grads['f16x3'][1], grads['fp32'][1]):.2e}")
-    assert _rel(grads["f16x3"][0], grads["fp32"][0]) <= 2e-2
-    assert _rel(grads["f16x3"][1], grads["fp32"][1]) <= 2e-2
+    # measured 1.9e-6 / 6.3e-6
+    assert _rel(grads["f16x3"][0], grads["fp32"][0]) <= 1e-4
+    assert _rel(grads["f16x3"][1], grads["fp32"][1]) <= 1e-4
 
 
 def test_autograd_lcp_matches_gpu_finite_differences():
@@ -194,20 +196,23 @@ def test_full_size_differentiation_against_finite_differences():
     # (measured at h = 4e-3 ... 5e-4: the differences wander by that much while the
     # adjoint stays fixed).  The binary32 storage of the field adds < 0.1 at h = 5e-4.
     # Away from kinks the adjoint matches the oracle to 1e-7 (the small cases above).
+    # Measured: relative differences 5e-6, 3.7e-4 and 1.2e-3 for the three lengthscales
+    # (gradients of magnitude 5e2 to 1e3) and 3.1e-3 for dL/dy . v (magnitude 3.3e2), all
+    # held to 5e-3 relative with no absolute slack.
     with torch.no_grad():
         for d in range(3):
             e = torch.zeros_like(l0)
             e[d] = 5e-4
             fd = (loss(y0, l0 + e, "fp64") - loss(y0, l0 - e, "fp64")).item() / 1e-3
             say(f"96^3 dL/dlog_ell[{d}]: adjoint {gl[d].item():.6e} fd {fd:.6e}")
-            assert abs(gl[d].item() - fd) <= 3e-3 * abs(fd) + 0.1
+            assert abs(gl[d].item() - fd) <= 5e-3 * abs(fd)
         v = torch.as_tensor(np.random.default_rng(99).standard_normal(W.m), device=DEV)
         v /= torch.linalg.norm(v)
         fd = (loss(y0 + 1e-4 * v, l0, "fp64") - loss(y0 - 1e-4 * v, l0, "fp64")).item() / 2e-4
         dd = float((gy * v).sum().item())
         say(f"96^3 dL/dy . v: adjoint {dd:.6e} fd {fd:.6e}")
-        assert abs(dd - fd) <= 3e-3 * abs(fd) + 0.5
+        assert abs(dd - fd) <= 5e-3 * abs(fd)
     ry = _rel(grads["f16x3"][0].cpu().numpy(), gy.cpu().numpy())
     rl = _rel(grads["f16x3"][1].cpu().numpy(), gl.cpu().numpy())
     say(f"96^3 f16x3 vs fp64 gradients: rel dy={ry:.2e} rel dlogell={rl:.2e}")
-    assert ry <= 2e-2 and rl <= 2e-2
+    assert ry <= 2e-3 and rl <= 2e-3          # measured 4.3e-4 / 8.8e-5
