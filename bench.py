@@ -99,7 +99,9 @@ def oracle_errors(oracle, M, W, args, band, c0, L, lcp_a, cells_in, keys, sample
                      "max_lcp_skipped": float(band[~inleaf].max()) if (~inleaf).any() else 0.0},
     }
     t0 = time.perf_counter()
-    keys_ref, _, _ = oracle.adaptive(M, W)
+    keys_ref, _, _ = oracle.adaptive(M, W, edge_bound=int(args.edge_bound),
+                                     bound_kind={"search": 0, "certified": 1, "local": 2}[args.bound],
+                                     split=1 if args.split == "kd" else 0, beta=args.beta)
     t_ad = time.perf_counter() - t0
     a, b = set(int(k) for k in keys), set(int(k) for k in keys_ref)
     out["leaf_set"] = {"gpu": len(a), "oracle": len(b), "mismatches": len(a ^ b), "oracle_s": t_ad}
@@ -286,6 +288,8 @@ def main():
                     help="--bound local: box enlargement of the local models in lengthscales")
     ap.add_argument("--split", default="octree", choices=["octree", "kd"],
                     help="subdivision of the adaptive query: the paper's octree, or a K-D tree")
+    ap.add_argument("--edge-bound", action="store_true",
+                    help="keep a finest-level node only if its edge-crossing union bound exceeds alpha (Sec. 9)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
@@ -325,7 +329,8 @@ def main():
     adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4,
                          bound_kind={"search": lcp.BOUND_SEARCH, "certified": lcp.BOUND_CERTIFIED,
                                      "local": lcp.BOUND_LOCAL}[args.bound],
-                         split=lcp.SPLIT_KD if args.split == "kd" else lcp.SPLIT_OCTREE, beta=args.beta)
+                         split=lcp.SPLIT_KD if args.split == "kd" else lcp.SPLIT_OCTREE, beta=args.beta,
+                         edge_bound=int(args.edge_bound))
     zb = torch.as_tensor(W.zbank, device=dev)
     nvert = W.n_vertices
 
@@ -465,6 +470,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "npts": args.npts, "m": m, "n_samples": W.n_samples, "alpha": W.alpha,
                    "precision": args.prec, "region_bound": args.bound, "subdivision": args.split,
+                   "edge_bound": bool(args.edge_bound),
                    **({"local_beta": args.beta} if args.bound == "local" else {}),
                    "parallelism": "1 GPU"},
         "dense_fp64_ms_per_step": dense_ms,

@@ -82,6 +82,12 @@ typedef struct {
     int split;               /* lcp_split (0 = the octree of Alg. 1) */
     double beta;             /* LCP_BOUND_LOCAL only: box enlargement of the local model, in
                                 lengthscales per axis, finite and >= 0 (Sec. 7.3 recommends 6) */
+    int edge_bound;          /* 1: the tighter bound from edge crossings that Sec. 9 proposes: a
+                                finest-level node the region test emits is kept only if the union
+                                bound sum_e P(edge e crossed) over a spanning tree of its vertices
+                                exceeds alpha (the event "some cell crossed" is "some tree edge
+                                crossed"); its edge terms use the bivariate posterior of the edge's
+                                ends.  0: Alg. 1 as printed */
 } lcp_adapt;
 
 typedef enum {

@@ -32,7 +32,8 @@ class Grid(C.Structure):
 
 class Adapt(C.Structure):
     _fields_ = [("alpha", C.c_double), ("min_leaf", C.c_int), ("bound_at_max_depth", C.c_int),
-                ("steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int), ("beta", C.c_double)]
+                ("steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int), ("beta", C.c_double),
+                ("edge_bound", C.c_int)]
 
 
 BOUND_SEARCH, BOUND_CERTIFIED, BOUND_LOCAL = 0, 1, 2
@@ -42,12 +43,13 @@ SPLIT_OCTREE, SPLIT_KD = 0, 1
 class NodeRec(C.Structure):
     _fields_ = [("key", C.c_uint64), ("level", C.c_int32), ("n_obs", C.c_int32), ("p1", C.c_double),
                 ("p2", C.c_double), ("path", C.c_int32), ("subdivide", C.c_int32), ("gmin", C.c_double),
-                ("ub", C.c_double), ("lattice_gap", C.c_double), ("d", C.c_int64), ("n_local", C.c_int64)]
+                ("ub", C.c_double), ("lattice_gap", C.c_double), ("d", C.c_int64), ("n_local", C.c_int64),
+                ("eb", C.c_double)]
 
 
 NODE_DTYPE = np.dtype([("key", "<u8"), ("level", "<i4"), ("n_obs", "<i4"), ("p1", "<f8"), ("p2", "<f8"),
                        ("path", "<i4"), ("subdivide", "<i4"), ("gmin", "<f8"), ("ub", "<f8"),
-                       ("lattice_gap", "<f8"), ("d", "<i8"), ("n_local", "<i8")])
+                       ("lattice_gap", "<f8"), ("d", "<i8"), ("n_local", "<i8"), ("eb", "<f8")])
 assert NODE_DTYPE.itemsize == C.sizeof(NodeRec)
 
 
@@ -98,6 +100,10 @@ def lib():
         _lib.orc_level_field.argtypes = [P, C.c_int64, P, C.c_int64, P]
         _lib.orc_level_field_kd.argtypes = [P, C.c_int64, P, C.c_int64, P]
         _lib.orc_num_threads.restype = C.c_int
+        _lib.orc_edge_cross.restype = C.c_double
+        _lib.orc_edge_cross.argtypes = [C.c_double] * 6
+        _lib.orc_node_edge_bound.restype = C.c_double
+        _lib.orc_node_edge_bound.argtypes = [P, P, P, P, C.c_double]
     return _lib
 
 
@@ -343,14 +349,15 @@ def octree_shape(W, min_leaf=None):
 
 
 def adaptive(M: FitModel, W, alpha=None, min_leaf=None, bound_at_max_depth=1, steps=4, cap=1 << 22,
-             bound_kind=BOUND_SEARCH, split=SPLIT_OCTREE, beta=6.0):
+             bound_kind=BOUND_SEARCH, split=SPLIT_OCTREE, beta=6.0, edge_bound=0):
     """Alg. 1: returns (leaves, skipped, node records), each sorted by key.  With the K-D
     tree, records and skipped keys carry the depth (0 .. dim Lmax); leaves keep the octree
     key of the finest level.  BOUND_LOCAL runs the region test on the local model of
-    Sec. 5.2 (box enlarged by beta lengthscales)."""
+    Sec. 5.2 (box enlarged by beta lengthscales).  edge_bound=1 emits a deepest-level node
+    only if its edge-crossing union bound (record field eb) exceeds alpha."""
     g = grid_of(W)
     A = Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf),
-              int(bound_at_max_depth), int(steps), int(bound_kind), int(split), float(beta))
+              int(bound_at_max_depth), int(steps), int(bound_kind), int(split), float(beta), int(edge_bound))
     leaves = np.zeros(cap, np.uint64)
     skipped = np.zeros(cap, np.uint64)
     recs = np.zeros(cap, NODE_DTYPE)
@@ -414,3 +421,17 @@ def level_field_kd(W, keys, min_leaf=None):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def edge_cross(mua, mub, va, vb, c, theta):
+    """P(edge crossed) for the bivariate normal of the two end values (Sec. 9 reading)."""
+    return lib().orc_edge_cross(float(mua), float(mub), float(va), float(vb), float(c), float(theta))
+
+
+def node_edge_bound(M: FitModel, W, vlo, vhi):
+    """Edge-crossing union bound of the node spanning vertices vlo .. vhi (inclusive)."""
+    g = grid_of(W)
+    lo = np.zeros(3, np.int64)
+    hi = np.zeros(3, np.int64)
+    lo[: W.dim], hi[: W.dim] = vlo, vhi
+    return lib().orc_node_edge_bound(C.byref(M.s), C.byref(g), _p(lo), _p(hi), W.theta)

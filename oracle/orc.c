@@ -76,6 +76,8 @@ typedef struct {
     int bound_kind;         /* 0: bounded search (lattice + steps), 1: certified box bounds */
     int split;              /* 0: octree (Alg. 1), 1: K-D tree splitting the axes in turn (Sec. 9) */
     double beta;            /* bound_kind 2: box enlargement of the local model, in lengthscales */
+    int edge_bound;         /* 1: a deepest-level node the region test would emit is emitted only if
+                               its edge-crossing union bound exceeds alpha (orc_node_edge_bound) */
 } orc_adapt;
 
 typedef struct {
@@ -90,6 +92,7 @@ typedef struct {
     double lattice_gap;/* second-smallest minus smallest lattice value */
     int64_t d;         /* grid vertices inside the node */
     int64_t n_local;   /* bound_kind 2: |M'| of the local model (-1: no region test) */
+    double eb;         /* edge_bound: the node's edge-crossing union bound (NaN: not evaluated) */
 } orc_node_rec;
 
 /* ---------------------------------------------------------------- kernels -- */
@@ -1321,6 +1324,129 @@ double orc_certified_margin(double side, double theta, const double* cb)
 
 /* ---------------------------------------------------- octree (Alg. 1) -- */
 
+/* -------------------------------------------- edge-crossing region bound (Sec. 9) -- */
+/*
+ * Sec. 9 names a tighter region bound from the crossing probabilities of grid edges as
+ * future work.  The event "some cell of a node is crossed" (Sec. 4: not all corner values
+ * on one side of theta) equals "the vertex values of the node are not all on one side",
+ * which equals "some edge of a spanning tree of the node's vertices joins values on the two
+ * sides".  By the union bound, P(node crossed) <= sum over the tree's edges of
+ * P(edge crossed), and every cell's LCP is at most P(node crossed).  The edge terms use the
+ * joint bivariate posterior of the two end vertices (eq. (sgp)), so strong neighbour
+ * correlation keeps them small where the marginal bound of eq. (upper_bound) is not.
+ */
+
+/* Integrand of Plackett's identity: with rho = sin t,
+ *   P(Za < h, Zb < k) = Phi(h) Phi(k) + (1 / 2pi) int_0^{asin rho} f(t) dt,
+ *   f(t) = exp(-(h^2 - 2 h k sin t + k^2) / (2 cos^2 t)),
+ * since d/drho P = phi2(h, k; rho) and drho = cos t dt.  The exponent is rewritten as
+ * -(h - k)^2 / (2 cos^2 t) - h k / (1 + sin t) (using 1 - sin t = cos^2 t / (1 + sin t)),
+ * which stays exact as cos t -> 0 and gives 0 < f <= 1. */
+static double plackett_f(double h, double k, double t)
+{
+    double c = cos(t), s = sin(t);
+    double e = -h * k / (1.0 + s);
+    if (h != k) e -= (h - k) * (h - k) / (2.0 * c * c);
+    return exp(e);
+}
+
+/* Adaptive Simpson quadrature (Kuncir 1962; Richardson-corrected on acceptance). */
+static double simpson_step(double h, double k, double a, double b, double fa, double fm, double fb, double whole,
+                           double tol, int depth)
+{
+    double m = 0.5 * (a + b), lm = 0.5 * (a + m), rm = 0.5 * (m + b);
+    double flm = plackett_f(h, k, lm), frm = plackett_f(h, k, rm);
+    double left = (m - a) / 6.0 * (fa + 4.0 * flm + fm);
+    double right = (b - m) / 6.0 * (fm + 4.0 * frm + fb);
+    double diff = left + right - whole;
+    if (depth <= 0 || !(fabs(diff) > 15.0 * tol)) return left + right + diff / 15.0;
+    return simpson_step(h, k, a, m, fa, flm, fm, left, 0.5 * tol, depth - 1) +
+           simpson_step(h, k, m, b, fm, frm, fb, right, 0.5 * tol, depth - 1);
+}
+
+static double plackett_integral(double h, double k, double t1)
+{
+    double fa = plackett_f(h, k, 0.0), fb = plackett_f(h, k, t1), fm = plackett_f(h, k, 0.5 * t1);
+    double whole = t1 / 6.0 * (fa + 4.0 * fm + fb);
+    return simpson_step(h, k, 0.0, t1, fa, fm, fb, whole, 1e-15, 40);
+}
+
+static double norm_sf(double t) { return 0.5 * erfc(t / sqrt(2.0)); }
+
+/* P(edge crossed) for the bivariate normal of its end values X, Y (means mua, mub,
+ * variances va, vb, covariance c): P(not both < theta and not both > theta), a value equal
+ * to theta counting as crossed (Sec. 4's cell rule on two vertices). */
+double orc_edge_cross(double mua, double mub, double va, double vb, double c, double theta)
+{
+    double sa = sqrt(va > 0.0 ? va : 0.0), sb = sqrt(vb > 0.0 ? vb : 0.0);
+    if (sa == 0.0 && sb == 0.0) {
+        int below = mua < theta && mub < theta, above = mua > theta && mub > theta;
+        return (below || above) ? 0.0 : 1.0;
+    }
+    if (sa == 0.0 || sb == 0.0) {
+        /* one end is a constant: crossed unless the random end falls on its side */
+        double mc = sa == 0.0 ? mua : mub, mr = sa == 0.0 ? mub : mua, sr = sa == 0.0 ? sb : sa;
+        if (mc == theta) return 1.0;
+        double hr = (theta - mr) / sr;                 /* P(random end < theta) = Phi(hr) */
+        return mc < theta ? norm_sf(hr) : norm_cdf(hr);
+    }
+    double h = (theta - mua) / sa, k = (theta - mub) / sb;
+    double rho = c / (sa * sb);
+    if (rho >= 1.0) return fabs(norm_cdf(h) - norm_cdf(k));        /* Y = mub + sb Za */
+    if (rho <= -1.0) return 1.0 - fabs(norm_cdf(h) - norm_cdf(-k)); /* Y = mub - sb Za */
+    /* A negative correlation is reflected (Zb -> -Zb, k -> -k turns "crossed" into "not
+     * crossed"), so the integral below runs over t in [0, pi / 2) only. */
+    int reflect = rho < 0.0;
+    if (reflect) {
+        rho = -rho;
+        k = -k;
+    }
+    /* P = Phi(h) + Phi(k) - 2 P(both < theta)
+     *   = Phi(h) Q(k) + Phi(k) Q(h) - (1 / pi) int_0^{asin rho} f */
+    double p = norm_cdf(h) * norm_sf(k) + norm_cdf(k) * norm_sf(h) -
+               plackett_integral(h, k, asin(rho)) / 3.14159265358979323846;
+    if (reflect) p = 1.0 - p;
+    return p > 0.0 ? (p < 1.0 ? p : 1.0) : 0.0;
+}
+
+/* The edge-crossing union bound of the node whose vertices are [clo, chi] (inclusive) on
+ * every axis.  Spanning tree: every x-edge; the y-edges of the first x column of each
+ * z-plane; the z-edges of the first (x, y) column.  Summed in that order. */
+double orc_node_edge_bound(const orc_model* M, const orc_grid* G, const int64_t* clo, const int64_t* chi,
+                           double theta)
+{
+    int D = G->dim;
+    int64_t box_n[3] = {1, 1, 1}, nv;
+    for (int d = 0; d < D; ++d) box_n[d] = chi[d] - clo[d] + 1;
+    double *mean, *var, *V;
+    if (box_posterior(M, G, clo, box_n, &mean, &var, &V, &nv) != ORC_OK) return NAN;
+    int64_t nx = box_n[0], ny = box_n[1], nz = D == 3 ? box_n[2] : 1;
+    double eb = 0.0;
+    for (int pass = 0; pass < 3; ++pass) {
+        int64_t ei = pass == 0, ej = pass == 1, ek = pass == 2;
+        if (pass == 2 && D < 3) break;
+        for (int64_t k = 0; k < nz - ek; ++k)
+            for (int64_t j = 0; j < (pass == 2 ? 1 : ny - ej); ++j)
+                for (int64_t i = 0; i < (pass == 0 ? nx - 1 : 1); ++i) {
+                    int64_t a = i + nx * (j + ny * k), b = (i + ei) + nx * ((j + ej) + ny * (k + ek));
+                    double xc[6], vv[2] = {var[a], var[b]}, S[4];
+                    const double* vc[2] = {V + a * vwidth(M), V + b * vwidth(M)};
+                    int64_t ia[3] = {clo[0] + i, clo[1] + j, clo[2] + k};
+                    int64_t ib[3] = {ia[0] + ei, ia[1] + ej, ia[2] + ek};
+                    for (int d = 0; d < D; ++d) {
+                        xc[d] = vertex_coord(G, d, ia[d]);
+                        xc[D + d] = vertex_coord(G, d, ib[d]);
+                    }
+                    cell_cov(M, 2, xc, vv, vc, S);
+                    eb += orc_edge_cross(mean[a], mean[b], S[0], S[3], S[1], theta);
+                }
+    }
+    free(mean);
+    free(var);
+    free(V);
+    return eb;
+}
+
 static uint64_t morton(int D, const int64_t* c, int level)
 {
     uint64_t key = 0;
@@ -1405,6 +1531,7 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
     rec.ub = NAN;
     rec.lattice_gap = NAN;
     rec.n_local = -1;
+    rec.eb = NAN;
 
     int subdivide = 0;
     if (level == T->Ldepth && !T->A->bound_at_max_depth) {
@@ -1480,6 +1607,12 @@ static void octree_node(octree_ctx* T, int level, const int64_t* c)
             rec.ub = orc_upper_bound(rec.gmin, d_pts);
             subdivide = rec.ub > alpha;
         }
+    }
+    if (subdivide && level == T->Ldepth && T->A->edge_bound) {
+        /* the edge-crossing union bound may still show that no cell of the node exceeds alpha */
+        int64_t vlo[3] = {clo[0], clo[1], D == 3 ? clo[2] : 0}, vhi[3] = {chi[0], chi[1], D == 3 ? chi[2] : 0};
+        rec.eb = orc_node_edge_bound(M, G, vlo, vhi, T->theta);
+        subdivide = rec.eb > T->A->alpha;
     }
     rec.subdivide = subdivide;
     omp_set_lock(&T->lock);

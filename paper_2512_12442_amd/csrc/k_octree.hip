@@ -726,6 +726,178 @@ __global__ void k_slots(const int32_t* __restrict__ vmask, const int32_t* __rest
     }
 }
 
+// ------------------------------------------------------------ edge-crossing bound (Sec. 9)
+//
+// Sec. 9 proposes a tighter region bound from the crossing probabilities of grid edges.  A
+// node has a crossed cell exactly when its vertex values are not all on one side of theta,
+// that is when some edge of a spanning tree of its vertices is crossed; so
+// P(some cell crossed) <= sum over the tree of P(edge crossed), and each cell's LCP is at
+// most that.  The tree: every x-edge, the y-edges of the first x column of each z-plane,
+// the z-edges of the first (x, y) column.  The edge terms come from the posterior and
+// neighbour cross-covariances the reconstruction has just computed for the node's
+// vertices.
+
+// P(edge crossed) for end values X, Y ~ N((mua, mub), [[va, c], [c, vb]]): not both below
+// and not both above theta (a value equal to theta counts as crossed).  With standardised
+// thresholds h, k and correlation rho >= 0 (a negative one is reflected: Zb -> -Zb, k -> -k
+// exchanges crossed and not crossed), write Za = a U + b V, Zb = a U - b V with
+// a = sqrt((1 + rho) / 2), b = sqrt((1 - rho) / 2) and U, V independent N(0, 1).  For fixed
+// V = v both ends are increasing in U with the same slope a, so the edge is crossed exactly
+// when U lies between (h - b v) / a and (k + b v) / a:
+//   P = int phi(v) |Phi((h - b v) / a) - Phi((k + b v) / a)| dv.
+// The integrand is analytic on either side of its kink v* = (h - k) / (2 b); the integral
+// runs over [-9, 9] (phi(9) ~ 1e-18) in six panels with 12-point Gauss-Legendre rules, the
+// panel holding v* split there.
+__device__ __forceinline__ double phi_cdf(double x) { return 0.5 * erfc(-0.70710678118654752440 * x); }
+
+__device__ double edge_cross_prob(double mua, double mub, double va, double vb, double c, double theta)
+{
+    const double sa = sqrt(fmax(va, 0.0)), sb = sqrt(fmax(vb, 0.0));
+    if (sa == 0.0 && sb == 0.0) {
+        const bool below = mua < theta && mub < theta, above = mua > theta && mub > theta;
+        return (below || above) ? 0.0 : 1.0;
+    }
+    if (sa == 0.0 || sb == 0.0) {
+        const double mc = sa == 0.0 ? mua : mub, mr = sa == 0.0 ? mub : mua, sr = sa == 0.0 ? sb : sa;
+        if (mc == theta) return 1.0;
+        const double hr = (theta - mr) / sr;
+        return mc < theta ? phi_cdf(-hr) : phi_cdf(hr);
+    }
+    const double h = (theta - mua) / sa;
+    double k = (theta - mub) / sb;
+    double rho = c / (sa * sb);
+    if (rho >= 1.0) return fabs(phi_cdf(h) - phi_cdf(k));
+    if (rho <= -1.0) return 1.0 - fabs(phi_cdf(h) - phi_cdf(-k));
+    const bool reflect = rho < 0.0;
+    if (reflect) {
+        rho = -rho;
+        k = -k;
+    }
+    const double a = sqrt(0.5 * (1.0 + rho)), b = sqrt(0.5 * (1.0 - rho));
+    const double ia = 1.0 / a;
+    const double vs = (h - k) / (2.0 * b);
+    constexpr double gx[6] = {0.1252334085114689, 0.3678314989981802, 0.5873179542866175,
+                              0.7699026741943047, 0.9041172563704748, 0.9815606342467192};
+    constexpr double gw[6] = {0.2491470458134027, 0.23349253653835464, 0.20316742672306565,
+                              0.1600783285433461, 0.10693932599531888, 0.04717533638651202};
+    auto f = [&](double v) {
+        return exp(-0.5 * v * v) * fabs(phi_cdf((h - b * v) * ia) - phi_cdf((k + b * v) * ia));
+    };
+    auto panel = [&](double lo, double hi) {
+        const double m = 0.5 * (hi + lo), r = 0.5 * (hi - lo);
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) acc += gw[i] * (f(m - r * gx[i]) + f(m + r * gx[i]));
+        return r * acc;
+    };
+    double p = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        const double lo = -9.0 + 3.0 * q, hi = lo + 3.0;
+        if (vs > lo && vs < hi) p += panel(lo, vs) + panel(vs, hi);
+        else p += panel(lo, hi);
+    }
+    p *= 0.39894228040143267794;          // 1 / sqrt(2 pi)
+    if (reflect) p = 1.0 - p;
+    return fmin(fmax(p, 0.0), 1.0);
+}
+
+// One wave per emitted node: flag[i] = (edge-crossing bound of leaf i) > alpha.  Lanes take
+// the tree's edges in turn; the partial sums meet in a fixed butterfly (deterministic).
+__global__ void __launch_bounds__(256) k_edge_bound(Oct o, int leaf_edge, const uint64_t* __restrict__ leaves,
+                                                    const int64_t* __restrict__ nl_dev, int64_t leaf_cap,
+                                                    const int32_t* __restrict__ slot, const double* __restrict__ vmean,
+                                                    const double* __restrict__ vvar,
+                                                    const double* __restrict__ cross, int32_t* __restrict__ flag,
+                                                    double* __restrict__ eb_out)
+{
+    const int64_t nl = *nl_dev;
+    if (nl > leaf_cap) return;
+    const int lane = threadIdx.x & 63;
+    const int D = o.D, NDIR = D == 3 ? 13 : 4;
+    for (int64_t lf = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; lf < nl;
+         lf += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+        int lv;
+        int64_t c[3];
+        key_coords_oct(D, leaves[lf], lv, c);
+        const int64_t sz = o.S0 >> lv;
+        int64_t lo[3] = {0, 0, 0}, nv[3] = {1, 1, 1};
+        for (int d = 0; d < D; ++d) {
+            lo[d] = c[d] * sz;
+            int64_t hi = (c[d] + 1) * sz;
+            if (hi > o.g.nc[d]) hi = o.g.nc[d];
+            nv[d] = hi - lo[d] + 1;
+        }
+        const int64_t ex = (nv[0] - 1) * nv[1] * nv[2], ey = (nv[1] - 1) * nv[2], ez = D == 3 ? nv[2] - 1 : 0;
+        // rounds of 64 edges; the node is kept as soon as the running sum exceeds alpha
+        double total = 0.0;
+        for (int64_t e0 = 0; e0 < ex + ey + ez && !(total > o.alpha); e0 += 64) {
+            const int64_t e = e0 + lane;
+            double part = 0.0;
+            if (e < ex + ey + ez) {
+                int64_t i = 0, j = 0, k = 0;
+                int ax;
+                if (e < ex) {
+                    ax = 0;
+                    i = e % (nv[0] - 1);
+                    j = (e / (nv[0] - 1)) % nv[1];
+                    k = e / ((nv[0] - 1) * nv[1]);
+                } else if (e < ex + ey) {
+                    ax = 1;
+                    j = (e - ex) % (nv[1] - 1);
+                    k = (e - ex) / (nv[1] - 1);
+                } else {
+                    ax = 2;
+                    k = e - ex - ey;
+                }
+                const int64_t va = (lo[0] + i) + o.g.n[0] * ((lo[1] + j) + o.g.n[1] * (lo[2] + k));
+                const int64_t step = ax == 0 ? 1 : (ax == 1 ? o.g.n[0] : o.g.n[0] * o.g.n[1]);
+                const int64_t sa = slot[va], sb = slot[va + step];
+                if (sa < 0 || sb < 0) {           // not reconstructed (never for a leaf's own vertices)
+                    part = 1.0;
+                } else {
+                    // neighbour direction index of +x, +y, +z in the cross-covariance layout
+                    const int dir = D == 3 ? (ax == 0 ? 0 : (ax == 1 ? 2 : 8)) : (ax == 0 ? 0 : 2);
+                    const double cab = cross[(size_t)sa * NDIR + dir];
+                    part = edge_cross_prob(vmean[sa], vmean[sb], vvar[sa], vvar[sb], cab, o.theta);
+                }
+            }
+            for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+            total += part;
+        }
+        if (lane == 0) {
+            flag[lf] = total > o.alpha ? 1 : 0;
+            if (eb_out) eb_out[lf] = total;
+        }
+    }
+}
+
+// Keep the flagged leaves (order preserved): out[off[i]] = leaves[i].
+__global__ void k_keep_leaves(const uint64_t* __restrict__ leaves, const int64_t* __restrict__ nl_dev, int64_t leaf_cap,
+                              const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
+                              uint64_t* __restrict__ out)
+{
+    const int64_t nl = *nl_dev;
+    if (nl > leaf_cap) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += (int64_t)gridDim.x * blockDim.x)
+        if (flag[i]) out[off[i]] = leaves[i];
+}
+
+// Copy the kept leaves back (unless the leaf list overflowed); the count follows in a
+// launch of its own, after every block here has read the old count.
+__global__ void k_store_kept(const uint64_t* __restrict__ kept, const int64_t* __restrict__ kept_n,
+                             uint64_t* __restrict__ leaves, const int64_t* __restrict__ nl_dev, int64_t leaf_cap)
+{
+    const int64_t nl = *nl_dev, nk = *kept_n;
+    if (nl > leaf_cap) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x)
+        leaves[i] = kept[i];
+}
+
+__global__ void k_set_leaf_count(int64_t* __restrict__ nl_dev, const int64_t* __restrict__ kept_n, int64_t leaf_cap)
+{
+    if (*nl_dev <= leaf_cap) *nl_dev = *kept_n;
+}
+
 // Octree level at which each cell's node stopped.
 __global__ void k_level_field(Oct o, const uint8_t* __restrict__ stat, uint8_t* __restrict__ field)
 {
@@ -1681,6 +1853,26 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     if (e != hipSuccess) return e;
     e = launch_cross(M, prec, g, vlist, nvd, L.nv, slot, V, cross, s);
     if (e != hipSuccess) return e;
+    if (A.edge_bound) {
+        // keep the emitted nodes whose edge-crossing bound exceeds alpha (octree buffers reused)
+        StageScope sc(s, ST_OCTREE);
+        int32_t* eflag = (int32_t*)P(L.o_flag);
+        int32_t* eoff2 = (int32_t*)P(L.o_fidx);
+        uint64_t* kept = (uint64_t*)P(L.o_keys0);
+        int64_t* kept_n = cnt + 41;
+        hipLaunchKernelGGL(k_edge_bound, dim3(gsz(leaf_cap * 64, 256)), dim3(256), 0, s, o, leaf_edge, leaves,
+                           n_leaves, leaf_cap, slot, vmean, vvar, cross, eflag, (double*)nullptr);
+        const int64_t ncap = leaf_cap < caps[Ldepth] ? leaf_cap : caps[Ldepth];   // the octree buffers' size
+        e = launch_scan(eflag, eoff2, ncap, n_leaves, kept_n, scanws, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_keep_leaves, dim3(gsz(leaf_cap, 256)), dim3(256), 0, s, leaves, n_leaves, leaf_cap,
+                           eflag, eoff2, kept);
+        hipLaunchKernelGGL(k_store_kept, dim3(gsz(leaf_cap, 256)), dim3(256), 0, s, kept, kept_n, leaves, n_leaves,
+                           leaf_cap);
+        hipLaunchKernelGGL(k_set_leaf_count, dim3(1), dim3(1), 0, s, n_leaves, kept_n, leaf_cap);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     float* zb32 = (float*)P(L.o_zb);
     if (prec != LCP_FP64) {
         e = launch_zbank32(zb, zb32, (int64_t)ns << D, s);

@@ -170,6 +170,7 @@ int check_adapt(const Model& M, const lcp_adapt* A)
     }
     if (A->split != LCP_SPLIT_OCTREE && A->split != LCP_SPLIT_KD)
         return fail(LCP_EINVAL, "split must be LCP_SPLIT_OCTREE or LCP_SPLIT_KD");
+    if (A->edge_bound != 0 && A->edge_bound != 1) return fail(LCP_EINVAL, "edge_bound must be 0 or 1");
     return LCP_OK;
 }
 

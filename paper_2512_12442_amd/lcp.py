@@ -40,7 +40,8 @@ class Grid(C.Structure):
 
 class Adapt(C.Structure):
     _fields_ = [("alpha", C.c_double), ("min_leaf_cells", C.c_int), ("bound_at_max_depth", C.c_int),
-                ("descent_steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int), ("beta", C.c_double)]
+                ("descent_steps", C.c_int), ("bound_kind", C.c_int), ("split", C.c_int), ("beta", C.c_double),
+                ("edge_bound", C.c_int)]
 
 
 BOUND_SEARCH, BOUND_CERTIFIED, BOUND_LOCAL = 0, 1, 2
@@ -453,9 +454,9 @@ def grid_of(W) -> Grid:
 
 
 def adapt_of(W, min_leaf=None, bound_at_max_depth=1, steps=4, alpha=None, bound_kind=BOUND_SEARCH,
-             split=SPLIT_OCTREE, beta=6.0) -> Adapt:
+             split=SPLIT_OCTREE, beta=6.0, edge_bound=0) -> Adapt:
     return Adapt(float(alpha if alpha is not None else W.alpha), int(min_leaf or W.min_leaf), int(bound_at_max_depth),
-                 int(steps), int(bound_kind), int(split), float(beta))
+                 int(steps), int(bound_kind), int(split), float(beta), int(edge_bound))
 
 
 class GPModelBatch:

@@ -46,14 +46,18 @@ def mean_error_bound32(W, M, P):
 
 
 def near_tie_keys(recs, alpha):
-    """Nodes whose decision depends on rounding: UB within 1e-8 relative of alpha, p1/p2
-    within 1e-12 of alpha, or two lattice minima within 1e-9 of each other."""
+    """Nodes whose decision depends on rounding: UB (or the edge-crossing bound) within 1e-8
+    relative of alpha, p1/p2 within 1e-12 of alpha, or two lattice minima within 1e-9 of each
+    other."""
     bad = set()
     for r in recs:
         if r["path"] in (1, 2) or (r["path"] != 0 and not np.isnan(r["ub"])):
             if abs(r["ub"] - alpha) <= 1e-8 * alpha or abs(r["lattice_gap"]) <= 1e-9 * max(1, abs(r["gmin"])):
                 bad.add(int(r["key"]))
         if r["n_obs"] > 0 and (abs(r["p1"] - alpha) <= 1e-12 or abs(r["p2"] - alpha) <= 1e-12):
+            bad.add(int(r["key"]))
+        # the edge-crossing bound: the GPU's quadrature agrees with the oracle's to ~1e-13
+        if "eb" in r.dtype.names and not np.isnan(r["eb"]) and abs(r["eb"] - alpha) <= 1e-8 * alpha:
             bad.add(int(r["key"]))
     return bad
 

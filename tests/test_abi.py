@@ -103,7 +103,9 @@ def test_adapt_struct_carries_the_bound_kind():
     a = lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 4})(), bound_kind=lcp.BOUND_CERTIFIED)
     assert a.bound_kind == 1 and a.descent_steps == 4 and a.min_leaf_cells == 4
     assert lcp.lcp.Adapt.bound_kind.offset == 20 and lcp.lcp.Adapt.split.offset == 24
-    assert lcp.lcp.Adapt.beta.offset == 32 and C.sizeof(lcp.lcp.Adapt) == 40
+    assert lcp.lcp.Adapt.beta.offset == 32 and lcp.lcp.Adapt.edge_bound.offset == 40
+    assert C.sizeof(lcp.lcp.Adapt) == 48
+    assert lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 4})(), edge_bound=1).edge_bound == 1
     a = lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 4})(), bound_kind=lcp.BOUND_LOCAL, beta=2.5)
     assert a.bound_kind == 2 and a.beta == 2.5
     assert lcp.adapt_of(type("W", (), {"alpha": 1e-3, "min_leaf": 2})(), split=lcp.SPLIT_KD).split == 1
