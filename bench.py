@@ -196,9 +196,12 @@ def run_local_blocks(args):
         "precision_per_model": {names[p]: sum(1 for q in sel if q == p) for p in set(sel)},
         "posterior_flop_share": {names[p]: f / total for p, f in flops.items()},
         "kappa_max_binary32": max([k for k, p in zip(kappa, sel) if p == lcp.PRECISIONS["fp32"]], default=None),
+        "tiles": {names[p]: {f"m_pad<={128 * (c + 1)}": "%dx%d" % lcp.batch_tiles(names[p], c) for c in range(8)}
+                  for p in set(sel)},
+        "tiles_source": "autotuned (paper_2512_12442_amd/autotune.py -> csrc/tune_table.inc)",
         "fit_ms": fit_ms, "stage_ms": stage_ms,
         "roofline": {"bound": "mfma", "kernel": "k_post_batch (the posterior GEMMs of all blocks, one launch per "
-                                                 "precision)",
+                                                 "precision and size class)",
                      "achieved": total / (dur * 1e-3) / 1e12, "peak": total / t_ideal / 1e12, "unit": "TFLOP/s",
                      "frac": t_ideal / (dur * 1e-3), "traffic": None, "avg_step_posterior_ms": dur,
                      "note": "peak = the algorithmic flop's time at each precision's MFMA peak (FP32 157.3, "

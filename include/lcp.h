@@ -337,6 +337,19 @@ int lcp_dense_batch(const lcp_model_batch* batch, const lcp_grid* grids, const d
  */
 int lcp_batch_precision(const lcp_model_batch* batch, int reduced, double kappa_max, int* prec, double* kappa,
                         void* stream);
+
+/*
+ * lcp_batch_tiles -- tile width nt (16 or 32 columns per work-group) and waves nw (4, 8 or 16)
+ * of the batched posterior for models of precision `prec` with m_pad = 128 (size_class + 1)
+ * (m_pad = m rounded up to 128; size_class 0..7).  The library's defaults come from the
+ * project's autotuner (paper_2512_12442_amd/autotune.py), which times every candidate on the
+ * batched workload and writes them into the build; nt = 0 restores them.  LCP_EINVAL if the
+ * pair is not a candidate or its tile exceeds the LDS.  Process-wide and not synchronised:
+ * set it before launches that other threads may issue.
+ * lcp_batch_tiles_get -- the current setting.
+ */
+int lcp_batch_tiles(int prec, int size_class, int nt, int nw);
+int lcp_batch_tiles_get(int prec, int size_class, int* nt, int* nw);
 int lcp_dense_batch_mixed_workspace(const lcp_model_batch* batch, const lcp_grid* grids, const int* prec,
                                     int n_samples, size_t* bytes);
 int lcp_dense_batch_mixed(const lcp_model_batch* batch, const lcp_grid* grids, const double* theta, const lcp_mc* mc,

@@ -21,7 +21,6 @@ namespace lcp {
 
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kWaves = 4;
 
 // Precision traits: operand types, MFMA k-step, fragment arrays and LDS element type.
@@ -843,8 +842,8 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
 
 }  // namespace
 
-// One launch over the listed models (idx) with tiles of NT columns.
-template <class P, int NT>
+// One launch over the listed models (idx) with tiles of NT columns and NW waves.
+template <class P, int NT, int NW>
 static hipError_t launch_batch_t(const Model* const* Ms, const PostTask* tasks, const std::vector<int>& idx,
                                  char* scratch, hipStream_t s, const void* const* A0, const void* const* A1)
 {
@@ -868,19 +867,93 @@ static hipError_t launch_batch_t(const Model* const* Ms, const PostTask* tasks, 
     if (e != hipSuccess) return e;
     if (toff[nb] == 0) return hipSuccess;
     const int ldb = (P::KS == 32) ? (mpmax + 63) / 64 * 64 + P::LPAD : mpmax + P::LPAD;
-    const size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (kThreads + NT);
-    e = hipFuncSetAttribute((const void*)k_post_batch<P, NT, kWaves>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (NW * 64 + NT);
+    e = hipFuncSetAttribute((const void*)k_post_batch<P, NT, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
     if (e != hipSuccess) return e;
     const int64_t grid = toff[nb] < 256 * 8 ? toff[nb] : 256 * 8;
-    hipLaunchKernelGGL((k_post_batch<P, NT, kWaves>), dim3((unsigned)grid), dim3(kThreads), lds, s, KAd, toffd, nb);
+    hipLaunchKernelGGL((k_post_batch<P, NT, NW>), dim3((unsigned)grid), dim3(NW * 64), lds, s, KAd, toffd, nb);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------- batched posterior tiles
+//
+// Tile width (columns per work-group) and waves per work-group of the batched posterior,
+// per precision and size class c (m_pad = 128 (c + 1)).  The defaults are the autotuner's
+// measured choices (paper_2512_12442_amd/autotune.py writes tune_table.inc); lcp_batch_tiles
+// overrides them.  Candidates: tile width 16 or 32, 4, 8 or 16 waves, whose B tile fits LDS.
+struct TileCfg {
+    int nt, nw;
+};
+
+constexpr int kSizeClasses = kMaxM / 128;
+#include "tune_table.inc"          // static const TileCfg kTunedTiles[4][kSizeClasses]
+static TileCfg g_tiles[4][kSizeClasses];
+static bool g_tiles_init = false;
+
+static size_t batch_lds_bytes(int prec, int nt, int nw, int mp)
+{
+    const bool split = prec == LCP_MIXED_F16X3 || prec == LCP_MIXED_BF16X3;
+    const int ldb = split ? (mp + 63) / 64 * 64 + 8 : mp + (prec == LCP_FP64 ? 1 : 2);
+    const size_t elem = prec == LCP_FP64 ? 8 : (prec == LCP_FP32 ? 4 : 2);
+    return elem * (split ? 2 : 1) * (size_t)nt * ldb + sizeof(double) * (nw * 64 + nt);
+}
+
+static bool tile_valid(int prec, int cls, int nt, int nw)
+{
+    return (nt == 16 || nt == 32) && (nw == 4 || nw == 8 || nw == 16) &&
+           batch_lds_bytes(prec, nt, nw, 128 * (cls + 1)) <= 160 * 1024;
+}
+
+static TileCfg tiles_of(int prec, int cls)
+{
+    if (!g_tiles_init) {
+        for (int p = 0; p < 4; ++p)
+            for (int c = 0; c < kSizeClasses; ++c) g_tiles[p][c] = kTunedTiles[p][c];
+        g_tiles_init = true;
+    }
+    return g_tiles[prec][cls];
+}
+
+int set_batch_tiles(int prec, int cls, int nt, int nw)
+{
+    if (prec < 0 || prec > 3 || cls < 0 || cls >= kSizeClasses) return -1;
+    tiles_of(prec, cls);
+    if (nt == 0) {
+        g_tiles[prec][cls] = kTunedTiles[prec][cls];
+        return 0;
+    }
+    if (!tile_valid(prec, cls, nt, nw)) return -1;
+    g_tiles[prec][cls] = TileCfg{nt, nw};
+    return 0;
+}
+
+void get_batch_tiles(int prec, int cls, int* nt, int* nw)
+{
+    const TileCfg t = tiles_of(prec, cls);
+    *nt = t.nt;
+    *nw = t.nw;
+}
+
+template <class P>
+static hipError_t launch_batch_cfg(TileCfg c, const Model* const* Ms, const PostTask* tasks, const std::vector<int>& idx,
+                                   char* scratch, hipStream_t s, const void* const* A0, const void* const* A1)
+{
+    switch (c.nt * 100 + c.nw) {
+    case 1604: return launch_batch_t<P, 16, 4>(Ms, tasks, idx, scratch, s, A0, A1);
+    case 1608: return launch_batch_t<P, 16, 8>(Ms, tasks, idx, scratch, s, A0, A1);
+    case 1616: return launch_batch_t<P, 16, 16>(Ms, tasks, idx, scratch, s, A0, A1);
+    case 3204: return launch_batch_t<P, 32, 4>(Ms, tasks, idx, scratch, s, A0, A1);
+    case 3208: return launch_batch_t<P, 32, 8>(Ms, tasks, idx, scratch, s, A0, A1);
+    case 3216: return launch_batch_t<P, 32, 16>(Ms, tasks, idx, scratch, s, A0, A1);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 size_t posterior_batch_scratch(int nb)
 {
-    // two launches (models up to 512 observations, and larger ones), each with its records
-    return 2 * (align256(sizeof(KArgs) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1)));
+    // the records of one launch (the size-class launches reuse them in stream order)
+    return align256(sizeof(KArgs) * (size_t)nb) + align256(sizeof(int64_t) * (size_t)(nb + 1));
 }
 
 hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks, int nb, int prec, char* scratch,
@@ -895,26 +968,20 @@ hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks,
               : prec == LCP_MIXED_F16X3 ? (const void*)M.Hhi : (const void*)M.Ahi;
         A1[b] = prec == LCP_MIXED_F16X3 ? (const void*)M.Hlo : prec == LCP_MIXED_BF16X3 ? (const void*)M.Alo : nullptr;
     }
-    // Models up to 512 observations take 32-column tiles (binary64: 16), larger ones half
-    // that, so B stays within 80 KB of LDS and two work-groups share a CU in both launches.
-    std::vector<int> small, large;
-    for (int b = 0; b < nb; ++b) (Ms[b]->m_pad <= 512 ? small : large).push_back(b);
-    char* sc2 = scratch + posterior_batch_scratch(nb) / 2;
-    hipError_t e;
-    if (prec == LCP_FP64) {
-        e = launch_batch_t<P64, 16>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
-        if (e == hipSuccess) e = launch_batch_t<P64, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
-    } else if (prec == LCP_FP32) {
-        e = launch_batch_t<P32, 32>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
-        if (e == hipSuccess) e = launch_batch_t<P32, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
-    } else if (prec == LCP_MIXED_F16X3) {
-        e = launch_batch_t<PH3, 32>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
-        if (e == hipSuccess) e = launch_batch_t<PH3, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
-    } else {
-        e = launch_batch_t<PB3, 32>(Ms, tasks, small, scratch, s, A0.data(), A1.data());
-        if (e == hipSuccess) e = launch_batch_t<PB3, 16>(Ms, tasks, large, sc2, s, A0.data(), A1.data());
+    // one launch per size class, with that class's tile configuration
+    std::vector<std::vector<int>> cls(kSizeClasses);
+    for (int b = 0; b < nb; ++b) cls[Ms[b]->m_pad / 128 - 1].push_back(b);
+    for (int c = 0; c < kSizeClasses; ++c) {
+        if (cls[c].empty()) continue;
+        const TileCfg t = tiles_of(prec, c);
+        hipError_t e;
+        if (prec == LCP_FP64) e = launch_batch_cfg<P64>(t, Ms, tasks, cls[c], scratch, s, A0.data(), A1.data());
+        else if (prec == LCP_FP32) e = launch_batch_cfg<P32>(t, Ms, tasks, cls[c], scratch, s, A0.data(), A1.data());
+        else if (prec == LCP_MIXED_F16X3) e = launch_batch_cfg<PH3>(t, Ms, tasks, cls[c], scratch, s, A0.data(), A1.data());
+        else e = launch_batch_cfg<PB3>(t, Ms, tasks, cls[c], scratch, s, A0.data(), A1.data());
+        if (e != hipSuccess) return e;
     }
-    return e;
+    return hipSuccess;
 }
 
 hipError_t launch_posterior_operand(const Model& M, int prec, const PostTask& t, const void* A0, hipStream_t s)

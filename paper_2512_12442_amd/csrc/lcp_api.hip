@@ -1021,3 +1021,22 @@ int lcp_batch_precision(const lcp_model_batch* B, int reduced, double kappa_max,
     }
     return ok();
 }
+
+int lcp_batch_tiles(int prec, int size_class, int nt, int nw)
+{
+    if (check_prec(prec)) return LCP_EINVAL;
+    if (size_class < 0 || size_class >= kMaxM / 128) return fail(LCP_EINVAL, "size_class must lie in 0..%d", kMaxM / 128 - 1);
+    if (set_batch_tiles(prec, size_class, nt, nw))
+        return fail(LCP_EINVAL, "tiles %d x %d waves: not a candidate, or the B tile exceeds LDS at m_pad = %d", nt, nw,
+                    128 * (size_class + 1));
+    return ok();
+}
+
+int lcp_batch_tiles_get(int prec, int size_class, int* nt, int* nw)
+{
+    if (check_prec(prec)) return LCP_EINVAL;
+    if (size_class < 0 || size_class >= kMaxM / 128) return fail(LCP_EINVAL, "size_class must lie in 0..%d", kMaxM / 128 - 1);
+    if (!nt || !nw) return fail(LCP_EINVAL, "nt and nw must not be NULL");
+    get_batch_tiles(prec, size_class, nt, nw);
+    return ok();
+}

@@ -323,6 +323,11 @@ hipError_t launch_factor_batch_finish(Model* const* Ms, int nb, char* scratch, h
 // Value columns of many models in one launch: KArgs-equivalent records built from tasks[b]
 // (COL_GRID or COL_POINTS, no device count) into scratch (posterior_batch_scratch bytes).
 size_t posterior_batch_scratch(int nb);
+// Tile configuration of the batched posterior for precision prec and size class cls
+// (m_pad = 128 (cls + 1)): set (nt = 0 restores the tuned default; -1 if the pair is not
+// a candidate or its B tile exceeds LDS) and read back.
+int set_batch_tiles(int prec, int cls, int nt, int nw);
+void get_batch_tiles(int prec, int cls, int* nt, int* nw);
 hipError_t launch_posterior_batch(const Model* const* Ms, const PostTask* tasks, int nb, int prec, char* scratch,
                                   hipStream_t s);
 

@@ -62,7 +62,7 @@ EXPORTS = ["lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_fit_factor
            "lcp_dense_batch", "gp_posterior_backward_workspace", "gp_posterior_backward",
            "lcp_backward_workspace", "lcp_bound_workspace", "lcp_bound_certified", "lcp_dense_noalloc",
            "lcp_cell_moments_workspace", "lcp_cell_moments", "lcp_batch_precision",
-           "lcp_dense_batch_mixed_workspace", "lcp_dense_batch_mixed"]
+           "lcp_dense_batch_mixed_workspace", "lcp_dense_batch_mixed", "lcp_batch_tiles", "lcp_batch_tiles_get"]
 
 STAGES = ["factor", "posterior", "bound", "cross", "cells", "octree", "misc"]
 
@@ -115,6 +115,8 @@ def lib():
     L.lcp_batch_precision.argtypes = [P, C.c_int, C.c_double, P, P, P]
     L.lcp_dense_batch_mixed_workspace.argtypes = [P, P, P, C.c_int, C.POINTER(SZ)]
     L.lcp_dense_batch_mixed.argtypes = [P, P, P, P, P, P, P, SZ, P]
+    L.lcp_batch_tiles.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    L.lcp_batch_tiles_get.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in EXPORTS:
         if name not in ("lcp_status_str", "lcp_last_error", "lcp_model_bytes", "gp_model_free",
                         "lcp_batch_model_bytes", "gp_model_batch_free"):
@@ -539,3 +541,14 @@ class GPModelBatch:
             _check(lib().lcp_dense_batch_mixed(self.h, G, th, C.byref(mc), pr, _ptr(out), _ptr(ws), ws.numel(),
                                                _stream()))
         return out, ws
+
+
+def batch_tiles(prec, size_class, nt=None, nw=None):
+    """Read (and with nt, nw set) the batched posterior's tile configuration for a
+    precision and size class (m_pad = 128 (size_class + 1)); nt = 0 restores the default."""
+    L = lib()
+    if nt is not None:
+        _check(L.lcp_batch_tiles(_prec(prec), int(size_class), int(nt), int(nw or 0)))
+    a, b = C.c_int(), C.c_int()
+    _check(L.lcp_batch_tiles_get(_prec(prec), int(size_class), C.byref(a), C.byref(b)))
+    return a.value, b.value
