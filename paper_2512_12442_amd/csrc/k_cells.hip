@@ -519,6 +519,197 @@ __global__ void __launch_bounds__(256) k_cells(R src, int64_t ncells_cap)
     }
 }
 
+// ------------------------------------------------------------ matrix-core Monte Carlo
+//
+// Reduced-precision paths, 3D.  The values y - theta of the 8 corners of 4 cells (32 rows)
+// for 32 samples (columns) form one 32 x 32 product.  With s a power of two per cell that
+// keeps the operands in FP16 range, row (cell, corner q) of the left operand holds s C_q and
+// s (mu_q - theta), each as an FP16 pair hi + lo, and column j of the right operand holds
+// z_j as an FP16 pair and a 1:
+//   s (mu_q - theta + C_q . z_j) = [C_hi | C_lo] [z_hi; z_hi] + [C_hi | m_hi m_lo 0..] [z_lo; 1 1 0..]
+// (two 32x32x16 MFMAs, binary32 accumulation).  The dropped C_lo z_lo term and the FP16
+// rounding of the lo halves stay below 2^-21 (|s mu| + |s C| |z|), inside the margin the
+// certificate keeps for binary32 loops.  The crossing test reads only signs, which s > 0
+// leaves unchanged.
+//
+// Row order: the MFMA leaves row r = 8a + 4h + c of the result in register 4a + c of lane
+// half h, and row r is corner 2a + (c & 1) of cell 2h + (c >> 1) of the quad, so each lane
+// holds all 8 corners of two cells for its sample.
+
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMcCells = 32;     // cells per wave (8 quads of 4)
+constexpr int kMcWaves = 4;
+
+// Split FP16 records of the z-bank, 24 halves per sample: [z_hi (8) | z_lo (8) | 1, 1, 0 x 6],
+// z = z_hi + z_lo to within 2^-22 |z|; samples ns .. nspad - 1 are zero.
+__global__ void k_zrec(const double* __restrict__ zb, int ns, int nspad, _Float16* __restrict__ rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nspad * 8) return;
+    const int64_t smp = i >> 3;
+    const int k = (int)(i & 7);
+    const double z = smp < ns ? zb[smp * 8 + k] : 0.0;
+    const _Float16 hi = (_Float16)(float)z;
+    rec[smp * 24 + k] = hi;
+    rec[smp * 24 + 8 + k] = (_Float16)(float)(z - (double)hi);
+    rec[smp * 24 + 16 + k] = (_Float16)(k < 2 ? 1.0f : 0.0f);
+}
+
+// Sign tests on the bit patterns (no NaN canonicalisation): for a non-NaN binary32 y,
+// y > 0 iff its bits as a signed integer are > 0, and y < 0 iff its bits as an unsigned
+// integer exceed 0x80000000 (-0 is 0x80000000).  So every corner of a cell is above theta
+// iff the signed minimum of its 8 values is > 0, and below iff the unsigned minimum is
+// > 0x80000000.  Registers o, o+1, o+4, o+5, o+8, o+9, o+12, o+13 hold one cell (o = 0, 2).
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ unsigned umin(unsigned a, unsigned b) { return a < b ? a : b; }
+template <int O>
+__device__ __forceinline__ int min8_i(const f32x16& a)
+{
+    const int m0 = imin(imin(__float_as_int(a[O]), __float_as_int(a[O + 1])), __float_as_int(a[O + 4]));
+    const int m1 = imin(imin(__float_as_int(a[O + 5]), __float_as_int(a[O + 8])), __float_as_int(a[O + 9]));
+    return imin(imin(m0, m1), imin(__float_as_int(a[O + 12]), __float_as_int(a[O + 13])));
+}
+template <int O>
+__device__ __forceinline__ unsigned min8_u(const f32x16& a)
+{
+    const unsigned m0 = umin(umin(__float_as_uint(a[O]), __float_as_uint(a[O + 1])), __float_as_uint(a[O + 4]));
+    const unsigned m1 = umin(umin(__float_as_uint(a[O + 5]), __float_as_uint(a[O + 8])), __float_as_uint(a[O + 9]));
+    return umin(umin(m0, m1), umin(__float_as_uint(a[O + 12]), __float_as_uint(a[O + 13])));
+}
+
+// Monte Carlo LCP of the listed cells (count = *wcount), 32 cells per wave: lanes 0..31
+// factor one cell each in binary64 and stage its scaled FP16 operand rows in LDS; the wave
+// then sweeps the sample blocks with the 8 quads' operands in registers and keeps the
+// crossing counts in scalar registers.
+template <class R>
+__global__ void __launch_bounds__(kMcWaves * 64) k_cells_mfma(R src, int64_t ncells_cap, const h8v* __restrict__ zrec)
+{
+    __shared__ __align__(16) h8v stage[kMcWaves][kMcCells][8][3];   // [cell][corner]: C_hi, C_lo, (m_hi, m_lo, 0..)
+    const CellTask& t0 = src.first();
+    int64_t total = *t0.wcount;
+    if (total > ncells_cap) total = ncells_cap;
+    const int ns = t0.ns;
+    const int nblk = (ns + 31) >> 5;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, r = lane & 31;
+    const int rcell = 2 * ((r >> 2) & 1) + ((r & 3) >> 1), rcorner = 2 * (r >> 3) + (r & 1);
+    const int tail = ns - 32 * (nblk - 1);                    // samples of the last block, 1..32
+    const uint64_t tm32 = tail == 32 ? 0xffffffffull : ((1ull << tail) - 1);
+    const uint64_t tmask = tm32 | (tm32 << 32);               // both lane halves hold the same samples
+    h8v (*st)[8][3] = stage[wave];
+    for (int64_t base = ((int64_t)blockIdx.x * kMcWaves + wave) * kMcCells; base < total;
+         base += (int64_t)gridDim.x * kMcWaves * kMcCells) {
+        int64_t lin = -1;
+        float* out = nullptr;
+        if (lane < kMcCells) {
+            double mu[8], Cd[8][8];
+            const int64_t it = base + lane;
+            if (it < total) {
+                int64_t le = 0;
+                const CellTask& t = src.resolve(t0.work[it], le);
+                int64_t sl[8];
+                if (cell_corners<3>(t, le, lin, sl) == 2) {
+                    cell_factor<3>(t, sl, mu, Cd);
+                    out = t.lcp;
+                }
+            }
+            if (out) {
+                double mx = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    mx = fmax(mx, fabs(mu[q]));
+#pragma unroll
+                    for (int k = 0; k <= q; ++k) mx = fmax(mx, fabs(Cd[q][k]));
+                }
+                int e = 0;
+                if (mx > 0.0) frexp(mx, &e);                  // mx < 2^e
+                if (e < -1000) e = -1000;
+                const double sc = ldexp(1.0, 14 - e);         // every scaled operand below 2^14
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    h8v hi, lo, mm;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const double x = k <= q ? Cd[q][k] * sc : 0.0;
+                        const _Float16 xh = (_Float16)(float)x;
+                        hi[k] = xh;
+                        lo[k] = (_Float16)(float)(x - (double)xh);
+                        mm[k] = (_Float16)0.0f;
+                    }
+                    const double m = mu[q] * sc;
+                    const _Float16 mh = (_Float16)(float)m;
+                    mm[0] = mh;
+                    mm[1] = (_Float16)(float)(m - (double)mh);
+                    st[lane][q][0] = hi;
+                    st[lane][q][1] = lo;
+                    st[lane][q][2] = mm;
+                }
+            } else {
+                const h8v z = {};
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    st[lane][q][0] = z;
+                    st[lane][q][1] = z;
+                    st[lane][q][2] = z;
+                }
+            }
+        }
+        // the staged rows are read by other lanes of this wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        h8v A1[8], A2[8];
+#pragma unroll
+        for (int Q = 0; Q < 8; ++Q) {
+            A1[Q] = st[4 * Q + rcell][rcorner][h];            // C_hi | C_lo
+            A2[Q] = st[4 * Q + rcell][rcorner][2 * h];        // C_hi | (m_hi, m_lo, 0..)
+        }
+        uint32_t cnt[8][4];
+#pragma unroll
+        for (int Q = 0; Q < 8; ++Q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cnt[Q][k] = 0;
+        const h8v* zp = zrec + 3 * r;                         // record of sample 32 b + r
+        h8v B1 = zp[0], B2 = zp[1 + h];
+        for (int b = 0; b < nblk; ++b) {
+            const h8v* zn = zp + (size_t)96 * (b + 1 < nblk ? b + 1 : b);
+            const h8v nB1 = zn[0], nB2 = zn[1 + h];
+            const uint64_t valid = b == nblk - 1 ? tmask : ~0ull;
+            // quad Q + 1's products are issued before quad Q's sign tests (two result sets)
+            f32x16 acc[2];
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A1[0], B1, f32x16{}, 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[0], B2, acc[0], 0, 0, 0);
+#pragma unroll
+            for (int Q = 0; Q < 8; ++Q) {
+                if (Q + 1 < 8) {
+                    acc[(Q + 1) & 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A1[Q + 1], B1, f32x16{}, 0, 0, 0);
+                    acc[(Q + 1) & 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[Q + 1], B2, acc[(Q + 1) & 1], 0, 0, 0);
+                }
+                const f32x16& a = acc[Q & 1];
+                // crossed unless every corner is above theta or every corner is below it
+                const uint64_t c0 = valid & ~(__ballot(min8_i<0>(a) > 0) | __ballot(min8_u<0>(a) > 0x80000000u));
+                const uint64_t c1 = valid & ~(__ballot(min8_i<2>(a) > 0) | __ballot(min8_u<2>(a) > 0x80000000u));
+                cnt[Q][0] += __builtin_popcount((uint32_t)c0);
+                cnt[Q][2] += __builtin_popcount((uint32_t)(c0 >> 32));
+                cnt[Q][1] += __builtin_popcount((uint32_t)c1);
+                cnt[Q][3] += __builtin_popcount((uint32_t)(c1 >> 32));
+            }
+            B1 = nB1;
+            B2 = nB2;
+        }
+        if (out) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int Q = 0; Q < 8; ++Q)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) c = lane == 4 * Q + k ? cnt[Q][k] : c;
+            out[lin] = (float)c / (float)ns;
+        }
+    }
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -979,17 +1170,24 @@ hipError_t launch_cross_batch(const Model* const* Ms, const GridP* grids, const 
 namespace {
 
 template <int D, class TM, class R>
-void cells_pair(R src, unsigned grid, int64_t cap, hipStream_t s)
+void cells_pair(R src, unsigned grid, int64_t cap, const void* zrec, hipStream_t s)
 {
     hipLaunchKernelGGL((k_cells_cert<D, TM, R>), dim3(grid), dim3(256), 0, s, src, cap);
-    hipLaunchKernelGGL((k_cells<D, TM, R>), dim3(grid), dim3(256), 0, s, src, cap);
+    if constexpr (D == 3 && std::is_same<TM, float>::value) {
+        const unsigned g = grid_for(cap, kMcWaves * kMcCells);
+        hipLaunchKernelGGL((k_cells_mfma<R>), dim3(g < 4096 ? g : 4096), dim3(kMcWaves * 64), 0, s, src, cap,
+                           (const h8v*)zrec);
+    } else {
+        (void)zrec;
+        hipLaunchKernelGGL((k_cells<D, TM, R>), dim3(grid), dim3(256), 0, s, src, cap);
+    }
 }
 
 template <int D, class R>
-void cells_dispatch(R src, bool f64, unsigned grid, int64_t cap, hipStream_t s)
+void cells_dispatch(R src, bool f64, unsigned grid, int64_t cap, const void* zrec, hipStream_t s)
 {
-    if (f64) cells_pair<D, double>(src, grid, cap, s);
-    else cells_pair<D, float>(src, grid, cap, s);
+    if (f64) cells_pair<D, double>(src, grid, cap, zrec, s);
+    else cells_pair<D, float>(src, grid, cap, zrec, s);
 }
 
 }  // namespace
@@ -1060,8 +1258,9 @@ hipError_t launch_cells(const CellTask& t, int64_t ncells_cap, hipStream_t s)
     hipLaunchKernelGGL(k_zmax, dim3(1), dim3(256), 0, s, t.zb64, t.ns, 1 << t.grid.dim, t.zmax);
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, t.wcount, (int64_t)0, (int64_t)1);
     const unsigned grid = grid_for(ncells_cap, 256);
-    if (t.grid.dim == 3) cells_dispatch<3>(CellsOne<3>{t}, t.prec == LCP_FP64, grid, ncells_cap, s);
-    else cells_dispatch<2>(CellsOne<2>{t}, t.prec == LCP_FP64, grid, ncells_cap, s);
+    const void* zrec = t.prec == LCP_FP64 ? nullptr : zbank_records(t.zb32, t.ns, t.grid.dim);
+    if (t.grid.dim == 3) cells_dispatch<3>(CellsOne<3>{t}, t.prec == LCP_FP64, grid, ncells_cap, zrec, s);
+    else cells_dispatch<2>(CellsOne<2>{t}, t.prec == LCP_FP64, grid, ncells_cap, zrec, s);
     return hipGetLastError();
 }
 
@@ -1086,15 +1285,22 @@ hipError_t launch_cells_batch(const CellTask* tasks, int nb, char* scratch, hipS
     hipLaunchKernelGGL(k_zmax, dim3(1), dim3(256), 0, s, t.zb64, t.ns, 1 << t.grid.dim, t.zmax);
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(64), 0, s, t.wcount, (int64_t)0, (int64_t)1);
     const unsigned grid = grid_for(coff[nb], 256);
-    if (t.grid.dim == 3) cells_dispatch<3>(CellsBatch{Td, cd, nb}, t.prec == LCP_FP64, grid, coff[nb], s);
-    else cells_dispatch<2>(CellsBatch{Td, cd, nb}, t.prec == LCP_FP64, grid, coff[nb], s);
+    const void* zrec = t.prec == LCP_FP64 ? nullptr : zbank_records(t.zb32, t.ns, t.grid.dim);
+    if (t.grid.dim == 3) cells_dispatch<3>(CellsBatch{Td, cd, nb}, t.prec == LCP_FP64, grid, coff[nb], zrec, s);
+    else cells_dispatch<2>(CellsBatch{Td, cd, nb}, t.prec == LCP_FP64, grid, coff[nb], zrec, s);
     return hipGetLastError();
 }
 
-hipError_t launch_zbank32(const double* zb, float* zb32, int64_t n, hipStream_t s)
+hipError_t launch_zbank32(const double* zb, float* zb32, int64_t ns, int dim, hipStream_t s)
 {
     StageScope sc(s, ST_MISC);
+    const int64_t n = ns << dim;
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, zb, zb32, n);
+    if (dim == 3) {
+        const int64_t nspad = (ns + 31) / 32 * 32;
+        hipLaunchKernelGGL(k_zrec, dim3((unsigned)ceil_div(nspad * 8, 256)), dim3(256), 0, s, zb, (int)ns, (int)nspad,
+                           (_Float16*)((char*)zb32 + align256(sizeof(float) * (size_t)n)));
+    }
     return hipGetLastError();
 }
 

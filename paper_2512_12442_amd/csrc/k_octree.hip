@@ -1566,7 +1566,7 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_vvar = take(8 * nv);
     L.o_V = take(vb * (size_t)nv * M.m_pad);
     L.o_cross = take(8 * (size_t)nv * ndir);
-    L.o_zb = take(4 * (size_t)ns * (1 << D));
+    L.o_zb = take(zbank32_bytes(ns, D));
     {
         int64_t cpl = 1;
         for (int d = 0; d < D; ++d) cpl *= S0 >> Lmax;
@@ -1875,7 +1875,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     }
     float* zb32 = (float*)P(L.o_zb);
     if (prec != LCP_FP64) {
-        e = launch_zbank32(zb, zb32, (int64_t)ns << D, s);
+        e = launch_zbank32(zb, zb32, ns, D, s);
         if (e != hipSuccess) return e;
     }
     CellTask ct{};

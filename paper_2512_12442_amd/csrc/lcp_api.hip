@@ -135,7 +135,7 @@ size_t dense_ws(const lcp_model* M, const GridP& g, int prec, int ns)
     b += align256(sizeof(double) * nv);                      // var
     b += align256(vb * (size_t)nv * M->m_pad);               // V
     b += align256(sizeof(double) * (size_t)nv * ndir(g.dim)); // cross
-    b += align256(sizeof(float) * (size_t)ns * (1 << g.dim)); // FP32 z-bank
+    b += zbank32_bytes(ns, g.dim);                           // FP32 z-bank and split records
     b += align256(sizeof(double) * ((size_t)ns * (1 << g.dim) + 1)); // uniforms of the smooth estimator, max |z|
     b += cells_scratch_bytes(g.nc[0] * g.nc[1] * g.nc[2]);   // Monte Carlo work list
     return b;
@@ -525,7 +525,7 @@ DenseWs carve_dense(const lcp_model* M, const GridP& g, int prec, int ns, char* 
     w.cross = (double*)p;
     p += align256(sizeof(double) * (size_t)nv * ndir(g.dim));
     w.zb32 = (float*)p;
-    p += align256(sizeof(float) * (size_t)ns * (1 << g.dim));
+    p += zbank32_bytes(ns, g.dim);
     w.wb = (double*)p;
     p += align256(sizeof(double) * ((size_t)ns * (1 << g.dim) + 1));
     const int64_t ncells = g.nc[0] * g.nc[1] * g.nc[2];
@@ -604,7 +604,7 @@ int lcp_dense(const lcp_model* M, const lcp_grid* grid, double theta, const lcp_
     const DenseWs w = carve_dense(M, g, prec, mc->n_samples, (char*)ws);
     hipError_t e;
     if (prec != LCP_FP64) {
-        e = launch_zbank32(mc->zbank, w.zb32, (int64_t)mc->n_samples << g.dim, s);
+        e = launch_zbank32(mc->zbank, w.zb32, mc->n_samples, g.dim, s);
         if (e != hipSuccess) return dev_fail(e, "z-bank");
     }
     e = launch_posterior(*M, prec, dense_task(g, w), s);
@@ -892,7 +892,7 @@ int dense_batch(const lcp_model_batch* B, const lcp_grid* grids, const double* t
     }
     hipError_t e;
     if (reduced) {
-        e = launch_zbank32(mc->zbank, w[0].zb32, (int64_t)mc->n_samples << gs[0].dim, s);
+        e = launch_zbank32(mc->zbank, w[0].zb32, mc->n_samples, gs[0].dim, s);
         if (e != hipSuccess) return dev_fail(e, "z-bank");
     }
     char* base = (char*)ws;

@@ -250,7 +250,9 @@ size_t cross_batch_scratch(int nb);
 hipError_t launch_cross_batch(const Model* const* Ms, const GridP* grids, const void* const* V, double* const* cross,
                               int nb, int prec, char* scratch, hipStream_t s);
 hipError_t launch_cells_batch(const CellTask* tasks, int nb, char* scratch, hipStream_t s);
-hipError_t launch_zbank32(const double* zb, float* zb32, int64_t n, hipStream_t s);
+// Reduced-precision z-bank region (zbank32_bytes): the binary32 copy of the ns x 2^dim bank,
+// then (3D) the split FP16 sample records of the matrix-core Monte Carlo loop.
+hipError_t launch_zbank32(const double* zb, float* zb32, int64_t ns, int dim, hipStream_t s);
 // Corner moments of listed cells (linear cell index, x fastest): flag their corner vertices,
 // number the flagged vertices (slot, vlist from an exclusive scan of vmask), then gather each
 // cell's 2^D means and 2^D x 2^D covariance from the per-slot posterior and cross terms.
@@ -376,5 +378,17 @@ private:
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of the reduced-precision z-bank region: the binary32 copy, then 48-byte split FP16
+// records of the samples padded to a multiple of 32 (read by the 3D Monte Carlo loop).
+constexpr int kZrecBytes = 48;
+inline size_t zbank32_bytes(int64_t ns, int dim)
+{
+    return align256(sizeof(float) * ((size_t)ns << dim)) + align256(kZrecBytes * (size_t)((ns + 31) / 32 * 32));
+}
+inline const void* zbank_records(const float* zb32, int64_t ns, int dim)
+{
+    return (const char*)zb32 + align256(sizeof(float) * ((size_t)ns << dim));
+}
 
 }  // namespace lcp
