@@ -527,10 +527,12 @@ __global__ void __launch_bounds__(256) k_cells(R src, int64_t ncells_cap)
 // s (mu_q - theta), each as an FP16 pair hi + lo, and column j of the right operand holds
 // z_j as an FP16 pair and a 1:
 //   s (mu_q - theta + C_q . z_j) = [C_hi | C_lo] [z_hi; z_hi] + [C_hi | m_hi m_lo 0..] [z_lo; 1 1 0..]
-// (two 32x32x16 MFMAs, binary32 accumulation).  The dropped C_lo z_lo term and the FP16
-// rounding of the lo halves stay below 2^-21 (|s mu| + |s C| |z|), inside the margin the
-// certificate keeps for binary32 loops.  The crossing test reads only signs, which s > 0
-// leaves unchanged.
+// (two 32x32x16 MFMAs, binary32 accumulation).  The operands are rounded once to binary32;
+// hi is their round-toward-zero FP16 value and lo the nearest FP16 value of the exact
+// binary32 residual, so hi + lo is within 2^-21 of the operand.  With the dropped C_lo z_lo
+// term and the binary32 accumulation of 18 terms, a corner value is within about 2^-19
+// (|s (mu - theta)| + sum |s C| |z|) of exact, inside the margin the certificate keeps for
+// binary32 loops (1e-5).  The crossing test reads only signs, which s > 0 leaves unchanged.
 //
 // Row order: the MFMA leaves row r = 8a + 4h + c of the result in register 4a + c of lane
 // half h, and row r is corner 2a + (c & 1) of cell 2h + (c >> 1) of the quad, so each lane
@@ -630,18 +632,23 @@ __global__ void __launch_bounds__(kMcWaves * 64) k_cells_mfma(R src, int64_t nce
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     h8v hi, lo, mm;
+                    float f[8];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const double x = k <= q ? Cd[q][k] * sc : 0.0;
-                        const _Float16 xh = (_Float16)(float)x;
-                        hi[k] = xh;
-                        lo[k] = (_Float16)(float)(x - (double)xh);
+                    for (int k = 0; k < 8; ++k) f[k] = k <= q ? (float)(Cd[q][k] * sc) : 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 8; k += 2) {
+                        const auto ph = __builtin_amdgcn_cvt_pkrtz(f[k], f[k + 1]);
+                        hi[k] = ph[0];
+                        hi[k + 1] = ph[1];
+                        lo[k] = (_Float16)(f[k] - (float)ph[0]);
+                        lo[k + 1] = (_Float16)(f[k + 1] - (float)ph[1]);
                         mm[k] = (_Float16)0.0f;
+                        mm[k + 1] = (_Float16)0.0f;
                     }
-                    const double m = mu[q] * sc;
-                    const _Float16 mh = (_Float16)(float)m;
-                    mm[0] = mh;
-                    mm[1] = (_Float16)(float)(m - (double)mh);
+                    const float m = (float)(mu[q] * sc);
+                    const auto pm = __builtin_amdgcn_cvt_pkrtz(m, 0.0f);
+                    mm[0] = pm[0];
+                    mm[1] = (_Float16)(m - (float)pm[0]);
                     st[lane][q][0] = hi;
                     st[lane][q][1] = lo;
                     st[lane][q][2] = mm;
@@ -672,12 +679,9 @@ __global__ void __launch_bounds__(kMcWaves * 64) k_cells_mfma(R src, int64_t nce
 #pragma unroll
             for (int k = 0; k < 4; ++k) cnt[Q][k] = 0;
         const h8v* zp = zrec + 3 * r;                         // record of sample 32 b + r
-        h8v B1 = zp[0], B2 = zp[1 + h];
-        for (int b = 0; b < nblk; ++b) {
-            const h8v* zn = zp + (size_t)96 * (b + 1 < nblk ? b + 1 : b);
-            const h8v nB1 = zn[0], nB2 = zn[1 + h];
-            const uint64_t valid = b == nblk - 1 ? tmask : ~0ull;
-            // quad Q + 1's products are issued before quad Q's sign tests (two result sets)
+        // one block of 32 samples for the 8 quads; quad Q + 1's products are issued before
+        // quad Q's sign tests (two result sets)
+        auto block = [&](const h8v& B1, const h8v& B2, uint64_t valid) {
             f32x16 acc[2];
             acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A1[0], B1, f32x16{}, 0, 0, 0);
             acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A2[0], B2, acc[0], 0, 0, 0);
@@ -696,9 +700,30 @@ __global__ void __launch_bounds__(kMcWaves * 64) k_cells_mfma(R src, int64_t nce
                 cnt[Q][1] += __builtin_popcount((uint32_t)c1);
                 cnt[Q][3] += __builtin_popcount((uint32_t)(c1 >> 32));
             }
-            B1 = nB1;
-            B2 = nB2;
+        };
+        // two record sets in turn: a block's records are requested one block ahead
+        auto ld = [&](int b, h8v& R1, h8v& R2) {
+            const size_t o = (size_t)96 * (b < nblk ? b : nblk - 1);
+            R1 = zp[o];
+            R2 = zp[o + 1 + h];
+        };
+        const int nfull = ns >> 5;                            // blocks of 32 live samples
+        h8v X1, X2, Y1, Y2;
+        ld(0, X1, X2);
+        int b = 0;
+        for (; b + 2 <= nfull; b += 2) {
+            ld(b + 1, Y1, Y2);
+            block(X1, X2, ~0ull);
+            ld(b + 2, X1, X2);
+            block(Y1, Y2, ~0ull);
         }
+        if (b < nfull) {                                      // odd count of full blocks
+            ld(b + 1, Y1, Y2);
+            block(X1, X2, ~0ull);
+            X1 = Y1;
+            X2 = Y2;
+        }
+        if (nfull < nblk) block(X1, X2, tmask);               // last, partial block
         if (out) {
             uint32_t c = 0;
 #pragma unroll

@@ -1017,8 +1017,10 @@ hipError_t launch_posterior(const Model& M, int prec, const PostTask& t, hipStre
             if (grad) return launch_t<P64, 16, 4, 16>(M, t, s, M.A64, nullptr);
             return launch_t<P64, 16, 1, 16>(M, t, s, M.A64, nullptr);
         }
-        if (grad) return launch_t<P64, 16, 4>(M, t, s, M.A64, nullptr);
-        return launch_t<P64, 16, 1>(M, t, s, M.A64, nullptr);
+        // larger launches: eight waves per work-group, two work-groups per CU (measured on
+        // the region bound at 128^3: 2.35 -> 2.26 ms against four waves; sixteen gave 2.33)
+        if (grad) return launch_t<P64, 16, 4, 8>(M, t, s, M.A64, nullptr);
+        return launch_t<P64, 16, 1, 8>(M, t, s, M.A64, nullptr);
     }
     if (prec == LCP_FP32) {
         if (grad) return launch_t<P32, 32, 4>(M, t, s, M.A32, nullptr);
