@@ -41,7 +41,7 @@ def leaf_cell_mask(keys, W, edge):
     return mask
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_post_f16x3_128cube_m500_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_post_ps_k_cross_k_cells_mfma_trig128_m500.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_12442_amd", "csrc", "k_posterior.hip")
 
 
@@ -413,7 +413,8 @@ def main():
     peak = {"f16x3": PEAK["fp16_mfma"], "bf16x3": PEAK["fp16_mfma"], "fp32": PEAK["fp32_mfma"],
             "fp64": PEAK["fp64_mfma"]}[args.prec]
     achieved = flops / (dur_ms * 1e-3)
-    roof = {"bound": "mfma", "kernel": f"k_post ({args.prec} posterior GEMM over leaf vertices)",
+    kname = "k_post_ps" if args.prec in ("f16x3", "bf16x3") else "k_post"
+    roof = {"bound": "mfma", "kernel": f"{kname} ({args.prec} posterior GEMM over leaf vertices)",
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic_per_launch(args.prec, args.npts) if args.workload == "trig128" else None,
             "avg_launch_ms": dur_ms, "launches_per_step": per_step_launches,
