@@ -1,6 +1,7 @@
 // Model factorisation on the GPU (binary64): K = k(X, X) + noise I, its Cholesky factor,
 // the explicit inverse L^-1 in the MFMA fragment orders used by the posterior kernel,
 // and a = K^-1 y.  Sec. 3 of the paper with the inducing set equal to the observations.
+#include <algorithm>
 #include <vector>
 
 #include "lcp_internal.h"
@@ -51,11 +52,10 @@ __global__ void k_scaled_obs(KParams kp, const double* __restrict__ Xp, const do
     Xs[i * 4 + 3] = i < m ? a[i] : 0.0;
 }
 
-__global__ void k_build_K(KParams kp, const double* __restrict__ Xp, int m, int mp, double noise,
-                          double* __restrict__ K)
+// Element t of the padded K + noise I (zero outside the m x m block).
+__device__ __forceinline__ void build_K_elem(const KParams& kp, const double* __restrict__ Xp, int m, int mp,
+                                             double noise, double* __restrict__ K, int64_t t)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)mp * mp) return;
     int i = (int)(t / mp), j = (int)(t % mp);
     double v = 0.0;
     if (i < m && j < m) {
@@ -65,72 +65,12 @@ __global__ void k_build_K(KParams kp, const double* __restrict__ Xp, int m, int 
     K[t] = v;
 }
 
-// Left-looking Cholesky of the leading m x m block of K (row-major, leading dim mp), in
-// place: on exit row j of the array holds row j of U = L^T (U[j][i] = L[i][j], i >= j).
-// One work-group; thread i owns column i's running diagonal d_i = K_ii - sum_k U[k][i]^2.
-__device__ __forceinline__ void cholesky_body(double* __restrict__ U, int m, int mp, double piv_min,
-                                              int* __restrict__ info)
+__global__ void k_build_K(KParams kp, const double* __restrict__ Xp, int m, int mp, double noise,
+                          double* __restrict__ K)
 {
-    __shared__ double d[kMaxM];
-    __shared__ double ucol[kMaxM];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < m; i += nt) d[i] = U[(int64_t)i * mp + i];
-    if (tid == 0) *info = 0;
-    for (int j = 0; j < m; ++j) {
-        __syncthreads();
-        double piv = d[j];
-        if (!(piv > piv_min)) {
-            if (tid == 0) *info = j + 1;
-            return;
-        }
-        double ujj = sqrt(piv);
-        for (int k = tid; k < j; k += nt) ucol[k] = U[(int64_t)k * mp + j];
-        __syncthreads();
-        double inv = 1.0 / ujj;
-        for (int i = j + 1 + tid; i < m; i += nt) {
-            double s = U[(int64_t)j * mp + i];
-            for (int k = 0; k < j; ++k) s = fma(-ucol[k], U[(int64_t)k * mp + i], s);
-            double u = s * inv;
-            U[(int64_t)j * mp + i] = u;
-            d[i] = fma(-u, u, d[i]);
-        }
-        if (tid == 0) U[(int64_t)j * mp + j] = ujj;
-    }
-    __syncthreads();
-    // clear the strictly lower part (it still holds K) so U is a clean upper factor
-    for (int64_t t = tid; t < (int64_t)m * m; t += nt) {
-        int i = (int)(t / m), j = (int)(t % m);
-        if (j < i) U[(int64_t)i * mp + j] = 0.0;
-    }
-}
-
-
-// Explicit inverse of L = U^T row by row: Linv[i][c] = -(sum_{k=c}^{i-1} L[i][k] Linv[k][c]) / L[i][i].
-__device__ __forceinline__ void amax_body(const double* __restrict__ Li, int mp, double* __restrict__ amax);
-
-__device__ __forceinline__ void trinv_body(const double* __restrict__ U, double* __restrict__ Li, int m, int mp,
-                                           double* __restrict__ amax)
-{
-    __shared__ double lrow[kMaxM];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int64_t t = tid; t < (int64_t)mp * mp; t += nt) Li[t] = 0.0;
-    __syncthreads();
-    for (int i = 0; i < m; ++i) {
-        for (int k = tid; k <= i; k += nt) lrow[k] = U[(int64_t)k * mp + i];
-        __syncthreads();
-        double inv = 1.0 / lrow[i];
-        for (int c = tid; c <= i; c += nt) {
-            if (c == i) {
-                Li[(int64_t)i * mp + i] = inv;
-            } else {
-                double s = 0.0;
-                for (int k = c; k < i; ++k) s = fma(lrow[k], Li[(int64_t)k * mp + c], s);
-                Li[(int64_t)i * mp + c] = -s * inv;
-            }
-        }
-        __syncthreads();
-    }
-    amax_body(Li, mp, amax);
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    build_K_elem(kp, Xp, m, mp, noise, K, t);
 }
 
 // Largest |Linv| and the power-of-two scale sA that brings it to [2^14, 2^15) (FP16 max is 65504).
@@ -245,8 +185,8 @@ __device__ __forceinline__ void blk_trinv(const double (*lo)[kFB + 1], double (*
 }
 
 // Step k, diagonal block: factor A_kk (upper, in U) in LDS, write U_kk and Linv_kk.
-__global__ void __launch_bounds__(256) k_chol_diag(double* __restrict__ U, int m, int mp, int kb, double piv_min,
-                                                   int* __restrict__ info, double* __restrict__ Lkk_inv)
+__device__ __forceinline__ void chol_diag_body(double* __restrict__ U, int m, int mp, int kb, double piv_min,
+                                               int* __restrict__ info, double* __restrict__ Lkk_inv)
 {
     __shared__ double a[kFB][kFB + 1], lo[kFB][kFB + 1];
     const int k0 = kb * kFB;
@@ -281,12 +221,11 @@ __global__ void __launch_bounds__(256) k_chol_diag(double* __restrict__ U, int m
     for (int t = threadIdx.x; t < kFB * kFB; t += 256) Lkk_inv[t] = a[t / kFB][t % kFB];
 }
 
-// Step k, panel: U_kj = Linv_kk A_kj for every block column j > k.
-__global__ void __launch_bounds__(256) k_chol_panel(double* __restrict__ U, int mp, int kb,
-                                                    const double* __restrict__ Lkk_inv)
+// Step k, panel: U_kj = Linv_kk A_kj for block column jb > k.
+__device__ __forceinline__ void chol_panel_body(double* __restrict__ U, int mp, int kb, int jb,
+                                                const double* __restrict__ Lkk_inv)
 {
     __shared__ double li[kFB][kFB + 1], b[kFB][kFB + 1];
-    const int jb = kb + 1 + blockIdx.x;
     for (int t = threadIdx.x; t < kFB * kFB; t += 256) li[t / kFB][t % kFB] = Lkk_inv[t];
     blk_load(b, U, mp, kb * kFB, jb * kFB);
     __syncthreads();
@@ -299,12 +238,13 @@ __global__ void __launch_bounds__(256) k_chol_panel(double* __restrict__ U, int 
         for (int c = 0; c < 4; ++c) U[(int64_t)(kb * kFB + ty * 4 + r) * mp + jb * kFB + tx * 4 + c] = acc[r][c];
 }
 
-// Step k, trailing update of the upper blocks: A_ij -= U_ki^T U_kj, k < i <= j.
-__global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ U, int mp, int kb, int nblk)
+// Step k, trailing update of the upper blocks: A_ij -= U_ki^T U_kj, k < i <= j; upper block
+// pair number idx of the T (T + 1) / 2, T = nblk - kb - 1.
+__device__ __forceinline__ void chol_update_body(double* __restrict__ U, int mp, int kb, int nblk, int idx)
 {
     __shared__ double a[kFB][kFB + 1], b[kFB][kFB + 1];
     const int T = nblk - kb - 1;
-    int rem = blockIdx.x, ii = 0;
+    int rem = idx, ii = 0;
     while (rem >= T - ii) { rem -= T - ii; ++ii; }
     const int ib = kb + 1 + ii, jb = ib + rem;
     blk_load(a, U, mp, kb * kFB, ib * kFB);
@@ -330,11 +270,11 @@ __global__ void k_clear_lower(double* __restrict__ U, int mp)
     if (t % mp < t / mp) U[t] = 0.0;
 }
 
-// Inverse, diagonal blocks: Linv_ii = L_ii^-1 with L_ii = U_ii^T.
-__global__ void __launch_bounds__(256) k_trinv_diag(const double* __restrict__ U, double* __restrict__ Li, int mp)
+// Inverse, diagonal block ib: Linv_ii = L_ii^-1 with L_ii = U_ii^T.
+__device__ __forceinline__ void trinv_diag_body(const double* __restrict__ U, double* __restrict__ Li, int mp, int ib)
 {
     __shared__ double lo[kFB][kFB + 1], inv[kFB][kFB + 1];
-    const int i0 = blockIdx.x * kFB;
+    const int i0 = ib * kFB;
     for (int t = threadIdx.x; t < kFB * kFB; t += 256) {
         const int r = t / kFB, c = t % kFB;
         lo[c][r] = U[(int64_t)(i0 + r) * mp + i0 + c];
@@ -346,11 +286,11 @@ __global__ void __launch_bounds__(256) k_trinv_diag(const double* __restrict__ U
 }
 
 // Inverse, block diagonal d: Linv_ij = -Linv_ii sum_{k=j}^{i-1} L_ik Linv_kj, i = j + d.
-__global__ void __launch_bounds__(256) k_trinv_off(const double* __restrict__ U, double* __restrict__ Li, int mp,
-                                                   int d)
+__device__ __forceinline__ void trinv_off_body(const double* __restrict__ U, double* __restrict__ Li, int mp, int d,
+                                               int jb)
 {
     __shared__ double a[kFB][kFB + 1], b[kFB][kFB + 1];
-    const int jb = blockIdx.x, ib = jb + d;
+    const int ib = jb + d;
     double acc[4][4] = {};
     for (int kb = jb; kb < ib; ++kb) {
         // a = L_ik = (U_ki)^T: load U_ki and use it transposed
@@ -376,22 +316,96 @@ __global__ void __launch_bounds__(256) k_trinv_off(const double* __restrict__ U,
         for (int c = 0; c < 4; ++c) Li[(int64_t)(ib * kFB + ty * 4 + r) * mp + jb * kFB + tx * 4 + c] = -out[r][c];
 }
 
-// One work-group per model of a batch.
+// One model: a launch per step, one work-group per block.
+__global__ void __launch_bounds__(256) k_chol_diag(double* __restrict__ U, int m, int mp, int kb, double piv_min,
+                                                   int* __restrict__ info, double* __restrict__ Lkk_inv)
+{
+    chol_diag_body(U, m, mp, kb, piv_min, info, Lkk_inv);
+}
+__global__ void __launch_bounds__(256) k_chol_panel(double* __restrict__ U, int mp, int kb,
+                                                    const double* __restrict__ Lkk_inv)
+{
+    chol_panel_body(U, mp, kb, kb + 1 + blockIdx.x, Lkk_inv);
+}
+__global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ U, int mp, int kb, int nblk)
+{
+    chol_update_body(U, mp, kb, nblk, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_trinv_diag(const double* __restrict__ U, double* __restrict__ Li, int mp)
+{
+    trinv_diag_body(U, Li, mp, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_trinv_off(const double* __restrict__ U, double* __restrict__ Li, int mp,
+                                                   int d)
+{
+    trinv_off_body(U, Li, mp, d, blockIdx.x);
+}
+
+// A batch: the same block steps for every model in one launch, blockIdx.y = model.  A
+// model runs the very arithmetic of its single-model factorisation, so its factor is
+// bitwise the one gp_fit_factor computes; work-groups past a model's block count return.
 struct FactorDesc {
+    const double* Xin;    // model inputs (device): m x dim, m
+    const double* yin;
+    double* X;            // packed m_pad x 4
+    double* w;            // packed values
     double* U;
     double* Linv;
     double* a;
-    const double* y;
     double* amax;
     int* info;
+    double* lkk;          // 64 x 64 scratch: Linv of the current diagonal block
+    KParams kp;
+    double noise;
     double piv_min;
-    int m, mp;
+    int m, mp, dim;
 };
 
-__global__ void __launch_bounds__(1024) k_cholesky_batch(const FactorDesc* __restrict__ D)
+__global__ void k_pack_batch(const FactorDesc* __restrict__ D)
 {
-    const FactorDesc& d = D[blockIdx.x];
-    cholesky_body(d.U, d.m, d.mp, d.piv_min, d.info);
+    const FactorDesc& d = D[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.mp) return;
+    for (int c = 0; c < 4; ++c) d.X[i * 4 + c] = (i < d.m && c < d.dim) ? d.Xin[(int64_t)i * d.dim + c] : 0.0;
+    d.w[i] = i < d.m ? d.yin[i] : 0.0;
+}
+
+__global__ void k_build_K_batch(const FactorDesc* __restrict__ D)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.mp * d.mp) return;
+    build_K_elem(d.kp, d.X, d.m, d.mp, d.noise, d.U, t);
+}
+
+__global__ void __launch_bounds__(256) k_chol_diag_batch(const FactorDesc* __restrict__ D, int kb)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    if (kb >= d.mp / kFB) return;
+    chol_diag_body(d.U, d.m, d.mp, kb, d.piv_min, d.info, d.lkk);
+}
+
+__global__ void __launch_bounds__(256) k_chol_panel_batch(const FactorDesc* __restrict__ D, int kb)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    if ((int)blockIdx.x >= d.mp / kFB - kb - 1) return;
+    chol_panel_body(d.U, d.mp, kb, kb + 1 + blockIdx.x, d.lkk);
+}
+
+__global__ void __launch_bounds__(256) k_chol_update_batch(const FactorDesc* __restrict__ D, int kb)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    const int T = d.mp / kFB - kb - 1;
+    if (T <= 0 || (int)blockIdx.x >= T * (T + 1) / 2) return;
+    chol_update_body(d.U, d.mp, kb, d.mp / kFB, blockIdx.x);
+}
+
+__global__ void k_clear_lower_batch(const FactorDesc* __restrict__ D)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d.mp * d.mp) return;
+    if (t % d.mp < t / d.mp) d.U[t] = 0.0;
 }
 
 __global__ void k_gather_info(const FactorDesc* __restrict__ D, int nb, int* __restrict__ out)
@@ -400,13 +414,32 @@ __global__ void k_gather_info(const FactorDesc* __restrict__ D, int nb, int* __r
     if (b < nb) out[b] = *D[b].info;
 }
 
-__global__ void __launch_bounds__(1024) k_trinv_alpha_batch(const FactorDesc* __restrict__ D)
+__global__ void k_zero_linv_batch(const FactorDesc* __restrict__ D)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (int64_t)d.mp * d.mp) d.Linv[t] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_trinv_diag_batch(const FactorDesc* __restrict__ D)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    if ((int)blockIdx.x >= d.mp / kFB) return;
+    trinv_diag_body(d.U, d.Linv, d.mp, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_trinv_off_batch(const FactorDesc* __restrict__ D, int dd)
+{
+    const FactorDesc& d = D[blockIdx.y];
+    if ((int)blockIdx.x + dd >= d.mp / kFB) return;
+    trinv_off_body(d.U, d.Linv, d.mp, dd, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_amax_alpha_batch(const FactorDesc* __restrict__ D)
 {
     const FactorDesc& d = D[blockIdx.x];
-    if (*d.info != 0) return;
-    trinv_body(d.U, d.Linv, d.m, d.mp, d.amax);
-    __syncthreads();
-    alpha_body(d.Linv, d.y, d.a, d.m, d.mp);
+    amax_body(d.Linv, d.mp, d.amax);
+    alpha_body(d.Linv, d.w, d.a, d.m, d.mp);
 }
 
 // Fragment orders of Linv.
@@ -485,7 +518,7 @@ struct Transposed {
     int ld;
     __device__ double operator()(int k, int j) const { return p[(int64_t)j * ld + k]; }
 };
-// F[i][k] = G[m-1-k][m-1-i] where the array holds G^T (row r = row r of G^T) after cholesky_body.
+// F[i][k] = G[m-1-k][m-1-i] where the array holds G^T (row r = row r of G^T) after the blocked Cholesky.
 struct ReversedFactor {
     const double* p;
     int ld, m;
@@ -683,52 +716,76 @@ hipError_t launch_sparse_finish(Model& M, hipStream_t s)
     return hipGetLastError();
 }
 
+// Descriptors, one 64 x 64 diagonal-block inverse per model, then the statuses (last).
 size_t factor_batch_scratch(int nb)
 {
-    return align256(sizeof(FactorDesc) * (size_t)nb) + align256(sizeof(int) * (size_t)nb);
+    return align256(sizeof(FactorDesc) * (size_t)nb) + align256(sizeof(double) * kFB * kFB * (size_t)nb) +
+           align256(sizeof(int) * (size_t)nb);
 }
 
-// Batched factorisation, part 1: pack and build K per model, then every model's Cholesky in
-// one launch (a work-group each); the statuses land in info_dev[b] (0 = positive definite).
+// Batched factorisation, part 1: pack and build K for every model, then the blocked
+// Cholesky of all models one block step at a time (three launches per step over the
+// largest model's block count); the statuses land in info_dev[b] (0 = positive definite).
 // X[b], y[b] are the models' device inputs; scratch holds factor_batch_scratch(nb) bytes.
 hipError_t launch_factor_batch(Model* const* Ms, int nb, const double* const* X, const double* const* y, char* scratch,
                                int* info_dev, hipStream_t s)
 {
     StageScope sc(s, ST_FACTOR);
     std::vector<FactorDesc> D(nb);
+    double* lkk = (double*)(scratch + align256(sizeof(FactorDesc) * (size_t)nb));
+    int mpmax = 0;
     for (int b = 0; b < nb; ++b) {
         Model& M = *Ms[b];
         carve(M, (char*)M.X);
-        const int mp = M.m_pad;
-        double* w = ybuf(M);
-        hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(mp, 256)), dim3(256), 0, s, X[b], y[b], M.m, mp, M.dim,
-                           M.X, w);
-        const int64_t n2 = (int64_t)mp * mp;
-        hipLaunchKernelGGL(k_build_K, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.kp, M.X, M.m, mp,
-                           M.k.noise_var, M.U);
-        D[b] = FactorDesc{M.U, M.Linv, M.a, w, M.amax, M.info,
-                          (double)M.m * 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var), M.m, mp};
+        D[b] = FactorDesc{X[b], y[b], M.X, ybuf(M), M.U, M.Linv, M.a, M.amax, M.info, lkk + (size_t)b * kFB * kFB,
+                          M.kp, M.k.noise_var, (double)M.m * 2.220446049250313e-16 * (M.k.signal_var + M.k.noise_var),
+                          M.m, M.m_pad, M.dim};
+        mpmax = std::max(mpmax, M.m_pad);
     }
     FactorDesc* Dd = (FactorDesc*)scratch;
     hipError_t e = hipMemcpyAsync(Dd, D.data(), sizeof(FactorDesc) * nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);       // pageable source
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cholesky_batch, dim3(nb), dim3(1024), 0, s, Dd);
+    const int64_t n2 = (int64_t)mpmax * mpmax;
+    const unsigned ub = (unsigned)nb;
+    hipLaunchKernelGGL(k_pack_batch, dim3((unsigned)ceil_div(mpmax, 256), ub), dim3(256), 0, s, Dd);
+    hipLaunchKernelGGL(k_build_K_batch, dim3((unsigned)ceil_div(n2, 256), ub), dim3(256), 0, s, Dd);
+    const int nblk = mpmax / kFB;
+    for (int kb = 0; kb < nblk; ++kb) {
+        hipLaunchKernelGGL(k_chol_diag_batch, dim3(1, ub), dim3(256), 0, s, Dd, kb);
+        const int T = nblk - kb - 1;
+        if (T == 0) break;
+        hipLaunchKernelGGL(k_chol_panel_batch, dim3((unsigned)T, ub), dim3(256), 0, s, Dd, kb);
+        hipLaunchKernelGGL(k_chol_update_batch, dim3((unsigned)(T * (T + 1) / 2), ub), dim3(256), 0, s, Dd, kb);
+    }
+    hipLaunchKernelGGL(k_clear_lower_batch, dim3((unsigned)ceil_div(n2, 256), ub), dim3(256), 0, s, Dd);
     hipLaunchKernelGGL(k_gather_info, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, s, Dd, nb, info_dev);
     return hipGetLastError();
 }
 
-// Part 2 (statuses read): inverse and a for every model in one launch, then the fragment
-// orders per model.  The observation posteriors are not computed (dense use only).
+// Part 2 (statuses read): the blocked inverse and a of every model, a block diagonal per
+// launch, then the scaled observations and the fragment orders per model.  The observation
+// posteriors are not computed (dense use only).
 hipError_t launch_factor_batch_finish(Model* const* Ms, int nb, char* scratch, hipStream_t s)
 {
     StageScope sc(s, ST_FACTOR);
-    hipLaunchKernelGGL(k_trinv_alpha_batch, dim3(nb), dim3(1024), 0, s, (const FactorDesc*)scratch);
+    const FactorDesc* Dd = (const FactorDesc*)scratch;
+    int mpmax = 0;
+    for (int b = 0; b < nb; ++b) mpmax = std::max(mpmax, Ms[b]->m_pad);
+    const int64_t n2 = (int64_t)mpmax * mpmax;
+    const unsigned ub = (unsigned)nb;
+    const int nblk = mpmax / kFB;
+    hipLaunchKernelGGL(k_zero_linv_batch, dim3((unsigned)ceil_div(n2, 256), ub), dim3(256), 0, s, Dd);
+    hipLaunchKernelGGL(k_trinv_diag_batch, dim3((unsigned)nblk, ub), dim3(256), 0, s, Dd);
+    for (int d = 1; d < nblk; ++d)
+        hipLaunchKernelGGL(k_trinv_off_batch, dim3((unsigned)(nblk - d), ub), dim3(256), 0, s, Dd, d);
+    hipLaunchKernelGGL(k_amax_alpha_batch, dim3(ub), dim3(1024), 0, s, Dd);
     for (int b = 0; b < nb; ++b) {
         Model& M = *Ms[b];
-        const int64_t n2 = (int64_t)M.m_pad * M.m_pad;
+        const int64_t m2 = (int64_t)M.m_pad * M.m_pad;
         hipLaunchKernelGGL(k_scaled_obs, dim3((unsigned)ceil_div(M.m_pad, 256)), dim3(256), 0, s, M.kp, M.X, M.a, M.m,
                            M.m_pad, M.Xs);
-        hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, M.m_pad, M.A64, M.A32,
+        hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(m2, 256)), dim3(256), 0, s, M.Linv, M.m_pad, M.A64, M.A32,
                            M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
     }
     return hipGetLastError();
