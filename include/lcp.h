@@ -189,8 +189,11 @@ void gp_model_free(lcp_model* model);
 
 /* Size queries of the workspace of each operation (host results); the workspace must be
  * 256-byte aligned.  n_samples is the Monte Carlo sample count the call will use.  With
- * LCP_BOUND_LOCAL the adaptive workspace also holds 1024 binary64 slots of
- * m_pad^2 + 128 m_pad doubles each (m_pad = m rounded up to 128; 2.7 GB at m = 500). */
+ * LCP_BOUND_LOCAL the adaptive workspace also holds one binary64 slot of
+ * m_pad^2 + 128 m_pad doubles (m_pad = m rounded up to 128) per work-group of the
+ * local-model kernel resident on the current device: its occupancy for the model's LDS use
+ * times the CU count, at most 1024 (4 per CU at m = 500 on a 256-CU device: 2.7 GB; 2 per
+ * CU at m = 1024).  The query and the call must run on the same device. */
 int lcp_posterior_workspace(const lcp_model* model, int64_t n, int prec, size_t* bytes);
 int lcp_dense_workspace(const lcp_model* model, const lcp_grid* grid, int prec, int n_samples, size_t* bytes);
 int lcp_adaptive_workspace(const lcp_model* model, const lcp_grid* grid, const lcp_adapt* adapt, int prec,

@@ -945,7 +945,8 @@ inline unsigned gsz(int64_t n, int per)
 // A factorisation that fails (pivot at or below m' eps (s2 + noise)) gives no bound: the
 // node is refined.
 constexpr int kLocB = 32;        // panel width; also the most right-hand sides per solve
-constexpr int kLocSlots = 1024;  // most work-groups of k_local_bound (four per CU), one slot each
+constexpr int kLocSlots = 1024;  // most work-groups of k_local_bound (four per CU), one slot each;
+                                 // the workspace holds as many slots as are resident together
 
 struct LocalBufs {
     KParams kp;
@@ -958,7 +959,7 @@ struct LocalBufs {
     double rad[3];       // beta ell_d
     const double* AM;    // sparse model: A_M (ld x ld); null for an exact GP
     int32_t* next;       // work counter: nodes handed out beyond the first gridDim.x (zeroed per launch)
-    double* slots;       // kLocSlots x (ld ld + 4 ld kLocB) doubles: L, V, inverted diagonal blocks, W, T
+    double* slots;       // one per resident work-group: ld ld + 4 ld kLocB doubles (L, V, inverted diagonal blocks, W, T)
 };
 
 __host__ __device__ __forceinline__ size_t local_slot_doubles(int ld) { return (size_t)ld * ld + 4 * (size_t)ld * kLocB; }
@@ -1486,6 +1487,7 @@ struct AdaptLayout {
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
+    int nloc;                            // local-model bound only: slots (resident work-groups)
     int64_t capF, nv;
 };
 
@@ -1493,6 +1495,21 @@ struct AdaptLayout {
 static int level_shift(int kd, int D, int level, int d)
 {
     return kd ? level / D + (d >= D - level % D ? 1 : 0) : level;
+}
+
+// Work-groups of k_local_bound that are resident together on this device (its persistent
+// grid, one workspace slot each): the occupancy for the model's LDS use times the CU count,
+// at most kLocSlots.
+static hipError_t local_slot_count(const Model& M, int D, int* slots)
+{
+    const size_t shm = (size_t)M.m_pad * (D + 1) * sizeof(double) + (size_t)M.m_pad * sizeof(int);
+    int per_cu = 0, dev = 0, ncu = 0;
+    hipError_t e = D == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_local_bound<3>, 256, shm)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_local_bound<2>, 256, shm);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    *slots = e == hipSuccess ? std::max(1, std::min(kLocSlots, per_cu * ncu)) : kLocSlots;
+    return e;
 }
 
 static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int Lmax, int prec, int ns, int bound_kind,
@@ -1579,8 +1596,11 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         L.o_cert = take(32 * (size_t)capF);
     }
     if (bound_kind == LCP_BOUND_LOCAL) {
+        int slots = kLocSlots;
+        (void)local_slot_count(M, D, &slots);        // kLocSlots if the query fails
+        L.nloc = slots;
         L.o_lnext = take(256);
-        L.o_loc = take(8 * local_slot_doubles(M.m_pad) * kLocSlots);
+        L.o_loc = take(8 * local_slot_doubles(M.m_pad) * (size_t)slots);
     }
     L.total = o;
     L.capF = capF;
@@ -1732,15 +1752,9 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             lb.next = (int32_t*)P(L.o_lnext);
             if ((e = launch_fill_i32(lb.next, 0, 1, s)) != hipSuccess) return e;
             StageScope sc(s, ST_BOUND);
-            // a persistent grid of the work-groups that are resident together (at most kLocSlots)
+            // a persistent grid of the work-groups that are resident together: one per slot
             const size_t shm = (size_t)M.m_pad * (D + 1) * sizeof(double) + (size_t)M.m_pad * sizeof(int);
-            int per_cu = 0, dev = 0, ncu = 0;
-            if (D == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_local_bound<3>, 256, shm);
-            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_local_bound<2>, 256, shm);
-            if (e != hipSuccess) return e;
-            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-            if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-            const int grid = std::max(1, std::min(kLocSlots, per_cu * ncu));
+            const int grid = L.nloc;
             if (D == 3)
                 hipLaunchKernelGGL(k_local_bound<3>, dim3(grid), dim3(256), shm, s, o, l, kin, path, B, lb, sub);
             else
