@@ -46,7 +46,9 @@ __device__ __forceinline__ void key_coords_oct(int D, uint64_t key, int& level, 
     uint64_t mc = key & ((1ull << 58) - 1);
     c[0] = c[1] = c[2] = 0;
     for (int b = 0; b < level; ++b)
-        for (int d = 0; d < D; ++d) c[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)                        // fixed bounds: c stays in registers
+            if (d < D) c[d] |= (int64_t)((mc >> (b * D + d)) & 1) << b;
 }
 
 __device__ __forceinline__ void key_coords(const Oct& o, uint64_t key, int& level, int64_t* c)
@@ -84,7 +86,9 @@ __device__ __forceinline__ uint64_t make_key(const Oct& o, int level, const int6
         }
     } else {
         for (int b = 0; b < level; ++b)
-            for (int d = 0; d < D; ++d) k |= (uint64_t)((c[d] >> b) & 1) << (b * D + d);
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (d < D) k |= (uint64_t)((c[d] >> b) & 1) << (b * D + d);
     }
     return ((uint64_t)level << 58) | k;
 }
@@ -124,6 +128,24 @@ __device__ __forceinline__ int wave_isum(int v)
     return v;
 }
 
+// Slots in a list shared by the whole launch: every thread of the block passes its item
+// count n and gets the first of n consecutive slots of *counter; the block takes its range
+// with one atomic.  The order of the blocks' ranges is not fixed, so a list built this way
+// only routes per-item work whose results do not depend on the position.  Every thread of
+// the block must call it (it holds barriers).
+__device__ int block_claim(int n, int64_t* counter)
+{
+    __shared__ int sh[65];
+    int tot;
+    const int ex = block_excl_scan(n, sh, &tot);
+    __shared__ int base;
+    if (threadIdx.x == 0) base = tot > 0 ? (int)atomicAdd((unsigned long long*)counter, (unsigned long long)tot) : 0;
+    __syncthreads();
+    const int r = base + ex;
+    __syncthreads();
+    return r;
+}
+
 // Standardised margin of one side: side (theta - mu) / sigma with the sigma = 0 limits.
 __device__ __forceinline__ double margin(double side, double theta, double mu, double var)
 {
@@ -157,19 +179,59 @@ __global__ void k_root(uint64_t* keys, int64_t* cnt)
 }
 
 // Preliminary decision of Alg. 1 for every frontier node (one wave per node).
+// Work lists and values of the region bound (Sec. 5.1), per level.
+struct BoundBufs {
+    int32_t* bnode;     // stage-1 node -> frontier index
+    double* side;
+    double* gmin;
+    double* cpts;       // stage-1 centres, 3 per node
+    double* cmean;
+    double* cvar;
+    int32_t* lnode;     // stage-2 node -> stage-1 node
+    int32_t* ngrid;     // node lattice of this level -> stage-2 node (-1: not in stage 2)
+    int32_t* lmask;     // per stage-2 node: lattice points it evaluates (owns), bit i = point i
+    int32_t* loff;      // per stage-2 node: first slot of its owned points
+    double* lat_pts;    // unique lattice points, 3 doubles each
+    double* lat_mean;
+    double* lat_var;
+    int32_t* dnode;     // stage-3 node -> stage-1 node
+    int32_t* done;
+    double* gp_mean;    // posterior (and gradient) at the stage-3 points
+    double* gp_var;
+    double* gp_dmean;
+    double* gp_dvar;
+    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes
+    double* box;        // certified bound: node box lo[D], hi[D] per stage-1 node (null: search)
+    double* cert;       //   mu(c), mu_lo, mu_hi, var_hi per stage-1 node
+};
+
 // path: 0 subdivide (both sides above alpha), 1 bound below, 2 bound above,
 //       3 finest level emitted without a test, 4 bound with side from the centre mean.
+// With direct set (the search bound), the search's stage-1 list is the frontier itself:
+// every node's centre is written, the nodes that need no bound are skipped at the stage-1
+// decision, the later stage lists start empty and the level's node lattice is cleared.
 __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t* __restrict__ keys,
                                                 const int64_t* __restrict__ nf_dev, int64_t cap,
                                                 const double* __restrict__ X, int m, const double* __restrict__ qlo,
                                                 const double* __restrict__ qhi, int32_t* __restrict__ path,
-                                                int32_t* __restrict__ need, int32_t* __restrict__ sub)
+                                                int32_t* __restrict__ need, int32_t* __restrict__ sub, BoundBufs B,
+                                                int direct)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     int64_t nf = *nf_dev;
     if (nf > cap) nf = cap;
+    if (direct) {
+        const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (gt == 0) {
+            B.cnt[0] = nf;
+            B.cnt[1] = 0;
+            B.cnt[2] = 0;
+            B.cnt[3] = 0;
+        }
+        for (int64_t i = gt; i < cap; i += (int64_t)gridDim.x * blockDim.x) B.ngrid[i] = -1;
+    }
     for (int64_t f = wid; f < nf; f += nw) {
         int lv;
         int64_t c[3], clo[3], chi[3], dp;
@@ -205,6 +267,10 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
             path[f] = pth;
             need[f] = (pth == 1 || pth == 2 || pth == 4) ? 1 : 0;
             sub[f] = (pth == 0 || pth == 3) ? 1 : 0;
+            if (direct) {
+                B.bnode[f] = (int32_t)f;
+                for (int d = 0; d < 3; ++d) B.cpts[f * 3 + d] = d < o.D ? 0.5 * (blo[d] + bhi[d]) : 0.0;
+            }
         }
     }
 }
@@ -215,35 +281,9 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
 //   stage 1: the box centre (also the side for nodes without observations);
 //   stage 2: the {lo, mid, hi}^D lattice for nodes stage 1 left open;
 //   stage 3: projected-gradient steps for nodes the lattice left open.
-struct BoundBufs {
-    int32_t* bnode;     // stage-1 node -> frontier index
-    double* side;
-    double* gmin;
-    double* cpts;       // stage-1 centres, 3 per node
-    double* cmean;
-    double* cvar;
-    int32_t* flag;      // per stage-1 node: needs the next stage
-    int32_t* fidx;      // prefix sum of flag
-    int32_t* lnode;     // stage-2 node -> stage-1 node
-    int32_t* ngrid;     // node lattice of this level -> stage-2 node (-1: not in stage 2)
-    int32_t* lmask;     // per stage-2 node: lattice points it evaluates (owns), bit i = point i
-    int32_t* lcnt;      // popcount of lmask
-    int32_t* loff;      // prefix sum of lcnt: first slot of the node's owned points
-    double* lat_pts;    // unique lattice points, 3 doubles each
-    double* lat_mean;
-    double* lat_var;
-    int32_t* dnode;     // stage-3 node -> stage-1 node
-    double* x;          // stage-3 search point, 3 per node
-    int32_t* done;
-    double* gp_mean;    // posterior (and gradient) at the stage-3 points
-    double* gp_var;
-    double* gp_dmean;
-    double* gp_dvar;
-    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes
-    double* box;        // certified bound: node box lo[D], hi[D] per stage-1 node (null: search)
-    double* cert;       //   mu(c), mu_lo, mu_hi, var_hi per stage-1 node
-};
-
+// The search's stage-1 list is the frontier; each stage's decision kernel appends the nodes
+// it leaves open to the next stage's list (block_claim), so the lists are built without
+// scans.  Every value a stage computes depends on its node alone, never on a list position.
 __device__ __forceinline__ double upper_bound(double gmin, int64_t dp)
 {
     double t;
@@ -303,26 +343,47 @@ __global__ void k_cert_decide(Oct o, int level, const uint64_t* __restrict__ key
     }
 }
 
-// Stage 1: side choice and the centre's bound.
-__global__ void k_bound_centre(Oct o, int level, const uint64_t* __restrict__ keys, const int32_t* __restrict__ path,
-                               BoundBufs B, int32_t* __restrict__ sub)
+// Linear index of a node in the node lattice of its level.
+__device__ __forceinline__ int64_t node_lin(const Oct& o, int level, const int64_t* c)
+{
+    return c[0] + o.nodes[level * 3 + 0] * (c[1] + o.nodes[level * 3 + 1] * c[2]);
+}
+
+// Stage 1: side choice and the centre's bound, for the stage-1 nodes that need a bound.
+// The nodes it leaves open join stage 2: a slot in its list and their place in the node
+// lattice of this level.
+__global__ void __launch_bounds__(256) k_bound_centre(Oct o, int level, const uint64_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ path,
+                                                      const int32_t* __restrict__ need, BoundBufs B,
+                                                      int32_t* __restrict__ sub)
 {
     const int64_t nb = B.cnt[0];
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t f = B.bnode[b];
-        const int p = path[f];
-        const double side = p == 1 ? 1.0 : (p == 2 ? -1.0 : (B.cmean[b] < o.theta ? 1.0 : -1.0));
-        const double g = margin(side, o.theta, B.cmean[b], B.cvar[b]);
-        int lv;
-        int64_t c[3], clo[3], chi[3], dp;
-        double blo[3], bhi[3];
-        key_coords(o, keys[f], lv, c);
-        node_box(o, level, c, clo, chi, blo, bhi, &dp);
-        B.side[b] = side;
-        B.gmin[b] = g;
-        const bool open = !(upper_bound(g, dp) > o.alpha);
-        if (!open) sub[f] = 1;
-        B.flag[b] = open ? 1 : 0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nb; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = base + threadIdx.x;
+        bool open = false;
+        int64_t c[3] = {0, 0, 0};
+        if (b < nb) {
+            const int32_t f = B.bnode[b];
+            if (need[f]) {
+                const int p = path[f];
+                const double side = p == 1 ? 1.0 : (p == 2 ? -1.0 : (B.cmean[b] < o.theta ? 1.0 : -1.0));
+                const double g = margin(side, o.theta, B.cmean[b], B.cvar[b]);
+                int lv;
+                int64_t clo[3], chi[3], dp;
+                double blo[3], bhi[3];
+                key_coords(o, keys[f], lv, c);
+                node_box(o, level, c, clo, chi, blo, bhi, &dp);
+                B.side[b] = side;
+                B.gmin[b] = g;
+                open = !(upper_bound(g, dp) > o.alpha);
+                if (!open) sub[f] = 1;
+            }
+        }
+        const int l = block_claim(open ? 1 : 0, B.cnt + 1);          // every thread of the block
+        if (open) {
+            B.lnode[l] = (int32_t)b;
+            B.ngrid[node_lin(o, level, c)] = l;
+        }
     }
 }
 
@@ -332,10 +393,6 @@ __global__ void k_bound_centre(Oct o, int level, const uint64_t* __restrict__ ke
 // coordinates for it (the shared face has the same vertex, the mid of a shared edge the
 // same two vertices).  It is evaluated once, by the open node with the lowest linear index
 // in the node lattice, and every node reads it from there.
-__device__ __forceinline__ int64_t node_lin(const Oct& o, int level, const int64_t* c)
-{
-    return c[0] + o.nodes[level * 3 + 0] * (c[1] + o.nodes[level * 3 + 1] * c[2]);
-}
 
 // Owner of point i (digits base 3, x fastest) of the node at c: its node lattice coords
 // and the point's index in the owner's lattice.  The node itself is always a candidate.
@@ -374,49 +431,6 @@ __device__ __forceinline__ void lattice_owner(const Oct& o, int level, const int
     *oi = bdig[0] + 3 * bdig[1] + (o.D == 3 ? 9 * bdig[2] : 0);
 }
 
-// Stage-2 nodes into the node lattice of this level.
-__global__ void k_lattice_grid(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
-{
-    const int64_t nb = B.cnt[0];
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        if (!B.flag[b]) continue;
-        const int32_t l = B.fidx[b];
-        B.lnode[l] = (int32_t)b;
-        int lv;
-        int64_t c[3];
-        key_coords(o, keys[B.bnode[b]], lv, c);
-        B.ngrid[node_lin(o, level, c)] = l;
-    }
-}
-
-// Which lattice points each stage-2 node owns: 32 lanes per node, lane i = point i.
-__global__ void k_lattice_own(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
-{
-    const int64_t nl = B.cnt[1];
-    const int npt = o.D == 3 ? 27 : 9;
-    const int sub_lane = threadIdx.x & 31;
-    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 32);
-    // every lane of a wave runs the same number of iterations (ballot below)
-    for (int64_t base = (int64_t)blockIdx.x * (blockDim.x / 32) + (threadIdx.x >> 6) * 2; base < nl; base += stride) {
-        const int64_t l = base + ((threadIdx.x >> 5) & 1);
-        bool own = false;
-        if (l < nl && sub_lane < npt) {
-            int lv;
-            int64_t c[3], oc[3];
-            key_coords(o, keys[B.bnode[B.lnode[l]]], lv, c);
-            int oi;
-            lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
-            own = node_lin(o, level, oc) == node_lin(o, level, c);
-        }
-        const uint64_t bal = __ballot(own);
-        const int32_t mask = (int32_t)((bal >> (threadIdx.x & 32)) & 0xffffffffu);
-        if (l < nl && sub_lane == 0) {
-            B.lmask[l] = mask;
-            B.lcnt[l] = __builtin_popcount(mask);
-        }
-    }
-}
-
 __device__ __forceinline__ void lattice_point(const Oct& o, const double* blo, const double* bhi, int i, double* x)
 {
     int r = i;
@@ -430,40 +444,57 @@ __device__ __forceinline__ void lattice_point(const Oct& o, const double* blo, c
     }
 }
 
-// Stage 2 set-up: the owned lattice points, compacted.
-__global__ void k_lattice_setup(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
+// Which lattice points each stage-2 node owns (32 lanes per node, lane i = point i), a
+// range of slots for them in the list of unique lattice points, and their coordinates there.
+__global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
 {
     const int64_t nl = B.cnt[1];
     const int npt = o.D == 3 ? 27 : 9;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x) {
-        int lv;
-        int64_t c[3], clo[3], chi[3], dp;
+    const int sub_lane = threadIdx.x & 31;
+    const int per = blockDim.x / 32;                                   // nodes per block and pass
+    for (int64_t base = (int64_t)blockIdx.x * per; base < nl; base += (int64_t)gridDim.x * per) {
+        const int64_t l = base + (threadIdx.x >> 5);
+        bool own = false;
         double blo[3], bhi[3];
-        key_coords(o, keys[B.bnode[B.lnode[l]]], lv, c);
-        node_box(o, level, c, clo, chi, blo, bhi, &dp);
-        const int32_t mask = B.lmask[l];
-        int64_t slot = B.loff[l];
-        for (int i = 0; i < npt; ++i) {
-            if (!((mask >> i) & 1)) continue;
+        if (l < nl && sub_lane < npt) {
+            int lv;
+            int64_t c[3], oc[3], clo[3], chi[3], dp;
+            key_coords(o, keys[B.bnode[B.lnode[l]]], lv, c);
+            node_box(o, level, c, clo, chi, blo, bhi, &dp);
+            int oi;
+            lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
+            own = node_lin(o, level, oc) == node_lin(o, level, c);
+        }
+        const uint64_t bal = __ballot(own);
+        const uint32_t mask = (uint32_t)(bal >> (threadIdx.x & 32));
+        const int first = block_claim((l < nl && sub_lane == 0) ? __builtin_popcount(mask) : 0, B.cnt + 2);
+        const int slot0 = __shfl(first, threadIdx.x & 32, 64);            // the node's first slot
+        if (own) {
             double x[3];
-            lattice_point(o, blo, bhi, i, x);
+            lattice_point(o, blo, bhi, sub_lane, x);
+            const int64_t slot = slot0 + __builtin_popcount(mask & ((1u << sub_lane) - 1));
             for (int d = 0; d < 3; ++d) B.lat_pts[slot * 3 + d] = x[d];
-            ++slot;
+        }
+        if (l < nl && sub_lane == 0) {
+            B.lmask[l] = (int32_t)mask;
+            B.loff[l] = slot0;
         }
     }
 }
 
 // Stage 2: lattice minimum (lowest index wins ties), start point, bound; nodes left open
-// go to the descent (or are skipped when the search has no steps).  32 lanes per node,
-// lane i reads point i from its owner's slot.
-__global__ void k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B, int32_t* __restrict__ sub)
+// join the descent -- a slot in the stage-3 list, their start point in gx -- or are skipped
+// when the search has no steps.  32 lanes per node, lane i reads point i from its owner's
+// slot.
+__global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
+                                                  int32_t* __restrict__ sub, double* __restrict__ gx)
 {
     const int64_t nl = B.cnt[1];
     const int npt = o.D == 3 ? 27 : 9;
     const int sub_lane = threadIdx.x & 31;
-    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 32);
-    for (int64_t base = (int64_t)blockIdx.x * (blockDim.x / 32) + (threadIdx.x >> 6) * 2; base < nl; base += stride) {
-        const int64_t l = base + ((threadIdx.x >> 5) & 1);
+    const int per = blockDim.x / 32;                                   // nodes per block and pass
+    for (int64_t base = (int64_t)blockIdx.x * per; base < nl; base += (int64_t)gridDim.x * per) {
+        const int64_t l = base + (threadIdx.x >> 5);
         const bool live = l < nl;
         int32_t b = 0, f = 0;
         int64_t c[3] = {0, 0, 0};
@@ -493,6 +524,8 @@ __global__ void k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, B
                 ib = oib;
             }
         }
+        bool enter = false;
+        double x[3] = {0.0, 0.0, 0.0};
         if (live && sub_lane == 0) {
             int64_t clo[3], chi[3], dp;
             double blo[3], bhi[3];
@@ -500,32 +533,15 @@ __global__ void k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, B
             B.gmin[b] = best;
             const bool open = !(upper_bound(best, dp) > o.alpha);
             if (!open) sub[f] = 1;
-            B.flag[b] = (open && o.steps > 0) ? 2 : 0;       // 2: enters the descent
-            double x[3];
+            enter = open && o.steps > 0;
             lattice_point(o, blo, bhi, best == __builtin_inf() ? 0 : ib, x);
-            for (int d = 0; d < 3; ++d) B.x[(int64_t)b * 3 + d] = x[d];
         }
-    }
-}
-
-// Clear the flags of nodes stage 2 did not see (resolved at stage 1).
-__global__ void k_flag_stage3(BoundBufs B)
-{
-    const int64_t nb = B.cnt[0];
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x)
-        B.flag[b] = B.flag[b] == 2 ? 1 : 0;
-}
-
-// Stage 3 set-up: compact the open nodes; their points move to the stage-3 arrays.
-__global__ void k_descent_setup(BoundBufs B, double* __restrict__ gx)
-{
-    const int64_t nb = B.cnt[0];
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
-        if (!B.flag[b]) continue;
-        const int64_t d = B.fidx[b];
-        B.dnode[d] = (int32_t)b;
-        B.done[d] = 0;
-        for (int k = 0; k < 3; ++k) gx[d * 3 + k] = B.x[(int64_t)b * 3 + k];
+        const int d = block_claim(enter ? 1 : 0, B.cnt + 3);          // every thread of the block
+        if (enter) {
+            B.dnode[d] = b;
+            B.done[d] = 0;
+            for (int k = 0; k < 3; ++k) gx[(int64_t)d * 3 + k] = x[k];
+        }
     }
 }
 
@@ -596,37 +612,39 @@ __global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ key
     }
 }
 
-// Number of keys each node emits: its in-domain children, or itself as a leaf.
+// Number of keys a node emits: its in-domain children, or itself as a leaf (0 unless sb).
+__device__ __forceinline__ int emit_count(const Oct& o, int level, uint64_t key, int sb)
+{
+    if (!sb) return 0;
+    if (level == o.Ldepth) return 1;
+    int lv;
+    int64_t c[3];
+    key_coords(o, key, lv, c);
+    if (o.kd) {
+        const int a = kd_axis(o.D, level);
+        const int64_t hs = o.S0 >> node_shift(o, level + 1, a);
+        return 1 + ((2 * pick3(c, a) + 1) * hs < pick3(o.g.nc, a) ? 1 : 0);
+    }
+    const int64_t hs = (o.S0 >> level) >> 1;
+    int n = 0;
+    for (int i = 0; i < (1 << o.D); ++i) {
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)                    // fixed bounds: c stays in registers
+            if (d < o.D) ok = ok && (2 * c[d] + ((i >> d) & 1)) * hs < o.g.nc[d];
+        n += ok ? 1 : 0;
+    }
+    return n;
+}
+
+// Emit counts of the frontier.
 __global__ void k_emit_count(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
                              int64_t cap, const int32_t* __restrict__ sub, int32_t* __restrict__ cnt)
 {
     int64_t nf = *nf_dev;
     if (nf > cap) nf = cap;
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
-        int n = 0;
-        if (sub[f]) {
-            if (level == o.Ldepth) {
-                n = 1;
-            } else {
-                int lv;
-                int64_t c[3];
-                key_coords(o, keys[f], lv, c);
-                if (o.kd) {
-                    const int a = kd_axis(o.D, level);
-                    const int64_t hs = o.S0 >> node_shift(o, level + 1, a);
-                    n = 1 + ((2 * pick3(c, a) + 1) * hs < pick3(o.g.nc, a) ? 1 : 0);
-                } else {
-                    const int64_t hs = (o.S0 >> level) >> 1;
-                    for (int i = 0; i < (1 << o.D); ++i) {
-                        bool ok = true;
-                        for (int d = 0; d < o.D; ++d) ok = ok && (2 * c[d] + ((i >> d) & 1)) * hs < o.g.nc[d];
-                        n += ok ? 1 : 0;
-                    }
-                }
-            }
-        }
-        cnt[f] = n;
-    }
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x)
+        cnt[f] = emit_count(o, level, keys[f], sub[f]);
 }
 
 __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
@@ -665,9 +683,12 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
         for (int i = 0; i < (1 << o.D); ++i) {
             int64_t cc[3] = {0, 0, 0};
             bool ok = true;
-            for (int d = 0; d < o.D; ++d) {
-                cc[d] = 2 * c[d] + ((i >> d) & 1);
-                ok = ok && cc[d] * hs < o.g.nc[d];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {                  // fixed bounds: cc stays in registers
+                if (d < o.D) {
+                    cc[d] = 2 * c[d] + ((i >> d) & 1);
+                    ok = ok && cc[d] * hs < o.g.nc[d];
+                }
             }
             if (!ok) continue;
             if (pos < out_cap) out[pos] = make_key(o, level + 1, cc);
@@ -1482,8 +1503,8 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
 struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
-    size_t o_bnode, o_side, o_gmin, o_x, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_flag, o_fidx, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_lcnt, o_loff;
+    size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
+    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
@@ -1552,18 +1573,14 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_cpts = take(24 * capF);
     L.o_cmean = take(8 * capF);
     L.o_cvar = take(8 * capF);
-    L.o_flag = take(4 * capF);
-    L.o_fidx = take(4 * capF);
     L.o_lnode = take(4 * capF);
     L.o_dnode = take(4 * capF);
     L.o_gx = take(24 * capF);
     L.o_side = take(8 * capF);
     L.o_gmin = take(8 * capF);
-    L.o_x = take(24 * capF);
     L.o_done = take(4 * capF);
     L.o_ngrid = take(4 * capF);
     L.o_lmask = take(4 * capF);
-    L.o_lcnt = take(4 * capF);
     L.o_loff = take(4 * capF);
     L.o_latp = take(24 * capF * npt);
     L.o_latm = take(8 * capF * npt);
@@ -1622,6 +1639,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     int64_t caps[24], nodes[72];
     const bool cert = A.bound_kind == LCP_BOUND_CERTIFIED;
     const bool local = A.bound_kind == LCP_BOUND_LOCAL;
+    const bool search = !cert && !local;
     const int kd = A.split == LCP_SPLIT_KD;
     const int Ldepth = kd ? g.dim * Lmax : Lmax;
     AdaptLayout L = adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, kd, caps, nodes);
@@ -1658,18 +1676,14 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.cpts = (double*)P(L.o_cpts);
     B.cmean = (double*)P(L.o_cmean);
     B.cvar = (double*)P(L.o_cvar);
-    B.flag = (int32_t*)P(L.o_flag);
-    B.fidx = (int32_t*)P(L.o_fidx);
     B.lnode = (int32_t*)P(L.o_lnode);
     B.ngrid = (int32_t*)P(L.o_ngrid);
     B.lmask = (int32_t*)P(L.o_lmask);
-    B.lcnt = (int32_t*)P(L.o_lcnt);
     B.loff = (int32_t*)P(L.o_loff);
     B.dnode = (int32_t*)P(L.o_dnode);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
     B.gmin = (double*)P(L.o_gmin);
-    B.x = (double*)P(L.o_x);
     B.done = (int32_t*)P(L.o_done);
     B.lat_pts = (double*)P(L.o_latp);
     B.lat_mean = (double*)P(L.o_latm);
@@ -1712,13 +1726,18 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         uint64_t* kout = keys[(l + 1) & 1];
         const int64_t cap = caps[l];
         const int64_t* nf = cnt + l;
+        // the finest level without a test emits every node (path 3): no bound to evaluate
+        const bool bounded = !(l == Ldepth && !A.bound_at_max_depth);
         {
         StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_prelim, dim3(gsz(cap * 64, 256)), dim3(256), 0, s, o, l, kin, nf, cap, M.X, M.m, qlo, qhi,
-                           path, need, sub);
-        e = launch_scan(need, nidx, cap, nf, B.cnt + 0, scanws, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bound_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, need, nidx, B);
+                           path, need, sub, B, (int)search);
+        if (!search) {
+            // the local and certified bounds take the nodes that need a bound, compacted
+            e = launch_scan(need, nidx, cap, nf, B.cnt + 0, scanws, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_bound_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, need, nidx, B);
+        }
         }
         auto post = [&](int64_t* count, int64_t cap_pts, const double* pts, double* mean, double* var, double* dmean,
                         double* dvar, int group) {
@@ -1736,7 +1755,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             t.stage = ST_BOUND;
             return launch_posterior(M, LCP_FP64, t, s);
         };
-        if (local) {
+        if (!bounded) {
+        } else if (local) {
             // the search on each node's local model, one work-group per node
             LocalBufs lb{};
             lb.kp = M.kp;
@@ -1770,32 +1790,21 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             StageScope sc(s, ST_OCTREE);
             hipLaunchKernelGGL(k_cert_decide, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
         } else {
-            // stage 1: centres
+            // stage 1: centres of the frontier; the decision builds the stage-2 list and the
+            // node lattice
             e = post(B.cnt + 0, cap, B.cpts, B.cmean, B.cvar, nullptr, nullptr, 1);
             if (e != hipSuccess) return e;
             {
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
-                e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 1, scanws, s);
-                if (e != hipSuccess) return e;
-                e = launch_fill_i32(B.ngrid, -1, cap, s);
-                if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(k_lattice_grid, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
-                hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B);
-                e = launch_scan(B.lcnt, B.loff, cap, B.cnt + 1, B.cnt + 2, scanws, s);
-                if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(k_lattice_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
+                hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, need, B, sub);
+                hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B);
             }
-            // stage 2: lattice
+            // stage 2: lattice; the decision builds the stage-3 list and its start points
             e = post(B.cnt + 2, cap * npt, B.lat_pts, B.lat_mean, B.lat_var, nullptr, nullptr, 1);
             if (e != hipSuccess) return e;
             {
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 256)), dim3(256), 0, s, o, l, kin, B, sub);
-                hipLaunchKernelGGL(k_flag_stage3, dim3(gsz(cap, 256)), dim3(256), 0, s, B);
-                e = launch_scan(B.flag, B.fidx, cap, B.cnt + 0, B.cnt + 3, scanws, s);
-                if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(k_descent_setup, dim3(gsz(cap, 256)), dim3(256), 0, s, B, gx);
+                hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, sub, gx);
             }
             // stage 3: projected-gradient steps
             for (int k = 0; k < A.descent_steps; ++k) {
@@ -1812,8 +1821,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             }
         }
         StageScope sc(s, ST_OCTREE);
-        hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
         int64_t* nout = (l == Ldepth) ? n_leaves : cnt + l + 1;
+        hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
         e = launch_scan(ecnt, eoff, cap, nf, nout, scanws, s);
         if (e != hipSuccess) return e;
         uint64_t* dst = (l == Ldepth) ? leaves : kout;
@@ -1870,8 +1879,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     if (A.edge_bound) {
         // keep the emitted nodes whose edge-crossing bound exceeds alpha (octree buffers reused)
         StageScope sc(s, ST_OCTREE);
-        int32_t* eflag = (int32_t*)P(L.o_flag);
-        int32_t* eoff2 = (int32_t*)P(L.o_fidx);
+        int32_t* eflag = need;
+        int32_t* eoff2 = nidx;
         uint64_t* kept = (uint64_t*)P(L.o_keys0);
         int64_t* kept_n = cnt + 41;
         hipLaunchKernelGGL(k_edge_bound, dim3(gsz(leaf_cap * 64, 256)), dim3(256), 0, s, o, leaf_edge, leaves,

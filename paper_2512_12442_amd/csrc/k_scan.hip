@@ -12,36 +12,6 @@ constexpr int kScanThreads = 1024;
 constexpr int kPerThread = 4;
 constexpr int kChunk = kScanThreads * kPerThread;
 
-__device__ __forceinline__ int wave_incl_scan(int v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Block-wide exclusive scan of one int per thread; returns the block total in *total.
-__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int inc = wave_incl_scan(v);
-    if (lane == 63) sh[wave] = inc;
-    __syncthreads();
-    if (wave == 0) {
-        int w = lane < nw ? sh[lane] : 0;
-        int wi = wave_incl_scan(w);
-        if (lane < nw) sh[lane] = wi - w;
-        if (lane == nw - 1) sh[64] = wi;
-    }
-    __syncthreads();
-    int ex = inc - v + sh[wave];
-    *total = sh[64];
-    __syncthreads();
-    return ex;
-}
-
 __device__ __forceinline__ int64_t scan_n(const int64_t* n_dev, int64_t n)
 {
     if (n_dev) {

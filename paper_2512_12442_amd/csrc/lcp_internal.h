@@ -61,6 +61,38 @@ __device__ __forceinline__ double kernel_r2(const KParams& p, const double* x, c
     return r2;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one int per thread (sh: 65 ints of LDS, at most 16 waves);
+// returns the block total in *total.
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        int w = lane < nw ? sh[lane] : 0;
+        int wi = wave_incl_scan(w);
+        if (lane < nw) sh[lane] = wi - w;
+        if (lane == nw - 1) sh[64] = wi;
+    }
+    __syncthreads();
+    int ex = inc - v + sh[wave];
+    *total = sh[64];
+    __syncthreads();
+    return ex;
+}
+
 // e^x for x <= 0 in binary64: Cody-Waite reduction x = n ln2 + r (ln2 split so that n * hi
 // is exact for |n| < 2^21), |r| <= ln2 / 2, then the degree-12 Taylor polynomial of e^r
 // (truncation below 2e-16 relative) and the exact scaling by 2^n; x < -745 gives 0.
