@@ -351,11 +351,14 @@ __device__ __forceinline__ int64_t node_lin(const Oct& o, int level, const int64
 
 // Stage 1: side choice and the centre's bound, for the stage-1 nodes that need a bound.
 // The nodes it leaves open join stage 2: a slot in its list and their place in the node
-// lattice of this level.
+// lattice of this level.  Without centre values (centre = 0) every such node joins stage 2
+// and a node without observations takes its side from the lattice's centre point there:
+// the centre is a lattice point and the bound only grows with more points, so the decisions
+// are those of the staged search.
 __global__ void __launch_bounds__(256) k_bound_centre(Oct o, int level, const uint64_t* __restrict__ keys,
                                                       const int32_t* __restrict__ path,
                                                       const int32_t* __restrict__ need, BoundBufs B,
-                                                      int32_t* __restrict__ sub)
+                                                      int32_t* __restrict__ sub, int centre)
 {
     const int64_t nb = B.cnt[0];
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nb; base += (int64_t)gridDim.x * blockDim.x) {
@@ -366,17 +369,22 @@ __global__ void __launch_bounds__(256) k_bound_centre(Oct o, int level, const ui
             const int32_t f = B.bnode[b];
             if (need[f]) {
                 const int p = path[f];
-                const double side = p == 1 ? 1.0 : (p == 2 ? -1.0 : (B.cmean[b] < o.theta ? 1.0 : -1.0));
-                const double g = margin(side, o.theta, B.cmean[b], B.cvar[b]);
                 int lv;
                 int64_t clo[3], chi[3], dp;
                 double blo[3], bhi[3];
                 key_coords(o, keys[f], lv, c);
-                node_box(o, level, c, clo, chi, blo, bhi, &dp);
-                B.side[b] = side;
-                B.gmin[b] = g;
-                open = !(upper_bound(g, dp) > o.alpha);
-                if (!open) sub[f] = 1;
+                if (centre) {
+                    const double side = p == 1 ? 1.0 : (p == 2 ? -1.0 : (B.cmean[b] < o.theta ? 1.0 : -1.0));
+                    const double g = margin(side, o.theta, B.cmean[b], B.cvar[b]);
+                    node_box(o, level, c, clo, chi, blo, bhi, &dp);
+                    B.side[b] = side;
+                    B.gmin[b] = g;
+                    open = !(upper_bound(g, dp) > o.alpha);
+                    if (!open) sub[f] = 1;
+                } else {
+                    B.side[b] = p == 1 ? 1.0 : (p == 2 ? -1.0 : 0.0);   // 0: from the lattice's centre
+                    open = true;
+                }
             }
         }
         const int l = block_claim(open ? 1 : 0, B.cnt + 1);          // every thread of the block
@@ -498,10 +506,11 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
         const bool live = l < nl;
         int32_t b = 0, f = 0;
         int64_t c[3] = {0, 0, 0};
-        double gv = __builtin_inf();
+        double gv = __builtin_inf(), side = 1.0, mu = 0.0, var = 0.0;
         if (live) {
             b = B.lnode[l];
             f = B.bnode[b];
+            side = B.side[b];
             int lv;
             key_coords(o, keys[f], lv, c);
             if (sub_lane < npt) {
@@ -510,9 +519,15 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
                 lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
                 const int32_t ol = B.ngrid[node_lin(o, level, oc)];
                 const int64_t slot = B.loff[ol] + __builtin_popcount(B.lmask[ol] & ((1 << oi) - 1));
-                gv = margin(B.side[b], o.theta, B.lat_mean[slot], B.lat_var[slot]);
+                mu = B.lat_mean[slot];
+                var = B.lat_var[slot];
             }
         }
+        // stage 1 skipped: a node without observations takes its side from the centre point
+        // (digits 1 on every axis: point (npt - 1) / 2), as stage 1 would
+        const double mc = __shfl(mu, (threadIdx.x & 32) + (npt - 1) / 2, 64);
+        if (side == 0.0) side = mc < o.theta ? 1.0 : -1.0;
+        if (live && sub_lane < npt) gv = margin(side, o.theta, mu, var);
         // minimum over the 32 lanes of the node, lowest point index on ties
         double best = gv;
         int ib = sub_lane;
@@ -530,6 +545,7 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
             int64_t clo[3], chi[3], dp;
             double blo[3], bhi[3];
             node_box(o, level, c, clo, chi, blo, bhi, &dp);
+            B.side[b] = side;
             B.gmin[b] = best;
             const bool open = !(upper_bound(best, dp) > o.alpha);
             if (!open) sub[f] = 1;
@@ -1632,6 +1648,9 @@ size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, 
     return adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, A.split == LCP_SPLIT_KD, caps, nodes).total;
 }
 
+// Levels of the search with at most this many nodes skip the centre stage.
+constexpr int64_t kLatticeOnly = 512;
+
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
                         int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
                         int64_t* n_leaves, uint8_t* level_field, char* ws, hipStream_t s)
@@ -1791,12 +1810,18 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             hipLaunchKernelGGL(k_cert_decide, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, B, sub);
         } else {
             // stage 1: centres of the frontier; the decision builds the stage-2 list and the
-            // node lattice
-            e = post(B.cnt + 0, cap, B.cpts, B.cmean, B.cvar, nullptr, nullptr, 1);
-            if (e != hipSuccess) return e;
+            // node lattice.  Levels of at most kLatticeOnly nodes go to the lattice at once:
+            // their probe launches are bound by one tile's latency, so the centre launch
+            // would cost as much as the lattice's.
+            const bool centre = cap > kLatticeOnly;
+            if (centre) {
+                e = post(B.cnt + 0, cap, B.cpts, B.cmean, B.cvar, nullptr, nullptr, 1);
+                if (e != hipSuccess) return e;
+            }
             {
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, need, B, sub);
+                hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, need, B, sub,
+                                   (int)centre);
                 hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B);
             }
             // stage 2: lattice; the decision builds the stage-3 list and its start points
