@@ -17,7 +17,8 @@ namespace {
 struct Oct {
     GridP g;
     int D;
-    int64_t S0;
+    int64_t S0;              // root edge in cells, a power of two
+    int lgS0;                // log2 S0
     int Lmax;
     double theta;
     double alpha;
@@ -191,6 +192,7 @@ struct BoundBufs {
     int32_t* ngrid;     // node lattice of this level -> stage-2 node (-1: not in stage 2)
     int32_t* lmask;     // per stage-2 node: lattice points it evaluates (owns), bit i = point i
     int32_t* loff;      // per stage-2 node: first slot of its owned points
+    int32_t* lown;      // per stage-2 node and lattice point i (32 per node): owner's stage-2 index * 32 + its point index
     double* lat_pts;    // unique lattice points, 3 doubles each
     double* lat_mean;
     double* lat_var;
@@ -472,6 +474,7 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
             int oi;
             lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
             own = node_lin(o, level, oc) == node_lin(o, level, c);
+            B.lown[l * 32 + sub_lane] = B.ngrid[node_lin(o, level, oc)] * 32 + oi;
         }
         const uint64_t bal = __ballot(own);
         const uint32_t mask = (uint32_t)(bal >> (threadIdx.x & 32));
@@ -493,7 +496,7 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
 // Stage 2: lattice minimum (lowest index wins ties), start point, bound; nodes left open
 // join the descent -- a slot in the stage-3 list, their start point in gx -- or are skipped
 // when the search has no steps.  32 lanes per node, lane i reads point i from its owner's
-// slot.
+// slot (owner as found by k_lattice_own).
 __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
                                                   int32_t* __restrict__ sub, double* __restrict__ gx)
 {
@@ -514,10 +517,8 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
             int lv;
             key_coords(o, keys[f], lv, c);
             if (sub_lane < npt) {
-                int64_t oc[3];
-                int oi;
-                lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
-                const int32_t ol = B.ngrid[node_lin(o, level, oc)];
+                const int32_t own = B.lown[l * 32 + sub_lane];
+                const int32_t ol = own >> 5, oi = own & 31;
                 const int64_t slot = B.loff[ol] + __builtin_popcount(B.lmask[ol] & ((1 << oi) - 1));
                 mu = B.lat_mean[slot];
                 var = B.lat_var[slot];
@@ -724,26 +725,40 @@ __global__ void k_mark(Oct o, int leaf_edge, const uint64_t* __restrict__ leaves
 {
     const int64_t nl = *nl_dev;
     if (nl > leaf_cap) return;
-    int64_t per = 1;
-    for (int d = 0; d < o.D; ++d) per *= leaf_edge + 1;
+    const int e1 = leaf_edge + 1;
+    int per = 1;
+    for (int d = 0; d < o.D; ++d) per *= e1;
     const int64_t total = nl * per;
+    const bool idx32 = total <= 0x7fffffffll;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t lf = it / per;
-        int64_t loc = it % per;
+        int64_t lf;
+        int loc;
+        if (idx32) {
+            const uint32_t u = (uint32_t)it;
+            lf = u / (uint32_t)per;
+            loc = (int)(u - (uint32_t)lf * (uint32_t)per);
+        } else {
+            lf = it / per;
+            loc = (int)(it - lf * per);
+        }
         int lv;
         int64_t c[3];
         key_coords_oct(o.D, leaves[lf], lv, c);
         const int64_t s = o.S0 >> lv;
         int64_t v[3] = {0, 0, 0};
         bool ok = true;
-        for (int d = 0; d < o.D; ++d) {
-            int64_t cmin = c[d] * s;
-            int64_t cmax = (c[d] + 1) * s;
-            if (cmax > o.g.nc[d]) cmax = o.g.nc[d];
-            v[d] = cmin + loc % (leaf_edge + 1);
-            loc /= leaf_edge + 1;
-            ok = ok && v[d] <= cmax;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (d < o.D) {
+                int64_t cmin = c[d] * s;
+                int64_t cmax = (c[d] + 1) * s;
+                if (cmax > o.g.nc[d]) cmax = o.g.nc[d];
+                const int q = loc / e1;
+                v[d] = cmin + (loc - q * e1);
+                loc = q;
+                ok = ok && v[d] <= cmax;
+            }
         }
         if (!ok) continue;
         vmask[v[0] + o.g.n[0] * (v[1] + o.g.n[1] * v[2])] = 1;
@@ -939,13 +954,26 @@ __global__ void k_set_leaf_count(int64_t* __restrict__ nl_dev, const int64_t* __
 __global__ void k_level_field(Oct o, const uint8_t* __restrict__ stat, uint8_t* __restrict__ field)
 {
     const int64_t nc = o.g.nc[0] * o.g.nc[1] * o.g.nc[2];
+    const bool idx32 = nc <= 0xffffffffll;
     for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nc; it += (int64_t)gridDim.x * blockDim.x) {
-        int64_t cell[3] = {it % o.g.nc[0], (it / o.g.nc[0]) % o.g.nc[1], it / (o.g.nc[0] * o.g.nc[1])};
+        int64_t cell[3];
+        if (idx32) {
+            const uint32_t u = (uint32_t)it, n0 = (uint32_t)o.g.nc[0], n1 = (uint32_t)o.g.nc[1];
+            const uint32_t r = u / n0;
+            cell[0] = u - r * n0;
+            cell[2] = r / n1;
+            cell[1] = r - (uint32_t)cell[2] * n1;
+        } else {
+            cell[0] = it % o.g.nc[0];
+            cell[1] = (it / o.g.nc[0]) % o.g.nc[1];
+            cell[2] = it / (o.g.nc[0] * o.g.nc[1]);
+        }
         uint8_t out = 255;
         for (int l = 0; l <= o.Ldepth; ++l) {
             const int64_t* nl = o.nodes + l * 3;
             int64_t q[3];
-            for (int d = 0; d < 3; ++d) q[d] = d < o.D ? cell[d] / (o.S0 >> node_shift(o, l, d)) : 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) q[d] = d < o.D ? cell[d] >> (o.lgS0 - node_shift(o, l, d)) : 0;   // node edge 2^(lgS0 - shift)
             const int64_t lin = q[0] + nl[0] * (q[1] + nl[1] * q[2]);
             uint8_t st = stat[o.statoff[l] + lin];
             if (st == 1 || (st == 2 && l == o.Ldepth)) {
@@ -1520,7 +1548,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff;
+    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff, o_lown;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
@@ -1598,6 +1626,7 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_ngrid = take(4 * capF);
     L.o_lmask = take(4 * capF);
     L.o_loff = take(4 * capF);
+    L.o_lown = take(4 * 32 * capF);
     L.o_latp = take(24 * capF * npt);
     L.o_latm = take(8 * capF * npt);
     L.o_latv = take(8 * capF * npt);
@@ -1668,6 +1697,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     o.g = g;
     o.D = D;
     o.S0 = S0;
+    o.lgS0 = 0;
+    while ((int64_t(1) << o.lgS0) < S0) ++o.lgS0;
     o.Lmax = Lmax;
     o.kd = kd;
     o.Ldepth = Ldepth;
@@ -1699,6 +1730,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.ngrid = (int32_t*)P(L.o_ngrid);
     B.lmask = (int32_t*)P(L.o_lmask);
     B.loff = (int32_t*)P(L.o_loff);
+    B.lown = (int32_t*)P(L.o_lown);
     B.dnode = (int32_t*)P(L.o_dnode);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
