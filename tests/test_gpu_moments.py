@@ -56,6 +56,26 @@ def test_cell_moments_fp64_match_oracle(name):
     assert np.array_equal(cov, np.swapaxes(cov, 1, 2))
 
 
+def test_cell_moments_fp64_top_layer_96cube():
+    """Every cell of the top z-layer of a 96^3-vertex grid against the oracle.  The
+    cross-covariance launch deals tiles of x-lines to the eight XCDs; at this size an XCD's
+    run count is not a multiple of the work-group's four waves, and the runs that end each
+    XCD's sequence own the vertices of the top planes (a launch that stopped at the last
+    whole work-group once left some of them unwritten)."""
+    W = workloads.field3d_trig(0, m=60, npts=96)
+    say("cell moments fp64 96^3 top layer")
+    M = oracle.fit(W)
+    n = 95
+    cells = np.arange(n * n) + (n - 1) * n * n
+    mu_ref, cov_ref = _oracle_moments(M, W, cells)
+    G = gpu_model(W)
+    mu, cov = G.cell_moments(lcp.grid_of(W), torch.as_tensor(cells, device=DEV), "fp64")
+    mu, cov = mu.cpu().numpy(), cov.cpu().numpy()
+    say(f"  {len(cells)} cells: max|dmu|={np.abs(mu - mu_ref).max():.2e} max|dcov|={np.abs(cov - cov_ref).max():.2e}")
+    assert np.abs(mu - mu_ref).max() <= 1e-9 * max(1.0, np.abs(mu_ref).max())
+    assert np.abs(cov - cov_ref).max() <= 1e-10
+
+
 def _ragged():
     W = workloads.field3d_trig(2, m=77, npts=13)
     W.npts[:] = [13, 9, 7]
