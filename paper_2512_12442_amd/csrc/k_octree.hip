@@ -193,6 +193,8 @@ struct BoundBufs {
     int32_t* lmask;     // per stage-2 node: lattice points it evaluates (owns), bit i = point i
     int32_t* loff;      // per stage-2 node: first slot of its owned points
     int32_t* lown;      // per stage-2 node and lattice point i (32 per node): owner's stage-2 index * 32 + its point index
+    int32_t* lnode2;    // corners first: the nodes the corners left open -> stage-1 node
+    int32_t* bidx;      // corners first: per stage-1 node, the lattice index of its best corner
     double* lat_pts;    // unique lattice points, 3 doubles each
     double* lat_mean;
     double* lat_var;
@@ -202,7 +204,8 @@ struct BoundBufs {
     double* gp_var;
     double* gp_dmean;
     double* gp_dvar;
-    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes
+    int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes,
+                        // [4] nodes the corners left open
     double* box;        // certified bound: node box lo[D], hi[D] per stage-1 node (null: search)
     double* cert;       //   mu(c), mu_lo, mu_hi, var_hi per stage-1 node
 };
@@ -231,6 +234,7 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
             B.cnt[1] = 0;
             B.cnt[2] = 0;
             B.cnt[3] = 0;
+            B.cnt[4] = 0;
         }
         for (int64_t i = gt; i < cap; i += (int64_t)gridDim.x * blockDim.x) B.ngrid[i] = -1;
     }
@@ -454,11 +458,15 @@ __device__ __forceinline__ void lattice_point(const Oct& o, const double* blo, c
     }
 }
 
-// Which lattice points each stage-2 node owns (32 lanes per node, lane i = point i), a
-// range of slots for them in the list of unique lattice points, and their coordinates there.
-__global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
+// Which of the lattice points in pmask (bit i = point i) each node of a stage-2 list owns (32
+// lanes per node, lane i = point i), a range of slots for them in the list of unique lattice
+// points (count B.cnt[2]), and their coordinates there.  The owners are found among the nodes
+// registered in the node lattice.
+__global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
+                                                     const int32_t* __restrict__ list, const int64_t* __restrict__ n_list,
+                                                     uint32_t pmask)
 {
-    const int64_t nl = B.cnt[1];
+    const int64_t nl = *n_list;
     const int npt = o.D == 3 ? 27 : 9;
     const int sub_lane = threadIdx.x & 31;
     const int per = blockDim.x / 32;                                   // nodes per block and pass
@@ -466,10 +474,10 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
         const int64_t l = base + (threadIdx.x >> 5);
         bool own = false;
         double blo[3], bhi[3];
-        if (l < nl && sub_lane < npt) {
+        if (l < nl && sub_lane < npt && ((pmask >> sub_lane) & 1)) {
             int lv;
             int64_t c[3], oc[3], clo[3], chi[3], dp;
-            key_coords(o, keys[B.bnode[B.lnode[l]]], lv, c);
+            key_coords(o, keys[B.bnode[list[l]]], lv, c);
             node_box(o, level, c, clo, chi, blo, bhi, &dp);
             int oi;
             lattice_owner(o, level, B.ngrid, c, sub_lane, oc, &oi);
@@ -495,12 +503,25 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
 
 // Stage 2: lattice minimum (lowest index wins ties), start point, bound; nodes left open
 // join the descent -- a slot in the stage-3 list, their start point in gx -- or are skipped
-// when the search has no steps.  32 lanes per node, lane i reads point i from its owner's
-// slot (owner as found by k_lattice_own).
+// when the search has no steps.  32 lanes per node, lane i reads point i (of pmask) from
+// its owner's slot (owner as found by k_lattice_own).  Large levels take the corners first:
+//   mode 0: every lattice point, the decision above;
+//   mode 1: the 2^D corners.  A node whose best corner already gives UB > alpha is
+//           subdivided; the others keep their best corner (value and index) and join a
+//           second list, which replaces the node lattice's entries (decided nodes: -1);
+//   mode 2: the other points of the second list's nodes, then the decision on the minimum
+//           of both passes (lowest index on ties), which is the minimum over the lattice.
+// A best corner with UB > alpha means a lattice minimum with UB > alpha (UB falls as g_min
+// grows, and the minimum is at most the corner's value); otherwise the minimum of both passes
+// is the lattice minimum and its point.  The decisions, minima and start points are those of
+// mode 0.  The corner passes run only after a centre stage, so every node's side is known.
 __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
-                                                  int32_t* __restrict__ sub, double* __restrict__ gx)
+                                                  int32_t* __restrict__ sub, double* __restrict__ gx,
+                                                  const int32_t* __restrict__ list, const int64_t* __restrict__ n_list,
+                                                  uint32_t pmask, int mode)
 {
-    const int64_t nl = B.cnt[1];
+    const int64_t nl = *n_list;
+    if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) B.cnt[2] = 0;   // the second pass's point slots
     const int npt = o.D == 3 ? 27 : 9;
     const int sub_lane = threadIdx.x & 31;
     const int per = blockDim.x / 32;                                   // nodes per block and pass
@@ -510,13 +531,14 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
         int32_t b = 0, f = 0;
         int64_t c[3] = {0, 0, 0};
         double gv = __builtin_inf(), side = 1.0, mu = 0.0, var = 0.0;
+        const bool in_mask = sub_lane < npt && ((pmask >> sub_lane) & 1);
         if (live) {
-            b = B.lnode[l];
+            b = list[l];
             f = B.bnode[b];
             side = B.side[b];
             int lv;
             key_coords(o, keys[f], lv, c);
-            if (sub_lane < npt) {
+            if (in_mask) {
                 const int32_t own = B.lown[l * 32 + sub_lane];
                 const int32_t ol = own >> 5, oi = own & 31;
                 const int64_t slot = B.loff[ol] + __builtin_popcount(B.lmask[ol] & ((1 << oi) - 1));
@@ -527,8 +549,8 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
         // stage 1 skipped: a node without observations takes its side from the centre point
         // (digits 1 on every axis: point (npt - 1) / 2), as stage 1 would
         const double mc = __shfl(mu, (threadIdx.x & 32) + (npt - 1) / 2, 64);
-        if (side == 0.0) side = mc < o.theta ? 1.0 : -1.0;
-        if (live && sub_lane < npt) gv = margin(side, o.theta, mu, var);
+        if (mode == 0 && side == 0.0) side = mc < o.theta ? 1.0 : -1.0;
+        if (live && in_mask) gv = margin(side, o.theta, mu, var);
         // minimum over the 32 lanes of the node, lowest point index on ties
         double best = gv;
         int ib = sub_lane;
@@ -540,24 +562,52 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
                 ib = oib;
             }
         }
-        bool enter = false;
+        bool enter = false, cont = false;
         double x[3] = {0.0, 0.0, 0.0};
         if (live && sub_lane == 0) {
             int64_t clo[3], chi[3], dp;
             double blo[3], bhi[3];
             node_box(o, level, c, clo, chi, blo, bhi, &dp);
-            B.side[b] = side;
-            B.gmin[b] = best;
-            const bool open = !(upper_bound(best, dp) > o.alpha);
-            if (!open) sub[f] = 1;
-            enter = open && o.steps > 0;
-            lattice_point(o, blo, bhi, best == __builtin_inf() ? 0 : ib, x);
+            if (mode == 2) {
+                // the best corner of the first pass against the best of the other points
+                const double bc = B.gmin[b];
+                const int ic = B.bidx[b];
+                if (!(best < bc || (best == bc && ib < ic))) {
+                    best = bc;
+                    ib = ic;
+                }
+            }
+            if (mode == 1) {
+                if (upper_bound(best, dp) > o.alpha) {
+                    sub[f] = 1;
+                    B.ngrid[node_lin(o, level, c)] = -1;
+                } else {
+                    cont = true;
+                    B.gmin[b] = best;
+                    B.bidx[b] = ib;
+                }
+            } else {
+                B.side[b] = side;
+                B.gmin[b] = best;
+                const bool open = !(upper_bound(best, dp) > o.alpha);
+                if (!open) sub[f] = 1;
+                enter = open && o.steps > 0;
+                lattice_point(o, blo, bhi, best == __builtin_inf() ? 0 : ib, x);
+            }
         }
-        const int d = block_claim(enter ? 1 : 0, B.cnt + 3);          // every thread of the block
-        if (enter) {
-            B.dnode[d] = b;
-            B.done[d] = 0;
-            for (int k = 0; k < 3; ++k) gx[(int64_t)d * 3 + k] = x[k];
+        if (mode == 1) {
+            const int l2 = block_claim(cont ? 1 : 0, B.cnt + 4);       // every thread of the block
+            if (cont) {
+                B.lnode2[l2] = b;
+                B.ngrid[node_lin(o, level, c)] = l2;
+            }
+        } else {
+            const int d = block_claim(enter ? 1 : 0, B.cnt + 3);       // every thread of the block
+            if (enter) {
+                B.dnode[d] = b;
+                B.done[d] = 0;
+                for (int k = 0; k < 3; ++k) gx[(int64_t)d * 3 + k] = x[k];
+            }
         }
     }
 }
@@ -1548,7 +1598,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff, o_lown;
+    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
@@ -1627,6 +1677,8 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_lmask = take(4 * capF);
     L.o_loff = take(4 * capF);
     L.o_lown = take(4 * 32 * capF);
+    L.o_lnode2 = take(4 * capF);
+    L.o_bidx = take(4 * capF);
     L.o_latp = take(24 * capF * npt);
     L.o_latm = take(8 * capF * npt);
     L.o_latv = take(8 * capF * npt);
@@ -1677,8 +1729,10 @@ size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, 
     return adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, A.split == LCP_SPLIT_KD, caps, nodes).total;
 }
 
-// Levels of the search with at most this many nodes skip the centre stage.
+// Levels of the search with at most this many nodes skip the centre stage; levels of at least
+// kCornersFirst nodes evaluate the lattice's corners before its other points.
 constexpr int64_t kLatticeOnly = 512;
+constexpr int64_t kCornersFirst = 32768;
 
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
                         int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
@@ -1731,6 +1785,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.lmask = (int32_t*)P(L.o_lmask);
     B.loff = (int32_t*)P(L.o_loff);
     B.lown = (int32_t*)P(L.o_lown);
+    B.lnode2 = (int32_t*)P(L.o_lnode2);
+    B.bidx = (int32_t*)P(L.o_bidx);
     B.dnode = (int32_t*)P(L.o_dnode);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
@@ -1854,14 +1910,35 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 StageScope sc(s, ST_OCTREE);
                 hipLaunchKernelGGL(k_bound_centre, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, path, need, B, sub,
                                    (int)centre);
-                hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B);
             }
-            // stage 2: lattice; the decision builds the stage-3 list and its start points
-            e = post(B.cnt + 2, cap * npt, B.lat_pts, B.lat_mean, B.lat_var, nullptr, nullptr, 1);
-            if (e != hipSuccess) return e;
-            {
+            // stage 2: lattice; the decision builds the stage-3 list and its start points.  Levels
+            // of at least kCornersFirst nodes (after a centre stage) evaluate the corners first.
+            const uint32_t all = (1u << npt) - 1;
+            uint32_t corners = 0;
+            for (int i = 0; i < npt; ++i) {
+                bool c = true;
+                for (int d = 0, r = i; d < D; ++d, r /= 3) c = c && (r % 3 != 1);
+                if (c) corners |= 1u << i;
+            }
+            const bool cfirst = centre && cap >= kCornersFirst;
+            auto lattice_pass = [&](const int32_t* list, int64_t* n_list, uint32_t pmask, int mode) {
+                {
+                    StageScope sc(s, ST_OCTREE);
+                    hipLaunchKernelGGL(k_lattice_own, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, list,
+                                       n_list, pmask);
+                }
+                hipError_t r = post(B.cnt + 2, cap * npt, B.lat_pts, B.lat_mean, B.lat_var, nullptr, nullptr, 1);
+                if (r != hipSuccess) return r;
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, sub, gx);
+                hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, sub, gx, list,
+                                   n_list, pmask, mode);
+                return hipGetLastError();
+            };
+            if (cfirst) {
+                if ((e = lattice_pass(B.lnode, B.cnt + 1, corners, 1)) != hipSuccess) return e;
+                if ((e = lattice_pass(B.lnode2, B.cnt + 4, all & ~corners, 2)) != hipSuccess) return e;
+            } else {
+                if ((e = lattice_pass(B.lnode, B.cnt + 1, all, 0)) != hipSuccess) return e;
             }
             // stage 3: projected-gradient steps
             for (int k = 0; k < A.descent_steps; ++k) {
