@@ -35,19 +35,28 @@ constexpr int kBwdGridQ = 1024;     // work-groups of the pairs pass (partials)
 constexpr int kBwdSplitPts = 4096;  // points per split of the rank-n product
 constexpr int kBwdMaxSplit = 32;
 
-// K^-1[i][j] = sum_k Linv[k][i] Linv[k][j], 16 x 16 tiles through LDS.
+// K^-1[i][j] = sum_k Linv[k][i] Linv[k][j]: a 16 x 16 tile per work-group, k in steps of 64
+// through LDS (few dependent load-barrier rounds).  Linv is lower triangular, so the sum
+// starts at the first step that reaches row max(i, j); every term it skips is an exact zero
+// and the FMAs run in increasing k as over the whole range.
 __global__ void __launch_bounds__(256) k_kinv(const double* __restrict__ Li, int mp, double* __restrict__ Ki)
 {
-    __shared__ double As[16][17], Bs[16][17];
+    __shared__ double As[16][65], Bs[64][17];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+    const int kfirst = (16 * (blockIdx.x > blockIdx.y ? blockIdx.x : blockIdx.y)) / 64 * 64;
     double c = 0.0;
-    for (int k0 = 0; k0 < mp; k0 += 16) {
-        As[ty][tx] = Li[(int64_t)(k0 + tx) * mp + blockIdx.y * 16 + ty];   // Linv^T[i][k]
-        Bs[ty][tx] = Li[(int64_t)(k0 + ty) * mp + j];                      // Linv[k][j]
+    for (int k0 = kfirst; k0 < mp; k0 += 64) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = 16 * q + (threadIdx.x >> 4), r = threadIdx.x & 15;      // 64 x 16 of each, rows coalesced
+            const bool in = k0 + kk < mp;
+            As[r][kk] = in ? Li[(int64_t)(k0 + kk) * mp + blockIdx.y * 16 + r] : 0.0;   // Linv^T[i][k]
+            Bs[kk][r] = in ? Li[(int64_t)(k0 + kk) * mp + blockIdx.x * 16 + r] : 0.0;   // Linv[k][j]
+        }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) c = fma(As[ty][k], Bs[k][tx], c);
+        for (int k = 0; k < 64; ++k) c = fma(As[ty][k], Bs[k][tx], c);
         __syncthreads();
     }
     Ki[(int64_t)i * mp + j] = c;

@@ -195,6 +195,11 @@ struct BoundBufs {
     int32_t* lown;      // per stage-2 node and lattice point i (32 per node): owner's stage-2 index * 32 + its point index
     int32_t* lnode2;    // corners first: the nodes the corners left open -> stage-1 node
     int32_t* bidx;      // corners first: per stage-1 node, the lattice index of its best corner
+    double* dpts;       // descent certificate: per stage-3 candidate, its node's centre (3) and box (lo[D], hi[D])
+    double* dbox;
+    double* dcert;      //   mu(c), mu_lo, mu_hi, var_hi per candidate
+    int32_t* dnode2;    //   the candidates the certificate leaves open -> stage-1 node
+    double* gx2;        //   and their start points
     double* lat_pts;    // unique lattice points, 3 doubles each
     double* lat_mean;
     double* lat_var;
@@ -205,7 +210,7 @@ struct BoundBufs {
     double* gp_dmean;
     double* gp_dvar;
     int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes,
-                        // [4] nodes the corners left open
+                        // [4] nodes the corners left open, [5] stage-3 nodes the certificate left open
     double* box;        // certified bound: node box lo[D], hi[D] per stage-1 node (null: search)
     double* cert;       //   mu(c), mu_lo, mu_hi, var_hi per stage-1 node
 };
@@ -235,6 +240,7 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
             B.cnt[2] = 0;
             B.cnt[3] = 0;
             B.cnt[4] = 0;
+            B.cnt[5] = 0;
         }
         for (int64_t i = gt; i < cap; i += (int64_t)gridDim.x * blockDim.x) B.ngrid[i] = -1;
     }
@@ -447,14 +453,17 @@ __device__ __forceinline__ void lattice_owner(const Oct& o, int level, const int
 
 __device__ __forceinline__ void lattice_point(const Oct& o, const double* blo, const double* bhi, int i, double* x)
 {
+    // Every lane forms lo, mid and hi and selects one: per-digit branches here were lowered
+    // with the hi copy in the digit-0 block (hipcc of ROCm 7.2, k_lattice with the box kept
+    // live), which left digit-2 coordinates unwritten.
     int r = i;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        x[d] = 0.0;
-        if (d < o.D) {
-            const int digit = r % 3;
-            r /= 3;
-            x[d] = digit == 0 ? blo[d] : (digit == 1 ? 0.5 * (blo[d] + bhi[d]) : bhi[d]);
-        }
+        const int digit = r % 3;
+        r /= 3;
+        const double lo = blo[d], hi = bhi[d], mid = 0.5 * (lo + hi);
+        const double v = digit == 0 ? lo : (digit == 1 ? mid : hi);
+        x[d] = d < o.D ? v : 0.0;
     }
 }
 
@@ -518,7 +527,7 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
 __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
                                                   int32_t* __restrict__ sub, double* __restrict__ gx,
                                                   const int32_t* __restrict__ list, const int64_t* __restrict__ n_list,
-                                                  uint32_t pmask, int mode)
+                                                  uint32_t pmask, int mode, int dsave)
 {
     const int64_t nl = *n_list;
     if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) B.cnt[2] = 0;   // the second pass's point slots
@@ -564,9 +573,9 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
         }
         bool enter = false, cont = false;
         double x[3] = {0.0, 0.0, 0.0};
+        double blo[3] = {0.0, 0.0, 0.0}, bhi[3] = {0.0, 0.0, 0.0};
         if (live && sub_lane == 0) {
             int64_t clo[3], chi[3], dp;
-            double blo[3], bhi[3];
             node_box(o, level, c, clo, chi, blo, bhi, &dp);
             if (mode == 2) {
                 // the best corner of the first pass against the best of the other points
@@ -607,7 +616,50 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
                 B.dnode[d] = b;
                 B.done[d] = 0;
                 for (int k = 0; k < 3; ++k) gx[(int64_t)d * 3 + k] = x[k];
+                if (dsave) {
+                    for (int k = 0; k < 3; ++k) B.dpts[(int64_t)d * 3 + k] = k < o.D ? 0.5 * (blo[k] + bhi[k]) : 0.0;
+                    for (int k = 0; k < o.D; ++k) {
+                        B.dbox[(int64_t)d * 2 * o.D + k] = blo[k];
+                        B.dbox[(int64_t)d * 2 * o.D + o.D + k] = bhi[k];
+                    }
+                }
             }
+        }
+    }
+}
+
+// Descent certificate (large levels): the certified box bounds of the posterior (k_bound.hip,
+// the guaranteed bound Sec. 9 leaves open) for each stage-3 candidate, with the search's own
+// side.  The certified margin is a lower bound of g over the whole box, so of every point the
+// descent could visit; when it already gives UB <= alpha (eq. (upper_bound)), the search's
+// minimum gives UB <= alpha too and the node is not subdivided, as the descent would
+// conclude.  The other candidates form the descent's list (count B.cnt[5]).
+__global__ void __launch_bounds__(256) k_descent_cert(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
+                                                      const double* __restrict__ gx)
+{
+    const int64_t nd = B.cnt[3];
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nd; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = base + threadIdx.x;
+        bool keep = false;
+        int32_t b = 0;
+        if (d < nd) {
+            b = B.dnode[d];
+            const double side = B.side[b];
+            const double* cb = B.dcert + d * 4;
+            const double mu = side > 0 ? cb[2] : cb[1];
+            const double g = side * (o.theta - mu) < 0.0 ? -__builtin_inf() : margin(side, o.theta, mu, cb[3]);
+            int lv;
+            int64_t c[3], clo[3], chi[3], dp;
+            double blo[3], bhi[3];
+            key_coords(o, keys[B.bnode[b]], lv, c);
+            node_box(o, level, c, clo, chi, blo, bhi, &dp);
+            keep = upper_bound(g, dp) > o.alpha;
+        }
+        const int d2 = block_claim(keep ? 1 : 0, B.cnt + 5);           // every thread of the block
+        if (keep) {
+            B.dnode2[d2] = b;
+            B.done[d2] = 0;
+            for (int k = 0; k < 3; ++k) B.gx2[(int64_t)d2 * 3 + k] = gx[d * 3 + k];
         }
     }
 }
@@ -615,9 +667,9 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
 // One projected step of the bound search at the current point x_k (posterior and its
 // gradient already evaluated).  For k >= 1 the value at x_k also enters the minimum.
 __global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ keys, BoundBufs B,
-                          double* __restrict__ gx)
+                          double* __restrict__ gx, const int64_t* __restrict__ nd_dev)
 {
-    const int64_t nd = B.cnt[3];
+    const int64_t nd = *nd_dev;
     double eta = 0.5;
     for (int i = 0; i < k; ++i) eta *= 0.5;
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
@@ -659,9 +711,9 @@ __global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ 
 
 // Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)), and the decision.
 __global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
-                              int32_t* __restrict__ sub)
+                              int32_t* __restrict__ sub, const int64_t* __restrict__ nd_dev)
 {
-    const int64_t nd = B.cnt[3];
+    const int64_t nd = *nd_dev;
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
         const int32_t b = B.dnode[d];
         double gmin = B.gmin[b];
@@ -1594,13 +1646,25 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
 }  // namespace
 
 // Workspace layout of lcp_adaptive.
+// Levels of the search with at most this many nodes skip the centre stage; levels of at least
+// kCornersFirst nodes evaluate the lattice's corners before its other points.
+constexpr int64_t kLatticeOnly = 512;
+constexpr int64_t kCornersFirst = 32768;
+// Octree levels of at least this many nodes run the descent certificate (k_descent_cert).  It
+// costs about one probe of the candidates and pays where many of them are far from the level
+// (the octree's 8-way splits leave such nodes at the deepest levels); the K-D tree refines one
+// axis at a time, so its deep candidates sit near the crossing and the certificate settles few.
+constexpr int64_t kDescentCert = 32768;
+
 struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
     size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
-    size_t o_cop, o_cw, o_box, o_cert;   // certified bound only (0 otherwise)
+    size_t o_cop, o_cw, o_box, o_cert;   // certified bound (o_cop, o_cw also for the descent certificate)
+    size_t o_dpts, o_dbox, o_dcert, o_dnode2, o_gx2;   // search: descent certificate
+    int dcert;                           // 1: the search has a level that runs the descent certificate
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
     int nloc;                            // local-model bound only: slots (resident work-groups)
     int64_t capF, nv;
@@ -1703,6 +1767,16 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         for (int d = 0; d < D; ++d) cpl *= S0 >> Lmax;
         L.o_cellws = take(cells_scratch_bytes(caps[Ldepth] * cpl));
     }
+    if (bound_kind == LCP_BOUND_SEARCH && !kd && capF >= kDescentCert) {
+        L.dcert = 1;
+        L.o_cop = take(cert_operand_bytes(M));
+        L.o_cw = take(8 * (size_t)M.m_pad * capF);
+        L.o_dpts = take(24 * (size_t)capF);
+        L.o_dbox = take(8 * 2 * (size_t)D * capF);
+        L.o_dcert = take(32 * (size_t)capF);
+        L.o_dnode2 = take(4 * (size_t)capF);
+        L.o_gx2 = take(24 * (size_t)capF);
+    }
     if (bound_kind == LCP_BOUND_CERTIFIED) {
         L.o_cop = take(cert_operand_bytes(M));
         L.o_cw = take(8 * (size_t)M.m_pad * capF);
@@ -1728,11 +1802,6 @@ size_t adaptive_workspace(const Model& M, const GridP& g, int64_t S0, int Lmax, 
     int64_t caps[24], nodes[72];
     return adapt_layout(M, g, S0, Lmax, prec, ns, A.bound_kind, A.split == LCP_SPLIT_KD, caps, nodes).total;
 }
-
-// Levels of the search with at most this many nodes skip the centre stage; levels of at least
-// kCornersFirst nodes evaluate the lattice's corners before its other points.
-constexpr int64_t kLatticeOnly = 512;
-constexpr int64_t kCornersFirst = 32768;
 
 hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_adapt& A, int64_t S0, int Lmax,
                         int prec, int ns, const double* zb, float* lcp, uint64_t* leaves, int64_t leaf_cap,
@@ -1802,7 +1871,12 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.cnt = cnt + 32;
     B.box = cert ? (double*)P(L.o_box) : nullptr;
     B.cert = cert ? (double*)P(L.o_cert) : nullptr;
-    double* certW = cert ? (double*)P(L.o_cw) : nullptr;
+    double* certW = (cert || L.dcert) ? (double*)P(L.o_cw) : nullptr;
+    B.dpts = L.dcert ? (double*)P(L.o_dpts) : nullptr;
+    B.dbox = L.dcert ? (double*)P(L.o_dbox) : nullptr;
+    B.dcert = L.dcert ? (double*)P(L.o_dcert) : nullptr;
+    B.dnode2 = L.dcert ? (int32_t*)P(L.o_dnode2) : nullptr;
+    B.gx2 = L.dcert ? (double*)P(L.o_gx2) : nullptr;
 
     hipError_t e;
     double* certF64 = nullptr;
@@ -1921,6 +1995,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (c) corners |= 1u << i;
             }
             const bool cfirst = centre && cap >= kCornersFirst;
+            const bool dcert = L.dcert && cap >= kDescentCert && A.descent_steps > 0;
             auto lattice_pass = [&](const int32_t* list, int64_t* n_list, uint32_t pmask, int mode) {
                 {
                     StageScope sc(s, ST_OCTREE);
@@ -1931,7 +2006,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (r != hipSuccess) return r;
                 StageScope sc(s, ST_OCTREE);
                 hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, sub, gx, list,
-                                   n_list, pmask, mode);
+                                   n_list, pmask, mode, (int)dcert);
                 return hipGetLastError();
             };
             if (cfirst) {
@@ -1940,18 +2015,36 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             } else {
                 if ((e = lattice_pass(B.lnode, B.cnt + 1, all, 0)) != hipSuccess) return e;
             }
+            // large levels: the certificate settles the candidates it can (k_descent_cert); the
+            // descent runs on the others
+            BoundBufs Bd = B;
+            double* gxd = gx;
+            int64_t* ndd = B.cnt + 3;
+            if (dcert) {
+                if (!certF64 && (e = launch_cert_operand(M, (char*)P(L.o_cop), &certF64, s)) != hipSuccess) return e;
+                if ((e = launch_cert_w(M, certF64, B.dpts, B.cnt + 3, cap, certW, B.cmean, B.cvar, s)) != hipSuccess)
+                    return e;
+                if ((e = launch_cert(M, B.dbox, B.cnt + 3, cap, certW, B.dcert, s)) != hipSuccess) return e;
+                {
+                    StageScope sc(s, ST_OCTREE);
+                    hipLaunchKernelGGL(k_descent_cert, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, gx);
+                }
+                Bd.dnode = B.dnode2;
+                gxd = B.gx2;
+                ndd = B.cnt + 5;
+            }
             // stage 3: projected-gradient steps
             for (int k = 0; k < A.descent_steps; ++k) {
-                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
+                e = post(ndd, cap, gxd, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
                 if (e != hipSuccess) return e;
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B, gx);
+                hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, Bd, gxd, ndd);
             }
             if (A.descent_steps > 0) {
-                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
+                e = post(ndd, cap, gxd, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
                 if (e != hipSuccess) return e;
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
+                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, Bd, sub, ndd);
             }
         }
         StageScope sc(s, ST_OCTREE);
