@@ -195,11 +195,10 @@ struct BoundBufs {
     int32_t* lown;      // per stage-2 node and lattice point i (32 per node): owner's stage-2 index * 32 + its point index
     int32_t* lnode2;    // corners first: the nodes the corners left open -> stage-1 node
     int32_t* bidx;      // corners first: per stage-1 node, the lattice index of its best corner
-    double* dpts;       // descent certificate: per stage-3 candidate, its node's centre (3) and box (lo[D], hi[D])
-    double* dbox;
-    double* dcert;      //   mu(c), mu_lo, mu_hi, var_hi per candidate
-    int32_t* dnode2;    //   the candidates the certificate leaves open -> stage-1 node
-    double* gx2;        //   and their start points
+    double* dpts;       // certificate between the lattice passes: per node the corners left open, its
+    double* dbox;       //   centre (3) and box (lo[D], hi[D]),
+    double* dcert;      //   mu(c), mu_lo, mu_hi, var_hi,
+    int32_t* lnode3;    //   and the nodes it leaves open -> stage-1 node
     double* lat_pts;    // unique lattice points, 3 doubles each
     double* lat_mean;
     double* lat_var;
@@ -210,7 +209,7 @@ struct BoundBufs {
     double* gp_dmean;
     double* gp_dvar;
     int64_t* cnt;       // [0] stage-1 nodes, [1] stage-2 nodes, [2] unique lattice points, [3] stage-3 nodes,
-                        // [4] nodes the corners left open, [5] stage-3 nodes the certificate left open
+                        // [4] nodes the corners left open, [5] of those, the nodes the certificate left open
     double* box;        // certified bound: node box lo[D], hi[D] per stage-1 node (null: search)
     double* cert;       //   mu(c), mu_lo, mu_hi, var_hi per stage-1 node
 };
@@ -527,7 +526,7 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
 __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
                                                   int32_t* __restrict__ sub, double* __restrict__ gx,
                                                   const int32_t* __restrict__ list, const int64_t* __restrict__ n_list,
-                                                  uint32_t pmask, int mode, int dsave)
+                                                  uint32_t pmask, int mode, int csave)
 {
     const int64_t nl = *n_list;
     if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) B.cnt[2] = 0;   // the second pass's point slots
@@ -609,6 +608,13 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
             if (cont) {
                 B.lnode2[l2] = b;
                 B.ngrid[node_lin(o, level, c)] = l2;
+                if (csave) {
+                    for (int k = 0; k < 3; ++k) B.dpts[(int64_t)l2 * 3 + k] = k < o.D ? 0.5 * (blo[k] + bhi[k]) : 0.0;
+                    for (int k = 0; k < o.D; ++k) {
+                        B.dbox[(int64_t)l2 * 2 * o.D + k] = blo[k];
+                        B.dbox[(int64_t)l2 * 2 * o.D + o.D + k] = bhi[k];
+                    }
+                }
             }
         } else {
             const int d = block_claim(enter ? 1 : 0, B.cnt + 3);       // every thread of the block
@@ -616,36 +622,31 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
                 B.dnode[d] = b;
                 B.done[d] = 0;
                 for (int k = 0; k < 3; ++k) gx[(int64_t)d * 3 + k] = x[k];
-                if (dsave) {
-                    for (int k = 0; k < 3; ++k) B.dpts[(int64_t)d * 3 + k] = k < o.D ? 0.5 * (blo[k] + bhi[k]) : 0.0;
-                    for (int k = 0; k < o.D; ++k) {
-                        B.dbox[(int64_t)d * 2 * o.D + k] = blo[k];
-                        B.dbox[(int64_t)d * 2 * o.D + o.D + k] = bhi[k];
-                    }
-                }
             }
         }
     }
 }
 
-// Descent certificate (large levels): the certified box bounds of the posterior (k_bound.hip,
-// the guaranteed bound Sec. 9 leaves open) for each stage-3 candidate, with the search's own
-// side.  The certified margin is a lower bound of g over the whole box, so of every point the
-// descent could visit; when it already gives UB <= alpha (eq. (upper_bound)), the search's
-// minimum gives UB <= alpha too and the node is not subdivided, as the descent would
-// conclude.  The other candidates form the descent's list (count B.cnt[5]).
-__global__ void __launch_bounds__(256) k_descent_cert(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
-                                                      const double* __restrict__ gx)
+// Certificate between the lattice passes (large levels): the certified box bounds of the
+// posterior (k_bound.hip, the guaranteed bound Sec. 9 leaves open) for each node the corners
+// left open, with the search's own side.  The certified margin is a lower bound of g over
+// the whole box, so of every point the rest of the lattice and the descent could visit; when
+// it already gives UB <= alpha (eq. (upper_bound)), the search's minimum gives UB <= alpha too
+// and the node is not subdivided, as the search would conclude.  Such nodes leave the node
+// lattice; the others form the list of the second pass (count B.cnt[5]) and re-register
+// there under their new index.
+__global__ void __launch_bounds__(256) k_lattice_cert(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B)
 {
-    const int64_t nd = B.cnt[3];
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nd; base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t d = base + threadIdx.x;
+    const int64_t n2 = B.cnt[4];
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n2; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = base + threadIdx.x;
         bool keep = false;
         int32_t b = 0;
-        if (d < nd) {
-            b = B.dnode[d];
+        int64_t lin = 0;
+        if (j < n2) {
+            b = B.lnode2[j];
             const double side = B.side[b];
-            const double* cb = B.dcert + d * 4;
+            const double* cb = B.dcert + j * 4;
             const double mu = side > 0 ? cb[2] : cb[1];
             const double g = side * (o.theta - mu) < 0.0 ? -__builtin_inf() : margin(side, o.theta, mu, cb[3]);
             int lv;
@@ -654,12 +655,13 @@ __global__ void __launch_bounds__(256) k_descent_cert(Oct o, int level, const ui
             key_coords(o, keys[B.bnode[b]], lv, c);
             node_box(o, level, c, clo, chi, blo, bhi, &dp);
             keep = upper_bound(g, dp) > o.alpha;
+            lin = node_lin(o, level, c);
+            if (!keep) B.ngrid[lin] = -1;
         }
-        const int d2 = block_claim(keep ? 1 : 0, B.cnt + 5);           // every thread of the block
+        const int j3 = block_claim(keep ? 1 : 0, B.cnt + 5);           // every thread of the block
         if (keep) {
-            B.dnode2[d2] = b;
-            B.done[d2] = 0;
-            for (int k = 0; k < 3; ++k) B.gx2[(int64_t)d2 * 3 + k] = gx[d * 3 + k];
+            B.lnode3[j3] = b;
+            B.ngrid[lin] = j3;
         }
     }
 }
@@ -667,9 +669,9 @@ __global__ void __launch_bounds__(256) k_descent_cert(Oct o, int level, const ui
 // One projected step of the bound search at the current point x_k (posterior and its
 // gradient already evaluated).  For k >= 1 the value at x_k also enters the minimum.
 __global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ keys, BoundBufs B,
-                          double* __restrict__ gx, const int64_t* __restrict__ nd_dev)
+                          double* __restrict__ gx)
 {
-    const int64_t nd = *nd_dev;
+    const int64_t nd = B.cnt[3];
     double eta = 0.5;
     for (int i = 0; i < k; ++i) eta *= 0.5;
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
@@ -711,9 +713,9 @@ __global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ 
 
 // Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)), and the decision.
 __global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
-                              int32_t* __restrict__ sub, const int64_t* __restrict__ nd_dev)
+                              int32_t* __restrict__ sub)
 {
-    const int64_t nd = *nd_dev;
+    const int64_t nd = B.cnt[3];
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
         const int32_t b = B.dnode[d];
         double gmin = B.gmin[b];
@@ -1650,11 +1652,12 @@ __global__ void __launch_bounds__(256, 4) k_local_bound(Oct o, int level, const 
 // kCornersFirst nodes evaluate the lattice's corners before its other points.
 constexpr int64_t kLatticeOnly = 512;
 constexpr int64_t kCornersFirst = 32768;
-// Octree levels of at least this many nodes run the descent certificate (k_descent_cert).  It
-// costs about one probe of the candidates and pays where many of them are far from the level
-// (the octree's 8-way splits leave such nodes at the deepest levels); the K-D tree refines one
-// axis at a time, so its deep candidates sit near the crossing and the certificate settles few.
-constexpr int64_t kDescentCert = 32768;
+// Octree levels of at least this many nodes (which take the corners first) run the certified
+// bound on the nodes the corners leave open (k_lattice_cert).  It costs about one probe of
+// those nodes and pays where many of them are far from the level (the octree's 8-way splits
+// leave such nodes at the deepest levels); the K-D tree refines one axis at a time, so its
+// deep candidates sit near the crossing and the certificate settles few.
+constexpr int64_t kLatticeCert = 32768;
 
 struct AdaptLayout {
     size_t total;
@@ -1663,8 +1666,8 @@ struct AdaptLayout {
     size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound (o_cop, o_cw also for the descent certificate)
-    size_t o_dpts, o_dbox, o_dcert, o_dnode2, o_gx2;   // search: descent certificate
-    int dcert;                           // 1: the search has a level that runs the descent certificate
+    size_t o_dpts, o_dbox, o_dcert, o_lnode3;   // search: certificate between the lattice passes
+    int lcert;                           // 1: the search has a level that runs it
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
     int nloc;                            // local-model bound only: slots (resident work-groups)
     int64_t capF, nv;
@@ -1767,15 +1770,14 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         for (int d = 0; d < D; ++d) cpl *= S0 >> Lmax;
         L.o_cellws = take(cells_scratch_bytes(caps[Ldepth] * cpl));
     }
-    if (bound_kind == LCP_BOUND_SEARCH && !kd && capF >= kDescentCert) {
-        L.dcert = 1;
+    if (bound_kind == LCP_BOUND_SEARCH && !kd && capF >= kLatticeCert) {
+        L.lcert = 1;
         L.o_cop = take(cert_operand_bytes(M));
         L.o_cw = take(8 * (size_t)M.m_pad * capF);
         L.o_dpts = take(24 * (size_t)capF);
         L.o_dbox = take(8 * 2 * (size_t)D * capF);
         L.o_dcert = take(32 * (size_t)capF);
-        L.o_dnode2 = take(4 * (size_t)capF);
-        L.o_gx2 = take(24 * (size_t)capF);
+        L.o_lnode3 = take(4 * (size_t)capF);
     }
     if (bound_kind == LCP_BOUND_CERTIFIED) {
         L.o_cop = take(cert_operand_bytes(M));
@@ -1871,12 +1873,11 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.cnt = cnt + 32;
     B.box = cert ? (double*)P(L.o_box) : nullptr;
     B.cert = cert ? (double*)P(L.o_cert) : nullptr;
-    double* certW = (cert || L.dcert) ? (double*)P(L.o_cw) : nullptr;
-    B.dpts = L.dcert ? (double*)P(L.o_dpts) : nullptr;
-    B.dbox = L.dcert ? (double*)P(L.o_dbox) : nullptr;
-    B.dcert = L.dcert ? (double*)P(L.o_dcert) : nullptr;
-    B.dnode2 = L.dcert ? (int32_t*)P(L.o_dnode2) : nullptr;
-    B.gx2 = L.dcert ? (double*)P(L.o_gx2) : nullptr;
+    double* certW = (cert || L.lcert) ? (double*)P(L.o_cw) : nullptr;
+    B.dpts = L.lcert ? (double*)P(L.o_dpts) : nullptr;
+    B.dbox = L.lcert ? (double*)P(L.o_dbox) : nullptr;
+    B.dcert = L.lcert ? (double*)P(L.o_dcert) : nullptr;
+    B.lnode3 = L.lcert ? (int32_t*)P(L.o_lnode3) : nullptr;
 
     hipError_t e;
     double* certF64 = nullptr;
@@ -1995,7 +1996,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (c) corners |= 1u << i;
             }
             const bool cfirst = centre && cap >= kCornersFirst;
-            const bool dcert = L.dcert && cap >= kDescentCert && A.descent_steps > 0;
+            // the certified bound between the passes (octree levels of at least kLatticeCert nodes)
+            const bool ccert = cfirst && L.lcert && cap >= kLatticeCert;
             auto lattice_pass = [&](const int32_t* list, int64_t* n_list, uint32_t pmask, int mode) {
                 {
                     StageScope sc(s, ST_OCTREE);
@@ -2006,45 +2008,43 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (r != hipSuccess) return r;
                 StageScope sc(s, ST_OCTREE);
                 hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, sub, gx, list,
-                                   n_list, pmask, mode, (int)dcert);
+                                   n_list, pmask, mode, (int)(ccert && mode == 1));
                 return hipGetLastError();
             };
             if (cfirst) {
                 if ((e = lattice_pass(B.lnode, B.cnt + 1, corners, 1)) != hipSuccess) return e;
-                if ((e = lattice_pass(B.lnode2, B.cnt + 4, all & ~corners, 2)) != hipSuccess) return e;
+                const int32_t* list2 = B.lnode2;
+                int64_t* n2 = B.cnt + 4;
+                if (ccert) {
+                    // w = Q k(c), box moments, decision: settled nodes skip the rest of the lattice
+                    // and the descent
+                    if (!certF64 && (e = launch_cert_operand(M, (char*)P(L.o_cop), &certF64, s)) != hipSuccess) return e;
+                    if ((e = launch_cert_w(M, certF64, B.dpts, B.cnt + 4, cap, certW, B.cmean, B.cvar, s)) != hipSuccess)
+                        return e;
+                    if ((e = launch_cert(M, B.dbox, B.cnt + 4, cap, certW, B.dcert, s)) != hipSuccess) return e;
+                    {
+                        StageScope sc(s, ST_OCTREE);
+                        hipLaunchKernelGGL(k_lattice_cert, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B);
+                    }
+                    list2 = B.lnode3;
+                    n2 = B.cnt + 5;
+                }
+                if ((e = lattice_pass(list2, n2, all & ~corners, 2)) != hipSuccess) return e;
             } else {
                 if ((e = lattice_pass(B.lnode, B.cnt + 1, all, 0)) != hipSuccess) return e;
             }
-            // large levels: the certificate settles the candidates it can (k_descent_cert); the
-            // descent runs on the others
-            BoundBufs Bd = B;
-            double* gxd = gx;
-            int64_t* ndd = B.cnt + 3;
-            if (dcert) {
-                if (!certF64 && (e = launch_cert_operand(M, (char*)P(L.o_cop), &certF64, s)) != hipSuccess) return e;
-                if ((e = launch_cert_w(M, certF64, B.dpts, B.cnt + 3, cap, certW, B.cmean, B.cvar, s)) != hipSuccess)
-                    return e;
-                if ((e = launch_cert(M, B.dbox, B.cnt + 3, cap, certW, B.dcert, s)) != hipSuccess) return e;
-                {
-                    StageScope sc(s, ST_OCTREE);
-                    hipLaunchKernelGGL(k_descent_cert, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, gx);
-                }
-                Bd.dnode = B.dnode2;
-                gxd = B.gx2;
-                ndd = B.cnt + 5;
-            }
             // stage 3: projected-gradient steps
             for (int k = 0; k < A.descent_steps; ++k) {
-                e = post(ndd, cap, gxd, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
+                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
                 if (e != hipSuccess) return e;
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, Bd, gxd, ndd);
+                hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B, gx);
             }
             if (A.descent_steps > 0) {
-                e = post(ndd, cap, gxd, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
+                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
                 if (e != hipSuccess) return e;
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, Bd, sub, ndd);
+                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
             }
         }
         StageScope sc(s, ST_OCTREE);
