@@ -147,16 +147,6 @@ __device__ int block_claim(int n, int64_t* counter)
     return r;
 }
 
-// Standardised margin of one side: side (theta - mu) / sigma with the sigma = 0 limits.
-__device__ __forceinline__ double margin(double side, double theta, double mu, double var)
-{
-    double num = side * (theta - mu);
-    if (var > 0.0) return num / sqrt(var);
-    if (num > 0.0) return __builtin_inf();
-    if (num < 0.0) return -__builtin_inf();
-    return 0.0;
-}
-
 // P(Y_i < theta), P(Y_i > theta) for each observation from its latent posterior.
 __global__ void k_obs_q(const double* __restrict__ mu, const double* __restrict__ var, int m, double theta,
                         double* __restrict__ qlo, double* __restrict__ qhi)
@@ -203,6 +193,8 @@ struct BoundBufs {
     double* lat_mean;
     double* lat_var;
     int32_t* dnode;     // stage-3 node -> stage-1 node
+    double* dbx;        // per stage-3 node: box lo[3], hi[3], side, g_min so far (64 B)
+    int64_t* ddp;       //   and its grid points
     int32_t* done;
     double* gp_mean;    // posterior (and gradient) at the stage-3 points
     double* gp_var;
@@ -295,15 +287,6 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
 // The search's stage-1 list is the frontier; each stage's decision kernel appends the nodes
 // it leaves open to the next stage's list (block_claim), so the lists are built without
 // scans.  Every value a stage computes depends on its node alone, never on a list position.
-__device__ __forceinline__ double upper_bound(double gmin, int64_t dp)
-{
-    double t;
-    if (gmin == __builtin_inf()) t = 0.0;
-    else if (gmin == -__builtin_inf()) t = 1.0;
-    else t = 0.5 * erfc(gmin / 1.41421356237309504880168872421);
-    return t >= 1.0 ? 1.0 : -expm1((double)dp * log1p(-t));
-}
-
 __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
                               int64_t cap, const int32_t* __restrict__ need, const int32_t* __restrict__ nidx,
                               BoundBufs B)
@@ -573,8 +556,9 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
         bool enter = false, cont = false;
         double x[3] = {0.0, 0.0, 0.0};
         double blo[3] = {0.0, 0.0, 0.0}, bhi[3] = {0.0, 0.0, 0.0};
+        int64_t dp = 0;
         if (live && sub_lane == 0) {
-            int64_t clo[3], chi[3], dp;
+            int64_t clo[3], chi[3];
             node_box(o, level, c, clo, chi, blo, bhi, &dp);
             if (mode == 2) {
                 // the best corner of the first pass against the best of the other points
@@ -621,7 +605,14 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
             if (enter) {
                 B.dnode[d] = b;
                 B.done[d] = 0;
-                for (int k = 0; k < 3; ++k) gx[(int64_t)d * 3 + k] = x[k];
+                B.ddp[d] = dp;
+                for (int k = 0; k < 3; ++k) {
+                    gx[(int64_t)d * 3 + k] = x[k];
+                    B.dbx[(int64_t)d * 8 + k] = blo[k];
+                    B.dbx[(int64_t)d * 8 + 3 + k] = bhi[k];
+                }
+                B.dbx[(int64_t)d * 8 + 6] = side;
+                B.dbx[(int64_t)d * 8 + 7] = best;
             }
         }
     }
@@ -666,70 +657,19 @@ __global__ void __launch_bounds__(256) k_lattice_cert(Oct o, int level, const ui
     }
 }
 
-// One projected step of the bound search at the current point x_k (posterior and its
-// gradient already evaluated).  For k >= 1 the value at x_k also enters the minimum.
-__global__ void k_descent(Oct o, int level, int k, const uint64_t* __restrict__ keys, BoundBufs B,
-                          double* __restrict__ gx)
-{
-    const int64_t nd = B.cnt[3];
-    double eta = 0.5;
-    for (int i = 0; i < k; ++i) eta *= 0.5;
-    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
-        if (B.done[d]) continue;
-        const int32_t b = B.dnode[d];
-        const double side = B.side[b];
-        const double mu = B.gp_mean[d], var = B.gp_var[d];
-        const double g = margin(side, o.theta, mu, var);
-        if (k >= 1 && g < B.gmin[b]) B.gmin[b] = g;
-        if (!(var > 0.0)) {
-            B.done[d] = 1;
-            continue;
-        }
-        int lv;
-        int64_t c[3], clo[3], chi[3], dp;
-        double blo[3], bhi[3];
-        key_coords(o, keys[B.bnode[b]], lv, c);
-        node_box(o, level, c, clo, chi, blo, bhi, &dp);
-        const double sd = sqrt(var);
-        double u[3], nrm = 0.0;
-        for (int a = 0; a < o.D; ++a) {
-            const double dsd = B.gp_dvar[d * 3 + a] / (2.0 * sd);
-            const double gr = side * (-B.gp_dmean[d * 3 + a] * sd - (o.theta - mu) * dsd) / var;
-            u[a] = (bhi[a] - blo[a]) * gr;
-            nrm += u[a] * u[a];
-        }
-        nrm = sqrt(nrm);
-        if (!(nrm > 0.0) || !isfinite(nrm)) {
-            B.done[d] = 1;
-            continue;
-        }
-        for (int a = 0; a < o.D; ++a) {
-            const double w = bhi[a] - blo[a];
-            const double xn = gx[d * 3 + a] - eta * w * u[a] / nrm;
-            gx[d * 3 + a] = xn < blo[a] ? blo[a] : (xn > bhi[a] ? bhi[a] : xn);
-        }
-    }
-}
-
-// Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)), and the decision.
-__global__ void k_bound_final(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
-                              int32_t* __restrict__ sub)
+// Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)) of eq. (upper_bound),
+// and the decision.
+__global__ void k_bound_final(BoundBufs B, double theta, double alpha, int32_t* __restrict__ sub)
 {
     const int64_t nd = B.cnt[3];
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t b = B.dnode[d];
-        double gmin = B.gmin[b];
+        const double* rec = B.dbx + d * 8;
+        double gmin = rec[7];
         if (!B.done[d]) {
-            const double g = margin(B.side[b], o.theta, B.gp_mean[d], B.gp_var[d]);
+            const double g = margin(rec[6], theta, B.gp_mean[d], B.gp_var[d]);
             if (g < gmin) gmin = g;
         }
-        const int32_t f = B.bnode[b];
-        int lv;
-        int64_t c[3], clo[3], chi[3], dp;
-        double blo[3], bhi[3];
-        key_coords(o, keys[f], lv, c);
-        node_box(o, level, c, clo, chi, blo, bhi, &dp);
-        sub[f] = upper_bound(gmin, dp) > o.alpha ? 1 : 0;
+        sub[B.bnode[B.dnode[d]]] = upper_bound(gmin, B.ddp[d]) > alpha ? 1 : 0;
     }
 }
 
@@ -1663,7 +1603,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
+    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound (o_cop, o_cw also for the descent certificate)
     size_t o_dpts, o_dbox, o_dcert, o_lnode3;   // search: certificate between the lattice passes
@@ -1736,6 +1676,8 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_cvar = take(8 * capF);
     L.o_lnode = take(4 * capF);
     L.o_dnode = take(4 * capF);
+    L.o_dbx = take(64 * capF);
+    L.o_ddp = take(8 * capF);
     L.o_gx = take(24 * capF);
     L.o_side = take(8 * capF);
     L.o_gmin = take(8 * capF);
@@ -1859,6 +1801,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.lnode2 = (int32_t*)P(L.o_lnode2);
     B.bidx = (int32_t*)P(L.o_bidx);
     B.dnode = (int32_t*)P(L.o_dnode);
+    B.dbx = (double*)P(L.o_dbx);
+    B.ddp = (int64_t*)P(L.o_ddp);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
     B.gmin = (double*)P(L.o_gmin);
@@ -2033,18 +1977,33 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             } else {
                 if ((e = lattice_pass(B.lnode, B.cnt + 1, all, 0)) != hipSuccess) return e;
             }
-            // stage 3: projected-gradient steps
+            // stage 3: projected-gradient steps, each in the epilogue of its probe (value and
+            // gradient columns), then the value at the last point and the decision
             for (int k = 0; k < A.descent_steps; ++k) {
-                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, B.gp_dmean, B.gp_dvar, 4);
-                if (e != hipSuccess) return e;
-                StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_descent, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, k, kin, B, gx);
+                PostTask t{};
+                t.mode = COL_POINTS;
+                t.group = 4;
+                t.count = B.cnt + 3;
+                t.n_points = cap;
+                t.pts = gx;
+                t.pstride = 3;
+                t.mean = B.gp_mean;
+                t.var = B.gp_var;
+                t.dmean = B.gp_dmean;
+                t.dvar = B.gp_dvar;
+                t.stage = ST_BOUND;
+                t.epi = EPI_STEP;
+                t.epi_step = k;
+                t.theta = theta;
+                t.cand_done = B.done;
+                t.cand_rec = B.dbx;
+                if ((e = launch_posterior(M, LCP_FP64, t, s)) != hipSuccess) return e;
             }
             if (A.descent_steps > 0) {
                 e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
                 if (e != hipSuccess) return e;
                 StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, B, sub);
+                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, B, theta, A.alpha, sub);
             }
         }
         StageScope sc(s, ST_OCTREE);

@@ -109,6 +109,72 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Region search (Sec. 5.1) in the epilogue of the group-4 probes, wave 0 of a binary64 tile.
+// The lane of a candidate's value column gathers its three derivative columns from the next
+// lanes.  The value enters g_min from the second step on; then one projected gradient step of
+// g = side (theta - mu) / sigma, of length eta = 2^-(k+1) times the box width along the
+// normalised direction u_a = w_a dg/dx_a, clamped to the node box.  A zero variance or a zero
+// or non-finite direction ends the candidate's descent.
+__device__ __forceinline__ void search_step(const KArgs& A, int64_t d, int comp, double dot, double mc, bool live)
+{
+    const PostTask& T = A.t;
+    const int lane = threadIdx.x & 63;
+    double dm[3], dv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dm[a] = __shfl(mc, lane + 1 + a, 64);
+        dv[a] = -2.0 * __shfl(dot, lane + 1 + a, 64);
+    }
+    if (!live || comp != 0) return;
+    // one round of independent loads: the candidate's record, flag and point
+    double* rec = T.cand_rec + d * 8;
+    const double2 r01 = *(const double2*)(rec + 0), r23 = *(const double2*)(rec + 2);
+    const double2 r45 = *(const double2*)(rec + 4), r67 = *(const double2*)(rec + 6);
+    const int done = T.cand_done[d];
+    double* x = (double*)T.pts + d * T.pstride;
+    const double x0 = x[0], x1 = x[1], x2 = x[2];
+    if (done) return;
+    const double lo[3] = {r01.x, r01.y, r23.x}, hi[3] = {r23.y, r45.x, r45.y};
+    const double xs[3] = {x0, x1, x2};
+    const double side = r67.x;
+    const double mu = mc;
+    const double vr = A.kp.s2 - dot;
+    const double var = vr > 0.0 ? vr : 0.0;
+    const double g = margin(side, T.theta, mu, var);
+    if (T.epi_step >= 1 && g < r67.y) rec[7] = g;
+    if (!(var > 0.0)) {
+        T.cand_done[d] = 1;
+        return;
+    }
+    const int dim = A.kp.dim;
+    const double sd = sqrt(var);
+    double u[3] = {0.0, 0.0, 0.0}, nrm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < dim) {
+            const double dsd = dv[a] / (2.0 * sd);
+            const double gr = side * (-dm[a] * sd - (T.theta - mu) * dsd) / var;
+            u[a] = (hi[a] - lo[a]) * gr;
+            nrm += u[a] * u[a];
+        }
+    }
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite(nrm)) {
+        T.cand_done[d] = 1;
+        return;
+    }
+    double eta = 0.5;
+    for (int i = 0; i < T.epi_step; ++i) eta *= 0.5;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < dim) {
+            const double w = hi[a] - lo[a];
+            const double xn = xs[a] - eta * w * u[a] / nrm;
+            x[a] = xn < lo[a] ? lo[a] : (xn > hi[a] ? hi[a] : xn);
+        }
+    }
+}
+
 // Tiles t_first, t_first + t_stride, ... (below t_limit and the column count) of one model.
 template <class P, int NT, int G, int NW>
 __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int64_t t_stride, int64_t t_limit)
@@ -451,21 +517,27 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
             if (gl == 0) red[wave * NT + 16 * ct + cl] = s;
         }
         __syncthreads();
-        if (tid < NT) {
-            double dot = 0.0;
-            for (int w = 0; w < kWaves; ++w) dot += red[w * NT + tid];
+        if (tid < 64) {   // wave 0: lane c < NT holds column col0 + c
+            double dot = 0.0, mc = 0.0;
             const int64_t col = col0 + tid;
             const int64_t p = col / G;
             const int comp = (int)(col % G);
-            if (p < npts) {
-                if (comp == 0) {
-                    T.mean[p] = mucol[tid];
-                    double v = A.kp.s2 - dot;
-                    T.var[p] = v > 0.0 ? v : 0.0;
-                } else if (comp - 1 < dim) {
-                    T.dmean[p * 3 + comp - 1] = mucol[tid];
-                    T.dvar[p * 3 + comp - 1] = -2.0 * dot;
+            if (tid < NT) {
+                for (int w = 0; w < kWaves; ++w) dot += red[w * NT + tid];
+                mc = mucol[tid];
+                if (p < npts) {
+                    if (comp == 0) {
+                        T.mean[p] = mc;
+                        double v = A.kp.s2 - dot;
+                        T.var[p] = v > 0.0 ? v : 0.0;
+                    } else if (comp - 1 < dim) {
+                        T.dmean[p * 3 + comp - 1] = mc;
+                        T.dvar[p * 3 + comp - 1] = -2.0 * dot;
+                    }
                 }
+            }
+            if constexpr (std::is_same<P, P64>::value && G == 4) {
+                if (T.epi == EPI_STEP) search_step(A, p, comp, dot, mc, tid < NT && p < npts);
             }
         }
     }

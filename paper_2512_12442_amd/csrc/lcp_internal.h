@@ -93,6 +93,27 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total)
     return ex;
 }
 
+// Region bound (Sec. 5.1): the node's margin g = side (theta - mu) / sigma at a point, and
+// the bound 1 - B^d = -expm1(d log1p(-t)), t = Phi(-g_min), of eq. (upper_bound) over the
+// node's d grid points.
+__device__ __forceinline__ double margin(double side, double theta, double mu, double var)
+{
+    double num = side * (theta - mu);
+    if (var > 0.0) return num / sqrt(var);
+    if (num > 0.0) return __builtin_inf();
+    if (num < 0.0) return -__builtin_inf();
+    return 0.0;
+}
+
+__device__ __forceinline__ double upper_bound(double gmin, int64_t dp)
+{
+    double t;
+    if (gmin == __builtin_inf()) t = 0.0;
+    else if (gmin == -__builtin_inf()) t = 1.0;
+    else t = 0.5 * erfc(gmin / 1.41421356237309504880168872421);
+    return t >= 1.0 ? 1.0 : -expm1((double)dp * log1p(-t));
+}
+
 // e^x for x <= 0 in binary64: Cody-Waite reduction x = n ln2 + r (ln2 split so that n * hi
 // is exact for |n| < 2^21), |r| <= ln2 / 2, then the degree-12 Taylor polynomial of e^r
 // (truncation below 2e-16 relative) and the exact scaling by 2^n; x < -745 gives 0.
@@ -218,7 +239,17 @@ struct PostTask {
     int stage;                // stage-timer stage of this launch
     int64_t vld;              // > 0: V column-major instead, column p at p * vld (vld >= m_pad)
     int dense;                // 1: the operand is a full (not lower-triangular) m_pad x m_pad matrix
+    // Region-search epilogue of the binary64 group-4 probes of descent candidates (COL_POINTS,
+    // the points are the candidates' current positions): EPI_STEP runs projected gradient step
+    // epi_step of each candidate and updates its point in place.
+    int epi;
+    int epi_step;
+    double theta;
+    int32_t* cand_done;         // per candidate: 1 = the descent stopped
+    double* cand_rec;           // per candidate: node box lo[3], hi[3], side, minimum of g so far
 };
+
+enum { EPI_NONE = 0, EPI_STEP = 1 };
 
 struct Model;  // defined below
 
