@@ -195,6 +195,7 @@ struct BoundBufs {
     int32_t* dnode;     // stage-3 node -> stage-1 node
     double* dbx;        // per stage-3 node: box lo[3], hi[3], side, g_min so far (64 B)
     int64_t* ddp;       //   and its grid points
+    int32_t* fcand;     // search: per frontier node, its stage-3 index or -1 (the emit count decides it)
     int32_t* done;
     double* gp_mean;    // posterior (and gradient) at the stage-3 points
     double* gp_var;
@@ -272,6 +273,7 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
             sub[f] = (pth == 0 || pth == 3) ? 1 : 0;
             if (direct) {
                 B.bnode[f] = (int32_t)f;
+                B.fcand[f] = -1;
                 for (int d = 0; d < 3; ++d) B.cpts[f * 3 + d] = d < o.D ? 0.5 * (blo[d] + bhi[d]) : 0.0;
             }
         }
@@ -606,6 +608,7 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
                 B.dnode[d] = b;
                 B.done[d] = 0;
                 B.ddp[d] = dp;
+                B.fcand[f] = d;
                 for (int k = 0; k < 3; ++k) {
                     gx[(int64_t)d * 3 + k] = x[k];
                     B.dbx[(int64_t)d * 8 + k] = blo[k];
@@ -657,22 +660,6 @@ __global__ void __launch_bounds__(256) k_lattice_cert(Oct o, int level, const ui
     }
 }
 
-// Value at the last point, the bound 1 - B^d = -expm1(d log1p(-t)) of eq. (upper_bound),
-// and the decision.
-__global__ void k_bound_final(BoundBufs B, double theta, double alpha, int32_t* __restrict__ sub)
-{
-    const int64_t nd = B.cnt[3];
-    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
-        const double* rec = B.dbx + d * 8;
-        double gmin = rec[7];
-        if (!B.done[d]) {
-            const double g = margin(rec[6], theta, B.gp_mean[d], B.gp_var[d]);
-            if (g < gmin) gmin = g;
-        }
-        sub[B.bnode[B.dnode[d]]] = upper_bound(gmin, B.ddp[d]) > alpha ? 1 : 0;
-    }
-}
-
 // Number of keys a node emits: its in-domain children, or itself as a leaf (0 unless sb).
 __device__ __forceinline__ int emit_count(const Oct& o, int level, uint64_t key, int sb)
 {
@@ -699,13 +686,30 @@ __device__ __forceinline__ int emit_count(const Oct& o, int level, uint64_t key,
 }
 
 // Emit counts of the frontier.
+// Emit counts of the frontier.  With the search's descent (fin set), a node that has a
+// descent candidate is decided here first: the value at the last point enters g_min, and
+// the node is subdivided when the bound 1 - B^d = -expm1(d log1p(-t)) of eq. (upper_bound)
+// exceeds alpha.
 __global__ void k_emit_count(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
-                             int64_t cap, const int32_t* __restrict__ sub, int32_t* __restrict__ cnt)
+                             int64_t cap, int32_t* __restrict__ sub, int32_t* __restrict__ cnt, BoundBufs B, int fin)
 {
     int64_t nf = *nf_dev;
     if (nf > cap) nf = cap;
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x)
-        cnt[f] = emit_count(o, level, keys[f], sub[f]);
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+        int32_t sb = sub[f];
+        const int32_t d = fin ? B.fcand[f] : -1;
+        if (d >= 0) {
+            const double* rec = B.dbx + (int64_t)d * 8;
+            double gmin = rec[7];
+            if (!B.done[d]) {
+                const double g = margin(rec[6], o.theta, B.gp_mean[d], B.gp_var[d]);
+                if (g < gmin) gmin = g;
+            }
+            sb = upper_bound(gmin, B.ddp[d]) > o.alpha ? 1 : 0;
+            sub[f] = sb;
+        }
+        cnt[f] = emit_count(o, level, keys[f], sb);
+    }
 }
 
 __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
@@ -1603,7 +1607,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
+    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_fcand, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound (o_cop, o_cw also for the descent certificate)
     size_t o_dpts, o_dbox, o_dcert, o_lnode3;   // search: certificate between the lattice passes
@@ -1678,6 +1682,7 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_dnode = take(4 * capF);
     L.o_dbx = take(64 * capF);
     L.o_ddp = take(8 * capF);
+    L.o_fcand = take(4 * capF);
     L.o_gx = take(24 * capF);
     L.o_side = take(8 * capF);
     L.o_gmin = take(8 * capF);
@@ -1803,6 +1808,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.dnode = (int32_t*)P(L.o_dnode);
     B.dbx = (double*)P(L.o_dbx);
     B.ddp = (int64_t*)P(L.o_ddp);
+    B.fcand = (int32_t*)P(L.o_fcand);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
     B.gmin = (double*)P(L.o_gmin);
@@ -1999,16 +2005,14 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 t.cand_rec = B.dbx;
                 if ((e = launch_posterior(M, LCP_FP64, t, s)) != hipSuccess) return e;
             }
-            if (A.descent_steps > 0) {
-                e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1);
-                if (e != hipSuccess) return e;
-                StageScope sc(s, ST_OCTREE);
-                hipLaunchKernelGGL(k_bound_final, dim3(gsz(cap, 256)), dim3(256), 0, s, B, theta, A.alpha, sub);
-            }
+            // the value at the last point; the emit count takes the decision
+            if (A.descent_steps > 0 && (e = post(B.cnt + 3, cap, gx, B.gp_mean, B.gp_var, nullptr, nullptr, 1)) != hipSuccess)
+                return e;
         }
         StageScope sc(s, ST_OCTREE);
         int64_t* nout = (l == Ldepth) ? n_leaves : cnt + l + 1;
-        hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt);
+        const int fin = search && bounded && A.descent_steps > 0;   // candidates' decisions pending
+        hipLaunchKernelGGL(k_emit_count, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, ecnt, B, fin);
         e = launch_scan(ecnt, eoff, cap, nf, nout, scanws, s);
         if (e != hipSuccess) return e;
         uint64_t* dst = (l == Ldepth) ? leaves : kout;
