@@ -246,19 +246,21 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
         if (level == o.Ldepth && !o.bound_at_max) {
             pth = 3;
         } else {
+            // Observation rows are zero padded beyond the dimension and so is the node box, so
+            // the three closed-interval tests hold for every axis; no branch per observation,
+            // and each lane's loads are independent of the previous iteration.
             int nin = 0;
             double p1 = -1.0, p2 = -1.0;
+#pragma unroll 4
             for (int i = lane; i < m; i += 64) {
-                bool in = true;
-                for (int d = 0; d < o.D; ++d) {
-                    double xi = X[i * 4 + d];
-                    in = in && (xi >= blo[d] && xi <= bhi[d]);
-                }
-                if (in) {
-                    ++nin;
-                    p1 = fmax(p1, qlo[i]);
-                    p2 = fmax(p2, qhi[i]);
-                }
+                const double2 x01 = *(const double2*)(X + (int64_t)i * 4);
+                const double x2 = X[(int64_t)i * 4 + 2];
+                const double ql = qlo[i], qh = qhi[i];
+                const bool in = (x01.x >= blo[0]) & (x01.x <= bhi[0]) & (x01.y >= blo[1]) & (x01.y <= bhi[1]) &
+                                (x2 >= blo[2]) & (x2 <= bhi[2]);
+                nin += in ? 1 : 0;
+                p1 = in ? fmax(p1, ql) : p1;
+                p2 = in ? fmax(p2, qh) : p2;
             }
             nin = wave_isum(nin);
             p1 = wave_max(p1);
