@@ -163,10 +163,13 @@ __global__ void k_obs_q(const double* __restrict__ mu, const double* __restrict_
     }
 }
 
-__global__ void k_root(uint64_t* keys, int64_t* cnt)
+__global__ void k_root(uint64_t* keys, int64_t* cnt, int32_t* sp_cnt)
 {
-    keys[0] = 0;
-    *cnt = 1;
+    if (threadIdx.x == 0) {
+        keys[0] = 0;
+        *cnt = 1;
+    }
+    for (int i = threadIdx.x; i < kSplitGrid; i += blockDim.x) sp_cnt[i] = 0;   // shared-tile counters
 }
 
 // Preliminary decision of Alg. 1 for every frontier node (one wave per node).
@@ -1609,7 +1612,7 @@ struct AdaptLayout {
     size_t total;
     size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
-    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_fcand, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
+    size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_fcand, o_spp, o_spc, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
     size_t o_cop, o_cw, o_box, o_cert;   // certified bound (o_cop, o_cw also for the descent certificate)
     size_t o_dpts, o_dbox, o_dcert, o_lnode3;   // search: certificate between the lattice passes
@@ -1685,6 +1688,8 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_dbx = take(64 * capF);
     L.o_ddp = take(8 * capF);
     L.o_fcand = take(4 * capF);
+    L.o_spp = take(8 * (size_t)kSplitGrid * 64);
+    L.o_spc = take(4 * (size_t)kSplitGrid);
     L.o_gx = take(24 * capF);
     L.o_side = take(8 * capF);
     L.o_gmin = take(8 * capF);
@@ -1811,6 +1816,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.dbx = (double*)P(L.o_dbx);
     B.ddp = (int64_t*)P(L.o_ddp);
     B.fcand = (int32_t*)P(L.o_fcand);
+    double* spp = (double*)P(L.o_spp);
+    int32_t* spc = (int32_t*)P(L.o_spc);
     double* gx = (double*)P(L.o_gx);
     B.side = (double*)P(L.o_side);
     B.gmin = (double*)P(L.o_gmin);
@@ -1850,7 +1857,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_obs_q, dim3((unsigned)ceil_div(M.m, 256)), dim3(256), 0, s, M.obs_mu, M.obs_var, M.m,
                            theta, qlo, qhi);
-        hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, keys[0], cnt + 0);
+        hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, keys[0], cnt + 0, spc);
     }
     e = launch_fill_f32(lcp, 0.0f, g.nc[0] * g.nc[1] * g.nc[2], s);
     if (e != hipSuccess) return e;
@@ -1887,6 +1894,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             t.dmean = dmean;
             t.dvar = dvar;
             t.stage = ST_BOUND;
+            t.sp_part = spp;
+            t.sp_cnt = spc;
             return launch_posterior(M, LCP_FP64, t, s);
         };
         if (!bounded) {
@@ -2005,6 +2014,8 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 t.theta = theta;
                 t.cand_done = B.done;
                 t.cand_rec = B.dbx;
+                t.sp_part = spp;
+                t.sp_cnt = spc;
                 if ((e = launch_posterior(M, LCP_FP64, t, s)) != hipSuccess) return e;
             }
             // the value at the last point; the emit count takes the decision

@@ -176,7 +176,12 @@ __device__ __forceinline__ void search_step(const KArgs& A, int64_t d, int comp,
 }
 
 // Tiles t_first, t_first + t_stride, ... (below t_limit and the column count) of one model.
-template <class P, int NT, int G, int NW>
+// SPLIT (small launches of the region search, T.sp_cnt set): when the tiles are few, W = 2 or
+// 4 work-groups share a tile.  Each takes every W-th row-block pair, on its first NW / W waves
+// (so one busy wave per SIMD at W = 4), and stores its partial dot products; the last of the
+// W to arrive (one atomic per work-group on the tile's counter, which it resets) adds the W
+// partials in a fixed order and writes the outputs.  No work-group waits for another.
+template <class P, int NT, int G, int NW, bool SPLIT = false>
 __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int64_t t_stride, int64_t t_limit)
 {
     constexpr int kThreads = NW * 64;
@@ -198,6 +203,13 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
     int64_t ntiles = (ncols + NT - 1) / NT;
     if (ntiles > t_limit) ntiles = t_limit;
     const int dim = A.kp.dim;
+    int ways = 1, spart = 0;
+    if constexpr (SPLIT) {
+        ways = ntiles * 4 <= t_stride ? 4 : (ntiles * 2 <= t_stride ? 2 : 1);   // t_stride: the grid
+        spart = (int)(t_first % ways);
+        t_first /= ways;
+        t_stride /= ways;
+    }
 
     // B generation layout: thread t serves point pc = t % NP of the tile (NP = NT / G points)
     // for the rows j = t / NP + k * (256 / NP); its mean partials cover its own columns only
@@ -357,9 +369,10 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
         // ping-pong: the L^-1 fragments of group g + U are requested before group g is
         // multiplied.  Loop bounds are rounded up to 2U k-steps (m_pad is a multiple of 128,
         // so no group leaves the padded matrix; steps past the diagonal multiply zeros).
+        const int wp = wave * ways + spart;            // this wave's pair within each group
         for (int q = 0; q * 2 * NW < A.nrb; ++q) {
-            const int ra = 2 * NW * q + wave, rbb = 2 * NW * q + 2 * NW - 1 - wave;
-            if (ra >= A.nrb) continue;                 // then rbb >= nrb as well
+            const int ra = 2 * NW * q + wp, rbb = 2 * NW * q + 2 * NW - 1 - wp;
+            if (wp >= NW || ra >= A.nrb) continue;     // then rbb >= nrb as well
             const bool hasB = rbb < A.nrb;
             typename P::Acc accA[NCT], accB[NCT];
 #pragma unroll
@@ -522,8 +535,24 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
             const int64_t col = col0 + tid;
             const int64_t p = col / G;
             const int comp = (int)(col % G);
-            if (tid < NT) {
+            if (tid < NT)
                 for (int w = 0; w < kWaves; ++w) dot += red[w * NT + tid];
+            if (SPLIT && ways > 1) {
+                double* sp = T.sp_part + ((int64_t)tile * ways) * NT;
+                if (tid < NT) __hip_atomic_store(sp + spart * NT + tid, dot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+                int last = 0;
+                if (tid == 0) last = atomicAdd(T.sp_cnt + tile, 1) == ways - 1 ? 1 : 0;
+                last = __shfl(last, 0, 64);
+                if (!last) continue;                   // another work-group of this tile finishes it
+                __threadfence();
+                dot = 0.0;
+                if (tid < NT)
+                    for (int r = 0; r < ways; ++r)
+                        dot += __hip_atomic_load(sp + r * NT + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (tid == 0) T.sp_cnt[tile] = 0;
+            }
+            if (tid < NT) {
                 mc = mucol[tid];
                 if (p < npts) {
                     if (comp == 0) {
@@ -547,6 +576,13 @@ template <class P, int NT, int G, int NW>
 __global__ void __launch_bounds__(NW * 64) k_post(KArgs A)
 {
     post_tiles<P, NT, G, NW>(A, blockIdx.x, gridDim.x, INT64_MAX);
+}
+
+// Small launches of the region search: a fixed grid, tiles shared by W work-groups when few.
+template <class P, int NT, int G, int NW>
+__global__ void __launch_bounds__(NW * 64) k_post_sp(KArgs A)
+{
+    post_tiles<P, NT, G, NW, true>(A, blockIdx.x, gridDim.x, INT64_MAX);
 }
 
 // Many models in one launch: model b owns tiles tile_off[b] .. tile_off[b + 1] - 1 of the
@@ -909,6 +945,14 @@ hipError_t launch_t(const Model& M, const PostTask& t, hipStream_t s, const void
     KArgs A = kargs_of(M, t, A0, A1);
     int ldb = (P::KS == 32) ? (M.m_pad + 63) / 64 * 64 + P::LPAD : M.m_pad + P::LPAD;
     size_t lds = sizeof(typename P::Elem) * (size_t)lds_planes<P>() * NT * ldb + sizeof(double) * (NW * 64 * G + NT);
+    if (NW == 16 && t.sp_cnt) {
+        // a fixed grid of one work-group per CU; the kernel shares small tile counts among them
+        hipError_t e = hipFuncSetAttribute((const void*)k_post_sp<P, NT, G, NW>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_post_sp<P, NT, G, NW>), dim3(kSplitGrid), dim3(NW * 64), lds, s, A);
+        return hipGetLastError();
+    }
     hipError_t e = hipFuncSetAttribute((const void*)k_post<P, NT, G, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;

@@ -247,7 +247,14 @@ struct PostTask {
     double theta;
     int32_t* cand_done;         // per candidate: 1 = the descent stopped
     double* cand_rec;           // per candidate: node box lo[3], hi[3], side, minimum of g so far
+    // Small binary64 launches of the region search may share each tile among work-groups:
+    // kSplitGrid x 64 doubles of partial products and kSplitGrid tile counters (zero before
+    // the first launch; every launch leaves them zero).  Null: one work-group per tile.
+    double* sp_part;
+    int32_t* sp_cnt;
 };
+
+constexpr int kSplitGrid = 256;   // work-groups of a shared-tile launch (one per CU)
 
 enum { EPI_NONE = 0, EPI_STEP = 1 };
 
