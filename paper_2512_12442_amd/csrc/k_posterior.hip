@@ -381,6 +381,7 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
                 accB[ct] = typename P::Acc{0, 0, 0, 0};
             }
             constexpr int U = P::KS == 4 ? 4 : 2;
+            bool ra_done = false;
             const int needA = T.dense ? nks_total : (16 * (ra + 1) + P::KS - 1) / P::KS;
             const int needB = T.dense ? nks_total : (16 * (rbb + 1) + P::KS - 1) / P::KS;
             const int gA = (needA + 2 * U - 1) / (2 * U) * (2 * U);
@@ -429,11 +430,31 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
                         ld(b0, AfB, g + 2 * U);
                         mul2(g + U, a1, b1);
                     }
-                    for (int g = gA; g < gB; g += 2 * U) {     // b0 holds group g
-                        ld(b1, AfB, g + U);
-                        mul1(g, b0, accB);
-                        ld(b0, AfB, g + 2 * U);
-                        mul1(g + U, b1, accB);
+                    if constexpr (SPLIT && G == 1) {
+                        // one busy wave per SIMD: block ra is complete, so its accumulator
+                        // takes every other group of rbb's tail (two independent chains; the
+                        // group-4 kernel has no registers to spare for it)
+                        if (gA < gB) {
+                            epilogue(ra, accA);
+                            ra_done = true;
+#pragma unroll
+                            for (int ct = 0; ct < NCT; ++ct) accA[ct] = typename P::Acc{0, 0, 0, 0};
+                            for (int g = gA; g < gB; g += 2 * U) {
+                                ld(b1, AfB, g + U);
+                                mul1(g, b0, accB);
+                                ld(b0, AfB, g + 2 * U);
+                                mul1(g + U, b1, accA);
+                            }
+#pragma unroll
+                            for (int ct = 0; ct < NCT; ++ct) accB[ct] += accA[ct];
+                        }
+                    } else {
+                        for (int g = gA; g < gB; g += 2 * U) {     // b0 holds group g
+                            ld(b1, AfB, g + U);
+                            mul1(g, b0, accB);
+                            ld(b0, AfB, g + 2 * U);
+                            mul1(g + U, b1, accB);
+                        }
                     }
                 } else {
                     ld(a0, AfA, 0);
@@ -517,7 +538,7 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
                     }
                 }
             }
-            epilogue(ra, accA);
+            if (!ra_done) epilogue(ra, accA);
             if (hasB) epilogue(rbb, accB);
         }
         // ---- reduce the dot partials: rows within lane, lane groups, waves
@@ -540,12 +561,13 @@ __device__ __forceinline__ void post_tiles(const KArgs& A, int64_t t_first, int6
             if (SPLIT && ways > 1) {
                 double* sp = T.sp_part + ((int64_t)tile * ways) * NT;
                 if (tid < NT) __hip_atomic_store(sp + spart * NT + tid, dot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __threadfence();
                 int last = 0;
-                if (tid == 0) last = atomicAdd(T.sp_cnt + tile, 1) == ways - 1 ? 1 : 0;
+                // release this work-group's partials; the last arrival acquires all of them
+                if (tid == 0)
+                    last = __hip_atomic_fetch_add(T.sp_cnt + tile, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                                   ways - 1 ? 1 : 0;
                 last = __shfl(last, 0, 64);
                 if (!last) continue;                   // another work-group of this tile finishes it
-                __threadfence();
                 dot = 0.0;
                 if (tid < NT)
                     for (int r = 0; r < ways; ++r)
