@@ -142,9 +142,10 @@ size_t lcp_model_bytes(int m, int dim);
  * gp_fit_factor -- factor the GP model (Sec. 3; the inducing set of eq. (sgp) is the
  * observation set, so mu_M and A_M are the latent posterior at the observations).
  * Builds K = k(X, X) + noise I in binary64, its Cholesky factor L, the explicit
- * inverse L^-1 (binary64, plus FP32 and split-BF16 copies), a = K^-1 y, and the
+ * inverse L^-1 (binary64, plus FP32 and split-BF16 copies), a = K^-1 y, the
  * posterior mean and variance at each observation (used by the preliminary node
- * test of Alg. 1).
+ * test of Alg. 1), and K^-1 = L^-T L^-1 in the matrix-core fragment order (the
+ * operand of the certified region bound).
  *   k        (host) kernel description
  *   m        number of observations, 1 <= m <= 1024
  *   X        m x dim observation locations (device, binary64)

@@ -200,7 +200,7 @@ __global__ void k_box_centres(const double* __restrict__ box, int D, int64_t n, 
 }
 
 struct CertLayout {
-    size_t kinv, f64, f32, pts, w, mean, var, total;
+    size_t pts, w, mean, var, total;
 };
 
 CertLayout cert_layout(const Model& M, int64_t n)
@@ -209,9 +209,6 @@ CertLayout cert_layout(const Model& M, int64_t n)
     const size_t mp = (size_t)M.m_pad, nn = (size_t)(n > 0 ? n : 1);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
-    L.kinv = take(8 * mp * mp);
-    L.f64 = take(8 * mp * mp);
-    L.f32 = take(4 * mp * mp);
     L.pts = take(24 * nn);
     L.w = take(8 * mp * nn);
     L.mean = take(8 * nn);
@@ -221,18 +218,6 @@ CertLayout cert_layout(const Model& M, int64_t n)
 }
 
 }  // namespace
-
-size_t cert_operand_bytes(const Model& M) { return align256(8 * (size_t)M.m_pad * M.m_pad) * 2 +
-                                                   align256(4 * (size_t)M.m_pad * M.m_pad); }
-
-hipError_t launch_cert_operand(const Model& M, char* ws, double** F64, hipStream_t s)
-{
-    const size_t mp = (size_t)M.m_pad;
-    double* Kinv = (double*)ws;
-    *F64 = (double*)(ws + align256(8 * mp * mp));
-    float* F32 = (float*)(ws + 2 * align256(8 * mp * mp));
-    return launch_kinv_frag(M, Kinv, *F64, F32, s);
-}
 
 hipError_t launch_cert_w(const Model& M, const double* F64, const double* pts, const int64_t* count, int64_t cap,
                          double* W, double* mean, double* var, hipStream_t s)
@@ -273,9 +258,8 @@ hipError_t launch_bound_certified(const Model& M, int64_t n, const double* box, 
 {
     if (n <= 0) return hipSuccess;
     const CertLayout L = cert_layout(M, n);
-    double* F64 = nullptr;
-    hipError_t e = launch_cert_operand(M, ws, &F64, s);
-    if (e != hipSuccess) return e;
+    const double* F64 = M.Q64;   // the operand Q, formed by the fit
+    hipError_t e;
     double* pts = (double*)(ws + L.pts);
     double* W = (double*)(ws + L.w);
     {

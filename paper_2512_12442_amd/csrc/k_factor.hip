@@ -26,6 +26,8 @@ size_t model_bytes(int m)
     b += 256;                                        // info
     b += align256(sizeof(double) * (size_t)mp * mp); // A_M (sparse model)
     b += align256(sizeof(double) * mp * 4);          // Xs
+    b += align256(sizeof(double) * (size_t)mp * mp); // Q64: K^-1 (T^T T) fragments, certified bound
+    b += align256(sizeof(float) * (size_t)mp * mp);  // Q32
     return b;
 }
 
@@ -617,6 +619,8 @@ static void carve(Model& M, char* base)
     M.info = (int*)take(256);
     M.AM = (double*)take(sizeof(double) * (size_t)mp * mp);
     M.Xs = (double*)take(sizeof(double) * mp * 4);
+    M.Q64 = (double*)take(sizeof(double) * (size_t)mp * mp);
+    M.Q32 = (float*)take(sizeof(float) * (size_t)mp * mp);
 }
 
 static double* ybuf(const Model& M)
@@ -665,7 +669,9 @@ hipError_t launch_factor_finish(Model& M, hipStream_t s)
     t.pstride = 4;
     t.mean = M.obs_mu;
     t.var = M.obs_var;
-    return launch_posterior(M, LCP_FP64, t, s);
+    e = launch_posterior(M, LCP_FP64, t, s);
+    if (e != hipSuccess) return e;
+    return launch_kinv_frag(M, M.U, M.Q64, M.Q32, s);   // U (L^T) is free now
 }
 
 // Sparse model, after launch_factor (K_MM + jitter I, mu_M in place of y) succeeded:
@@ -713,7 +719,9 @@ hipError_t launch_sparse_finish(Model& M, hipStream_t s)
     hipLaunchKernelGGL(k_amax, dim3(1), dim3(1024), 0, s, M.Linv, mp, M.amax);
     hipLaunchKernelGGL(k_frag, dim3((unsigned)ceil_div(n2, 256)), dim3(256), 0, s, M.Linv, mp, M.A64, M.A32,
                        M.Ahi, M.Alo, M.Hhi, M.Hlo, M.amax);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_kinv_frag(M, M.U, M.Q64, M.Q32, s);   // Q = T^T T; U (a copy of T) is free now
 }
 
 // Descriptors, one 64 x 64 diagonal-block inverse per model, then the statuses (last).

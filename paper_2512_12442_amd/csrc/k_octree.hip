@@ -1614,7 +1614,7 @@ struct AdaptLayout {
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
     size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_fcand, o_spp, o_spc, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
-    size_t o_cop, o_cw, o_box, o_cert;   // certified bound (o_cop, o_cw also for the descent certificate)
+    size_t o_cw, o_box, o_cert;          // certified bound (o_cw also for the certificate between the lattice passes)
     size_t o_dpts, o_dbox, o_dcert, o_lnode3;   // search: certificate between the lattice passes
     int lcert;                           // 1: the search has a level that runs it
     size_t o_loc, o_lnext;               // local-model bound only: per-work-group slots, work counter
@@ -1726,7 +1726,6 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     }
     if (bound_kind == LCP_BOUND_SEARCH && !kd && capF >= kLatticeCert) {
         L.lcert = 1;
-        L.o_cop = take(cert_operand_bytes(M));
         L.o_cw = take(8 * (size_t)M.m_pad * capF);
         L.o_dpts = take(24 * (size_t)capF);
         L.o_dbox = take(8 * 2 * (size_t)D * capF);
@@ -1734,7 +1733,6 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
         L.o_lnode3 = take(4 * (size_t)capF);
     }
     if (bound_kind == LCP_BOUND_CERTIFIED) {
-        L.o_cop = take(cert_operand_bytes(M));
         L.o_cw = take(8 * (size_t)M.m_pad * capF);
         L.o_box = take(8 * 2 * (size_t)D * capF);
         L.o_cert = take(32 * (size_t)capF);
@@ -1839,11 +1837,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     B.lnode3 = L.lcert ? (int32_t*)P(L.o_lnode3) : nullptr;
 
     hipError_t e;
-    double* certF64 = nullptr;
-    if (cert) {
-        e = launch_cert_operand(M, (char*)P(L.o_cop), &certF64, s);
-        if (e != hipSuccess) return e;
-    }
+    const double* certF64 = M.Q64;   // the certified bound's operand Q, formed by the fit
     {
         int64_t acc = 0;
         for (int l = 0; l < 24; ++l) {
@@ -1979,7 +1973,6 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (ccert) {
                     // w = Q k(c), box moments, decision: settled nodes skip the rest of the lattice
                     // and the descent
-                    if (!certF64 && (e = launch_cert_operand(M, (char*)P(L.o_cop), &certF64, s)) != hipSuccess) return e;
                     if ((e = launch_cert_w(M, certF64, B.dpts, B.cnt + 4, cap, certW, B.cmean, B.cvar, s)) != hipSuccess)
                         return e;
                     if ((e = launch_cert(M, B.dbox, B.cnt + 4, cap, certW, B.dcert, s)) != hipSuccess) return e;

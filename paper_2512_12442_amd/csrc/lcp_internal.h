@@ -351,6 +351,8 @@ struct Model {
     _Float16* Hhi;    // (Linv * sA) split into FP16 halves, 16x16x32 fragment order
     _Float16* Hlo;
     double* amax;     // [0] max |Linv|, [1] sA (power of two), device
+    double* Q64;      // Q = L^-T L^-1 (T^T T for a sparse model) in 16x16x4 fragment order, binary64,
+    float* Q32;       //   and binary32: the certified bound's operand, formed by the single-model fits
     double* obs_mu;   // m
     double* obs_var;  // m
     double* AM;       // sparse model: A_M (m_pad x m_pad, zero padded), kept for local models
@@ -376,12 +378,9 @@ hipError_t launch_lcp_backward(const Model& M, const GridP& g, double theta, int
                                const double* gl, double* dy, double* dlogell, char* ws, hipStream_t s);
 // K^-1 = Linv^T Linv (row-major) and its 16 x 16 x 4 fragment copies (binary64, binary32).
 hipError_t launch_kinv_frag(const Model& M, double* Kinv, double* F64, float* F32, hipStream_t s);
-// Certified region bound (k_bound.hip).  The operand Q = Linv^T Linv in fragment order
-// (cert_operand_bytes of ws; *F64 receives its binary64 copy); w = Q k(c) for box centres
-// (3 doubles per point, device count or cap), W column b at b * m_pad; then per box
-// (lo[dim], hi[dim]) the bounds mu(c), mu_lo, mu_hi, var_hi.
-size_t cert_operand_bytes(const Model& M);
-hipError_t launch_cert_operand(const Model& M, char* ws, double** F64, hipStream_t s);
+// Certified region bound (k_bound.hip).  w = Q k(c) for box centres against the model's operand
+// Q (Model::Q64, F64 below), 3 doubles per point, device count or cap, W column b at
+// b * m_pad; then per box (lo[dim], hi[dim]) the bounds mu(c), mu_lo, mu_hi, var_hi.
 hipError_t launch_cert_w(const Model& M, const double* F64, const double* pts, const int64_t* count, int64_t cap,
                          double* W, double* mean, double* var, hipStream_t s);
 hipError_t launch_cert(const Model& M, const double* box, const int64_t* count, int64_t cap, const double* W,
