@@ -12,7 +12,11 @@
 // In k_post, row blocks of 16 are dealt to the four waves in a balanced (snake) order; the
 // 16-bit split value columns run in k_post_ps (below).  In both, every column's result
 // depends only on that column, so a vertex gets bitwise the same numbers whatever tile or
-// launch it is computed in.
+// launch it is computed in.  k_post_sp (the region search's small binary64 launches) may
+// share a tile among 2 or 4 work-groups and add their partial dot products in a fixed order:
+// its results depend on the launch's tile count as well, and are the same on every run.
+// The group-4 launches of the search also take each candidate's descent step in their
+// epilogue (search_step).
 #include <vector>
 
 #include "lcp_internal.h"
