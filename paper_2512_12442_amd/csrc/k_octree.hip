@@ -294,6 +294,10 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
 // The search's stage-1 list is the frontier; each stage's decision kernel appends the nodes
 // it leaves open to the next stage's list (block_claim), so the lists are built without
 // scans.  Every value a stage computes depends on its node alone, never on a list position.
+// Large levels take the lattice's corners first, and at the largest octree levels the
+// certified box bound (k_lattice_cert) settles nodes between the two lattice passes.  The
+// descent steps run in the epilogue of their binary64 probes, and the emit count takes the
+// decision of the nodes that reached the descent.
 __global__ void k_bound_setup(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
                               int64_t cap, const int32_t* __restrict__ need, const int32_t* __restrict__ nidx,
                               BoundBufs B)
