@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(512) k_lattice_own(Oct o, int level, const uin
 __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_t* __restrict__ keys, BoundBufs B,
                                                   int32_t* __restrict__ sub, double* __restrict__ gx,
                                                   const int32_t* __restrict__ list, const int64_t* __restrict__ n_list,
-                                                  uint32_t pmask, int mode, int csave)
+                                                  uint32_t pmask, int mode, int csave, int cvals)
 {
     const int64_t nl = *n_list;
     if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) B.cnt[2] = 0;   // the second pass's point slots
@@ -534,6 +534,8 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
         int64_t c[3] = {0, 0, 0};
         double gv = __builtin_inf(), side = 1.0, mu = 0.0, var = 0.0;
         const bool in_mask = sub_lane < npt && ((pmask >> sub_lane) & 1);
+        // cvals: the centre (point (npt - 1) / 2) is not in pmask; its value is stage 1's
+        const bool from_centre = cvals && sub_lane == (npt - 1) / 2;
         if (live) {
             b = list[l];
             f = B.bnode[b];
@@ -546,13 +548,16 @@ __global__ void __launch_bounds__(512) k_lattice(Oct o, int level, const uint64_
                 const int64_t slot = B.loff[ol] + __builtin_popcount(B.lmask[ol] & ((1 << oi) - 1));
                 mu = B.lat_mean[slot];
                 var = B.lat_var[slot];
+            } else if (from_centre) {
+                mu = B.cmean[b];
+                var = B.cvar[b];
             }
         }
         // stage 1 skipped: a node without observations takes its side from the centre point
         // (digits 1 on every axis: point (npt - 1) / 2), as stage 1 would
         const double mc = __shfl(mu, (threadIdx.x & 32) + (npt - 1) / 2, 64);
         if (mode == 0 && side == 0.0) side = mc < o.theta ? 1.0 : -1.0;
-        if (live && in_mask) gv = margin(side, o.theta, mu, var);
+        if (live && (in_mask || from_centre)) gv = margin(side, o.theta, mu, var);
         // minimum over the 32 lanes of the node, lowest point index on ties
         double best = gv;
         int ib = sub_lane;
@@ -1957,6 +1962,9 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
             const bool cfirst = centre && cap >= kCornersFirst;
             // the certified bound between the passes (octree levels of at least kLatticeCert nodes)
             const bool ccert = cfirst && L.lcert && cap >= kLatticeCert;
+            // after a centre stage the lattice reuses the centres' values (stage 1) instead of
+            // evaluating that point again
+            const uint32_t ctr = centre ? 1u << ((npt - 1) / 2) : 0u;
             auto lattice_pass = [&](const int32_t* list, int64_t* n_list, uint32_t pmask, int mode) {
                 {
                     StageScope sc(s, ST_OCTREE);
@@ -1967,7 +1975,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (r != hipSuccess) return r;
                 StageScope sc(s, ST_OCTREE);
                 hipLaunchKernelGGL(k_lattice, dim3(gsz(cap * 32, 512)), dim3(512), 0, s, o, l, kin, B, sub, gx, list,
-                                   n_list, pmask, mode, (int)(ccert && mode == 1));
+                                   n_list, pmask, mode, (int)(ccert && mode == 1), (int)(centre && mode != 1));
                 return hipGetLastError();
             };
             if (cfirst) {
@@ -1977,7 +1985,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                 if (ccert) {
                     // w = Q k(c), box moments, decision: settled nodes skip the rest of the lattice
                     // and the descent
-                    if ((e = launch_cert_w(M, certF64, B.dpts, B.cnt + 4, cap, certW, B.cmean, B.cvar, s)) != hipSuccess)
+                    if ((e = launch_cert_w(M, certF64, B.dpts, B.cnt + 4, cap, certW, B.gp_mean, B.gp_var, s)) != hipSuccess)
                         return e;
                     if ((e = launch_cert(M, B.dbox, B.cnt + 4, cap, certW, B.dcert, s)) != hipSuccess) return e;
                     {
@@ -1987,9 +1995,9 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
                     list2 = B.lnode3;
                     n2 = B.cnt + 5;
                 }
-                if ((e = lattice_pass(list2, n2, all & ~corners, 2)) != hipSuccess) return e;
+                if ((e = lattice_pass(list2, n2, all & ~corners & ~ctr, 2)) != hipSuccess) return e;
             } else {
-                if ((e = lattice_pass(B.lnode, B.cnt + 1, all, 0)) != hipSuccess) return e;
+                if ((e = lattice_pass(B.lnode, B.cnt + 1, all & ~ctr, 0)) != hipSuccess) return e;
             }
             // stage 3: projected-gradient steps, each in the epilogue of its probe (value and
             // gradient columns), then the value at the last point and the decision
