@@ -163,11 +163,12 @@ __global__ void k_obs_q(const double* __restrict__ mu, const double* __restrict_
     }
 }
 
-__global__ void k_root(uint64_t* keys, int64_t* cnt, int32_t* sp_cnt)
+__global__ void k_root(uint64_t* keys, int64_t* cnt, int32_t* sp_cnt, uint8_t* hob)
 {
     if (threadIdx.x == 0) {
         keys[0] = 0;
         *cnt = 1;
+        hob[0] = 1;   // the root may hold observations
     }
     for (int i = threadIdx.x; i < kSplitGrid; i += blockDim.x) sp_cnt[i] = 0;   // shared-tile counters
 }
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
                                                 const double* __restrict__ X, int m, const double* __restrict__ qlo,
                                                 const double* __restrict__ qhi, int32_t* __restrict__ path,
                                                 int32_t* __restrict__ need, int32_t* __restrict__ sub, BoundBufs B,
-                                                int direct)
+                                                int direct, const uint8_t* __restrict__ hob)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -254,8 +255,11 @@ __global__ void __launch_bounds__(256) k_prelim(Oct o, int level, const uint64_t
             // and each lane's loads are independent of the previous iteration.
             int nin = 0;
             double p1 = -1.0, p2 = -1.0;
+            // a node's closed box lies in its parent's, so a parent without observations has
+            // children without them (hob: the parent held some)
+            const int mm = hob[f] ? m : 0;
 #pragma unroll 4
-            for (int i = lane; i < m; i += 64) {
+            for (int i = lane; i < mm; i += 64) {
                 const double2 x01 = *(const double2*)(X + (int64_t)i * 4);
                 const double x2 = X[(int64_t)i * 4 + 2];
                 const double ql = qlo[i], qh = qhi[i];
@@ -728,7 +732,8 @@ __global__ void k_emit_count(Oct o, int level, const uint64_t* __restrict__ keys
 
 __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, const int64_t* __restrict__ nf_dev,
                        int64_t cap, const int32_t* __restrict__ sub, const int32_t* __restrict__ off,
-                       uint64_t* __restrict__ out, int64_t out_cap, uint8_t* __restrict__ stat)
+                       uint64_t* __restrict__ out, int64_t out_cap, uint8_t* __restrict__ stat,
+                       const int32_t* __restrict__ path, uint8_t* __restrict__ hob_out)
 {
     int64_t nf = *nf_dev;
     if (nf > cap) nf = cap;
@@ -740,6 +745,7 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
         stat[c[0] + nl[0] * (c[1] + nl[1] * c[2])] = sub[f] ? 2 : 1;
         if (!sub[f]) continue;
         int64_t pos = off[f];
+        const uint8_t obs = path[f] != 4 ? 1 : 0;     // path 4: no observation in the node
         if (level == o.Ldepth) {
             // leaves keep the octree key of the finest level (the K-D code at depth D Lmax is
             // the same Morton code)
@@ -753,7 +759,10 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
                 const int64_t ca = 2 * pick3(c, a) + i;
                 const int64_t cc[3] = {a == 0 ? ca : c[0], a == 1 ? ca : c[1], a == 2 ? ca : c[2]};
                 if (ca * hs >= pick3(o.g.nc, a)) continue;
-                if (pos < out_cap) out[pos] = make_key(o, level + 1, cc);
+                if (pos < out_cap) {
+                    out[pos] = make_key(o, level + 1, cc);
+                    hob_out[pos] = obs;
+                }
                 ++pos;
             }
             continue;
@@ -770,7 +779,10 @@ __global__ void k_emit(Oct o, int level, const uint64_t* __restrict__ keys, cons
                 }
             }
             if (!ok) continue;
-            if (pos < out_cap) out[pos] = make_key(o, level + 1, cc);
+            if (pos < out_cap) {
+                out[pos] = make_key(o, level + 1, cc);
+                hob_out[pos] = obs;
+            }
             ++pos;
         }
     }
@@ -1619,7 +1631,7 @@ constexpr int64_t kLatticeCert = 32768;
 
 struct AdaptLayout {
     size_t total;
-    size_t o_q, o_cnt, o_keys0, o_keys1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
+    size_t o_q, o_cnt, o_keys0, o_keys1, o_hob0, o_hob1, o_path, o_need, o_nidx, o_sub, o_ecnt, o_eoff, o_ub;
     size_t o_bnode, o_side, o_gmin, o_done, o_latp, o_latm, o_latv, o_gm, o_gv, o_gdm, o_gdv;
     size_t o_cpts, o_cmean, o_cvar, o_lnode, o_dnode, o_dbx, o_ddp, o_fcand, o_spp, o_spc, o_gx, o_ngrid, o_lmask, o_loff, o_lown, o_lnode2, o_bidx;
     size_t o_stat, o_statoff, o_scan, o_vmask, o_voff, o_slot, o_vlist, o_vmean, o_vvar, o_V, o_cross, o_zb, o_cellws;
@@ -1681,6 +1693,8 @@ static AdaptLayout adapt_layout(const Model& M, const GridP& g, int64_t S0, int 
     L.o_cnt = take(sizeof(int64_t) * 64);
     L.o_keys0 = take(8 * capF);
     L.o_keys1 = take(8 * capF);
+    L.o_hob0 = take((size_t)capF);
+    L.o_hob1 = take((size_t)capF);
     L.o_path = take(4 * capF);
     L.o_need = take(4 * capF);
     L.o_nidx = take(4 * capF);
@@ -1799,6 +1813,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
     double* qhi = qlo + M.m_pad;
     int64_t* cnt = (int64_t*)P(L.o_cnt);   // [0..22] frontier counts, [32..35] bound stages, [40] vertices
     uint64_t* keys[2] = {(uint64_t*)P(L.o_keys0), (uint64_t*)P(L.o_keys1)};
+    uint8_t* hob[2] = {(uint8_t*)P(L.o_hob0), (uint8_t*)P(L.o_hob1)};   // per frontier node: parent held observations
     int32_t* path = (int32_t*)P(L.o_path);
     int32_t* need = (int32_t*)P(L.o_need);
     int32_t* nidx = (int32_t*)P(L.o_nidx);
@@ -1860,7 +1875,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_obs_q, dim3((unsigned)ceil_div(M.m, 256)), dim3(256), 0, s, M.obs_mu, M.obs_var, M.m,
                            theta, qlo, qhi);
-        hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, keys[0], cnt + 0, spc);
+        hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, keys[0], cnt + 0, spc, hob[0]);
     }
     e = launch_fill_f32(lcp, 0.0f, g.nc[0] * g.nc[1] * g.nc[2], s);
     if (e != hipSuccess) return e;
@@ -1875,7 +1890,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         {
         StageScope sc(s, ST_OCTREE);
         hipLaunchKernelGGL(k_prelim, dim3(gsz(cap * 64, 256)), dim3(256), 0, s, o, l, kin, nf, cap, M.X, M.m, qlo, qhi,
-                           path, need, sub, B, (int)search);
+                           path, need, sub, B, (int)search, hob[l & 1]);
         if (!search) {
             // the local and certified bounds take the nodes that need a bound, compacted
             e = launch_scan(need, nidx, cap, nf, B.cnt + 0, scanws, s);
@@ -2036,7 +2051,7 @@ hipError_t run_adaptive(const Model& M, const GridP& g, double theta, const lcp_
         uint64_t* dst = (l == Ldepth) ? leaves : kout;
         const int64_t dcap = (l == Ldepth) ? leaf_cap : caps[l + 1];
         hipLaunchKernelGGL(k_emit, dim3(gsz(cap, 256)), dim3(256), 0, s, o, l, kin, nf, cap, sub, eoff, dst, dcap,
-                           stat + o.statoff[l]);
+                           stat + o.statoff[l], path, hob[(l + 1) & 1]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
