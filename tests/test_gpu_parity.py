@@ -126,6 +126,9 @@ ADAPT_CASES = {
     "cfg2_64": lambda: workloads.make("cfg2_3d", m=200, npts=64),
     "ragged": lambda: _ragged_adapt(),
     "cfg1_2d_leaf2": lambda: _twod(),
+    # m_pad = 768: the probes' second group of row-block pairs is partly empty (blocks without
+    # a partner), in the shared-tile launches as in the others
+    "trig33_m700": lambda: workloads.field3d_trig(1, m=700, npts=33),
 }
 
 
