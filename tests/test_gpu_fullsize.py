@@ -168,6 +168,26 @@ def test_full_size_sparse_model_leaf_set():
     assert len(sym) == 0 or len(ties) > 0
 
 
+def test_full_size_kd_leaf_set(full):
+    """The benchmarked field with the K-D tree (Sec. 9) at 128^3: the leaf set and the depth
+    field equal the oracle's (up to its near-ties).  Its depths 12 and 13 have about 100
+    descent tiles, so their binary64 probes share each tile between two work-groups."""
+    W, M, G = full
+    adapt = lcp.adapt_of(W, min_leaf=4, bound_at_max_depth=1, steps=4, split=lcp.SPLIT_KD)
+    out, leaves, nl, lf, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, adapt, zbank(W), "f16x3")
+    n = int(nl.item())
+    got = leaves[:n].cpu().numpy().astype(np.uint64)
+    leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, min_leaf=4, bound_at_max_depth=1, steps=4,
+                                                    split=oracle.SPLIT_KD)
+    ties = near_tie_keys(recs, W.alpha)
+    sym, excused = compare_adaptive(W, M, None, got, lf.cpu().numpy(), leaves_ref, skipped_ref, ties, split=1,
+                                    counts_exact=False)
+    say(f"128^3 K-D adaptive: leaves gpu={n} oracle={len(leaves_ref)} differ={len(sym)} near-ties={len(ties)} "
+        f"excused cells={int(excused.sum())}")
+    assert n > 0 and len(skipped_ref) > 0
+    assert len(sym) == 0 or len(ties) > 0
+
+
 def test_full_size_256_adaptive_leaf_set_and_sampled_cells():
     """The largest configuration of the mixed-precision workload: 256^3, m = 500, adaptive
     f16x3 with the binary64 bound.  Leaf set against the oracle's Alg. 1 (about a minute of
