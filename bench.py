@@ -295,8 +295,8 @@ def main():
                     help="keep a finest-level node only if its edge-crossing union bound exceeds alpha (Sec. 9)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
-                                   "DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU only; splitting the grid over several GPUs "
+                                   "is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.print_source_hash:

@@ -40,7 +40,7 @@ typedef enum {
     LCP_ECAPACITY = 3,       /* an output list is smaller than the result; *count holds the true size */
     LCP_ENOMEM = 4,          /* model memory or workspace smaller than required */
     LCP_EDEVICE = 5,         /* a HIP runtime call failed */
-    LCP_ENOTSUPPORTED = 6    /* operation not provided by this build */
+    LCP_ENOTSUPPORTED = 6    /* operation not provided by this library */
 } lcp_status;
 
 typedef enum {
@@ -347,8 +347,9 @@ int lcp_batch_precision(const lcp_model_batch* batch, int reduced, double kappa_
  * of the batched posterior for models of precision `prec` with m_pad = 128 (size_class + 1)
  * (m_pad = m rounded up to 128; size_class 0..7).  The library's defaults come from the
  * project's autotuner (paper_2512_12442_amd/autotune.py), which times every candidate on the
- * batched workload and writes them into the build; nt = 0 restores them.  LCP_EINVAL if the
- * pair is not a candidate or its tile exceeds the LDS.  Process-wide and not synchronised:
+ * batched workload and writes the winners into the compiled table (csrc/tune_table.inc);
+ * nt = 0 restores them.  LCP_EINVAL if the pair is not a candidate or its tile exceeds the
+ * LDS.  Process-wide and not synchronised:
  * set it before launches that other threads may issue.
  * lcp_batch_tiles_get -- the current setting.
  */

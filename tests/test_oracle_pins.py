@@ -331,7 +331,8 @@ def test_bound_search_not_worse_than_any_grid_vertex(kind):
 
 
 def test_bound_dominates_cell_lcp_in_region():
-    """UB(node) >= LCP of every cell in the node (the benchmark spec), up to MC slack."""
+    """UB(node) >= LCP of every cell in the node (Sec. 5.1: the region bound is an upper bound
+    on the probability of a crossing anywhere in the region), up to MC slack."""
     W = small(26, 3, 15, 9, ell=0.3, signal_var=0.05, noise_var=1e-4)
     M = oracle.fit(W)
     lcp = oracle.lcp_dense(M, W)
