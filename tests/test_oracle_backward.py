@@ -75,3 +75,22 @@ def test_posterior_backward_rejects_the_sparse_model():
     W = workloads.sgpr_field(56, m=8, npts=5, train_npts=6)
     with pytest.raises(AssertionError):
         oracle.posterior_backward(oracle.fit(W), np.zeros((1, 3)), np.ones(1), None)
+
+
+@pytest.mark.parametrize("kind", [workloads.SE, workloads.MATERN52])
+def test_posterior_backward_variance_gives_no_value_gradient(kind):
+    """The variance of eq. (sgp) does not involve y, so an upstream on the variance alone gives
+    dL/dy = 0 exactly, while its log-lengthscale gradient is the one of the variance term of
+    the combined upstream (the two terms of the loss are additive)."""
+    W = small(57, 3, 14, 4, kind=kind, signal_var=0.8, ell=0.3, noise_var=1e-3)
+    P = np.random.default_rng(58).random((25, 3))
+    rng = np.random.default_rng(59)
+    gm, gv = rng.standard_normal(25), rng.standard_normal(25)
+    M = oracle.fit(W)
+    dy_v, dl_v = oracle.posterior_backward(M, P, None, gv)
+    assert np.all(dy_v == 0.0)
+    dy_m, dl_m = oracle.posterior_backward(M, P, gm, None)
+    dy_b, dl_b = oracle.posterior_backward(M, P, gm, gv)
+    assert np.allclose(dy_b, dy_m, rtol=1e-12, atol=1e-12)
+    assert np.allclose(dl_b, dl_m + dl_v, rtol=1e-10, atol=1e-12)
+    assert np.any(dl_v != 0.0)
