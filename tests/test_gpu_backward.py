@@ -81,6 +81,8 @@ def test_posterior_backward_partial_upstreams_and_empty():
         dy, dl = G.posterior_backward(t(P), None if a is None else t(a), None if b is None else t(b), "fp64")
         assert np.allclose(dy.cpu().numpy(), dy_ref, rtol=0, atol=1e-8 * max(1.0, np.abs(dy_ref).max()))
         assert np.allclose(dl.cpu().numpy(), dl_ref, rtol=0, atol=1e-8 * max(1.0, np.abs(dl_ref).max()))
+        if a is None:   # the variance does not involve y: no value gradient at all
+            assert float(dy.abs().max()) == 0.0
     dy, dl = G.posterior_backward(torch.zeros((0, 3), dtype=torch.float64, device=DEV), None, None, "fp64")
     assert float(dy.abs().max()) == 0.0 and float(dl.abs().max()) == 0.0
 
