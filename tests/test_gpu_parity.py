@@ -209,3 +209,27 @@ def test_tiny_grids_and_single_observation():
         leaves_ref, _, _ = oracle.adaptive(M, W)
         out, leaves, nl, _, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, lcp.adapt_of(W), zbank(W), "fp64")
         assert np.array_equal(leaves[: int(nl.item())].cpu().numpy().astype(np.uint64), leaves_ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f16x3"])
+@pytest.mark.parametrize("side", [1.0, -1.0])
+def test_adaptive_level_outside_the_field_emits_nothing(prec, side):
+    """A level far above (below) every posterior value: the root's bound (Sec. 5.1, eq.
+    (upper_bound)) is far below alpha, so Alg. 1 stops at the root with no leaf, and both
+    the adaptive and the dense field are zero (Sec. 5.3).  Every stage then runs on empty
+    lists: no probe points after the root, no leaf vertices, no cells."""
+    W = workloads.random_small(7, 3, 40, 24, signal_var=0.3, ell=0.3, min_leaf=2)
+    W.theta = float(W.y.max() + 10.0) if side > 0 else float(W.y.min() - 10.0)
+    say(f"level outside the field: theta={W.theta:.3f} prec={prec}")
+    M = oracle.fit(W)
+    leaves_ref, skipped_ref, recs = oracle.adaptive(M, W)
+    assert len(leaves_ref) == 0
+    G = gpu_model(W)
+    out, leaves, nl, lf, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, lcp.adapt_of(W), zbank(W), prec)
+    assert int(nl.item()) == 0
+    assert float(out.abs().sum()) == 0.0
+    sym, _ = compare_adaptive(W, M, out.cpu().numpy(), np.zeros(0, np.uint64), lf.cpu().numpy(), leaves_ref,
+                              skipped_ref, near_tie_keys(recs, W.alpha))
+    assert len(sym) == 0
+    dense, _ = G.lcp_dense(lcp.grid_of(W), W.theta, zbank(W), prec)
+    assert float(dense.abs().sum()) == 0.0
