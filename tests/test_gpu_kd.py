@@ -63,3 +63,23 @@ def test_kd_and_octree_agree_where_the_oracle_says_so():
     no, nk = int(a_oct[2].item()), int(a_kd[2].item())
     assert no == nk and np.array_equal(a_oct[1][:no].cpu().numpy(), a_kd[1][:nk].cpu().numpy())
     assert np.array_equal(a_oct[0].cpu().numpy(), a_kd[0].cpu().numpy())
+
+
+def test_kd_level_outside_the_field_emits_nothing():
+    """The K-D tree with a level far above every posterior value: the root's bound is far
+    below alpha, so the tree stops at its root with no leaf and a zero field, as the
+    oracle's K-D variant of Alg. 1 gives."""
+    W = workloads.random_small(8, 3, 40, 24, signal_var=0.3, ell=0.3, min_leaf=2)
+    W.theta = float(W.y.max() + 10.0)
+    say(f"K-D tree, level outside the field: theta={W.theta:.3f}")
+    M = oracle.fit(W)
+    leaves_ref, skipped_ref, recs = oracle.adaptive(M, W, split=oracle.SPLIT_KD)
+    assert len(leaves_ref) == 0
+    G = gpu_model(W)
+    out, leaves, nl, lf, _ = G.lcp_adaptive(lcp.grid_of(W), W.theta, lcp.adapt_of(W, split=lcp.SPLIT_KD), zbank(W),
+                                            "fp64")
+    assert int(nl.item()) == 0
+    assert float(out.abs().sum()) == 0.0
+    sym, _ = compare_adaptive(W, M, out.cpu().numpy(), np.zeros(0, np.uint64), lf.cpu().numpy(), leaves_ref,
+                              skipped_ref, near_tie_keys(recs, W.alpha), split=1)
+    assert len(sym) == 0
